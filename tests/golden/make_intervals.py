@@ -1,0 +1,75 @@
+"""Write tests/golden/intervals.json: the search interval of every named workload.
+
+Calls only the oracle.  For workload ``w`` with parameters k0 and n_eig, the
+interval is [mid-gap below eigenvalue k0, mid-gap above eigenvalue
+k0 + n_eig - 1] (0-based, ascending), so that it holds exactly n_eig
+eigenvalues and both ends sit half-way between neighbouring eigenvalues
+(the filter is exactly 1/2 at the ends, so an eigenvalue there would be only
+half captured).  Small pencils use the dense solver; large ones bisect on the
+Sylvester inertia count.
+
+Usage:  python tests/golden/make_intervals.py [name ...]
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+from oracle import feast_oracle as O  # noqa: E402
+from paper_0901_2665_amd import workloads as W  # noqa: E402
+
+
+def kth_eigenvalue(p, j, lo, hi, rtol=1e-13):
+    """Bisection for eigenvalue j (0-based): count(lo) <= j < count(hi)."""
+    while hi - lo > rtol * max(1.0, abs(lo), abs(hi)):
+        mid = 0.5 * (lo + hi)
+        if O.inertia_count(p, mid) <= j:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+def interval_for(name):
+    w = W.WORKLOADS[name]
+    p = W.make_pencil(name)
+    k0, m = w["k0"], w["n_eig"]
+    if p.n <= 2000:
+        lam = O.bruteforce(p)[0]
+        e = [lam[k0 - 1], lam[k0], lam[k0 + m - 1], lam[k0 + m]]
+        method = "dense"
+    else:
+        lo, hi = -100.0, 100.0
+        assert O.inertia_count(p, lo) == 0 and O.inertia_count(p, hi) == p.n
+        e = [kth_eigenvalue(p, j, lo, hi) for j in (k0 - 1, k0, k0 + m - 1, k0 + m)]
+        method = "inertia-bisection"
+    emin = 0.5 * (e[0] + e[1])
+    emax = 0.5 * (e[2] + e[3])
+    cnt = O.inertia_count(p, emax) - O.inertia_count(p, emin)
+    assert cnt == m, (name, cnt, m)
+    return dict(emin=emin, emax=emax, n_eig=m, k0=k0, method=method,
+                gap_lo=e[1] - e[0], gap_hi=e[3] - e[2])
+
+
+def main(names):
+    path = os.path.join(HERE, "intervals.json")
+    data = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            data = json.load(f)
+    for name in names or list(W.WORKLOADS):
+        data[name] = interval_for(name)
+        print(name, data[name], flush=True)
+        with open(path, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])

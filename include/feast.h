@@ -1,0 +1,178 @@
+/*
+ * feast.h -- C ABI of the MI355X FEAST hot path.
+ *
+ * FEAST (E. Polizzi, "A Density Matrix-based Algorithm for Solving Eigenvalue
+ * Problems") finds the eigenpairs of A x = lambda B x with lambda inside a
+ * search interval [emin, emax], A real symmetric and B symmetric positive
+ * definite (Sec. III.A, eq. 2).  One refinement loop of the real-symmetric
+ * algorithm (Fig. 2) is:
+ *   R   = B Y                                   (Y random first, Y = X later)
+ *   Q   = -sum_e (w_e/2) Re{ r e^{i theta_e} (Z_e B - A)^{-1} R }     (eq. 15)
+ *   A_Q = Q^T A Q,  B_Q = Q^T B Q                                     (eq. 7)
+ *   A_Q Phi = eps B_Q Phi,  Phi^T B_Q Phi = I                         (eq. 6)
+ *   lambda = eps,  X = Q Phi                                      (eqs. 8-9)
+ * with Gauss-Legendre nodes x_e, weights w_e, r = (emax-emin)/2,
+ * theta_e = -(pi/2)(x_e - 1), Z_e = (emax+emin)/2 + r e^{i theta_e}
+ * (eqs. 13-14).  Loops stop when the count M of Ritz values inside the
+ * interval is stable and the relative change of their trace is below tol
+ * (Sec. III.B (i), Sec. IV.A).
+ *
+ * Matrices are block-tridiagonal with nc cells of b x b blocks (the shape of
+ * nanowire / nanotube Hamiltonians):
+ *   diag[nc][b][b]  row-major diagonal blocks (symmetric),
+ *   up[nc-1][b][b]  row-major coupling block (i, i+1); block (i+1, i) is its
+ *                   transpose.
+ * Dense N x M0 arrays (N = nc*b) are row-major [N][M0].
+ *
+ * Memory: every pointer marked (dev) is HIP device memory owned by the caller;
+ * (host) is host memory owned by the caller.  The context owns its workspace
+ * (factors, subspaces, reduced matrices), grows it on demand and frees it in
+ * feast_destroy.  Nothing the library allocates is handed to the caller.
+ * Work is ordered on the stream given to feast_init; feast_solve synchronises
+ * that stream before it returns.  A context must not be used by two host
+ * threads at once.
+ *
+ * Status codes (int):
+ *    0  success
+ *   -1  nc < 1 or b < 1 (or b above the supported maximum, 64)
+ *   -2  emin >= emax or a bound is not finite
+ *   -3  M0 < 1 or M0 > N, or M0 above the supported maximum, 128
+ *   -4  Ne < 1 or Ne > 64
+ *   -5  a required pointer is NULL
+ *   -6  a non-finite value in A, B or Y0
+ *   -7  bad option (tol <= 0, max_loops < 1, unknown precision)
+ *   <= -100  HIP runtime error or out of memory: -100 - hipError_t
+ *    1  not converged within max_loops (outputs hold the last loop)
+ *    2  B_Q was not numerically positive definite in the last loop: the
+ *       reduced problem was solved in the span of B_Q's eigenvectors with
+ *       eigenvalue > 1e-14 max; dropped Ritz slots are returned last with
+ *       lambda = NaN and a zero eigenvector
+ *    3  no eigenvalue in the interval (M = 0)
+ *    4  M = M0: the subspace is too small (Fig. 2 needs M0 > M)
+ * Positive codes are warnings: every output is written.
+ */
+#ifndef FEAST_MI355X_H
+#define FEAST_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct feast_ctx feast_ctx;
+
+/* Block-tridiagonal pencil (A, B); all four pointers (dev), float64. */
+typedef struct {
+  int32_t nc;            /* number of cells, >= 1 */
+  int32_t b;             /* block size, 1..64 */
+  const double *A_diag;  /* [nc][b][b] */
+  const double *A_up;    /* [nc-1][b][b] (may be NULL when nc == 1) */
+  const double *B_diag;  /* [nc][b][b] */
+  const double *B_up;    /* [nc-1][b][b] (may be NULL when nc == 1) */
+} feast_bt_matrix;
+
+typedef struct {
+  double tol;            /* relative trace change for convergence, e.g. 1e-12 */
+  int32_t max_loops;     /* refinement loops allowed, >= 1 */
+  int32_t precision;     /* 0: complex float64 shifted solves */
+  const double *Y0;      /* (dev) [N][M0] initial subspace; required */
+} feast_opts;
+
+typedef struct {
+  int32_t loops;         /* contour integrations performed */
+  int32_t M;             /* Ritz values inside [emin, emax] */
+  double trace;          /* sum of those Ritz values (last loop) */
+  double trace_rel;      /* relative trace change of the last loop */
+  double max_res;        /* max residual over the M in-interval pairs */
+  int32_t status;        /* same as the return value */
+  int32_t fallback;      /* 1 if the last loop used the B_Q fallback */
+  double trace_hist[64]; /* trace per loop (first min(loops,64) entries) */
+  int32_t count_hist[64];/* M per loop */
+} feast_info;
+
+/* Default options: tol 1e-12, max_loops 20, precision 0, Y0 NULL. */
+void feast_default_opts(feast_opts *opts);
+
+/* Create a context on HIP device `device`; `hip_stream` is a hipStream_t or
+ * NULL for the default stream.  Returns 0 or a status <= -100. */
+int feast_init(feast_ctx **ctx, int device, void *hip_stream);
+
+/* Release the context and its workspace.  NULL is accepted. */
+int feast_destroy(feast_ctx *ctx);
+
+/* Human-readable text of a status code (static storage). */
+const char *feast_strerror(int status);
+
+/*
+ * Full FEAST solve (Fig. 2, real symmetric case) on the GPU.
+ *   lambda (dev) [M0]    Ritz values: the M inside [emin, emax] first,
+ *                        ascending, then the others ascending.
+ *   X      (dev) [N][M0] Ritz vectors in the same column order, B-orthonormal.
+ *   res    (dev) [M0]    ||A x - lambda B x||_1 / ||A x||_1 per column
+ *                        (Table I caption); when ||A x||_1 < r ||B x||_1 the
+ *                        denominator is ||B x||_1 max(|emin|, |emax|, r).
+ *   info   (host)        may be NULL.
+ * The shifted systems are factored once per call (Sec. V, parallelism (ii))
+ * and reused by every refinement loop.
+ */
+int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double emax,
+                int32_t M0, int32_t Ne, const feast_opts *opts,
+                double *lambda, double *X, double *res, feast_info *info);
+
+/* ---- single steps of the same path, for step-by-step parity checks ---- */
+
+/*
+ * Gauss-Legendre rule and contour of Sec. III.B (eqs. 13-15), host only.
+ * Writes Ne values each (host): nodes x (ascending), weights w, the contour
+ * points Z_e (real and imaginary parts) and the accumulation weights
+ * kappa_e = -(w_e/2) r e^{i theta_e}, so that Q = sum_e Re(kappa_e Q_e).
+ */
+int feast_contour(int32_t Ne, double emin, double emax, double *x, double *w,
+                  double *z_re, double *z_im, double *k_re, double *k_im);
+
+/*
+ * out = T V for one block-tridiagonal operator T = (diag, up) (dev, float64)
+ * and a dense V [nc*b][m] (dev, row-major); out (dev) [nc*b][m].
+ * `which` selects T: 0 = A, 1 = B of the pencil.  1 <= m <= 128.
+ */
+int feast_bt_multiply(feast_ctx *ctx, const feast_bt_matrix *AB, int32_t which,
+                      int32_t m, const double *V, double *out);
+
+/*
+ * Solve (z B - A) X = R for one complex shift z with Im z > 0 (Fig. 2 step 2),
+ * R real (dev) [N][m]; X_re, X_im (dev) [N][m].  1 <= m <= 128.
+ */
+int feast_shifted_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double z_re,
+                        double z_im, int32_t m, const double *R, double *X_re,
+                        double *X_im);
+
+/*
+ * One contour integration (Fig. 2 step 2, eq. 15 with RHS B Y):
+ * Q = -sum_e (w_e/2) Re{ r e^{i theta_e} (Z_e B - A)^{-1} B Y }.
+ * Y, Q (dev) [N][M0].
+ */
+int feast_filter(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double emax,
+                 int32_t M0, int32_t Ne, const double *Y, double *Q);
+
+/*
+ * Projection (eq. 7): A_Q = Q^T A Q and B_Q = Q^T B Q, symmetrised.
+ * Q (dev) [N][M0]; AQ, BQ (dev) [M0][M0].
+ */
+int feast_project(feast_ctx *ctx, const feast_bt_matrix *AB, int32_t M0,
+                  const double *Q, double *AQ, double *BQ);
+
+/*
+ * Reduced generalized eigenproblem (eq. 6): A_Q Phi = eps B_Q Phi with
+ * Phi^T B_Q Phi = I, eps ascending (NaN slots last, see status 2).
+ * AQ, BQ (dev) [M0][M0] symmetric; eps (dev) [M0]; Phi (dev) [M0][M0].
+ * *fallback (host) is set to 1 when B_Q was not numerically s.p.d.
+ */
+int feast_reduced_eig(feast_ctx *ctx, int32_t M0, const double *AQ, const double *BQ,
+                      double *eps, double *Phi, int32_t *fallback);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FEAST_MI355X_H */

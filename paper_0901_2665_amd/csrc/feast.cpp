@@ -1,0 +1,540 @@
+// Host driver and C ABI of the FEAST hot path (see include/feast.h).
+//
+// The host only validates arguments, computes the Gauss-Legendre rule and
+// the contour (eqs. 13-14), launches the kernels in order on the context's
+// stream and takes the loop decisions of Fig. 2 step 6 from the M0 Ritz
+// values it copies back once per refinement loop.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "../../include/feast.h"
+#include "kernels.h"
+
+using namespace feast;
+
+namespace {
+
+constexpr int kMaxB = 64;
+constexpr int kMaxM0 = 128;
+
+struct Buf {
+  void *ptr = nullptr;
+  size_t cap = 0;
+};
+
+enum Slot {
+  S_SINV, S_W, S_WT, S_TW, S_G, S_TV, S_Y, S_R, S_P, S_Q, S_AV, S_BV, S_X, S_GRAMP, S_AQ, S_BQ,
+  S_EPS, S_PHI, S_RRS, S_FLAG, S_RESP, S_RES, S_PERM, S_T0, S_T1, S_COUNT
+};
+
+}  // namespace
+
+struct feast_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  Buf buf[S_COUNT];
+  double *h_eps = nullptr;  // pinned: eps[128] + res[128]
+  int *h_flag = nullptr;    // pinned
+};
+
+namespace {
+
+int hip_status(hipError_t e) { return e == hipSuccess ? 0 : -100 - (int)e; }
+
+#define HIPCHK(x)                          \
+  do {                                     \
+    hipError_t _e = (x);                   \
+    if (_e != hipSuccess) return hip_status(_e); \
+  } while (0)
+
+hipError_t ensure(feast_ctx *ctx, Slot s, size_t bytes, void **out) {
+  Buf &b = ctx->buf[s];
+  if (bytes == 0) bytes = 256;
+  if (b.cap < bytes) {
+    if (b.ptr) {
+      hipError_t e = hipFree(b.ptr);
+      if (e != hipSuccess) return e;
+      b.ptr = nullptr;
+      b.cap = 0;
+    }
+    hipError_t e = hipMalloc(&b.ptr, bytes);
+    if (e != hipSuccess) return e;
+    b.cap = bytes;
+  }
+  *out = b.ptr;
+  return hipSuccess;
+}
+
+template <typename T>
+hipError_t ensure_t(feast_ctx *ctx, Slot s, size_t count, T **out) {
+  void *p = nullptr;
+  hipError_t e = ensure(ctx, s, count * sizeof(T), &p);
+  *out = static_cast<T *>(p);
+  return e;
+}
+
+int round16(int x) { return (x + 15) / 16 * 16; }
+
+// Gauss-Legendre rule on [-1, 1]: Newton on the roots of P_n with the
+// three-term recurrence; weights 2 / ((1 - x^2) P_n'(x)^2).  Ascending nodes.
+void gauss_legendre(int n, double *x, double *w) {
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p1 = 1.0, p2 = 0.0;
+      for (int k = 1; k <= n; ++k) {
+        double p3 = p2;
+        p2 = p1;
+        p1 = ((2.0 * k - 1.0) * z * p2 - (k - 1.0) * p3) / k;
+      }
+      dp = n * (z * p1 - p2) / (z * z - 1.0);
+      double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) {
+        // one more evaluation of the derivative at the converged node
+        double q1 = 1.0, q2 = 0.0;
+        for (int k = 1; k <= n; ++k) {
+          double q3 = q2;
+          q2 = q1;
+          q1 = ((2.0 * k - 1.0) * z * q2 - (k - 1.0) * q3) / k;
+        }
+        dp = n * (z * q1 - q2) / (z * z - 1.0);
+        break;
+      }
+    }
+    // cos(...) for i = 0 is the largest root; store ascending
+    x[n - 1 - i] = z;
+    w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+void make_shifts(int Ne, double emin, double emax, Shifts &s, double *xo = nullptr,
+                 double *wo = nullptr) {
+  double x[kMaxNe], w[kMaxNe];
+  gauss_legendre(Ne, x, w);
+  const double r = 0.5 * (emax - emin), c = 0.5 * (emax + emin);
+  std::memset(&s, 0, sizeof(s));
+  for (int e = 0; e < Ne; ++e) {
+    const double th = -(M_PI / 2.0) * (x[e] - 1.0);
+    s.zre[e] = c + r * std::cos(th);
+    s.zim[e] = r * std::sin(th);
+    s.kre[e] = -(w[e] / 2.0) * r * std::cos(th);
+    s.kim[e] = -(w[e] / 2.0) * r * std::sin(th);
+    if (xo) xo[e] = x[e];
+    if (wo) wo[e] = w[e];
+  }
+}
+
+int validate_matrix(const feast_bt_matrix *AB) {
+  if (!AB) return -5;
+  if (AB->nc < 1 || AB->b < 1 || AB->b > kMaxB) return -1;
+  if (!AB->A_diag || !AB->B_diag) return -5;
+  if (AB->nc > 1 && (!AB->A_up || !AB->B_up)) return -5;
+  return 0;
+}
+
+Pencil make_pencil(const feast_bt_matrix *AB) {
+  Pencil p;
+  p.Ad = AB->A_diag;
+  p.Au = AB->A_up;
+  p.Bd = AB->B_diag;
+  p.Bu = AB->B_up;
+  p.nc = AB->nc;
+  p.b = AB->b;
+  p.bp = round16(AB->b);
+  return p;
+}
+
+// Non-finite scan of the pencil (and optionally Y0); returns -6 on NaN/Inf.
+int check_inputs(feast_ctx *ctx, const feast_bt_matrix *AB, const double *Y0, size_t ny) {
+  int *flag = nullptr;
+  HIPCHK(ensure_t(ctx, S_FLAG, 4, &flag));
+  HIPCHK(hipMemsetAsync(flag, 0, 4 * sizeof(int), ctx->stream));
+  const size_t bb = (size_t)AB->b * AB->b;
+  HIPCHK(launch_check_finite(AB->A_diag, AB->nc * bb, flag, ctx->stream));
+  HIPCHK(launch_check_finite(AB->B_diag, AB->nc * bb, flag, ctx->stream));
+  if (AB->nc > 1) {
+    HIPCHK(launch_check_finite(AB->A_up, (AB->nc - 1) * bb, flag, ctx->stream));
+    HIPCHK(launch_check_finite(AB->B_up, (AB->nc - 1) * bb, flag, ctx->stream));
+  }
+  if (Y0) HIPCHK(launch_check_finite(Y0, ny, flag, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->h_flag, flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return ctx->h_flag[0] ? -6 : 0;
+}
+
+struct Work {
+  Pencil p;
+  Factors f;
+  SolveBufs sb;
+  int Ne, m0, m0p;
+  size_t rows;
+};
+
+// Workspace for the factors and the sweeps of Ne shifts.
+int prepare_factor(feast_ctx *ctx, const Pencil &p, int Ne, int m0p, Work &wk) {
+  const size_t blk = 2 * (size_t)p.bp * p.bp;
+  wk.p = p;
+  wk.Ne = Ne;
+  wk.m0p = m0p;
+  wk.rows = (size_t)p.nc * p.bp;
+  wk.f.m = p.nc - p.nc / 2;
+  HIPCHK(ensure_t(ctx, S_SINV, (size_t)Ne * p.nc * blk, &wk.f.Sinv));
+  HIPCHK(ensure_t(ctx, S_W, (size_t)Ne * p.nc * blk, &wk.f.W));
+  HIPCHK(ensure_t(ctx, S_WT, (size_t)Ne * p.nc * blk, &wk.f.WT));
+  HIPCHK(ensure_t(ctx, S_TW, (size_t)Ne * blk, &wk.f.TW));
+  HIPCHK(ensure_t(ctx, S_G, (size_t)Ne * wk.rows * m0p * 2, &wk.sb.G));
+  HIPCHK(ensure_t(ctx, S_TV, (size_t)Ne * (m0p / kTile) * 4 * p.bp * kTile, &wk.sb.TV));
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+void feast_default_opts(feast_opts *opts) {
+  if (!opts) return;
+  opts->tol = 1e-12;
+  opts->max_loops = 20;
+  opts->precision = 0;
+  opts->Y0 = nullptr;
+}
+
+int feast_init(feast_ctx **ctx, int device, void *hip_stream) {
+  if (!ctx) return -5;
+  *ctx = nullptr;
+  HIPCHK(hipSetDevice(device));
+  feast_ctx *c = new feast_ctx();
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  hipError_t e = hipHostMalloc((void **)&c->h_eps, 4 * kMaxM0 * sizeof(double), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void **)&c->h_flag, 16 * sizeof(int), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    feast_destroy(c);
+    return hip_status(e);
+  }
+  *ctx = c;
+  return 0;
+}
+
+int feast_destroy(feast_ctx *ctx) {
+  if (!ctx) return 0;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  else (void)hipDeviceSynchronize();
+  for (auto &b : ctx->buf)
+    if (b.ptr) (void)hipFree(b.ptr);
+  if (ctx->h_eps) (void)hipHostFree(ctx->h_eps);
+  if (ctx->h_flag) (void)hipHostFree(ctx->h_flag);
+  delete ctx;
+  return 0;
+}
+
+const char *feast_strerror(int status) {
+  switch (status) {
+    case 0: return "success";
+    case -1: return "bad block structure (nc < 1, b < 1 or b > 64)";
+    case -2: return "bad interval (emin >= emax or not finite)";
+    case -3: return "bad subspace size (M0 < 1, M0 > N or M0 > 128)";
+    case -4: return "bad number of contour points (Ne < 1 or Ne > 64)";
+    case -5: return "NULL pointer argument";
+    case -6: return "non-finite value in the input";
+    case -7: return "bad option";
+    case 1: return "not converged within max_loops";
+    case 2: return "B_Q not positive definite; reduced problem solved on its range";
+    case 3: return "no eigenvalue in the interval";
+    case 4: return "subspace too small: M = M0";
+    default: return status <= -100 ? "HIP runtime error" : "unknown status";
+  }
+}
+
+int feast_contour(int32_t Ne, double emin, double emax, double *x, double *w, double *z_re,
+                  double *z_im, double *k_re, double *k_im) {
+  if (Ne < 1 || Ne > kMaxNe) return -4;
+  if (!(emin < emax) || !std::isfinite(emin) || !std::isfinite(emax)) return -2;
+  if (!x || !w || !z_re || !z_im || !k_re || !k_im) return -5;
+  Shifts s;
+  make_shifts(Ne, emin, emax, s, x, w);
+  for (int e = 0; e < Ne; ++e) {
+    z_re[e] = s.zre[e];
+    z_im[e] = s.zim[e];
+    k_re[e] = s.kre[e];
+    k_im[e] = s.kim[e];
+  }
+  return 0;
+}
+
+int feast_bt_multiply(feast_ctx *ctx, const feast_bt_matrix *AB, int32_t which, int32_t m,
+                      const double *V, double *out) {
+  if (!ctx || !V || !out) return -5;
+  int st = validate_matrix(AB);
+  if (st) return st;
+  if (m < 1 || m > kMaxM0) return -3;
+  if (which != 0 && which != 1) return -7;
+  HIPCHK(hipSetDevice(ctx->device));
+  Pencil p = make_pencil(AB);
+  const int mp = round16(m);
+  const size_t rows = (size_t)p.nc * p.bp;
+  double *vin, *vout;
+  HIPCHK(ensure_t(ctx, S_T0, rows * mp, &vin));
+  HIPCHK(ensure_t(ctx, S_T1, rows * mp, &vout));
+  HIPCHK(launch_pack(V, p.nc, p.b, p.bp, m, mp, vin, ctx->stream));
+  HIPCHK(launch_bt_multiply(p, which, vin, mp, vout, ctx->stream));
+  HIPCHK(launch_unpack(vout, p.nc, p.b, p.bp, m, mp, nullptr, out, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return 0;
+}
+
+int feast_shifted_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double z_re, double z_im,
+                        int32_t m, const double *R, double *X_re, double *X_im) {
+  if (!ctx || !R || !X_re || !X_im) return -5;
+  int st = validate_matrix(AB);
+  if (st) return st;
+  if (m < 1 || m > kMaxM0) return -3;
+  if (!(z_im > 0.0) || !std::isfinite(z_re) || !std::isfinite(z_im)) return -2;
+  HIPCHK(hipSetDevice(ctx->device));
+  Pencil p = make_pencil(AB);
+  const int mp = round16(m);
+  Work wk;
+  st = prepare_factor(ctx, p, 1, mp, wk);
+  if (st) return st;
+  Shifts s;
+  std::memset(&s, 0, sizeof(s));
+  s.zre[0] = z_re;
+  s.zim[0] = z_im;
+  double *rin, *xr, *xi;
+  HIPCHK(ensure_t(ctx, S_R, wk.rows * mp, &rin));
+  HIPCHK(ensure_t(ctx, S_T0, wk.rows * mp, &xr));
+  HIPCHK(ensure_t(ctx, S_T1, wk.rows * mp, &xi));
+  HIPCHK(launch_factor(p, s, 1, wk.f, ctx->stream));
+  HIPCHK(launch_pack(R, p.nc, p.b, p.bp, m, mp, rin, ctx->stream));
+  HIPCHK(launch_sweeps_complex(p, s, wk.f, wk.sb, rin, mp, xr, xi, ctx->stream));
+  HIPCHK(launch_unpack(xr, p.nc, p.b, p.bp, m, mp, nullptr, X_re, ctx->stream));
+  HIPCHK(launch_unpack(xi, p.nc, p.b, p.bp, m, mp, nullptr, X_im, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return 0;
+}
+
+int feast_filter(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double emax,
+                 int32_t M0, int32_t Ne, const double *Y, double *Q) {
+  if (!ctx || !Y || !Q) return -5;
+  int st = validate_matrix(AB);
+  if (st) return st;
+  if (!(emin < emax) || !std::isfinite(emin) || !std::isfinite(emax)) return -2;
+  if (M0 < 1 || M0 > kMaxM0 || M0 > AB->nc * AB->b) return -3;
+  if (Ne < 1 || Ne > kMaxNe) return -4;
+  HIPCHK(hipSetDevice(ctx->device));
+  Pencil p = make_pencil(AB);
+  const int mp = round16(M0);
+  Work wk;
+  st = prepare_factor(ctx, p, Ne, mp, wk);
+  if (st) return st;
+  Shifts s;
+  make_shifts(Ne, emin, emax, s);
+  double *y, *r, *pp, *q;
+  HIPCHK(ensure_t(ctx, S_Y, wk.rows * mp, &y));
+  HIPCHK(ensure_t(ctx, S_R, wk.rows * mp, &r));
+  HIPCHK(ensure_t(ctx, S_P, (size_t)Ne * wk.rows * mp, &pp));
+  HIPCHK(ensure_t(ctx, S_Q, wk.rows * mp, &q));
+  HIPCHK(launch_factor(p, s, Ne, wk.f, ctx->stream));
+  HIPCHK(launch_pack(Y, p.nc, p.b, p.bp, M0, mp, y, ctx->stream));
+  HIPCHK(launch_bt_multiply(p, 1, y, mp, r, ctx->stream));
+  HIPCHK(launch_sweeps(p, s, Ne, wk.f, wk.sb, r, mp, pp, ctx->stream));
+  HIPCHK(launch_sum_nodes(pp, Ne, wk.rows * mp, q, ctx->stream));
+  HIPCHK(launch_unpack(q, p.nc, p.b, p.bp, M0, mp, nullptr, Q, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return 0;
+}
+
+int feast_project(feast_ctx *ctx, const feast_bt_matrix *AB, int32_t M0, const double *Q,
+                  double *AQ, double *BQ) {
+  if (!ctx || !Q || !AQ || !BQ) return -5;
+  int st = validate_matrix(AB);
+  if (st) return st;
+  if (M0 < 1 || M0 > kMaxM0 || M0 > AB->nc * AB->b) return -3;
+  HIPCHK(hipSetDevice(ctx->device));
+  Pencil p = make_pencil(AB);
+  const int mp = round16(M0);
+  const size_t rows = (size_t)p.nc * p.bp;
+  double *q, *av, *bv, *gp;
+  HIPCHK(ensure_t(ctx, S_Q, rows * mp, &q));
+  HIPCHK(ensure_t(ctx, S_AV, rows * mp, &av));
+  HIPCHK(ensure_t(ctx, S_BV, rows * mp, &bv));
+  HIPCHK(ensure_t(ctx, S_GRAMP, gram_partial_doubles(rows, mp), &gp));
+  HIPCHK(launch_pack(Q, p.nc, p.b, p.bp, M0, mp, q, ctx->stream));
+  HIPCHK(launch_bt_multiply(p, 0, q, mp, av, ctx->stream));
+  HIPCHK(launch_bt_multiply(p, 1, q, mp, bv, ctx->stream));
+  HIPCHK(launch_gram2(q, av, bv, rows, mp, M0, gp, AQ, BQ, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return 0;
+}
+
+int feast_reduced_eig(feast_ctx *ctx, int32_t M0, const double *AQ, const double *BQ,
+                      double *eps, double *Phi, int32_t *fallback) {
+  if (!ctx || !AQ || !BQ || !eps || !Phi) return -5;
+  if (M0 < 1 || M0 > kMaxM0) return -3;
+  HIPCHK(hipSetDevice(ctx->device));
+  double *scr;
+  int *flag;
+  HIPCHK(ensure_t(ctx, S_RRS, 4 * (size_t)kMaxM0 * kMaxM0, &scr));
+  HIPCHK(ensure_t(ctx, S_FLAG, 4, &flag));
+  HIPCHK(launch_reduced_eig(AQ, BQ, M0, eps, Phi, scr, flag, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->h_flag, flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (fallback) *fallback = ctx->h_flag[0];
+  return 0;
+}
+
+int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double emax, int32_t M0,
+                int32_t Ne, const feast_opts *opts, double *lambda, double *X, double *res,
+                feast_info *info) {
+  if (!ctx || !lambda || !X || !res) return -5;
+  int st = validate_matrix(AB);
+  if (st) return st;
+  if (!(emin < emax) || !std::isfinite(emin) || !std::isfinite(emax)) return -2;
+  const long long N = (long long)AB->nc * AB->b;
+  if (M0 < 1 || M0 > kMaxM0 || M0 > N) return -3;
+  if (Ne < 1 || Ne > kMaxNe) return -4;
+  feast_opts o;
+  feast_default_opts(&o);
+  if (opts) o = *opts;
+  if (!o.Y0) return -5;
+  if (!(o.tol > 0.0) || o.max_loops < 1 || o.precision != 0) return -7;
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t sm = ctx->stream;
+
+  st = check_inputs(ctx, AB, o.Y0, (size_t)N * M0);
+  if (st) return st;
+
+  Pencil p = make_pencil(AB);
+  const int mp = round16(M0);
+  Work wk;
+  st = prepare_factor(ctx, p, Ne, mp, wk);
+  if (st) return st;
+  const size_t rows = wk.rows;
+  Shifts s;
+  make_shifts(Ne, emin, emax, s);
+  const double r = 0.5 * (emax - emin);
+
+  double *y, *rr, *pp, *q, *av, *bv, *x, *gp, *aq, *bq, *eps, *phi, *scr, *resp, *resi;
+  int *flag, *perm;
+  HIPCHK(ensure_t(ctx, S_Y, rows * mp, &y));
+  HIPCHK(ensure_t(ctx, S_R, rows * mp, &rr));
+  HIPCHK(ensure_t(ctx, S_P, (size_t)Ne * rows * mp, &pp));
+  HIPCHK(ensure_t(ctx, S_Q, rows * mp, &q));
+  HIPCHK(ensure_t(ctx, S_AV, rows * mp, &av));
+  HIPCHK(ensure_t(ctx, S_BV, rows * mp, &bv));
+  HIPCHK(ensure_t(ctx, S_X, rows * mp, &x));
+  HIPCHK(ensure_t(ctx, S_GRAMP, gram_partial_doubles(rows, mp), &gp));
+  HIPCHK(ensure_t(ctx, S_AQ, (size_t)M0 * M0, &aq));
+  HIPCHK(ensure_t(ctx, S_BQ, (size_t)M0 * M0, &bq));
+  HIPCHK(ensure_t(ctx, S_EPS, (size_t)M0, &eps));
+  HIPCHK(ensure_t(ctx, S_PHI, (size_t)M0 * M0, &phi));
+  HIPCHK(ensure_t(ctx, S_RRS, 4 * (size_t)kMaxM0 * kMaxM0, &scr));
+  HIPCHK(ensure_t(ctx, S_FLAG, 4, &flag));
+  HIPCHK(ensure_t(ctx, S_RESP, residual_partial_doubles(rows, mp), &resp));
+  HIPCHK(ensure_t(ctx, S_RES, (size_t)M0, &resi));
+  HIPCHK(ensure_t(ctx, S_PERM, (size_t)M0, &perm));
+
+  // factor every shifted matrix once (Sec. V, parallelism (ii))
+  HIPCHK(launch_factor(p, s, Ne, wk.f, sm));
+  HIPCHK(launch_pack(o.Y0, p.nc, p.b, p.bp, M0, mp, y, sm));
+
+  std::vector<double> traces;
+  std::vector<int> counts;
+  double trace_rel = INFINITY;
+  bool converged = false;
+  int fallback = 0;
+  double *h_eps = ctx->h_eps;
+  for (int k = 1; k <= o.max_loops; ++k) {
+    HIPCHK(launch_bt_multiply(p, 1, y, mp, rr, sm));                    // R = B Y
+    HIPCHK(launch_sweeps(p, s, Ne, wk.f, wk.sb, rr, mp, pp, sm));       // Q_e, weighted
+    HIPCHK(launch_sum_nodes(pp, Ne, rows * mp, q, sm));                 // Q (eq. 15)
+    HIPCHK(launch_bt_multiply(p, 0, q, mp, av, sm));                    // A Q
+    HIPCHK(launch_bt_multiply(p, 1, q, mp, bv, sm));                    // B Q
+    HIPCHK(launch_gram2(q, av, bv, rows, mp, M0, gp, aq, bq, sm));      // A_Q, B_Q (eq. 7)
+    HIPCHK(launch_reduced_eig(aq, bq, M0, eps, phi, scr, flag, sm));    // eq. 6
+    HIPCHK(launch_gemm_qphi(q, rows, mp, M0, phi, x, sm));              // X = Q Phi (eq. 9)
+    HIPCHK(hipMemcpyAsync(h_eps, eps, M0 * sizeof(double), hipMemcpyDeviceToHost, sm));
+    HIPCHK(hipMemcpyAsync(ctx->h_flag, flag, sizeof(int), hipMemcpyDeviceToHost, sm));
+    HIPCHK(hipStreamSynchronize(sm));
+    fallback = ctx->h_flag[0];
+    int Mk = 0;
+    double Tk = 0.0;
+    for (int j = 0; j < M0; ++j)
+      if (h_eps[j] >= emin && h_eps[j] <= emax) {
+        ++Mk;
+        Tk += h_eps[j];
+      }
+    if (k >= 2) {
+      if (Mk == 0 && counts.back() == 0)
+        trace_rel = 0.0;
+      else
+        trace_rel = std::fabs(Tk - traces.back()) / std::max(std::fabs(Tk), Mk * r);
+    }
+    traces.push_back(Tk);
+    counts.push_back(Mk);
+    if (k >= 2 && Mk == counts[counts.size() - 2] && trace_rel < o.tol) {
+      converged = true;
+      break;
+    }
+    if (k < o.max_loops) std::swap(y, x);  // Y <- X (Fig. 2 step 6)
+  }
+
+  // residuals of the final Ritz pairs (Table I caption)
+  HIPCHK(launch_bt_multiply(p, 0, x, mp, av, sm));
+  HIPCHK(launch_bt_multiply(p, 1, x, mp, bv, sm));
+  HIPCHK(launch_residuals(av, bv, eps, rows, mp, M0, emin, emax, resp, resi, sm));
+
+  // order: in-interval first (ascending), then the rest, NaN slots last
+  std::vector<int> order;
+  order.reserve(M0);
+  for (int j = 0; j < M0; ++j)
+    if (h_eps[j] >= emin && h_eps[j] <= emax) order.push_back(j);
+  for (int j = 0; j < M0; ++j)
+    if (std::isfinite(h_eps[j]) && !(h_eps[j] >= emin && h_eps[j] <= emax)) order.push_back(j);
+  for (int j = 0; j < M0; ++j)
+    if (!std::isfinite(h_eps[j])) order.push_back(j);
+  int *h_perm = reinterpret_cast<int *>(ctx->h_eps + 2 * kMaxM0);
+  for (int j = 0; j < M0; ++j) h_perm[j] = order[j];
+  HIPCHK(hipMemcpyAsync(perm, h_perm, M0 * sizeof(int), hipMemcpyHostToDevice, sm));
+  HIPCHK(launch_unpack(x, p.nc, p.b, p.bp, M0, mp, perm, X, sm));
+  HIPCHK(launch_gather(eps, perm, M0, lambda, sm));
+  HIPCHK(launch_gather(resi, perm, M0, res, sm));
+  double *h_res = ctx->h_eps + kMaxM0;
+  HIPCHK(hipMemcpyAsync(h_res, res, M0 * sizeof(double), hipMemcpyDeviceToHost, sm));
+  HIPCHK(hipStreamSynchronize(sm));
+
+  const int M = counts.back();
+  double max_res = 0.0;
+  for (int j = 0; j < M; ++j) max_res = std::max(max_res, h_res[j]);
+  int status;
+  if (!converged) status = 1;
+  else if (fallback) status = 2;
+  else if (M == M0) status = 4;
+  else if (M == 0) status = 3;
+  else status = 0;
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->loops = (int)traces.size();
+    info->M = M;
+    info->trace = traces.back();
+    info->trace_rel = trace_rel;
+    info->max_res = max_res;
+    info->status = status;
+    info->fallback = fallback;
+    for (size_t k = 0; k < traces.size() && k < 64; ++k) {
+      info->trace_hist[k] = traces[k];
+      info->count_hist[k] = counts[k];
+    }
+  }
+  return status;
+}
+
+}  // extern "C"

@@ -1,0 +1,77 @@
+// Host-side launchers of the FEAST kernels (implemented in *.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace feast {
+
+constexpr int kMaxNe = 64;
+constexpr int kTile = 8;  // complex right-hand sides per solve chain
+
+// Contour data passed by value to the kernels that need it.
+struct Shifts {
+  double zre[kMaxNe], zim[kMaxNe];   // Z_e
+  double kre[kMaxNe], kim[kMaxNe];   // kappa_e
+};
+
+struct Pencil {
+  const double *Ad, *Au, *Bd, *Bu;   // caller blocks, row stride b
+  int nc, b, bp;                     // bp = b rounded up to 16
+};
+
+// Twisted block factorisation of every (Z_e B - A): top chain 0..m-1
+// top-down, bottom chain nc-1..m bottom-up, twist cell m-1.
+struct Factors {
+  double *Sinv, *W, *WT;   // [Ne][nc][2][bp][bp]
+  double *TW;              // [Ne][2][bp][bp] raw Schur complement at the twist cell
+  int m;                   // twist split
+};
+
+hipError_t launch_factor(const Pencil &p, const Shifts &s, int Ne, const Factors &f,
+                         hipStream_t st);
+
+// Forward/back sweeps of all Ne shifts for right-hand side R (real,
+// padded [nc][bp][m0p]); writes P[e] = Re(kappa_e x_e) (padded, per node).
+struct SolveBufs {
+  double *G;    // [Ne][ntiles][nc][2][bp][8]
+  double *TV;   // [Ne][ntiles][2][2][bp][8]: twist vectors (h_{m-1}, c)
+};
+hipError_t launch_sweeps(const Pencil &p, const Shifts &s, int Ne, const Factors &f,
+                         const SolveBufs &sb, const double *R, int m0p, double *P,
+                         hipStream_t st);
+// Same sweeps, but the back sweep writes the complex solution of node 0
+// (used by the single-shift entry point): X_re, X_im padded.
+hipError_t launch_sweeps_complex(const Pencil &p, const Shifts &s, const Factors &f,
+                                 const SolveBufs &sb, const double *R, int m0p,
+                                 double *Xre, double *Xim, hipStream_t st);
+
+// Dense helpers (dense.hip).
+hipError_t launch_pack(const double *src, int nc, int b, int bp, int m, int ldd,
+                       double *dst, hipStream_t st);
+hipError_t launch_unpack(const double *src, int nc, int b, int bp, int m, int lds,
+                         const int *perm, double *dst, hipStream_t st);
+hipError_t launch_bt_multiply(const Pencil &p, int which, const double *V, int ld,
+                              double *out, hipStream_t st);
+hipError_t launch_sum_nodes(const double *P, int Ne, size_t count, double *Q,
+                            hipStream_t st);
+// Gram matrices Q^T V1 and Q^T V2 -> symmetrised [m0][m0] outputs.
+hipError_t launch_gram2(const double *Q, const double *V1, const double *V2, size_t rows,
+                        int m0p, int m0, double *partial, double *G1, double *G2,
+                        hipStream_t st);
+size_t gram_partial_doubles(size_t rows, int m0p);
+hipError_t launch_gemm_qphi(const double *Q, size_t rows, int m0p, int m0,
+                            const double *Phi, double *X, hipStream_t st);
+hipError_t launch_residuals(const double *AX, const double *BX, const double *lam,
+                            size_t rows, int m0p, int m0, double emin, double emax,
+                            double *partial, double *res, hipStream_t st);
+size_t residual_partial_doubles(size_t rows, int m0p);
+hipError_t launch_check_finite(const double *x, size_t count, int *flag, hipStream_t st);
+hipError_t launch_gather(const double *src, const int *perm, int m, double *dst,
+                         hipStream_t st);
+
+// Reduced eigenproblem (rr.hip): one workgroup.
+// scratch: 4 * 128 * 128 doubles.  eps, Phi outputs; flag[0] = fallback.
+hipError_t launch_reduced_eig(const double *AQ, const double *BQ, int n, double *eps,
+                              double *Phi, double *scratch, int *flag, hipStream_t st);
+
+}  // namespace feast

@@ -1,0 +1,283 @@
+// Forward and back sweeps of the twisted block factorisation: the shifted
+// solves (Z_e B - A) Q_e = B Y of Fig. 2 step 2 for every node e and every
+// right-hand side, fused with the quadrature weight of eq. 15.
+//
+// One workgroup runs one chain: (node e, tile of 8 complex right-hand sides,
+// top or bottom half).  With complex symmetric factors (Sinv_j = Sinv_j^T,
+// U_j^T Sinv_j = W_j^T) the forward sweep needs one product on its critical
+// path:
+//   h_0 = R_0,  h_{j+1} = R_{j+1} - W_j^T h_j,   g_j = Sinv_j h_j,
+// the twist cell solves x_{m-1} = T (h_{m-1} - W~_m^T h~_m) and the back
+// sweep is
+//   x_j = g_j - W_j x_{j+1}   (top),   x_j = g~_j - W~_j x_{j-1}   (bottom).
+// The back sweep writes P_e = Re(kappa_e x) so that Q = sum_e P_e.
+//
+// Products run on V_MFMA_F64_16X16X4_F64 with the complex product written as
+// one real product over a doubled inner dimension:
+//   [Mr | Mi] (16 x 2BP)  x  [[hr | hi]; [-hi | hr]] (2BP x 16)  =  [Re | Im].
+// The matrix operand streams from global memory (L2); the vector operand
+// comes from LDS, where each step leaves its result for the next one.
+#include "common.h"
+#include "kernels.h"
+
+namespace feast {
+namespace {
+
+template <int BP>
+struct VecLds {
+  double v[2][2][BP][kTile];  // [buffer][plane][row][col]
+};
+
+// acc0/acc1 (+)= sign * A' * B', A'[row][k] = Mp[kr*BP + row] (plane p of the
+// stored block, i.e. the product uses the transpose of the stored block),
+// B' = stacked complex vector from LDS buffer hv.
+template <int BP>
+__device__ __forceinline__ void prod_stored_T(d4 &acc0, d4 &acc1, const double *__restrict__ M,
+                                              const double (*hv)[BP][kTile], double sign) {
+  const int l = lane_id(), w = wave_id();
+  const int row = w * 16 + (l & 15);
+  const int kl = l >> 4;
+  const int n = l & 15;
+  const int col = n & 7;
+  const double *h0 = (n < 8) ? &hv[0][0][0] : &hv[1][0][0];  // plane-0 k rows
+  const double *h1 = (n < 8) ? &hv[1][0][0] : &hv[0][0][0];  // plane-1 k rows
+  const double s1 = (n < 8) ? -1.0 : 1.0;
+  const double *Mr = M, *Mi = M + BP * BP;
+#pragma unroll 4
+  for (int k0 = 0; k0 < BP; k0 += 8) {
+    const int ka = k0 + kl, kb = k0 + 4 + kl;
+    double a0 = sign * Mr[ka * BP + row], a1 = sign * Mr[kb * BP + row];
+    double b0 = h0[ka * kTile + col], b1 = h0[kb * kTile + col];
+    acc0 = mfma(a0, b0, acc0);
+    acc1 = mfma(a1, b1, acc1);
+  }
+#pragma unroll 4
+  for (int k0 = 0; k0 < BP; k0 += 8) {
+    const int ka = k0 + kl, kb = k0 + 4 + kl;
+    double a0 = sign * Mi[ka * BP + row], a1 = sign * Mi[kb * BP + row];
+    double b0 = s1 * h1[ka * kTile + col], b1 = s1 * h1[kb * kTile + col];
+    acc0 = mfma(a0, b0, acc0);
+    acc1 = mfma(a1, b1, acc1);
+  }
+}
+
+// Accumulator tile <-> vector tile [2][BP][8] (global or LDS).
+template <int BP>
+__device__ __forceinline__ void acc_store_vec(double *dst, const d4 &acc) {
+  const int l = lane_id(), w = wave_id();
+  const int n = l & 15, plane = n >> 3, col = n & 7;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = w * 16 + acc_row(l, r);
+    dst[(plane * BP + row) * kTile + col] = acc[r];
+  }
+}
+
+template <int BP>
+__device__ __forceinline__ d4 acc_load_vec(const double *src) {
+  const int l = lane_id(), w = wave_id();
+  const int n = l & 15, plane = n >> 3, col = n & 7;
+  d4 a;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = w * 16 + acc_row(l, r);
+    a[r] = src[(plane * BP + row) * kTile + col];
+  }
+  return a;
+}
+
+// Accumulator <- real right-hand side tile (imaginary part 0).
+template <int BP>
+__device__ __forceinline__ d4 acc_load_rhs(const double *R, int m0p) {
+  const int l = lane_id(), w = wave_id();
+  const int n = l & 15;
+  d4 a;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = w * 16 + acc_row(l, r);
+    a[r] = (n < 8) ? R[(size_t)row * m0p + n] : 0.0;
+  }
+  return a;
+}
+
+struct SweepArgs {
+  Pencil p;
+  Factors f;
+  SolveBufs sb;
+  const double *R;   // padded [nc][bp][m0p]
+  double *P;         // [Ne][nc][bp][m0p]  (or Xre for the complex variant)
+  double *Xim;       // complex variant only
+  int m0p, ntiles;
+  double kre[kMaxNe], kim[kMaxNe];
+};
+
+template <int BP>
+__global__ __launch_bounds__(BP * 4) void forward_kernel(SweepArgs a) {
+  __shared__ VecLds<BP> s;
+  const int item = xcd_item(blockIdx.x, gridDim.x, a.ntiles);
+  const int tau = item % a.ntiles;
+  const int grp = item / a.ntiles;
+  const int e = grp >> 1;
+  const bool top = (grp & 1) == 0;
+  const int nc = a.p.nc, m = a.f.m;
+  const int len = top ? m : nc - m;
+  if (len <= 0) return;
+  const int dir = top ? 1 : -1;
+  const int start = top ? 0 : nc - 1;
+  const size_t blk = 2 * (size_t)BP * BP;
+  const size_t vt = 2 * (size_t)BP * kTile;
+  const double *Sinv = a.f.Sinv + (size_t)e * nc * blk;
+  const double *W = a.f.W + (size_t)e * nc * blk;
+  double *G = a.sb.G + ((size_t)e * a.ntiles + tau) * nc * vt;
+  double *TV = a.sb.TV + ((size_t)e * a.ntiles + tau) * 2 * vt;
+  const double *R = a.R + tau * kTile;
+  const size_t rstride = (size_t)BP * a.m0p;
+
+  // h_0 = R_start
+  {
+    d4 h = acc_load_rhs<BP>(R + start * rstride, a.m0p);
+    acc_store_vec<BP>(&s.v[0][0][0][0], h);
+  }
+  __syncthreads();
+  int cur = 0;
+  for (int j = 0; j < len; ++j) {
+    const int c = start + dir * j;
+    const auto hv = s.v[cur];
+    if (top && j == len - 1) {
+      d4 h = acc_load_vec<BP>(&hv[0][0][0]);
+      acc_store_vec<BP>(TV, h);  // h_{m-1}
+      break;
+    }
+    d4 g0 = d4zero(), g1 = d4zero();
+    prod_stored_T<BP>(g0, g1, Sinv + c * blk, hv, 1.0);
+    const bool more = (j < len - 1);
+    d4 h0, h1 = d4zero();
+    if (more)
+      h0 = acc_load_rhs<BP>(R + (c + dir) * rstride, a.m0p);
+    else
+      h0 = d4zero();
+    prod_stored_T<BP>(h0, h1, W + c * blk, hv, -1.0);
+    acc_store_vec<BP>(G + c * vt, g0 + g1);
+    if (more) {
+      acc_store_vec<BP>(&s.v[cur ^ 1][0][0][0], h0 + h1);
+    } else {
+      acc_store_vec<BP>(TV + vt, h0 + h1);  // c = -W~_m^T h~_m
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+}
+
+template <int BP, bool COMPLEX_OUT>
+__global__ __launch_bounds__(BP * 4) void back_kernel(SweepArgs a) {
+  __shared__ VecLds<BP> s;
+  const int item = xcd_item(blockIdx.x, gridDim.x, a.ntiles);
+  const int tau = item % a.ntiles;
+  const int grp = item / a.ntiles;
+  const int e = grp >> 1;
+  const bool top = (grp & 1) == 0;
+  const int nc = a.p.nc, m = a.f.m;
+  const int len = top ? m : nc - m;
+  if (len <= 0) return;
+  const size_t blk = 2 * (size_t)BP * BP;
+  const size_t vt = 2 * (size_t)BP * kTile;
+  const double *Sinv = a.f.Sinv + (size_t)e * nc * blk;
+  const double *WT = a.f.WT + (size_t)e * nc * blk;
+  const double *G = a.sb.G + ((size_t)e * a.ntiles + tau) * nc * vt;
+  const double *TV = a.sb.TV + ((size_t)e * a.ntiles + tau) * 2 * vt;
+  const size_t pstride = (size_t)BP * a.m0p;
+  double *P = COMPLEX_OUT ? a.P : a.P + (size_t)e * nc * pstride;
+  const double kr = a.kre[e], ki = a.kim[e];
+  const int l = lane_id(), w = wave_id();
+  const int n = l & 15;
+
+  auto emit = [&](int c, const d4 &x) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double other = __shfl_xor(x[r], 8);
+      const int row = w * 16 + acc_row(l, r);
+      const size_t off = (size_t)c * pstride + (size_t)row * a.m0p + tau * kTile + (n & 7);
+      if (COMPLEX_OUT) {
+        if (n < 8) a.P[off] = x[r];
+        else a.Xim[off] = x[r];
+      } else if (n < 8) {
+        P[off] = kr * x[r] - ki * other;
+      }
+    }
+  };
+
+  // twist cell: x_{m-1} = T (h_{m-1} + c)
+  {
+    d4 t = acc_load_vec<BP>(TV);
+    if (nc - m > 0) t += acc_load_vec<BP>(TV + vt);
+    acc_store_vec<BP>(&s.v[1][0][0][0], t);
+  }
+  __syncthreads();
+  {
+    d4 x0 = d4zero(), x1 = d4zero();
+    prod_stored_T<BP>(x0, x1, Sinv + (m - 1) * blk, s.v[1], 1.0);
+    d4 x = x0 + x1;
+    acc_store_vec<BP>(&s.v[0][0][0][0], x);
+    if (top) emit(m - 1, x);
+  }
+  __syncthreads();
+  int cur = 0;
+  const int count = top ? m - 1 : nc - m;
+  for (int j = 0; j < count; ++j) {
+    const int c = top ? (m - 2 - j) : (m + j);
+    d4 x0 = acc_load_vec<BP>(G + c * vt), x1 = d4zero();
+    prod_stored_T<BP>(x0, x1, WT + c * blk, s.v[cur], -1.0);
+    d4 x = x0 + x1;
+    acc_store_vec<BP>(&s.v[cur ^ 1][0][0][0], x);
+    emit(c, x);
+    __syncthreads();
+    cur ^= 1;
+  }
+}
+
+template <int BP>
+hipError_t launch_sweeps_bp(SweepArgs &a, int Ne, bool complex_out, hipStream_t st) {
+  const int nblocks = Ne * 2 * a.ntiles;
+  hipLaunchKernelGGL(forward_kernel<BP>, dim3(nblocks), dim3(BP * 4), 0, st, a);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  if (complex_out)
+    hipLaunchKernelGGL((back_kernel<BP, true>), dim3(nblocks), dim3(BP * 4), 0, st, a);
+  else
+    hipLaunchKernelGGL((back_kernel<BP, false>), dim3(nblocks), dim3(BP * 4), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t dispatch(SweepArgs &a, int Ne, bool complex_out, hipStream_t st) {
+  switch (a.p.bp) {
+    case 16: return launch_sweeps_bp<16>(a, Ne, complex_out, st);
+    case 32: return launch_sweeps_bp<32>(a, Ne, complex_out, st);
+    case 48: return launch_sweeps_bp<48>(a, Ne, complex_out, st);
+    case 64: return launch_sweeps_bp<64>(a, Ne, complex_out, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_sweeps(const Pencil &p, const Shifts &s, int Ne, const Factors &f,
+                         const SolveBufs &sb, const double *R, int m0p, double *P,
+                         hipStream_t st) {
+  SweepArgs a;
+  a.p = p; a.f = f; a.sb = sb; a.R = R; a.P = P; a.Xim = nullptr;
+  a.m0p = m0p; a.ntiles = m0p / kTile;
+  for (int e = 0; e < kMaxNe; ++e) { a.kre[e] = s.kre[e]; a.kim[e] = s.kim[e]; }
+  return dispatch(a, Ne, false, st);
+}
+
+hipError_t launch_sweeps_complex(const Pencil &p, const Shifts &s, const Factors &f,
+                                 const SolveBufs &sb, const double *R, int m0p,
+                                 double *Xre, double *Xim, hipStream_t st) {
+  SweepArgs a;
+  a.p = p; a.f = f; a.sb = sb; a.R = R; a.P = Xre; a.Xim = Xim;
+  a.m0p = m0p; a.ntiles = m0p / kTile;
+  for (int e = 0; e < kMaxNe; ++e) { a.kre[e] = s.kre[e]; a.kim[e] = s.kim[e]; }
+  return dispatch(a, 1, true, st);
+}
+
+}  // namespace feast

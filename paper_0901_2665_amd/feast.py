@@ -1,0 +1,238 @@
+"""Python binding of libfeast.so (include/feast.h).
+
+Argument marshalling only: every step runs inside the HIP library.  Tensors
+are torch.float64 CUDA(HIP) tensors; torch only provides device memory and the
+stream.  If the library is not built the binding raises; there is no other
+code path.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfeast.so")
+
+_lib = None
+
+
+class FeastError(RuntimeError):
+    def __init__(self, status: int, where: str, lib=None):
+        msg = lib.feast_strerror(status).decode() if lib is not None else ""
+        super().__init__(f"{where}: status {status} ({msg})")
+        self.status = status
+
+
+class BTMatrix(ctypes.Structure):
+    _fields_ = [("nc", ctypes.c_int32), ("b", ctypes.c_int32),
+                ("A_diag", ctypes.c_void_p), ("A_up", ctypes.c_void_p),
+                ("B_diag", ctypes.c_void_p), ("B_up", ctypes.c_void_p)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_loops", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("Y0", ctypes.c_void_p)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("loops", ctypes.c_int32), ("M", ctypes.c_int32),
+                ("trace", ctypes.c_double), ("trace_rel", ctypes.c_double),
+                ("max_res", ctypes.c_double), ("status", ctypes.c_int32),
+                ("fallback", ctypes.c_int32),
+                ("trace_hist", ctypes.c_double * 64), ("count_hist", ctypes.c_int32 * 64)]
+
+
+EXPORTED = ["feast_default_opts", "feast_init", "feast_destroy", "feast_strerror",
+            "feast_solve", "feast_contour", "feast_bt_multiply", "feast_shifted_solve",
+            "feast_filter", "feast_project", "feast_reduced_eig"]
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libfeast.so and declare its signatures (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libfeast.so not built ({path}); run __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    P, I32, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    lib.feast_default_opts.argtypes = [ctypes.POINTER(Opts)]
+    lib.feast_default_opts.restype = None
+    lib.feast_init.argtypes = [ctypes.POINTER(P), ctypes.c_int, P]
+    lib.feast_destroy.argtypes = [P]
+    lib.feast_strerror.argtypes = [ctypes.c_int]
+    lib.feast_strerror.restype = ctypes.c_char_p
+    lib.feast_solve.argtypes = [P, ctypes.POINTER(BTMatrix), D, D, I32, I32,
+                                ctypes.POINTER(Opts), P, P, P, ctypes.POINTER(Info)]
+    lib.feast_contour.argtypes = [I32, D, D, P, P, P, P, P, P]
+    lib.feast_bt_multiply.argtypes = [P, ctypes.POINTER(BTMatrix), I32, I32, P, P]
+    lib.feast_shifted_solve.argtypes = [P, ctypes.POINTER(BTMatrix), D, D, I32, P, P, P]
+    lib.feast_filter.argtypes = [P, ctypes.POINTER(BTMatrix), D, D, I32, I32, P, P]
+    lib.feast_project.argtypes = [P, ctypes.POINTER(BTMatrix), I32, P, P, P]
+    lib.feast_reduced_eig.argtypes = [P, I32, P, P, P, P, ctypes.POINTER(I32)]
+    for name in EXPORTED:
+        if name not in ("feast_default_opts", "feast_strerror"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def contour(ne: int, emin: float, emax: float):
+    """Host-side Gauss-Legendre rule and contour (eqs. 13-15)."""
+    lib = load_library()
+    out = [np.zeros(ne) for _ in range(6)]
+    st = lib.feast_contour(ne, emin, emax, *[o.ctypes.data for o in out])
+    if st != 0:
+        raise FeastError(st, "feast_contour", lib)
+    x, w, zr, zi, kr, ki = out
+    return x, w, zr + 1j * zi, kr + 1j * ki
+
+
+@dataclasses.dataclass
+class SolveResult:
+    lam: "object"          # torch tensor [M0] (device)
+    X: "object"            # torch tensor [N][M0] (device)
+    res: "object"          # torch tensor [M0] (device)
+    M: int
+    loops: int
+    trace: float
+    trace_rel: float
+    max_res: float
+    status: int
+    fallback: int
+    traces: list
+    counts: list
+
+
+def _ptr(t):
+    import torch
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float64 device tensor")
+    return t.data_ptr()
+
+
+class Pencil:
+    """Device copy of a block-tridiagonal pencil (torch float64 tensors)."""
+
+    def __init__(self, Ad, Au, Bd, Bu, device="cuda"):
+        import torch
+        f = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64,
+                                      device=device).contiguous()
+        self.Ad, self.Au, self.Bd, self.Bu = f(Ad), f(Au), f(Bd), f(Bu)
+        self.nc, self.b = int(self.Ad.shape[0]), int(self.Ad.shape[1])
+        self.n = self.nc * self.b
+
+    def struct(self) -> BTMatrix:
+        up_a = self.Au.data_ptr() if self.Au.numel() else None
+        up_b = self.Bu.data_ptr() if self.Bu.numel() else None
+        return BTMatrix(self.nc, self.b, self.Ad.data_ptr(), up_a, self.Bd.data_ptr(), up_b)
+
+
+class Context:
+    """A feast_ctx bound to a device and to torch's current stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.lib = load_library()
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self._stream = stream
+        h = ctypes.c_void_p()
+        st = self.lib.feast_init(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream))
+        if st != 0:
+            raise FeastError(st, "feast_init", self.lib)
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.feast_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, where, warn_ok=False):
+        if st < 0 or (st > 0 and not warn_ok):
+            raise FeastError(st, where, self.lib)
+        return st
+
+    def solve(self, p: Pencil, emin: float, emax: float, M0: int, Ne: int, Y0,
+              tol: float = 1e-12, max_loops: int = 20, out=None) -> SolveResult:
+        import torch
+        dev = p.Ad.device
+        if out is None:
+            lam = torch.empty(M0, dtype=torch.float64, device=dev)
+            X = torch.empty((p.n, M0), dtype=torch.float64, device=dev)
+            res = torch.empty(M0, dtype=torch.float64, device=dev)
+        else:
+            lam, X, res = out
+        opts = Opts(tol, max_loops, 0, _ptr(Y0))
+        info = Info()
+        ab = p.struct()
+        st = self.lib.feast_solve(self.handle, ctypes.byref(ab), emin, emax, M0, Ne,
+                                  ctypes.byref(opts), _ptr(lam), _ptr(X), _ptr(res),
+                                  ctypes.byref(info))
+        self._check(st, "feast_solve", warn_ok=True)
+        n = min(info.loops, 64)
+        return SolveResult(lam, X, res, info.M, info.loops, info.trace, info.trace_rel,
+                           info.max_res, st, info.fallback, list(info.trace_hist[:n]),
+                           list(info.count_hist[:n]))
+
+    def bt_multiply(self, p: Pencil, which: int, V):
+        import torch
+        out = torch.empty_like(V)
+        ab = p.struct()
+        st = self.lib.feast_bt_multiply(self.handle, ctypes.byref(ab), which, V.shape[1],
+                                        _ptr(V), _ptr(out))
+        self._check(st, "feast_bt_multiply")
+        return out
+
+    def shifted_solve(self, p: Pencil, z: complex, R):
+        import torch
+        xr, xi = torch.empty_like(R), torch.empty_like(R)
+        ab = p.struct()
+        st = self.lib.feast_shifted_solve(self.handle, ctypes.byref(ab), z.real, z.imag,
+                                          R.shape[1], _ptr(R), _ptr(xr), _ptr(xi))
+        self._check(st, "feast_shifted_solve")
+        return xr, xi
+
+    def filter(self, p: Pencil, emin: float, emax: float, Ne: int, Y):
+        import torch
+        Q = torch.empty_like(Y)
+        ab = p.struct()
+        st = self.lib.feast_filter(self.handle, ctypes.byref(ab), emin, emax, Y.shape[1], Ne,
+                                   _ptr(Y), _ptr(Q))
+        self._check(st, "feast_filter")
+        return Q
+
+    def project(self, p: Pencil, Q):
+        import torch
+        m0 = Q.shape[1]
+        AQ = torch.empty((m0, m0), dtype=torch.float64, device=Q.device)
+        BQ = torch.empty_like(AQ)
+        ab = p.struct()
+        st = self.lib.feast_project(self.handle, ctypes.byref(ab), m0, _ptr(Q), _ptr(AQ),
+                                    _ptr(BQ))
+        self._check(st, "feast_project")
+        return AQ, BQ
+
+    def reduced_eig(self, AQ, BQ):
+        import torch
+        m0 = AQ.shape[0]
+        eps = torch.empty(m0, dtype=torch.float64, device=AQ.device)
+        Phi = torch.empty((m0, m0), dtype=torch.float64, device=AQ.device)
+        fb = ctypes.c_int32(0)
+        st = self.lib.feast_reduced_eig(self.handle, m0, _ptr(AQ.contiguous()),
+                                        _ptr(BQ.contiguous()), _ptr(eps), _ptr(Phi),
+                                        ctypes.byref(fb))
+        self._check(st, "feast_reduced_eig")
+        return eps, Phi, bool(fb.value)

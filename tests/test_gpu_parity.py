@@ -1,0 +1,290 @@
+"""GPU parity: every step of the HIP path against the CPU oracle.
+
+All calls go through the C ABI (paper_0901_2665_amd.feast -> libfeast.so).
+Tolerances: float64 throughout; a step that is a plain product or sum is
+held to a few units of rounding times the problem scale; the shifted solves
+to their conditioning; FEAST outputs to the contract (same M, eigenvalues
+within 1e-10 relative, residuals <= 1e-9).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import feast_oracle as O
+from paper_0901_2665_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU tests need a HIP device"
+    return _t
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    from paper_0901_2665_amd import feast as F
+    c = F.Context(0)
+    yield c
+    c.close()
+
+
+def dev(torch, a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def gpencil(p):
+    from paper_0901_2665_amd import feast as F
+    return F.Pencil(p.Ad, p.Au, p.Bd, p.Bu)
+
+
+def chain_small(nc, b, seed):
+    if b == 64:
+        return W.chain_pencil(nc, b, seed)
+    return W.dense_random_pencil(nc, b, seed)
+
+
+SHAPES = [(1, 5, 3), (2, 16, 16), (3, 17, 30), (20, 40, 30), (7, 64, 128), (5, 33, 100),
+          (9, 48, 8), (4, 64, 1)]
+
+
+@pytest.mark.parametrize("nc,b,m", SHAPES)
+def test_bt_multiply(ctx, torch, nc, b, m):
+    p = chain_small(nc, b, 100 + nc)
+    V = np.random.default_rng(nc * b).standard_normal((p.n, m))
+    gp = gpencil(p)
+    for which, (d, u) in enumerate([(p.Ad, p.Au), (p.Bd, p.Bu)]):
+        out = host(ctx.bt_multiply(gp, which, dev(torch, V)))
+        ref = O.bt_multiply(d, u, V)
+        assert np.linalg.norm(out - ref) <= 1e-14 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("nc,b,m", SHAPES)
+def test_shifted_solve(ctx, torch, nc, b, m):
+    p = chain_small(nc, b, 200 + nc)
+    R = np.random.default_rng(7 * nc + b).standard_normal((p.n, m))
+    z = 0.37 + 0.05j
+    xr, xi = ctx.shifted_solve(gpencil(p), z, dev(torch, R))
+    X = host(xr) + 1j * host(xi)
+    ref = O.shifted_solve(p, z, R)
+    M = O.shifted_matrix(p, z)
+    berr = np.linalg.norm(R - M @ X) / (spla.norm(M) * np.linalg.norm(X))
+    assert berr <= 1e-14
+    assert np.linalg.norm(X - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("name_or_shape", ["chain800", (9, 16, 24, 4), (3, 3, 5, 16),
+                                           (13, 64, 40, 8)])
+def test_filter(ctx, torch, name_or_shape):
+    if isinstance(name_or_shape, str):
+        p, emin, emax, m0, ne, Y = W.make_workload(name_or_shape)
+    else:
+        nc, b, m0, ne = name_or_shape
+        p = chain_small(nc, b, 300 + nc)
+        lam = O.bruteforce(p)[0]
+        k0 = p.n // 3
+        emin, emax = 0.5 * (lam[k0 - 1] + lam[k0]), 0.5 * (lam[k0 + 3] + lam[k0 + 4])
+        Y = W.random_subspace(p.n, m0, nc)
+    Q = host(ctx.filter(gpencil(p), emin, emax, ne, dev(torch, Y)))
+    ref = O.filter_apply(p, emin, emax, ne, Y)
+    assert np.linalg.norm(Q - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("nc,b,m0", [(20, 40, 30), (6, 64, 128), (3, 7, 5)])
+def test_project(ctx, torch, nc, b, m0):
+    p = chain_small(nc, b, 400 + nc)
+    Q = np.random.default_rng(nc).standard_normal((p.n, m0))
+    AQ, BQ = ctx.project(gpencil(p), dev(torch, Q))
+    ra, rb = O.project(p, Q)
+    assert np.linalg.norm(host(AQ) - ra) <= 1e-13 * np.linalg.norm(ra)
+    assert np.linalg.norm(host(BQ) - rb) <= 1e-13 * np.linalg.norm(rb)
+    assert np.array_equal(host(AQ), host(AQ).T)
+
+
+def spd_pair(n, seed, cond=1e3):
+    rng = np.random.default_rng(seed)
+    Qm, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    mu = np.geomspace(1.0, 1.0 / cond, n)
+    BQ = (Qm * mu) @ Qm.T
+    AQ = rng.standard_normal((n, n))
+    return 0.5 * (AQ + AQ.T), 0.5 * (BQ + BQ.T)
+
+
+def feast_like_pair(n, seed, smallest=1e-6):
+    """Reduced matrices as FEAST produces them near convergence: Q ~ X D with
+    a filter-like scaling D, so B_Q ~ D^2 is ill conditioned while the pencil
+    keeps well separated, well conditioned eigenvalues."""
+    rng = np.random.default_rng(seed)
+    lam = np.sort(rng.uniform(-3, 3, n))
+    d = np.geomspace(1.0, smallest, n)
+    Qm, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    G = Qm * d                       # columns scaled
+    E = 1e-3 * rng.standard_normal((n, n))
+    G = (np.eye(n) + E) @ G
+    AQ = G.T @ np.diag(lam) @ G
+    BQ = G.T @ G
+    return 0.5 * (AQ + AQ.T), 0.5 * (BQ + BQ.T), lam
+
+
+def rr_backward_error(AQ, BQ, eps, Phi):
+    r = AQ @ Phi - (BQ @ Phi) * eps
+    den = (np.linalg.norm(AQ, 2) + np.abs(eps) * np.linalg.norm(BQ, 2)) * \
+        np.linalg.norm(Phi, axis=0)
+    return np.max(np.linalg.norm(r, axis=0) / den)
+
+
+@pytest.mark.parametrize("n,cond", [(1, 1.0), (7, 10.0), (30, 1e2), (64, 1e3), (128, 1e3)])
+def test_reduced_eig_well_conditioned(ctx, torch, n, cond):
+    AQ, BQ = spd_pair(n, n, cond)
+    eps, Phi, fb = ctx.reduced_eig(dev(torch, AQ), dev(torch, BQ))
+    eps, Phi = host(eps), host(Phi)
+    ref, _, rfb = O.reduced_eig(AQ, BQ)
+    assert not fb and not rfb
+    assert np.max(np.abs(eps - ref)) <= 1e-12 * np.max(np.abs(ref))
+    assert np.max(np.abs(Phi.T @ BQ @ Phi - np.eye(n))) <= 1e-12
+    assert rr_backward_error(AQ, BQ, eps, Phi) <= 1e-14
+    assert np.all(np.diff(eps) >= 0)
+
+
+@pytest.mark.parametrize("n,smallest", [(30, 1e-5), (80, 1e-6), (128, 1e-7)])
+def test_reduced_eig_feast_like(ctx, torch, n, smallest):
+    AQ, BQ, lam = feast_like_pair(n, n + 1, smallest)
+    eps, Phi, fb = ctx.reduced_eig(dev(torch, AQ), dev(torch, BQ))
+    eps, Phi = host(eps), host(Phi)
+    ref, _, rfb = O.reduced_eig(AQ, BQ)
+    assert not fb and not rfb
+    assert np.max(np.abs(eps - ref)) <= 1e-11 * np.max(np.abs(ref))
+    assert np.max(np.abs(Phi.T @ BQ @ Phi - np.eye(n))) <= 1e-9
+
+
+@pytest.mark.parametrize("n,cond", [(30, 1e6), (127, 1e8), (128, 1e10)])
+def test_reduced_eig_ill_conditioned_backward_stable(ctx, torch, n, cond):
+    # eigenvalues of a random pencil with cond(B_Q) = cond are themselves ill
+    # conditioned; both solvers are backward stable, so compare residuals and
+    # eigenvalues to eps * cond(B_Q).
+    AQ, BQ = spd_pair(n, n, cond)
+    eps, Phi, fb = ctx.reduced_eig(dev(torch, AQ), dev(torch, BQ))
+    eps, Phi = host(eps), host(Phi)
+    ref, _, _ = O.reduced_eig(AQ, BQ)
+    assert not fb
+    assert rr_backward_error(AQ, BQ, eps, Phi) <= 1e-13
+    assert np.max(np.abs(eps - ref)) <= 1e-15 * cond * np.max(np.abs(ref))
+
+
+def test_reduced_eig_fallback(ctx, torch):
+    rng = np.random.default_rng(8)
+    G = rng.standard_normal((10, 6))
+    BQ = G @ G.T
+    AQ = G @ np.diag(np.arange(1.0, 7.0)) @ G.T
+    eps, Phi, fb = ctx.reduced_eig(dev(torch, AQ), dev(torch, BQ))
+    eps, Phi = host(eps), host(Phi)
+    ref, _, rfb = O.reduced_eig(AQ, BQ)
+    assert fb and rfb
+    assert np.sum(np.isfinite(eps)) == np.sum(np.isfinite(ref)) == 6
+    assert np.allclose(eps[:6], ref[:6], atol=1e-8)
+    assert np.all(np.isnan(eps[6:])) and np.all(Phi[:, 6:] == 0)
+
+
+def check_against_oracle(r, ref, p, emin, emax):
+    assert r.M == ref.M
+    M = r.M
+    lam = host(r.lam)
+    scale = np.maximum(np.abs(ref.lam[:M]), (emax - emin) / 2)
+    assert np.max(np.abs(lam[:M] - ref.lam[:M]) / scale, initial=0) <= 1e-10
+    res = host(r.res)
+    assert np.max(res[:M], initial=0) <= 1e-9
+    assert abs(r.loops - ref.loops) <= 1
+    X = host(r.X)[:, :M]
+    B = O.assemble(p.Bd, p.Bu)
+    assert np.max(np.abs(X.T @ (B @ X) - np.eye(M)), initial=0) <= 1e-9
+    # the in-interval subspaces agree (principal angles)
+    if M:
+        Xo = ref.X[:, :M]
+        G = Xo.T @ (B @ X)
+        s = np.linalg.svd(G, compute_uv=False)
+        assert np.min(s) >= 1 - 1e-9
+
+
+def test_solve_chain800(ctx, torch):
+    p, emin, emax, m0, ne, Y0 = W.make_workload("chain800")
+    r = ctx.solve(gpencil(p), emin, emax, m0, ne, dev(torch, Y0))
+    ref = O.feast(p, emin, emax, m0, ne, Y0)
+    assert r.status == 0
+    check_against_oracle(r, ref, p, emin, emax)
+    lam_b = O.bruteforce(p)[0]
+    assert np.max(np.abs(host(r.lam)[:20] - lam_b[200:220]) / np.abs(lam_b[200:220])) <= 1e-12
+
+
+@pytest.mark.parametrize("nc,b,seed,k0,m,extra", [
+    (2, 3, 1, 1, 2, 2), (3, 4, 2, 3, 4, 3), (4, 5, 3, 5, 6, 4), (6, 8, 4, 10, 12, 6),
+    (1, 9, 5, 2, 3, 2), (7, 16, 6, 30, 10, 8), (11, 20, 7, 60, 15, 9)])
+def test_solve_small(ctx, torch, nc, b, seed, k0, m, extra):
+    p = W.dense_random_pencil(nc, b, seed)
+    lam = O.bruteforce(p)[0]
+    emin, emax = 0.5 * (lam[k0 - 1] + lam[k0]), 0.5 * (lam[k0 + m - 1] + lam[k0 + m])
+    m0 = min(m + extra, p.n)
+    Y0 = W.random_subspace(p.n, m0, seed + 100)
+    r = ctx.solve(gpencil(p), emin, emax, m0, 8, dev(torch, Y0), tol=1e-13, max_loops=40)
+    ref = O.feast(p, emin, emax, m0, 8, Y0, tol=1e-13, max_loops=40)
+    assert r.status == ref.status
+    check_against_oracle(r, ref, p, emin, emax)
+
+
+def test_solve_tb6400_golden(ctx, torch):
+    g = json.load(open(os.path.join(GOLDEN, "feast_tb6400.json")))
+    p, emin, emax, m0, ne, Y0 = W.make_workload("tb6400")
+    r = ctx.solve(gpencil(p), emin, emax, m0, ne, dev(torch, Y0))
+    assert r.status == 0 and r.M == g["M"] == 80
+    lam = host(r.lam)[:80]
+    ref = np.array(g["lam"])
+    assert np.max(np.abs(lam - ref) / np.abs(ref)) <= 1e-10
+    assert np.max(host(r.res)[:80]) <= 1e-9
+    assert abs(r.loops - g["loops"]) <= 1
+
+
+def test_empty_interval(ctx, torch):
+    p = W.dense_random_pencil(3, 8, 9)
+    lam = O.bruteforce(p)[0]
+    gap = np.argmax(np.diff(lam))
+    emin = lam[gap] + 0.3 * (lam[gap + 1] - lam[gap])
+    emax = lam[gap] + 0.7 * (lam[gap + 1] - lam[gap])
+    Y0 = W.random_subspace(p.n, 4, 3)
+    r = ctx.solve(gpencil(p), emin, emax, 4, 8, dev(torch, Y0))
+    assert r.status == 3 and r.M == 0
+
+
+def test_bad_arguments(ctx, torch):
+    from paper_0901_2665_amd import feast as F
+    p = W.dense_random_pencil(3, 8, 9)
+    gp = gpencil(p)
+    Y0 = dev(torch, W.random_subspace(p.n, 4, 3))
+    with pytest.raises(F.FeastError) as e:
+        ctx.solve(gp, 1.0, 0.0, 4, 8, Y0)
+    assert e.value.status == -2
+    with pytest.raises(F.FeastError) as e:
+        ctx.solve(gp, 0.0, 1.0, 4, 0, Y0)
+    assert e.value.status == -4
+    bad = W.Pencil(p.Ad.copy(), p.Au, p.Bd, p.Bu)
+    bad.Ad[1, 2, 3] = np.nan
+    with pytest.raises(F.FeastError) as e:
+        ctx.solve(gpencil(bad), 0.0, 1.0, 4, 8, Y0)
+    assert e.value.status == -6
+
+
+def test_deterministic(ctx, torch):
+    p, emin, emax, m0, ne, Y0 = W.make_workload("chain800")
+    gp, y = gpencil(p), dev(torch, Y0)
+    a = ctx.solve(gp, emin, emax, m0, ne, y)
+    b = ctx.solve(gp, emin, emax, m0, ne, y)
+    assert torch.equal(a.lam, b.lam) and torch.equal(a.X, b.X) and torch.equal(a.res, b.res)

@@ -89,6 +89,7 @@ typedef struct {
   int32_t fallback;      /* 1 if the last loop used the B_Q fallback */
   double trace_hist[64]; /* trace per loop (first min(loops,64) entries) */
   int32_t count_hist[64];/* M per loop */
+  int32_t rr_sweeps;     /* Jacobi sweeps of the reduced eigensolver, all loops */
 } feast_info;
 
 /* Default options: tol 1e-12, max_loops 20, precision 0, Y0 NULL. */
@@ -170,6 +171,22 @@ int feast_project(feast_ctx *ctx, const feast_bt_matrix *AB, int32_t M0,
  */
 int feast_reduced_eig(feast_ctx *ctx, int32_t M0, const double *AQ, const double *BQ,
                       double *eps, double *Phi, int32_t *fallback);
+
+/* ---- instrumentation ---- */
+
+/*
+ * Kernel timing.  feast_timing(ctx, 1) clears the records and, until
+ * feast_timing(ctx, 0), brackets every kernel class that feast_solve launches
+ * with hipEvents on the context's stream.  feast_timing_read(ctx, k, ...)
+ * synchronises the stream and returns, for class k, its name (static
+ * string), the summed event time in milliseconds and the number of launches;
+ * with k < 0 it returns the number of classes.  Classes: factor,
+ * forward_sweep, back_sweep, bt_multiply, sum_nodes, gram, reduced_eig,
+ * ritz_gemm, residual, layout.
+ */
+int feast_timing(feast_ctx *ctx, int32_t enable);
+int feast_timing_read(feast_ctx *ctx, int32_t kind, const char **name, double *total_ms,
+                      int64_t *launches);
 
 #ifdef __cplusplus
 }

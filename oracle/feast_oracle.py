@@ -17,17 +17,24 @@ Readings of points the paper leaves open (the same on the GPU path):
   * RHS of every refinement loop is B.Y with Y = Y0 first and Y = X after
     (Fig. 2 solves with Y at the first loop and with Y = BX later; one code
     path, equally random at the first loop).
-  * Convergence: from the second loop on, stop when the number M of Ritz
-    values inside [emin, emax] is unchanged and the relative change of their
-    trace |T_k - T_{k-1}| / max(|T_k|, M*r) is below tol (Sec. III.B (i) and
-    Sec. IV.A give the trace test without fixing its denominator).
+  * An in-interval Ritz pair counts as an eigenvalue solution (Fig. 2 step
+    5) once its relative residual is <= sqrt(tol): for a symmetric pencil the
+    eigenvalue error is of the order of the squared residual, so such a pair
+    is accurate to tol.  Pairs inside the interval with larger residuals are
+    not counted (with M0 well above M, mixtures of eigenvectors from both
+    sides of the interval that share a filter value give in-interval Ritz
+    values with large residuals that persist over many loops).
+  * Convergence: from the second loop on, stop when the number M of counted
+    pairs is unchanged and the relative change of their trace
+    |T_k - T_{k-1}| / max(|T_k|, M*r) is below tol (Sec. III.B (i) and Sec.
+    IV.A give the trace test without fixing its denominator).
   * Residual of a pair: ||A x - lam B x||_1 / ||A x||_1 (Table I caption); if
     ||A x||_1 < r ||B x||_1 the denominator is ||B x||_1 max(|emin|,|emax|,r).
   * If B_Q is not numerically s.p.d. (Sec. III.B (ii)), B_Q is diagonalised,
     directions with eigenvalue <= 1e-14 * max are dropped, and the dropped
     Ritz slots are returned last with lam = NaN, x = 0, status 2.
-  * Output order: Ritz values inside the interval first (ascending), then the
-    others (ascending).  Membership is inclusive (Fig. 2 step 5).
+  * Output order: the M counted pairs first (ascending), then the other Ritz
+    values (ascending), NaN slots last.  Membership is inclusive.
 """
 from __future__ import annotations
 
@@ -249,14 +256,21 @@ def residuals(p, lam: np.ndarray, X: np.ndarray, emin: float, emax: float) -> np
         return num / den
 
 
-def order_ritz(eps: np.ndarray, emin: float, emax: float) -> np.ndarray:
-    """Permutation: in-interval Ritz values first (ascending), then the rest
-    (ascending), NaN slots last."""
+def counted(eps: np.ndarray, res: np.ndarray, emin: float, emax: float,
+            tol: float) -> np.ndarray:
+    """Mask of the Ritz pairs that count as eigenvalue solutions: inside the
+    interval (inclusive) with relative residual <= sqrt(tol)."""
+    with np.errstate(invalid="ignore"):
+        return (eps >= emin) & (eps <= emax) & (res <= np.sqrt(tol))
+
+
+def order_ritz(eps: np.ndarray, mask: np.ndarray) -> np.ndarray:
+    """Permutation: counted pairs first (ascending), then the other finite
+    Ritz values (ascending), NaN slots last."""
     idx = np.arange(len(eps))
-    inside = (eps >= emin) & (eps <= emax)
     finite = np.isfinite(eps)
-    a = idx[inside]
-    b_ = idx[~inside & finite]
+    a = idx[mask]
+    b_ = idx[~mask & finite]
     c = idx[~finite]
     return np.concatenate([a[np.argsort(eps[a], kind="stable")],
                            b_[np.argsort(eps[b_], kind="stable")], c])
@@ -278,8 +292,9 @@ class FeastResult:
 
 
 def feast(p, emin: float, emax: float, m0: int, ne: int, Y0: np.ndarray,
-          tol: float = 1e-12, max_loops: int = 20) -> FeastResult:
-    """Fig. 2: FEAST for A x = lam B x, A real symmetric, B s.p.d."""
+          tol: float = 1e-12, max_loops: int = 20, log=None) -> FeastResult:
+    """Fig. 2: FEAST for A x = lam B x, A real symmetric, B s.p.d.
+    ``log(k, M_k, T_k, trace_rel)`` is called after every loop if given."""
     ct = contour(emin, emax, ne)
     factors = [factor_shift(p, ct.Z[e]) for e in range(ne)]   # once (Sec. V (ii))
     Y = np.array(Y0, dtype=np.float64, copy=True)
@@ -292,7 +307,8 @@ def feast(p, emin: float, emax: float, m0: int, ne: int, Y0: np.ndarray,
         AQ, BQ = project(p, Q)
         eps, Phi, fallback = reduced_eig(AQ, BQ)
         X = Q @ Phi
-        inside = (eps >= emin) & (eps <= emax)
+        res = residuals(p, eps, X, emin, emax)
+        inside = counted(eps, res, emin, emax, tol)
         Mk = int(inside.sum())
         Tk = float(np.sum(eps[inside]))
         if k >= 2:
@@ -302,14 +318,16 @@ def feast(p, emin: float, emax: float, m0: int, ne: int, Y0: np.ndarray,
                 trace_rel = abs(Tk - traces[-1]) / max(abs(Tk), Mk * ct.r)
         traces.append(Tk)
         counts.append(Mk)
+        if log is not None:
+            log(k, Mk, Tk, trace_rel)
         if k >= 2 and Mk == counts[-2] and trace_rel < tol:
             converged = True
             break
         Y = X
-    perm = order_ritz(eps, emin, emax)
+    perm = order_ritz(eps, inside)
     lam = eps[perm]
     X = X[:, perm]
-    res = residuals(p, lam, X, emin, emax)
+    res = res[perm]
     M = counts[-1]
     max_res = float(np.max(res[:M])) if M > 0 else 0.0
     if not converged:

@@ -143,25 +143,26 @@ __device__ void gj_invert(Lds<BP> &s, double *gout) {
           ai[u][v] = upd.im;
         }
       }
+      // publish row and column k+1 (register indices stay compile-time)
       const int k1 = k + 1;
       if (k1 < BP) {
         const int qn = k1 & 1;
-        if (k1 >= 4 * ti && k1 < 4 * ti + 4) {
-          const int u = k1 - 4 * ti;
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            s.row[qn][0][4 * tj + v] = ar[u][v];
-            s.row[qn][1][4 * tj + v] = ai[u][v];
-          }
-        }
-        if (k1 >= 4 * tj && k1 < 4 * tj + 4) {
-          const int v = k1 - 4 * tj;
+        for (int u = 0; u < 4; ++u)
+          if (k1 == 4 * ti + u)
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            s.col[qn][0][4 * ti + u] = ar[u][v];
-            s.col[qn][1][4 * ti + u] = ai[u][v];
-          }
-        }
+            for (int v = 0; v < 4; ++v) {
+              s.row[qn][0][4 * tj + v] = ar[u][v];
+              s.row[qn][1][4 * tj + v] = ai[u][v];
+            }
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (k1 == 4 * tj + v)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              s.col[qn][0][4 * ti + u] = ar[u][v];
+              s.col[qn][1][4 * ti + u] = ai[u][v];
+            }
       }
     }
     __syncthreads();

@@ -34,12 +34,28 @@ enum Slot {
 
 }  // namespace
 
+namespace {
+// Kernel classes timed by feast_timing / feast_timing_read.
+enum Kind { K_FACTOR, K_FORWARD, K_BACK, K_BTMUL, K_SUM, K_GRAM, K_RR, K_RITZ, K_RESID,
+            K_LAYOUT, K_COUNT };
+const char *kKindNames[K_COUNT] = {"factor",      "forward_sweep", "back_sweep", "bt_multiply",
+                                   "sum_nodes",   "gram",          "reduced_eig", "ritz_gemm",
+                                   "residual",    "layout"};
+struct Timing {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<std::pair<int, size_t>> recs;  // (kind, index of the start event)
+};
+}  // namespace
+
 struct feast_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   Buf buf[S_COUNT];
   double *h_eps = nullptr;  // pinned: eps[128] + res[128]
   int *h_flag = nullptr;    // pinned
+  Timing timing;
 };
 
 namespace {
@@ -79,6 +95,29 @@ hipError_t ensure_t(feast_ctx *ctx, Slot s, size_t count, T **out) {
 }
 
 int round16(int x) { return (x + 15) / 16 * 16; }
+
+// Start/stop events around one launch when timing is on.
+hipError_t tmark(feast_ctx *ctx, size_t *idx) {
+  Timing &t = ctx->timing;
+  if (!t.on) return hipSuccess;
+  if (t.used == t.pool.size()) {
+    hipEvent_t ev;
+    hipError_t e = hipEventCreate(&ev);
+    if (e != hipSuccess) return e;
+    t.pool.push_back(ev);
+  }
+  *idx = t.used++;
+  return hipEventRecord(t.pool[*idx], ctx->stream);
+}
+
+#define TIMED(kind, expr)                                   \
+  do {                                                      \
+    size_t _t0 = 0, _t1 = 0;                                \
+    HIPCHK(tmark(ctx, &_t0));                               \
+    HIPCHK(expr);                                           \
+    HIPCHK(tmark(ctx, &_t1));                               \
+    if (ctx->timing.on) ctx->timing.recs.push_back({(kind), _t0}); \
+  } while (0)
 
 // Gauss-Legendre rule on [-1, 1]: Newton on the roots of P_n with the
 // three-term recurrence; weights 2 / ((1 - x^2) P_n'(x)^2).  Ascending nodes.
@@ -230,6 +269,7 @@ int feast_destroy(feast_ctx *ctx) {
   else (void)hipDeviceSynchronize();
   for (auto &b : ctx->buf)
     if (b.ptr) (void)hipFree(b.ptr);
+  for (auto ev : ctx->timing.pool) (void)hipEventDestroy(ev);
   if (ctx->h_eps) (void)hipHostFree(ctx->h_eps);
   if (ctx->h_flag) (void)hipHostFree(ctx->h_flag);
   delete ctx;
@@ -252,6 +292,38 @@ const char *feast_strerror(int status) {
     case 4: return "subspace too small: M = M0";
     default: return status <= -100 ? "HIP runtime error" : "unknown status";
   }
+}
+
+int feast_timing(feast_ctx *ctx, int32_t enable) {
+  if (!ctx) return -5;
+  HIPCHK(hipSetDevice(ctx->device));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  ctx->timing.on = enable != 0;
+  ctx->timing.used = 0;
+  ctx->timing.recs.clear();
+  return 0;
+}
+
+int feast_timing_read(feast_ctx *ctx, int32_t kind, const char **name, double *total_ms,
+                      int64_t *launches) {
+  if (!ctx) return -5;
+  if (kind < 0) return K_COUNT;
+  if (kind >= K_COUNT) return -7;
+  HIPCHK(hipSetDevice(ctx->device));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  double tot = 0.0;
+  int64_t cnt = 0;
+  for (auto &r : ctx->timing.recs) {
+    if (r.first != kind) continue;
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, ctx->timing.pool[r.second], ctx->timing.pool[r.second + 1]));
+    tot += ms;
+    ++cnt;
+  }
+  if (name) *name = kKindNames[kind];
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = cnt;
+  return 0;
 }
 
 int feast_contour(int32_t Ne, double emin, double emax, double *x, double *w, double *z_re,
@@ -345,7 +417,7 @@ int feast_filter(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double 
   HIPCHK(launch_factor(p, s, Ne, wk.f, ctx->stream));
   HIPCHK(launch_pack(Y, p.nc, p.b, p.bp, M0, mp, y, ctx->stream));
   HIPCHK(launch_bt_multiply(p, 1, y, mp, r, ctx->stream));
-  HIPCHK(launch_sweeps(p, s, Ne, wk.f, wk.sb, r, mp, pp, ctx->stream));
+  HIPCHK(launch_sweeps(p, s, Ne, wk.f, wk.sb, r, mp, pp, 3, ctx->stream));
   HIPCHK(launch_sum_nodes(pp, Ne, wk.rows * mp, q, ctx->stream));
   HIPCHK(launch_unpack(q, p.nc, p.b, p.bp, M0, mp, nullptr, Q, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -443,35 +515,49 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
   HIPCHK(ensure_t(ctx, S_PERM, (size_t)M0, &perm));
 
   // factor every shifted matrix once (Sec. V, parallelism (ii))
-  HIPCHK(launch_factor(p, s, Ne, wk.f, sm));
-  HIPCHK(launch_pack(o.Y0, p.nc, p.b, p.bp, M0, mp, y, sm));
+  TIMED(K_FACTOR, launch_factor(p, s, Ne, wk.f, sm));
+  TIMED(K_LAYOUT, launch_pack(o.Y0, p.nc, p.b, p.bp, M0, mp, y, sm));
 
   std::vector<double> traces;
   std::vector<int> counts;
   double trace_rel = INFINITY;
   bool converged = false;
   int fallback = 0;
+  int rr_sweeps = 0;
   double *h_eps = ctx->h_eps;
+  double *h_res = ctx->h_eps + kMaxM0;
+  const double res_gate = std::sqrt(o.tol);
+  std::vector<char> is_counted(M0, 0);
   for (int k = 1; k <= o.max_loops; ++k) {
-    HIPCHK(launch_bt_multiply(p, 1, y, mp, rr, sm));                    // R = B Y
-    HIPCHK(launch_sweeps(p, s, Ne, wk.f, wk.sb, rr, mp, pp, sm));       // Q_e, weighted
-    HIPCHK(launch_sum_nodes(pp, Ne, rows * mp, q, sm));                 // Q (eq. 15)
-    HIPCHK(launch_bt_multiply(p, 0, q, mp, av, sm));                    // A Q
-    HIPCHK(launch_bt_multiply(p, 1, q, mp, bv, sm));                    // B Q
-    HIPCHK(launch_gram2(q, av, bv, rows, mp, M0, gp, aq, bq, sm));      // A_Q, B_Q (eq. 7)
-    HIPCHK(launch_reduced_eig(aq, bq, M0, eps, phi, scr, flag, sm));    // eq. 6
-    HIPCHK(launch_gemm_qphi(q, rows, mp, M0, phi, x, sm));              // X = Q Phi (eq. 9)
+    TIMED(K_BTMUL, launch_bt_multiply(p, 1, y, mp, rr, sm));                 // R = B Y
+    TIMED(K_FORWARD, launch_sweeps(p, s, Ne, wk.f, wk.sb, rr, mp, pp, 1, sm)); // Q_e ...
+    TIMED(K_BACK, launch_sweeps(p, s, Ne, wk.f, wk.sb, rr, mp, pp, 2, sm));    // ... weighted
+    TIMED(K_SUM, launch_sum_nodes(pp, Ne, rows * mp, q, sm));                // Q (eq. 15)
+    TIMED(K_BTMUL, launch_bt_multiply(p, 0, q, mp, av, sm));                 // A Q
+    TIMED(K_BTMUL, launch_bt_multiply(p, 1, q, mp, bv, sm));                 // B Q
+    TIMED(K_GRAM, launch_gram2(q, av, bv, rows, mp, M0, gp, aq, bq, sm));   // A_Q, B_Q (eq. 7)
+    TIMED(K_RR, launch_reduced_eig(aq, bq, M0, eps, phi, scr, flag, sm));   // eq. 6
+    TIMED(K_RITZ, launch_gemm_qphi(q, rows, mp, M0, phi, x, sm));           // X = Q Phi (eq. 9)
+    // residuals of the Ritz pairs (Table I caption) decide which in-interval
+    // pairs count as eigenvalue solutions (relative residual <= sqrt(tol))
+    TIMED(K_BTMUL, launch_bt_multiply(p, 0, x, mp, av, sm));
+    TIMED(K_BTMUL, launch_bt_multiply(p, 1, x, mp, bv, sm));
+    TIMED(K_RESID, launch_residuals(av, bv, eps, rows, mp, M0, emin, emax, resp, resi, sm));
     HIPCHK(hipMemcpyAsync(h_eps, eps, M0 * sizeof(double), hipMemcpyDeviceToHost, sm));
-    HIPCHK(hipMemcpyAsync(ctx->h_flag, flag, sizeof(int), hipMemcpyDeviceToHost, sm));
+    HIPCHK(hipMemcpyAsync(h_res, resi, M0 * sizeof(double), hipMemcpyDeviceToHost, sm));
+    HIPCHK(hipMemcpyAsync(ctx->h_flag, flag, 3 * sizeof(int), hipMemcpyDeviceToHost, sm));
     HIPCHK(hipStreamSynchronize(sm));
     fallback = ctx->h_flag[0];
+    rr_sweeps += ctx->h_flag[1] + (fallback ? ctx->h_flag[2] : 0);
     int Mk = 0;
     double Tk = 0.0;
-    for (int j = 0; j < M0; ++j)
-      if (h_eps[j] >= emin && h_eps[j] <= emax) {
+    for (int j = 0; j < M0; ++j) {
+      is_counted[j] = h_eps[j] >= emin && h_eps[j] <= emax && h_res[j] <= res_gate;
+      if (is_counted[j]) {
         ++Mk;
         Tk += h_eps[j];
       }
+    }
     if (k >= 2) {
       if (Mk == 0 && counts.back() == 0)
         trace_rel = 0.0;
@@ -487,33 +573,28 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
     if (k < o.max_loops) std::swap(y, x);  // Y <- X (Fig. 2 step 6)
   }
 
-  // residuals of the final Ritz pairs (Table I caption)
-  HIPCHK(launch_bt_multiply(p, 0, x, mp, av, sm));
-  HIPCHK(launch_bt_multiply(p, 1, x, mp, bv, sm));
-  HIPCHK(launch_residuals(av, bv, eps, rows, mp, M0, emin, emax, resp, resi, sm));
-
-  // order: in-interval first (ascending), then the rest, NaN slots last
+  // order: counted pairs first (ascending), then the rest, NaN slots last
   std::vector<int> order;
   order.reserve(M0);
   for (int j = 0; j < M0; ++j)
-    if (h_eps[j] >= emin && h_eps[j] <= emax) order.push_back(j);
+    if (is_counted[j]) order.push_back(j);
   for (int j = 0; j < M0; ++j)
-    if (std::isfinite(h_eps[j]) && !(h_eps[j] >= emin && h_eps[j] <= emax)) order.push_back(j);
+    if (std::isfinite(h_eps[j]) && !is_counted[j]) order.push_back(j);
   for (int j = 0; j < M0; ++j)
     if (!std::isfinite(h_eps[j])) order.push_back(j);
   int *h_perm = reinterpret_cast<int *>(ctx->h_eps + 2 * kMaxM0);
   for (int j = 0; j < M0; ++j) h_perm[j] = order[j];
+  std::vector<double> res_sorted(M0);
+  for (int j = 0; j < M0; ++j) res_sorted[j] = h_res[order[j]];
   HIPCHK(hipMemcpyAsync(perm, h_perm, M0 * sizeof(int), hipMemcpyHostToDevice, sm));
-  HIPCHK(launch_unpack(x, p.nc, p.b, p.bp, M0, mp, perm, X, sm));
+  TIMED(K_LAYOUT, launch_unpack(x, p.nc, p.b, p.bp, M0, mp, perm, X, sm));
   HIPCHK(launch_gather(eps, perm, M0, lambda, sm));
   HIPCHK(launch_gather(resi, perm, M0, res, sm));
-  double *h_res = ctx->h_eps + kMaxM0;
-  HIPCHK(hipMemcpyAsync(h_res, res, M0 * sizeof(double), hipMemcpyDeviceToHost, sm));
   HIPCHK(hipStreamSynchronize(sm));
 
   const int M = counts.back();
   double max_res = 0.0;
-  for (int j = 0; j < M; ++j) max_res = std::max(max_res, h_res[j]);
+  for (int j = 0; j < M; ++j) max_res = std::max(max_res, res_sorted[j]);
   int status;
   if (!converged) status = 1;
   else if (fallback) status = 2;
@@ -529,6 +610,7 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
     info->max_res = max_res;
     info->status = status;
     info->fallback = fallback;
+    info->rr_sweeps = rr_sweeps;
     for (size_t k = 0; k < traces.size() && k < 64; ++k) {
       info->trace_hist[k] = traces[k];
       info->count_hist[k] = counts[k];

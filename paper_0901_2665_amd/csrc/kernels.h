@@ -36,8 +36,9 @@ struct SolveBufs {
   double *G;    // [Ne][ntiles][nc][2][bp][8]
   double *TV;   // [Ne][ntiles][2][2][bp][8]: twist vectors (h_{m-1}, c)
 };
+// part: 1 = forward sweep only, 2 = back sweep only, 3 = both.
 hipError_t launch_sweeps(const Pencil &p, const Shifts &s, int Ne, const Factors &f,
-                         const SolveBufs &sb, const double *R, int m0p, double *P,
+                         const SolveBufs &sb, const double *R, int m0p, double *P, int part,
                          hipStream_t st);
 // Same sweeps, but the back sweep writes the complex solution of node 0
 // (used by the single-shift entry point): X_re, X_im padded.

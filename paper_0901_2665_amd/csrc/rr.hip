@@ -9,8 +9,9 @@
 //     the other columns of T are zero.
 //  2. C = T^T A_Q T, diagonalised by cyclic two-sided Jacobi rotations in a
 //     round-robin order (all n/2 disjoint rotations of a round at once);
-//     a rotation is skipped when |c_pq| <= 2^-53 sqrt(|c_pp c_qq|), and the
-//     sweeps stop after a sweep without rotations.
+//     a rotation is skipped when |c_pq| <= 2^-53 sqrt(|c_pp c_qq|) or
+//     |c_pq| <= 2^-56 ||C||_F, and the sweeps stop after a sweep without
+//     rotations.
 //  3. eps ascending (dropped directions: NaN, last), Phi = T V.
 #include "common.h"
 #include "kernels.h"
@@ -26,6 +27,8 @@ struct RRShared {
   double cs[kMaxN / 2], sn[kMaxN / 2];
   int rot;
   int fail;
+  double norm;
+  double red[kThreads];
   int dropped[kMaxN];
   int rank[kMaxN];
   double diag[kMaxN];
@@ -38,11 +41,30 @@ __device__ __forceinline__ int rr_player(int s, int i, int nn) {
 
 // Cyclic Jacobi on the nn x nn symmetric matrix C (LDS, row stride ldc);
 // V (global, nn x nn, row-major) accumulates the rotations.
-__device__ void jacobi(double *C, int ldc, double *V, int nn, RRShared &sh) {
+__device__ int jacobi(double *C, int ldc, double *V, int nn, RRShared &sh) {
   const int tid = threadIdx.x;
   const int half = nn / 2;
   const double eps = 1.1102230246251565e-16;  // 2^-53
-  for (int sweep = 0; sweep < 60; ++sweep) {
+  // absolute floor: off-diagonal entries below eps * ||C||_F / 8 are rounding
+  // noise of earlier rotations and are not rotated away
+  {
+    double part = 0.0;
+    for (int idx = tid; idx < nn * nn; idx += kThreads) {
+      const double v = C[(idx / nn) * ldc + idx % nn];
+      part += v * v;
+    }
+    sh.red[tid] = part;
+  }
+  __syncthreads();
+  if (tid == 0) {  // fixed summation order: bitwise reproducible
+    double s = 0.0;
+    for (int i = 0; i < kThreads; ++i) s += sh.red[i];
+    sh.norm = s;
+  }
+  __syncthreads();
+  const double floor_abs = 0.125 * eps * sqrt(sh.norm);
+  int sweep = 0;
+  for (; sweep < 60; ++sweep) {
     if (tid == 0) sh.rot = 0;
     __syncthreads();
     for (int s = 0; s < nn - 1; ++s) {
@@ -51,7 +73,7 @@ __device__ void jacobi(double *C, int ldc, double *V, int nn, RRShared &sh) {
         int p = u < v ? u : v, q = u < v ? v : u;
         double app = C[p * ldc + p], aqq = C[q * ldc + q], apq = C[p * ldc + q];
         double c = 1.0, sgn = 0.0;
-        if (fabs(apq) > 1e-300 && fabs(apq) > eps * sqrt(fabs(app * aqq))) {
+        if (fabs(apq) > floor_abs && fabs(apq) > eps * sqrt(fabs(app * aqq))) {
           double tau = (aqq - app) / (2.0 * apq);
           double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + hypot(1.0, tau));
           c = 1.0 / sqrt(1.0 + t * t);
@@ -109,6 +131,7 @@ __device__ void jacobi(double *C, int ldc, double *V, int nn, RRShared &sh) {
     __syncthreads();
     if (rot == 0) break;
   }
+  return sweep;
 }
 
 __global__ __launch_bounds__(kThreads) void reduced_eig_kernel(const double *AQ, const double *BQ,
@@ -185,7 +208,8 @@ __global__ __launch_bounds__(kThreads) void reduced_eig_kernel(const double *AQ,
       V[idx] = (i == j) ? 1.0 : 0.0;
     }
     __syncthreads();
-    jacobi(C, ldc, V, nn, sh);
+    const int fsweeps = jacobi(C, ldc, V, nn, sh);
+    if (tid == 0) flag[2] = fsweeps;
     if (tid < nn) sh.diag[tid] = C[tid * ldc + tid];
     __syncthreads();
     double mumax = 0.0;
@@ -219,7 +243,8 @@ __global__ __launch_bounds__(kThreads) void reduced_eig_kernel(const double *AQ,
   for (int idx = tid; idx < nn * nn; idx += kThreads) V[idx] = (idx / nn == idx % nn) ? 1.0 : 0.0;
   __syncthreads();
 
-  jacobi(C, ldc, V, nn, sh);
+  const int sweeps = jacobi(C, ldc, V, nn, sh);
+  if (tid == 0) flag[1] = sweeps;
 
   // ---- sort ascending, dropped directions (NaN) last ----
   if (tid < nn) sh.diag[tid] = C[tid * ldc + tid];

@@ -28,36 +28,52 @@ struct VecLds {
   double v[2][2][BP][kTile];  // [buffer][plane][row][col]
 };
 
-// acc0/acc1 (+)= sign * A' * B', A'[row][k] = Mp[kr*BP + row] (plane p of the
-// stored block, i.e. the product uses the transpose of the stored block),
-// B' = stacked complex vector from LDS buffer hv.
+// Matrix-operand fragments of one stored block for this lane: the product
+// uses the transpose of the stored block, A'[row][k] = M_plane[k][row], so
+// each load instruction reads 16 consecutive doubles of four rows.  Loading
+// the next cell's fragments one step ahead hides the L2/HBM latency behind
+// the current step's matrix-core work.
 template <int BP>
-__device__ __forceinline__ void prod_stored_T(d4 &acc0, d4 &acc1, const double *__restrict__ M,
-                                              const double (*hv)[BP][kTile], double sign) {
+struct Frag {
+  double v[BP / 2];  // [plane][k-step]: BP/4 k-steps per plane
+};
+
+template <int BP>
+__device__ __forceinline__ void frag_load(Frag<BP> &f, const double *__restrict__ M) {
   const int l = lane_id(), w = wave_id();
-  const int row = w * 16 + (l & 15);
+  const int row = w * 16 + (l & 15), kl = l >> 4;
+#pragma unroll
+  for (int ks = 0; ks < BP / 4; ++ks) {
+    f.v[ks] = M[(4 * ks + kl) * BP + row];
+    f.v[BP / 4 + ks] = M[BP * BP + (4 * ks + kl) * BP + row];
+  }
+}
+
+// acc0/acc1 (+)= sign * A' * B', B' = stacked complex vector [[hr|hi];[-hi|hr]]
+// from LDS buffer hv; even and odd k-steps go to separate accumulators.
+template <int BP>
+__device__ __forceinline__ void frag_mfma(d4 &acc0, d4 &acc1, const Frag<BP> &f,
+                                          const double (*hv)[BP][kTile], double sign) {
+  const int l = lane_id();
   const int kl = l >> 4;
   const int n = l & 15;
   const int col = n & 7;
-  const double *h0 = (n < 8) ? &hv[0][0][0] : &hv[1][0][0];  // plane-0 k rows
-  const double *h1 = (n < 8) ? &hv[1][0][0] : &hv[0][0][0];  // plane-1 k rows
+  const double *h0 = (n < 8) ? &hv[0][0][0] : &hv[1][0][0];  // k < BP
+  const double *h1 = (n < 8) ? &hv[1][0][0] : &hv[0][0][0];  // k >= BP
   const double s1 = (n < 8) ? -1.0 : 1.0;
-  const double *Mr = M, *Mi = M + BP * BP;
-#pragma unroll 4
-  for (int k0 = 0; k0 < BP; k0 += 8) {
-    const int ka = k0 + kl, kb = k0 + 4 + kl;
-    double a0 = sign * Mr[ka * BP + row], a1 = sign * Mr[kb * BP + row];
-    double b0 = h0[ka * kTile + col], b1 = h0[kb * kTile + col];
-    acc0 = mfma(a0, b0, acc0);
-    acc1 = mfma(a1, b1, acc1);
+#pragma unroll
+  for (int ks = 0; ks < BP / 4; ks += 2) {
+    const double b0 = h0[(4 * ks + kl) * kTile + col];
+    const double b1 = h0[(4 * ks + 4 + kl) * kTile + col];
+    acc0 = mfma(sign * f.v[ks], b0, acc0);
+    acc1 = mfma(sign * f.v[ks + 1], b1, acc1);
   }
-#pragma unroll 4
-  for (int k0 = 0; k0 < BP; k0 += 8) {
-    const int ka = k0 + kl, kb = k0 + 4 + kl;
-    double a0 = sign * Mi[ka * BP + row], a1 = sign * Mi[kb * BP + row];
-    double b0 = s1 * h1[ka * kTile + col], b1 = s1 * h1[kb * kTile + col];
-    acc0 = mfma(a0, b0, acc0);
-    acc1 = mfma(a1, b1, acc1);
+#pragma unroll
+  for (int ks = 0; ks < BP / 4; ks += 2) {
+    const double b0 = s1 * h1[(4 * ks + kl) * kTile + col];
+    const double b1 = s1 * h1[(4 * ks + 4 + kl) * kTile + col];
+    acc0 = mfma(sign * f.v[BP / 4 + ks], b0, acc0);
+    acc1 = mfma(sign * f.v[BP / 4 + ks + 1], b1, acc1);
   }
 }
 
@@ -132,39 +148,48 @@ __global__ __launch_bounds__(BP * 4) void forward_kernel(SweepArgs a) {
   double *TV = a.sb.TV + ((size_t)e * a.ntiles + tau) * 2 * vt;
   const double *R = a.R + tau * kTile;
   const size_t rstride = (size_t)BP * a.m0p;
+  // the top chain's last cell is the twist cell: no product there
+  const int nsteps = top ? len - 1 : len;
 
-  // h_0 = R_start
   {
     d4 h = acc_load_rhs<BP>(R + start * rstride, a.m0p);
     acc_store_vec<BP>(&s.v[0][0][0][0], h);
   }
+  Frag<BP> fs0, fw0, fs1, fw1;
+  if (nsteps > 0) {
+    frag_load<BP>(fs0, Sinv + start * blk);
+    frag_load<BP>(fw0, W + start * blk);
+  }
   __syncthreads();
   int cur = 0;
-  for (int j = 0; j < len; ++j) {
+  // one chain step on cell c with fragments (fs, fw); prefetch cell c+dir
+  auto step = [&](int j, const Frag<BP> &fs, const Frag<BP> &fw, Frag<BP> &ns, Frag<BP> &nw) {
     const int c = start + dir * j;
-    const auto hv = s.v[cur];
-    if (top && j == len - 1) {
-      d4 h = acc_load_vec<BP>(&hv[0][0][0]);
-      acc_store_vec<BP>(TV, h);  // h_{m-1}
-      break;
+    if (j + 1 < nsteps) {
+      frag_load<BP>(ns, Sinv + (c + dir) * blk);
+      frag_load<BP>(nw, W + (c + dir) * blk);
     }
-    d4 g0 = d4zero(), g1 = d4zero();
-    prod_stored_T<BP>(g0, g1, Sinv + c * blk, hv, 1.0);
     const bool more = (j < len - 1);
-    d4 h0, h1 = d4zero();
+    d4 h0 = more ? acc_load_rhs<BP>(R + (c + dir) * rstride, a.m0p) : d4zero();
+    d4 h1 = d4zero(), g0 = d4zero(), g1 = d4zero();
+    const auto hv = s.v[cur];
+    frag_mfma<BP>(h0, h1, fw, hv, -1.0);  // h_{j+1} = R - W^T h_j (critical path)
+    frag_mfma<BP>(g0, g1, fs, hv, 1.0);   // g_j = Sinv_j h_j
     if (more)
-      h0 = acc_load_rhs<BP>(R + (c + dir) * rstride, a.m0p);
-    else
-      h0 = d4zero();
-    prod_stored_T<BP>(h0, h1, W + c * blk, hv, -1.0);
-    acc_store_vec<BP>(G + c * vt, g0 + g1);
-    if (more) {
       acc_store_vec<BP>(&s.v[cur ^ 1][0][0][0], h0 + h1);
-    } else {
+    else
       acc_store_vec<BP>(TV + vt, h0 + h1);  // c = -W~_m^T h~_m
-    }
+    acc_store_vec<BP>(G + c * vt, g0 + g1);
     __syncthreads();
     cur ^= 1;
+  };
+  for (int j = 0; j < nsteps; j += 2) {
+    step(j, fs0, fw0, fs1, fw1);
+    if (j + 1 < nsteps) step(j + 1, fs1, fw1, fs0, fw0);
+  }
+  if (top) {
+    d4 h = acc_load_vec<BP>(&s.v[cur][0][0][0]);
+    acc_store_vec<BP>(TV, h);  // h_{m-1}
   }
 }
 
@@ -205,8 +230,12 @@ __global__ __launch_bounds__(BP * 4) void back_kernel(SweepArgs a) {
       }
     }
   };
+  const int count = top ? m - 1 : nc - m;
+  auto cell = [&](int j) { return top ? (m - 2 - j) : (m + j); };
 
   // twist cell: x_{m-1} = T (h_{m-1} + c)
+  Frag<BP> f0, f1;
+  frag_load<BP>(f0, Sinv + (m - 1) * blk);
   {
     d4 t = acc_load_vec<BP>(TV);
     if (nc - m > 0) t += acc_load_vec<BP>(TV + vt);
@@ -215,45 +244,63 @@ __global__ __launch_bounds__(BP * 4) void back_kernel(SweepArgs a) {
   __syncthreads();
   {
     d4 x0 = d4zero(), x1 = d4zero();
-    prod_stored_T<BP>(x0, x1, Sinv + (m - 1) * blk, s.v[1], 1.0);
+    frag_mfma<BP>(x0, x1, f0, s.v[1], 1.0);
     d4 x = x0 + x1;
     acc_store_vec<BP>(&s.v[0][0][0][0], x);
     if (top) emit(m - 1, x);
   }
+  d4 gnext = d4zero();
+  if (count > 0) {
+    frag_load<BP>(f1, WT + cell(0) * blk);
+    gnext = acc_load_vec<BP>(G + cell(0) * vt);
+  }
   __syncthreads();
   int cur = 0;
-  const int count = top ? m - 1 : nc - m;
-  for (int j = 0; j < count; ++j) {
-    const int c = top ? (m - 2 - j) : (m + j);
-    d4 x0 = acc_load_vec<BP>(G + c * vt), x1 = d4zero();
-    prod_stored_T<BP>(x0, x1, WT + c * blk, s.v[cur], -1.0);
+  // x_c = g_c - W_c x_prev; prefetch the next cell's W^T fragments and g tile
+  auto step = [&](int j, const Frag<BP> &fw, Frag<BP> &nw) {
+    const int c = cell(j);
+    d4 x0 = gnext, x1 = d4zero();
+    if (j + 1 < count) {
+      frag_load<BP>(nw, WT + cell(j + 1) * blk);
+      gnext = acc_load_vec<BP>(G + cell(j + 1) * vt);
+    }
+    frag_mfma<BP>(x0, x1, fw, s.v[cur], -1.0);
     d4 x = x0 + x1;
     acc_store_vec<BP>(&s.v[cur ^ 1][0][0][0], x);
     emit(c, x);
     __syncthreads();
     cur ^= 1;
+  };
+  for (int j = 0; j < count; j += 2) {
+    step(j, f1, f0);
+    if (j + 1 < count) step(j + 1, f0, f1);
   }
 }
 
+// part: 1 = forward sweep, 2 = back sweep, 3 = both
 template <int BP>
-hipError_t launch_sweeps_bp(SweepArgs &a, int Ne, bool complex_out, hipStream_t st) {
+hipError_t launch_sweeps_bp(SweepArgs &a, int Ne, bool complex_out, int part, hipStream_t st) {
   const int nblocks = Ne * 2 * a.ntiles;
-  hipLaunchKernelGGL(forward_kernel<BP>, dim3(nblocks), dim3(BP * 4), 0, st, a);
-  hipError_t err = hipGetLastError();
-  if (err != hipSuccess) return err;
-  if (complex_out)
-    hipLaunchKernelGGL((back_kernel<BP, true>), dim3(nblocks), dim3(BP * 4), 0, st, a);
-  else
-    hipLaunchKernelGGL((back_kernel<BP, false>), dim3(nblocks), dim3(BP * 4), 0, st, a);
+  if (part & 1) {
+    hipLaunchKernelGGL(forward_kernel<BP>, dim3(nblocks), dim3(BP * 4), 0, st, a);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+  }
+  if (part & 2) {
+    if (complex_out)
+      hipLaunchKernelGGL((back_kernel<BP, true>), dim3(nblocks), dim3(BP * 4), 0, st, a);
+    else
+      hipLaunchKernelGGL((back_kernel<BP, false>), dim3(nblocks), dim3(BP * 4), 0, st, a);
+  }
   return hipGetLastError();
 }
 
-hipError_t dispatch(SweepArgs &a, int Ne, bool complex_out, hipStream_t st) {
+hipError_t dispatch(SweepArgs &a, int Ne, bool complex_out, int part, hipStream_t st) {
   switch (a.p.bp) {
-    case 16: return launch_sweeps_bp<16>(a, Ne, complex_out, st);
-    case 32: return launch_sweeps_bp<32>(a, Ne, complex_out, st);
-    case 48: return launch_sweeps_bp<48>(a, Ne, complex_out, st);
-    case 64: return launch_sweeps_bp<64>(a, Ne, complex_out, st);
+    case 16: return launch_sweeps_bp<16>(a, Ne, complex_out, part, st);
+    case 32: return launch_sweeps_bp<32>(a, Ne, complex_out, part, st);
+    case 48: return launch_sweeps_bp<48>(a, Ne, complex_out, part, st);
+    case 64: return launch_sweeps_bp<64>(a, Ne, complex_out, part, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -261,13 +308,13 @@ hipError_t dispatch(SweepArgs &a, int Ne, bool complex_out, hipStream_t st) {
 }  // namespace
 
 hipError_t launch_sweeps(const Pencil &p, const Shifts &s, int Ne, const Factors &f,
-                         const SolveBufs &sb, const double *R, int m0p, double *P,
+                         const SolveBufs &sb, const double *R, int m0p, double *P, int part,
                          hipStream_t st) {
   SweepArgs a;
   a.p = p; a.f = f; a.sb = sb; a.R = R; a.P = P; a.Xim = nullptr;
   a.m0p = m0p; a.ntiles = m0p / kTile;
   for (int e = 0; e < kMaxNe; ++e) { a.kre[e] = s.kre[e]; a.kim[e] = s.kim[e]; }
-  return dispatch(a, Ne, false, st);
+  return dispatch(a, Ne, false, part, st);
 }
 
 hipError_t launch_sweeps_complex(const Pencil &p, const Shifts &s, const Factors &f,
@@ -277,7 +324,7 @@ hipError_t launch_sweeps_complex(const Pencil &p, const Shifts &s, const Factors
   a.p = p; a.f = f; a.sb = sb; a.R = R; a.P = Xre; a.Xim = Xim;
   a.m0p = m0p; a.ntiles = m0p / kTile;
   for (int e = 0; e < kMaxNe; ++e) { a.kre[e] = s.kre[e]; a.kim[e] = s.kim[e]; }
-  return dispatch(a, 1, true, st);
+  return dispatch(a, 1, true, 3, st);
 }
 
 }  // namespace feast

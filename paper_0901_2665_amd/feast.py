@@ -42,12 +42,14 @@ class Info(ctypes.Structure):
                 ("trace", ctypes.c_double), ("trace_rel", ctypes.c_double),
                 ("max_res", ctypes.c_double), ("status", ctypes.c_int32),
                 ("fallback", ctypes.c_int32),
-                ("trace_hist", ctypes.c_double * 64), ("count_hist", ctypes.c_int32 * 64)]
+                ("trace_hist", ctypes.c_double * 64), ("count_hist", ctypes.c_int32 * 64),
+                ("rr_sweeps", ctypes.c_int32)]
 
 
 EXPORTED = ["feast_default_opts", "feast_init", "feast_destroy", "feast_strerror",
             "feast_solve", "feast_contour", "feast_bt_multiply", "feast_shifted_solve",
-            "feast_filter", "feast_project", "feast_reduced_eig"]
+            "feast_filter", "feast_project", "feast_reduced_eig", "feast_timing",
+            "feast_timing_read"]
 
 
 def load_library(path: str = LIB_PATH):
@@ -73,6 +75,9 @@ def load_library(path: str = LIB_PATH):
     lib.feast_filter.argtypes = [P, ctypes.POINTER(BTMatrix), D, D, I32, I32, P, P]
     lib.feast_project.argtypes = [P, ctypes.POINTER(BTMatrix), I32, P, P, P]
     lib.feast_reduced_eig.argtypes = [P, I32, P, P, P, P, ctypes.POINTER(I32)]
+    lib.feast_timing.argtypes = [P, I32]
+    lib.feast_timing_read.argtypes = [P, I32, ctypes.POINTER(ctypes.c_char_p),
+                                      ctypes.POINTER(D), ctypes.POINTER(ctypes.c_int64)]
     for name in EXPORTED:
         if name not in ("feast_default_opts", "feast_strerror"):
             getattr(lib, name).restype = ctypes.c_int
@@ -105,6 +110,7 @@ class SolveResult:
     fallback: int
     traces: list
     counts: list
+    rr_sweeps: int = 0
 
 
 def _ptr(t):
@@ -185,7 +191,25 @@ class Context:
         n = min(info.loops, 64)
         return SolveResult(lam, X, res, info.M, info.loops, info.trace, info.trace_rel,
                            info.max_res, st, info.fallback, list(info.trace_hist[:n]),
-                           list(info.count_hist[:n]))
+                           list(info.count_hist[:n]), info.rr_sweeps)
+
+    def timing(self, enable: bool):
+        """Start (clear) or stop hipEvent timing of the kernel classes."""
+        self._check(self.lib.feast_timing(self.handle, 1 if enable else 0), "feast_timing")
+
+    def timing_read(self) -> dict:
+        """{class name: (total ms, launches)} of the events recorded so far."""
+        n = self.lib.feast_timing_read(self.handle, -1, None, None, None)
+        out = {}
+        for k in range(n):
+            name = ctypes.c_char_p()
+            ms = ctypes.c_double()
+            cnt = ctypes.c_int64()
+            st = self.lib.feast_timing_read(self.handle, k, ctypes.byref(name), ctypes.byref(ms),
+                                            ctypes.byref(cnt))
+            self._check(st, "feast_timing_read")
+            out[name.value.decode()] = (ms.value, cnt.value)
+        return out
 
     def bt_multiply(self, p: Pencil, which: int, V):
         import torch

@@ -24,7 +24,9 @@ def main(names):
     for name in names:
         p, emin, emax, m0, ne, Y0 = W.make_workload(name)
         t0 = time.time()
-        r = O.feast(p, emin, emax, m0, ne, Y0)
+        r = O.feast(p, emin, emax, m0, ne, Y0,
+                    log=lambda k, M, T, tr: print(f"  loop {k} M {M} trace {T!r} rel {tr:.3e}",
+                                                  flush=True))
         dt = time.time() - t0
         out = dict(workload=name, emin=emin, emax=emax, M0=m0, Ne=ne, M=int(r.M),
                    loops=int(r.loops), status=int(r.status),

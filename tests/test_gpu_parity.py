@@ -170,15 +170,15 @@ def test_reduced_eig_feast_like(ctx, torch, n, smallest):
 
 @pytest.mark.parametrize("n,cond", [(30, 1e6), (127, 1e8), (128, 1e10)])
 def test_reduced_eig_ill_conditioned_backward_stable(ctx, torch, n, cond):
-    # eigenvalues of a random pencil with cond(B_Q) = cond are themselves ill
-    # conditioned; both solvers are backward stable, so compare residuals and
-    # eigenvalues to eps * cond(B_Q).
+    # with cond(B_Q) large, a Cholesky-based reduction has a backward error
+    # growing with cond(B_Q) (so does LAPACK's): hold the GPU to the oracle's
+    # own backward error, and the eigenvalues to eps * cond(B_Q).
     AQ, BQ = spd_pair(n, n, cond)
     eps, Phi, fb = ctx.reduced_eig(dev(torch, AQ), dev(torch, BQ))
     eps, Phi = host(eps), host(Phi)
-    ref, _, _ = O.reduced_eig(AQ, BQ)
+    ref, rPhi, _ = O.reduced_eig(AQ, BQ)
     assert not fb
-    assert rr_backward_error(AQ, BQ, eps, Phi) <= 1e-13
+    assert rr_backward_error(AQ, BQ, eps, Phi) <= 10 * rr_backward_error(AQ, BQ, ref, rPhi) + 1e-15
     assert np.max(np.abs(eps - ref)) <= 1e-15 * cond * np.max(np.abs(ref))
 
 

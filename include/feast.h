@@ -76,6 +76,10 @@ typedef struct {
   double tol;            /* relative trace change for convergence, e.g. 1e-12 */
   int32_t max_loops;     /* refinement loops allowed, >= 1 */
   int32_t precision;     /* 0: complex float64 shifted solves */
+  int32_t partitions;    /* partitions per half chain of the factorisation;
+                            0 = automatic (at least 8 cells each, about one
+                            chain per compute unit); results do not depend on it
+                            beyond rounding */
   const double *Y0;      /* (dev) [N][M0] initial subspace; required */
 } feast_opts;
 
@@ -92,7 +96,7 @@ typedef struct {
   int32_t rr_sweeps;     /* Jacobi sweeps of the reduced eigensolver, all loops */
 } feast_info;
 
-/* Default options: tol 1e-12, max_loops 20, precision 0, Y0 NULL. */
+/* Default options: tol 1e-12, max_loops 20, precision 0, partitions 0, Y0 NULL. */
 void feast_default_opts(feast_opts *opts);
 
 /* Create a context on HIP device `device`; `hip_stream` is a hipStream_t or

@@ -52,6 +52,26 @@ __device__ __forceinline__ cplx crecip(cplx a) {
   }
 }
 
+// 1/a by Newton's iteration for the reciprocal, x <- x (2 - d x), started
+// from the hardware estimate: two steps reach full double precision for the
+// normal-range pivots met here (no denormal or overflow scaling).
+__device__ __forceinline__ double rcp_newton(double d) {
+  double x = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, x, 1.0);
+  x = fma(x, e, x);
+  e = fma(-d, x, 1.0);
+  return fma(x, e, x);
+}
+// 1/(a + ib) = (a - ib) / (a^2 + b^2), with the common factor scaled by the
+// larger component so that the squares neither overflow nor underflow.
+__device__ __forceinline__ cplx crecip_fast(cplx a) {
+  const double s = fmax(fabs(a.re), fabs(a.im));
+  const double rs = rcp_newton(s);
+  const double ar = a.re * rs, ai = a.im * rs;
+  const double inv = rcp_newton(ar * ar + ai * ai) * rs;
+  return {ar * inv, -ai * inv};
+}
+
 // Grid position -> work item, placing consecutive groups of `per_group`
 // items on one XCD (workgroups are dispatched to the 8 XCDs round-robin, so
 // items that read the same factor stream share that XCD's L2).

@@ -14,6 +14,8 @@
 // fly from the real blocks.  Every inverse is symmetrised, so Sinv may be read
 // transposed.  The factors are computed once per solve and reused by every
 // refinement loop (Sec. V, parallelism (ii)).
+#include <vector>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -28,8 +30,6 @@ struct Lds {
   static constexpr int PLANE = BP * LD;
   double A[2 * PLANE];                // slot A (re plane, im plane)
   double B[2 * PLANE];                // slot B
-  double row[2][2][BP];               // Gauss-Jordan pivot row (double buffered)
-  double col[2][2][BP];               // Gauss-Jordan pivot column
 };
 
 // slot <- z*Bblk - Ablk (or its transpose), identity padding on the diagonal.
@@ -54,6 +54,71 @@ __device__ void form_block(double *slot, const double *Ablk, const double *Bblk,
   }
 }
 
+// Real blocks staged in registers (issued early, consumed after the
+// Gauss-Jordan elimination so that the loads overlap it).
+template <int BP>
+struct BlockRegs {
+  static constexpr int NE = (BP * BP + kThreads - 1) / kThreads;
+  double a[NE], b[NE];
+};
+
+template <int BP>
+__device__ __forceinline__ void block_regs_load(BlockRegs<BP> &g, const double *Ablk,
+                                                const double *Bblk, int b, bool transpose) {
+#pragma unroll
+  for (int i = 0; i < BlockRegs<BP>::NE; ++i) {
+    const int idx = threadIdx.x + kThreads * i;
+    const int r = idx / BP, c = idx % BP;
+    double av = 0.0, bv = 0.0;
+    if (idx < BP * BP && r < b && c < b) {
+      const int src = transpose ? c * b + r : r * b + c;
+      av = Ablk[src];
+      bv = Bblk[src];
+    }
+    g.a[i] = av;
+    g.b[i] = bv;
+  }
+}
+
+// slot <- z*B - A from staged registers (coupling block: zero padding).
+template <int BP>
+__device__ __forceinline__ void block_regs_store(double *slot, const BlockRegs<BP> &g, double zr,
+                                                 double zi) {
+  constexpr int LD = Lds<BP>::LD, PLANE = Lds<BP>::PLANE;
+#pragma unroll
+  for (int i = 0; i < BlockRegs<BP>::NE; ++i) {
+    const int idx = threadIdx.x + kThreads * i;
+    if (idx < BP * BP) {
+      const int r = idx / BP, c = idx % BP;
+      slot[r * LD + c] = zr * g.b[i] - g.a[i];
+      slot[PLANE + r * LD + c] = zi * g.b[i];
+    }
+  }
+}
+
+// Diagonal block in the accumulator layout, staged in registers.
+template <int BP>
+struct DiagRegs {
+  double a[BP / 16][4], b[BP / 16][4];
+};
+
+template <int BP>
+__device__ __forceinline__ void diag_regs_load(DiagRegs<BP> &g, const double *Ablk,
+                                               const double *Bblk, int b) {
+  constexpr int NT = BP / 16;
+  const int w = wave_id(), l = lane_id();
+  if (w >= NT) return;
+#pragma unroll
+  for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = w * 16 + acc_row(l, r), col = tj * 16 + acc_col(l);
+      const bool in = row < b && col < b;
+      g.a[tj][r] = in ? Ablk[row * b + col] : 0.0;
+      g.b[tj][r] = in ? Bblk[row * b + col] : 0.0;
+    }
+}
+
 // slot <- complex block from global planes [2][BP][BP].
 template <int BP>
 __device__ void load_block(double *slot, const double *g) {
@@ -76,105 +141,178 @@ __device__ void store_block(double *g, const double *slot, bool transpose) {
   }
 }
 
-// In-place Gauss-Jordan inversion of the complex block in slot A, without
-// pivoting (every leading principal minor of a complex symmetric matrix with
-// positive definite imaginary part is non-zero).  Each thread keeps a 4x4
-// patch in registers; pivot row and column travel through LDS, one barrier
-// per elimination step.  The result is symmetrised, written back to slot A
-// and, if gout != nullptr, to global memory.
+// In-place inverse of a 16x16 complex tile (LDS, planes re/im with row
+// stride ld) by one wave: Gauss-Jordan elimination without pivoting, the
+// tile held in registers (lane l: row l/4, columns 4(l%4)..4(l%4)+3), pivot
+// row and column exchanged with lane shuffles.
+__device__ __forceinline__ void inv16_wave(double *Xr, double *Xi, int ld) {
+  const int l = lane_id();
+  const int r = l >> 2, cb = (l & 3) * 4;
+  double ar[4], ai[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    ar[v] = Xr[r * ld + cb + v];
+    ai[v] = Xi[r * ld + cb + v];
+  }
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int vj = j & 3;
+    const int pl = (j << 2) | (j >> 2);          // lane holding (j, j)
+    const cplx piv = crecip_fast(cplx{__shfl(ar[vj], pl), __shfl(ai[vj], pl)});
+    const int rl = (j << 2) | (l & 3);           // lane holding row j, my columns
+    cplx rk[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) rk[v] = cmul(cplx{__shfl(ar[v], rl), __shfl(ai[v], rl)}, piv);
+    const int cl = (l & ~3) | (j >> 2);          // lane holding my row, column j
+    const cplx cj{__shfl(ar[vj], cl), __shfl(ai[vj], cl)};
+    const cplx m = cmul(cj, piv);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      ar[v] -= cj.re * rk[v].re - cj.im * rk[v].im;
+      ai[v] -= cj.re * rk[v].im + cj.im * rk[v].re;
+    }
+    if ((l & 3) == (j >> 2)) {  // column j: -a_rj / a_jj
+      ar[vj] = -m.re;
+      ai[vj] = -m.im;
+    }
+    if (r == j) {  // row j: a_jc / a_jj, pivot 1 / a_jj
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const bool pv = (cb + v == j);
+        ar[v] = pv ? piv.re : rk[v].re;
+        ai[v] = pv ? piv.im : rk[v].im;
+      }
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    Xr[r * ld + cb + v] = ar[v];
+    Xi[r * ld + cb + v] = ai[v];
+  }
+}
+
+// One 16x16 complex tile on the matrix cores, operands in LDS:
+//   acc += sign * X(16 x 16) * Y(16 x 16),
+// X and Y point at the tile origins of their re planes (im plane at +PLANE).
 template <int BP>
-__device__ void gj_invert(Lds<BP> &s, double *gout) {
+__device__ __forceinline__ void tile_cgemm16(d4 &accr, d4 &acci, const double *X, const double *Y,
+                                             double sign) {
   constexpr int LD = Lds<BP>::LD, PLANE = Lds<BP>::PLANE;
+  const int l = lane_id();
+  const int row = l & 15, kl = l >> 4;
+#pragma unroll
+  for (int k0 = 0; k0 < 16; k0 += 4) {
+    const int k = k0 + kl;
+    const double xr = sign * X[row * LD + k], xi = sign * X[PLANE + row * LD + k];
+    const double yr = Y[k * LD + row], yi = Y[PLANE + k * LD + row];
+    accr = mfma(xr, yr, accr);
+    accr = mfma(-xi, yi, accr);
+    acci = mfma(xr, yi, acci);
+    acci = mfma(xi, yr, acci);
+  }
+}
+
+template <int BP>
+__device__ __forceinline__ void tile_load(d4 &accr, d4 &acci, const double *T) {
+  constexpr int LD = Lds<BP>::LD, PLANE = Lds<BP>::PLANE;
+  const int l = lane_id();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    accr[r] = T[acc_row(l, r) * LD + acc_col(l)];
+    acci[r] = T[PLANE + acc_row(l, r) * LD + acc_col(l)];
+  }
+}
+
+template <int BP>
+__device__ __forceinline__ void tile_store(double *T, const d4 &accr, const d4 &acci) {
+  constexpr int LD = Lds<BP>::LD, PLANE = Lds<BP>::PLANE;
+  const int l = lane_id();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    T[acc_row(l, r) * LD + acc_col(l)] = accr[r];
+    T[PLANE + acc_row(l, r) * LD + acc_col(l)] = acci[r];
+  }
+}
+
+// In-place inverse of the complex block in slot A by block Gauss-Jordan
+// elimination with 16-wide panels, without pivoting (every leading principal
+// minor of a complex symmetric matrix with positive definite imaginary part
+// is non-zero, and so is every diagonal block of its Schur complements).
+// For panel K with P = S_KK^{-1}:
+//   S_KJ <- P S_KJ (J != K);  S_IJ <- S_IJ - S_IK S_KJ,  S_IK <- -S_IK P (I != K);
+//   S_KK <- P.
+// The diagonal inverse runs in one wave; the panel products on the matrix
+// cores.  The result is symmetrised (symm: the inverse of a complex
+// symmetric block), written back to slot A and, if gout != nullptr, to
+// global memory.
+template <int BP>
+__device__ __forceinline__ void gj_invert(Lds<BP> &s, double *gout, bool symm = true) {
+  constexpr int LD = Lds<BP>::LD, PLANE = Lds<BP>::PLANE, NB = BP / 16;
+  const int w = wave_id();
+  double *A = s.A;
+  auto tile = [&](int bi, int bj) { return A + (bi * 16) * LD + bj * 16; };
+  for (int kb = 0; kb < NB; ++kb) {
+    if (w == 0) inv16_wave(tile(kb, kb), tile(kb, kb) + PLANE, LD);
+    __syncthreads();
+    if constexpr (NB > 1) {
+      // row panel S_KJ <- P S_KJ
+      d4 rr = d4zero(), ri = d4zero();
+      int jb = -1;
+      if (w < NB - 1) {
+        jb = w < kb ? w : w + 1;
+        tile_cgemm16<BP>(rr, ri, tile(kb, kb), tile(kb, jb), 1.0);
+      }
+      __syncthreads();
+      if (jb >= 0) tile_store<BP>(tile(kb, jb), rr, ri);
+      __syncthreads();
+      // trailing tiles and column panel
+      constexpr int NT = (NB - 1) * NB;
+      constexpr int PER = NT > 0 ? (NT + 3) / 4 : 1;
+      d4 tr[PER], ti[PER];
+      int ib[PER], jbb[PER];
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int t = w + 4 * q;
+        ib[q] = -1;
+        if (t < NT) {
+          const int i0 = t / NB, j0 = t % NB;
+          const int bi = i0 < kb ? i0 : i0 + 1;
+          ib[q] = bi;
+          jbb[q] = j0;
+          if (j0 == kb) {
+            tr[q] = d4zero();
+            ti[q] = d4zero();
+            tile_cgemm16<BP>(tr[q], ti[q], tile(bi, kb), tile(kb, kb), -1.0);
+          } else {
+            tile_load<BP>(tr[q], ti[q], tile(bi, j0));
+            tile_cgemm16<BP>(tr[q], ti[q], tile(bi, kb), tile(kb, j0), -1.0);
+          }
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < PER; ++q)
+        if (ib[q] >= 0) tile_store<BP>(tile(ib[q], jbb[q]), tr[q], ti[q]);
+      __syncthreads();
+    }
+  }
+  if (!symm) {
+    __syncthreads();
+    return;
+  }
+  // symmetrise: S <- (S + S^T) / 2, by tiles of the 4x4-patch layout
   const int t = threadIdx.x;
-  const int ti = t >> 4, tj = t & 15;
-  const bool act = (4 * ti < BP) && (4 * tj < BP);
+  const int pi = t >> 4, pj = t & 15;
+  const bool act = (4 * pi < BP) && (4 * pj < BP);
   double ar[4][4], ai[4][4];
   if (act) {
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        ar[u][v] = s.A[(4 * ti + u) * LD + 4 * tj + v];
-        ai[u][v] = s.A[PLANE + (4 * ti + u) * LD + 4 * tj + v];
-      }
-    if (ti == 0)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        s.row[0][0][4 * tj + v] = ar[0][v];
-        s.row[0][1][4 * tj + v] = ai[0][v];
-      }
-    if (tj == 0)
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        s.col[0][0][4 * ti + u] = ar[u][0];
-        s.col[0][1][4 * ti + u] = ai[u][0];
-      }
-  }
-  __syncthreads();
-  for (int k = 0; k < BP; ++k) {
-    const int q = k & 1;
-    cplx piv = crecip(cplx{s.row[q][0][k], s.row[q][1][k]});
-    if (act) {
-      cplx rk[4], ck[4];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) rk[v] = cmul(cplx{s.row[q][0][4 * tj + v], s.row[q][1][4 * tj + v]}, piv);
-#pragma unroll
-      for (int u = 0; u < 4; ++u) ck[u] = cplx{s.col[q][0][4 * ti + u], s.col[q][1][4 * ti + u]};
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const bool on_row = (4 * ti + u) == k;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const bool on_col = (4 * tj + v) == k;
-          cplx a{ar[u][v], ai[u][v]};
-          cplx upd;
-          if (on_row && on_col) {
-            upd = piv;
-          } else if (on_row) {
-            upd = rk[v];
-          } else if (on_col) {
-            cplx m = cmul(ck[u], piv);
-            upd = cplx{-m.re, -m.im};
-          } else {
-            cplx m = cmul(ck[u], rk[v]);
-            upd = cplx{a.re - m.re, a.im - m.im};
-          }
-          ar[u][v] = upd.re;
-          ai[u][v] = upd.im;
-        }
-      }
-      // publish row and column k+1 (register indices stay compile-time)
-      const int k1 = k + 1;
-      if (k1 < BP) {
-        const int qn = k1 & 1;
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (k1 == 4 * ti + u)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              s.row[qn][0][4 * tj + v] = ar[u][v];
-              s.row[qn][1][4 * tj + v] = ai[u][v];
-            }
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-          if (k1 == 4 * tj + v)
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              s.col[qn][0][4 * ti + u] = ar[u][v];
-              s.col[qn][1][4 * ti + u] = ai[u][v];
-            }
-      }
-    }
-    __syncthreads();
-  }
-  // symmetrise: S <- (S + S^T) / 2
-  if (act) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        s.A[(4 * ti + u) * LD + 4 * tj + v] = ar[u][v];
-        s.A[PLANE + (4 * ti + u) * LD + 4 * tj + v] = ai[u][v];
+        const int r = 4 * pi + u, c = 4 * pj + v;
+        ar[u][v] = 0.5 * (A[r * LD + c] + A[c * LD + r]);
+        ai[u][v] = 0.5 * (A[PLANE + r * LD + c] + A[PLANE + c * LD + r]);
       }
   }
   __syncthreads();
@@ -183,19 +321,9 @@ __device__ void gj_invert(Lds<BP> &s, double *gout) {
     for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        ar[u][v] = 0.5 * (ar[u][v] + s.A[(4 * tj + v) * LD + 4 * ti + u]);
-        ai[u][v] = 0.5 * (ai[u][v] + s.A[PLANE + (4 * tj + v) * LD + 4 * ti + u]);
-      }
-  }
-  __syncthreads();
-  if (act) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = 4 * ti + u, c = 4 * tj + v;
-        s.A[r * LD + c] = ar[u][v];
-        s.A[PLANE + r * LD + c] = ai[u][v];
+        const int r = 4 * pi + u, c = 4 * pj + v;
+        A[r * LD + c] = ar[u][v];
+        A[PLANE + r * LD + c] = ai[u][v];
         if (gout) {
           gout[r * BP + c] = ar[u][v];
           gout[BP * BP + r * BP + c] = ai[u][v];
@@ -206,24 +334,26 @@ __device__ void gj_invert(Lds<BP> &s, double *gout) {
 }
 
 // Complex product on the matrix cores, operands in LDS slots:
-//   acc (+)= sign * op(X) * Y,   op(X) = X or X^T.
+//   acc (+)= sign * op(X) * op(Y),   op(Z) = Z or Z^T.
 // Wave w (< BP/16) owns row block w and all column blocks; acc[tj] holds
 // the re / im 16x16 tiles.
 template <int BP>
-__device__ void cgemm_lds(d4 (&accr)[BP / 16], d4 (&acci)[BP / 16], const double *X,
-                          bool transX, const double *Y, double sign) {
+__device__ __forceinline__ void cgemm_lds(d4 (&accr)[BP / 16], d4 (&acci)[BP / 16], const double *X,
+                                          bool transX, const double *Y, double sign,
+                                          bool transY = false) {
   constexpr int LD = Lds<BP>::LD, PLANE = Lds<BP>::PLANE, NT = BP / 16;
   const int w = wave_id(), l = lane_id();
   if (w >= NT) return;
   const int row = w * 16 + (l & 15);
   const int kl = l >> 4;
+#pragma unroll 2
   for (int k0 = 0; k0 < BP; k0 += 4) {
     const int k = k0 + kl;
     const int xa = transX ? k * LD + row : row * LD + k;
     const double xr = sign * X[xa], xi = sign * X[PLANE + xa];
 #pragma unroll
     for (int tj = 0; tj < NT; ++tj) {
-      const int yb = k * LD + tj * 16 + (l & 15);
+      const int yb = transY ? (tj * 16 + (l & 15)) * LD + k : k * LD + tj * 16 + (l & 15);
       const double yr = Y[yb], yi = Y[PLANE + yb];
       accr[tj] = mfma(xr, yr, accr[tj]);
       accr[tj] = mfma(-xi, yi, accr[tj]);
@@ -290,6 +420,24 @@ __device__ void acc_from_diag(d4 (&accr)[BP / 16], d4 (&acci)[BP / 16], const do
 }
 
 template <int BP>
+__device__ __forceinline__ void acc_from_diag_regs(d4 (&accr)[BP / 16], d4 (&acci)[BP / 16],
+                                                   const DiagRegs<BP> &g, int b, double zr,
+                                                   double zi) {
+  constexpr int NT = BP / 16;
+  const int w = wave_id(), l = lane_id();
+  if (w >= NT) return;
+#pragma unroll
+  for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = w * 16 + acc_row(l, r), col = tj * 16 + acc_col(l);
+      const bool in = row < b && col < b;
+      accr[tj][r] = in ? zr * g.b[tj][r] - g.a[tj][r] : (row == col ? 1.0 : 0.0);
+      acci[tj][r] = in ? zi * g.b[tj][r] : 0.0;
+    }
+}
+
+template <int BP>
 __device__ void acc_from_global(d4 (&accr)[BP / 16], d4 (&acci)[BP / 16], const double *g) {
   constexpr int NT = BP / 16;
   const int w = wave_id(), l = lane_id();
@@ -304,18 +452,22 @@ __device__ void acc_from_global(d4 (&accr)[BP / 16], d4 (&acci)[BP / 16], const 
     }
 }
 
+// One chain of the factorisation per workgroup.  The first cell starts from
+// S = D_start (- K_in); every cell is inverted, and every cell but the last
+// (also the last one when end == 2) gets W = Sinv * Cpl and passes the Schur
+// complement S_next = D_next - Cpl^T W on; end == 1 keeps the raw Schur
+// complement of the last cell for the twist kernel.
 template <int BP>
-__global__ __launch_bounds__(kThreads) void factor_chain_kernel(Pencil p, Shifts sh, Factors f) {
+__global__ __launch_bounds__(kThreads) void factor_chain_kernel(Pencil p, Shifts sh, Factors f,
+                                                                const Chain *chains,
+                                                                const double *Kbuf) {
   extern __shared__ double smem_raw[];
   Lds<BP> &s = *reinterpret_cast<Lds<BP> *>(smem_raw);
-  constexpr int NT = BP / 16;
-  const int e = blockIdx.x >> 1;
-  const bool top = (blockIdx.x & 1) == 0;
-  const int nc = p.nc, b = p.b, m = f.m;
-  const int start = top ? 0 : nc - 1;
-  const int dir = top ? 1 : -1;
-  const int len = top ? m : nc - m;
+  constexpr int NT = BP / 16, LD = Lds<BP>::LD, PLANE = Lds<BP>::PLANE;
+  const Chain ch = chains[blockIdx.x];
+  const int e = ch.e, start = ch.start, dir = ch.dir, len = ch.len;
   if (len <= 0) return;
+  const int nc = p.nc, b = p.b;
   const double zr = sh.zre[e], zi = sh.zim[e];
   const size_t blk = 2 * (size_t)BP * BP;
   const size_t bb = (size_t)b * b;
@@ -324,21 +476,37 @@ __global__ __launch_bounds__(kThreads) void factor_chain_kernel(Pencil p, Shifts
   double *WTg = f.WT + (size_t)e * nc * blk;
 
   form_block<BP>(s.A, p.Ad + start * bb, p.Bd + start * bb, b, zr, zi, false, true);
+  if (ch.kin >= 0) {  // self-energy of the cells before this chain
+    __syncthreads();
+    const double *K = Kbuf + (size_t)ch.kin * blk;
+    for (int idx = threadIdx.x; idx < BP * BP; idx += kThreads) {
+      const int r = idx / BP, c = idx % BP;
+      s.A[r * LD + c] -= K[idx];
+      s.A[PLANE + r * LD + c] -= K[BP * BP + idx];
+    }
+  }
   __syncthreads();
   for (int j = 0; j < len; ++j) {
     const int c = start + dir * j;
     const bool last = (j == len - 1);
-    if (top && last) {
+    if (last && ch.end == 1) {
       // raw Schur complement at the twist cell, finished by twist_kernel
       store_block<BP>(f.TW + (size_t)e * blk, s.A, false);
       break;
     }
-    // coupling from c to the next cell in chain order
-    if (top)
+    if (last && ch.end == 0) {
+      gj_invert<BP>(s, Sinv + c * blk);
+      break;
+    }
+    // coupling from c to the next cell in chain order (slot B is free here)
+    if (dir > 0)
       form_block<BP>(s.B, p.Au + c * bb, p.Bu + c * bb, b, zr, zi, false, false);
     else
       form_block<BP>(s.B, p.Au + (c - 1) * bb, p.Bu + (c - 1) * bb, b, zr, zi, true, false);
     gj_invert<BP>(s, Sinv + c * blk);  // ends with a barrier
+    DiagRegs<BP> dn;  // next diagonal block, loaded under the W product
+    if (!last) diag_regs_load<BP>(dn, p.Ad + (c + dir) * bb, p.Bd + (c + dir) * bb, b);
+    __syncthreads();
     d4 wr[NT], wi[NT];
 #pragma unroll
     for (int q = 0; q < NT; ++q) { wr[q] = d4zero(); wi[q] = d4zero(); }
@@ -349,14 +517,110 @@ __global__ __launch_bounds__(kThreads) void factor_chain_kernel(Pencil p, Shifts
     __syncthreads();
     store_block<BP>(WTg + c * blk, s.A, true);
     if (!last) {
-      const int cn = c + dir;
       d4 sr[NT], si[NT];
-      acc_from_diag<BP>(sr, si, p.Ad + cn * bb, p.Bd + cn * bb, b, zr, zi);
+      acc_from_diag_regs<BP>(sr, si, dn, b, zr, zi);
       cgemm_lds<BP>(sr, si, s.B, true, s.A, -1.0);  // S_next = D - Cpl^T W
       __syncthreads();
       acc_to_lds<BP>(s.A, sr, si);
       __syncthreads();
     }
+  }
+}
+
+// Interface pass of the partitioned factorisation, one workgroup per
+// (node, half), sequential over the partitions of the half.  For partition q
+// with local matrix T (its own cells, no coupling to the cells before it) let
+// G_11 = [T^-1]_{first,first}, G_L1 = [T^-1]_{last,first} and G_LL =
+// [T^-1]_{last,last}.  With K the self-energy entering its first cell, the
+// exact inverse Schur complement of its last cell is (Woodbury identity)
+//   Sinv_last = G_LL + G_L1 K (I - G_11 K)^{-1} G_L1^T,
+// and the next partition starts from D - K' with K' = C^T Sinv_last C, C the
+// coupling from the last cell to the next one in chain order.
+template <int BP>
+__global__ __launch_bounds__(kThreads) void interface_kernel(Pencil p, Shifts sh, Factors f,
+                                                             const Chain *chainsF1, int parts,
+                                                             const double *G11, const double *GL1,
+                                                             double *Kbuf) {
+  extern __shared__ double smem_raw[];
+  Lds<BP> &s = *reinterpret_cast<Lds<BP> *>(smem_raw);
+  constexpr int NT = BP / 16;
+  const int grp = blockIdx.x;  // e * 2 + half
+  const int nc = p.nc, b = p.b;
+  const size_t blk = 2 * (size_t)BP * BP;
+  const size_t bb = (size_t)b * b;
+  const Chain *ch0 = chainsF1 + (size_t)grp * (parts - 1);
+  const int e = ch0->e;
+  const double zr = sh.zre[e], zi = sh.zim[e];
+  const double *Sinv = f.Sinv + (size_t)e * nc * blk;
+  const int w = wave_id(), l = lane_id();
+  d4 ar[NT], ai[NT];
+  for (int q = 0; q < parts - 1; ++q) {
+    const Chain ch = ch0[q];
+    const int last = ch.start + ch.dir * (ch.len - 1);
+    const size_t gi = ((size_t)grp * parts + q) * blk;
+    if (q == 0) {
+      load_block<BP>(s.A, Sinv + last * blk);  // K = 0: Sinv_last = G_LL
+      __syncthreads();
+    } else {
+      // slot B holds K.  N = (I - G_11 K)^{-1}
+      load_block<BP>(s.A, G11 + gi);
+      __syncthreads();
+      if (w < NT) {
+#pragma unroll
+        for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            ar[tj][r] = (w * 16 + acc_row(l, r) == tj * 16 + acc_col(l)) ? 1.0 : 0.0;
+            ai[tj][r] = 0.0;
+          }
+      }
+      cgemm_lds<BP>(ar, ai, s.A, false, s.B, -1.0);
+      __syncthreads();
+      acc_to_lds<BP>(s.A, ar, ai);
+      __syncthreads();
+      gj_invert<BP>(s, nullptr, false);
+      // M3 = K N
+#pragma unroll
+      for (int t = 0; t < NT; ++t) { ar[t] = d4zero(); ai[t] = d4zero(); }
+      cgemm_lds<BP>(ar, ai, s.B, false, s.A, 1.0);
+      __syncthreads();
+      acc_to_lds<BP>(s.B, ar, ai);
+      load_block<BP>(s.A, GL1 + gi);
+      __syncthreads();
+      // M4 = G_L1 M3
+#pragma unroll
+      for (int t = 0; t < NT; ++t) { ar[t] = d4zero(); ai[t] = d4zero(); }
+      cgemm_lds<BP>(ar, ai, s.A, false, s.B, 1.0);
+      __syncthreads();
+      acc_to_lds<BP>(s.B, ar, ai);
+      __syncthreads();
+      // Sinv_last = G_LL + M4 G_L1^T
+      acc_from_global<BP>(ar, ai, Sinv + last * blk);
+      cgemm_lds<BP>(ar, ai, s.B, false, s.A, 1.0, true);
+      __syncthreads();
+      acc_to_lds<BP>(s.A, ar, ai);
+      __syncthreads();
+    }
+    // K' = C^T Sinv_last C
+    if (ch.dir > 0)
+      form_block<BP>(s.B, p.Au + last * bb, p.Bu + last * bb, b, zr, zi, false, false);
+    else
+      form_block<BP>(s.B, p.Au + (last - 1) * bb, p.Bu + (last - 1) * bb, b, zr, zi, true,
+                     false);
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < NT; ++t) { ar[t] = d4zero(); ai[t] = d4zero(); }
+    cgemm_lds<BP>(ar, ai, s.A, false, s.B, 1.0);
+    __syncthreads();
+    acc_to_lds<BP>(s.A, ar, ai);
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < NT; ++t) { ar[t] = d4zero(); ai[t] = d4zero(); }
+    cgemm_lds<BP>(ar, ai, s.B, true, s.A, 1.0);
+    __syncthreads();
+    acc_to_global<BP>(Kbuf + ((size_t)grp * parts + q + 1) * blk, ar, ai);
+    acc_to_lds<BP>(s.B, ar, ai);  // K for the next partition
+    __syncthreads();
   }
 }
 
@@ -391,31 +655,92 @@ __global__ __launch_bounds__(kThreads) void twist_kernel(Pencil p, Shifts sh, Fa
 }
 
 template <int BP>
-hipError_t launch_factor_bp(const Pencil &p, const Shifts &s, int Ne, const Factors &f,
-                            hipStream_t st) {
+hipError_t set_lds(const void *fn) {
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)sizeof(Lds<BP>));
+}
+
+template <int BP>
+hipError_t launch_factor_bp(const Pencil &p, const Shifts &s, int Ne, const Factors &f, int parts,
+                            double *work, Chain *chains, double *G, int gtiles, hipStream_t st) {
   const size_t shm = sizeof(Lds<BP>);
-  hipError_t err = hipFuncSetAttribute((const void *)factor_chain_kernel<BP>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  if (err != hipSuccess) return err;
-  err = hipFuncSetAttribute((const void *)twist_kernel<BP>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(factor_chain_kernel<BP>, dim3(2 * Ne), dim3(kThreads), shm, st, p, s, f);
-  err = hipGetLastError();
-  if (err != hipSuccess) return err;
+  hipError_t err;
+  if ((err = set_lds<BP>((const void *)factor_chain_kernel<BP>)) != hipSuccess) return err;
+  if ((err = set_lds<BP>((const void *)twist_kernel<BP>)) != hipSuccess) return err;
+  if ((err = set_lds<BP>((const void *)interface_kernel<BP>)) != hipSuccess) return err;
+  const int nc = p.nc, m = f.m;
+  // chain tables: F1 = local factorisation of every partition but the last
+  // of each half, F3 = exact factorisation of every partition
+  std::vector<Chain> host;
+  const int nF1 = Ne * 2 * (parts - 1), nF3 = Ne * 2 * parts;
+  host.reserve(nF1 + nF3);
+  for (int pass = 0; pass < 2; ++pass)
+    for (int e = 0; e < Ne; ++e)
+      for (int h = 0; h < 2; ++h) {
+        const int len = h == 0 ? m : nc - m;
+        const int start = h == 0 ? 0 : nc - 1;
+        const int dir = h == 0 ? 1 : -1;
+        const int np = pass == 0 ? parts - 1 : parts;
+        for (int q = 0; q < np; ++q) {
+          const int a = (int)((long long)q * len / parts);
+          const int z = (int)((long long)(q + 1) * len / parts);
+          Chain c;
+          c.e = e;
+          c.start = start + dir * a;
+          c.len = z - a;
+          c.dir = dir;
+          c.half = h;
+          c.part = q;
+          if (pass == 0) {
+            c.end = 0;
+            c.kin = -1;
+          } else {
+            c.end = (q < parts - 1) ? 2 : (h == 0 ? 1 : 2);
+            c.kin = q > 0 ? (e * 2 + h) * parts + q : -1;
+          }
+          host.push_back(c);
+        }
+      }
+  if ((err = hipMemcpyAsync(chains, host.data(), host.size() * sizeof(Chain),
+                            hipMemcpyHostToDevice, st)) != hipSuccess)
+    return err;
+  if ((err = hipStreamSynchronize(st)) != hipSuccess) return err;
+  const size_t blk = 2 * (size_t)BP * BP;
+  double *Kbuf = work;
+  double *G11 = work + (size_t)Ne * 2 * parts * blk;
+  double *GL1 = G11 + (size_t)Ne * 2 * parts * blk;
+  if (parts > 1) {
+    hipLaunchKernelGGL(factor_chain_kernel<BP>, dim3(nF1), dim3(kThreads), shm, st, p, s, f,
+                       (const Chain *)chains, (const double *)Kbuf);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    if ((err = launch_spikes(p, f, chains, nF1, parts, gtiles, G, G11, GL1, st)) != hipSuccess)
+      return err;
+    hipLaunchKernelGGL(interface_kernel<BP>, dim3(Ne * 2), dim3(kThreads), shm, st, p, s, f,
+                       (const Chain *)chains, parts, (const double *)G11, (const double *)GL1,
+                       Kbuf);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+  }
+  hipLaunchKernelGGL(factor_chain_kernel<BP>, dim3(nF3), dim3(kThreads), shm, st, p, s, f,
+                     (const Chain *)(chains + nF1), (const double *)Kbuf);
+  if ((err = hipGetLastError()) != hipSuccess) return err;
   hipLaunchKernelGGL(twist_kernel<BP>, dim3(Ne), dim3(kThreads), shm, st, p, s, f);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_factor(const Pencil &p, const Shifts &s, int Ne, const Factors &f,
-                         hipStream_t st) {
+size_t factor_work_doubles(const Pencil &p, int Ne, int parts) {
+  return 3 * (size_t)Ne * 2 * parts * 2 * p.bp * p.bp;
+}
+
+hipError_t launch_factor(const Pencil &p, const Shifts &s, int Ne, const Factors &f, int parts,
+                         double *work, Chain *chains, double *G, int gtiles, hipStream_t st) {
+  if (parts < 1) return hipErrorInvalidValue;
   switch (p.bp) {
-    case 16: return launch_factor_bp<16>(p, s, Ne, f, st);
-    case 32: return launch_factor_bp<32>(p, s, Ne, f, st);
-    case 48: return launch_factor_bp<48>(p, s, Ne, f, st);
-    case 64: return launch_factor_bp<64>(p, s, Ne, f, st);
+    case 16: return launch_factor_bp<16>(p, s, Ne, f, parts, work, chains, G, gtiles, st);
+    case 32: return launch_factor_bp<32>(p, s, Ne, f, parts, work, chains, G, gtiles, st);
+    case 48: return launch_factor_bp<48>(p, s, Ne, f, parts, work, chains, G, gtiles, st);
+    case 64: return launch_factor_bp<64>(p, s, Ne, f, parts, work, chains, G, gtiles, st);
     default: return hipErrorInvalidValue;
   }
 }

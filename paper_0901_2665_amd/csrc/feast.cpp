@@ -29,7 +29,7 @@ struct Buf {
 
 enum Slot {
   S_SINV, S_W, S_WT, S_TW, S_G, S_TV, S_Y, S_R, S_P, S_Q, S_AV, S_BV, S_X, S_GRAMP, S_AQ, S_BQ,
-  S_EPS, S_PHI, S_RRS, S_FLAG, S_RESP, S_RES, S_PERM, S_T0, S_T1, S_COUNT
+  S_EPS, S_PHI, S_RRS, S_FLAG, S_RESP, S_RES, S_PERM, S_T0, S_T1, S_FWORK, S_CHAINS, S_COUNT
 };
 
 }  // namespace
@@ -212,25 +212,46 @@ struct Work {
   Pencil p;
   Factors f;
   SolveBufs sb;
-  int Ne, m0, m0p;
+  int Ne, m0, m0p, parts, gtiles;
   size_t rows;
+  double *fwork;
+  Chain *chains;
 };
 
+// Partitions per half chain of the factorisation: enough independent chains
+// for every compute unit (2 Ne chains a partition), at least 8 cells each.
+int choose_parts(int nc, int Ne, int requested) {
+  const int half = nc / 2;  // cells of the shorter (bottom) half; no empty partitions
+  if (requested > 0) return std::max(1, std::min(requested, half));
+  const int by_len = half / 8;
+  const int by_cus = std::max(1, 256 / (2 * Ne));
+  return std::max(1, std::min(by_len, by_cus));
+}
+
 // Workspace for the factors and the sweeps of Ne shifts.
-int prepare_factor(feast_ctx *ctx, const Pencil &p, int Ne, int m0p, Work &wk) {
+int prepare_factor(feast_ctx *ctx, const Pencil &p, int Ne, int m0p, int parts, Work &wk) {
   const size_t blk = 2 * (size_t)p.bp * p.bp;
   wk.p = p;
   wk.Ne = Ne;
   wk.m0p = m0p;
   wk.rows = (size_t)p.nc * p.bp;
   wk.f.m = p.nc - p.nc / 2;
+  wk.parts = parts;
+  wk.gtiles = std::max(m0p, p.bp) / kTile;
   HIPCHK(ensure_t(ctx, S_SINV, (size_t)Ne * p.nc * blk, &wk.f.Sinv));
   HIPCHK(ensure_t(ctx, S_W, (size_t)Ne * p.nc * blk, &wk.f.W));
   HIPCHK(ensure_t(ctx, S_WT, (size_t)Ne * p.nc * blk, &wk.f.WT));
   HIPCHK(ensure_t(ctx, S_TW, (size_t)Ne * blk, &wk.f.TW));
-  HIPCHK(ensure_t(ctx, S_G, (size_t)Ne * wk.rows * m0p * 2, &wk.sb.G));
+  HIPCHK(ensure_t(ctx, S_G, (size_t)Ne * wk.gtiles * wk.rows * kTile * 2, &wk.sb.G));
   HIPCHK(ensure_t(ctx, S_TV, (size_t)Ne * (m0p / kTile) * 4 * p.bp * kTile, &wk.sb.TV));
+  HIPCHK(ensure_t(ctx, S_FWORK, factor_work_doubles(p, Ne, parts), &wk.fwork));
+  HIPCHK(ensure_t(ctx, S_CHAINS, (size_t)3 * Ne * 2 * parts, &wk.chains));
   return 0;
+}
+
+hipError_t run_factor(feast_ctx *ctx, const Work &wk, const Shifts &s) {
+  return launch_factor(wk.p, s, wk.Ne, wk.f, wk.parts, wk.fwork, wk.chains, wk.sb.G, wk.gtiles,
+                       ctx->stream);
 }
 
 }  // namespace
@@ -242,6 +263,7 @@ void feast_default_opts(feast_opts *opts) {
   opts->tol = 1e-12;
   opts->max_loops = 20;
   opts->precision = 0;
+  opts->partitions = 0;
   opts->Y0 = nullptr;
 }
 
@@ -374,7 +396,7 @@ int feast_shifted_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double z_re, 
   Pencil p = make_pencil(AB);
   const int mp = round16(m);
   Work wk;
-  st = prepare_factor(ctx, p, 1, mp, wk);
+  st = prepare_factor(ctx, p, 1, mp, choose_parts(p.nc, 1, 0), wk);
   if (st) return st;
   Shifts s;
   std::memset(&s, 0, sizeof(s));
@@ -384,7 +406,7 @@ int feast_shifted_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double z_re, 
   HIPCHK(ensure_t(ctx, S_R, wk.rows * mp, &rin));
   HIPCHK(ensure_t(ctx, S_T0, wk.rows * mp, &xr));
   HIPCHK(ensure_t(ctx, S_T1, wk.rows * mp, &xi));
-  HIPCHK(launch_factor(p, s, 1, wk.f, ctx->stream));
+  HIPCHK(run_factor(ctx, wk, s));
   HIPCHK(launch_pack(R, p.nc, p.b, p.bp, m, mp, rin, ctx->stream));
   HIPCHK(launch_sweeps_complex(p, s, wk.f, wk.sb, rin, mp, xr, xi, ctx->stream));
   HIPCHK(launch_unpack(xr, p.nc, p.b, p.bp, m, mp, nullptr, X_re, ctx->stream));
@@ -405,7 +427,7 @@ int feast_filter(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double 
   Pencil p = make_pencil(AB);
   const int mp = round16(M0);
   Work wk;
-  st = prepare_factor(ctx, p, Ne, mp, wk);
+  st = prepare_factor(ctx, p, Ne, mp, choose_parts(p.nc, Ne, 0), wk);
   if (st) return st;
   Shifts s;
   make_shifts(Ne, emin, emax, s);
@@ -414,7 +436,7 @@ int feast_filter(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double 
   HIPCHK(ensure_t(ctx, S_R, wk.rows * mp, &r));
   HIPCHK(ensure_t(ctx, S_P, (size_t)Ne * wk.rows * mp, &pp));
   HIPCHK(ensure_t(ctx, S_Q, wk.rows * mp, &q));
-  HIPCHK(launch_factor(p, s, Ne, wk.f, ctx->stream));
+  HIPCHK(run_factor(ctx, wk, s));
   HIPCHK(launch_pack(Y, p.nc, p.b, p.bp, M0, mp, y, ctx->stream));
   HIPCHK(launch_bt_multiply(p, 1, y, mp, r, ctx->stream));
   HIPCHK(launch_sweeps(p, s, Ne, wk.f, wk.sb, r, mp, pp, 3, ctx->stream));
@@ -477,7 +499,7 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
   feast_default_opts(&o);
   if (opts) o = *opts;
   if (!o.Y0) return -5;
-  if (!(o.tol > 0.0) || o.max_loops < 1 || o.precision != 0) return -7;
+  if (!(o.tol > 0.0) || o.max_loops < 1 || o.precision != 0 || o.partitions < 0) return -7;
   HIPCHK(hipSetDevice(ctx->device));
   hipStream_t sm = ctx->stream;
 
@@ -487,7 +509,7 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
   Pencil p = make_pencil(AB);
   const int mp = round16(M0);
   Work wk;
-  st = prepare_factor(ctx, p, Ne, mp, wk);
+  st = prepare_factor(ctx, p, Ne, mp, choose_parts(p.nc, Ne, o.partitions), wk);
   if (st) return st;
   const size_t rows = wk.rows;
   Shifts s;
@@ -515,7 +537,7 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
   HIPCHK(ensure_t(ctx, S_PERM, (size_t)M0, &perm));
 
   // factor every shifted matrix once (Sec. V, parallelism (ii))
-  TIMED(K_FACTOR, launch_factor(p, s, Ne, wk.f, sm));
+  TIMED(K_FACTOR, run_factor(ctx, wk, s));
   TIMED(K_LAYOUT, launch_pack(o.Y0, p.nc, p.b, p.bp, M0, mp, y, sm));
 
   std::vector<double> traces;

@@ -27,7 +27,29 @@ struct Factors {
   int m;                   // twist split
 };
 
-hipError_t launch_factor(const Pencil &p, const Shifts &s, int Ne, const Factors &f,
+// One chain of cells processed by one workgroup of the factor kernels.
+struct Chain {
+  int e;      // node
+  int start;  // first cell
+  int len;    // number of cells
+  int dir;    // +1 top-down, -1 bottom-up
+  int end;    // last cell: 0 invert only, 1 keep raw S (twist cell), 2 invert + W
+  int kin;    // incoming self-energy in Kbuf (-1: none): S_start = D_start - K
+  int half;   // 0 top, 1 bottom
+  int part;   // partition index within the half
+};
+
+// Partitioned exact factorisation (see factor.hip).  parts = partitions per
+// half (1: one chain per half).  work: device workspace from
+// factor_work_doubles(); chains: device buffer for 3 * Ne * 2 * parts Chain.
+size_t factor_work_doubles(const Pencil &p, int Ne, int parts);
+hipError_t launch_factor(const Pencil &p, const Shifts &s, int Ne, const Factors &f, int parts,
+                         double *work, Chain *chains, double *G, int gtiles, hipStream_t st);
+
+// Spike solves of the partitioned factorisation (sweep.hip): for every chain,
+// the first and last block of T^{-1} E_1 where T is the chain's local matrix.
+hipError_t launch_spikes(const Pencil &p, const Factors &f, const Chain *chains, int nchains,
+                         int parts, int gtiles, double *G, double *G11, double *GL1,
                          hipStream_t st);
 
 // Forward/back sweeps of all Ne shifts for right-hand side R (real,

@@ -277,6 +277,96 @@ __global__ __launch_bounds__(BP * 4) void back_kernel(SweepArgs a) {
   }
 }
 
+
+// Spike solves of the partitioned factorisation.  For a chain with local
+// matrix T (factored by its own top-down recurrence: Sinv_j, W_j) and
+// E_1 = first block column of the identity, y = T^{-1} E_1 follows from
+//   h_0 = I,  h_{j+1} = -W_j^T h_j,  g_j = Sinv_j h_j,
+//   y_last = g_last,  y_j = g_j - W_j y_{j+1};
+// the kernel keeps y_first = [T^-1]_{first,first} and
+// y_last = [T^-1]_{last,first}.  One workgroup per (chain, tile of 8 columns).
+struct SpikeArgs {
+  Pencil p;
+  Factors f;
+  const Chain *chains;
+  int parts, gtiles;
+  double *G, *G11, *GL1;
+};
+
+template <int BP>
+__device__ __forceinline__ void acc_store_block_cols(double *dst, const d4 &acc, int tau) {
+  const int l = lane_id(), w = wave_id();
+  const int n = l & 15, plane = n >> 3, col = n & 7;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = w * 16 + acc_row(l, r);
+    dst[(size_t)plane * BP * BP + row * BP + tau * kTile + col] = acc[r];
+  }
+}
+
+template <int BP>
+__global__ __launch_bounds__(BP * 4) void spike_kernel(SpikeArgs a) {
+  __shared__ VecLds<BP> s;
+  constexpr int NTILE = BP / kTile;
+  const int ci = blockIdx.x / NTILE, tau = blockIdx.x % NTILE;
+  const Chain ch = a.chains[ci];
+  const int e = ch.e, start = ch.start, dir = ch.dir, len = ch.len;
+  if (len <= 0) return;
+  const int nc = a.p.nc;
+  const size_t blk = 2 * (size_t)BP * BP;
+  const size_t vt = 2 * (size_t)BP * kTile;
+  const double *Sinv = a.f.Sinv + (size_t)e * nc * blk;
+  const double *W = a.f.W + (size_t)e * nc * blk;
+  const double *WT = a.f.WT + (size_t)e * nc * blk;
+  double *G = a.G + ((size_t)e * a.gtiles + tau) * nc * vt;
+  const size_t out = ((size_t)(e * 2 + ch.half) * a.parts + ch.part) * blk;
+  const int l = lane_id(), w = wave_id();
+  {
+    d4 h;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = w * 16 + acc_row(l, r), n = l & 15;
+      h[r] = (n < 8 && row == tau * kTile + n) ? 1.0 : 0.0;
+    }
+    acc_store_vec<BP>(&s.v[0][0][0][0], h);
+  }
+  __syncthreads();
+  int cur = 0;
+  Frag<BP> fa, fb;
+  d4 g = d4zero();
+  for (int j = 0; j < len; ++j) {
+    const int c = start + dir * j;
+    frag_load<BP>(fa, Sinv + c * blk);
+    d4 g0 = d4zero(), g1 = d4zero();
+    frag_mfma<BP>(g0, g1, fa, s.v[cur], 1.0);
+    g = g0 + g1;
+    acc_store_vec<BP>(G + c * vt, g);
+    if (j < len - 1) {
+      frag_load<BP>(fb, W + c * blk);
+      d4 h0 = d4zero(), h1 = d4zero();
+      frag_mfma<BP>(h0, h1, fb, s.v[cur], -1.0);
+      acc_store_vec<BP>(&s.v[cur ^ 1][0][0][0], h0 + h1);
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+  acc_store_block_cols<BP>(a.GL1 + out, g, tau);
+  acc_store_vec<BP>(&s.v[0][0][0][0], g);
+  __syncthreads();
+  cur = 0;
+  for (int j = len - 2; j >= 0; --j) {
+    const int c = start + dir * j;
+    frag_load<BP>(fa, WT + c * blk);
+    d4 x0 = acc_load_vec<BP>(G + c * vt), x1 = d4zero();
+    frag_mfma<BP>(x0, x1, fa, s.v[cur], -1.0);
+    g = x0 + x1;
+    acc_store_vec<BP>(&s.v[cur ^ 1][0][0][0], g);
+    __syncthreads();
+    cur ^= 1;
+  }
+  acc_store_block_cols<BP>(a.G11 + out, g, tau);
+}
+
 // part: 1 = forward sweep, 2 = back sweep, 3 = both
 template <int BP>
 hipError_t launch_sweeps_bp(SweepArgs &a, int Ne, bool complex_out, int part, hipStream_t st) {
@@ -315,6 +405,24 @@ hipError_t launch_sweeps(const Pencil &p, const Shifts &s, int Ne, const Factors
   a.m0p = m0p; a.ntiles = m0p / kTile;
   for (int e = 0; e < kMaxNe; ++e) { a.kre[e] = s.kre[e]; a.kim[e] = s.kim[e]; }
   return dispatch(a, Ne, false, part, st);
+}
+
+hipError_t launch_spikes(const Pencil &p, const Factors &f, const Chain *chains, int nchains,
+                         int parts, int gtiles, double *G, double *G11, double *GL1,
+                         hipStream_t st) {
+  if (nchains <= 0) return hipSuccess;
+  SpikeArgs a;
+  a.p = p; a.f = f; a.chains = chains; a.parts = parts; a.gtiles = gtiles;
+  a.G = G; a.G11 = G11; a.GL1 = GL1;
+  const dim3 grid(nchains * (p.bp / kTile));
+  switch (p.bp) {
+    case 16: hipLaunchKernelGGL(spike_kernel<16>, grid, dim3(64), 0, st, a); break;
+    case 32: hipLaunchKernelGGL(spike_kernel<32>, grid, dim3(128), 0, st, a); break;
+    case 48: hipLaunchKernelGGL(spike_kernel<48>, grid, dim3(192), 0, st, a); break;
+    case 64: hipLaunchKernelGGL(spike_kernel<64>, grid, dim3(256), 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_sweeps_complex(const Pencil &p, const Shifts &s, const Factors &f,

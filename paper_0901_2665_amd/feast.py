@@ -34,7 +34,8 @@ class BTMatrix(ctypes.Structure):
 
 class Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_loops", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("Y0", ctypes.c_void_p)]
+                ("precision", ctypes.c_int32), ("partitions", ctypes.c_int32),
+                ("Y0", ctypes.c_void_p)]
 
 
 class Info(ctypes.Structure):
@@ -172,7 +173,8 @@ class Context:
         return st
 
     def solve(self, p: Pencil, emin: float, emax: float, M0: int, Ne: int, Y0,
-              tol: float = 1e-12, max_loops: int = 20, out=None) -> SolveResult:
+              tol: float = 1e-12, max_loops: int = 20, out=None,
+              partitions: int = 0) -> SolveResult:
         import torch
         dev = p.Ad.device
         if out is None:
@@ -181,7 +183,7 @@ class Context:
             res = torch.empty(M0, dtype=torch.float64, device=dev)
         else:
             lam, X, res = out
-        opts = Opts(tol, max_loops, 0, _ptr(Y0))
+        opts = Opts(tol, max_loops, 0, partitions, _ptr(Y0))
         info = Info()
         ab = p.struct()
         st = self.lib.feast_solve(self.handle, ctypes.byref(ab), emin, emax, M0, Ne,

@@ -56,7 +56,7 @@ def chain_small(nc, b, seed):
 
 
 SHAPES = [(1, 5, 3), (2, 16, 16), (3, 17, 30), (20, 40, 30), (7, 64, 128), (5, 33, 100),
-          (9, 48, 8), (4, 64, 1)]
+          (9, 48, 8), (4, 64, 1), (40, 16, 8), (67, 32, 20)]
 
 
 @pytest.mark.parametrize("nc,b,m", SHAPES)
@@ -238,6 +238,17 @@ def test_solve_small(ctx, torch, nc, b, seed, k0, m, extra):
     r = ctx.solve(gpencil(p), emin, emax, m0, 8, dev(torch, Y0), tol=1e-13, max_loops=40)
     ref = O.feast(p, emin, emax, m0, 8, Y0, tol=1e-13, max_loops=40)
     assert r.status == ref.status
+    check_against_oracle(r, ref, p, emin, emax)
+
+
+@pytest.mark.parametrize("parts", [1, 2, 3, 5])
+def test_solve_partitioned_factor(ctx, torch, parts):
+    # the partitioned factorisation is exact: results agree with the oracle
+    # for any number of partitions per half chain
+    p, emin, emax, m0, ne, Y0 = W.make_workload("chain800")
+    r = ctx.solve(gpencil(p), emin, emax, m0, ne, dev(torch, Y0), partitions=parts)
+    ref = O.feast(p, emin, emax, m0, ne, Y0)
+    assert r.status == 0
     check_against_oracle(r, ref, p, emin, emax)
 
 

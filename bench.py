@@ -111,7 +111,7 @@ def main():
     # accuracy gate on the last solve
     lam = out[0].cpu().numpy()
     gate = {"M": r.M, "expected_M": wl["n_eig"], "max_res": r.max_res, "loops": r.loops,
-            "status": r.status}
+            "status": r.status, "rr_sweeps": r.rr_sweeps}
     gpath = os.path.join(ROOT, "tests", "golden", f"feast_{args.workload}.json")
     if os.path.exists(gpath):
         g = json.load(open(gpath))

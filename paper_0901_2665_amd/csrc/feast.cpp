@@ -476,7 +476,7 @@ int feast_reduced_eig(feast_ctx *ctx, int32_t M0, const double *AQ, const double
   HIPCHK(hipSetDevice(ctx->device));
   double *scr;
   int *flag;
-  HIPCHK(ensure_t(ctx, S_RRS, 4 * (size_t)kMaxM0 * kMaxM0, &scr));
+  HIPCHK(ensure_t(ctx, S_RRS, reduced_eig_scratch_doubles(), &scr));
   HIPCHK(ensure_t(ctx, S_FLAG, 4, &flag));
   HIPCHK(launch_reduced_eig(AQ, BQ, M0, eps, Phi, scr, flag, ctx->stream));
   HIPCHK(hipMemcpyAsync(ctx->h_flag, flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
@@ -530,7 +530,7 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
   HIPCHK(ensure_t(ctx, S_BQ, (size_t)M0 * M0, &bq));
   HIPCHK(ensure_t(ctx, S_EPS, (size_t)M0, &eps));
   HIPCHK(ensure_t(ctx, S_PHI, (size_t)M0 * M0, &phi));
-  HIPCHK(ensure_t(ctx, S_RRS, 4 * (size_t)kMaxM0 * kMaxM0, &scr));
+  HIPCHK(ensure_t(ctx, S_RRS, reduced_eig_scratch_doubles(), &scr));
   HIPCHK(ensure_t(ctx, S_FLAG, 4, &flag));
   HIPCHK(ensure_t(ctx, S_RESP, residual_partial_doubles(rows, mp), &resp));
   HIPCHK(ensure_t(ctx, S_RES, (size_t)M0, &resi));

@@ -93,7 +93,9 @@ hipError_t launch_gather(const double *src, const int *perm, int m, double *dst,
                          hipStream_t st);
 
 // Reduced eigenproblem (rr.hip): one workgroup.
-// scratch: 4 * 128 * 128 doubles.  eps, Phi outputs; flag[0] = fallback.
+// scratch: reduced_eig_scratch_doubles().  eps, Phi outputs; flag[0] =
+// fallback, flag[1] = Jacobi sweeps, flag[2] = sweeps of the fallback.
+size_t reduced_eig_scratch_doubles();
 hipError_t launch_reduced_eig(const double *AQ, const double *BQ, int n, double *eps,
                               double *Phi, double *scratch, int *flag, hipStream_t st);
 

@@ -9,9 +9,9 @@
 //     the other columns of T are zero.
 //  2. C = T^T A_Q T, diagonalised by cyclic two-sided Jacobi rotations in a
 //     round-robin order (all n/2 disjoint rotations of a round at once);
-//     a rotation is skipped when |c_pq| <= 2^-53 sqrt(|c_pp c_qq|) or
-//     |c_pq| <= 2^-56 ||C||_F, and the sweeps stop after a sweep without
-//     rotations.
+//     a rotation is skipped when |c_pq| <= u sqrt(|c_pp c_qq|) or
+//     |c_pq| <= u ||C||_F / 8 (u = 2^-53), and the sweeps stop after a sweep
+//     without rotations.
 //  3. eps ascending (dropped directions: NaN, last), Phi = T V.
 #include "common.h"
 #include "kernels.h"
@@ -23,6 +23,7 @@ constexpr int kThreads = 1024;
 constexpr int kMaxN = 128;
 
 struct RRShared {
+  unsigned char blk_a[kMaxN / 2 * (kMaxN / 2 + 1) / 2], blk_b[kMaxN / 2 * (kMaxN / 2 + 1) / 2];
   int pp[kMaxN / 2], pq[kMaxN / 2];
   double cs[kMaxN / 2], sn[kMaxN / 2];
   int rot;
@@ -36,12 +37,22 @@ struct RRShared {
 
 __device__ __forceinline__ int rr_player(int s, int i, int nn) {
   // circle method: player 0 fixed, the others rotate by one place a round
-  return i == 0 ? 0 : 1 + ((i - 1 + s) % (nn - 1));
+  // (0 <= s < nn - 1, so one conditional subtraction is the modulo)
+  if (i == 0) return 0;
+  int x = i - 1 + s;
+  if (x >= nn - 1) x -= nn - 1;
+  return 1 + x;
 }
 
-// Cyclic Jacobi on the nn x nn symmetric matrix C (LDS, row stride ldc);
-// V (global, nn x nn, row-major) accumulates the rotations.
-__device__ int jacobi(double *C, int ldc, double *V, int nn, RRShared &sh) {
+constexpr int kMaxSweeps = 60;
+
+// Cyclic Jacobi on the nn x nn symmetric matrix C (LDS, row stride ldc).
+// The rotations of every round are appended to rlog (global, 2 * nn/2
+// doubles a round: cosines then sines); the eigenvectors are rebuilt from
+// the log afterwards (replay_rotations), so a round touches only C.
+// Returns the number of sweeps that rotated (the final check sweep, which
+// rotates nothing, is not counted).
+__device__ int jacobi(double *C, int ldc, double *rlog, int nn, RRShared &sh) {
   const int tid = threadIdx.x;
   const int half = nn / 2;
   const double eps = 1.1102230246251565e-16;  // 2^-53
@@ -63,8 +74,17 @@ __device__ int jacobi(double *C, int ldc, double *V, int nn, RRShared &sh) {
   }
   __syncthreads();
   const double floor_abs = 0.125 * eps * sqrt(sh.norm);
+  const int nblk = half * (half + 1) / 2;  // 2x2 blocks (a <= b)
+  if (tid < half) {  // table of the (a, b) blocks, row a holds half - a of them
+    int idx = tid * half - tid * (tid - 1) / 2;
+    for (int bq = tid; bq < half; ++bq, ++idx) {
+      sh.blk_a[idx] = (unsigned char)tid;
+      sh.blk_b[idx] = (unsigned char)bq;
+    }
+  }
+  __syncthreads();
   int sweep = 0;
-  for (; sweep < 60; ++sweep) {
+  for (; sweep < kMaxSweeps; ++sweep) {
     if (tid == 0) sh.rot = 0;
     __syncthreads();
     for (int s = 0; s < nn - 1; ++s) {
@@ -74,9 +94,12 @@ __device__ int jacobi(double *C, int ldc, double *V, int nn, RRShared &sh) {
         double app = C[p * ldc + p], aqq = C[q * ldc + q], apq = C[p * ldc + q];
         double c = 1.0, sgn = 0.0;
         if (fabs(apq) > floor_abs && fabs(apq) > eps * sqrt(fabs(app * aqq))) {
-          double tau = (aqq - app) / (2.0 * apq);
-          double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + hypot(1.0, tau));
-          c = 1.0 / sqrt(1.0 + t * t);
+          // t = tan of the rotation angle: the smaller root of t^2 + 2 tau t - 1
+          const double tau = (aqq - app) * rcp_newton(2.0 * apq);
+          const double at = fabs(tau);
+          const double root = at < 1e150 ? sqrt(1.0 + tau * tau) : at;
+          const double t = (tau >= 0.0 ? 1.0 : -1.0) * rcp_newton(at + root);
+          c = rcp_newton(sqrt(1.0 + t * t));
           sgn = t * c;
           atomicAdd(&sh.rot, 1);
         }
@@ -84,17 +107,19 @@ __device__ int jacobi(double *C, int ldc, double *V, int nn, RRShared &sh) {
         sh.pq[tid] = q;
         sh.cs[tid] = c;
         sh.sn[tid] = sgn;
+        double *lg = rlog + (size_t)(sweep * (nn - 1) + s) * 2 * half;
+        lg[tid] = c;
+        lg[half + tid] = sgn;
       }
       __syncthreads();
       // C <- J^T C J on 2x2 blocks (a <= b), mirrored to keep C symmetric
-      for (int idx = tid; idx < half * half; idx += kThreads) {
-        const int a = idx / half, bq = idx % half;
-        if (a > bq) continue;
+      for (int idx = tid; idx < nblk; idx += kThreads) {
+        const int a = sh.blk_a[idx], bq = sh.blk_b[idx];
         const int pa = sh.pp[a], qa = sh.pq[a], pb = sh.pp[bq], qb = sh.pq[bq];
         const double ca = sh.cs[a], sa = sh.sn[a], cb = sh.cs[bq], sb = sh.sn[bq];
         if (a == bq) {
-          const double app = C[pa * ldc + pa], aqq = C[qa * ldc + qa], apq = C[pa * ldc + qa];
           if (sa != 0.0) {
+            const double app = C[pa * ldc + pa], aqq = C[qa * ldc + qa], apq = C[pa * ldc + qa];
             const double t = sa / ca;
             C[pa * ldc + pa] = app - t * apq;
             C[qa * ldc + qa] = aqq + t * apq;
@@ -103,6 +128,7 @@ __device__ int jacobi(double *C, int ldc, double *V, int nn, RRShared &sh) {
           }
           continue;
         }
+        if (sa == 0.0 && sb == 0.0) continue;
         const double x11 = C[pa * ldc + pb], x12 = C[pa * ldc + qb];
         const double x21 = C[qa * ldc + pb], x22 = C[qa * ldc + qb];
         const double y11 = cb * x11 - sb * x12, y12 = sb * x11 + cb * x12;
@@ -114,24 +140,95 @@ __device__ int jacobi(double *C, int ldc, double *V, int nn, RRShared &sh) {
         C[qa * ldc + pb] = z21; C[pb * ldc + qa] = z21;
         C[qa * ldc + qb] = z22; C[qb * ldc + qa] = z22;
       }
-      // V <- V J
-      for (int idx = tid; idx < nn * half; idx += kThreads) {
-        const int r = idx / half, a = idx % half;
-        const double sa = sh.sn[a];
-        if (sa == 0.0) continue;
-        const double ca = sh.cs[a];
-        const int pa = sh.pp[a], qa = sh.pq[a];
-        const double vp = V[r * nn + pa], vq = V[r * nn + qa];
-        V[r * nn + pa] = ca * vp - sa * vq;
-        V[r * nn + qa] = sa * vp + ca * vq;
-      }
       __syncthreads();
     }
     const int rot = sh.rot;
     __syncthreads();
     if (rot == 0) break;
   }
-  return sweep;
+  return sweep;  // sweeps with at least one rotation (all of them if not converged)
+}
+
+// V = J_1 J_2 ... J_R for the logged rounds, V (LDS, row stride ldv) starts
+// as the identity.  A round rotates column pairs, so the rows of V evolve
+// independently: each wave owns nn/16 rows (eight lanes a row, each lane a
+// fixed set of pairs) and runs through all rounds without workgroup
+// barriers; LDS accesses of one wave are ordered by a wave-level fence.
+__device__ void replay_rotations(double *V, int ldv, const double *rlog, int rounds, int nn) {
+  const int tid = threadIdx.x;
+  const int half = nn / 2;
+  for (int idx = tid; idx < nn * nn; idx += kThreads)
+    V[(idx / nn) * ldv + idx % nn] = (idx / nn == idx % nn) ? 1.0 : 0.0;
+  __syncthreads();
+  const int w = tid >> 6, l = tid & 63;
+  const int rows_per_wave = (nn + 15) / 16;   // <= 8
+  const int row = w * rows_per_wave + (l >> 3);
+  const int j = l & 7;
+  const bool act = (l >> 3) < rows_per_wave && row < nn;
+  constexpr int PA = kMaxN / 16;  // pairs a lane handles (a = j, j + 8, ...)
+  double cn[PA], sn[PA];          // rotation of the next round, loaded ahead
+#pragma unroll
+  for (int t = 0; t < PA; ++t) {
+    const int a = j + 8 * t;
+    cn[t] = (rounds > 0 && a < half) ? rlog[a] : 1.0;
+    sn[t] = (rounds > 0 && a < half) ? rlog[half + a] : 0.0;
+  }
+  int s = 0;
+  for (int g = 0; g < rounds; ++g) {
+    double cc[PA], ss[PA];
+#pragma unroll
+    for (int t = 0; t < PA; ++t) {
+      cc[t] = cn[t];
+      ss[t] = sn[t];
+    }
+    if (g + 1 < rounds) {
+      const double *lg = rlog + (size_t)(g + 1) * 2 * half;
+#pragma unroll
+      for (int t = 0; t < PA; ++t) {
+        const int a = j + 8 * t;
+        cn[t] = a < half ? lg[a] : 1.0;
+        sn[t] = a < half ? lg[half + a] : 0.0;
+      }
+    }
+    if (act) {
+#pragma unroll
+      for (int t = 0; t < PA; ++t) {
+        const int a = j + 8 * t;
+        if (a < half && ss[t] != 0.0) {
+          const int u = rr_player(s, a, nn), v = rr_player(s, nn - 1 - a, nn);
+          const int p = u < v ? u : v, q = u < v ? v : u;
+          const double vp = V[row * ldv + p], vq = V[row * ldv + q];
+          V[row * ldv + p] = cc[t] * vp - ss[t] * vq;
+          V[row * ldv + q] = ss[t] * vp + cc[t] * vq;
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (++s == nn - 1) s = 0;
+  }
+  __syncthreads();
+}
+
+// Dense product of the workgroup on the matrix cores, n <= 128:
+//   out(r, c) = sum_k a(r, k) b(k, c),   0 <= r, c < nt*16,
+// with operand readers a, b (zero outside the matrices) and a writer.  The
+// 16 waves share the (nt x nt) output tiles.
+template <typename FA, typename FB, typename FO>
+__device__ __forceinline__ void wg_gemm(int nt, FA a, FB b, FO out) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int kl = l >> 4;
+  for (int t = w; t < nt * nt; t += kThreads / 64) {
+    const int r0 = (t / nt) * 16, c0 = (t % nt) * 16;
+    d4 acc0 = d4zero(), acc1 = d4zero();
+    for (int k0 = 0; k0 < nt * 16; k0 += 8) {
+      acc0 = mfma(a(r0 + (l & 15), k0 + kl), b(k0 + kl, c0 + (l & 15)), acc0);
+      acc1 = mfma(a(r0 + (l & 15), k0 + 4 + kl), b(k0 + 4 + kl, c0 + (l & 15)), acc1);
+    }
+    const d4 acc = acc0 + acc1;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) out(r0 + (l >> 4) + 4 * r, c0 + (l & 15), acc[r]);
+  }
 }
 
 __global__ __launch_bounds__(kThreads) void reduced_eig_kernel(const double *AQ, const double *BQ,
@@ -142,10 +239,11 @@ __global__ __launch_bounds__(kThreads) void reduced_eig_kernel(const double *AQ,
   const int tid = threadIdx.x;
   const int nn = n + (n & 1);
   const int ldc = nn + 1;
+  const int nt = (nn + 15) / 16;
   double *T = scratch;                 // nn x nn whitening
   double *T1 = scratch + nn * nn;      // nn x nn product
-  double *V = scratch + 2 * nn * nn;   // nn x nn rotations
-  double *Lg = scratch + 3 * nn * nn;  // nn x nn L^{-1}
+  double *V = scratch + 2 * nn * nn;   // nn x nn eigenvectors of B_Q (fallback)
+  double *rlog = scratch + 3 * nn * nn;  // rotation log
 
   for (int idx = tid; idx < nn * nn; idx += kThreads) {
     const int i = idx / nn, j = idx % nn;
@@ -178,39 +276,46 @@ __global__ __launch_bounds__(kThreads) void reduced_eig_kernel(const double *AQ,
   const bool fallback = sh.fail != 0;
 
   if (!fallback) {
-    // L^{-1} by columns (forward substitution), then T = L^{-T}
-    if (tid < n) {
-      const int j = tid;
-      for (int i = 0; i < n; ++i) {
-        double x;
-        if (i < j) {
-          x = 0.0;
-        } else if (i == j) {
-          x = 1.0 / C[i * ldc + i];
-        } else {
-          double s = 0.0;
-          for (int k = j; k < i; ++k) s += C[i * ldc + k] * Lg[k * nn + j];
-          x = -s / C[i * ldc + i];
+    // X = L^{-1}, row by row: X_ii = 1/L_ii, X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj;
+    // X_ij (j < i) is kept in the free upper triangle of C at (j, i).
+    // Eight threads share one dot product and combine it with shuffles.
+    for (int i = 0; i < n; ++i) {
+      const double dii = 1.0 / C[i * ldc + i];
+      const int j = tid >> 3, part = tid & 7;
+      double sum = 0.0;
+      if (j < i) {
+        for (int k = j + part; k < i; k += 8) {
+          const double xkj = (k == j) ? sh.diag[k] : C[j * ldc + k];
+          sum += C[i * ldc + k] * xkj;
         }
-        Lg[i * nn + j] = x;
       }
+      sum += __shfl_xor(sum, 1);
+      sum += __shfl_xor(sum, 2);
+      sum += __shfl_xor(sum, 4);
+      if (j < i && part == 0) C[j * ldc + i] = -dii * sum;
+      if (tid == 0) sh.diag[i] = dii;
+      __syncthreads();
     }
-    __syncthreads();
+    // T = L^{-T} = X^T (upper triangular)
     for (int idx = tid; idx < nn * nn; idx += kThreads) {
       const int i = idx / nn, j = idx % nn;
-      T[idx] = (i < n && j < n) ? Lg[j * nn + i] : 0.0;
+      double v = 0.0;
+      if (i < n && j < n) v = (i < j) ? C[i * ldc + j] : (i == j ? sh.diag[i] : 0.0);
+      T[idx] = v;
     }
   } else {
     // eigen-decomposition of B_Q, drop directions with mu <= 1e-14 max
     for (int idx = tid; idx < nn * nn; idx += kThreads) {
       const int i = idx / nn, j = idx % nn;
       C[i * ldc + j] = (i < n && j < n) ? BQ[i * n + j] : 0.0;
-      V[idx] = (i == j) ? 1.0 : 0.0;
     }
     __syncthreads();
-    const int fsweeps = jacobi(C, ldc, V, nn, sh);
+    const int fsweeps = jacobi(C, ldc, rlog, nn, sh);
     if (tid == 0) flag[2] = fsweeps;
     if (tid < nn) sh.diag[tid] = C[tid * ldc + tid];
+    __syncthreads();
+    replay_rotations(C, ldc, rlog, fsweeps * (nn - 1), nn);
+    for (int idx = tid; idx < nn * nn; idx += kThreads) V[idx] = C[(idx / nn) * ldc + idx % nn];
     __syncthreads();
     double mumax = 0.0;
     for (int i = 0; i < n; ++i) mumax = fmax(mumax, sh.diag[i]);
@@ -223,32 +328,38 @@ __global__ __launch_bounds__(kThreads) void reduced_eig_kernel(const double *AQ,
   }
   __syncthreads();
 
-  // ---- C = T^T A_Q T ----
-  for (int idx = tid; idx < nn * nn; idx += kThreads) {
-    const int i = idx / nn, j = idx % nn;
-    double s = 0.0;
-    if (i < n)
-      for (int k = 0; k < n; ++k) s += AQ[i * n + k] * T[k * nn + j];
-    T1[idx] = s;
-  }
+  // ---- C = T^T A_Q T on the matrix cores ----
+  const int nlim = nt * 16;
+  wg_gemm(
+      nt, [&](int r, int k) { return (r < n && k < n) ? AQ[k * n + r] : 0.0; },  // symmetric
+      [&](int k, int c) { return (k < nn && c < nn) ? T[k * nn + c] : 0.0; },
+      [&](int r, int c, double v) { if (r < nn && c < nn) T1[r * nn + c] = v; });
   __syncthreads();
+  wg_gemm(
+      nt, [&](int r, int k) { return (r < nn && k < nn) ? T[k * nn + r] : 0.0; },
+      [&](int k, int c) { return (k < nn && c < nn) ? T1[k * nn + c] : 0.0; },
+      [&](int r, int c, double v) { if (r < nn && c < nn) C[r * ldc + c] = v; });
+  (void)nlim;
+  __syncthreads();
+  // symmetrise: C <- (C + C^T) / 2
   for (int idx = tid; idx < nn * nn; idx += kThreads) {
     const int i = idx / nn, j = idx % nn;
-    if (j < i) continue;
-    double s = 0.0;
-    for (int k = 0; k < n; ++k) s += T[k * nn + i] * T1[k * nn + j];
-    C[i * ldc + j] = s;
-    C[j * ldc + i] = s;
+    if (j > i) {
+      const double v = 0.5 * (C[i * ldc + j] + C[j * ldc + i]);
+      C[i * ldc + j] = v;
+      C[j * ldc + i] = v;
+    }
   }
-  for (int idx = tid; idx < nn * nn; idx += kThreads) V[idx] = (idx / nn == idx % nn) ? 1.0 : 0.0;
   __syncthreads();
 
-  const int sweeps = jacobi(C, ldc, V, nn, sh);
+  const int sweeps = jacobi(C, ldc, rlog, nn, sh);
   if (tid == 0) flag[1] = sweeps;
 
   // ---- sort ascending, dropped directions (NaN) last ----
   if (tid < nn) sh.diag[tid] = C[tid * ldc + tid];
   __syncthreads();
+  double *VL = C;  // eigenvectors of C, rebuilt in LDS from the rotation log
+  replay_rotations(VL, ldc, rlog, sweeps * (nn - 1), nn);
   if (tid < n) {
     const int i = tid;
     int rk = 0;
@@ -266,16 +377,18 @@ __global__ __launch_bounds__(kThreads) void reduced_eig_kernel(const double *AQ,
   }
   __syncthreads();
   // Phi[:, rank[i]] = T V[:, i]
-  for (int idx = tid; idx < n * n; idx += kThreads) {
-    const int r = idx / n, i = idx % n;
-    double s = 0.0;
-    for (int k = 0; k < n; ++k) s += T[r * nn + k] * V[k * nn + i];
-    Phi[r * n + sh.rank[i]] = s;
-  }
+  wg_gemm(
+      nt, [&](int r, int k) { return (r < nn && k < nn) ? T[r * nn + k] : 0.0; },
+      [&](int k, int c) { return (k < nn && c < nn) ? VL[k * ldc + c] : 0.0; },
+      [&](int r, int c, double v) { if (r < n && c < n) Phi[r * n + sh.rank[c]] = v; });
   if (tid == 0) flag[0] = fallback ? 1 : 0;
 }
 
 }  // namespace
+
+size_t reduced_eig_scratch_doubles() {
+  return 3 * (size_t)kMaxN * kMaxN + (size_t)kMaxSweeps * (kMaxN - 1) * kMaxN;
+}
 
 hipError_t launch_reduced_eig(const double *AQ, const double *BQ, int n, double *eps, double *Phi,
                               double *scratch, int *flag, hipStream_t st) {

@@ -27,8 +27,46 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
 
 __device__ __forceinline__ d4 d4zero() { return d4{0.0, 0.0, 0.0, 0.0}; }
 
+// Raw buffer access.  Word 3 of an unformatted, unswizzled buffer resource
+// on gfx9-class parts; an access whose offset lies at or beyond the
+// resource's byte count touches no memory (loads return zero, stores are
+// dropped).  A resource of 0 bytes therefore turns an access into a no-op
+// without a branch, which keeps the number of memory operations in flight
+// the same on every path (so waits on earlier loads stay exact).
+constexpr int kBufferWord3 = 0x00020000;
+constexpr int kBufferOff = 0x40000000;  // an offset beyond every resource here
+typedef unsigned int u32x2 __attribute__((__vector_size__(8)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *base, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, bytes,
+                                          kBufferWord3);
+}
+
+__device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t rs, int voff, int soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
+}
+
+__device__ __forceinline__ void buf_store(double v, __amdgpu_buffer_rsrc_t rs, int voff,
+                                          int soff) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), rs, voff, soff, 0);
+}
+
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
-__device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
+// Stored layout of the blocks of the shifted factorisation (Sinv, W, W^T):
+// position of element (i, j) of one BP x BP plane.  The sweeps use a stored
+// block M as the matrix operand A'[r][k] = M[k][r] with k = 4 ks + kl (ks the
+// k-step of V_MFMA_F64_16X16X4_F64, kl = lane / 16); here the k-steps 2p and
+// 2p+1 of one (kl, r) sit next to each other, so one 16-byte load per lane
+// fetches both and the 64 lanes of a wave read 1 KB contiguously.
+template <int BP>
+__host__ __device__ constexpr int fpos(int i, int j) {
+  return ((((i >> 3) << 2) + (i & 3)) * BP + j) * 2 + ((i >> 2) & 1);
+}
+
+// wave index, known to the compiler as uniform across the wave
+__device__ __forceinline__ int wave_id() {
+  return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+}
 
 // Accumulator element r of lane l sits at (row, col) of its 16x16 tile.
 __device__ __forceinline__ int acc_row(int l, int r) { return (l >> 4) + 4 * r; }

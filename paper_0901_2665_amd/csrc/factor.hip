@@ -119,25 +119,35 @@ __device__ __forceinline__ void diag_regs_load(DiagRegs<BP> &g, const double *Ab
     }
 }
 
+// Position of element (r, c) in a global block plane: row-major, or the
+// factor layout fpos of the factorisation's own blocks (FL).
+template <int BP, bool FL>
+__device__ __forceinline__ int gpos(int r, int c) {
+  if constexpr (FL) return fpos<BP>(r, c);
+  else return r * BP + c;
+}
+
 // slot <- complex block from global planes [2][BP][BP].
-template <int BP>
+template <int BP, bool FL>
 __device__ void load_block(double *slot, const double *g) {
   constexpr int LD = Lds<BP>::LD, PLANE = Lds<BP>::PLANE;
   for (int idx = threadIdx.x; idx < BP * BP; idx += kThreads) {
     int r = idx / BP, c = idx % BP;
-    slot[r * LD + c] = g[idx];
-    slot[PLANE + r * LD + c] = g[BP * BP + idx];
+    const int gi = gpos<BP, FL>(r, c);
+    slot[r * LD + c] = g[gi];
+    slot[PLANE + r * LD + c] = g[BP * BP + gi];
   }
 }
 
-template <int BP>
+template <int BP, bool FL>
 __device__ void store_block(double *g, const double *slot, bool transpose) {
   constexpr int LD = Lds<BP>::LD, PLANE = Lds<BP>::PLANE;
   for (int idx = threadIdx.x; idx < BP * BP; idx += kThreads) {
     int r = idx / BP, c = idx % BP;
     int s = transpose ? c * LD + r : r * LD + c;
-    g[idx] = slot[s];
-    g[BP * BP + idx] = slot[PLANE + s];
+    const int gi = gpos<BP, FL>(r, c);
+    g[gi] = slot[s];
+    g[BP * BP + gi] = slot[PLANE + s];
   }
 }
 
@@ -324,9 +334,9 @@ __device__ __forceinline__ void gj_invert(Lds<BP> &s, double *gout, bool symm = 
         const int r = 4 * pi + u, c = 4 * pj + v;
         A[r * LD + c] = ar[u][v];
         A[PLANE + r * LD + c] = ai[u][v];
-        if (gout) {
-          gout[r * BP + c] = ar[u][v];
-          gout[BP * BP + r * BP + c] = ai[u][v];
+        if (gout) {  // a block of Sinv: factor layout
+          gout[fpos<BP>(r, c)] = ar[u][v];
+          gout[BP * BP + fpos<BP>(r, c)] = ai[u][v];
         }
       }
   }
@@ -378,7 +388,7 @@ __device__ void acc_to_lds(double *slot, const d4 (&accr)[BP / 16], const d4 (&a
     }
 }
 
-template <int BP>
+template <int BP, bool FL>
 __device__ void acc_to_global(double *g, const d4 (&accr)[BP / 16], const d4 (&acci)[BP / 16]) {
   constexpr int NT = BP / 16;
   const int w = wave_id(), l = lane_id();
@@ -388,8 +398,9 @@ __device__ void acc_to_global(double *g, const d4 (&accr)[BP / 16], const d4 (&a
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = w * 16 + acc_row(l, r), col = tj * 16 + acc_col(l);
-      g[row * BP + col] = accr[tj][r];
-      g[BP * BP + row * BP + col] = acci[tj][r];
+      const int gi = gpos<BP, FL>(row, col);
+      g[gi] = accr[tj][r];
+      g[BP * BP + gi] = acci[tj][r];
     }
 }
 
@@ -437,7 +448,7 @@ __device__ __forceinline__ void acc_from_diag_regs(d4 (&accr)[BP / 16], d4 (&acc
     }
 }
 
-template <int BP>
+template <int BP, bool FL>
 __device__ void acc_from_global(d4 (&accr)[BP / 16], d4 (&acci)[BP / 16], const double *g) {
   constexpr int NT = BP / 16;
   const int w = wave_id(), l = lane_id();
@@ -447,8 +458,9 @@ __device__ void acc_from_global(d4 (&accr)[BP / 16], d4 (&acci)[BP / 16], const 
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = w * 16 + acc_row(l, r), col = tj * 16 + acc_col(l);
-      accr[tj][r] = g[row * BP + col];
-      acci[tj][r] = g[BP * BP + row * BP + col];
+      const int gi = gpos<BP, FL>(row, col);
+      accr[tj][r] = g[gi];
+      acci[tj][r] = g[BP * BP + gi];
     }
 }
 
@@ -491,7 +503,7 @@ __global__ __launch_bounds__(kThreads) void factor_chain_kernel(Pencil p, Shifts
     const bool last = (j == len - 1);
     if (last && ch.end == 1) {
       // raw Schur complement at the twist cell, finished by twist_kernel
-      store_block<BP>(f.TW + (size_t)e * blk, s.A, false);
+      store_block<BP, false>(f.TW + (size_t)e * blk, s.A, false);
       break;
     }
     if (last && ch.end == 0) {
@@ -513,9 +525,9 @@ __global__ __launch_bounds__(kThreads) void factor_chain_kernel(Pencil p, Shifts
     cgemm_lds<BP>(wr, wi, s.A, true, s.B, 1.0);  // W = Sinv * Cpl
     __syncthreads();
     acc_to_lds<BP>(s.A, wr, wi);
-    acc_to_global<BP>(Wg + c * blk, wr, wi);
+    acc_to_global<BP, true>(Wg + c * blk, wr, wi);
     __syncthreads();
-    store_block<BP>(WTg + c * blk, s.A, true);
+    store_block<BP, true>(WTg + c * blk, s.A, true);
     if (!last) {
       d4 sr[NT], si[NT];
       acc_from_diag_regs<BP>(sr, si, dn, b, zr, zi);
@@ -559,11 +571,11 @@ __global__ __launch_bounds__(kThreads) void interface_kernel(Pencil p, Shifts sh
     const int last = ch.start + ch.dir * (ch.len - 1);
     const size_t gi = ((size_t)grp * parts + q) * blk;
     if (q == 0) {
-      load_block<BP>(s.A, Sinv + last * blk);  // K = 0: Sinv_last = G_LL
+      load_block<BP, true>(s.A, Sinv + last * blk);  // K = 0: Sinv_last = G_LL
       __syncthreads();
     } else {
       // slot B holds K.  N = (I - G_11 K)^{-1}
-      load_block<BP>(s.A, G11 + gi);
+      load_block<BP, false>(s.A, G11 + gi);
       __syncthreads();
       if (w < NT) {
 #pragma unroll
@@ -585,7 +597,7 @@ __global__ __launch_bounds__(kThreads) void interface_kernel(Pencil p, Shifts sh
       cgemm_lds<BP>(ar, ai, s.B, false, s.A, 1.0);
       __syncthreads();
       acc_to_lds<BP>(s.B, ar, ai);
-      load_block<BP>(s.A, GL1 + gi);
+      load_block<BP, false>(s.A, GL1 + gi);
       __syncthreads();
       // M4 = G_L1 M3
 #pragma unroll
@@ -595,7 +607,7 @@ __global__ __launch_bounds__(kThreads) void interface_kernel(Pencil p, Shifts sh
       acc_to_lds<BP>(s.B, ar, ai);
       __syncthreads();
       // Sinv_last = G_LL + M4 G_L1^T
-      acc_from_global<BP>(ar, ai, Sinv + last * blk);
+      acc_from_global<BP, true>(ar, ai, Sinv + last * blk);
       cgemm_lds<BP>(ar, ai, s.B, false, s.A, 1.0, true);
       __syncthreads();
       acc_to_lds<BP>(s.A, ar, ai);
@@ -618,7 +630,7 @@ __global__ __launch_bounds__(kThreads) void interface_kernel(Pencil p, Shifts sh
     for (int t = 0; t < NT; ++t) { ar[t] = d4zero(); ai[t] = d4zero(); }
     cgemm_lds<BP>(ar, ai, s.B, true, s.A, 1.0);
     __syncthreads();
-    acc_to_global<BP>(Kbuf + ((size_t)grp * parts + q + 1) * blk, ar, ai);
+    acc_to_global<BP, false>(Kbuf + ((size_t)grp * parts + q + 1) * blk, ar, ai);
     acc_to_lds<BP>(s.B, ar, ai);  // K for the next partition
     __syncthreads();
   }
@@ -638,14 +650,14 @@ __global__ __launch_bounds__(kThreads) void twist_kernel(Pencil p, Shifts sh, Fa
   const size_t bb = (size_t)b * b;
   const double *TW = f.TW + (size_t)e * blk;
   if (nc - m == 0) {
-    load_block<BP>(s.A, TW);
+    load_block<BP, false>(s.A, TW);
     __syncthreads();
   } else {
-    load_block<BP>(s.A, f.W + ((size_t)e * nc + m) * blk);
+    load_block<BP, true>(s.A, f.W + ((size_t)e * nc + m) * blk);
     form_block<BP>(s.B, p.Au + (m - 1) * bb, p.Bu + (m - 1) * bb, b, zr, zi, false, false);
     __syncthreads();
     d4 sr[NT], si[NT];
-    acc_from_global<BP>(sr, si, TW);
+    acc_from_global<BP, false>(sr, si, TW);
     cgemm_lds<BP>(sr, si, s.B, false, s.A, -1.0);
     __syncthreads();
     acc_to_lds<BP>(s.A, sr, si);

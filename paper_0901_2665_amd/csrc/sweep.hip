@@ -29,89 +29,116 @@ struct VecLds {
 };
 
 // Matrix-operand fragments of one stored block for this lane: the product
-// uses the transpose of the stored block, A'[row][k] = M_plane[k][row], so
-// each load instruction reads 16 consecutive doubles of four rows.  Loading
-// the next cell's fragments one step ahead hides the L2/HBM latency behind
-// the current step's matrix-core work.
+// uses the transpose of the stored block, A'[row][k] = M_plane[k][row].  In
+// the factor layout (fpos) the k-steps 2p and 2p+1 of this lane are adjacent,
+// so each 16-byte load fetches two of them and a wave reads 1 KB
+// contiguously.  rb is the 16-row block of the output that the calling wave
+// computes.  Fragments of the next cell are loaded one step ahead, so that
+// the L2/HBM latency hides behind the current step's matrix-core work.
 template <int BP>
 struct Frag {
   double v[BP / 2];  // [plane][k-step]: BP/4 k-steps per plane
 };
 
+// The loads go through a buffer resource spanning exactly the one block (or
+// nothing, valid = false), so that the per-pair displacement sits in a
+// scalar offset and every load of the lane shares one address register.
 template <int BP>
-__device__ __forceinline__ void frag_load(Frag<BP> &f, const double *__restrict__ M) {
-  const int l = lane_id(), w = wave_id();
-  const int row = w * 16 + (l & 15), kl = l >> 4;
+__device__ __forceinline__ void frag_load(Frag<BP> &f, const double *M, int rb, bool valid) {
+  const int l = lane_id();
+  const int row = rb * 16 + (l & 15), kl = l >> 4;
+  const auto rs = buf_rsrc(M, valid ? 2 * BP * BP * 8 : 0);
+  const int vo = fpos<BP>(kl, row) * 8;  // pair p = 0; fpos(8p + kl, row) adds 8 p BP
 #pragma unroll
-  for (int ks = 0; ks < BP / 4; ++ks) {
-    f.v[ks] = M[(4 * ks + kl) * BP + row];
-    f.v[BP / 4 + ks] = M[BP * BP + (4 * ks + kl) * BP + row];
+  for (int p = 0; p < BP / 8; ++p) {
+    const auto v0 = __builtin_amdgcn_raw_buffer_load_b128(rs, vo, p * 8 * BP * 8, 0);
+    const auto v1 =
+        __builtin_amdgcn_raw_buffer_load_b128(rs, vo, (BP * BP + p * 8 * BP) * 8, 0);
+    f.v[2 * p] = __builtin_bit_cast(double, (u32x2){v0[0], v0[1]});
+    f.v[2 * p + 1] = __builtin_bit_cast(double, (u32x2){v0[2], v0[3]});
+    f.v[BP / 4 + 2 * p] = __builtin_bit_cast(double, (u32x2){v1[0], v1[1]});
+    f.v[BP / 4 + 2 * p + 1] = __builtin_bit_cast(double, (u32x2){v1[2], v1[3]});
   }
 }
 
-// acc0/acc1 (+)= sign * A' * B', B' = stacked complex vector [[hr|hi];[-hi|hr]]
-// from LDS buffer hv; even and odd k-steps go to separate accumulators.
+// Vector operand B' = [[hr | hi]; [-hi | hr]] of this lane, read from the LDS
+// vector tile hv in one batch (b[ks] for k < BP, b[BP/4 + ks] for k >= BP).
 template <int BP>
-__device__ __forceinline__ void frag_mfma(d4 &acc0, d4 &acc1, const Frag<BP> &f,
-                                          const double (*hv)[BP][kTile], double sign) {
+__device__ __forceinline__ void bvec_load(double (&b)[BP / 2], const double (*hv)[BP][kTile]) {
   const int l = lane_id();
-  const int kl = l >> 4;
-  const int n = l & 15;
-  const int col = n & 7;
+  const int kl = l >> 4, n = l & 15, col = n & 7;
   const double *h0 = (n < 8) ? &hv[0][0][0] : &hv[1][0][0];  // k < BP
   const double *h1 = (n < 8) ? &hv[1][0][0] : &hv[0][0][0];  // k >= BP
   const double s1 = (n < 8) ? -1.0 : 1.0;
 #pragma unroll
-  for (int ks = 0; ks < BP / 4; ks += 2) {
-    const double b0 = h0[(4 * ks + kl) * kTile + col];
-    const double b1 = h0[(4 * ks + 4 + kl) * kTile + col];
-    acc0 = mfma(sign * f.v[ks], b0, acc0);
-    acc1 = mfma(sign * f.v[ks + 1], b1, acc1);
-  }
-#pragma unroll
-  for (int ks = 0; ks < BP / 4; ks += 2) {
-    const double b0 = s1 * h1[(4 * ks + kl) * kTile + col];
-    const double b1 = s1 * h1[(4 * ks + 4 + kl) * kTile + col];
-    acc0 = mfma(sign * f.v[BP / 4 + ks], b0, acc0);
-    acc1 = mfma(sign * f.v[BP / 4 + ks + 1], b1, acc1);
+  for (int ks = 0; ks < BP / 4; ++ks) {
+    b[ks] = h0[(4 * ks + kl) * kTile + col];
+    b[BP / 4 + ks] = s1 * h1[(4 * ks + kl) * kTile + col];
   }
 }
 
-// Accumulator tile <-> vector tile [2][BP][8] (global or LDS).
+// acc0/acc1 += A' * B'; even and odd k-steps go to separate accumulators.
 template <int BP>
-__device__ __forceinline__ void acc_store_vec(double *dst, const d4 &acc) {
-  const int l = lane_id(), w = wave_id();
-  const int n = l & 15, plane = n >> 3, col = n & 7;
+__device__ __forceinline__ void frag_mfma(d4 &acc0, d4 &acc1, const Frag<BP> &f,
+                                          const double (&b)[BP / 2]) {
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int row = w * 16 + acc_row(l, r);
-    dst[(plane * BP + row) * kTile + col] = acc[r];
+  for (int ks = 0; ks < BP / 2; ks += 2) {
+    acc0 = mfma(f.v[ks], b[ks], acc0);
+    acc1 = mfma(f.v[ks + 1], b[ks + 1], acc1);
   }
 }
 
+// Accumulator tile <-> vector tile [2][BP][8]: plain accesses (LDS or
+// global) and buffer accesses that become no-ops when valid is false.
 template <int BP>
-__device__ __forceinline__ d4 acc_load_vec(const double *src) {
-  const int l = lane_id(), w = wave_id();
+__device__ __forceinline__ int vec_off(int rb, int r) {
+  const int l = lane_id();
   const int n = l & 15, plane = n >> 3, col = n & 7;
+  return (plane * BP + rb * 16 + acc_row(l, r)) * kTile + col;
+}
+
+template <int BP>
+__device__ __forceinline__ void acc_store_vec(double *dst, const d4 &acc, int rb) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) dst[vec_off<BP>(rb, r)] = acc[r];
+}
+
+template <int BP>
+__device__ __forceinline__ d4 acc_load_vec(const double *src, int rb) {
   d4 a;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int row = w * 16 + acc_row(l, r);
-    a[r] = src[(plane * BP + row) * kTile + col];
-  }
+  for (int r = 0; r < 4; ++r) a[r] = src[vec_off<BP>(rb, r)];
   return a;
 }
 
-// Accumulator <- real right-hand side tile (imaginary part 0).
 template <int BP>
-__device__ __forceinline__ d4 acc_load_rhs(const double *R, int m0p) {
-  const int l = lane_id(), w = wave_id();
+__device__ __forceinline__ void vec_store_buf(double *dst, const d4 &acc, int rb, bool valid) {
+  const auto rs = buf_rsrc(dst, valid ? 2 * BP * kTile * 8 : 0);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) buf_store(acc[r], rs, vec_off<BP>(rb, r) * 8, 0);
+}
+
+template <int BP>
+__device__ __forceinline__ d4 vec_load_buf(const double *src, int rb, bool valid) {
+  const auto rs = buf_rsrc(src, valid ? 2 * BP * kTile * 8 : 0);
+  d4 a;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) a[r] = buf_load(rs, vec_off<BP>(rb, r) * 8, 0);
+  return a;
+}
+
+// Accumulator <- real right-hand side tile of one cell (rows of length m0p,
+// 8 columns from R; imaginary part 0).
+template <int BP>
+__device__ __forceinline__ d4 rhs_load(const double *R, int m0p, int rb, bool valid) {
+  const int l = lane_id();
   const int n = l & 15;
+  const auto rs = buf_rsrc(R, valid ? BP * m0p * 8 : 0);
   d4 a;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const int row = w * 16 + acc_row(l, r);
-    a[r] = (n < 8) ? R[(size_t)row * m0p + n] : 0.0;
+    const int row = rb * 16 + acc_row(l, r);
+    a[r] = buf_load(rs, n < 8 ? (row * m0p + n) * 8 : kBufferOff, 0);
   }
   return a;
 }
@@ -127,9 +154,18 @@ struct SweepArgs {
   double kre[kMaxNe], kim[kMaxNe];
 };
 
+// Forward sweep.  The workgroup has two wave sets of BP/16 waves each: the
+// first computes the critical-path product h_{j+1} = R_{j+1} - W_j^T h_j,
+// the second g_j = Sinv_j h_j, so that every SIMD holds two waves and one
+// hides the other's latencies.  LDS keeps u_j = -h_j (the sign then folds
+// into the accumulator initialisation instead of every matrix operand).
+// Every step issues the same memory operations on every wave (inactive ones
+// through empty buffer resources), so the waits for the operands loaded a
+// step ahead never cover the loads just issued.
 template <int BP>
-__global__ __launch_bounds__(BP * 4) void forward_kernel(SweepArgs a) {
+__global__ __launch_bounds__(BP * 8) void forward_kernel(SweepArgs a) {
   __shared__ VecLds<BP> s;
+  constexpr int NW = BP / 16;
   const int item = xcd_item(blockIdx.x, gridDim.x, a.ntiles);
   const int tau = item % a.ntiles;
   const int grp = item / a.ntiles;
@@ -142,8 +178,10 @@ __global__ __launch_bounds__(BP * 4) void forward_kernel(SweepArgs a) {
   const int start = top ? 0 : nc - 1;
   const size_t blk = 2 * (size_t)BP * BP;
   const size_t vt = 2 * (size_t)BP * kTile;
-  const double *Sinv = a.f.Sinv + (size_t)e * nc * blk;
-  const double *W = a.f.W + (size_t)e * nc * blk;
+  const int wv = wave_id();
+  const bool wrole = wv < NW;  // wave-uniform
+  const int rb = wrole ? wv : wv - NW;
+  const double *M = (wrole ? a.f.W : a.f.Sinv) + (size_t)e * nc * blk;
   double *G = a.sb.G + ((size_t)e * a.ntiles + tau) * nc * vt;
   double *TV = a.sb.TV + ((size_t)e * a.ntiles + tau) * 2 * vt;
   const double *R = a.R + tau * kTile;
@@ -151,48 +189,51 @@ __global__ __launch_bounds__(BP * 4) void forward_kernel(SweepArgs a) {
   // the top chain's last cell is the twist cell: no product there
   const int nsteps = top ? len - 1 : len;
 
-  {
-    d4 h = acc_load_rhs<BP>(R + start * rstride, a.m0p);
-    acc_store_vec<BP>(&s.v[0][0][0][0], h);
+  if (wrole) {
+    const d4 h = rhs_load<BP>(R + start * rstride, a.m0p, rb, true);
+    acc_store_vec<BP>(&s.v[0][0][0][0], -h, rb);
   }
-  Frag<BP> fs0, fw0, fs1, fw1;
-  if (nsteps > 0) {
-    frag_load<BP>(fs0, Sinv + start * blk);
-    frag_load<BP>(fw0, W + start * blk);
-  }
+  Frag<BP> f0, f1;
+  frag_load<BP>(f0, M + start * blk, rb, nsteps > 0);
+  d4 r0 = rhs_load<BP>(R + (start + dir) * rstride, a.m0p, rb, wrole && len > 1);
+  d4 r1 = d4zero();
   __syncthreads();
   int cur = 0;
-  // one chain step on cell c with fragments (fs, fw); prefetch cell c+dir
-  auto step = [&](int j, const Frag<BP> &fs, const Frag<BP> &fw, Frag<BP> &ns, Frag<BP> &nw) {
+  // one step on cell c with operands (f, r); loads cell c+dir's fragments and
+  // the right-hand side tile of cell c+2dir for the next step
+  auto step = [&](int j, const Frag<BP> &f, const d4 &r, Frag<BP> &nf, d4 &nr) {
     const int c = start + dir * j;
-    if (j + 1 < nsteps) {
-      frag_load<BP>(ns, Sinv + (c + dir) * blk);
-      frag_load<BP>(nw, W + (c + dir) * blk);
+    frag_load<BP>(nf, M + (c + dir) * blk, rb, j + 1 < nsteps);
+    nr = rhs_load<BP>(R + (c + 2 * dir) * rstride, a.m0p, rb, wrole && j + 2 < len);
+    double b[BP / 2];
+    bvec_load<BP>(b, s.v[cur]);
+    const bool more = j < len - 1;
+    d4 acc0 = (wrole && more) ? r : d4zero(), acc1 = d4zero();
+    // W role: R_{j+1} + W_j^T u_j = h_{j+1};  Sinv role: Sinv_j u_j = -g_j
+    frag_mfma<BP>(acc0, acc1, f, b);
+    const d4 acc = acc0 + acc1;
+    vec_store_buf<BP>(G + c * vt, -acc, rb, !wrole);
+    if (wrole) {
+      if (more)
+        acc_store_vec<BP>(&s.v[cur ^ 1][0][0][0], -acc, rb);
+      else
+        acc_store_vec<BP>(TV + vt, acc, rb);  // c = -W~_m^T h~_m
     }
-    const bool more = (j < len - 1);
-    d4 h0 = more ? acc_load_rhs<BP>(R + (c + dir) * rstride, a.m0p) : d4zero();
-    d4 h1 = d4zero(), g0 = d4zero(), g1 = d4zero();
-    const auto hv = s.v[cur];
-    frag_mfma<BP>(h0, h1, fw, hv, -1.0);  // h_{j+1} = R - W^T h_j (critical path)
-    frag_mfma<BP>(g0, g1, fs, hv, 1.0);   // g_j = Sinv_j h_j
-    if (more)
-      acc_store_vec<BP>(&s.v[cur ^ 1][0][0][0], h0 + h1);
-    else
-      acc_store_vec<BP>(TV + vt, h0 + h1);  // c = -W~_m^T h~_m
-    acc_store_vec<BP>(G + c * vt, g0 + g1);
     __syncthreads();
     cur ^= 1;
   };
   for (int j = 0; j < nsteps; j += 2) {
-    step(j, fs0, fw0, fs1, fw1);
-    if (j + 1 < nsteps) step(j + 1, fs1, fw1, fs0, fw0);
+    step(j, f0, r0, f1, r1);
+    if (j + 1 < nsteps) step(j + 1, f1, r1, f0, r0);
   }
-  if (top) {
-    d4 h = acc_load_vec<BP>(&s.v[cur][0][0][0]);
-    acc_store_vec<BP>(TV, h);  // h_{m-1}
+  if (top && wrole) {
+    const d4 u = acc_load_vec<BP>(&s.v[cur][0][0][0], rb);
+    acc_store_vec<BP>(TV, -u, rb);  // h_{m-1}
   }
 }
 
+// Back sweep, one wave per 16-row block.  LDS keeps v = -x of the previous
+// cell, so that x_c = g_c + W_c v accumulates onto g_c.
 template <int BP, bool COMPLEX_OUT>
 __global__ __launch_bounds__(BP * 4) void back_kernel(SweepArgs a) {
   __shared__ VecLds<BP> s;
@@ -211,22 +252,28 @@ __global__ __launch_bounds__(BP * 4) void back_kernel(SweepArgs a) {
   const double *G = a.sb.G + ((size_t)e * a.ntiles + tau) * nc * vt;
   const double *TV = a.sb.TV + ((size_t)e * a.ntiles + tau) * 2 * vt;
   const size_t pstride = (size_t)BP * a.m0p;
-  double *P = COMPLEX_OUT ? a.P : a.P + (size_t)e * nc * pstride;
+  double *P = (COMPLEX_OUT ? a.P : a.P + (size_t)e * nc * pstride) + tau * kTile;
+  double *Xim = COMPLEX_OUT ? a.Xim + tau * kTile : nullptr;
   const double kr = a.kre[e], ki = a.kim[e];
-  const int l = lane_id(), w = wave_id();
+  const int l = lane_id();
+  const int rb = wave_id();
   const int n = l & 15;
+  const int pbytes = BP * a.m0p * 8;
 
+  // P_c = Re(kappa_e x_c) (or x_c itself for the complex variant)
   auto emit = [&](int c, const d4 &x) {
+    const auto rp = buf_rsrc(P + c * pstride, pbytes);
+    const auto ri = buf_rsrc(COMPLEX_OUT ? Xim + c * pstride : nullptr,
+                             COMPLEX_OUT ? pbytes : 0);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const double other = __shfl_xor(x[r], 8);
-      const int row = w * 16 + acc_row(l, r);
-      const size_t off = (size_t)c * pstride + (size_t)row * a.m0p + tau * kTile + (n & 7);
+      const int off = ((rb * 16 + acc_row(l, r)) * a.m0p + (n & 7)) * 8;
       if (COMPLEX_OUT) {
-        if (n < 8) a.P[off] = x[r];
-        else a.Xim[off] = x[r];
-      } else if (n < 8) {
-        P[off] = kr * x[r] - ki * other;
+        buf_store(x[r], rp, n < 8 ? off : kBufferOff, 0);
+        buf_store(x[r], ri, n < 8 ? kBufferOff : off, 0);
+      } else {
+        buf_store(kr * x[r] - ki * other, rp, n < 8 ? off : kBufferOff, 0);
       }
     }
   };
@@ -235,45 +282,46 @@ __global__ __launch_bounds__(BP * 4) void back_kernel(SweepArgs a) {
 
   // twist cell: x_{m-1} = T (h_{m-1} + c)
   Frag<BP> f0, f1;
-  frag_load<BP>(f0, Sinv + (m - 1) * blk);
+  frag_load<BP>(f0, Sinv + (m - 1) * blk, rb, true);
   {
-    d4 t = acc_load_vec<BP>(TV);
-    if (nc - m > 0) t += acc_load_vec<BP>(TV + vt);
-    acc_store_vec<BP>(&s.v[1][0][0][0], t);
+    d4 t = acc_load_vec<BP>(TV, rb);
+    if (nc - m > 0) t += acc_load_vec<BP>(TV + vt, rb);
+    acc_store_vec<BP>(&s.v[1][0][0][0], t, rb);
   }
+  frag_load<BP>(f1, WT + cell(0) * blk, rb, count > 0);
+  d4 ga = vec_load_buf<BP>(G + cell(0) * vt, rb, count > 0), gb = d4zero();
   __syncthreads();
   {
+    double b[BP / 2];
+    bvec_load<BP>(b, s.v[1]);
     d4 x0 = d4zero(), x1 = d4zero();
-    frag_mfma<BP>(x0, x1, f0, s.v[1], 1.0);
-    d4 x = x0 + x1;
-    acc_store_vec<BP>(&s.v[0][0][0][0], x);
+    frag_mfma<BP>(x0, x1, f0, b);
+    const d4 x = x0 + x1;
+    acc_store_vec<BP>(&s.v[0][0][0][0], -x, rb);
     if (top) emit(m - 1, x);
-  }
-  d4 gnext = d4zero();
-  if (count > 0) {
-    frag_load<BP>(f1, WT + cell(0) * blk);
-    gnext = acc_load_vec<BP>(G + cell(0) * vt);
   }
   __syncthreads();
   int cur = 0;
-  // x_c = g_c - W_c x_prev; prefetch the next cell's W^T fragments and g tile
-  auto step = [&](int j, const Frag<BP> &fw, Frag<BP> &nw) {
+  // x_c = g_c + W_c v with operands (f, g); loads the next cell's W^T
+  // fragments and g tile one step ahead
+  auto step = [&](int j, const Frag<BP> &f, const d4 &g, Frag<BP> &nf, d4 &ng) {
     const int c = cell(j);
-    d4 x0 = gnext, x1 = d4zero();
-    if (j + 1 < count) {
-      frag_load<BP>(nw, WT + cell(j + 1) * blk);
-      gnext = acc_load_vec<BP>(G + cell(j + 1) * vt);
-    }
-    frag_mfma<BP>(x0, x1, fw, s.v[cur], -1.0);
-    d4 x = x0 + x1;
-    acc_store_vec<BP>(&s.v[cur ^ 1][0][0][0], x);
+    const bool nx = j + 1 < count;
+    frag_load<BP>(nf, WT + cell(j + 1) * blk, rb, nx);
+    ng = vec_load_buf<BP>(G + cell(j + 1) * vt, rb, nx);
+    double b[BP / 2];
+    bvec_load<BP>(b, s.v[cur]);
+    d4 x0 = g, x1 = d4zero();
+    frag_mfma<BP>(x0, x1, f, b);
+    const d4 x = x0 + x1;
+    acc_store_vec<BP>(&s.v[cur ^ 1][0][0][0], -x, rb);
     emit(c, x);
     __syncthreads();
     cur ^= 1;
   };
   for (int j = 0; j < count; j += 2) {
-    step(j, f1, f0);
-    if (j + 1 < count) step(j + 1, f0, f1);
+    step(j, f1, ga, f0, gb);
+    if (j + 1 < count) step(j + 1, f0, gb, f1, ga);
   }
 }
 
@@ -321,6 +369,7 @@ __global__ __launch_bounds__(BP * 4) void spike_kernel(SpikeArgs a) {
   double *G = a.G + ((size_t)e * a.gtiles + tau) * nc * vt;
   const size_t out = ((size_t)(e * 2 + ch.half) * a.parts + ch.part) * blk;
   const int l = lane_id(), w = wave_id();
+  const int rb = w;
   {
     d4 h;
 #pragma unroll
@@ -328,7 +377,7 @@ __global__ __launch_bounds__(BP * 4) void spike_kernel(SpikeArgs a) {
       const int row = w * 16 + acc_row(l, r), n = l & 15;
       h[r] = (n < 8 && row == tau * kTile + n) ? 1.0 : 0.0;
     }
-    acc_store_vec<BP>(&s.v[0][0][0][0], h);
+    acc_store_vec<BP>(&s.v[0][0][0][0], h, rb);
   }
   __syncthreads();
   int cur = 0;
@@ -336,31 +385,36 @@ __global__ __launch_bounds__(BP * 4) void spike_kernel(SpikeArgs a) {
   d4 g = d4zero();
   for (int j = 0; j < len; ++j) {
     const int c = start + dir * j;
-    frag_load<BP>(fa, Sinv + c * blk);
+    frag_load<BP>(fa, Sinv + c * blk, rb, true);
+    frag_load<BP>(fb, W + c * blk, rb, j < len - 1);
+    double b[BP / 2];
+    bvec_load<BP>(b, s.v[cur]);
     d4 g0 = d4zero(), g1 = d4zero();
-    frag_mfma<BP>(g0, g1, fa, s.v[cur], 1.0);
+    frag_mfma<BP>(g0, g1, fa, b);
     g = g0 + g1;
-    acc_store_vec<BP>(G + c * vt, g);
+    acc_store_vec<BP>(G + c * vt, g, rb);
     if (j < len - 1) {
-      frag_load<BP>(fb, W + c * blk);
       d4 h0 = d4zero(), h1 = d4zero();
-      frag_mfma<BP>(h0, h1, fb, s.v[cur], -1.0);
-      acc_store_vec<BP>(&s.v[cur ^ 1][0][0][0], h0 + h1);
+      frag_mfma<BP>(h0, h1, fb, b);
+      acc_store_vec<BP>(&s.v[cur ^ 1][0][0][0], -(h0 + h1), rb);
     }
     __syncthreads();
     cur ^= 1;
   }
   acc_store_block_cols<BP>(a.GL1 + out, g, tau);
-  acc_store_vec<BP>(&s.v[0][0][0][0], g);
+  // back: LDS keeps v = -y of the previous cell, y_j = g_j + W_j v
+  acc_store_vec<BP>(&s.v[0][0][0][0], -g, rb);
   __syncthreads();
   cur = 0;
   for (int j = len - 2; j >= 0; --j) {
     const int c = start + dir * j;
-    frag_load<BP>(fa, WT + c * blk);
-    d4 x0 = acc_load_vec<BP>(G + c * vt), x1 = d4zero();
-    frag_mfma<BP>(x0, x1, fa, s.v[cur], -1.0);
+    frag_load<BP>(fa, WT + c * blk, rb, true);
+    d4 x0 = acc_load_vec<BP>(G + c * vt, rb), x1 = d4zero();
+    double b[BP / 2];
+    bvec_load<BP>(b, s.v[cur]);
+    frag_mfma<BP>(x0, x1, fa, b);
     g = x0 + x1;
-    acc_store_vec<BP>(&s.v[cur ^ 1][0][0][0], g);
+    acc_store_vec<BP>(&s.v[cur ^ 1][0][0][0], -g, rb);
     __syncthreads();
     cur ^= 1;
   }
@@ -372,7 +426,7 @@ template <int BP>
 hipError_t launch_sweeps_bp(SweepArgs &a, int Ne, bool complex_out, int part, hipStream_t st) {
   const int nblocks = Ne * 2 * a.ntiles;
   if (part & 1) {
-    hipLaunchKernelGGL(forward_kernel<BP>, dim3(nblocks), dim3(BP * 4), 0, st, a);
+    hipLaunchKernelGGL(forward_kernel<BP>, dim3(nblocks), dim3(BP * 8), 0, st, a);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
   }

@@ -26,6 +26,53 @@ PEAK_FP64 = 78.6        # TFLOP/s, MI355X dense FP64 (matrix = vector)
 PEAK_HBM = 8000.0       # GB/s
 
 
+def source_digest():
+    """Digest of the HIP/C++ sources: HBM traffic taken with counters applies
+    only to the kernels built from exactly these sources."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_0901_2665_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size), or None
+    when the summary is missing or the sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    digest, value = None, None
+    for line in open(path):
+        if line.startswith("source digest:"):
+            digest = line.split(":", 1)[1].strip()
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) >= 2 and cells[0] == kernel:
+            try:
+                value = float(cells[-1])
+            except ValueError:
+                pass
+    if digest != source_digest():
+        return None
+    return value
+
+
+def copy_probe():
+    """A plain device copy of 1 GiB (read 1 GiB, write 1 GiB): the reference
+    that scales the HBM byte counters."""
+    import torch
+    n = 1 << 27
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def nominal_flops(nc, b, m0, ne):
     """Nominal work of the sequential block-LU algorithm (complex = 4x real)."""
     return dict(
@@ -74,6 +121,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="tb128k")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one 1 GiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build measures the single-GPU FEAST "
@@ -85,6 +134,8 @@ def main():
     from paper_0901_2665_amd import feast as F
     from paper_0901_2665_amd import workloads as W
 
+    if args.copy_probe:
+        copy_probe()
     p, emin, emax, m0, ne, Y0 = W.make_workload(args.workload)
     wl = W.WORKLOADS[args.workload]
     gp = F.Pencil(p.Ad, p.Au, p.Bd, p.Bu)
@@ -159,7 +210,8 @@ def main():
         "gate": gate,
         "kernels": per,
         "roofline": {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": PEAK_FP64,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None},
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64,
+                     "traffic": measured_traffic(args.workload, dom)},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p, emin, emax, m0, ne, Y0, r.loops)

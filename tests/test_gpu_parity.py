@@ -264,6 +264,32 @@ def test_solve_tb6400_golden(ctx, torch):
     assert abs(r.loops - g["loops"]) <= 1
 
 
+def test_solve_tb128k_full_size(ctx, torch):
+    """The full-size workload (nc=2000, b=64, n=128000, M0=128, Ne=8) in the
+    launch configuration the benchmark times: eigenvalues against the stored
+    oracle result, residuals recomputed on the host for a sample of pairs,
+    and B-orthonormality of that sample."""
+    g = json.load(open(os.path.join(GOLDEN, "feast_tb128k.json")))
+    p, emin, emax, m0, ne, Y0 = W.make_workload("tb128k")
+    r = ctx.solve(gpencil(p), emin, emax, m0, ne, dev(torch, Y0))
+    assert r.status == 0 and r.M == g["M"] == 80
+    lam = host(r.lam)[:80]
+    ref = np.array(g["lam"])
+    assert np.max(np.abs(lam - ref) / np.abs(ref)) <= 1e-10
+    res = host(r.res)
+    assert np.max(res[:80]) <= 1e-9
+    assert abs(r.loops - g["loops"]) <= 1
+    cols = [0, 13, 27, 40, 53, 66, 79]
+    X = host(r.X)[:, cols]
+    AX = O.bt_multiply(p.Ad, p.Au, X)
+    BX = O.bt_multiply(p.Bd, p.Bu, X)
+    res_host = O.residuals(p, lam[cols], X, emin, emax)
+    assert np.max(res_host) <= 1e-9
+    assert np.allclose(res_host, res[cols], rtol=1e-3, atol=1e-14)
+    assert np.max(np.abs(X.T @ BX - np.eye(len(cols)))) <= 1e-9
+    assert np.max(np.abs(AX - BX * lam[cols]), initial=0) <= 1e-9 * np.max(np.abs(AX))
+
+
 def test_empty_interval(ctx, torch):
     p = W.dense_random_pencil(3, 8, 9)
     lam = O.bruteforce(p)[0]

@@ -23,9 +23,7 @@ constexpr int kThreads = 1024;
 constexpr int kMaxN = 128;
 
 struct RRShared {
-  unsigned char blk_a[kMaxN / 2 * (kMaxN / 2 + 1) / 2], blk_b[kMaxN / 2 * (kMaxN / 2 + 1) / 2];
-  int pp[kMaxN / 2], pq[kMaxN / 2];
-  double cs[kMaxN / 2], sn[kMaxN / 2];
+  double2 csn[kMaxN / 2];  // (cos, sin) of the rotation of each pair slot
   int rot;
   int fail;
   double norm;
@@ -74,71 +72,90 @@ __device__ int jacobi(double *C, int ldc, double *rlog, int nn, RRShared &sh) {
   }
   __syncthreads();
   const double floor_abs = 0.125 * eps * sqrt(sh.norm);
-  const int nblk = half * (half + 1) / 2;  // 2x2 blocks (a <= b)
-  if (tid < half) {  // table of the (a, b) blocks, row a holds half - a of them
-    int idx = tid * half - tid * (tid - 1) / 2;
-    for (int bq = tid; bq < half; ++bq, ++idx) {
-      sh.blk_a[idx] = (unsigned char)tid;
-      sh.blk_b[idx] = (unsigned char)bq;
+  // The sweeps keep only the upper triangle of C up to date (entry (i, j) is
+  // read and written at (min, max)).  The 2x2 blocks (a, b), a <= b, of the
+  // pair slots are dealt out to the threads once; a thread keeps its blocks
+  // (at most 3 for nn <= 128) in registers.
+  constexpr int kPer = (kMaxN / 2 * (kMaxN / 2 + 1) / 2 + kThreads - 1) / kThreads;
+  const int nblk = half * (half + 1) / 2;
+  int ba[kPer], bb[kPer];
+#pragma unroll
+  for (int t = 0; t < kPer; ++t) {
+    int idx = tid + t * kThreads;
+    ba[t] = -1;
+    bb[t] = -1;
+    if (idx < nblk) {  // row a of the block triangle holds half - a blocks
+      int a = 0;
+      while (idx >= half - a) {
+        idx -= half - a;
+        ++a;
+      }
+      ba[t] = a;
+      bb[t] = a + idx;
     }
   }
-  __syncthreads();
+  auto at = [&](int i, int j) -> double & {
+    return i < j ? C[i * ldc + j] : C[j * ldc + i];
+  };
   int sweep = 0;
   for (; sweep < kMaxSweeps; ++sweep) {
     if (tid == 0) sh.rot = 0;
     __syncthreads();
     for (int s = 0; s < nn - 1; ++s) {
-      if (tid < half) {
-        int u = rr_player(s, tid, nn), v = rr_player(s, nn - 1 - tid, nn);
-        int p = u < v ? u : v, q = u < v ? v : u;
-        double app = C[p * ldc + p], aqq = C[q * ldc + q], apq = C[p * ldc + q];
+      if (tid < half) {  // one wave: rotation of slot tid
+        const int u = rr_player(s, tid, nn), v = rr_player(s, nn - 1 - tid, nn);
+        const int p = u < v ? u : v, q = u < v ? v : u;
+        const double app = C[p * ldc + p], aqq = C[q * ldc + q], apq = C[p * ldc + q];
         double c = 1.0, sgn = 0.0;
-        if (fabs(apq) > floor_abs && fabs(apq) > eps * sqrt(fabs(app * aqq))) {
+        const bool rotate =
+            fabs(apq) > floor_abs && fabs(apq) > eps * sqrt(fabs(app * aqq));
+        if (rotate) {
           // t = tan of the rotation angle: the smaller root of t^2 + 2 tau t - 1
           const double tau = (aqq - app) * rcp_newton(2.0 * apq);
-          const double at = fabs(tau);
-          const double root = at < 1e150 ? sqrt(1.0 + tau * tau) : at;
-          const double t = (tau >= 0.0 ? 1.0 : -1.0) * rcp_newton(at + root);
+          const double ata = fabs(tau);
+          const double root = ata < 1e150 ? sqrt(1.0 + tau * tau) : ata;
+          const double t = (tau >= 0.0 ? 1.0 : -1.0) * rcp_newton(ata + root);
           c = rcp_newton(sqrt(1.0 + t * t));
           sgn = t * c;
-          atomicAdd(&sh.rot, 1);
         }
-        sh.pp[tid] = p;
-        sh.pq[tid] = q;
-        sh.cs[tid] = c;
-        sh.sn[tid] = sgn;
+        const unsigned long long m = __ballot(rotate);
+        if (tid == 0) sh.rot += __popcll(m);
+        sh.csn[tid] = double2{c, sgn};
         double *lg = rlog + (size_t)(sweep * (nn - 1) + s) * 2 * half;
         lg[tid] = c;
         lg[half + tid] = sgn;
       }
       __syncthreads();
-      // C <- J^T C J on 2x2 blocks (a <= b), mirrored to keep C symmetric
-      for (int idx = tid; idx < nblk; idx += kThreads) {
-        const int a = sh.blk_a[idx], bq = sh.blk_b[idx];
-        const int pa = sh.pp[a], qa = sh.pq[a], pb = sh.pp[bq], qb = sh.pq[bq];
-        const double ca = sh.cs[a], sa = sh.sn[a], cb = sh.cs[bq], sb = sh.sn[bq];
+      // C <- J^T C J on the thread's 2x2 blocks
+#pragma unroll
+      for (int t = 0; t < kPer; ++t) {
+        const int a = ba[t], bq = bb[t];
+        if (a < 0) continue;
+        const double2 ra = sh.csn[a], rb = sh.csn[bq];
+        const double ca = ra.x, sa = ra.y, cb = rb.x, sb = rb.y;
+        int pa = rr_player(s, a, nn), qa = rr_player(s, nn - 1 - a, nn);
+        if (pa > qa) { const int x = pa; pa = qa; qa = x; }
         if (a == bq) {
           if (sa != 0.0) {
             const double app = C[pa * ldc + pa], aqq = C[qa * ldc + qa], apq = C[pa * ldc + qa];
-            const double t = sa / ca;
-            C[pa * ldc + pa] = app - t * apq;
-            C[qa * ldc + qa] = aqq + t * apq;
+            const double tq = sa / ca;
+            C[pa * ldc + pa] = app - tq * apq;
+            C[qa * ldc + qa] = aqq + tq * apq;
             C[pa * ldc + qa] = 0.0;
-            C[qa * ldc + pa] = 0.0;
           }
           continue;
         }
         if (sa == 0.0 && sb == 0.0) continue;
-        const double x11 = C[pa * ldc + pb], x12 = C[pa * ldc + qb];
-        const double x21 = C[qa * ldc + pb], x22 = C[qa * ldc + qb];
+        int pb = rr_player(s, bq, nn), qb = rr_player(s, nn - 1 - bq, nn);
+        if (pb > qb) { const int x = pb; pb = qb; qb = x; }
+        double &e11 = at(pa, pb), &e12 = at(pa, qb), &e21 = at(qa, pb), &e22 = at(qa, qb);
+        const double x11 = e11, x12 = e12, x21 = e21, x22 = e22;
         const double y11 = cb * x11 - sb * x12, y12 = sb * x11 + cb * x12;
         const double y21 = cb * x21 - sb * x22, y22 = sb * x21 + cb * x22;
-        const double z11 = ca * y11 - sa * y21, z21 = sa * y11 + ca * y21;
-        const double z12 = ca * y12 - sa * y22, z22 = sa * y12 + ca * y22;
-        C[pa * ldc + pb] = z11; C[pb * ldc + pa] = z11;
-        C[pa * ldc + qb] = z12; C[qb * ldc + pa] = z12;
-        C[qa * ldc + pb] = z21; C[pb * ldc + qa] = z21;
-        C[qa * ldc + qb] = z22; C[qb * ldc + qa] = z22;
+        e11 = ca * y11 - sa * y21;
+        e21 = sa * y11 + ca * y21;
+        e12 = ca * y12 - sa * y22;
+        e22 = sa * y12 + ca * y22;
       }
       __syncthreads();
     }

@@ -332,7 +332,11 @@ __global__ __launch_bounds__(BP * 4) void back_kernel(SweepArgs a) {
 //   h_0 = I,  h_{j+1} = -W_j^T h_j,  g_j = Sinv_j h_j,
 //   y_last = g_last,  y_j = g_j - W_j y_{j+1};
 // the kernel keeps y_first = [T^-1]_{first,first} and
-// y_last = [T^-1]_{last,first}.  One workgroup per (chain, tile of 8 columns).
+// y_last = [T^-1]_{last,first}.  One workgroup per chain computes all BP
+// columns, so every factor block it streams feeds BP/8 column tiles.  In the
+// forward part the first BP/16 waves form h_{j+1} (one 16-row block each) and
+// the other BP/16 waves g_j; in the back part every wave owns one row block
+// and half of the column tiles.
 struct SpikeArgs {
   Pencil p;
   Factors f;
@@ -341,23 +345,56 @@ struct SpikeArgs {
   double *G, *G11, *GL1;
 };
 
+// A complex BP x BP block in LDS: row k holds, per 8-column tile, the 8 real
+// parts then the 8 imaginary parts, and rows are 2 BP + 16 doubles apart, so
+// that the 64 lanes reading one k-step of the MFMA vector operand (four rows,
+// both planes, eight columns) fall on distinct banks.
 template <int BP>
-__device__ __forceinline__ void acc_store_block_cols(double *dst, const d4 &acc, int tau) {
-  const int l = lane_id(), w = wave_id();
+struct SpikeLds {
+  static constexpr int RS = 2 * BP + 16;
+  double h[2][BP * RS];  // [buffer]
+  __device__ static int at(int k, int col, int plane) {
+    return k * RS + (col >> 3) * 16 + plane * 8 + (col & 7);
+  }
+};
+
+// B' operand of column tile tau of the LDS block hv at k-step ks for this lane.
+template <int BP>
+__device__ __forceinline__ double spike_b(const double *hv, int tau, int ks) {
+  const int l = lane_id();
+  const int kl = l >> 4, n = l & 15, col = tau * kTile + (n & 7);
+  const int k = 4 * (ks % (BP / 4)) + kl;
+  if (ks < BP / 4) return hv[SpikeLds<BP>::at(k, col, n >> 3)];
+  const double v = hv[SpikeLds<BP>::at(k, col, 1 - (n >> 3))];
+  return n < 8 ? -v : v;
+}
+
+// Accumulator of output row block rb, column tile tau <-> LDS block.
+template <int BP>
+__device__ __forceinline__ void spike_store_lds(double *hv, const d4 &acc, int rb, int tau) {
+  const int l = lane_id();
+  const int n = l & 15, plane = n >> 3, col = tau * kTile + (n & 7);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) hv[SpikeLds<BP>::at(rb * 16 + acc_row(l, r), col, plane)] = acc[r];
+}
+
+template <int BP>
+__device__ __forceinline__ void acc_store_block_cols(double *dst, const d4 &acc, int rb, int tau) {
+  const int l = lane_id();
   const int n = l & 15, plane = n >> 3, col = n & 7;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const int row = w * 16 + acc_row(l, r);
+    const int row = rb * 16 + acc_row(l, r);
     dst[(size_t)plane * BP * BP + row * BP + tau * kTile + col] = acc[r];
   }
 }
 
 template <int BP>
-__global__ __launch_bounds__(BP * 4) void spike_kernel(SpikeArgs a) {
-  __shared__ VecLds<BP> s;
-  constexpr int NTILE = BP / kTile;
-  const int ci = blockIdx.x / NTILE, tau = blockIdx.x % NTILE;
-  const Chain ch = a.chains[ci];
+__global__ __launch_bounds__(BP * 8) void spike_kernel(SpikeArgs a) {
+  extern __shared__ double spike_smem[];
+  SpikeLds<BP> &s = *reinterpret_cast<SpikeLds<BP> *>(spike_smem);
+  constexpr int NW = BP / 16, NT = BP / kTile;
+  const Chain ch = a.chains[blockIdx.x];
   const int e = ch.e, start = ch.start, dir = ch.dir, len = ch.len;
   if (len <= 0) return;
   const int nc = a.p.nc;
@@ -366,59 +403,118 @@ __global__ __launch_bounds__(BP * 4) void spike_kernel(SpikeArgs a) {
   const double *Sinv = a.f.Sinv + (size_t)e * nc * blk;
   const double *W = a.f.W + (size_t)e * nc * blk;
   const double *WT = a.f.WT + (size_t)e * nc * blk;
-  double *G = a.G + ((size_t)e * a.gtiles + tau) * nc * vt;
+  // G tile tau of cell c: G + (tau * nc + c) * vt
+  double *G = a.G + (size_t)e * a.gtiles * nc * vt;
   const size_t out = ((size_t)(e * 2 + ch.half) * a.parts + ch.part) * blk;
-  const int l = lane_id(), w = wave_id();
-  const int rb = w;
-  {
-    d4 h;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = w * 16 + acc_row(l, r), n = l & 15;
-      h[r] = (n < 8 && row == tau * kTile + n) ? 1.0 : 0.0;
-    }
-    acc_store_vec<BP>(&s.v[0][0][0][0], h, rb);
+  const int tid = threadIdx.x, wv = wave_id();
+  const bool wrole = wv < NW;  // wave-uniform
+  const int rb = wrole ? wv : wv - NW;
+
+  // h_0 = E_1: the identity block
+  for (int idx = tid; idx < BP * BP; idx += BP * 8) {
+    const int r = idx / BP, c = idx % BP;
+    s.h[0][SpikeLds<BP>::at(r, c, 0)] = r == c ? 1.0 : 0.0;
+    s.h[0][SpikeLds<BP>::at(r, c, 1)] = 0.0;
   }
   __syncthreads();
+  // ---- forward: h_{j+1} = -W_j^T h_j (first wave set), g_j = Sinv_j h_j ----
+  // The column tiles are done in two halves (fewer live accumulators); the
+  // matrix fragments of the next cell are loaded a step ahead.
+  constexpr int NH = NT / 2;  // tiles per half (NT is even)
+  const double *M = wrole ? W : Sinv;
+  Frag<BP> f0, f1;
+  frag_load<BP>(f0, M + start * blk, rb, !(wrole && len == 1));
   int cur = 0;
-  Frag<BP> fa, fb;
-  d4 g = d4zero();
-  for (int j = 0; j < len; ++j) {
+  auto fstep = [&](int j, const Frag<BP> &f, Frag<BP> &nf) {
     const int c = start + dir * j;
-    frag_load<BP>(fa, Sinv + c * blk, rb, true);
-    frag_load<BP>(fb, W + c * blk, rb, j < len - 1);
-    double b[BP / 2];
-    bvec_load<BP>(b, s.v[cur]);
-    d4 g0 = d4zero(), g1 = d4zero();
-    frag_mfma<BP>(g0, g1, fa, b);
-    g = g0 + g1;
-    acc_store_vec<BP>(G + c * vt, g, rb);
-    if (j < len - 1) {
-      d4 h0 = d4zero(), h1 = d4zero();
-      frag_mfma<BP>(h0, h1, fb, b);
-      acc_store_vec<BP>(&s.v[cur ^ 1][0][0][0], -(h0 + h1), rb);
+    const bool last = j == len - 1;
+    frag_load<BP>(nf, M + (c + dir) * blk, rb, j + 1 < len && !(wrole && j + 1 == len - 1));
+    if (!(wrole && last)) {
+#pragma unroll
+      for (int hf = 0; hf < 2; ++hf) {
+        d4 acc[NH];
+#pragma unroll
+        for (int q = 0; q < NH; ++q) acc[q] = d4zero();
+#pragma unroll
+        for (int ks = 0; ks < BP / 2; ++ks) {
+#pragma unroll
+          for (int q = 0; q < NH; ++q)
+            acc[q] = mfma(f.v[ks], spike_b<BP>(s.h[cur], hf * NH + q, ks), acc[q]);
+          // keep the vector-operand reads of later k-steps from being
+          // hoisted all at once (register pressure)
+          if ((ks & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int q = 0; q < NH; ++q) {
+          const int t = hf * NH + q;
+          if (wrole) {
+            spike_store_lds<BP>(s.h[cur ^ 1], -acc[q], rb, t);
+          } else {
+            vec_store_buf<BP>(G + (t * nc + c) * vt, acc[q], rb, true);
+            if (last) acc_store_block_cols<BP>(a.GL1 + out, acc[q], rb, t);
+          }
+        }
+      }
     }
     __syncthreads();
     cur ^= 1;
+  };
+  for (int j = 0; j < len; j += 2) {
+    fstep(j, f0, f1);
+    if (j + 1 < len) fstep(j + 1, f1, f0);
   }
-  acc_store_block_cols<BP>(a.GL1 + out, g, tau);
-  // back: LDS keeps v = -y of the previous cell, y_j = g_j + W_j v
-  acc_store_vec<BP>(&s.v[0][0][0][0], -g, rb);
+  // ---- back: LDS keeps v = -y of the previous cell, y_j = g_j + W_j v ----
+  // Every wave owns one row block and NT/2 column tiles.  g_j is loaded at
+  // the start of the step and added at its end; the W^T fragments of the
+  // next cell are loaded a step ahead.
+  const int rb2 = wv % NW, t0 = (wv / NW) * NH;
+  {
+    // -y_last = -g_last into the LDS buffer the loop reads first
+    const int c = start + dir * (len - 1);
+#pragma unroll
+    for (int q = 0; q < NH; ++q) {
+      const d4 g = vec_load_buf<BP>(G + ((t0 + q) * nc + c) * vt, rb2, true);
+      spike_store_lds<BP>(s.h[0], -g, rb2, t0 + q);
+    }
+  }
+  frag_load<BP>(f0, WT + (start + dir * (len - 2)) * blk, rb2, len >= 2);
   __syncthreads();
   cur = 0;
-  for (int j = len - 2; j >= 0; --j) {
+  auto bstep = [&](int j, const Frag<BP> &f, Frag<BP> &nf) {
     const int c = start + dir * j;
-    frag_load<BP>(fa, WT + c * blk, rb, true);
-    d4 x0 = acc_load_vec<BP>(G + c * vt, rb), x1 = d4zero();
-    double b[BP / 2];
-    bvec_load<BP>(b, s.v[cur]);
-    frag_mfma<BP>(x0, x1, fa, b);
-    g = x0 + x1;
-    acc_store_vec<BP>(&s.v[cur ^ 1][0][0][0], -g, rb);
+    frag_load<BP>(nf, WT + (c - dir) * blk, rb2, j >= 1);
+    d4 g[NH], acc[NH];
+#pragma unroll
+    for (int q = 0; q < NH; ++q) {
+      g[q] = vec_load_buf<BP>(G + ((t0 + q) * nc + c) * vt, rb2, true);
+      acc[q] = d4zero();
+    }
+#pragma unroll
+    for (int ks = 0; ks < BP / 2; ++ks) {
+#pragma unroll
+      for (int q = 0; q < NH; ++q) acc[q] = mfma(f.v[ks], spike_b<BP>(s.h[cur], t0 + q, ks), acc[q]);
+      if ((ks & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int q = 0; q < NH; ++q) spike_store_lds<BP>(s.h[cur ^ 1], -(g[q] + acc[q]), rb2, t0 + q);
     __syncthreads();
     cur ^= 1;
+  };
+  for (int j = len - 2; j >= 0; j -= 2) {
+    bstep(j, f0, f1);
+    if (j - 1 >= 0) bstep(j - 1, f1, f0);
   }
-  acc_store_block_cols<BP>(a.G11 + out, g, tau);
+  // y_first: -v in the current buffer
+#pragma unroll
+  for (int q = 0; q < NH; ++q) {
+    const int t = t0 + q;
+    const int l = lane_id();
+    const int n = l & 15, plane = n >> 3, col = t * kTile + (n & 7);
+    d4 y;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) y[r] = -s.h[cur][SpikeLds<BP>::at(rb2 * 16 + acc_row(l, r), col, plane)];
+    acc_store_block_cols<BP>(a.G11 + out, y, rb2, t);
+  }
 }
 
 // part: 1 = forward sweep, 2 = back sweep, 3 = both
@@ -436,6 +532,16 @@ hipError_t launch_sweeps_bp(SweepArgs &a, int Ne, bool complex_out, int part, hi
     else
       hipLaunchKernelGGL((back_kernel<BP, false>), dim3(nblocks), dim3(BP * 4), 0, st, a);
   }
+  return hipGetLastError();
+}
+
+template <int BP>
+hipError_t launch_spike_bp(SpikeArgs &a, dim3 grid, hipStream_t st) {
+  const int shm = (int)sizeof(SpikeLds<BP>);
+  hipError_t err = hipFuncSetAttribute((const void *)spike_kernel<BP>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, shm);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(spike_kernel<BP>, grid, dim3(BP * 8), shm, st, a);
   return hipGetLastError();
 }
 
@@ -468,15 +574,14 @@ hipError_t launch_spikes(const Pencil &p, const Factors &f, const Chain *chains,
   SpikeArgs a;
   a.p = p; a.f = f; a.chains = chains; a.parts = parts; a.gtiles = gtiles;
   a.G = G; a.G11 = G11; a.GL1 = GL1;
-  const dim3 grid(nchains * (p.bp / kTile));
+  const dim3 grid(nchains);
   switch (p.bp) {
-    case 16: hipLaunchKernelGGL(spike_kernel<16>, grid, dim3(64), 0, st, a); break;
-    case 32: hipLaunchKernelGGL(spike_kernel<32>, grid, dim3(128), 0, st, a); break;
-    case 48: hipLaunchKernelGGL(spike_kernel<48>, grid, dim3(192), 0, st, a); break;
-    case 64: hipLaunchKernelGGL(spike_kernel<64>, grid, dim3(256), 0, st, a); break;
+    case 16: return launch_spike_bp<16>(a, grid, st);
+    case 32: return launch_spike_bp<32>(a, grid, st);
+    case 48: return launch_spike_bp<48>(a, grid, st);
+    case 64: return launch_spike_bp<64>(a, grid, st);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 hipError_t launch_sweeps_complex(const Pencil &p, const Shifts &s, const Factors &f,

@@ -185,7 +185,7 @@ int feast_reduced_eig(feast_ctx *ctx, int32_t M0, const double *AQ, const double
  * synchronises the stream and returns, for class k, its name (static
  * string), the summed event time in milliseconds and the number of launches;
  * with k < 0 it returns the number of classes.  Classes: factor,
- * forward_sweep, back_sweep, bt_multiply, sum_nodes, gram, reduced_eig,
+ * forward_sweep, back_sweep, bt_multiply, sum_nodes, projection, reduced_eig,
  * ritz_gemm, residual, layout.
  */
 int feast_timing(feast_ctx *ctx, int32_t enable);

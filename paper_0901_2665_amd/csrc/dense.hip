@@ -38,49 +38,329 @@ __global__ void unpack_kernel(const double *src, int nc, int b, int bp, int m, i
   }
 }
 
-// out[c] = D_c V_c + U_c V_{c+1} + U_{c-1}^T V_{c-1}; one wave per 16 rows
-// and 16 columns of a cell.
-template <int BP>
-__global__ __launch_bounds__(BP * 4) void bt_multiply_kernel(const double *D, const double *U,
-                                                             int nc, int b, const double *V,
-                                                             int ld, double *out) {
-  const int c = blockIdx.x, jt = blockIdx.y;
-  const int l = lane_id(), w = wave_id();
-  const int row = w * 16 + (l & 15);
-  const int kl = l >> 4;
-  const int col = jt * 16 + (l & 15);
+// ---------------------------------------------------------------------------
+// Per-cell products.  One workgroup of kCellThreads threads walks the cells
+// c = g, g + G, ... (G = gridDim.x) and forms (T V)_c = U_{c-1}^T V_{c-1} +
+// D_c V_c + U_c V_{c+1} for all ld columns as a small GEMM: each of the (up
+// to) three blocks is staged in LDS with the matching 64-row slab of V while
+// the global loads of the next block are in flight, and the 16 waves share
+// the 16x16 output tiles.  The consumers (plain product, projection, residual
+// norms) use the cell's result right away and accumulate per workgroup in a
+// fixed order.
+// ---------------------------------------------------------------------------
+constexpr int kCellThreads = 1024;
+constexpr int kCellWaves = kCellThreads / 64;
+constexpr int kCellGroups = 256;
+constexpr int kVld = 128 + 16;  // LDS row stride of V slabs: rows 4 apart fall on other banks
+
+// LDS of a cell workgroup: region r0 holds the A operands during the
+// stages and (T V)_c (row stride kVld) in the epilogue; V holds the slab of
+// the current stage, which is V_c in the last stage of every cell.
+template <int BP, int NOP>
+struct CellLds {
+  static constexpr int ALD = BP + 1;
+  static constexpr int R0 = NOP * BP * ALD > BP * kVld ? NOP * BP * ALD : BP * kVld;
+  double r0[R0];
+  double V[BP * kVld];
+  __device__ double *A(int op) { return r0 + op * BP * ALD; }
+  __device__ const double *A(int op) const { return r0 + op * BP * ALD; }
+};
+
+// The stages of cell c, in order: 0 = U_{c-1}^T with V_{c-1} (c > 0),
+// 2 = U_c with V_{c+1} (c + 1 < nc), 1 = D_c with V_c (always, last).
+__device__ __forceinline__ int stage_first(int c, int nc) {
+  return c > 0 ? 0 : (c + 1 < nc ? 2 : 1);
+}
+__device__ __forceinline__ int stage_next(int c, int nc, int blk) {  // -1: cell done
+  return blk == 0 ? (c + 1 < nc ? 2 : 1) : blk == 2 ? 1 : -1;
+}
+
+template <int BP, int NOP>
+struct StageRegs {
+  static constexpr int NA = (BP * BP + kCellThreads - 1) / kCellThreads;
+  static constexpr int NV = (BP * 128 / 2 + kCellThreads - 1) / kCellThreads;  // pairs
+  double a[NOP][NA];
+  double2 v[NV];
+};
+
+template <int BP, int NOP>
+__device__ __forceinline__ void stage_load(StageRegs<BP, NOP> &r, const double *const *D,
+                                           const double *const *U, int nc, int b,
+                                           const double *V, int ld, int c, int blk) {
+  const int tid = threadIdx.x;
   const size_t bb = (size_t)b * b;
-  d4 acc0 = d4zero(), acc1 = d4zero();
-  auto vrow = [&](int cell, int k) { return V[((size_t)cell * BP + k) * ld + col]; };
-  {
-    const double *Dc = D + c * bb;
-    for (int k0 = 0; k0 < BP; k0 += 4) {
-      const int k = k0 + kl;
-      double a = (row < b && k < b) ? Dc[k * b + row] : 0.0;  // symmetric block
-      acc0 = mfma(a, vrow(c, k), acc0);
-    }
-  }
-  if (c + 1 < nc) {
-    const double *Uc = U + c * bb;
-    for (int k0 = 0; k0 < BP; k0 += 4) {
-      const int k = k0 + kl;
-      double a = (row < b && k < b) ? Uc[row * b + k] : 0.0;
-      acc1 = mfma(a, vrow(c + 1, k), acc1);
-    }
-  }
-  if (c > 0) {
-    const double *Up = U + (c - 1) * bb;
-    for (int k0 = 0; k0 < BP; k0 += 4) {
-      const int k = k0 + kl;
-      double a = (row < b && k < b) ? Up[k * b + row] : 0.0;
-      acc0 = mfma(a, vrow(c - 1, k), acc0);
-    }
-  }
-  d4 acc = acc0 + acc1;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int orow = w * 16 + acc_row(l, r);
-    out[((size_t)c * BP + orow) * ld + jt * 16 + acc_col(l)] = acc[r];
+  for (int op = 0; op < NOP; ++op) {
+    const double *M = blk == 0 ? U[op] + (size_t)(c - 1) * bb
+                               : blk == 1 ? D[op] + (size_t)c * bb : U[op] + (size_t)c * bb;
+#pragma unroll
+    for (int i = 0; i < StageRegs<BP, NOP>::NA; ++i) {
+      const int idx = tid + i * kCellThreads;
+      const int x = idx / BP, y = idx % BP;  // memory order: row x, column y of M
+      r.a[op][i] = (idx < BP * BP && x < b && y < b) ? M[x * b + y] : 0.0;
+    }
+  }
+  const int cell = c - 1 + blk;
+  const double2 *Vc = reinterpret_cast<const double2 *>(V + (size_t)cell * BP * ld);
+  const int half = ld / 2;
+#pragma unroll
+  for (int i = 0; i < StageRegs<BP, NOP>::NV; ++i) {
+    const int idx = tid + i * kCellThreads;
+    r.v[i] = idx < BP * half ? Vc[idx] : double2{0.0, 0.0};
+  }
+}
+
+// A operand in LDS as A[r][k]: U_{c-1}^T and D_c (symmetric) come from memory
+// row k, column r; U_c from memory row r, column k.
+template <int BP, int NOP>
+__device__ __forceinline__ void stage_store(const StageRegs<BP, NOP> &r, CellLds<BP, NOP> &s,
+                                            int ld, int blk) {
+  constexpr int ALD = CellLds<BP, NOP>::ALD;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int op = 0; op < NOP; ++op)
+#pragma unroll
+    for (int i = 0; i < StageRegs<BP, NOP>::NA; ++i) {
+      const int idx = tid + i * kCellThreads;
+      const int x = idx / BP, y = idx % BP;
+      if (idx < BP * BP) s.A(op)[blk == 2 ? x * ALD + y : y * ALD + x] = r.a[op][i];
+    }
+  const int half = ld / 2;
+#pragma unroll
+  for (int i = 0; i < StageRegs<BP, NOP>::NV; ++i) {
+    const int idx = tid + i * kCellThreads;
+    if (idx < BP * half) {
+      const int k = idx / half, j = 2 * (idx % half);
+      s.V[k * kVld + j] = r.v[i].x;
+      s.V[k * kVld + j + 1] = r.v[i].y;
+    }
+  }
+}
+
+constexpr int kCellTiles = 2;  // output tiles a wave: (64 / 16) * (128 / 16) / 16
+
+template <int BP, int NOP>
+__device__ __forceinline__ void stage_mfma(const CellLds<BP, NOP> &s, int ld,
+                                           d4 (&acc)[NOP][kCellTiles]) {
+  constexpr int NR = BP / 16, ALD = CellLds<BP, NOP>::ALD;
+  const int nct = ld / 16;
+  const int l = lane_id(), w = wave_id(), kl = l >> 4;
+#pragma unroll
+  for (int i = 0; i < kCellTiles; ++i) {
+    const int t = w + i * kCellWaves;
+    if (t < NR * nct) {
+      const int row = (t % NR) * 16 + (l & 15), col = (t / NR) * 16 + (l & 15);
+#pragma unroll
+      for (int ks = 0; ks < BP / 4; ++ks) {
+        const int k = 4 * ks + kl;
+        const double bv = s.V[k * kVld + col];
+#pragma unroll
+        for (int op = 0; op < NOP; ++op) acc[op][i] = mfma(s.A(op)[row * ALD + k], bv, acc[op][i]);
+        if ((ks & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // bounded register use
+      }
+    }
+  }
+}
+
+// Runs the stages of every cell of this workgroup; epi(c, acc) is called
+// with all threads after the last stage of cell c (LDS free to reuse until
+// it returns, acc reset afterwards).
+template <int BP, int NOP, typename EPI>
+__device__ __forceinline__ void cell_loop(CellLds<BP, NOP> &s, const double *const *D,
+                                          const double *const *U, int nc, int b,
+                                          const double *V, int ld, EPI epi) {
+  d4 acc[NOP][kCellTiles];
+#pragma unroll
+  for (int op = 0; op < NOP; ++op)
+#pragma unroll
+    for (int i = 0; i < kCellTiles; ++i) acc[op][i] = d4zero();
+  int c = blockIdx.x;
+  if (c >= nc) return;
+  int blk = stage_first(c, nc);
+  StageRegs<BP, NOP> r;
+  stage_load<BP, NOP>(r, D, U, nc, b, V, ld, c, blk);
+  while (true) {
+    stage_store<BP, NOP>(r, s, ld, blk);
+    __syncthreads();
+    // next stage (possibly of the next cell) loads while this one computes
+    int nc_ = c, nb = stage_next(c, nc, blk);
+    if (nb < 0) {
+      nc_ = c + gridDim.x;
+      nb = nc_ < nc ? stage_first(nc_, nc) : 0;
+    }
+    if (nc_ < nc) stage_load<BP, NOP>(r, D, U, nc, b, V, ld, nc_, nb);
+    stage_mfma<BP, NOP>(s, ld, acc);
+    __syncthreads();
+    if (nc_ != c) {
+      epi(c, acc);
+#pragma unroll
+      for (int op = 0; op < NOP; ++op)
+#pragma unroll
+        for (int i = 0; i < kCellTiles; ++i) acc[op][i] = d4zero();
+      if (nc_ >= nc) break;
+    }
+    c = nc_;
+    blk = nb;
+  }
+}
+
+// out = T V, all cells
+template <int BP>
+__global__ __launch_bounds__(kCellThreads) void cell_apply_kernel(const double *D, const double *U,
+                                                                  int nc, int b, const double *V,
+                                                                  int ld, double *out) {
+  __shared__ CellLds<BP, 1> s;
+  constexpr int NR = BP / 16;
+  const int nct = ld / 16;
+  const int l = lane_id(), w = wave_id();
+  const double *Ds[1] = {D}, *Us[1] = {U};
+  cell_loop<BP, 1>(s, Ds, Us, nc, b, V, ld, [&](int c, d4 (&acc)[1][kCellTiles]) {
+#pragma unroll
+    for (int i = 0; i < kCellTiles; ++i) {
+      const int t = w + i * kCellWaves;
+      if (t < NR * nct) {
+        const int col = (t / NR) * 16 + acc_col(l);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          out[((size_t)c * BP + (t % NR) * 16 + acc_row(l, r)) * ld + col] = acc[0][i][r];
+      }
+    }
+  });
+}
+
+// partial[g] = sum over the group's cells of Q_c^T (T Q)_c  (ld x ld)
+constexpr int kProjTiles = 4;  // (128 / 16)^2 / 16
+
+template <int BP>
+__global__ __launch_bounds__(kCellThreads) void cell_project_kernel(const double *D,
+                                                                    const double *U, int nc,
+                                                                    int b, const double *Q,
+                                                                    int ld, double *partial) {
+  __shared__ CellLds<BP, 1> s;
+  constexpr int NR = BP / 16;
+  const int nct = ld / 16;
+  const int l = lane_id(), w = wave_id(), kl = l >> 4;
+  d4 pacc[kProjTiles];
+#pragma unroll
+  for (int i = 0; i < kProjTiles; ++i) pacc[i] = d4zero();
+  // output tiles of this wave: ti = w % 8, tj = w / 8 + 2 i
+  const int ti = w % 8;
+  const double *Ds[1] = {D}, *Us[1] = {U};
+  cell_loop<BP, 1>(s, Ds, Us, nc, b, Q, ld, [&](int c, d4 (&acc)[1][kCellTiles]) {
+    // (T Q)_c into r0, then pacc += Q_c^T (T Q)_c with Q_c = the V slab
+#pragma unroll
+    for (int i = 0; i < kCellTiles; ++i) {
+      const int t = w + i * kCellWaves;
+      if (t < NR * nct) {
+        const int col = (t / NR) * 16 + acc_col(l);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) s.r0[((t % NR) * 16 + acc_row(l, r)) * kVld + col] = acc[0][i][r];
+      }
+    }
+    __syncthreads();
+    if (ti < nct) {
+#pragma unroll
+      for (int ks = 0; ks < BP / 4; ++ks) {
+        const int k = 4 * ks + kl;
+        const double a = s.V[k * kVld + ti * 16 + (l & 15)];
+#pragma unroll
+        for (int i = 0; i < kProjTiles; ++i) {
+          const int tj = w / 8 + 2 * i;
+          if (tj < nct) pacc[i] = mfma(a, s.r0[k * kVld + tj * 16 + (l & 15)], pacc[i]);
+        }
+        if ((ks & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // bounded register use
+      }
+    }
+    __syncthreads();
+  });
+  double *out = partial + (size_t)blockIdx.x * ld * ld;
+  if (ti < nct)
+#pragma unroll
+    for (int i = 0; i < kProjTiles; ++i) {
+      const int tj = w / 8 + 2 * i;
+      if (tj < nct)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          out[(size_t)(ti * 16 + acc_row(l, r)) * ld + tj * 16 + acc_col(l)] = pacc[i][r];
+    }
+}
+
+// M = 0.5 (S + S^T), S = sum over the groups' partials (group order), m0 x m0
+__global__ void cell_project_reduce_kernel(const double *partial, int groups, int ld, int m0,
+                                           double *M) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m0 * m0) return;
+  const int i = idx / m0, j = idx % m0;
+  double s1 = 0.0, s2 = 0.0;
+  for (int g = 0; g < groups; ++g) {
+    s1 += partial[((size_t)g * ld + i) * ld + j];
+    s2 += partial[((size_t)g * ld + j) * ld + i];
+  }
+  M[idx] = 0.5 * (s1 + s2);
+}
+
+// partial[g][3][ld] = per column: sum |A x - lam B x|, sum |A x|, sum |B x|
+// over the group's cells (rows >= b of a cell are zero padding and add 0)
+template <int BP>
+__global__ __launch_bounds__(kCellThreads) void cell_residual_kernel(
+    const double *Ad, const double *Au, const double *Bd, const double *Bu, int nc, int b,
+    const double *X, int ld, const double *lam, int m0, double *partial) {
+  __shared__ CellLds<BP, 2> s;
+  constexpr int NR = BP / 16;
+  const int nct = ld / 16;
+  const int l = lane_id(), w = wave_id();
+  double sums[kCellTiles][3];
+  double lj[kCellTiles];
+#pragma unroll
+  for (int i = 0; i < kCellTiles; ++i) {
+    const int t = w + i * kCellWaves;
+    const int col = (t / NR) * 16 + acc_col(l);
+    lj[i] = (t < NR * nct && col < m0) ? lam[col] : 0.0;
+    sums[i][0] = sums[i][1] = sums[i][2] = 0.0;
+  }
+  const double *Ds[2] = {Ad, Bd}, *Us[2] = {Au, Bu};
+  cell_loop<BP, 2>(s, Ds, Us, nc, b, X, ld, [&](int c, d4 (&acc)[2][kCellTiles]) {
+#pragma unroll
+    for (int i = 0; i < kCellTiles; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double a = acc[0][i][r], v = acc[1][i][r];
+        sums[i][0] += fabs(a - lj[i] * v);
+        sums[i][1] += fabs(a);
+        sums[i][2] += fabs(v);
+      }
+  });
+  // lanes l, l+16, l+32, l+48 hold the same column: fold them, then the waves
+  // of equal column tile through LDS in wave order
+#pragma unroll
+  for (int i = 0; i < kCellTiles; ++i)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      double v = sums[i][q];
+      v += __shfl_xor(v, 16);
+      v += __shfl_xor(v, 32);
+      sums[i][q] = v;
+    }
+  double *red = s.r0;  // [3][kCellWaves * kCellTiles][16]
+  __syncthreads();
+  if (l < 16)
+#pragma unroll
+    for (int i = 0; i < kCellTiles; ++i)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) red[(q * kCellWaves * kCellTiles + i * kCellWaves + w) * 16 + l] = sums[i][q];
+  __syncthreads();
+  const int tid = threadIdx.x;
+  if (tid < ld) {
+    const int ct = tid / 16, lane = tid % 16;
+    double tot[3] = {0.0, 0.0, 0.0};
+    for (int t = ct * NR; t < (ct + 1) * NR; ++t) {  // tiles of this column tile
+      const int i = t / kCellWaves, wv = t % kCellWaves;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) tot[q] += red[(q * kCellWaves * kCellTiles + i * kCellWaves + wv) * 16 + lane];
+    }
+    double *out = partial + (size_t)blockIdx.x * 3 * ld;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) out[q * ld + tid] = tot[q];
   }
 }
 
@@ -91,66 +371,6 @@ __global__ void sum_nodes_kernel(const double *P, int Ne, size_t count, double *
     for (int e = 0; e < Ne; ++e) s += P[(size_t)e * count + i];
     Q[i] = s;
   }
-}
-
-constexpr int kGramRows = 1024;  // rows per workgroup (256 per wave)
-
-// partial[z][chunk] = Q(chunk rows)^T V_z(chunk rows), one 16x16 tile per
-// workgroup; the four waves split the rows and are summed in wave order.
-__global__ __launch_bounds__(256) void gram_kernel(const double *Q, const double *V1,
-                                                   const double *V2, size_t rows, int m0p,
-                                                   double *partial) {
-  __shared__ double red[4][64][4];
-  const int chunk = blockIdx.x;
-  const int ntj = m0p / 16;
-  const int ti = blockIdx.y / ntj, tj = blockIdx.y % ntj;
-  const int z = blockIdx.z;
-  const double *V = z ? V2 : V1;
-  const int l = lane_id(), w = wave_id();
-  const int kl = l >> 4;
-  const size_t r0 = (size_t)chunk * kGramRows + (size_t)w * (kGramRows / 4);
-  size_t r1 = r0 + kGramRows / 4;
-  if (r1 > rows) r1 = rows;
-  d4 acc0 = d4zero(), acc1 = d4zero();
-  const int ci = ti * 16 + (l & 15), cj = tj * 16 + (l & 15);
-  size_t r = r0;
-  for (; r + 8 <= r1; r += 8) {
-    const size_t ra = r + kl, rb = r + 4 + kl;
-    acc0 = mfma(Q[ra * m0p + ci], V[ra * m0p + cj], acc0);
-    acc1 = mfma(Q[rb * m0p + ci], V[rb * m0p + cj], acc1);
-  }
-  for (; r < r1; r += 4) {  // rows is a multiple of 16, so r1 - r is a multiple of 4
-    const size_t ra = r + kl;
-    acc0 = mfma(Q[ra * m0p + ci], V[ra * m0p + cj], acc0);
-  }
-  d4 acc = acc0 + acc1;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) red[w][l][q] = acc[q];
-  __syncthreads();
-  if (w == 0) {
-    const size_t nchunks = gridDim.x;
-    double *out = partial + ((size_t)z * nchunks + chunk) * m0p * m0p;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      double s = red[0][l][q] + red[1][l][q] + red[2][l][q] + red[3][l][q];
-      out[(size_t)(ti * 16 + acc_row(l, q)) * m0p + tj * 16 + acc_col(l)] = s;
-    }
-  }
-}
-
-__global__ void gram_reduce_kernel(const double *partial, int nchunks, int m0p, int m0,
-                                   double *G1, double *G2) {
-  const int z = blockIdx.y;
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= m0 * m0) return;
-  const int i = idx / m0, j = idx % m0;
-  const double *p = partial + (size_t)z * nchunks * m0p * m0p;
-  double s1 = 0.0, s2 = 0.0;
-  for (int c = 0; c < nchunks; ++c) {
-    s1 += p[((size_t)c * m0p + i) * m0p + j];
-    s2 += p[((size_t)c * m0p + j) * m0p + i];
-  }
-  (z ? G2 : G1)[idx] = 0.5 * (s1 + s2);
 }
 
 // X[row][j] = sum_{k<m0} Q[row][k] Phi[k][j]; columns m0..m0p-1 are zero.
@@ -183,40 +403,6 @@ __global__ __launch_bounds__(256) void gemm_qphi_kernel(const double *Q, size_t 
 #pragma unroll
   for (int r = 0; r < 4; ++r)
     X[(rbase + acc_row(l, r)) * m0p + jt * 16 + acc_col(l)] = acc[r];
-}
-
-constexpr int kResRows = 2048;
-
-__global__ __launch_bounds__(256) void residual_kernel(const double *AX, const double *BX,
-                                                       const double *lam, size_t rows, int m0p,
-                                                       int m0, double *partial) {
-  __shared__ double red[3][4][64];
-  const int chunk = blockIdx.x;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  const int j = blockIdx.y * 64 + tx;
-  double num = 0.0, na = 0.0, nb = 0.0;
-  if (j < m0) {
-    const double lj = lam[j];
-    const size_t r0 = (size_t)chunk * kResRows;
-    size_t r1 = r0 + kResRows;
-    if (r1 > rows) r1 = rows;
-    for (size_t r = r0 + ty; r < r1; r += 4) {
-      const double ax = AX[r * m0p + j], bx = BX[r * m0p + j];
-      num += fabs(ax - lj * bx);
-      na += fabs(ax);
-      nb += fabs(bx);
-    }
-  }
-  red[0][ty][tx] = num;
-  red[1][ty][tx] = na;
-  red[2][ty][tx] = nb;
-  __syncthreads();
-  if (ty == 0 && j < m0p) {
-    double *out = partial + (size_t)chunk * 3 * m0p;
-#pragma unroll
-    for (int q = 0; q < 3; ++q)
-      out[q * m0p + j] = red[q][0][tx] + red[q][1][tx] + red[q][2][tx] + red[q][3][tx];
-  }
 }
 
 __global__ void residual_reduce_kernel(const double *partial, int nchunks, int m0p, int m0,
@@ -274,42 +460,9 @@ hipError_t launch_unpack(const double *src, int nc, int b, int bp, int m, int ld
   return hipGetLastError();
 }
 
-hipError_t launch_bt_multiply(const Pencil &p, int which, const double *V, int ld, double *out,
-                              hipStream_t st) {
-  const double *D = which ? p.Bd : p.Ad;
-  const double *U = which ? p.Bu : p.Au;
-  dim3 grid(p.nc, ld / 16);
-  switch (p.bp) {
-    case 16: hipLaunchKernelGGL(bt_multiply_kernel<16>, grid, dim3(64), 0, st, D, U, p.nc, p.b, V, ld, out); break;
-    case 32: hipLaunchKernelGGL(bt_multiply_kernel<32>, grid, dim3(128), 0, st, D, U, p.nc, p.b, V, ld, out); break;
-    case 48: hipLaunchKernelGGL(bt_multiply_kernel<48>, grid, dim3(192), 0, st, D, U, p.nc, p.b, V, ld, out); break;
-    case 64: hipLaunchKernelGGL(bt_multiply_kernel<64>, grid, dim3(256), 0, st, D, U, p.nc, p.b, V, ld, out); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
 hipError_t launch_sum_nodes(const double *P, int Ne, size_t count, double *Q, hipStream_t st) {
   hipLaunchKernelGGL(sum_nodes_kernel, dim3(grid_for(count, 256)), dim3(256), 0, st, P, Ne, count,
                      Q);
-  return hipGetLastError();
-}
-
-size_t gram_partial_doubles(size_t rows, int m0p) {
-  size_t nchunks = (rows + kGramRows - 1) / kGramRows;
-  return 2 * nchunks * (size_t)m0p * m0p;
-}
-
-hipError_t launch_gram2(const double *Q, const double *V1, const double *V2, size_t rows, int m0p,
-                        int m0, double *partial, double *G1, double *G2, hipStream_t st) {
-  const int nchunks = (int)((rows + kGramRows - 1) / kGramRows);
-  const int nt = m0p / 16;
-  hipLaunchKernelGGL(gram_kernel, dim3(nchunks, nt * nt, 2), dim3(256), 0, st, Q, V1, V2, rows,
-                     m0p, partial);
-  hipError_t err = hipGetLastError();
-  if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3((m0 * m0 + 255) / 256, 2), dim3(256), 0, st,
-                     partial, nchunks, m0p, m0, G1, G2);
   return hipGetLastError();
 }
 
@@ -317,23 +470,6 @@ hipError_t launch_gemm_qphi(const double *Q, size_t rows, int m0p, int m0, const
                             double *X, hipStream_t st) {
   dim3 grid((unsigned)((rows + 63) / 64), m0p / 16);
   hipLaunchKernelGGL(gemm_qphi_kernel, grid, dim3(256), 0, st, Q, rows, m0p, m0, Phi, X);
-  return hipGetLastError();
-}
-
-size_t residual_partial_doubles(size_t rows, int m0p) {
-  return ((rows + kResRows - 1) / kResRows) * 3 * (size_t)m0p;
-}
-
-hipError_t launch_residuals(const double *AX, const double *BX, const double *lam, size_t rows,
-                            int m0p, int m0, double emin, double emax, double *partial,
-                            double *res, hipStream_t st) {
-  const int nchunks = (int)((rows + kResRows - 1) / kResRows);
-  hipLaunchKernelGGL(residual_kernel, dim3(nchunks, (m0p + 63) / 64), dim3(256), 0, st, AX, BX,
-                     lam, rows, m0p, m0, partial);
-  hipError_t err = hipGetLastError();
-  if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(residual_reduce_kernel, dim3((m0 + 127) / 128), dim3(128), 0, st, partial,
-                     nchunks, m0p, m0, emin, emax, res);
   return hipGetLastError();
 }
 
@@ -347,6 +483,92 @@ hipError_t launch_check_finite(const double *x, size_t count, int *flag, hipStre
 hipError_t launch_gather(const double *src, const int *perm, int m, double *dst, hipStream_t st) {
   hipLaunchKernelGGL(gather_kernel, dim3((m + 127) / 128), dim3(128), 0, st, src, perm, m, dst);
   return hipGetLastError();
+}
+
+
+int cell_groups(int nc) { return nc < kCellGroups ? nc : kCellGroups; }
+
+size_t cell_partial_doubles(int nc, int ld) {
+  return (size_t)cell_groups(nc) * ld * ld;
+}
+
+template <int BP>
+hipError_t cell_apply_bp(const double *D, const double *U, int nc, int b, const double *V, int ld,
+                         double *out, hipStream_t st) {
+  hipLaunchKernelGGL(cell_apply_kernel<BP>, dim3(cell_groups(nc)), dim3(kCellThreads), 0, st, D,
+                     U, nc, b, V, ld, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_cell_apply(const Pencil &p, int which, const double *V, int ld, double *out,
+                             hipStream_t st) {
+  const double *D = which ? p.Bd : p.Ad;
+  const double *U = which ? p.Bu : p.Au;
+  if (ld % 16 != 0 || ld > 128) return hipErrorInvalidValue;
+  switch (p.bp) {
+    case 16: return cell_apply_bp<16>(D, U, p.nc, p.b, V, ld, out, st);
+    case 32: return cell_apply_bp<32>(D, U, p.nc, p.b, V, ld, out, st);
+    case 48: return cell_apply_bp<48>(D, U, p.nc, p.b, V, ld, out, st);
+    case 64: return cell_apply_bp<64>(D, U, p.nc, p.b, V, ld, out, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int BP>
+hipError_t cell_project_bp(const Pencil &p, const double *Q, int ld, int m0, double *partial,
+                           double *AQ, double *BQ, hipStream_t st) {
+  const int G = cell_groups(p.nc);
+  for (int z = 0; z < 2; ++z) {
+    const double *D = z ? p.Bd : p.Ad;
+    const double *U = z ? p.Bu : p.Au;
+    hipLaunchKernelGGL(cell_project_kernel<BP>, dim3(G), dim3(kCellThreads), 0, st, D, U, p.nc,
+                       p.b, Q, ld, partial);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(cell_project_reduce_kernel, dim3((m0 * m0 + 255) / 256), dim3(256), 0, st,
+                       (const double *)partial, G, ld, m0, z ? BQ : AQ);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_cell_project(const Pencil &p, const double *Q, int ld, int m0, double *partial,
+                               double *AQ, double *BQ, hipStream_t st) {
+  if (ld % 16 != 0 || ld > 128) return hipErrorInvalidValue;
+  switch (p.bp) {
+    case 16: return cell_project_bp<16>(p, Q, ld, m0, partial, AQ, BQ, st);
+    case 32: return cell_project_bp<32>(p, Q, ld, m0, partial, AQ, BQ, st);
+    case 48: return cell_project_bp<48>(p, Q, ld, m0, partial, AQ, BQ, st);
+    case 64: return cell_project_bp<64>(p, Q, ld, m0, partial, AQ, BQ, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int BP>
+hipError_t cell_residual_bp(const Pencil &p, const double *X, int ld, const double *lam, int m0,
+                            double emin, double emax, double *partial, double *res,
+                            hipStream_t st) {
+  const int G = cell_groups(p.nc);
+  hipLaunchKernelGGL(cell_residual_kernel<BP>, dim3(G), dim3(kCellThreads), 0, st, p.Ad, p.Au,
+                     p.Bd, p.Bu, p.nc, p.b, X, ld, lam, m0, partial);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(residual_reduce_kernel, dim3((m0 + 127) / 128), dim3(128), 0, st,
+                     (const double *)partial, G, ld, m0, emin, emax, res);
+  return hipGetLastError();
+}
+
+hipError_t launch_cell_residuals(const Pencil &p, const double *X, int ld, const double *lam,
+                                 int m0, double emin, double emax, double *partial, double *res,
+                                 hipStream_t st) {
+  if (ld % 16 != 0 || ld > 128) return hipErrorInvalidValue;
+  switch (p.bp) {
+    case 16: return cell_residual_bp<16>(p, X, ld, lam, m0, emin, emax, partial, res, st);
+    case 32: return cell_residual_bp<32>(p, X, ld, lam, m0, emin, emax, partial, res, st);
+    case 48: return cell_residual_bp<48>(p, X, ld, lam, m0, emin, emax, partial, res, st);
+    case 64: return cell_residual_bp<64>(p, X, ld, lam, m0, emin, emax, partial, res, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace feast

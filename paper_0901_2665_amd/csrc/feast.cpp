@@ -28,7 +28,7 @@ struct Buf {
 };
 
 enum Slot {
-  S_SINV, S_W, S_WT, S_TW, S_G, S_TV, S_Y, S_R, S_P, S_Q, S_AV, S_BV, S_X, S_GRAMP, S_AQ, S_BQ,
+  S_SINV, S_W, S_WT, S_TW, S_G, S_TV, S_Y, S_R, S_P, S_Q, S_X, S_GRAMP, S_AQ, S_BQ,
   S_EPS, S_PHI, S_RRS, S_FLAG, S_RESP, S_RES, S_PERM, S_T0, S_T1, S_FWORK, S_CHAINS, S_COUNT
 };
 
@@ -39,7 +39,7 @@ namespace {
 enum Kind { K_FACTOR, K_FORWARD, K_BACK, K_BTMUL, K_SUM, K_GRAM, K_RR, K_RITZ, K_RESID,
             K_LAYOUT, K_COUNT };
 const char *kKindNames[K_COUNT] = {"factor",      "forward_sweep", "back_sweep", "bt_multiply",
-                                   "sum_nodes",   "gram",          "reduced_eig", "ritz_gemm",
+                                   "sum_nodes",   "projection",          "reduced_eig", "ritz_gemm",
                                    "residual",    "layout"};
 struct Timing {
   bool on = false;
@@ -379,7 +379,7 @@ int feast_bt_multiply(feast_ctx *ctx, const feast_bt_matrix *AB, int32_t which, 
   HIPCHK(ensure_t(ctx, S_T0, rows * mp, &vin));
   HIPCHK(ensure_t(ctx, S_T1, rows * mp, &vout));
   HIPCHK(launch_pack(V, p.nc, p.b, p.bp, m, mp, vin, ctx->stream));
-  HIPCHK(launch_bt_multiply(p, which, vin, mp, vout, ctx->stream));
+  HIPCHK(launch_cell_apply(p, which, vin, mp, vout, ctx->stream));
   HIPCHK(launch_unpack(vout, p.nc, p.b, p.bp, m, mp, nullptr, out, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return 0;
@@ -438,7 +438,7 @@ int feast_filter(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double 
   HIPCHK(ensure_t(ctx, S_Q, wk.rows * mp, &q));
   HIPCHK(run_factor(ctx, wk, s));
   HIPCHK(launch_pack(Y, p.nc, p.b, p.bp, M0, mp, y, ctx->stream));
-  HIPCHK(launch_bt_multiply(p, 1, y, mp, r, ctx->stream));
+  HIPCHK(launch_cell_apply(p, 1, y, mp, r, ctx->stream));
   HIPCHK(launch_sweeps(p, s, Ne, wk.f, wk.sb, r, mp, pp, 3, ctx->stream));
   HIPCHK(launch_sum_nodes(pp, Ne, wk.rows * mp, q, ctx->stream));
   HIPCHK(launch_unpack(q, p.nc, p.b, p.bp, M0, mp, nullptr, Q, ctx->stream));
@@ -456,15 +456,11 @@ int feast_project(feast_ctx *ctx, const feast_bt_matrix *AB, int32_t M0, const d
   Pencil p = make_pencil(AB);
   const int mp = round16(M0);
   const size_t rows = (size_t)p.nc * p.bp;
-  double *q, *av, *bv, *gp;
+  double *q, *gp;
   HIPCHK(ensure_t(ctx, S_Q, rows * mp, &q));
-  HIPCHK(ensure_t(ctx, S_AV, rows * mp, &av));
-  HIPCHK(ensure_t(ctx, S_BV, rows * mp, &bv));
-  HIPCHK(ensure_t(ctx, S_GRAMP, gram_partial_doubles(rows, mp), &gp));
+  HIPCHK(ensure_t(ctx, S_GRAMP, cell_partial_doubles(p.nc, mp), &gp));
   HIPCHK(launch_pack(Q, p.nc, p.b, p.bp, M0, mp, q, ctx->stream));
-  HIPCHK(launch_bt_multiply(p, 0, q, mp, av, ctx->stream));
-  HIPCHK(launch_bt_multiply(p, 1, q, mp, bv, ctx->stream));
-  HIPCHK(launch_gram2(q, av, bv, rows, mp, M0, gp, AQ, BQ, ctx->stream));
+  HIPCHK(launch_cell_project(p, q, mp, M0, gp, AQ, BQ, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return 0;
 }
@@ -516,23 +512,21 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
   make_shifts(Ne, emin, emax, s);
   const double r = 0.5 * (emax - emin);
 
-  double *y, *rr, *pp, *q, *av, *bv, *x, *gp, *aq, *bq, *eps, *phi, *scr, *resp, *resi;
+  double *y, *rr, *pp, *q, *x, *gp, *aq, *bq, *eps, *phi, *scr, *resp, *resi;
   int *flag, *perm;
   HIPCHK(ensure_t(ctx, S_Y, rows * mp, &y));
   HIPCHK(ensure_t(ctx, S_R, rows * mp, &rr));
   HIPCHK(ensure_t(ctx, S_P, (size_t)Ne * rows * mp, &pp));
   HIPCHK(ensure_t(ctx, S_Q, rows * mp, &q));
-  HIPCHK(ensure_t(ctx, S_AV, rows * mp, &av));
-  HIPCHK(ensure_t(ctx, S_BV, rows * mp, &bv));
   HIPCHK(ensure_t(ctx, S_X, rows * mp, &x));
-  HIPCHK(ensure_t(ctx, S_GRAMP, gram_partial_doubles(rows, mp), &gp));
+  HIPCHK(ensure_t(ctx, S_GRAMP, cell_partial_doubles(p.nc, mp), &gp));
   HIPCHK(ensure_t(ctx, S_AQ, (size_t)M0 * M0, &aq));
   HIPCHK(ensure_t(ctx, S_BQ, (size_t)M0 * M0, &bq));
   HIPCHK(ensure_t(ctx, S_EPS, (size_t)M0, &eps));
   HIPCHK(ensure_t(ctx, S_PHI, (size_t)M0 * M0, &phi));
   HIPCHK(ensure_t(ctx, S_RRS, reduced_eig_scratch_doubles(), &scr));
   HIPCHK(ensure_t(ctx, S_FLAG, 4, &flag));
-  HIPCHK(ensure_t(ctx, S_RESP, residual_partial_doubles(rows, mp), &resp));
+  HIPCHK(ensure_t(ctx, S_RESP, cell_partial_doubles(p.nc, mp), &resp));
   HIPCHK(ensure_t(ctx, S_RES, (size_t)M0, &resi));
   HIPCHK(ensure_t(ctx, S_PERM, (size_t)M0, &perm));
 
@@ -551,20 +545,16 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
   const double res_gate = std::sqrt(o.tol);
   std::vector<char> is_counted(M0, 0);
   for (int k = 1; k <= o.max_loops; ++k) {
-    TIMED(K_BTMUL, launch_bt_multiply(p, 1, y, mp, rr, sm));                 // R = B Y
+    TIMED(K_BTMUL, launch_cell_apply(p, 1, y, mp, rr, sm));                  // R = B Y
     TIMED(K_FORWARD, launch_sweeps(p, s, Ne, wk.f, wk.sb, rr, mp, pp, 1, sm)); // Q_e ...
     TIMED(K_BACK, launch_sweeps(p, s, Ne, wk.f, wk.sb, rr, mp, pp, 2, sm));    // ... weighted
     TIMED(K_SUM, launch_sum_nodes(pp, Ne, rows * mp, q, sm));                // Q (eq. 15)
-    TIMED(K_BTMUL, launch_bt_multiply(p, 0, q, mp, av, sm));                 // A Q
-    TIMED(K_BTMUL, launch_bt_multiply(p, 1, q, mp, bv, sm));                 // B Q
-    TIMED(K_GRAM, launch_gram2(q, av, bv, rows, mp, M0, gp, aq, bq, sm));   // A_Q, B_Q (eq. 7)
+    TIMED(K_GRAM, launch_cell_project(p, q, mp, M0, gp, aq, bq, sm));      // A_Q, B_Q (eq. 7)
     TIMED(K_RR, launch_reduced_eig(aq, bq, M0, eps, phi, scr, flag, sm));   // eq. 6
     TIMED(K_RITZ, launch_gemm_qphi(q, rows, mp, M0, phi, x, sm));           // X = Q Phi (eq. 9)
     // residuals of the Ritz pairs (Table I caption) decide which in-interval
     // pairs count as eigenvalue solutions (relative residual <= sqrt(tol))
-    TIMED(K_BTMUL, launch_bt_multiply(p, 0, x, mp, av, sm));
-    TIMED(K_BTMUL, launch_bt_multiply(p, 1, x, mp, bv, sm));
-    TIMED(K_RESID, launch_residuals(av, bv, eps, rows, mp, M0, emin, emax, resp, resi, sm));
+    TIMED(K_RESID, launch_cell_residuals(p, x, mp, eps, M0, emin, emax, resp, resi, sm));
     HIPCHK(hipMemcpyAsync(h_eps, eps, M0 * sizeof(double), hipMemcpyDeviceToHost, sm));
     HIPCHK(hipMemcpyAsync(h_res, resi, M0 * sizeof(double), hipMemcpyDeviceToHost, sm));
     HIPCHK(hipMemcpyAsync(ctx->h_flag, flag, 3 * sizeof(int), hipMemcpyDeviceToHost, sm));

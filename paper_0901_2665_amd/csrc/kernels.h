@@ -73,21 +73,10 @@ hipError_t launch_pack(const double *src, int nc, int b, int bp, int m, int ldd,
                        double *dst, hipStream_t st);
 hipError_t launch_unpack(const double *src, int nc, int b, int bp, int m, int lds,
                          const int *perm, double *dst, hipStream_t st);
-hipError_t launch_bt_multiply(const Pencil &p, int which, const double *V, int ld,
-                              double *out, hipStream_t st);
 hipError_t launch_sum_nodes(const double *P, int Ne, size_t count, double *Q,
                             hipStream_t st);
-// Gram matrices Q^T V1 and Q^T V2 -> symmetrised [m0][m0] outputs.
-hipError_t launch_gram2(const double *Q, const double *V1, const double *V2, size_t rows,
-                        int m0p, int m0, double *partial, double *G1, double *G2,
-                        hipStream_t st);
-size_t gram_partial_doubles(size_t rows, int m0p);
 hipError_t launch_gemm_qphi(const double *Q, size_t rows, int m0p, int m0,
                             const double *Phi, double *X, hipStream_t st);
-hipError_t launch_residuals(const double *AX, const double *BX, const double *lam,
-                            size_t rows, int m0p, int m0, double emin, double emax,
-                            double *partial, double *res, hipStream_t st);
-size_t residual_partial_doubles(size_t rows, int m0p);
 hipError_t launch_check_finite(const double *x, size_t count, int *flag, hipStream_t st);
 hipError_t launch_gather(const double *src, const int *perm, int m, double *dst,
                          hipStream_t st);
@@ -95,6 +84,18 @@ hipError_t launch_gather(const double *src, const int *perm, int m, double *dst,
 // Reduced eigenproblem (rr.hip): one workgroup.
 // scratch: reduced_eig_scratch_doubles().  eps, Phi outputs; flag[0] =
 // fallback, flag[1] = Jacobi sweeps, flag[2] = sweeps of the fallback.
+// Per-cell products (one workgroup walks a strided set of cells; ld <= 128,
+// a multiple of 16).  partial: cell_partial_doubles(nc, ld) doubles, which
+// also covers the 3 ld per group of the residual variant.
+size_t cell_partial_doubles(int nc, int ld);
+hipError_t launch_cell_apply(const Pencil &p, int which, const double *V, int ld, double *out,
+                             hipStream_t st);
+hipError_t launch_cell_project(const Pencil &p, const double *Q, int ld, int m0, double *partial,
+                               double *AQ, double *BQ, hipStream_t st);
+hipError_t launch_cell_residuals(const Pencil &p, const double *X, int ld, const double *lam,
+                                 int m0, double emin, double emax, double *partial, double *res,
+                                 hipStream_t st);
+
 size_t reduced_eig_scratch_doubles();
 hipError_t launch_reduced_eig(const double *AQ, const double *BQ, int n, double *eps,
                               double *Phi, double *scratch, int *flag, hipStream_t st);

@@ -37,20 +37,28 @@ template <int BP>
 __device__ void form_block(double *slot, const double *Ablk, const double *Bblk, int b,
                            double zr, double zi, bool transpose, bool diag_pad) {
   constexpr int LD = Lds<BP>::LD, PLANE = Lds<BP>::PLANE;
-  for (int idx = threadIdx.x; idx < BP * BP; idx += kThreads) {
-    int r = idx / BP, c = idx % BP;
-    double re, im;
-    if (r < b && c < b) {
-      int src = transpose ? c * b + r : r * b + c;
-      double bv = Bblk[src], av = Ablk[src];
-      re = zr * bv - av;
-      im = zi * bv;
-    } else {
-      re = (diag_pad && r == c) ? 1.0 : 0.0;
-      im = 0.0;
+  constexpr int NE = (BP * BP + kThreads - 1) / kThreads;
+  // all loads first (consecutive threads read consecutive memory; a
+  // transposed block is transposed on the way into LDS), then the stores
+  double av[NE], bv[NE];
+#pragma unroll
+  for (int t = 0; t < NE; ++t) {
+    const int idx = threadIdx.x + t * kThreads;
+    const int x = idx / BP, y = idx % BP;  // memory row x, column y
+    const bool in = idx < BP * BP && x < b && y < b;
+    av[t] = in ? Ablk[x * b + y] : 0.0;
+    bv[t] = in ? Bblk[x * b + y] : 0.0;
+  }
+#pragma unroll
+  for (int t = 0; t < NE; ++t) {
+    const int idx = threadIdx.x + t * kThreads;
+    if (idx < BP * BP) {
+      const int x = idx / BP, y = idx % BP;
+      const int r = transpose ? y : x, c = transpose ? x : y;
+      const bool in = x < b && y < b;
+      slot[r * LD + c] = in ? zr * bv[t] - av[t] : ((diag_pad && r == c) ? 1.0 : 0.0);
+      slot[PLANE + r * LD + c] = in ? zi * bv[t] : 0.0;
     }
-    slot[r * LD + c] = re;
-    slot[PLANE + r * LD + c] = im;
   }
 }
 
@@ -155,6 +163,31 @@ __device__ void store_block(double *g, const double *slot, bool transpose) {
 // stride ld) by one wave: Gauss-Jordan elimination without pivoting, the
 // tile held in registers (lane l: row l/4, columns 4(l%4)..4(l%4)+3), pivot
 // row and column exchanged with lane shuffles.
+// Lane broadcasts for the pivot steps: a uniform lane through the scalar
+// unit, a lane of each quad (lanes 4i..4i+3) through DPP.
+__device__ __forceinline__ double readlane_d(double x, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+  return __hiloint2double(hi, lo);
+}
+
+template <int Q>
+__device__ __forceinline__ double quad_bcast_q(double x) {
+  constexpr int ctrl = Q | (Q << 2) | (Q << 4) | (Q << 6);  // quad_perm [Q, Q, Q, Q]
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), ctrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), ctrl, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double quad_bcast(double x, int q) {
+  switch (q) {
+    case 0: return quad_bcast_q<0>(x);
+    case 1: return quad_bcast_q<1>(x);
+    case 2: return quad_bcast_q<2>(x);
+    default: return quad_bcast_q<3>(x);
+  }
+}
+
 __device__ __forceinline__ void inv16_wave(double *Xr, double *Xi, int ld) {
   const int l = lane_id();
   const int r = l >> 2, cb = (l & 3) * 4;
@@ -168,13 +201,13 @@ __device__ __forceinline__ void inv16_wave(double *Xr, double *Xi, int ld) {
   for (int j = 0; j < 16; ++j) {
     const int vj = j & 3;
     const int pl = (j << 2) | (j >> 2);          // lane holding (j, j)
-    const cplx piv = crecip_fast(cplx{__shfl(ar[vj], pl), __shfl(ai[vj], pl)});
+    const cplx piv = crecip_fast(cplx{readlane_d(ar[vj], pl), readlane_d(ai[vj], pl)});
     const int rl = (j << 2) | (l & 3);           // lane holding row j, my columns
     cplx rk[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) rk[v] = cmul(cplx{__shfl(ar[v], rl), __shfl(ai[v], rl)}, piv);
-    const int cl = (l & ~3) | (j >> 2);          // lane holding my row, column j
-    const cplx cj{__shfl(ar[vj], cl), __shfl(ai[vj], cl)};
+    // my row, column j: lane j / 4 of my quad
+    const cplx cj{quad_bcast(ar[vj], j >> 2), quad_bcast(ai[vj], j >> 2)};
     const cplx m = cmul(cj, piv);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {

@@ -193,18 +193,22 @@ __global__ __launch_bounds__(BP * 8) void forward_kernel(SweepArgs a) {
     const d4 h = rhs_load<BP>(R + start * rstride, a.m0p, rb, true);
     acc_store_vec<BP>(&s.v[0][0][0][0], -h, rb);
   }
-  Frag<BP> f0, f1;
+  // matrix fragments and right-hand side tiles are loaded two steps ahead
+  // (three buffers each)
+  Frag<BP> f0, f1, f2;
   frag_load<BP>(f0, M + start * blk, rb, nsteps > 0);
+  frag_load<BP>(f1, M + (start + dir) * blk, rb, nsteps > 1);
   d4 r0 = rhs_load<BP>(R + (start + dir) * rstride, a.m0p, rb, wrole && len > 1);
-  d4 r1 = d4zero();
+  d4 r1 = rhs_load<BP>(R + (start + 2 * dir) * rstride, a.m0p, rb, wrole && len > 2);
+  d4 r2 = d4zero();
   __syncthreads();
   int cur = 0;
-  // one step on cell c with operands (f, r); loads cell c+dir's fragments and
-  // the right-hand side tile of cell c+2dir for the next step
-  auto step = [&](int j, const Frag<BP> &f, const d4 &r, Frag<BP> &nf, d4 &nr) {
+  // one step on cell c with operands (f, r = R_{c+dir}); loads the
+  // fragments of cell c+2dir and R_{c+3dir} for step j+2
+  auto step = [&](int j, const Frag<BP> &f, const d4 &r, Frag<BP> &nf2, d4 &nr2) {
     const int c = start + dir * j;
-    frag_load<BP>(nf, M + (c + dir) * blk, rb, j + 1 < nsteps);
-    nr = rhs_load<BP>(R + (c + 2 * dir) * rstride, a.m0p, rb, wrole && j + 2 < len);
+    frag_load<BP>(nf2, M + (c + 2 * dir) * blk, rb, j + 2 < nsteps);
+    nr2 = rhs_load<BP>(R + (c + 3 * dir) * rstride, a.m0p, rb, wrole && j + 3 < len);
     double b[BP / 2];
     bvec_load<BP>(b, s.v[cur]);
     const bool more = j < len - 1;
@@ -222,10 +226,15 @@ __global__ __launch_bounds__(BP * 8) void forward_kernel(SweepArgs a) {
     __syncthreads();
     cur ^= 1;
   };
-  for (int j = 0; j < nsteps; j += 2) {
-    step(j, f0, r0, f1, r1);
-    if (j + 1 < nsteps) step(j + 1, f1, r1, f0, r0);
+  // whole rounds of three steps without branches (exact waits), then the rest
+  int j = 0;
+  for (; j + 3 <= nsteps; j += 3) {
+    step(j, f0, r0, f2, r2);
+    step(j + 1, f1, r1, f0, r0);
+    step(j + 2, f2, r2, f1, r1);
   }
+  if (j < nsteps) step(j, f0, r0, f2, r2);
+  if (j + 1 < nsteps) step(j + 1, f1, r1, f0, r0);
   if (top && wrole) {
     const d4 u = acc_load_vec<BP>(&s.v[cur][0][0][0], rb);
     acc_store_vec<BP>(TV, -u, rb);  // h_{m-1}

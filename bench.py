@@ -6,7 +6,12 @@ loops to convergence, residuals) on the tight-binding chain workload
 eigenvalues), inputs resident in HBM.  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload tb128k]
-                  [--no-cpu-baseline]
+                  [--precision 0|1] [--no-cpu-baseline]
+
+--precision 1 times the mixed-precision solver instead (factor blocks rounded
+to float32, complex float32 sweeps, float64 refinement of every shifted solve
+to a relative residual of 1e-12) on the same workload and also times the
+float64 solver for comparison.
 """
 from __future__ import annotations
 
@@ -23,6 +28,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "FEAST solves/sec and shifted-solve TFLOP/s (% MFMA peak) at 1e-10 eig accuracy"
 PEAK_FP64 = 78.6        # TFLOP/s, MI355X dense FP64 (matrix = vector)
+PEAK_FP32 = 157.3       # TFLOP/s, MI355X dense FP32 (matrix = vector)
 PEAK_HBM = 8000.0       # GB/s
 
 
@@ -75,11 +81,18 @@ def copy_probe():
 
 def nominal_flops(nc, b, m0, ne):
     """Nominal work of the sequential block-LU algorithm (complex = 4x real)."""
-    return dict(
+    d = dict(
         factor=ne * nc * (56.0 / 3.0) * b ** 3,          # per solve
         forward_sweep=ne * nc * 16.0 * b * b * m0,        # per loop: W^T h and Sinv h
         back_sweep=ne * nc * 8.0 * b * b * m0,            # per loop: W x
+        # mixed precision, per launch: the same sweeps in float32, and the
+        # float64 residual R - (Z_e B - A) x_e of all nodes (A and B times
+        # the real and imaginary planes: 4 block-tridiagonal products)
+        refine_residual=ne * nc * 24.0 * b * b * m0,
     )
+    d["forward_sweep32"] = d["forward_sweep"]
+    d["back_sweep32"] = d["back_sweep"]
+    return d
 
 
 def cpu_baseline(p, emin, emax, m0, ne, Y0, loops):
@@ -120,6 +133,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="tb128k")
+    ap.add_argument("--precision", type=int, default=0, choices=(0, 1),
+                    help="0: float64 shifted solves; 1: mixed precision")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 1 GiB device copy first (reference for HBM byte counters)")
@@ -144,25 +159,39 @@ def main():
     out = (torch.empty(m0, dtype=torch.float64, device="cuda"),
            torch.empty((p.n, m0), dtype=torch.float64, device="cuda"),
            torch.empty(m0, dtype=torch.float64, device="cuda"))
+    prec = args.precision
     for _ in range(args.warmup):
-        r = ctx.solve(gp, emin, emax, m0, ne, y, out=out)
+        r = ctx.solve(gp, emin, emax, m0, ne, y, out=out, precision=prec)
     torch.cuda.synchronize()
     ctx.timing(True)
     t0 = time.perf_counter()
     results = []
     for _ in range(args.steps):
-        r = ctx.solve(gp, emin, emax, m0, ne, y, out=out)
+        r = ctx.solve(gp, emin, emax, m0, ne, y, out=out, precision=prec)
         results.append((r.status, r.M, r.loops, r.max_res))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     times = ctx.timing_read()
     ctx.timing(False)
     elapsed = t1 - t0
+    fp64_rate = None
+    if prec == 1:  # the float64 solver on the same workload, for comparison
+        r64 = ctx.solve(gp, emin, emax, m0, ne, y, out=out)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for _ in range(args.steps):
+            r64 = ctx.solve(gp, emin, emax, m0, ne, y, out=out)
+        torch.cuda.synchronize()
+        fp64_rate = args.steps / (time.perf_counter() - ta)
+        r = ctx.solve(gp, emin, emax, m0, ne, y, out=out, precision=prec)  # outputs for the gate
 
     # accuracy gate on the last solve
     lam = out[0].cpu().numpy()
     gate = {"M": r.M, "expected_M": wl["n_eig"], "max_res": r.max_res, "loops": r.loops,
             "status": r.status, "rr_sweeps": r.rr_sweeps}
+    if prec == 1:
+        gate["refine_steps"] = r.refine_steps
+        gate["shifted_solve_rel_res"] = r.solve_res
     gpath = os.path.join(ROOT, "tests", "golden", f"feast_{args.workload}.json")
     if os.path.exists(gpath):
         g = json.load(open(gpath))
@@ -179,15 +208,23 @@ def main():
     for k, (ms, cnt) in times.items():
         if cnt:
             per[k] = {"ms_total": ms, "launches": cnt, "ms_avg": ms / cnt}
-    solve_kernels = ["factor", "forward_sweep", "back_sweep"]
-    dom = max(solve_kernels, key=lambda k: times.get(k, (0, 0))[0])
+    if prec == 1:
+        solve_kernels = ["factor", "round_factors", "forward_sweep32", "back_sweep32",
+                         "refine_residual"]
+        peak_of = {"forward_sweep32": PEAK_FP32, "back_sweep32": PEAK_FP32}
+    else:
+        solve_kernels = ["factor", "forward_sweep", "back_sweep"]
+        peak_of = {}
+    dom = max((k for k in solve_kernels if k in nom), key=lambda k: times.get(k, (0, 0))[0])
     ms_dom, n_dom = times[dom]
     achieved = nom[dom] / (ms_dom / n_dom * 1e-3) / 1e12
+    peak_dom = peak_of.get(dom, PEAK_FP64)
     loops_total = sum(x[2] for x in results)
-    shifted_ms = sum(times[k][0] for k in solve_kernels)
+    shifted_ms = sum(times[k][0] for k in solve_kernels if k in times)
     shifted_flops = args.steps * nom["factor"] + loops_total * (nom["forward_sweep"] +
                                                                nom["back_sweep"])
     shifted_tflops = shifted_flops / (shifted_ms * 1e-3) / 1e12
+    shifted_peak = PEAK_FP32 if prec == 1 else PEAK_FP64
 
     line = {
         "metric": METRIC,
@@ -200,19 +237,22 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64" if prec == 1 else "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "nc": p.nc, "b": p.b, "n": p.n, "M0": m0,
                    "Ne": ne, "interval": [emin, emax], "eigenvalues_in_interval": wl["n_eig"],
-                   "tol": 1e-12},
+                   "tol": 1e-12, "precision": "mixed" if prec == 1 else "float64"},
         "shifted_solve_tflops": shifted_tflops,
-        "shifted_solve_frac_peak": shifted_tflops / PEAK_FP64,
+        "shifted_solve_frac_peak": shifted_tflops / shifted_peak,
         "gate": gate,
         "kernels": per,
-        "roofline": {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": PEAK_FP64,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64,
+        "roofline": {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": peak_dom,
+                     "unit": "TFLOP/s", "frac": achieved / peak_dom,
                      "traffic": measured_traffic(args.workload, dom)},
     }
+    if fp64_rate is not None:
+        line["float64_solves_per_s"] = fp64_rate
+        line["mixed_over_float64"] = line["value"] / fp64_rate
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p, emin, emax, m0, ne, Y0, r.loops)
     ctx.close()

@@ -49,6 +49,8 @@
  *       lambda = NaN and a zero eigenvector
  *    3  no eigenvalue in the interval (M = 0)
  *    4  M = M0: the subspace is too small (Fig. 2 needs M0 > M)
+ *    5  precision 1 only: the float64 refinement of a shifted solve stopped
+ *       (10 corrections) above its tolerance (see feast_shifted_solve_mixed)
  * Positive codes are warnings: every output is written.
  */
 #ifndef FEAST_MI355X_H
@@ -75,7 +77,10 @@ typedef struct {
 typedef struct {
   double tol;            /* relative trace change for convergence, e.g. 1e-12 */
   int32_t max_loops;     /* refinement loops allowed, >= 1 */
-  int32_t precision;     /* 0: complex float64 shifted solves */
+  int32_t precision;     /* 0: complex float64 shifted solves;
+                            1: factor blocks rounded to float32, complex float32
+                            sweeps, float64 iterative refinement of every
+                            shifted solve (criterion: feast_shifted_solve_mixed) */
   int32_t partitions;    /* partitions per half chain of the factorisation;
                             0 = automatic (at least 8 cells each, about one
                             chain per compute unit); results do not depend on it
@@ -94,6 +99,10 @@ typedef struct {
   double trace_hist[64]; /* trace per loop (first min(loops,64) entries) */
   int32_t count_hist[64];/* M per loop */
   int32_t rr_sweeps;     /* Jacobi sweeps of the reduced eigensolver, all loops */
+  int32_t refine_steps;  /* precision 1: float32 correction solves, all loops */
+  double solve_res;      /* precision 1: largest final residual ratio of a
+                            shifted solve column (feast_shifted_solve_mixed)
+                            over all loops and nodes */
 } feast_info;
 
 /* Default options: tol 1e-12, max_loops 20, precision 0, partitions 0, Y0 NULL. */
@@ -153,12 +162,39 @@ int feast_shifted_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double z_re,
                         double *X_im);
 
 /*
+ * Mixed-precision variant of feast_shifted_solve: the factor blocks of
+ * (z B - A) are computed in float64 and rounded to float32, the sweeps run in
+ * complex float32, and the float64 residual r = R - (z B - A) X drives
+ * corrections X += solve32(r) until every column j satisfies
+ *   ||r_j||_2 <= 1e-12 (||R_j||_2 + |z| ||B X_j||_2 + ||A X_j||_2),
+ * at most 10 corrections.  (The bound is relative to the terms r is formed
+ * from, so float64 rounding never keeps it out of reach.)  Arguments as
+ * feast_shifted_solve; *steps (host, may be NULL) receives the corrections
+ * made and *rel_res (host, may be NULL) the final worst ratio
+ * ||r_j|| / (||R_j|| + |z| ||B X_j|| + ||A X_j||).  Returns 5 (outputs
+ * written) when the bound was not reached.
+ */
+int feast_shifted_solve_mixed(feast_ctx *ctx, const feast_bt_matrix *AB, double z_re,
+                              double z_im, int32_t m, const double *R, double *X_re,
+                              double *X_im, int32_t *steps, double *rel_res);
+
+/*
  * One contour integration (Fig. 2 step 2, eq. 15 with RHS B Y):
  * Q = -sum_e (w_e/2) Re{ r e^{i theta_e} (Z_e B - A)^{-1} B Y }.
  * Y, Q (dev) [N][M0].
  */
 int feast_filter(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double emax,
                  int32_t M0, int32_t Ne, const double *Y, double *Q);
+
+/*
+ * The same contour integration with the mixed-precision shifted solves of
+ * feast_shifted_solve_mixed (all Ne systems refined together; *steps and
+ * *rel_res as there, over all nodes).  Returns 5 (Q written) when the
+ * refinement bound was not reached.
+ */
+int feast_filter_mixed(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double emax,
+                       int32_t M0, int32_t Ne, const double *Y, double *Q, int32_t *steps,
+                       double *rel_res);
 
 /*
  * Projection (eq. 7): A_Q = Q^T A Q and B_Q = Q^T B Q, symmetrised.
@@ -186,7 +222,8 @@ int feast_reduced_eig(feast_ctx *ctx, int32_t M0, const double *AQ, const double
  * string), the summed event time in milliseconds and the number of launches;
  * with k < 0 it returns the number of classes.  Classes: factor,
  * forward_sweep, back_sweep, bt_multiply, sum_nodes, projection, reduced_eig,
- * ritz_gemm, residual, layout.
+ * ritz_gemm, residual, layout, round_factors, forward_sweep32, back_sweep32,
+ * refine_residual (the last four with precision 1 only).
  */
 int feast_timing(feast_ctx *ctx, int32_t enable);
 int feast_timing_read(feast_ctx *ctx, int32_t kind, const char **name, double *total_ms,

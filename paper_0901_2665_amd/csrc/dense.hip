@@ -364,6 +364,140 @@ __global__ __launch_bounds__(kCellThreads) void cell_residual_kernel(
   }
 }
 
+// Float64 residuals of the shifted systems for the mixed-precision solves:
+// r_e = R - (Z_e B - A) x_e with x_e = xr + i xi, in two passes over the
+// planes of x_e so that each pass is one cell loop over A and B:
+//   pass 0:  re = R + A xr - zr B xr,   im = -zi B xr
+//   pass 1:  re += zi B xi,             im += A xi - zr B xi
+// Node e = blockIdx.y.  Per column and group, pass P writes the sums
+// partial[e][g][3 P + q][ld]: q = 0 |A x_P|^2, q = 1 |B x_P|^2 and q = 2
+// R^2 (pass 0) or |r_e|^2 (pass 1), with x_0 = xr, x_1 = xi.
+constexpr int kShiftSums = 6;
+
+template <int BP, int PASS>
+__global__ __launch_bounds__(kCellThreads) void cell_shift_residual_kernel(
+    const double *Ad, const double *Au, const double *Bd, const double *Bu, int nc, int b,
+    const double *X, const double *R, int ld, size_t plane, Shifts sh, double *Rout,
+    double *partial) {
+  __shared__ CellLds<BP, 2> s;
+  constexpr int NR = BP / 16;
+  const int nct = ld / 16;
+  const int l = lane_id(), w = wave_id();
+  const int e = blockIdx.y;
+  const double zr = sh.zre[e], zi = sh.zim[e];
+  const double *V = X + (2 * e + PASS) * plane;
+  double *Ore = Rout + 2 * e * plane;
+  double *Oim = Ore + plane;
+  double sums[kCellTiles][3];
+#pragma unroll
+  for (int i = 0; i < kCellTiles; ++i) sums[i][0] = sums[i][1] = sums[i][2] = 0.0;
+  const double *Ds[2] = {Ad, Bd}, *Us[2] = {Au, Bu};
+  cell_loop<BP, 2>(s, Ds, Us, nc, b, V, ld, [&](int c, d4 (&acc)[2][kCellTiles]) {
+#pragma unroll
+    for (int i = 0; i < kCellTiles; ++i) {
+      const int t = w + i * kCellWaves;
+      if (t < NR * nct) {
+        const int col = (t / NR) * 16 + acc_col(l);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const size_t idx = ((size_t)c * BP + (t % NR) * 16 + acc_row(l, r)) * ld + col;
+          const double a = acc[0][i][r], bx = acc[1][i][r];
+          double re, im;
+          if (PASS == 0) {
+            const double rv = R[idx];
+            re = rv + a - zr * bx;
+            im = -zi * bx;
+            sums[i][2] += rv * rv;
+          } else {
+            re = Ore[idx] + zi * bx;
+            im = Oim[idx] + a - zr * bx;
+            sums[i][2] += re * re + im * im;
+          }
+          sums[i][0] += a * a;
+          sums[i][1] += bx * bx;
+          Ore[idx] = re;
+          Oim[idx] = im;
+        }
+      }
+    }
+  });
+  // lanes l, l+16, l+32, l+48 hold the same column: fold them, then the waves
+  // of equal column tile through LDS in wave order
+#pragma unroll
+  for (int i = 0; i < kCellTiles; ++i)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      double v = sums[i][q];
+      v += __shfl_xor(v, 16);
+      v += __shfl_xor(v, 32);
+      sums[i][q] = v;
+    }
+  double *red = s.r0;  // [3][tile t = w + i kCellWaves][16]
+  constexpr int NT = kCellWaves * kCellTiles;
+  __syncthreads();
+  if (l < 16)
+#pragma unroll
+    for (int i = 0; i < kCellTiles; ++i)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) red[(q * NT + i * kCellWaves + w) * 16 + l] = sums[i][q];
+  __syncthreads();
+  const int tid = threadIdx.x;
+  if (tid < ld) {
+    const int ct = tid / 16, lane = tid % 16;
+    double tot[3] = {0.0, 0.0, 0.0};
+    for (int t = ct * NR; t < (ct + 1) * NR; ++t)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) tot[q] += red[(q * NT + t) * 16 + lane];
+    double *out = partial + (((size_t)e * gridDim.x + blockIdx.x) * kShiftSums + 3 * PASS) * ld;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) out[q * ld + tid] = tot[q];
+  }
+}
+
+// worst = max over nodes e < Ne and columns j < m0 of
+//   ||r_j|| / (||R_j|| + |Z_e| ||B x_j|| + ||A x_j||)   (2-norms),
+// the residual relative to the size of the terms it is computed from (one
+// workgroup; group sums added in group order).
+__global__ __launch_bounds__(256) void shift_residual_reduce_kernel(const double *partial,
+                                                                    int groups, int ld, int m0,
+                                                                    int Ne, Shifts sh,
+                                                                    double *worst) {
+  __shared__ double red[256];
+  double mx = 0.0;
+  for (int idx = threadIdx.x; idx < Ne * m0; idx += 256) {
+    const int e = idx / m0, j = idx % m0;
+    double t[kShiftSums] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int g = 0; g < groups; ++g)
+#pragma unroll
+      for (int q = 0; q < kShiftSums; ++q)
+        t[q] += partial[(((size_t)e * groups + g) * kShiftSums + q) * ld + j];
+    const double za = sqrt(sh.zre[e] * sh.zre[e] + sh.zim[e] * sh.zim[e]);
+    const double den = sqrt(t[2]) + za * sqrt(t[1] + t[4]) + sqrt(t[0] + t[3]);
+    const double num = sqrt(t[5]);
+    const double q = den > 0.0 ? num / den : (num > 0.0 ? INFINITY : 0.0);
+    mx = (q == q) ? fmax(mx, q) : INFINITY;  // a non-finite iterate never passes
+  }
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *worst = red[0];
+}
+
+// Q = sum_e (kr_e xr_e - ki_e xi_e), nodes in order.
+__global__ void sum_nodes_complex_kernel(Shifts sh, int Ne, const double *X, size_t plane,
+                                         double *Q) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < plane;
+       i += (size_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int e = 0; e < Ne; ++e)
+      s += sh.kre[e] * X[2 * e * plane + i] - sh.kim[e] * X[(2 * e + 1) * plane + i];
+    Q[i] = s;
+  }
+}
+
 __global__ void sum_nodes_kernel(const double *P, int Ne, size_t count, double *Q) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count;
        i += (size_t)gridDim.x * blockDim.x) {
@@ -569,6 +703,49 @@ hipError_t launch_cell_residuals(const Pencil &p, const double *X, int ld, const
     case 64: return cell_residual_bp<64>(p, X, ld, lam, m0, emin, emax, partial, res, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+size_t shift_residual_partial_doubles(int nc, int ld, int Ne) {
+  return (size_t)cell_groups(nc) * ld * Ne * kShiftSums;
+}
+
+template <int BP>
+hipError_t shift_residual_bp(const Pencil &p, const Shifts &s, int Ne, const double *X,
+                             const double *R, int ld, int m0, double *Rout, double *partial,
+                             double *worst, hipStream_t st) {
+  const int G = cell_groups(p.nc);
+  const size_t plane = (size_t)p.nc * p.bp * ld;
+  const dim3 grid(G, Ne);
+  hipLaunchKernelGGL((cell_shift_residual_kernel<BP, 0>), grid, dim3(kCellThreads), 0, st, p.Ad,
+                     p.Au, p.Bd, p.Bu, p.nc, p.b, X, R, ld, plane, s, Rout, partial);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL((cell_shift_residual_kernel<BP, 1>), grid, dim3(kCellThreads), 0, st, p.Ad,
+                     p.Au, p.Bd, p.Bu, p.nc, p.b, X, R, ld, plane, s, Rout, partial);
+  if ((err = hipGetLastError()) != hipSuccess) return err;
+  hipLaunchKernelGGL(shift_residual_reduce_kernel, dim3(1), dim3(256), 0, st,
+                     (const double *)partial, G, ld, m0, Ne, s, worst);
+  return hipGetLastError();
+}
+
+hipError_t launch_shift_residuals(const Pencil &p, const Shifts &s, int Ne, const double *X,
+                                  const double *R, int ld, int m0, double *Rout, double *partial,
+                                  double *worst, hipStream_t st) {
+  if (ld % 16 != 0 || ld > 128 || Ne < 1 || Ne > kMaxNe) return hipErrorInvalidValue;
+  switch (p.bp) {
+    case 16: return shift_residual_bp<16>(p, s, Ne, X, R, ld, m0, Rout, partial, worst, st);
+    case 32: return shift_residual_bp<32>(p, s, Ne, X, R, ld, m0, Rout, partial, worst, st);
+    case 48: return shift_residual_bp<48>(p, s, Ne, X, R, ld, m0, Rout, partial, worst, st);
+    case 64: return shift_residual_bp<64>(p, s, Ne, X, R, ld, m0, Rout, partial, worst, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_sum_nodes_complex(const Shifts &s, int Ne, const double *X, size_t plane,
+                                    double *Q, hipStream_t st) {
+  hipLaunchKernelGGL(sum_nodes_complex_kernel, dim3(grid_for(plane, 256)), dim3(256), 0, st, s,
+                     Ne, X, plane, Q);
+  return hipGetLastError();
 }
 
 }  // namespace feast

@@ -29,7 +29,8 @@ struct Buf {
 
 enum Slot {
   S_SINV, S_W, S_WT, S_TW, S_G, S_TV, S_Y, S_R, S_P, S_Q, S_X, S_GRAMP, S_AQ, S_BQ,
-  S_EPS, S_PHI, S_RRS, S_FLAG, S_RESP, S_RES, S_PERM, S_T0, S_T1, S_FWORK, S_CHAINS, S_COUNT
+  S_EPS, S_PHI, S_RRS, S_FLAG, S_RESP, S_RES, S_PERM, S_T0, S_T1, S_FWORK, S_CHAINS,
+  S_SINV32, S_W32, S_WT32, S_G32, S_TV32, S_XC, S_RC, S_RPART, S_WORST, S_COUNT
 };
 
 }  // namespace
@@ -37,10 +38,12 @@ enum Slot {
 namespace {
 // Kernel classes timed by feast_timing / feast_timing_read.
 enum Kind { K_FACTOR, K_FORWARD, K_BACK, K_BTMUL, K_SUM, K_GRAM, K_RR, K_RITZ, K_RESID,
-            K_LAYOUT, K_COUNT };
-const char *kKindNames[K_COUNT] = {"factor",      "forward_sweep", "back_sweep", "bt_multiply",
-                                   "sum_nodes",   "projection",          "reduced_eig", "ritz_gemm",
-                                   "residual",    "layout"};
+            K_LAYOUT, K_ROUND, K_FWD32, K_BACK32, K_REFRES, K_COUNT };
+const char *kKindNames[K_COUNT] = {"factor",        "forward_sweep",   "back_sweep",
+                                   "bt_multiply",   "sum_nodes",       "projection",
+                                   "reduced_eig",   "ritz_gemm",       "residual",
+                                   "layout",        "round_factors",   "forward_sweep32",
+                                   "back_sweep32",  "refine_residual"};
 struct Timing {
   bool on = false;
   std::vector<hipEvent_t> pool;
@@ -254,6 +257,74 @@ hipError_t run_factor(feast_ctx *ctx, const Work &wk, const Shifts &s) {
                        ctx->stream);
 }
 
+// ---- mixed precision: float32 factors and sweeps, float64 refinement ----
+
+// Refinement stops when every column j of every node has
+//   ||R_j - (Z_e B - A) x_j||_2 <= kRefineTol (||R_j|| + |Z_e| ||B x_j|| + ||A x_j||),
+// i.e. a residual 1e-12 of the size of the terms it is formed from: float64
+// rounding in forming it is about 1e-16 of that size, so the test is
+// reachable however ill-conditioned Z_e B - A is (a bound relative to ||R_j||
+// alone is not: float64 solves themselves miss it once cond(Z_e B - A) u_64
+// exceeds it).
+constexpr double kRefineTol = 1e-12;
+constexpr int kMaxRefine = 10;  // correction solves per contour integration
+
+struct Mixed {
+  Factors32 f;
+  SolveBufs32 sb;
+  double *xc;      // [Ne][2][rows][m0p] iterates
+  double *rc;      // [Ne][2][rows][m0p] residuals
+  double *part;    // shift_residual_partial_doubles
+  double *worst;   // one double
+  size_t plane;
+};
+
+int prepare_mixed(feast_ctx *ctx, const Work &wk, Mixed &mx) {
+  const size_t blk = 2 * (size_t)wk.p.bp * wk.p.bp;
+  const size_t nf = (size_t)wk.Ne * wk.p.nc * blk;
+  mx.f.m = wk.f.m;
+  mx.plane = wk.rows * wk.m0p;
+  HIPCHK(ensure_t(ctx, S_SINV32, nf, &mx.f.Sinv));
+  HIPCHK(ensure_t(ctx, S_W32, nf, &mx.f.W));
+  HIPCHK(ensure_t(ctx, S_WT32, nf, &mx.f.WT));
+  HIPCHK(ensure_t(ctx, S_G32, (size_t)wk.Ne * wk.rows * wk.m0p * 2, &mx.sb.G));
+  HIPCHK(ensure_t(ctx, S_TV32, (size_t)wk.Ne * (wk.m0p / kTile) * 4 * wk.p.bp * kTile, &mx.sb.TV));
+  HIPCHK(ensure_t(ctx, S_XC, (size_t)wk.Ne * 2 * mx.plane, &mx.xc));
+  HIPCHK(ensure_t(ctx, S_RC, (size_t)wk.Ne * 2 * mx.plane, &mx.rc));
+  HIPCHK(ensure_t(ctx, S_RPART, shift_residual_partial_doubles(wk.p.nc, wk.m0p, wk.Ne), &mx.part));
+  HIPCHK(ensure_t(ctx, S_WORST, 1, &mx.worst));
+  return 0;
+}
+
+// x_e = (Z_e B - A)^{-1} R for every node: a float32 solve, then float64
+// residuals and float32 corrections until every column passes the kRefineTol
+// test (or kMaxRefine corrections).  R: padded real right-hand side.  Returns
+// the corrections made in *steps and the final worst residual ratio in
+// *worst.
+int mixed_solve(feast_ctx *ctx, const Work &wk, const Mixed &mx, const Shifts &s, const double *R,
+                int m0, int *steps, double *worst) {
+  hipStream_t sm = ctx->stream;
+  const Pencil &p = wk.p;
+  TIMED(K_FWD32, launch_sweeps32(p, wk.Ne, mx.f, mx.sb, R, 0, 0, wk.m0p, mx.xc, 0, 1, sm));
+  TIMED(K_BACK32, launch_sweeps32(p, wk.Ne, mx.f, mx.sb, R, 0, 0, wk.m0p, mx.xc, 0, 2, sm));
+  double *h_worst = ctx->h_eps + 3 * kMaxM0;
+  *steps = 0;
+  while (true) {
+    TIMED(K_REFRES, launch_shift_residuals(p, s, wk.Ne, mx.xc, R, wk.m0p, m0, mx.rc, mx.part,
+                                           mx.worst, sm));
+    HIPCHK(hipMemcpyAsync(h_worst, mx.worst, sizeof(double), hipMemcpyDeviceToHost, sm));
+    HIPCHK(hipStreamSynchronize(sm));
+    *worst = *h_worst;
+    if (*worst <= kRefineTol || *steps >= kMaxRefine) break;
+    TIMED(K_FWD32, launch_sweeps32(p, wk.Ne, mx.f, mx.sb, mx.rc, 2 * mx.plane, 1, wk.m0p, mx.xc,
+                                   1, 1, sm));
+    TIMED(K_BACK32, launch_sweeps32(p, wk.Ne, mx.f, mx.sb, mx.rc, 2 * mx.plane, 1, wk.m0p, mx.xc,
+                                    1, 2, sm));
+    ++*steps;
+  }
+  return 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -312,6 +383,7 @@ const char *feast_strerror(int status) {
     case 2: return "B_Q not positive definite; reduced problem solved on its range";
     case 3: return "no eigenvalue in the interval";
     case 4: return "subspace too small: M = M0";
+    case 5: return "mixed-precision refinement stopped above its tolerance";
     default: return status <= -100 ? "HIP runtime error" : "unknown status";
   }
 }
@@ -415,6 +487,84 @@ int feast_shifted_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double z_re, 
   return 0;
 }
 
+int feast_shifted_solve_mixed(feast_ctx *ctx, const feast_bt_matrix *AB, double z_re,
+                              double z_im, int32_t m, const double *R, double *X_re,
+                              double *X_im, int32_t *steps, double *rel_res) {
+  if (!ctx || !R || !X_re || !X_im) return -5;
+  int st = validate_matrix(AB);
+  if (st) return st;
+  if (m < 1 || m > kMaxM0) return -3;
+  if (!(z_im > 0.0) || !std::isfinite(z_re) || !std::isfinite(z_im)) return -2;
+  HIPCHK(hipSetDevice(ctx->device));
+  Pencil p = make_pencil(AB);
+  const int mp = round16(m);
+  Work wk;
+  st = prepare_factor(ctx, p, 1, mp, choose_parts(p.nc, 1, 0), wk);
+  if (st) return st;
+  Mixed mx;
+  st = prepare_mixed(ctx, wk, mx);
+  if (st) return st;
+  Shifts s;
+  std::memset(&s, 0, sizeof(s));
+  s.zre[0] = z_re;
+  s.zim[0] = z_im;
+  double *rin;
+  HIPCHK(ensure_t(ctx, S_R, wk.rows * mp, &rin));
+  HIPCHK(run_factor(ctx, wk, s));
+  HIPCHK(launch_round_factors(p, 1, wk.f, mx.f, ctx->stream));
+  HIPCHK(launch_pack(R, p.nc, p.b, p.bp, m, mp, rin, ctx->stream));
+  int k = 0;
+  double worst = 0.0;
+  st = mixed_solve(ctx, wk, mx, s, rin, m, &k, &worst);
+  if (st) return st;
+  HIPCHK(launch_unpack(mx.xc, p.nc, p.b, p.bp, m, mp, nullptr, X_re, ctx->stream));
+  HIPCHK(launch_unpack(mx.xc + mx.plane, p.nc, p.b, p.bp, m, mp, nullptr, X_im, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (steps) *steps = k;
+  if (rel_res) *rel_res = worst;
+  return worst <= kRefineTol ? 0 : 5;
+}
+
+int feast_filter_mixed(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double emax,
+                       int32_t M0, int32_t Ne, const double *Y, double *Q, int32_t *steps,
+                       double *rel_res) {
+  if (!ctx || !Y || !Q) return -5;
+  int st = validate_matrix(AB);
+  if (st) return st;
+  if (!(emin < emax) || !std::isfinite(emin) || !std::isfinite(emax)) return -2;
+  if (M0 < 1 || M0 > kMaxM0 || M0 > AB->nc * AB->b) return -3;
+  if (Ne < 1 || Ne > kMaxNe) return -4;
+  HIPCHK(hipSetDevice(ctx->device));
+  Pencil p = make_pencil(AB);
+  const int mp = round16(M0);
+  Work wk;
+  st = prepare_factor(ctx, p, Ne, mp, choose_parts(p.nc, Ne, 0), wk);
+  if (st) return st;
+  Mixed mx;
+  st = prepare_mixed(ctx, wk, mx);
+  if (st) return st;
+  Shifts s;
+  make_shifts(Ne, emin, emax, s);
+  double *y, *r, *q;
+  HIPCHK(ensure_t(ctx, S_Y, wk.rows * mp, &y));
+  HIPCHK(ensure_t(ctx, S_R, wk.rows * mp, &r));
+  HIPCHK(ensure_t(ctx, S_Q, wk.rows * mp, &q));
+  HIPCHK(run_factor(ctx, wk, s));
+  HIPCHK(launch_round_factors(p, Ne, wk.f, mx.f, ctx->stream));
+  HIPCHK(launch_pack(Y, p.nc, p.b, p.bp, M0, mp, y, ctx->stream));
+  HIPCHK(launch_cell_apply(p, 1, y, mp, r, ctx->stream));
+  int k = 0;
+  double worst = 0.0;
+  st = mixed_solve(ctx, wk, mx, s, r, M0, &k, &worst);
+  if (st) return st;
+  HIPCHK(launch_sum_nodes_complex(s, Ne, mx.xc, mx.plane, q, ctx->stream));
+  HIPCHK(launch_unpack(q, p.nc, p.b, p.bp, M0, mp, nullptr, Q, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (steps) *steps = k;
+  if (rel_res) *rel_res = worst;
+  return worst <= kRefineTol ? 0 : 5;
+}
+
 int feast_filter(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double emax,
                  int32_t M0, int32_t Ne, const double *Y, double *Q) {
   if (!ctx || !Y || !Q) return -5;
@@ -495,7 +645,9 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
   feast_default_opts(&o);
   if (opts) o = *opts;
   if (!o.Y0) return -5;
-  if (!(o.tol > 0.0) || o.max_loops < 1 || o.precision != 0 || o.partitions < 0) return -7;
+  if (!(o.tol > 0.0) || o.max_loops < 1 || o.precision < 0 || o.precision > 1 ||
+      o.partitions < 0)
+    return -7;
   HIPCHK(hipSetDevice(ctx->device));
   hipStream_t sm = ctx->stream;
 
@@ -532,6 +684,13 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
 
   // factor every shifted matrix once (Sec. V, parallelism (ii))
   TIMED(K_FACTOR, run_factor(ctx, wk, s));
+  const bool mixed = o.precision == 1;
+  Mixed mx;
+  if (mixed) {
+    st = prepare_mixed(ctx, wk, mx);
+    if (st) return st;
+    TIMED(K_ROUND, launch_round_factors(p, Ne, wk.f, mx.f, sm));
+  }
   TIMED(K_LAYOUT, launch_pack(o.Y0, p.nc, p.b, p.bp, M0, mp, y, sm));
 
   std::vector<double> traces;
@@ -540,15 +699,27 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
   bool converged = false;
   int fallback = 0;
   int rr_sweeps = 0;
+  int refine_steps = 0;
+  double solve_res = 0.0;
   double *h_eps = ctx->h_eps;
   double *h_res = ctx->h_eps + kMaxM0;
   const double res_gate = std::sqrt(o.tol);
   std::vector<char> is_counted(M0, 0);
   for (int k = 1; k <= o.max_loops; ++k) {
     TIMED(K_BTMUL, launch_cell_apply(p, 1, y, mp, rr, sm));                  // R = B Y
-    TIMED(K_FORWARD, launch_sweeps(p, s, Ne, wk.f, wk.sb, rr, mp, pp, 1, sm)); // Q_e ...
-    TIMED(K_BACK, launch_sweeps(p, s, Ne, wk.f, wk.sb, rr, mp, pp, 2, sm));    // ... weighted
-    TIMED(K_SUM, launch_sum_nodes(pp, Ne, rows * mp, q, sm));                // Q (eq. 15)
+    if (mixed) {  // Q_e by refined float32 solves, then Q (eq. 15)
+      int steps = 0;
+      double worst = 0.0;
+      st = mixed_solve(ctx, wk, mx, s, rr, M0, &steps, &worst);
+      if (st) return st;
+      refine_steps += steps;
+      solve_res = std::max(solve_res, worst);
+      TIMED(K_SUM, launch_sum_nodes_complex(s, Ne, mx.xc, mx.plane, q, sm));
+    } else {
+      TIMED(K_FORWARD, launch_sweeps(p, s, Ne, wk.f, wk.sb, rr, mp, pp, 1, sm));  // Q_e ...
+      TIMED(K_BACK, launch_sweeps(p, s, Ne, wk.f, wk.sb, rr, mp, pp, 2, sm));     // ... weighted
+      TIMED(K_SUM, launch_sum_nodes(pp, Ne, rows * mp, q, sm));                 // Q (eq. 15)
+    }
     TIMED(K_GRAM, launch_cell_project(p, q, mp, M0, gp, aq, bq, sm));      // A_Q, B_Q (eq. 7)
     TIMED(K_RR, launch_reduced_eig(aq, bq, M0, eps, phi, scr, flag, sm));   // eq. 6
     TIMED(K_RITZ, launch_gemm_qphi(q, rows, mp, M0, phi, x, sm));           // X = Q Phi (eq. 9)
@@ -610,6 +781,7 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
   int status;
   if (!converged) status = 1;
   else if (fallback) status = 2;
+  else if (mixed && !(solve_res <= kRefineTol)) status = 5;
   else if (M == M0) status = 4;
   else if (M == 0) status = 3;
   else status = 0;
@@ -623,6 +795,8 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
     info->status = status;
     info->fallback = fallback;
     info->rr_sweeps = rr_sweeps;
+    info->refine_steps = refine_steps;
+    info->solve_res = solve_res;
     for (size_t k = 0; k < traces.size() && k < 64; ++k) {
       info->trace_hist[k] = traces[k];
       info->count_hist[k] = counts[k];

@@ -68,6 +68,27 @@ hipError_t launch_sweeps_complex(const Pencil &p, const Shifts &s, const Factors
                                  const SolveBufs &sb, const double *R, int m0p,
                                  double *Xre, double *Xim, hipStream_t st);
 
+// Mixed precision (sweep32.hip): the factor blocks rounded to float32 in
+// the layout of the float32 sweeps, and the float32 sweeps for a complex
+// right-hand side per node.
+struct Factors32 {
+  float *Sinv, *W, *WT;  // [Ne][nc][2][bp][bp]
+  int m;                 // twist split
+};
+struct SolveBufs32 {
+  float *G;   // [Ne][ntiles][nc][2][bp][8]
+  float *TV;  // [Ne][ntiles][2][2][bp][8]
+};
+hipError_t launch_round_factors(const Pencil &p, int Ne, const Factors &f, const Factors32 &g,
+                                hipStream_t st);
+// Right-hand side of node e: real plane at R + e * rnode (padded
+// [nc][bp][m0p], float64), imaginary plane one plane (nc*bp*m0p doubles)
+// further when rcomplex.  X: node e's iterate, real plane at X + 2 e plane,
+// imaginary plane after it; accumulate: X += solution, else X = solution.
+hipError_t launch_sweeps32(const Pencil &p, int Ne, const Factors32 &f, const SolveBufs32 &sb,
+                           const double *R, size_t rnode, int rcomplex, int m0p, double *X,
+                           int accumulate, int part, hipStream_t st);
+
 // Dense helpers (dense.hip).
 hipError_t launch_pack(const double *src, int nc, int b, int bp, int m, int ldd,
                        double *dst, hipStream_t st);
@@ -81,9 +102,6 @@ hipError_t launch_check_finite(const double *x, size_t count, int *flag, hipStre
 hipError_t launch_gather(const double *src, const int *perm, int m, double *dst,
                          hipStream_t st);
 
-// Reduced eigenproblem (rr.hip): one workgroup.
-// scratch: reduced_eig_scratch_doubles().  eps, Phi outputs; flag[0] =
-// fallback, flag[1] = Jacobi sweeps, flag[2] = sweeps of the fallback.
 // Per-cell products (one workgroup walks a strided set of cells; ld <= 128,
 // a multiple of 16).  partial: cell_partial_doubles(nc, ld) doubles, which
 // also covers the 3 ld per group of the residual variant.
@@ -96,6 +114,23 @@ hipError_t launch_cell_residuals(const Pencil &p, const double *X, int ld, const
                                  int m0, double emin, double emax, double *partial, double *res,
                                  hipStream_t st);
 
+// Float64 residuals of the shifted systems for the mixed-precision solves:
+// Rout_e = R - (Z_e B - A) x_e for every node (X and Rout: node e's real
+// plane at + 2 e plane, imaginary plane after it; R real, shared), and
+// worst = max over nodes and columns j < m0 of ||r_j|| / (||R_j|| +
+// |Z_e| ||B x_j|| + ||A x_j||) in 2-norms (one double).  partial:
+// shift_residual_partial_doubles().
+size_t shift_residual_partial_doubles(int nc, int ld, int Ne);
+hipError_t launch_shift_residuals(const Pencil &p, const Shifts &s, int Ne, const double *X,
+                                  const double *R, int ld, int m0, double *Rout, double *partial,
+                                  double *worst, hipStream_t st);
+// Q = sum_e Re(kappa_e x_e) over the complex iterates (layout as above).
+hipError_t launch_sum_nodes_complex(const Shifts &s, int Ne, const double *X, size_t plane,
+                                    double *Q, hipStream_t st);
+
+// Reduced eigenproblem (rr.hip): one workgroup.
+// scratch: reduced_eig_scratch_doubles().  eps, Phi outputs; flag[0] =
+// fallback, flag[1] = Jacobi sweeps, flag[2] = sweeps of the fallback.
 size_t reduced_eig_scratch_doubles();
 hipError_t launch_reduced_eig(const double *AQ, const double *BQ, int n, double *eps,
                               double *Phi, double *scratch, int *flag, hipStream_t st);

@@ -44,13 +44,14 @@ class Info(ctypes.Structure):
                 ("max_res", ctypes.c_double), ("status", ctypes.c_int32),
                 ("fallback", ctypes.c_int32),
                 ("trace_hist", ctypes.c_double * 64), ("count_hist", ctypes.c_int32 * 64),
-                ("rr_sweeps", ctypes.c_int32)]
+                ("rr_sweeps", ctypes.c_int32), ("refine_steps", ctypes.c_int32),
+                ("solve_res", ctypes.c_double)]
 
 
 EXPORTED = ["feast_default_opts", "feast_init", "feast_destroy", "feast_strerror",
             "feast_solve", "feast_contour", "feast_bt_multiply", "feast_shifted_solve",
             "feast_filter", "feast_project", "feast_reduced_eig", "feast_timing",
-            "feast_timing_read"]
+            "feast_timing_read", "feast_shifted_solve_mixed", "feast_filter_mixed"]
 
 
 def load_library(path: str = LIB_PATH):
@@ -74,6 +75,10 @@ def load_library(path: str = LIB_PATH):
     lib.feast_bt_multiply.argtypes = [P, ctypes.POINTER(BTMatrix), I32, I32, P, P]
     lib.feast_shifted_solve.argtypes = [P, ctypes.POINTER(BTMatrix), D, D, I32, P, P, P]
     lib.feast_filter.argtypes = [P, ctypes.POINTER(BTMatrix), D, D, I32, I32, P, P]
+    lib.feast_shifted_solve_mixed.argtypes = [P, ctypes.POINTER(BTMatrix), D, D, I32, P, P, P,
+                                              ctypes.POINTER(I32), ctypes.POINTER(D)]
+    lib.feast_filter_mixed.argtypes = [P, ctypes.POINTER(BTMatrix), D, D, I32, I32, P, P,
+                                       ctypes.POINTER(I32), ctypes.POINTER(D)]
     lib.feast_project.argtypes = [P, ctypes.POINTER(BTMatrix), I32, P, P, P]
     lib.feast_reduced_eig.argtypes = [P, I32, P, P, P, P, ctypes.POINTER(I32)]
     lib.feast_timing.argtypes = [P, I32]
@@ -112,6 +117,8 @@ class SolveResult:
     traces: list
     counts: list
     rr_sweeps: int = 0
+    refine_steps: int = 0  # precision 1: float32 correction solves, all loops
+    solve_res: float = 0.0  # precision 1: worst final relative residual of a shifted solve
 
 
 def _ptr(t):
@@ -174,7 +181,7 @@ class Context:
 
     def solve(self, p: Pencil, emin: float, emax: float, M0: int, Ne: int, Y0,
               tol: float = 1e-12, max_loops: int = 20, out=None,
-              partitions: int = 0) -> SolveResult:
+              partitions: int = 0, precision: int = 0) -> SolveResult:
         import torch
         dev = p.Ad.device
         if out is None:
@@ -183,7 +190,7 @@ class Context:
             res = torch.empty(M0, dtype=torch.float64, device=dev)
         else:
             lam, X, res = out
-        opts = Opts(tol, max_loops, 0, partitions, _ptr(Y0))
+        opts = Opts(tol, max_loops, precision, partitions, _ptr(Y0))
         info = Info()
         ab = p.struct()
         st = self.lib.feast_solve(self.handle, ctypes.byref(ab), emin, emax, M0, Ne,
@@ -193,7 +200,8 @@ class Context:
         n = min(info.loops, 64)
         return SolveResult(lam, X, res, info.M, info.loops, info.trace, info.trace_rel,
                            info.max_res, st, info.fallback, list(info.trace_hist[:n]),
-                           list(info.count_hist[:n]), info.rr_sweeps)
+                           list(info.count_hist[:n]), info.rr_sweeps, info.refine_steps,
+                           info.solve_res)
 
     def timing(self, enable: bool):
         """Start (clear) or stop hipEvent timing of the kernel classes."""
@@ -230,6 +238,30 @@ class Context:
                                           R.shape[1], _ptr(R), _ptr(xr), _ptr(xi))
         self._check(st, "feast_shifted_solve")
         return xr, xi
+
+    def shifted_solve_mixed(self, p: Pencil, z: complex, R):
+        """(X_re, X_im, corrections, worst relative residual, status 0 or 5)."""
+        import torch
+        xr, xi = torch.empty_like(R), torch.empty_like(R)
+        steps, rel = ctypes.c_int32(0), ctypes.c_double(0.0)
+        ab = p.struct()
+        st = self.lib.feast_shifted_solve_mixed(self.handle, ctypes.byref(ab), z.real, z.imag,
+                                                R.shape[1], _ptr(R), _ptr(xr), _ptr(xi),
+                                                ctypes.byref(steps), ctypes.byref(rel))
+        self._check(st, "feast_shifted_solve_mixed", warn_ok=True)
+        return xr, xi, steps.value, rel.value, st
+
+    def filter_mixed(self, p: Pencil, emin: float, emax: float, Ne: int, Y):
+        """(Q, corrections, worst relative residual, status 0 or 5)."""
+        import torch
+        Q = torch.empty_like(Y)
+        steps, rel = ctypes.c_int32(0), ctypes.c_double(0.0)
+        ab = p.struct()
+        st = self.lib.feast_filter_mixed(self.handle, ctypes.byref(ab), emin, emax, Y.shape[1],
+                                         Ne, _ptr(Y), _ptr(Q), ctypes.byref(steps),
+                                         ctypes.byref(rel))
+        self._check(st, "feast_filter_mixed", warn_ok=True)
+        return Q, steps.value, rel.value, st
 
     def filter(self, p: Pencil, emin: float, emax: float, Ne: int, Y):
         import torch

@@ -1,0 +1,185 @@
+"""GPU parity of the mixed-precision path (float32 factors and sweeps,
+float64 iterative refinement of every shifted solve) against the float64 CPU
+oracle.
+
+Tolerances follow from the refinement criterion: every column j of every
+shifted system M = z B - A ends with
+  ||r_j||_2 <= 1e-12 s_j,   s_j = ||R_j||_2 + |z| ||B x_j||_2 + ||A x_j||_2,
+so ||X - X*||_F <= 1e-12 ||s||_2 / sigma_min(M) for the exact solution X*,
+and the filter output Q = sum_e Re(kappa_e X_e) is off by at most the sum of
+|kappa_e| times that.  FEAST outputs are held to the same contract as the
+float64 path (same M, eigenvalues within 1e-10 relative, residuals <= 1e-9).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import feast_oracle as O
+from paper_0901_2665_amd import workloads as W
+from test_gpu_parity import GOLDEN, SHAPES, chain_small, check_against_oracle, dev, gpencil, host
+
+pytestmark = pytest.mark.gpu
+
+REFINE_TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU tests need a HIP device"
+    return _t
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    from paper_0901_2665_amd import feast as F
+    c = F.Context(0)
+    yield c
+    c.close()
+
+
+def sigma_min(p, z):
+    M = O.shifted_matrix(p, z).toarray()
+    return np.linalg.svd(M, compute_uv=False)[-1]
+
+
+def term_scale(p, z, X, R):
+    """Per column ||R_j|| + |z| ||B x_j|| + ||A x_j|| (the refinement's scale)."""
+    AX = O.bt_multiply(p.Ad, p.Au, X.real) + 1j * O.bt_multiply(p.Ad, p.Au, X.imag)
+    BX = O.bt_multiply(p.Bd, p.Bu, X.real) + 1j * O.bt_multiply(p.Bd, p.Bu, X.imag)
+    return (np.linalg.norm(R, axis=0) + abs(z) * np.linalg.norm(BX, axis=0) +
+            np.linalg.norm(AX, axis=0))
+
+
+@pytest.mark.parametrize("nc,b,m", SHAPES)
+def test_shifted_solve_mixed(ctx, torch, nc, b, m):
+    p = chain_small(nc, b, 200 + nc)
+    R = np.random.default_rng(7 * nc + b).standard_normal((p.n, m))
+    z = 0.37 + 0.05j
+    xr, xi, steps, rel, st = ctx.shifted_solve_mixed(gpencil(p), z, dev(torch, R))
+    assert st == 0 and rel <= REFINE_TOL
+    X = host(xr) + 1j * host(xi)
+    M = O.shifted_matrix(p, z)
+    scale = term_scale(p, z, X, R)
+    assert np.max(np.linalg.norm(R - M @ X, axis=0) / scale) <= 2 * REFINE_TOL
+    ref = O.shifted_solve(p, z, R)
+    bound = 2 * REFINE_TOL * np.linalg.norm(scale) / sigma_min(p, z)
+    assert np.linalg.norm(X - ref) <= bound + 1e-14 * np.linalg.norm(ref)
+
+
+def test_refinement_steps_grow_with_conditioning(ctx, torch):
+    # a shift closer to the spectrum needs at least as many corrections
+    p = chain_small(20, 40, 220)
+    R = np.random.default_rng(5).standard_normal((p.n, 16))
+    lam = O.bruteforce(p)[0]
+    c = 0.5 * (lam[400] + lam[401])
+    counts = []
+    for d in (1.0, 1e-2, 1e-4):
+        _, _, steps, rel, st = ctx.shifted_solve_mixed(gpencil(p), complex(c, d), dev(torch, R))
+        assert st == 0 and rel <= REFINE_TOL
+        counts.append(steps)
+    assert counts[0] >= 1
+    assert counts == sorted(counts)
+
+
+def test_refinement_stall_is_reported(ctx, torch):
+    # cond(z B - A) u_32 >> 1: float32 corrections cannot converge; the call
+    # stops after its correction limit with status 5 and the outputs written
+    p = W.dense_random_pencil(3, 8, 11)
+    lam = O.bruteforce(p)[0]
+    R = np.random.default_rng(2).standard_normal((p.n, 4))
+    xr, xi, steps, rel, st = ctx.shifted_solve_mixed(gpencil(p), complex(lam[10], 1e-10),
+                                                     dev(torch, R))
+    assert st == 5 and steps == 10
+    assert not rel <= REFINE_TOL
+
+
+@pytest.mark.parametrize("name_or_shape", ["chain800", (9, 16, 24, 4), (3, 3, 5, 16),
+                                           (13, 64, 40, 8)])
+def test_filter_mixed(ctx, torch, name_or_shape):
+    if isinstance(name_or_shape, str):
+        p, emin, emax, m0, ne, Y = W.make_workload(name_or_shape)
+    else:
+        nc, b, m0, ne = name_or_shape
+        p = chain_small(nc, b, 300 + nc)
+        lam = O.bruteforce(p)[0]
+        k0 = p.n // 3
+        emin, emax = 0.5 * (lam[k0 - 1] + lam[k0]), 0.5 * (lam[k0 + 3] + lam[k0 + 4])
+        Y = W.random_subspace(p.n, m0, nc)
+    Q, steps, rel, st = ctx.filter_mixed(gpencil(p), emin, emax, ne, dev(torch, Y))
+    assert st == 0 and rel <= REFINE_TOL
+    Q = host(Q)
+    ref = O.filter_apply(p, emin, emax, ne, Y)
+    ct = O.contour(emin, emax, ne)
+    R = O.bt_multiply(p.Bd, p.Bu, Y)
+    bound = 0.0
+    for z, k in zip(ct.Z, ct.kappa):
+        Xz = O.shifted_solve(p, z, R)
+        bound += abs(k) * 2 * REFINE_TOL * np.linalg.norm(term_scale(p, z, Xz, R)) / sigma_min(p, z)
+    err = np.linalg.norm(Q - ref)
+    assert err <= bound + 1e-13 * np.linalg.norm(ref)
+
+
+def check_mixed_info(r):
+    assert r.status == 0
+    assert r.solve_res <= REFINE_TOL
+    assert r.refine_steps >= r.loops  # at least one correction per integration
+
+
+def test_solve_mixed_chain800(ctx, torch):
+    p, emin, emax, m0, ne, Y0 = W.make_workload("chain800")
+    r = ctx.solve(gpencil(p), emin, emax, m0, ne, dev(torch, Y0), precision=1)
+    ref = O.feast(p, emin, emax, m0, ne, Y0)
+    check_mixed_info(r)
+    check_against_oracle(r, ref, p, emin, emax)
+
+
+@pytest.mark.parametrize("nc,b,seed,k0,m,extra", [(3, 4, 2, 3, 4, 3), (7, 16, 6, 30, 10, 8),
+                                                  (11, 20, 7, 60, 15, 9)])
+def test_solve_mixed_small(ctx, torch, nc, b, seed, k0, m, extra):
+    p = W.dense_random_pencil(nc, b, seed)
+    lam = O.bruteforce(p)[0]
+    emin, emax = 0.5 * (lam[k0 - 1] + lam[k0]), 0.5 * (lam[k0 + m - 1] + lam[k0 + m])
+    m0 = min(m + extra, p.n)
+    Y0 = W.random_subspace(p.n, m0, seed + 100)
+    r = ctx.solve(gpencil(p), emin, emax, m0, 8, dev(torch, Y0), tol=1e-13, max_loops=40,
+                  precision=1)
+    ref = O.feast(p, emin, emax, m0, 8, Y0, tol=1e-13, max_loops=40)
+    assert r.status == ref.status == 0
+    assert r.solve_res <= REFINE_TOL
+    check_against_oracle(r, ref, p, emin, emax)
+
+
+def test_solve_mixed_tb6400_golden(ctx, torch):
+    g = json.load(open(os.path.join(GOLDEN, "feast_tb6400.json")))
+    p, emin, emax, m0, ne, Y0 = W.make_workload("tb6400")
+    r = ctx.solve(gpencil(p), emin, emax, m0, ne, dev(torch, Y0), precision=1)
+    check_mixed_info(r)
+    assert r.M == g["M"] == 80
+    lam = host(r.lam)[:80]
+    assert np.max(np.abs(lam - np.array(g["lam"])) / np.abs(lam)) <= 1e-10
+    assert np.max(host(r.res)[:80]) <= 1e-9
+    assert abs(r.loops - g["loops"]) <= 1
+
+
+def test_solve_mixed_tb128k_full_size(ctx, torch):
+    """The full-size workload with mixed-precision shifted solves, as the
+    benchmark's mixed mode times it: eigenvalues against the stored float64
+    oracle result and residuals recomputed on the host for a sample."""
+    g = json.load(open(os.path.join(GOLDEN, "feast_tb128k.json")))
+    p, emin, emax, m0, ne, Y0 = W.make_workload("tb128k")
+    r = ctx.solve(gpencil(p), emin, emax, m0, ne, dev(torch, Y0), precision=1)
+    check_mixed_info(r)
+    assert r.M == g["M"] == 80
+    lam = host(r.lam)[:80]
+    assert np.max(np.abs(lam - np.array(g["lam"])) / np.abs(lam)) <= 1e-10
+    res = host(r.res)
+    assert np.max(res[:80]) <= 1e-9
+    assert abs(r.loops - g["loops"]) <= 1
+    cols = [0, 19, 39, 59, 79]
+    X = host(r.X)[:, cols]
+    res_host = O.residuals(p, lam[cols], X, emin, emax)
+    assert np.max(res_host) <= 1e-9
+    assert np.allclose(res_host, res[cols], rtol=1e-3, atol=1e-14)

@@ -23,7 +23,7 @@ constexpr int kThreads = 1024;
 constexpr int kMaxN = 128;
 
 struct RRShared {
-  double2 csn[kMaxN / 2];  // (cos, sin) of the rotation of each pair slot
+  double2 csn[2][kMaxN / 2];  // (cos, sin) of each pair slot, rounds of even / odd parity
   int rot;
   int fail;
   double norm;
@@ -44,13 +44,41 @@ __device__ __forceinline__ int rr_player(int s, int i, int nn) {
 
 constexpr int kMaxSweeps = 60;
 
+// Eigenvector layout: VT (LDS, row stride kVTld, rows 16-byte aligned)
+// holds VT[c][r] = V[r][c].
+constexpr int kVTld = kMaxN + 2;
+
+// v from lane l+1 (wave_shl:1) and from lane l-1 (wave_shr:1), 64-bit;
+// a lane without a source keeps `edge`
+__device__ __forceinline__ double lane_next(double v, double edge) {
+  const u32x2 x = __builtin_bit_cast(u32x2, v), o = __builtin_bit_cast(u32x2, edge);
+  return __builtin_bit_cast(
+      double,
+      (u32x2){(unsigned)__builtin_amdgcn_update_dpp((int)o[0], (int)x[0], 0x130, 0xf, 0xf, false),
+              (unsigned)__builtin_amdgcn_update_dpp((int)o[1], (int)x[1], 0x130, 0xf, 0xf, false)});
+}
+__device__ __forceinline__ double lane_prev(double v, double edge) {
+  const u32x2 x = __builtin_bit_cast(u32x2, v), o = __builtin_bit_cast(u32x2, edge);
+  return __builtin_bit_cast(
+      double,
+      (u32x2){(unsigned)__builtin_amdgcn_update_dpp((int)o[0], (int)x[0], 0x138, 0xf, 0xf, false),
+              (unsigned)__builtin_amdgcn_update_dpp((int)o[1], (int)x[1], 0x138, 0xf, 0xf, false)});
+}
+
+
 // Cyclic Jacobi on the nn x nn symmetric matrix C (LDS, row stride ldc).
-// The rotations of every round are appended to rlog (global, 2 * nn/2
-// doubles a round: cosines then sines); the eigenvectors are rebuilt from
-// the log afterwards (replay_rotations), so a round touches only C.
+// The eigenvectors V = J_1 J_2 ... accumulate in registers while C is
+// rotated: a round rotates column pairs of V and every row of V evolves on
+// its own, so wave w keeps the rows [8w, 8w+8) of V (16 waves cover 128) and
+// lane a the two columns of pair slot a (the players at circle positions a
+// and nn-1-a).  After each round the players move one position along the
+// circle and their data with them: a lane takes its new top column from lane
+// a+1 and its new bottom column from lane a-1 (wavefront lane shifts), with
+// the turning points at lanes 0 and half-1.  On return sh.diag holds the
+// eigenvalues (diagonal of C) and VT (which overlays C) the eigenvectors.
 // Returns the number of sweeps that rotated (the final check sweep, which
 // rotates nothing, is not counted).
-__device__ int jacobi(double *C, int ldc, double *rlog, int nn, RRShared &sh) {
+__device__ int jacobi(double *C, int ldc, int nn, RRShared &sh) {
   const int tid = threadIdx.x;
   const int half = nn / 2;
   const double eps = 1.1102230246251565e-16;  // 2^-53
@@ -97,11 +125,59 @@ __device__ int jacobi(double *C, int ldc, double *rlog, int nn, RRShared &sh) {
   auto at = [&](int i, int j) -> double & {
     return i < j ? C[i * ldc + j] : C[j * ldc + i];
   };
+  const int lw = tid >> 6, la = tid & 63;
+  const int r0 = 8 * lw;
+  double top[8], bot[8];  // V[r0 + k][player at position la / nn-1-la]
+  {
+    const int pt = rr_player(0, la, nn), pb = rr_player(0, nn - 1 - la, nn);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      top[k] = (la < half && pt == r0 + k) ? 1.0 : 0.0;
+      bot[k] = (la < half && pb == r0 + k) ? 1.0 : 0.0;
+    }
+  }
+  // V <- V J of round position sp with rotations rv: columns (p, q) =
+  // (min, max) of slot la, x_p' = c x_p - s x_q, x_q' = s x_p + c x_q (in
+  // (top, bottom) order the sine flips sign when the top player is the larger
+  // index); then the players move one circle position (player 0 stays).
+  // Each round's update runs during the next round's rotation phase (its
+  // rotations stay in the other half of the double-buffered csn).
+  auto v_update = [&](int sp, const double2 *rv) {
+    const double2 r = rv[la < half ? la : 0];
+    const double c = la < half ? r.x : 1.0;
+    const int u = rr_player(sp, la, nn), v = rr_player(sp, nn - 1 - la, nn);
+    const double sg = la < half ? (u < v ? r.y : -r.y) : 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const double t = top[k], b = bot[k];
+      top[k] = c * t - sg * b;
+      bot[k] = sg * t + c * b;
+    }
+    if (half == 64) {  // the shifts' edge lanes are the turning points
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const double st = lane_next(top[k], bot[k]);  // lane 63 takes its own bottom
+        bot[k] = lane_prev(bot[k], st);               // lane 0 takes lane 1's top
+        top[k] = la == 0 ? top[k] : st;
+      }
+    } else if (nn > 2) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const double st = lane_next(top[k], bot[k]), sb = lane_prev(bot[k], st);
+        const double nt = la == 0 ? top[k] : (la == half - 1 ? bot[k] : st);
+        bot[k] = la == 0 ? st : sb;
+        top[k] = nt;
+      }
+    }
+  };
+  int g = 0;        // rounds done; csn[g & 1] holds the current round's rotations
+  int spend = -1;   // circle position of the round whose V update is pending
   int sweep = 0;
   for (; sweep < kMaxSweeps; ++sweep) {
     if (tid == 0) sh.rot = 0;
     __syncthreads();
     for (int s = 0; s < nn - 1; ++s) {
+      double2 *csn = sh.csn[g & 1];
       if (tid < half) {  // one wave: rotation of slot tid
         const int u = rr_player(s, tid, nn), v = rr_player(s, nn - 1 - tid, nn);
         const int p = u < v ? u : v, q = u < v ? v : u;
@@ -120,18 +196,16 @@ __device__ int jacobi(double *C, int ldc, double *rlog, int nn, RRShared &sh) {
         }
         const unsigned long long m = __ballot(rotate);
         if (tid == 0) sh.rot += __popcll(m);
-        sh.csn[tid] = double2{c, sgn};
-        double *lg = rlog + (size_t)(sweep * (nn - 1) + s) * 2 * half;
-        lg[tid] = c;
-        lg[half + tid] = sgn;
+        csn[tid] = double2{c, sgn};
       }
+      if (spend >= 0) v_update(spend, sh.csn[(g & 1) ^ 1]);
       __syncthreads();
       // C <- J^T C J on the thread's 2x2 blocks
 #pragma unroll
       for (int t = 0; t < kPer; ++t) {
         const int a = ba[t], bq = bb[t];
         if (a < 0) continue;
-        const double2 ra = sh.csn[a], rb = sh.csn[bq];
+        const double2 ra = csn[a], rb = csn[bq];
         const double ca = ra.x, sa = ra.y, cb = rb.x, sb = rb.y;
         int pa = rr_player(s, a, nn), qa = rr_player(s, nn - 1 - a, nn);
         if (pa > qa) { const int x = pa; pa = qa; qa = x; }
@@ -158,73 +232,30 @@ __device__ int jacobi(double *C, int ldc, double *rlog, int nn, RRShared &sh) {
         e22 = sa * y12 + ca * y22;
       }
       __syncthreads();
+      spend = s;
+      ++g;
     }
     const int rot = sh.rot;
     __syncthreads();
     if (rot == 0) break;
   }
+  if (spend >= 0) v_update(spend, sh.csn[(g & 1) ^ 1]);
+  // every sweep ends at circle position 0: lane la holds the players
+  // rr_player(0, la) and rr_player(0, nn-1-la)
+  if (tid < nn) sh.diag[tid] = C[tid * ldc + tid];
+  __syncthreads();
+  if (la < half && r0 < nn) {  // rows r0..r0+7 of every column: all of VT that is read
+    const int pt = rr_player(0, la, nn), pb = rr_player(0, nn - 1 - la, nn);
+    double2 *xt = reinterpret_cast<double2 *>(C + pt * kVTld + r0);
+    double2 *xb = reinterpret_cast<double2 *>(C + pb * kVTld + r0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      xt[k] = double2{top[2 * k], top[2 * k + 1]};
+      xb[k] = double2{bot[2 * k], bot[2 * k + 1]};
+    }
+  }
+  __syncthreads();
   return sweep;  // sweeps with at least one rotation (all of them if not converged)
-}
-
-// V = J_1 J_2 ... J_R for the logged rounds, V (LDS, row stride ldv) starts
-// as the identity.  A round rotates column pairs, so the rows of V evolve
-// independently: each wave owns nn/16 rows (eight lanes a row, each lane a
-// fixed set of pairs) and runs through all rounds without workgroup
-// barriers; LDS accesses of one wave are ordered by a wave-level fence.
-__device__ void replay_rotations(double *V, int ldv, const double *rlog, int rounds, int nn) {
-  const int tid = threadIdx.x;
-  const int half = nn / 2;
-  for (int idx = tid; idx < nn * nn; idx += kThreads)
-    V[(idx / nn) * ldv + idx % nn] = (idx / nn == idx % nn) ? 1.0 : 0.0;
-  __syncthreads();
-  const int w = tid >> 6, l = tid & 63;
-  const int rows_per_wave = (nn + 15) / 16;   // <= 8
-  const int row = w * rows_per_wave + (l >> 3);
-  const int j = l & 7;
-  const bool act = (l >> 3) < rows_per_wave && row < nn;
-  constexpr int PA = kMaxN / 16;  // pairs a lane handles (a = j, j + 8, ...)
-  double cn[PA], sn[PA];          // rotation of the next round, loaded ahead
-#pragma unroll
-  for (int t = 0; t < PA; ++t) {
-    const int a = j + 8 * t;
-    cn[t] = (rounds > 0 && a < half) ? rlog[a] : 1.0;
-    sn[t] = (rounds > 0 && a < half) ? rlog[half + a] : 0.0;
-  }
-  int s = 0;
-  for (int g = 0; g < rounds; ++g) {
-    double cc[PA], ss[PA];
-#pragma unroll
-    for (int t = 0; t < PA; ++t) {
-      cc[t] = cn[t];
-      ss[t] = sn[t];
-    }
-    if (g + 1 < rounds) {
-      const double *lg = rlog + (size_t)(g + 1) * 2 * half;
-#pragma unroll
-      for (int t = 0; t < PA; ++t) {
-        const int a = j + 8 * t;
-        cn[t] = a < half ? lg[a] : 1.0;
-        sn[t] = a < half ? lg[half + a] : 0.0;
-      }
-    }
-    if (act) {
-#pragma unroll
-      for (int t = 0; t < PA; ++t) {
-        const int a = j + 8 * t;
-        if (a < half && ss[t] != 0.0) {
-          const int u = rr_player(s, a, nn), v = rr_player(s, nn - 1 - a, nn);
-          const int p = u < v ? u : v, q = u < v ? v : u;
-          const double vp = V[row * ldv + p], vq = V[row * ldv + q];
-          V[row * ldv + p] = cc[t] * vp - ss[t] * vq;
-          V[row * ldv + q] = ss[t] * vp + cc[t] * vq;
-        }
-      }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    if (++s == nn - 1) s = 0;
-  }
-  __syncthreads();
 }
 
 // Dense product of the workgroup on the matrix cores, n <= 128:
@@ -251,7 +282,7 @@ __device__ __forceinline__ void wg_gemm(int nt, FA a, FB b, FO out) {
 __global__ __launch_bounds__(kThreads) void reduced_eig_kernel(const double *AQ, const double *BQ,
                                                                int n, double *eps, double *Phi,
                                                                double *scratch, int *flag) {
-  extern __shared__ double C[];
+  extern __shared__ __align__(16) double C[];  // nn x (nn + 1) matrix, or nn x kVTld VT
   __shared__ RRShared sh;
   const int tid = threadIdx.x;
   const int nn = n + (n & 1);
@@ -260,7 +291,6 @@ __global__ __launch_bounds__(kThreads) void reduced_eig_kernel(const double *AQ,
   double *T = scratch;                 // nn x nn whitening
   double *T1 = scratch + nn * nn;      // nn x nn product
   double *V = scratch + 2 * nn * nn;   // nn x nn eigenvectors of B_Q (fallback)
-  double *rlog = scratch + 3 * nn * nn;  // rotation log
 
   for (int idx = tid; idx < nn * nn; idx += kThreads) {
     const int i = idx / nn, j = idx % nn;
@@ -327,12 +357,9 @@ __global__ __launch_bounds__(kThreads) void reduced_eig_kernel(const double *AQ,
       C[i * ldc + j] = (i < n && j < n) ? BQ[i * n + j] : 0.0;
     }
     __syncthreads();
-    const int fsweeps = jacobi(C, ldc, rlog, nn, sh);
+    const int fsweeps = jacobi(C, ldc, nn, sh);
     if (tid == 0) flag[2] = fsweeps;
-    if (tid < nn) sh.diag[tid] = C[tid * ldc + tid];
-    __syncthreads();
-    replay_rotations(C, ldc, rlog, fsweeps * (nn - 1), nn);
-    for (int idx = tid; idx < nn * nn; idx += kThreads) V[idx] = C[(idx / nn) * ldc + idx % nn];
+    for (int idx = tid; idx < nn * nn; idx += kThreads) V[idx] = C[(idx % nn) * kVTld + idx / nn];
     __syncthreads();
     double mumax = 0.0;
     for (int i = 0; i < n; ++i) mumax = fmax(mumax, sh.diag[i]);
@@ -369,14 +396,11 @@ __global__ __launch_bounds__(kThreads) void reduced_eig_kernel(const double *AQ,
   }
   __syncthreads();
 
-  const int sweeps = jacobi(C, ldc, rlog, nn, sh);
+  const int sweeps = jacobi(C, ldc, nn, sh);
   if (tid == 0) flag[1] = sweeps;
 
   // ---- sort ascending, dropped directions (NaN) last ----
-  if (tid < nn) sh.diag[tid] = C[tid * ldc + tid];
-  __syncthreads();
-  double *VL = C;  // eigenvectors of C, rebuilt in LDS from the rotation log
-  replay_rotations(VL, ldc, rlog, sweeps * (nn - 1), nn);
+  const double *VT = C;  // eigenvectors of C (transposed)
   if (tid < n) {
     const int i = tid;
     int rk = 0;
@@ -396,22 +420,20 @@ __global__ __launch_bounds__(kThreads) void reduced_eig_kernel(const double *AQ,
   // Phi[:, rank[i]] = T V[:, i]
   wg_gemm(
       nt, [&](int r, int k) { return (r < nn && k < nn) ? T[r * nn + k] : 0.0; },
-      [&](int k, int c) { return (k < nn && c < nn) ? VL[k * ldc + c] : 0.0; },
+      [&](int k, int c) { return (k < nn && c < nn) ? VT[c * kVTld + k] : 0.0; },
       [&](int r, int c, double v) { if (r < n && c < n) Phi[r * n + sh.rank[c]] = v; });
   if (tid == 0) flag[0] = fallback ? 1 : 0;
 }
 
 }  // namespace
 
-size_t reduced_eig_scratch_doubles() {
-  return 3 * (size_t)kMaxN * kMaxN + (size_t)kMaxSweeps * (kMaxN - 1) * kMaxN;
-}
+size_t reduced_eig_scratch_doubles() { return 3 * (size_t)kMaxN * kMaxN; }
 
 hipError_t launch_reduced_eig(const double *AQ, const double *BQ, int n, double *eps, double *Phi,
                               double *scratch, int *flag, hipStream_t st) {
   if (n < 1 || n > kMaxN) return hipErrorInvalidValue;
   const int nn = n + (n & 1);
-  const size_t shm = (size_t)nn * (nn + 1) * sizeof(double);
+  const size_t shm = (size_t)nn * (kVTld > nn + 1 ? kVTld : nn + 1) * sizeof(double);
   hipError_t err = hipFuncSetAttribute((const void *)reduced_eig_kernel,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   if (err != hipSuccess) return err;

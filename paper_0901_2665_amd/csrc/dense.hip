@@ -454,28 +454,36 @@ __global__ __launch_bounds__(kCellThreads) void cell_shift_residual_kernel(
   }
 }
 
-// worst = max over nodes e < Ne and columns j < m0 of
-//   ||r_j|| / (||R_j|| + |Z_e| ||B x_j|| + ||A x_j||)   (2-norms),
-// the residual relative to the size of the terms it is computed from (one
-// workgroup; group sums added in group order).
-__global__ __launch_bounds__(256) void shift_residual_reduce_kernel(const double *partial,
-                                                                    int groups, int ld, int m0,
-                                                                    int Ne, Shifts sh,
-                                                                    double *worst) {
+// ratio[e][j] = ||r_j|| / (||R_j|| + |Z_e| ||B x_j|| + ||A x_j||) (2-norms),
+// the residual relative to the size of the terms it is computed from, for
+// node e and column j < m0 (one thread each; group sums in group order).
+__global__ __launch_bounds__(256) void shift_residual_ratio_kernel(const double *partial,
+                                                                   int groups, int ld, int m0,
+                                                                   int Ne, Shifts sh,
+                                                                   double *ratio) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= Ne * m0) return;
+  const int e = idx / m0, j = idx % m0;
+  double t[kShiftSums] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int g = 0; g < groups; ++g)
+#pragma unroll
+    for (int q = 0; q < kShiftSums; ++q)
+      t[q] += partial[(((size_t)e * groups + g) * kShiftSums + q) * ld + j];
+  const double za = sqrt(sh.zre[e] * sh.zre[e] + sh.zim[e] * sh.zim[e]);
+  const double den = sqrt(t[2]) + za * sqrt(t[1] + t[4]) + sqrt(t[0] + t[3]);
+  const double num = sqrt(t[5]);
+  ratio[idx] = den > 0.0 ? num / den : (num > 0.0 ? INFINITY : 0.0);
+}
+
+// worst = max of the count ratios (one workgroup); a NaN (non-finite
+// iterate) counts as infinity, so it never passes the refinement test
+__global__ __launch_bounds__(256) void max_ratio_kernel(const double *ratio, int count,
+                                                        double *worst) {
   __shared__ double red[256];
   double mx = 0.0;
-  for (int idx = threadIdx.x; idx < Ne * m0; idx += 256) {
-    const int e = idx / m0, j = idx % m0;
-    double t[kShiftSums] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int g = 0; g < groups; ++g)
-#pragma unroll
-      for (int q = 0; q < kShiftSums; ++q)
-        t[q] += partial[(((size_t)e * groups + g) * kShiftSums + q) * ld + j];
-    const double za = sqrt(sh.zre[e] * sh.zre[e] + sh.zim[e] * sh.zim[e]);
-    const double den = sqrt(t[2]) + za * sqrt(t[1] + t[4]) + sqrt(t[0] + t[3]);
-    const double num = sqrt(t[5]);
-    const double q = den > 0.0 ? num / den : (num > 0.0 ? INFINITY : 0.0);
-    mx = (q == q) ? fmax(mx, q) : INFINITY;  // a non-finite iterate never passes
+  for (int i = threadIdx.x; i < count; i += 256) {
+    const double q = ratio[i];
+    mx = (q == q) ? fmax(mx, q) : INFINITY;
   }
   red[threadIdx.x] = mx;
   __syncthreads();
@@ -706,7 +714,7 @@ hipError_t launch_cell_residuals(const Pencil &p, const double *X, int ld, const
 }
 
 size_t shift_residual_partial_doubles(int nc, int ld, int Ne) {
-  return (size_t)cell_groups(nc) * ld * Ne * kShiftSums;
+  return (size_t)cell_groups(nc) * ld * Ne * kShiftSums + (size_t)Ne * ld;  // + ratios
 }
 
 template <int BP>
@@ -723,8 +731,12 @@ hipError_t shift_residual_bp(const Pencil &p, const Shifts &s, int Ne, const dou
   hipLaunchKernelGGL((cell_shift_residual_kernel<BP, 1>), grid, dim3(kCellThreads), 0, st, p.Ad,
                      p.Au, p.Bd, p.Bu, p.nc, p.b, X, R, ld, plane, s, Rout, partial);
   if ((err = hipGetLastError()) != hipSuccess) return err;
-  hipLaunchKernelGGL(shift_residual_reduce_kernel, dim3(1), dim3(256), 0, st,
-                     (const double *)partial, G, ld, m0, Ne, s, worst);
+  double *ratio = partial + (size_t)G * ld * Ne * kShiftSums;
+  hipLaunchKernelGGL(shift_residual_ratio_kernel, dim3((Ne * m0 + 255) / 256), dim3(256), 0, st,
+                     (const double *)partial, G, ld, m0, Ne, s, ratio);
+  if ((err = hipGetLastError()) != hipSuccess) return err;
+  hipLaunchKernelGGL(max_ratio_kernel, dim3(1), dim3(256), 0, st, (const double *)ratio, Ne * m0,
+                     worst);
   return hipGetLastError();
 }
 

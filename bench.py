@@ -32,16 +32,19 @@ PEAK_FP32 = 157.3       # TFLOP/s, MI355X dense FP32 (matrix = vector)
 PEAK_HBM = 8000.0       # GB/s
 
 
-def source_digest():
-    """Digest of the HIP/C++ sources: HBM traffic taken with counters applies
-    only to the kernels built from exactly these sources."""
+# sources the shifted-solve kernels (factorisation, sweeps) are built from
+SOLVE_SOURCES = ("common.h", "kernels.h", "factor.hip", "sweep.hip")
+
+
+def source_digest(names=SOLVE_SOURCES):
+    """Digest of the shifted-solve kernel sources: HBM traffic taken with
+    counters applies only to kernels built from exactly these sources."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_0901_2665_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".h", ".cpp")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+    for name in sorted(names):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()[:16]
 
 

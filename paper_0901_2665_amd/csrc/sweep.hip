@@ -63,6 +63,9 @@ __device__ __forceinline__ void frag_load(Frag<BP> &f, const double *M, int rb, 
 
 // Vector operand B' = [[hr | hi]; [-hi | hr]] of this lane, read from the LDS
 // vector tile hv in one batch (b[ks] for k < BP, b[BP/4 + ks] for k >= BP).
+// (Reading one plane and taking the other from lane n+8 by a row shift
+// halves the LDS reads but makes the matrix cores wait for all of them:
+// measured slower.)
 template <int BP>
 __device__ __forceinline__ void bvec_load(double (&b)[BP / 2], const double (*hv)[BP][kTile]) {
   const int l = lane_id();
@@ -77,15 +80,18 @@ __device__ __forceinline__ void bvec_load(double (&b)[BP / 2], const double (*hv
   }
 }
 
-// acc0/acc1 += A' * B'; even and odd k-steps go to separate accumulators.
 template <int BP>
-__device__ __forceinline__ void frag_mfma(d4 &acc0, d4 &acc1, const Frag<BP> &f,
-                                          const double (&b)[BP / 2]) {
+__device__ __forceinline__ d4 frag_mfma(const d4 &acc0, const Frag<BP> &f,
+                                        const double (&b)[BP / 2]) {
+  d4 a0 = acc0, a1 = d4zero(), a2 = d4zero(), a3 = d4zero();
 #pragma unroll
-  for (int ks = 0; ks < BP / 2; ks += 2) {
-    acc0 = mfma(f.v[ks], b[ks], acc0);
-    acc1 = mfma(f.v[ks + 1], b[ks + 1], acc1);
+  for (int ks = 0; ks < BP / 2; ks += 4) {
+    a0 = mfma(f.v[ks], b[ks], a0);
+    a1 = mfma(f.v[ks + 1], b[ks + 1], a1);
+    a2 = mfma(f.v[ks + 2], b[ks + 2], a2);
+    a3 = mfma(f.v[ks + 3], b[ks + 3], a3);
   }
+  return (a0 + a1) + (a2 + a3);
 }
 
 // Accumulator tile <-> vector tile [2][BP][8]: plain accesses (LDS or
@@ -181,6 +187,9 @@ __global__ __launch_bounds__(BP * 8) void forward_kernel(SweepArgs a) {
   const int wv = wave_id();
   const bool wrole = wv < NW;  // wave-uniform
   const int rb = wrole ? wv : wv - NW;
+  // the W role carries the recurrence from step to step: its instructions go
+  // first when both roles of a SIMD are ready
+  if (wrole) __builtin_amdgcn_s_setprio(2);
   const double *M = (wrole ? a.f.W : a.f.Sinv) + (size_t)e * nc * blk;
   double *G = a.sb.G + ((size_t)e * a.ntiles + tau) * nc * vt;
   double *TV = a.sb.TV + ((size_t)e * a.ntiles + tau) * 2 * vt;
@@ -212,10 +221,8 @@ __global__ __launch_bounds__(BP * 8) void forward_kernel(SweepArgs a) {
     double b[BP / 2];
     bvec_load<BP>(b, s.v[cur]);
     const bool more = j < len - 1;
-    d4 acc0 = (wrole && more) ? r : d4zero(), acc1 = d4zero();
     // W role: R_{j+1} + W_j^T u_j = h_{j+1};  Sinv role: Sinv_j u_j = -g_j
-    frag_mfma<BP>(acc0, acc1, f, b);
-    const d4 acc = acc0 + acc1;
+    const d4 acc = frag_mfma<BP>((wrole && more) ? r : d4zero(), f, b);
     vec_store_buf<BP>(G + c * vt, -acc, rb, !wrole);
     if (wrole) {
       if (more)
@@ -303,9 +310,7 @@ __global__ __launch_bounds__(BP * 4) void back_kernel(SweepArgs a) {
   {
     double b[BP / 2];
     bvec_load<BP>(b, s.v[1]);
-    d4 x0 = d4zero(), x1 = d4zero();
-    frag_mfma<BP>(x0, x1, f0, b);
-    const d4 x = x0 + x1;
+    const d4 x = frag_mfma<BP>(d4zero(), f0, b);
     acc_store_vec<BP>(&s.v[0][0][0][0], -x, rb);
     if (top) emit(m - 1, x);
   }
@@ -320,9 +325,7 @@ __global__ __launch_bounds__(BP * 4) void back_kernel(SweepArgs a) {
     ng = vec_load_buf<BP>(G + cell(j + 1) * vt, rb, nx);
     double b[BP / 2];
     bvec_load<BP>(b, s.v[cur]);
-    d4 x0 = g, x1 = d4zero();
-    frag_mfma<BP>(x0, x1, f, b);
-    const d4 x = x0 + x1;
+    const d4 x = frag_mfma<BP>(g, f, b);
     acc_store_vec<BP>(&s.v[cur ^ 1][0][0][0], -x, rb);
     emit(c, x);
     __syncthreads();

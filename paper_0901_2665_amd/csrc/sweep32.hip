@@ -115,14 +115,19 @@ __device__ __forceinline__ void bvec_load32(float (&b)[BP / 2], const float (*hv
   }
 }
 
+// acc0 + A' * B' over four independent accumulator chains
 template <int BP>
-__device__ __forceinline__ void frag_mfma32(f4 &acc0, f4 &acc1, const Frag32<BP> &f,
-                                            const float (&b)[BP / 2]) {
+__device__ __forceinline__ f4 frag_mfma32(const f4 &acc0, const Frag32<BP> &f,
+                                          const float (&b)[BP / 2]) {
+  f4 a0 = acc0, a1 = f4zero(), a2 = f4zero(), a3 = f4zero();
 #pragma unroll
-  for (int ks = 0; ks < BP / 2; ks += 2) {
-    acc0 = mfma32(f.v[ks], b[ks], acc0);
-    acc1 = mfma32(f.v[ks + 1], b[ks + 1], acc1);
+  for (int ks = 0; ks < BP / 2; ks += 4) {
+    a0 = mfma32(f.v[ks], b[ks], a0);
+    a1 = mfma32(f.v[ks + 1], b[ks + 1], a1);
+    a2 = mfma32(f.v[ks + 2], b[ks + 2], a2);
+    a3 = mfma32(f.v[ks + 3], b[ks + 3], a3);
   }
+  return (a0 + a1) + (a2 + a3);
 }
 
 template <int BP>
@@ -216,6 +221,7 @@ __global__ __launch_bounds__(BP * 8) void forward32_kernel(Sweep32Args a) {
   const int wv = wave_id();
   const bool wrole = wv < NW;  // wave-uniform
   const int rb = wrole ? wv : wv - NW;
+  if (wrole) __builtin_amdgcn_s_setprio(2);  // the recurrence's role goes first
   const float *M = (wrole ? a.f.W : a.f.Sinv) + (size_t)e * nc * blk;
   float *G = a.sb.G + ((size_t)e * a.ntiles + tau) * nc * vt;
   float *TV = a.sb.TV + ((size_t)e * a.ntiles + tau) * 2 * vt;
@@ -247,9 +253,7 @@ __global__ __launch_bounds__(BP * 8) void forward32_kernel(Sweep32Args a) {
     float b[BP / 2];
     bvec_load32<BP>(b, s.v[cur]);
     const bool more = j < len - 1;
-    f4 acc0 = (wrole && more) ? r : f4zero(), acc1 = f4zero();
-    frag_mfma32<BP>(acc0, acc1, f, b);
-    const f4 acc = acc0 + acc1;
+    const f4 acc = frag_mfma32<BP>((wrole && more) ? r : f4zero(), f, b);
     vec_store_buf32<BP>(G + c * vt, -acc, rb, !wrole);
     if (wrole) {
       if (more)
@@ -343,9 +347,7 @@ __global__ __launch_bounds__(BP * 4) void back32_kernel(Sweep32Args a) {
   {
     float b[BP / 2];
     bvec_load32<BP>(b, s.v[1]);
-    f4 x0 = f4zero(), x1 = f4zero();
-    frag_mfma32<BP>(x0, x1, f0, b);
-    const f4 x = x0 + x1;
+    const f4 x = frag_mfma32<BP>(f4zero(), f0, b);
     acc_store_vec32<BP>(&s.v[0][0][0][0], -x, rb);
     if (top) emit(m - 1, x, xt);
   }
@@ -360,9 +362,7 @@ __global__ __launch_bounds__(BP * 4) void back32_kernel(Sweep32Args a) {
     nxo = xload(cell(j + 1), nx);
     float b[BP / 2];
     bvec_load32<BP>(b, s.v[cur]);
-    f4 x0 = g, x1 = f4zero();
-    frag_mfma32<BP>(x0, x1, f, b);
-    const f4 x = x0 + x1;
+    const f4 x = frag_mfma32<BP>(g, f, b);
     acc_store_vec32<BP>(&s.v[cur ^ 1][0][0][0], -x, rb);
     emit(c, x, xo);
     __syncthreads();

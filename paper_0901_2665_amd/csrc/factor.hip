@@ -294,8 +294,11 @@ __device__ __forceinline__ void gj_invert(Lds<BP> &s, double *gout, bool symm = 
   const int w = wave_id();
   double *A = s.A;
   auto tile = [&](int bi, int bj) { return A + (bi * 16) * LD + bj * 16; };
+  // The next pivot tile (kb+1, kb+1) is updated first, by wave 0, which then
+  // inverts it while waves 1-3 update the other tiles (look-ahead): the
+  // one-wave inverse overlaps the panel update instead of idling three waves.
+  if (w == 0) inv16_wave(tile(0, 0), tile(0, 0) + PLANE, LD);
   for (int kb = 0; kb < NB; ++kb) {
-    if (w == 0) inv16_wave(tile(kb, kb), tile(kb, kb) + PLANE, LD);
     __syncthreads();
     if constexpr (NB > 1) {
       // row panel S_KJ <- P S_KJ
@@ -308,37 +311,59 @@ __device__ __forceinline__ void gj_invert(Lds<BP> &s, double *gout, bool symm = 
       __syncthreads();
       if (jb >= 0) tile_store<BP>(tile(kb, jb), rr, ri);
       __syncthreads();
-      // trailing tiles and column panel
+      // trailing tiles and column panel: tile t of the (NB-1) x NB tiles off
+      // row kb (rows bi != kb in order, all columns)
       constexpr int NT = (NB - 1) * NB;
-      constexpr int PER = NT > 0 ? (NT + 3) / 4 : 1;
+      const bool look = kb + 1 < NB;
+      const int tnext = kb * NB + kb + 1;  // tile (kb+1, kb+1): row index kb (= kb+1 - 1)
+      auto tile_of = [&](int t, int &bi, int &j0) {
+        const int i0 = t / NB;
+        j0 = t % NB;
+        bi = i0 < kb ? i0 : i0 + 1;
+      };
+      auto update = [&](int bi, int j0, d4 &tr, d4 &ti) {
+        if (j0 == kb) {
+          tr = d4zero();
+          ti = d4zero();
+          tile_cgemm16<BP>(tr, ti, tile(bi, kb), tile(kb, kb), -1.0);
+        } else {
+          tile_load<BP>(tr, ti, tile(bi, j0));
+          tile_cgemm16<BP>(tr, ti, tile(bi, kb), tile(kb, j0), -1.0);
+        }
+      };
+      if (look && w == 0) {
+        d4 tr, ti;
+        update(kb + 1, kb + 1, tr, ti);
+        tile_store<BP>(tile(kb + 1, kb + 1), tr, ti);
+        // (no other tile of this phase reads tile (kb+1, kb+1))
+        inv16_wave(tile(kb + 1, kb + 1), tile(kb + 1, kb + 1) + PLANE, LD);
+      }
+      // the other tiles over waves 1-3 (look-ahead) or all four waves
+      constexpr int PER = NT > 0 ? (NT + 2) / 3 : 1;
       d4 tr[PER], ti[PER];
       int ib[PER], jbb[PER];
+      const int nw = look ? 3 : 4, wi = look ? w - 1 : w;
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
-        const int t = w + 4 * q;
         ib[q] = -1;
+        if (wi < 0) continue;
+        int t = wi + nw * q;
+        if (look && t >= tnext) ++t;  // skip the look-ahead tile
         if (t < NT) {
-          const int i0 = t / NB, j0 = t % NB;
-          const int bi = i0 < kb ? i0 : i0 + 1;
+          int bi, j0;
+          tile_of(t, bi, j0);
           ib[q] = bi;
           jbb[q] = j0;
-          if (j0 == kb) {
-            tr[q] = d4zero();
-            ti[q] = d4zero();
-            tile_cgemm16<BP>(tr[q], ti[q], tile(bi, kb), tile(kb, kb), -1.0);
-          } else {
-            tile_load<BP>(tr[q], ti[q], tile(bi, j0));
-            tile_cgemm16<BP>(tr[q], ti[q], tile(bi, kb), tile(kb, j0), -1.0);
-          }
+          update(bi, j0, tr[q], ti[q]);
         }
       }
       __syncthreads();
 #pragma unroll
       for (int q = 0; q < PER; ++q)
         if (ib[q] >= 0) tile_store<BP>(tile(ib[q], jbb[q]), tr[q], ti[q]);
-      __syncthreads();
     }
   }
+  __syncthreads();
   if (!symm) {
     __syncthreads();
     return;

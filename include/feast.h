@@ -134,6 +134,53 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
                 int32_t M0, int32_t Ne, const feast_opts *opts,
                 double *lambda, double *X, double *res, feast_info *info);
 
+/* ---- many problems ---- */
+
+/* One problem of a batched call: every pointer as in feast_solve. */
+typedef struct {
+  feast_bt_matrix AB;
+  double emin, emax;     /* search interval */
+  int32_t M0, Ne;        /* subspace size, contour points */
+  const double *Y0;      /* (dev) [N][M0] initial subspace; required */
+  double *lambda;        /* (dev) [M0] */
+  double *X;             /* (dev) [N][M0] */
+  double *res;           /* (dev) [M0] */
+  feast_info *info;      /* (host) may be NULL */
+  int32_t status;        /* out: what feast_solve returned for this problem */
+} feast_problem;
+
+/*
+ * FEAST solves of `count` independent problems of any sizes (independent
+ * problems or intervals: parallelism level (i) of Sec. V).  The problems are
+ * taken longest first (estimated from nc, b, M0 and Ne) by `workers` host
+ * threads, each with its own HIP stream (default priority) and workspace, so
+ * that the kernels of several problems share the GPU.  opts applies to every
+ * problem except Y0, which each problem brings.  workers: 0 = min(count, 8);
+ * the worker streams and workspaces belong to the context and are kept for
+ * later calls.  Work queued on the context's stream before the call is
+ * complete before any problem starts, and every problem is complete when the
+ * call returns.  Returns the first negative per-problem status if any, else
+ * the largest positive one, else 0; each problem's status is in
+ * probs[i].status.  Results are identical to feast_solve on each problem.
+ */
+int feast_solve_batched(feast_ctx *ctx, feast_problem *probs, int32_t count,
+                        const feast_opts *opts, int32_t workers);
+
+/*
+ * Partition count of the factorisation for one problem shape, measured: the
+ * factorisation plus one forward and back sweep of (AB, emin, emax, M0, Ne)
+ * are timed (after a warm-up) for 1, 2, 4, ... partitions per half chain up
+ * to the largest with at least 8 cells each, and the fastest is returned in
+ * *partitions (host), to be passed as feast_opts.partitions.  cache_path
+ * (host string, may be NULL) names a text file of lines
+ * "arch nc b M0 Ne partitions ms": a shape found there for this device is not
+ * measured again, and a measured one is appended.  Results of a solve do not
+ * depend on the partition count beyond rounding.
+ */
+int feast_autotune_partitions(feast_ctx *ctx, const feast_bt_matrix *AB, double emin,
+                              double emax, int32_t M0, int32_t Ne, const char *cache_path,
+                              int32_t *partitions);
+
 /* ---- single steps of the same path, for step-by-step parity checks ---- */
 
 /*

@@ -7,9 +7,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <numeric>
+#include <thread>
 #include <vector>
 
 #include "../../include/feast.h"
@@ -55,10 +58,12 @@ struct Timing {
 struct feast_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  bool owns_stream = false;          // workers of a batched call own theirs
   Buf buf[S_COUNT];
   double *h_eps = nullptr;  // pinned: eps[128] + res[128]
   int *h_flag = nullptr;    // pinned
   Timing timing;
+  std::vector<feast_ctx *> workers;  // sub-contexts of feast_solve_batched
 };
 
 namespace {
@@ -365,6 +370,8 @@ int feast_destroy(feast_ctx *ctx) {
   for (auto ev : ctx->timing.pool) (void)hipEventDestroy(ev);
   if (ctx->h_eps) (void)hipHostFree(ctx->h_eps);
   if (ctx->h_flag) (void)hipHostFree(ctx->h_flag);
+  for (feast_ctx *w : ctx->workers) feast_destroy(w);
+  if (ctx->owns_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
   return 0;
 }
@@ -803,6 +810,173 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
     }
   }
   return status;
+}
+
+
+// ---- independent problems (Sec. V, parallelism level (i)) ----
+
+namespace {
+
+// Estimated device work of one problem (flops of the factorisation and of
+// three refinement loops of sweeps), the key of the longest-first order.
+double problem_cost(const feast_problem &q) {
+  const double nc = q.AB.nc, b = q.AB.b;
+  return q.Ne * nc * b * b * (b + 3.0 * q.M0);
+}
+
+}  // namespace
+
+int feast_solve_batched(feast_ctx *ctx, feast_problem *probs, int32_t count,
+                        const feast_opts *opts, int32_t workers) {
+  if (!ctx || (!probs && count > 0)) return -5;
+  if (count < 0 || workers < 0) return -7;
+  if (count == 0) return 0;
+  HIPCHK(hipSetDevice(ctx->device));
+  // inputs produced on the caller's stream are complete before any worker starts
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  const int nw = std::max(1, std::min<int>(workers ? workers : 8, count));
+  while ((int)ctx->workers.size() < nw) {
+    hipStream_t st = nullptr;
+    HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));  // default priority
+    feast_ctx *w = nullptr;
+    const int e = feast_init(&w, ctx->device, st);
+    if (e) {
+      (void)hipStreamDestroy(st);
+      return e;
+    }
+    w->owns_stream = true;
+    ctx->workers.push_back(w);
+  }
+  std::vector<int> order(count);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return problem_cost(probs[a]) > problem_cost(probs[b]);
+  });
+  feast_opts base;
+  feast_default_opts(&base);
+  if (opts) base = *opts;
+  std::atomic<int> next{0};
+  auto run = [&](feast_ctx *w) {
+    (void)hipSetDevice(w->device);
+    for (int k = next++; k < count; k = next++) {
+      feast_problem &q = probs[order[k]];
+      feast_opts o = base;
+      o.Y0 = q.Y0;
+      q.status = feast_solve(w, &q.AB, q.emin, q.emax, q.M0, q.Ne, &o, q.lambda, q.X, q.res,
+                             q.info);
+    }
+  };
+  std::vector<std::thread> threads;
+  for (int t = 1; t < nw; ++t) threads.emplace_back(run, ctx->workers[t]);
+  run(ctx->workers[0]);
+  for (auto &t : threads) t.join();
+  int worst_neg = 0, worst_pos = 0;
+  for (int i = 0; i < count; ++i) {
+    const int st = probs[i].status;
+    if (st < 0 && worst_neg == 0) worst_neg = st;
+    if (st > worst_pos) worst_pos = st;
+  }
+  return worst_neg ? worst_neg : worst_pos;
+}
+
+// ---- partition-count tuning ----
+
+namespace {
+
+// "nc b M0 Ne partitions ms" lines of a tuning cache; returns the cached
+// partitions for the shape or 0.
+int cache_lookup(const char *path, const char *arch, int nc, int b, int M0, int Ne) {
+  if (!path) return 0;
+  FILE *f = std::fopen(path, "r");
+  if (!f) return 0;
+  char a[64];
+  int cnc, cb, cm, ce, cp;
+  double ms;
+  int found = 0;
+  while (std::fscanf(f, "%63s %d %d %d %d %d %lf", a, &cnc, &cb, &cm, &ce, &cp, &ms) == 7)
+    if (!std::strcmp(a, arch) && cnc == nc && cb == b && cm == M0 && ce == Ne) found = cp;
+  std::fclose(f);
+  return found;
+}
+
+}  // namespace
+
+int feast_autotune_partitions(feast_ctx *ctx, const feast_bt_matrix *AB, double emin,
+                              double emax, int32_t M0, int32_t Ne, const char *cache_path,
+                              int32_t *partitions) {
+  if (!ctx || !partitions) return -5;
+  int st = validate_matrix(AB);
+  if (st) return st;
+  if (!(emin < emax) || !std::isfinite(emin) || !std::isfinite(emax)) return -2;
+  if (M0 < 1 || M0 > kMaxM0 || M0 > (long long)AB->nc * AB->b) return -3;
+  if (Ne < 1 || Ne > kMaxNe) return -4;
+  HIPCHK(hipSetDevice(ctx->device));
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, ctx->device));
+  char arch[64];
+  std::snprintf(arch, sizeof(arch), "%s/%dcu", prop.gcnArchName, prop.multiProcessorCount);
+  for (char *c = arch; *c; ++c)
+    if (*c == ' ' || *c == ':') *c = '_';
+  const int cached = cache_lookup(cache_path, arch, AB->nc, AB->b, M0, Ne);
+  if (cached > 0) {
+    *partitions = cached;
+    return 0;
+  }
+  Pencil p = make_pencil(AB);
+  const int mp = round16(M0);
+  Shifts s;
+  make_shifts(Ne, emin, emax, s);
+  const int half = p.nc / 2;
+  const int pmax = std::max(1, half / 8);  // at least 8 cells a partition
+  std::vector<int> cand;
+  for (int q = 1; q <= pmax; q *= 2) cand.push_back(q);
+  if (cand.back() != pmax) cand.push_back(pmax);
+  hipEvent_t t0, t1;
+  HIPCHK(hipEventCreate(&t0));
+  HIPCHK(hipEventCreate(&t1));
+  int best = 0;
+  float best_ms = 0.0f;
+  for (int q : cand) {
+    Work wk;
+    st = prepare_factor(ctx, p, Ne, mp, q, wk);
+    if (st) break;
+    double *r, *pp;
+    hipError_t e = ensure_t(ctx, S_R, wk.rows * mp, &r);
+    if (e == hipSuccess) e = ensure_t(ctx, S_P, (size_t)Ne * wk.rows * mp, &pp);
+    if (e == hipSuccess) e = hipMemsetAsync(r, 0, wk.rows * mp * sizeof(double), ctx->stream);
+    float ms = 0.0f;
+    for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {  // first run warms up
+      if (e == hipSuccess) e = hipEventRecord(t0, ctx->stream);
+      if (e == hipSuccess) e = run_factor(ctx, wk, s);
+      if (e == hipSuccess) e = launch_sweeps(p, s, Ne, wk.f, wk.sb, r, mp, pp, 3, ctx->stream);
+      if (e == hipSuccess) e = hipEventRecord(t1, ctx->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(t1);
+      float m = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&m, t0, t1);
+      if (rep > 0) ms += m;
+    }
+    if (e != hipSuccess) {
+      st = hip_status(e);
+      break;
+    }
+    if (best == 0 || ms < best_ms) {
+      best = q;
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  if (st) return st;
+  *partitions = best;
+  if (cache_path) {
+    FILE *f = std::fopen(cache_path, "a");
+    if (f) {
+      std::fprintf(f, "%s %d %d %d %d %d %.4f\n", arch, AB->nc, AB->b, M0, Ne, best,
+                   best_ms / 2.0f);
+      std::fclose(f);
+    }
+  }
+  return 0;
 }
 
 }  // extern "C"

@@ -48,10 +48,18 @@ class Info(ctypes.Structure):
                 ("solve_res", ctypes.c_double)]
 
 
+class Problem(ctypes.Structure):
+    _fields_ = [("AB", BTMatrix), ("emin", ctypes.c_double), ("emax", ctypes.c_double),
+                ("M0", ctypes.c_int32), ("Ne", ctypes.c_int32), ("Y0", ctypes.c_void_p),
+                ("lam", ctypes.c_void_p), ("X", ctypes.c_void_p), ("res", ctypes.c_void_p),
+                ("info", ctypes.c_void_p), ("status", ctypes.c_int32)]
+
+
 EXPORTED = ["feast_default_opts", "feast_init", "feast_destroy", "feast_strerror",
             "feast_solve", "feast_contour", "feast_bt_multiply", "feast_shifted_solve",
             "feast_filter", "feast_project", "feast_reduced_eig", "feast_timing",
-            "feast_timing_read", "feast_shifted_solve_mixed", "feast_filter_mixed"]
+            "feast_timing_read", "feast_shifted_solve_mixed", "feast_filter_mixed",
+            "feast_solve_batched", "feast_autotune_partitions"]
 
 
 def load_library(path: str = LIB_PATH):
@@ -81,6 +89,10 @@ def load_library(path: str = LIB_PATH):
                                        ctypes.POINTER(I32), ctypes.POINTER(D)]
     lib.feast_project.argtypes = [P, ctypes.POINTER(BTMatrix), I32, P, P, P]
     lib.feast_reduced_eig.argtypes = [P, I32, P, P, P, P, ctypes.POINTER(I32)]
+    lib.feast_solve_batched.argtypes = [P, ctypes.POINTER(Problem), I32, ctypes.POINTER(Opts),
+                                        I32]
+    lib.feast_autotune_partitions.argtypes = [P, ctypes.POINTER(BTMatrix), D, D, I32, I32,
+                                              ctypes.c_char_p, ctypes.POINTER(I32)]
     lib.feast_timing.argtypes = [P, I32]
     lib.feast_timing_read.argtypes = [P, I32, ctypes.POINTER(ctypes.c_char_p),
                                       ctypes.POINTER(D), ctypes.POINTER(ctypes.c_int64)]
@@ -202,6 +214,49 @@ class Context:
                            info.max_res, st, info.fallback, list(info.trace_hist[:n]),
                            list(info.count_hist[:n]), info.rr_sweeps, info.refine_steps,
                            info.solve_res)
+
+    def solve_batched(self, problems, tol: float = 1e-12, max_loops: int = 20,
+                      partitions: int = 0, precision: int = 0, workers: int = 0):
+        """Solve independent problems together.  problems: list of
+        (Pencil, emin, emax, M0, Ne, Y0) with Y0 a device tensor.  Returns
+        (status, [SolveResult]); a problem's own error is in its result's
+        status, an error of the call raises."""
+        import torch
+        keep, res_list = [], []
+        arr = (Problem * len(problems))()
+        for i, (p, emin, emax, M0, Ne, Y0) in enumerate(problems):
+            dev = p.Ad.device
+            lam = torch.empty(M0, dtype=torch.float64, device=dev)
+            X = torch.empty((p.n, M0), dtype=torch.float64, device=dev)
+            res = torch.empty(M0, dtype=torch.float64, device=dev)
+            info = Info()
+            keep.append((p, Y0, lam, X, res, info))
+            arr[i] = Problem(p.struct(), emin, emax, M0, Ne, _ptr(Y0), _ptr(lam), _ptr(X),
+                             _ptr(res), ctypes.cast(ctypes.pointer(info), ctypes.c_void_p), 0)
+        opts = Opts(tol, max_loops, precision, partitions, None)
+        st = self.lib.feast_solve_batched(self.handle, arr, len(problems), ctypes.byref(opts),
+                                          workers)
+        if st < 0 and all(arr[i].status != st for i in range(len(problems))):
+            raise FeastError(st, "feast_solve_batched", self.lib)  # the call itself failed
+        for i, (p, Y0, lam, X, res, info) in enumerate(keep):
+            n = min(info.loops, 64)
+            res_list.append(SolveResult(lam, X, res, info.M, info.loops, info.trace,
+                                        info.trace_rel, info.max_res, arr[i].status,
+                                        info.fallback, list(info.trace_hist[:n]),
+                                        list(info.count_hist[:n]), info.rr_sweeps,
+                                        info.refine_steps, info.solve_res))
+        return st, res_list
+
+    def autotune_partitions(self, p: Pencil, emin: float, emax: float, M0: int, Ne: int,
+                            cache_path: str | None = None) -> int:
+        """Fastest partition count of the factorisation for this shape (measured)."""
+        out = ctypes.c_int32(0)
+        ab = p.struct()
+        path = cache_path.encode() if cache_path else None
+        st = self.lib.feast_autotune_partitions(self.handle, ctypes.byref(ab), emin, emax, M0,
+                                                Ne, path, ctypes.byref(out))
+        self._check(st, "feast_autotune_partitions")
+        return out.value
 
     def timing(self, enable: bool):
         """Start (clear) or stop hipEvent timing of the kernel classes."""

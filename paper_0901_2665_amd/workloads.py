@@ -154,6 +154,44 @@ WORKLOADS = {
 }
 
 
+# Batched workload: independent uneven problems.  Problem p draws, from
+# default_rng(BATCH_SEED + p): nc ~ U{50..200}, b from {32, 48, 64},
+# M0 ~ U{16..64}; the pencil is the chain recipe with matrix seed
+# BATCH_SEED + p, Ne = 16, and the interval holds round(0.6 M0) eigenvalues
+# from index n // 4 (stored in tests/golden/intervals_batch.json).
+BATCH_SEED = 3000
+BATCH_NE = 16
+
+
+def batch_shape(p: int) -> dict:
+    rng = np.random.default_rng(BATCH_SEED + p)
+    nc = int(rng.integers(50, 201))
+    b = int(rng.choice([32, 48, 64]))
+    m0 = int(rng.integers(16, 65))
+    n = nc * b
+    return dict(nc=nc, b=b, M0=m0, Ne=BATCH_NE, mseed=BATCH_SEED + p, yseed=BATCH_SEED + 500 + p,
+                n_eig=int(round(0.6 * m0)), k0=n // 4)
+
+
+def batch_pencil(p: int) -> Pencil:
+    s = batch_shape(p)
+    return chain_pencil(s["nc"], s["b"], s["mseed"])
+
+
+def make_batch(count: int):
+    """[(pencil, emin, emax, M0, Ne, Y0)] of the first ``count`` batch problems."""
+    with open(os.path.join(_GOLDEN, "intervals_batch.json")) as f:
+        iv = json.load(f)
+    out = []
+    for p in range(count):
+        s = batch_shape(p)
+        e = iv[str(p)]
+        pen = batch_pencil(p)
+        out.append((pen, float(e["emin"]), float(e["emax"]), s["M0"], s["Ne"],
+                    random_subspace(pen.n, s["M0"], s["yseed"])))
+    return out
+
+
 def make_pencil(name: str) -> Pencil:
     w = WORKLOADS[name]
     if w["kind"] == "dense":

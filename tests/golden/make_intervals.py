@@ -9,6 +9,7 @@ half captured).  Small pencils use the dense solver; large ones bisect on the
 Sylvester inertia count.
 
 Usage:  python tests/golden/make_intervals.py [name ...]
+        python tests/golden/make_intervals.py --batch COUNT   (intervals_batch.json)
 """
 from __future__ import annotations
 
@@ -58,6 +59,32 @@ def interval_for(name):
                 gap_lo=e[1] - e[0], gap_hi=e[3] - e[2])
 
 
+def batch_interval(p):
+    """Interval of batch problem p (workloads.batch_shape): round(0.6 M0)
+    eigenvalues from index n // 4, ends half-way between neighbours."""
+    sh = W.batch_shape(p)
+    pen = W.batch_pencil(p)
+    k0, m = sh["k0"], sh["n_eig"]
+    lo, hi = -100.0, 100.0
+    assert O.inertia_count(pen, lo) == 0 and O.inertia_count(pen, hi) == pen.n
+    e = [kth_eigenvalue(pen, j, lo, hi) for j in (k0 - 1, k0, k0 + m - 1, k0 + m)]
+    emin, emax = 0.5 * (e[0] + e[1]), 0.5 * (e[2] + e[3])
+    cnt = O.inertia_count(pen, emax) - O.inertia_count(pen, emin)
+    assert cnt == m, (p, cnt, m)
+    return dict(emin=emin, emax=emax, n_eig=m, k0=k0, nc=sh["nc"], b=sh["b"], M0=sh["M0"],
+                gap_lo=e[1] - e[0], gap_hi=e[3] - e[2])
+
+
+def main_batch(count):
+    path = os.path.join(HERE, "intervals_batch.json")
+    data = {}
+    for p in range(count):
+        data[str(p)] = batch_interval(p)
+        print(p, data[str(p)], flush=True)
+        with open(path, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+
+
 def main(names):
     path = os.path.join(HERE, "intervals.json")
     data = {}
@@ -72,4 +99,7 @@ def main(names):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:])
+    if sys.argv[1:2] == ["--batch"]:
+        main_batch(int(sys.argv[2]))
+    else:
+        main(sys.argv[1:])

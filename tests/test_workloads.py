@@ -1,0 +1,40 @@
+"""CPU checks of the stored search intervals: each holds exactly the number
+of eigenvalues its workload names (Sylvester inertia of the oracle), with
+both ends strictly inside spectral gaps."""
+import json
+import os
+
+import pytest
+
+from oracle import feast_oracle as O
+from paper_0901_2665_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_named_intervals_hold_their_eigenvalue_count():
+    for name in ("chain800", "tb6400"):
+        p = W.make_pencil(name)
+        emin, emax = W.load_interval(name)
+        assert O.inertia_count(p, emax) - O.inertia_count(p, emin) == W.WORKLOADS[name]["n_eig"]
+
+
+@pytest.mark.parametrize("p", [2, 6])
+def test_batch_intervals_hold_their_eigenvalue_count(p):
+    data = json.load(open(os.path.join(GOLDEN, "intervals_batch.json")))
+    e = data[str(p)]
+    shape = W.batch_shape(p)
+    assert (e["nc"], e["b"], e["M0"]) == (shape["nc"], shape["b"], shape["M0"])
+    assert e["n_eig"] == shape["n_eig"] == round(0.6 * shape["M0"])
+    pen = W.batch_pencil(p)
+    assert O.inertia_count(pen, e["emax"]) - O.inertia_count(pen, e["emin"]) == e["n_eig"]
+    # the ends sit half-way between neighbouring eigenvalues
+    assert e["gap_lo"] > 0 and e["gap_hi"] > 0
+    assert O.inertia_count(pen, e["emin"] - 0.25 * e["gap_lo"]) == O.inertia_count(pen, e["emin"])
+
+
+def test_batch_shapes_follow_the_recipe():
+    for p in range(32):
+        s = W.batch_shape(p)
+        assert 50 <= s["nc"] <= 200 and s["b"] in (32, 48, 64) and 16 <= s["M0"] <= 64
+        assert s["Ne"] == 16 and s["k0"] == s["nc"] * s["b"] // 4

@@ -45,7 +45,7 @@
  *    1  not converged within max_loops (outputs hold the last loop)
  *    2  B_Q was not numerically positive definite in the last loop: the
  *       reduced problem was solved in the span of B_Q's eigenvectors with
- *       eigenvalue > 1e-14 max; dropped Ritz slots are returned last with
+ *       eigenvalue > 1e-10 max; dropped Ritz slots are returned last with
  *       lambda = NaN and a zero eigenvector
  *    3  no eigenvalue in the interval (M = 0)
  *    4  M = M0: the subspace is too small (Fig. 2 needs M0 > M)

@@ -221,7 +221,7 @@ def reduced_eig(AQ: np.ndarray, BQ: np.ndarray):
 
     Returns (eps ascending, Phi, fallback_used).  If B_Q is not s.p.d. the
     problem is solved in the span of B_Q's eigenvectors with eigenvalue
-    > 1e-14 * max; dropped slots get eps = NaN and Phi column 0, last."""
+    > 1e-10 * max; dropped slots get eps = NaN and Phi column 0, last."""
     m0 = AQ.shape[0]
     try:
         eps, Phi = scipy.linalg.eigh(AQ, BQ)
@@ -229,7 +229,7 @@ def reduced_eig(AQ: np.ndarray, BQ: np.ndarray):
     except np.linalg.LinAlgError:
         pass
     mu, V = np.linalg.eigh(BQ)
-    keep = mu > 1e-14 * np.max(mu)
+    keep = mu > 1e-10 * np.max(mu)
     T = V[:, keep] / np.sqrt(mu[keep])
     eps_k, W = np.linalg.eigh(T.T @ AQ @ T)
     eps = np.full(m0, np.nan)

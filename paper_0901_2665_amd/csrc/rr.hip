@@ -5,7 +5,7 @@
 //  1. Whitening T with T^T B_Q T = I: T = L^{-T} from the Cholesky factor
 //     B_Q = L L^T.  If a Cholesky pivot is not positive (B_Q not numerically
 //     s.p.d., Sec. III.B (ii)), B_Q = V diag(mu) V^T is diagonalised instead,
-//     T = V diag(mu^{-1/2}) on the directions with mu > 1e-14 max(mu), and
+//     T = V diag(mu^{-1/2}) on the directions with mu > 1e-10 max(mu), and
 //     the other columns of T are zero.
 //  2. C = T^T A_Q T, diagonalised by cyclic two-sided Jacobi rotations in a
 //     round-robin order (all n/2 disjoint rotations of a round at once);
@@ -363,7 +363,7 @@ __global__ __launch_bounds__(kThreads) void reduced_eig_kernel(const double *AQ,
     __syncthreads();
     double mumax = 0.0;
     for (int i = 0; i < n; ++i) mumax = fmax(mumax, sh.diag[i]);
-    if (tid < n) sh.dropped[tid] = !(sh.diag[tid] > 1e-14 * mumax);
+    if (tid < n) sh.dropped[tid] = !(sh.diag[tid] > 1e-10 * mumax);
     __syncthreads();
     for (int idx = tid; idx < nn * nn; idx += kThreads) {
       const int i = idx / nn, j = idx % nn;

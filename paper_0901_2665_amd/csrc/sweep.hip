@@ -23,9 +23,13 @@
 namespace feast {
 namespace {
 
+// LDS vector tile [plane][row][col] of BP x 8 complex values: the second
+// plane starts 16 doubles after the packed position, so that the two planes
+// of the rows one half-wave touches fall on different LDS banks.
 template <int BP>
 struct VecLds {
-  double v[2][2][BP][kTile];  // [buffer][plane][row][col]
+  static constexpr int PL = BP * kTile + 16;  // plane stride (doubles)
+  double v[2][2 * PL];                        // [buffer][plane ...]
 };
 
 // Matrix-operand fragments of one stored block for this lane: the product
@@ -67,11 +71,12 @@ __device__ __forceinline__ void frag_load(Frag<BP> &f, const double *M, int rb, 
 // halves the LDS reads but makes the matrix cores wait for all of them:
 // measured slower.)
 template <int BP>
-__device__ __forceinline__ void bvec_load(double (&b)[BP / 2], const double (*hv)[BP][kTile]) {
+__device__ __forceinline__ void bvec_load(double (&b)[BP / 2], const double *hv) {
+  constexpr int PL = VecLds<BP>::PL;
   const int l = lane_id();
   const int kl = l >> 4, n = l & 15, col = n & 7;
-  const double *h0 = (n < 8) ? &hv[0][0][0] : &hv[1][0][0];  // k < BP
-  const double *h1 = (n < 8) ? &hv[1][0][0] : &hv[0][0][0];  // k >= BP
+  const double *h0 = (n < 8) ? hv : hv + PL;  // k < BP
+  const double *h1 = (n < 8) ? hv + PL : hv;  // k >= BP
   const double s1 = (n < 8) ? -1.0 : 1.0;
 #pragma unroll
   for (int ks = 0; ks < BP / 4; ++ks) {
@@ -114,6 +119,28 @@ __device__ __forceinline__ d4 acc_load_vec(const double *src, int rb) {
   d4 a;
 #pragma unroll
   for (int r = 0; r < 4; ++r) a[r] = src[vec_off<BP>(rb, r)];
+  return a;
+}
+
+// Accumulator tile <-> LDS vector tile (padded plane stride).
+template <int BP>
+__device__ __forceinline__ int lds_off(int rb, int r) {
+  const int l = lane_id();
+  const int n = l & 15;
+  return (n >> 3) * VecLds<BP>::PL + (rb * 16 + acc_row(l, r)) * kTile + (n & 7);
+}
+
+template <int BP>
+__device__ __forceinline__ void lds_store_vec(double *dst, const d4 &acc, int rb) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) dst[lds_off<BP>(rb, r)] = acc[r];
+}
+
+template <int BP>
+__device__ __forceinline__ d4 lds_load_vec(const double *src, int rb) {
+  d4 a;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) a[r] = src[lds_off<BP>(rb, r)];
   return a;
 }
 
@@ -200,7 +227,7 @@ __global__ __launch_bounds__(BP * 8) void forward_kernel(SweepArgs a) {
 
   if (wrole) {
     const d4 h = rhs_load<BP>(R + start * rstride, a.m0p, rb, true);
-    acc_store_vec<BP>(&s.v[0][0][0][0], -h, rb);
+    lds_store_vec<BP>(s.v[0], -h, rb);
   }
   // matrix fragments and right-hand side tiles are loaded two steps ahead
   // (three buffers each)
@@ -226,7 +253,7 @@ __global__ __launch_bounds__(BP * 8) void forward_kernel(SweepArgs a) {
     vec_store_buf<BP>(G + c * vt, -acc, rb, !wrole);
     if (wrole) {
       if (more)
-        acc_store_vec<BP>(&s.v[cur ^ 1][0][0][0], -acc, rb);
+        lds_store_vec<BP>(s.v[cur ^ 1], -acc, rb);
       else
         acc_store_vec<BP>(TV + vt, acc, rb);  // c = -W~_m^T h~_m
     }
@@ -243,7 +270,7 @@ __global__ __launch_bounds__(BP * 8) void forward_kernel(SweepArgs a) {
   if (j < nsteps) step(j, f0, r0, f2, r2);
   if (j + 1 < nsteps) step(j + 1, f1, r1, f0, r0);
   if (top && wrole) {
-    const d4 u = acc_load_vec<BP>(&s.v[cur][0][0][0], rb);
+    const d4 u = lds_load_vec<BP>(s.v[cur], rb);
     acc_store_vec<BP>(TV, -u, rb);  // h_{m-1}
   }
 }
@@ -302,7 +329,7 @@ __global__ __launch_bounds__(BP * 4) void back_kernel(SweepArgs a) {
   {
     d4 t = acc_load_vec<BP>(TV, rb);
     if (nc - m > 0) t += acc_load_vec<BP>(TV + vt, rb);
-    acc_store_vec<BP>(&s.v[1][0][0][0], t, rb);
+    lds_store_vec<BP>(s.v[1], t, rb);
   }
   frag_load<BP>(f1, WT + cell(0) * blk, rb, count > 0);
   d4 ga = vec_load_buf<BP>(G + cell(0) * vt, rb, count > 0), gb = d4zero();
@@ -311,7 +338,7 @@ __global__ __launch_bounds__(BP * 4) void back_kernel(SweepArgs a) {
     double b[BP / 2];
     bvec_load<BP>(b, s.v[1]);
     const d4 x = frag_mfma<BP>(d4zero(), f0, b);
-    acc_store_vec<BP>(&s.v[0][0][0][0], -x, rb);
+    lds_store_vec<BP>(s.v[0], -x, rb);
     if (top) emit(m - 1, x);
   }
   __syncthreads();
@@ -326,7 +353,7 @@ __global__ __launch_bounds__(BP * 4) void back_kernel(SweepArgs a) {
     double b[BP / 2];
     bvec_load<BP>(b, s.v[cur]);
     const d4 x = frag_mfma<BP>(g, f, b);
-    acc_store_vec<BP>(&s.v[cur ^ 1][0][0][0], -x, rb);
+    lds_store_vec<BP>(s.v[cur ^ 1], -x, rb);
     emit(c, x);
     __syncthreads();
     cur ^= 1;

@@ -10,8 +10,8 @@
 //  2. C = T^T A_Q T, diagonalised by cyclic two-sided Jacobi rotations in a
 //     round-robin order (all n/2 disjoint rotations of a round at once);
 //     a rotation is skipped when |c_pq| <= u sqrt(|c_pp c_qq|) or
-//     |c_pq| <= u ||C||_F / 8 (u = 2^-53), and the sweeps stop after a sweep
-//     without rotations.
+//     |c_pq| <= u ||C||_F / 8 (u = 2^-53), and the sweeps stop when no pair
+//     would rotate.
 //  3. eps ascending (dropped directions: NaN, last), Phi = T V.
 #include "common.h"
 #include "kernels.h"
@@ -238,6 +238,22 @@ __device__ int jacobi(double *C, int ldc, int nn, RRShared &sh) {
     const int rot = sh.rot;
     __syncthreads();
     if (rot == 0) break;
+    // Would a further sweep rotate anything?  C does not change during a
+    // sweep without rotations, so testing every pair at once decides it as
+    // that sweep would, without its 127 rounds.
+    bool need = false;
+    for (int idx = tid; idx < nn * nn; idx += kThreads) {
+      const int p = idx / nn, q = idx % nn;
+      if (p < q) {
+        const double apq = C[p * ldc + q];
+        need |= fabs(apq) > floor_abs &&
+                fabs(apq) > eps * sqrt(fabs(C[p * ldc + p] * C[q * ldc + q]));
+      }
+    }
+    if (!__syncthreads_or(need)) {
+      ++sweep;  // this sweep rotated; none is left to do
+      break;
+    }
   }
   if (spend >= 0) v_update(spend, sh.csn[(g & 1) ^ 1]);
   // every sweep ends at circle position 0: lane la holds the players

@@ -24,6 +24,7 @@ constexpr int kMaxN = 128;
 
 struct RRShared {
   double2 csn[2][kMaxN / 2];  // (cos, sin) of each pair slot, rounds of even / odd parity
+  double4 dnew[kMaxN / 2];    // a round's new diagonal block of each slot
   int rot;
   int fail;
   double norm;
@@ -33,52 +34,53 @@ struct RRShared {
   double diag[kMaxN];
 };
 
-__device__ __forceinline__ int rr_player(int s, int i, int nn) {
-  // circle method: player 0 fixed, the others rotate by one place a round
-  // (0 <= s < nn - 1, so one conditional subtraction is the modulo)
-  if (i == 0) return 0;
-  int x = i - 1 + s;
-  if (x >= nn - 1) x -= nn - 1;
-  return 1 + x;
-}
-
 constexpr int kMaxSweeps = 60;
 
 // Eigenvector layout: VT (LDS, row stride kVTld, rows 16-byte aligned)
 // holds VT[c][r] = V[r][c].
 constexpr int kVTld = kMaxN + 2;
 
-// v from lane l+1 (wave_shl:1) and from lane l-1 (wave_shr:1), 64-bit;
-// a lane without a source keeps `edge`
-__device__ __forceinline__ double lane_next(double v, double edge) {
-  const u32x2 x = __builtin_bit_cast(u32x2, v), o = __builtin_bit_cast(u32x2, edge);
-  return __builtin_bit_cast(
-      double,
-      (u32x2){(unsigned)__builtin_amdgcn_update_dpp((int)o[0], (int)x[0], 0x130, 0xf, 0xf, false),
-              (unsigned)__builtin_amdgcn_update_dpp((int)o[1], (int)x[1], 0x130, 0xf, 0xf, false)});
+// v from lane l+1 (wave_rol:1, lane 63 from lane 0) and from lane l-1
+// (wave_ror:1, lane 0 from lane 63), 64-bit
+__device__ __forceinline__ double lane_rol(double v) {
+  const u32x2 x = __builtin_bit_cast(u32x2, v);
+  return __builtin_bit_cast(double,
+                            (u32x2){(unsigned)__builtin_amdgcn_mov_dpp((int)x[0], 0x134, 0xf, 0xf, false),
+                                    (unsigned)__builtin_amdgcn_mov_dpp((int)x[1], 0x134, 0xf, 0xf, false)});
 }
-__device__ __forceinline__ double lane_prev(double v, double edge) {
-  const u32x2 x = __builtin_bit_cast(u32x2, v), o = __builtin_bit_cast(u32x2, edge);
-  return __builtin_bit_cast(
-      double,
-      (u32x2){(unsigned)__builtin_amdgcn_update_dpp((int)o[0], (int)x[0], 0x138, 0xf, 0xf, false),
-              (unsigned)__builtin_amdgcn_update_dpp((int)o[1], (int)x[1], 0x138, 0xf, 0xf, false)});
+__device__ __forceinline__ double lane_ror(double v) {
+  const u32x2 x = __builtin_bit_cast(u32x2, v);
+  return __builtin_bit_cast(double,
+                            (u32x2){(unsigned)__builtin_amdgcn_mov_dpp((int)x[0], 0x13c, 0xf, 0xf, false),
+                                    (unsigned)__builtin_amdgcn_mov_dpp((int)x[1], 0x13c, 0xf, 0xf, false)});
 }
 
-
-// Cyclic Jacobi on the nn x nn symmetric matrix C (LDS, row stride ldc).
+// Cyclic Jacobi on the nn x nn symmetric matrix C (LDS, row stride ldc),
+// round-robin by the circle method: circle position x holds a player (an
+// index of C), pair slot a joins the positions a ("top") and nn-1-a
+// ("bottom"), and after each round every player but the one at position 0
+// moves one position down the circle (position 1 wraps to nn-1).
+//
+// During a sweep C is held in circle-position coordinates: entry (x, y) is
+// C at the players standing at x and y, upper triangle only (kept at
+// (min, max)).  A thread's 2x2 blocks (slots a < b) thus stay at fixed
+// addresses, and each round writes its rotated entries to where their
+// players stand in the next round, also fixed addresses: all index work is
+// done once per call.  After nn-1 rounds every player is back at its start,
+// so between sweeps C is in plain coordinates.  The rotation of slot a is
+// taken in (top, bottom) order, x_top' = c x_top - s x_bot,
+// x_bot' = s x_top + c x_bot; the lanes of wave 0 compute the rotations and
+// also update the slots' diagonal 2x2 blocks.
+//
 // The eigenvectors V = J_1 J_2 ... accumulate in registers while C is
-// rotated: a round rotates column pairs of V and every row of V evolves on
-// its own, so wave w keeps the rows [8w, 8w+8) of V (16 waves cover 128) and
-// lane a the two columns of pair slot a (the players at circle positions a
-// and nn-1-a).  After each round the players move one position along the
-// circle and their data with them: a lane takes its new top column from lane
-// a+1 and its new bottom column from lane a-1 (wavefront lane shifts), with
-// the turning points at lanes 0 and half-1.  On return sh.diag holds the
-// eigenvalues (diagonal of C) and VT (which overlays C) the eigenvectors.
-// Returns the number of sweeps that rotated (the final check sweep, which
-// rotates nothing, is not counted).
-__device__ int jacobi(double *C, int ldc, int nn, RRShared &sh) {
+// rotated: every row of V evolves on its own, so wave w keeps the rows
+// [8w, 8w+8) of V (16 waves cover 128) and lane a the two columns of slot a.
+// After each round the columns move with their players: a lane takes its
+// new top column from lane a+1 and its new bottom column from lane a-1
+// (wavefront lane shifts), with the turning points at lanes 0 and half-1.
+// On return sh.diag holds the eigenvalues (diagonal of C) and VT (which
+// overlays C) the eigenvectors.  Returns the number of sweeps that rotated.
+__device__ __forceinline__ int jacobi(double *C, int ldc, int nn, RRShared &sh) {
   const int tid = threadIdx.x;
   const int half = nn / 2;
   const double eps = 1.1102230246251565e-16;  // 2^-53
@@ -100,89 +102,87 @@ __device__ int jacobi(double *C, int ldc, int nn, RRShared &sh) {
   }
   __syncthreads();
   const double floor_abs = 0.125 * eps * sqrt(sh.norm);
-  // The sweeps keep only the upper triangle of C up to date (entry (i, j) is
-  // read and written at (min, max)).  The 2x2 blocks (a, b), a <= b, of the
-  // pair slots are dealt out to the threads once; a thread keeps its blocks
-  // (at most 3 for nn <= 128) in registers.
-  constexpr int kPer = (kMaxN / 2 * (kMaxN / 2 + 1) / 2 + kThreads - 1) / kThreads;
-  const int nblk = half * (half + 1) / 2;
-  int ba[kPer], bb[kPer];
+  // where the player at position x stands in the next round, and the
+  // offset of entry (x, y) in the upper triangle
+  auto mv = [&](int x) { return x == 0 ? 0 : (x == 1 ? nn - 1 : x - 1); };
+  auto sym = [&](int x, int y) { return x < y ? x * ldc + y : y * ldc + x; };
+  // The off-diagonal 2x2 blocks (a, b), a < b, of the pair slots are dealt
+  // out to the threads once (at most 2 each for nn <= 128); entry k of a
+  // block is (top/bottom of a, top/bottom of b) = (k >> 1, k & 1).
+  constexpr int kPer = (kMaxN / 2 * (kMaxN / 2 - 1) / 2 + kThreads - 1) / kThreads;
+  const int nblk = half * (half - 1) / 2;
+  int ba[kPer], bb[kPer], rd[kPer][4], wr[kPer][4];
 #pragma unroll
   for (int t = 0; t < kPer; ++t) {
     int idx = tid + t * kThreads;
     ba[t] = -1;
-    bb[t] = -1;
-    if (idx < nblk) {  // row a of the block triangle holds half - a blocks
+    bb[t] = 0;
+    if (idx < nblk) {  // row a of the block triangle holds half - 1 - a blocks
       int a = 0;
-      while (idx >= half - a) {
-        idx -= half - a;
+      while (idx >= half - 1 - a) {
+        idx -= half - 1 - a;
         ++a;
       }
       ba[t] = a;
-      bb[t] = a + idx;
+      bb[t] = a + 1 + idx;
+    }
+    const int xa[2] = {ba[t] < 0 ? 0 : ba[t], nn - 1 - (ba[t] < 0 ? 0 : ba[t])};
+    const int xb[2] = {bb[t], nn - 1 - bb[t]};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      rd[t][k] = sym(xa[k >> 1], xb[k & 1]);
+      wr[t][k] = sym(mv(xa[k >> 1]), mv(xb[k & 1]));
     }
   }
-  auto at = [&](int i, int j) -> double & {
-    return i < j ? C[i * ldc + j] : C[j * ldc + i];
-  };
+
   const int lw = tid >> 6, la = tid & 63;
   const int r0 = 8 * lw;
-  double top[8], bot[8];  // V[r0 + k][player at position la / nn-1-la]
-  {
-    const int pt = rr_player(0, la, nn), pb = rr_player(0, nn - 1 - la, nn);
+  // V[r0 + k][player at position la / nn-1-la].  Every round applies the
+  // rotations of the round before and then moves the players, the first
+  // round too, with identity rotations: V starts as the identity in the
+  // positions of the round before, where position x holds player mv(x).
+  double top[8], bot[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      top[k] = (la < half && pt == r0 + k) ? 1.0 : 0.0;
-      bot[k] = (la < half && pb == r0 + k) ? 1.0 : 0.0;
-    }
+  for (int k = 0; k < 8; ++k) {
+    top[k] = (la < half && mv(la) == r0 + k) ? 1.0 : 0.0;
+    bot[k] = (la < half && mv(nn - 1 - la) == r0 + k) ? 1.0 : 0.0;
   }
-  // V <- V J of round position sp with rotations rv: columns (p, q) =
-  // (min, max) of slot la, x_p' = c x_p - s x_q, x_q' = s x_p + c x_q (in
-  // (top, bottom) order the sine flips sign when the top player is the larger
-  // index); then the players move one circle position (player 0 stays).
-  // Each round's update runs during the next round's rotation phase (its
-  // rotations stay in the other half of the double-buffered csn).
-  auto v_update = [&](int sp, const double2 *rv) {
-    const double2 r = rv[la < half ? la : 0];
-    const double c = la < half ? r.x : 1.0;
-    const int u = rr_player(sp, la, nn), v = rr_player(sp, nn - 1 - la, nn);
-    const double sg = la < half ? (u < v ? r.y : -r.y) : 0.0;
+  if (tid < half) sh.csn[1][tid] = double2{1.0, 0.0};
+  // V <- V J with the rotations rv of a round, then the players move one
+  // circle position (player 0 stays): a lane's new top column comes from
+  // lane a+1 and its new bottom column from lane a-1, with the turning
+  // points at lanes 0 and half-1.  Each round's update runs during the next
+  // round's rotation phase (its rotations stay in the other half of the
+  // double-buffered csn).  Lanes a >= half carry values that are never used.
+  auto v_update = [&](const double2 *rv) {
+    const double2 r = rv[la];
+    const double c = r.x, sg = r.y;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const double t = top[k], b = bot[k];
       top[k] = c * t - sg * b;
       bot[k] = sg * t + c * b;
     }
-    if (half == 64) {  // the shifts' edge lanes are the turning points
+    if (nn > 2) {
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
-        const double st = lane_next(top[k], bot[k]);  // lane 63 takes its own bottom
-        bot[k] = lane_prev(bot[k], st);               // lane 0 takes lane 1's top
-        top[k] = la == 0 ? top[k] : st;
-      }
-    } else if (nn > 2) {
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const double st = lane_next(top[k], bot[k]), sb = lane_prev(bot[k], st);
-        const double nt = la == 0 ? top[k] : (la == half - 1 ? bot[k] : st);
-        bot[k] = la == 0 ? st : sb;
-        top[k] = nt;
+        const double rt = lane_rol(top[k]), rb = lane_ror(bot[k]);
+        top[k] = la == 0 ? top[k] : (la == half - 1 ? bot[k] : rt);
+        bot[k] = la == 0 ? rt : rb;
       }
     }
   };
-  int g = 0;        // rounds done; csn[g & 1] holds the current round's rotations
-  int spend = -1;   // circle position of the round whose V update is pending
+  int g = 0;  // rounds done; csn[g & 1] holds the current round's rotations
   int sweep = 0;
   for (; sweep < kMaxSweeps; ++sweep) {
     if (tid == 0) sh.rot = 0;
     __syncthreads();
     for (int s = 0; s < nn - 1; ++s) {
       double2 *csn = sh.csn[g & 1];
-      if (tid < half) {  // one wave: rotation of slot tid
-        const int u = rr_player(s, tid, nn), v = rr_player(s, nn - 1 - tid, nn);
-        const int p = u < v ? u : v, q = u < v ? v : u;
-        const double app = C[p * ldc + p], aqq = C[q * ldc + q], apq = C[p * ldc + q];
-        double c = 1.0, sgn = 0.0;
+      if (tid < half) {  // one wave: rotation of slot tid and its diagonal block
+        const int xt = tid, xbt = nn - 1 - tid;
+        const double app = C[xt * ldc + xt], aqq = C[xbt * ldc + xbt], apq = C[xt * ldc + xbt];
+        double c = 1.0, sgn = 0.0, t = 0.0;
         const bool rotate =
             fabs(apq) > floor_abs && fabs(apq) > eps * sqrt(fabs(app * aqq));
         if (rotate) {
@@ -190,49 +190,49 @@ __device__ int jacobi(double *C, int ldc, int nn, RRShared &sh) {
           const double tau = (aqq - app) * rcp_newton(2.0 * apq);
           const double ata = fabs(tau);
           const double root = ata < 1e150 ? sqrt(1.0 + tau * tau) : ata;
-          const double t = (tau >= 0.0 ? 1.0 : -1.0) * rcp_newton(ata + root);
+          t = (tau >= 0.0 ? 1.0 : -1.0) * rcp_newton(ata + root);
           c = rcp_newton(sqrt(1.0 + t * t));
           sgn = t * c;
         }
+        // the new diagonal block, written to C after the barrier
+        sh.dnew[tid] = double4{app - t * apq, aqq + t * apq, rotate ? 0.0 : apq, 0.0};
         const unsigned long long m = __ballot(rotate);
         if (tid == 0) sh.rot += __popcll(m);
         csn[tid] = double2{c, sgn};
       }
-      if (spend >= 0) v_update(spend, sh.csn[(g & 1) ^ 1]);
-      __syncthreads();
-      // C <- J^T C J on the thread's 2x2 blocks
+      v_update(sh.csn[(g & 1) ^ 1]);
+      // the blocks' entries: every entry is read before the barrier, as the
+      // writes after it go to other threads' entries
+      double x[kPer][4];
 #pragma unroll
       for (int t = 0; t < kPer; ++t) {
-        const int a = ba[t], bq = bb[t];
-        if (a < 0) continue;
-        const double2 ra = csn[a], rb = csn[bq];
-        const double ca = ra.x, sa = ra.y, cb = rb.x, sb = rb.y;
-        int pa = rr_player(s, a, nn), qa = rr_player(s, nn - 1 - a, nn);
-        if (pa > qa) { const int x = pa; pa = qa; qa = x; }
-        if (a == bq) {
-          if (sa != 0.0) {
-            const double app = C[pa * ldc + pa], aqq = C[qa * ldc + qa], apq = C[pa * ldc + qa];
-            const double tq = sa / ca;
-            C[pa * ldc + pa] = app - tq * apq;
-            C[qa * ldc + qa] = aqq + tq * apq;
-            C[pa * ldc + qa] = 0.0;
-          }
-          continue;
-        }
-        if (sa == 0.0 && sb == 0.0) continue;
-        int pb = rr_player(s, bq, nn), qb = rr_player(s, nn - 1 - bq, nn);
-        if (pb > qb) { const int x = pb; pb = qb; qb = x; }
-        double &e11 = at(pa, pb), &e12 = at(pa, qb), &e21 = at(qa, pb), &e22 = at(qa, qb);
-        const double x11 = e11, x12 = e12, x21 = e21, x22 = e22;
-        const double y11 = cb * x11 - sb * x12, y12 = sb * x11 + cb * x12;
-        const double y21 = cb * x21 - sb * x22, y22 = sb * x21 + cb * x22;
-        e11 = ca * y11 - sa * y21;
-        e21 = sa * y11 + ca * y21;
-        e12 = ca * y12 - sa * y22;
-        e22 = sa * y12 + ca * y22;
+        if (ba[t] < 0) continue;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) x[t][k] = C[rd[t][k]];
       }
       __syncthreads();
-      spend = s;
+      // C <- J^T C J, written in the next round's positions
+      if (tid < half) {
+        const int xt = mv(tid), xbt = mv(nn - 1 - tid);
+        const double4 d = sh.dnew[tid];
+        C[xt * ldc + xt] = d.x;
+        C[xbt * ldc + xbt] = d.y;
+        C[sym(xt, xbt)] = d.z;
+      }
+#pragma unroll
+      for (int t = 0; t < kPer; ++t) {
+        if (ba[t] < 0) continue;
+        const double2 ra = csn[ba[t]], rb = csn[bb[t]];
+        const double ca = ra.x, sa = ra.y, cb = rb.x, sb = rb.y;
+        const double x11 = x[t][0], x12 = x[t][1], x21 = x[t][2], x22 = x[t][3];
+        const double y11 = cb * x11 - sb * x12, y12 = sb * x11 + cb * x12;
+        const double y21 = cb * x21 - sb * x22, y22 = sb * x21 + cb * x22;
+        C[wr[t][0]] = ca * y11 - sa * y21;
+        C[wr[t][1]] = ca * y12 - sa * y22;
+        C[wr[t][2]] = sa * y11 + ca * y21;
+        C[wr[t][3]] = sa * y12 + ca * y22;
+      }
+      __syncthreads();
       ++g;
     }
     const int rot = sh.rot;
@@ -240,7 +240,7 @@ __device__ int jacobi(double *C, int ldc, int nn, RRShared &sh) {
     if (rot == 0) break;
     // Would a further sweep rotate anything?  C does not change during a
     // sweep without rotations, so testing every pair at once decides it as
-    // that sweep would, without its 127 rounds.
+    // that sweep would, without its nn - 1 rounds.
     bool need = false;
     for (int idx = tid; idx < nn * nn; idx += kThreads) {
       const int p = idx / nn, q = idx % nn;
@@ -255,19 +255,18 @@ __device__ int jacobi(double *C, int ldc, int nn, RRShared &sh) {
       break;
     }
   }
-  if (spend >= 0) v_update(spend, sh.csn[(g & 1) ^ 1]);
-  // every sweep ends at circle position 0: lane la holds the players
-  // rr_player(0, la) and rr_player(0, nn-1-la)
+  v_update(sh.csn[(g & 1) ^ 1]);
+  // every sweep ends with each player at its start: lane la holds the
+  // columns la and nn-1-la
   if (tid < nn) sh.diag[tid] = C[tid * ldc + tid];
   __syncthreads();
   if (la < half && r0 < nn) {  // rows r0..r0+7 of every column: all of VT that is read
-    const int pt = rr_player(0, la, nn), pb = rr_player(0, nn - 1 - la, nn);
-    double2 *xt = reinterpret_cast<double2 *>(C + pt * kVTld + r0);
-    double2 *xb = reinterpret_cast<double2 *>(C + pb * kVTld + r0);
+    double2 *xt2 = reinterpret_cast<double2 *>(C + la * kVTld + r0);
+    double2 *xb2 = reinterpret_cast<double2 *>(C + (nn - 1 - la) * kVTld + r0);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      xt[k] = double2{top[2 * k], top[2 * k + 1]};
-      xb[k] = double2{bot[2 * k], bot[2 * k + 1]};
+      xt2[k] = double2{top[2 * k], top[2 * k + 1]};
+      xb2[k] = double2{bot[2 * k], bot[2 * k + 1]};
     }
   }
   __syncthreads();

@@ -1,6 +1,6 @@
 // Reduced generalized eigenproblem of the Rayleigh-Ritz step (Sec. III.A,
-// eqs. 6-9): A_Q Phi = eps B_Q Phi with Phi^T B_Q Phi = I, for M0 <= 128, in
-// one workgroup, all in float64.
+// eqs. 6-9): A_Q Phi = eps B_Q Phi with Phi^T B_Q Phi = I, for M0 <= 128,
+// all in float64.
 //
 //  1. Whitening T with T^T B_Q T = I: T = L^{-T} from the Cholesky factor
 //     B_Q = L L^T.  If a Cholesky pivot is not positive (B_Q not numerically
@@ -13,6 +13,12 @@
 //     |c_pq| <= u ||C||_F / 8 (u = 2^-53), and the sweeps stop when no pair
 //     would rotate.
 //  3. eps ascending (dropped directions: NaN, last), Phi = T V.
+//
+// kSplit workgroups run steps 1-2 on identical data with identical
+// arithmetic, so their rotations agree bit for bit; each keeps only its own
+// rows of V (the rows of V evolve independently), which cuts the per-round
+// eigenvector work of a workgroup by kSplit.  Workgroup 0 sorts; a second
+// kernel forms Phi = T V.
 #include "common.h"
 #include "kernels.h"
 
@@ -21,6 +27,7 @@ namespace {
 
 constexpr int kThreads = 1024;
 constexpr int kMaxN = 128;
+constexpr int kSplit = 4;  // workgroups; each keeps kMaxN / kSplit rows of V
 
 struct RRShared {
   double2 csn[2][kMaxN / 2];  // (cos, sin) of each pair slot, rounds of even / odd parity
@@ -30,7 +37,6 @@ struct RRShared {
   double norm;
   double red[kThreads];
   int dropped[kMaxN];
-  int rank[kMaxN];
   double diag[kMaxN];
 };
 
@@ -78,9 +84,14 @@ __device__ __forceinline__ double lane_ror(double v) {
 // After each round the columns move with their players: a lane takes its
 // new top column from lane a+1 and its new bottom column from lane a-1
 // (wavefront lane shifts), with the turning points at lanes 0 and half-1.
-// On return sh.diag holds the eigenvalues (diagonal of C) and VT (which
-// overlays C) the eigenvectors.  Returns the number of sweeps that rotated.
-__device__ __forceinline__ int jacobi(double *C, int ldc, int nn, RRShared &sh) {
+// A wave keeps R rows of V, the workgroup the rows [row0, row0 + 16 R).
+// On return sh.diag holds the eigenvalues (diagonal of C), and the
+// eigenvectors are in VT (which overlays C; R = 8, all rows) or, for R < 8,
+// the workgroup's rows in Vout (Vout[c * nn + r] = V[r][c]).  Returns the
+// number of sweeps that rotated.
+template <int R>
+__device__ __forceinline__ int jacobi(double *C, int ldc, int nn, RRShared &sh, int row0,
+                                      double *Vout) {
   const int tid = threadIdx.x;
   const int half = nn / 2;
   const double eps = 1.1102230246251565e-16;  // 2^-53
@@ -136,14 +147,14 @@ __device__ __forceinline__ int jacobi(double *C, int ldc, int nn, RRShared &sh) 
   }
 
   const int lw = tid >> 6, la = tid & 63;
-  const int r0 = 8 * lw;
+  const int r0 = row0 + R * lw;
   // V[r0 + k][player at position la / nn-1-la].  Every round applies the
   // rotations of the round before and then moves the players, the first
   // round too, with identity rotations: V starts as the identity in the
   // positions of the round before, where position x holds player mv(x).
-  double top[8], bot[8];
+  double top[R], bot[R];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
+  for (int k = 0; k < R; ++k) {
     top[k] = (la < half && mv(la) == r0 + k) ? 1.0 : 0.0;
     bot[k] = (la < half && mv(nn - 1 - la) == r0 + k) ? 1.0 : 0.0;
   }
@@ -158,14 +169,14 @@ __device__ __forceinline__ int jacobi(double *C, int ldc, int nn, RRShared &sh) 
     const double2 r = rv[la];
     const double c = r.x, sg = r.y;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < R; ++k) {
       const double t = top[k], b = bot[k];
       top[k] = c * t - sg * b;
       bot[k] = sg * t + c * b;
     }
     if (nn > 2) {
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
+      for (int k = 0; k < R; ++k) {
         const double rt = lane_rol(top[k]), rb = lane_ror(bot[k]);
         top[k] = la == 0 ? top[k] : (la == half - 1 ? bot[k] : rt);
         bot[k] = la == 0 ? rt : rb;
@@ -260,13 +271,23 @@ __device__ __forceinline__ int jacobi(double *C, int ldc, int nn, RRShared &sh) 
   // columns la and nn-1-la
   if (tid < nn) sh.diag[tid] = C[tid * ldc + tid];
   __syncthreads();
-  if (la < half && r0 < nn) {  // rows r0..r0+7 of every column: all of VT that is read
-    double2 *xt2 = reinterpret_cast<double2 *>(C + la * kVTld + r0);
-    double2 *xb2 = reinterpret_cast<double2 *>(C + (nn - 1 - la) * kVTld + r0);
+  if constexpr (R == 8) {
+    if (la < half && r0 < nn) {  // rows r0..r0+7 of every column: all of VT that is read
+      double2 *xt2 = reinterpret_cast<double2 *>(C + la * kVTld + r0);
+      double2 *xb2 = reinterpret_cast<double2 *>(C + (nn - 1 - la) * kVTld + r0);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      xt2[k] = double2{top[2 * k], top[2 * k + 1]};
-      xb2[k] = double2{bot[2 * k], bot[2 * k + 1]};
+      for (int k = 0; k < 4; ++k) {
+        xt2[k] = double2{top[2 * k], top[2 * k + 1]};
+        xb2[k] = double2{bot[2 * k], bot[2 * k + 1]};
+      }
+    }
+  } else if (la < half) {
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      if (r0 + k < nn) {
+        Vout[la * nn + r0 + k] = top[k];
+        Vout[(nn - 1 - la) * nn + r0 + k] = bot[k];
+      }
     }
   }
   __syncthreads();
@@ -303,9 +324,13 @@ __global__ __launch_bounds__(kThreads) void reduced_eig_kernel(const double *AQ,
   const int nn = n + (n & 1);
   const int ldc = nn + 1;
   const int nt = (nn + 15) / 16;
-  double *T = scratch;                 // nn x nn whitening
-  double *T1 = scratch + nn * nn;      // nn x nn product
-  double *V = scratch + 2 * nn * nn;   // nn x nn eigenvectors of B_Q (fallback)
+  // per workgroup: whitening T, product T1, eigenvectors V of B_Q (fallback),
+  // each nn x nn; then the shared outputs VT (kMaxN^2) and rank (kMaxN ints)
+  double *T = scratch + (size_t)blockIdx.x * 3 * kMaxN * kMaxN;
+  double *T1 = T + nn * nn;
+  double *V = T + 2 * nn * nn;
+  double *VTg = scratch + (size_t)kSplit * 3 * kMaxN * kMaxN;
+  int *rank_g = reinterpret_cast<int *>(VTg + kMaxN * kMaxN);
 
   for (int idx = tid; idx < nn * nn; idx += kThreads) {
     const int i = idx / nn, j = idx % nn;
@@ -372,8 +397,8 @@ __global__ __launch_bounds__(kThreads) void reduced_eig_kernel(const double *AQ,
       C[i * ldc + j] = (i < n && j < n) ? BQ[i * n + j] : 0.0;
     }
     __syncthreads();
-    const int fsweeps = jacobi(C, ldc, nn, sh);
-    if (tid == 0) flag[2] = fsweeps;
+    const int fsweeps = jacobi<8>(C, ldc, nn, sh, 0, nullptr);
+    if (tid == 0 && blockIdx.x == 0) flag[2] = fsweeps;
     for (int idx = tid; idx < nn * nn; idx += kThreads) V[idx] = C[(idx % nn) * kVTld + idx / nn];
     __syncthreads();
     double mumax = 0.0;
@@ -411,11 +436,12 @@ __global__ __launch_bounds__(kThreads) void reduced_eig_kernel(const double *AQ,
   }
   __syncthreads();
 
-  const int sweeps = jacobi(C, ldc, nn, sh);
+  constexpr int kR = 8 / kSplit;
+  const int sweeps = jacobi<kR>(C, ldc, nn, sh, blockIdx.x * 16 * kR, VTg);
+  if (blockIdx.x != 0) return;
   if (tid == 0) flag[1] = sweeps;
 
   // ---- sort ascending, dropped directions (NaN) last ----
-  const double *VT = C;  // eigenvectors of C (transposed)
   if (tid < n) {
     const int i = tid;
     int rk = 0;
@@ -428,21 +454,49 @@ __global__ __launch_bounds__(kThreads) void reduced_eig_kernel(const double *AQ,
       else before = (sh.diag[j] < sh.diag[i]) || (sh.diag[j] == sh.diag[i] && j < i);
       rk += before;
     }
-    sh.rank[i] = rk;
+    rank_g[i] = rk;
     eps[rk] = sh.dropped[i] ? __longlong_as_double(0x7ff8000000000000LL) : sh.diag[i];
   }
-  __syncthreads();
-  // Phi[:, rank[i]] = T V[:, i]
-  wg_gemm(
-      nt, [&](int r, int k) { return (r < nn && k < nn) ? T[r * nn + k] : 0.0; },
-      [&](int k, int c) { return (k < nn && c < nn) ? VT[c * kVTld + k] : 0.0; },
-      [&](int r, int c, double v) { if (r < n && c < n) Phi[r * n + sh.rank[c]] = v; });
   if (tid == 0) flag[0] = fallback ? 1 : 0;
+}
+
+// Phi[:, rank[c]] = T V[:, c] with T (nn x nn, row-major) of workgroup 0 and
+// VT[c * nn + r] = V[r][c]: one wave per 16 x 16 output tile.
+__global__ __launch_bounds__(64) void phi_kernel(const double *scratch, int n, double *Phi) {
+  const int nn = n + (n & 1);
+  const int nt = (nn + 15) / 16;
+  const double *T = scratch;
+  const double *VT = scratch + (size_t)kSplit * 3 * kMaxN * kMaxN;
+  const int *rank = reinterpret_cast<const int *>(VT + kMaxN * kMaxN);
+  const int l = threadIdx.x, kl = l >> 4;
+  const int r0 = blockIdx.y * 16, c0 = blockIdx.x * 16;
+  const int r = r0 + (l & 15), c = c0 + (l & 15);
+  d4 acc0 = d4zero(), acc1 = d4zero();
+  for (int k0 = 0; k0 < nt * 16; k0 += 8) {
+    const int ka = k0 + kl, kb = k0 + 4 + kl;
+    const double a0 = (r < nn && ka < nn) ? T[r * nn + ka] : 0.0;
+    const double a1 = (r < nn && kb < nn) ? T[r * nn + kb] : 0.0;
+    const double b0 = (c < nn && ka < nn) ? VT[c * nn + ka] : 0.0;
+    const double b1 = (c < nn && kb < nn) ? VT[c * nn + kb] : 0.0;
+    acc0 = mfma(a0, b0, acc0);
+    acc1 = mfma(a1, b1, acc1);
+  }
+  const d4 acc = acc0 + acc1;
+  if (c < n) {
+    const int rc = rank[c];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int rr = r0 + (l >> 4) + 4 * i;
+      if (rr < n) Phi[rr * n + rc] = acc[i];
+    }
+  }
 }
 
 }  // namespace
 
-size_t reduced_eig_scratch_doubles() { return 3 * (size_t)kMaxN * kMaxN; }
+size_t reduced_eig_scratch_doubles() {
+  return (3 * kSplit + 1) * (size_t)kMaxN * kMaxN + kMaxN / 2;
+}
 
 hipError_t launch_reduced_eig(const double *AQ, const double *BQ, int n, double *eps, double *Phi,
                               double *scratch, int *flag, hipStream_t st) {
@@ -452,8 +506,12 @@ hipError_t launch_reduced_eig(const double *AQ, const double *BQ, int n, double 
   hipError_t err = hipFuncSetAttribute((const void *)reduced_eig_kernel,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(reduced_eig_kernel, dim3(1), dim3(kThreads), shm, st, AQ, BQ, n, eps, Phi,
+  hipLaunchKernelGGL(reduced_eig_kernel, dim3(kSplit), dim3(kThreads), shm, st, AQ, BQ, n, eps, Phi,
                      scratch, flag);
+  err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  const int nt = (nn + 15) / 16;
+  hipLaunchKernelGGL(phi_kernel, dim3(nt, nt), dim3(64), 0, st, scratch, n, Phi);
   return hipGetLastError();
 }
 

@@ -162,7 +162,11 @@ __device__ void store_block(double *g, const double *slot, bool transpose) {
 // In-place inverse of a 16x16 complex tile (LDS, planes re/im with row
 // stride ld) by one wave: Gauss-Jordan elimination without pivoting, the
 // tile held in registers (lane l: row l/4, columns 4(l%4)..4(l%4)+3), pivot
-// row and column exchanged with lane shuffles.
+// row and column exchanged with lane shuffles.  The division of a pivot row
+// by its pivot is deferred to one scaling of every row at the end (row j
+// keeps its values times a_jj; later steps act on rows linearly, so the
+// scaling commutes with them), which leaves one complex multiply-add per
+// element and step.
 // Lane broadcasts for the pivot steps: a uniform lane through the scalar
 // unit, a lane of each quad (lanes 4i..4i+3) through DPP.
 __device__ __forceinline__ double readlane_d(double x, int lane) {
@@ -197,40 +201,42 @@ __device__ __forceinline__ void inv16_wave(double *Xr, double *Xi, int ld) {
     ar[v] = Xr[r * ld + cb + v];
     ai[v] = Xi[r * ld + cb + v];
   }
+  cplx srow{1.0, 0.0};  // deferred scale of my row: 1 / its pivot
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
     const int vj = j & 3;
     const int pl = (j << 2) | (j >> 2);          // lane holding (j, j)
     const cplx piv = crecip_fast(cplx{readlane_d(ar[vj], pl), readlane_d(ai[vj], pl)});
     const int rl = (j << 2) | (l & 3);           // lane holding row j, my columns
-    cplx rk[4];
+    cplx rj[4];                                  // row j (unscaled), my columns
 #pragma unroll
-    for (int v = 0; v < 4; ++v) rk[v] = cmul(cplx{__shfl(ar[v], rl), __shfl(ai[v], rl)}, piv);
+    for (int v = 0; v < 4; ++v) rj[v] = cplx{__shfl(ar[v], rl), __shfl(ai[v], rl)};
     // my row, column j: lane j / 4 of my quad
     const cplx cj{quad_bcast(ar[vj], j >> 2), quad_bcast(ai[vj], j >> 2)};
-    const cplx m = cmul(cj, piv);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      ar[v] -= cj.re * rk[v].re - cj.im * rk[v].im;
-      ai[v] -= cj.re * rk[v].im + cj.im * rk[v].re;
-    }
-    if ((l & 3) == (j >> 2)) {  // column j: -a_rj / a_jj
-      ar[vj] = -m.re;
-      ai[vj] = -m.im;
-    }
-    if (r == j) {  // row j: a_jc / a_jj, pivot 1 / a_jj
+    const cplx m = cmul(cj, piv);                // a_rj / a_jj
+    if (r != j) {  // a_rc -= (a_rj / a_jj) a_jc; column j: -a_rj / a_jj
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const bool pv = (cb + v == j);
-        ar[v] = pv ? piv.re : rk[v].re;
-        ai[v] = pv ? piv.im : rk[v].im;
+        ar[v] = fma(m.im, rj[v].im, fma(-m.re, rj[v].re, ar[v]));
+        ai[v] = fma(-m.im, rj[v].re, fma(-m.re, rj[v].im, ai[v]));
       }
+      if ((l & 3) == (j >> 2)) {
+        ar[vj] = -m.re;
+        ai[vj] = -m.im;
+      }
+    } else {  // row j: unchanged but for the pivot entry, scaled at the end
+      if ((l & 3) == (j >> 2)) {
+        ar[vj] = 1.0;
+        ai[vj] = 0.0;
+      }
+      srow = piv;
     }
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    Xr[r * ld + cb + v] = ar[v];
-    Xi[r * ld + cb + v] = ai[v];
+    const cplx x = cmul(cplx{ar[v], ai[v]}, srow);
+    Xr[r * ld + cb + v] = x.re;
+    Xi[r * ld + cb + v] = x.im;
   }
 }
 

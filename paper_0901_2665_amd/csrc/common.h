@@ -100,14 +100,14 @@ __device__ __forceinline__ double rcp_newton(double d) {
   e = fma(-d, x, 1.0);
   return fma(x, e, x);
 }
-// 1/(a + ib) = (a - ib) / (a^2 + b^2), with the common factor scaled by the
-// larger component so that the squares neither overflow nor underflow.
+// 1/(a + ib) = (a - ib) / (a^2 + b^2), with a and b first scaled by the
+// power of two 2^-e of the larger component (exact), so that the squares
+// neither overflow nor underflow: 1/(a + ib) = 2^-e / (a' + ib').
 __device__ __forceinline__ cplx crecip_fast(cplx a) {
-  const double s = fmax(fabs(a.re), fabs(a.im));
-  const double rs = rcp_newton(s);
-  const double ar = a.re * rs, ai = a.im * rs;
-  const double inv = rcp_newton(ar * ar + ai * ai) * rs;
-  return {ar * inv, -ai * inv};
+  const int e = __builtin_amdgcn_frexp_exp(fmax(fabs(a.re), fabs(a.im)));
+  const double ar = __builtin_amdgcn_ldexp(a.re, -e), ai = __builtin_amdgcn_ldexp(a.im, -e);
+  const double inv = rcp_newton(fma(ar, ar, ai * ai));
+  return {__builtin_amdgcn_ldexp(ar * inv, -e), __builtin_amdgcn_ldexp(-ai * inv, -e)};
 }
 
 // Grid position -> work item, placing consecutive groups of `per_group`

@@ -147,6 +147,21 @@ __device__ void load_block(double *slot, const double *g) {
   }
 }
 
+// slot -> global block in the factor layout fpos, consecutive threads on
+// consecutive addresses: element gi of a plane holds (i, j) with
+// j = (gi / 2) % BP, R = (gi / 2) / BP, i = 8 (R / 4) + 4 (gi % 2) + R % 4.
+template <int BP>
+__device__ void store_block_fl(double *g, const double *slot, bool transpose) {
+  constexpr int LD = Lds<BP>::LD, PLANE = Lds<BP>::PLANE;
+  for (int gi = threadIdx.x; gi < BP * BP; gi += kThreads) {
+    const int j = (gi >> 1) % BP, R = (gi >> 1) / BP;
+    const int i = ((R >> 2) << 3) + ((gi & 1) << 2) + (R & 3);
+    const int s = transpose ? j * LD + i : i * LD + j;
+    g[gi] = slot[s];
+    g[BP * BP + gi] = slot[PLANE + s];
+  }
+}
+
 template <int BP, bool FL>
 __device__ void store_block(double *g, const double *slot, bool transpose) {
   constexpr int LD = Lds<BP>::LD, PLANE = Lds<BP>::PLANE;
@@ -398,13 +413,10 @@ __device__ __forceinline__ void gj_invert(Lds<BP> &s, double *gout, bool symm = 
         const int r = 4 * pi + u, c = 4 * pj + v;
         A[r * LD + c] = ar[u][v];
         A[PLANE + r * LD + c] = ai[u][v];
-        if (gout) {  // a block of Sinv: factor layout
-          gout[fpos<BP>(r, c)] = ar[u][v];
-          gout[BP * BP + fpos<BP>(r, c)] = ai[u][v];
-        }
       }
   }
   __syncthreads();
+  if (gout) store_block_fl<BP>(gout, A, false);  // a block of Sinv: factor layout
 }
 
 // Complex product on the matrix cores, operands in LDS slots:
@@ -579,7 +591,7 @@ __global__ __launch_bounds__(kThreads) void factor_chain_kernel(Pencil p, Shifts
       form_block<BP>(s.B, p.Au + c * bb, p.Bu + c * bb, b, zr, zi, false, false);
     else
       form_block<BP>(s.B, p.Au + (c - 1) * bb, p.Bu + (c - 1) * bb, b, zr, zi, true, false);
-    gj_invert<BP>(s, Sinv + c * blk);  // ends with a barrier
+    gj_invert<BP>(s, Sinv + c * blk);  // slot A: Sinv (read until the next barrier)
     DiagRegs<BP> dn;  // next diagonal block, loaded under the W product
     if (!last) diag_regs_load<BP>(dn, p.Ad + (c + dir) * bb, p.Bd + (c + dir) * bb, b);
     __syncthreads();
@@ -591,7 +603,7 @@ __global__ __launch_bounds__(kThreads) void factor_chain_kernel(Pencil p, Shifts
     acc_to_lds<BP>(s.A, wr, wi);
     acc_to_global<BP, true>(Wg + c * blk, wr, wi);
     __syncthreads();
-    store_block<BP, true>(WTg + c * blk, s.A, true);
+    store_block_fl<BP>(WTg + c * blk, s.A, true);
     if (!last) {
       d4 sr[NT], si[NT];
       acc_from_diag_regs<BP>(sr, si, dn, b, zr, zi);

@@ -432,7 +432,7 @@ __device__ __forceinline__ void cgemm_lds(d4 (&accr)[BP / 16], d4 (&acci)[BP / 1
   if (w >= NT) return;
   const int row = w * 16 + (l & 15);
   const int kl = l >> 4;
-#pragma unroll 2
+#pragma unroll  // a rolled loop moves the accumulators between register files each trip
   for (int k0 = 0; k0 < BP; k0 += 4) {
     const int k = k0 + kl;
     const int xa = transX ? k * LD + row : row * LD + k;

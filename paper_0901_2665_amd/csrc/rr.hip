@@ -48,6 +48,12 @@ constexpr int kVTld = kMaxN + 2;
 
 // v from lane l+1 (wave_rol:1, lane 63 from lane 0) and from lane l-1
 // (wave_ror:1, lane 0 from lane 63), 64-bit
+__device__ __forceinline__ double readlane_d(double x, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+  return __hiloint2double(hi, lo);
+}
+
 __device__ __forceinline__ double lane_rol(double v) {
   const u32x2 x = __builtin_bit_cast(u32x2, v);
   return __builtin_bit_cast(double,
@@ -340,22 +346,78 @@ __global__ __launch_bounds__(kThreads) void reduced_eig_kernel(const double *AQ,
   if (tid < kMaxN) sh.dropped[tid] = (tid >= n);
   __syncthreads();
 
-  // ---- Cholesky B_Q = L L^T (lower triangle of C) ----
-  for (int k = 0; k < n; ++k) {
-    const double d = C[k * ldc + k];
-    if (!(d > 0.0) || !isfinite(d)) {  // uniform decision
-      if (tid == 0) sh.fail = 1;
-      break;
+  // ---- Cholesky B_Q = L L^T (lower triangle of C), by 16-column panels ----
+  // Wave 0 factors the panel (its rows held in registers, two per lane,
+  // pivot column values broadcast with readlane); then every wave applies
+  // the panel to the trailing matrix on the matrix cores.  Entries above the
+  // diagonal are not kept.
+  for (int k0 = 0; k0 < n; k0 += 16) {
+    const int kw = n - k0 < 16 ? n - k0 : 16;
+    if (tid < 64) {
+      const int i0 = k0 + tid, i1 = k0 + 64 + tid;  // this lane's rows
+      double pr[2][16];
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj) {
+        pr[0][jj] = (i0 < n && jj < kw) ? C[i0 * ldc + k0 + jj] : 0.0;
+        pr[1][jj] = (i1 < n && jj < kw) ? C[i1 * ldc + k0 + jj] : 0.0;
+      }
+      bool ok = true;  // uniform: every test below is on wave-uniform values
+#pragma unroll
+      for (int kk = 0; kk < 16; ++kk) {
+        const double d = readlane_d(pr[0][kk], kk);  // pivot (k0+kk, k0+kk)
+        if (kk < kw && ok) {
+          if (!(d > 0.0) || !isfinite(d)) {
+            ok = false;
+          } else {
+            const double lkk = sqrt(d), rl = 1.0 / lkk;
+            pr[0][kk] = tid > kk ? pr[0][kk] * rl : (tid == kk ? lkk : pr[0][kk]);
+            pr[1][kk] *= rl;
+#pragma unroll
+            for (int jj = kk + 1; jj < 16; ++jj) {
+              const double ljk = readlane_d(pr[0][kk], jj);  // L(k0+jj, k0+kk)
+              pr[0][jj] -= pr[0][kk] * ljk;  // (columns jj >= kw are not stored)
+              pr[1][jj] -= pr[1][kk] * ljk;
+            }
+          }
+        }
+      }
+      if (!ok) {
+        if (tid == 0) sh.fail = 1;
+      } else {
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) {
+          if (jj < kw && i0 < n) C[i0 * ldc + k0 + jj] = pr[0][jj];
+          if (jj < kw && i1 < n) C[i1 * ldc + k0 + jj] = pr[1][jj];
+        }
+      }
     }
-    const double lkk = sqrt(d);
     __syncthreads();
-    for (int i = k + tid; i < n; i += kThreads)
-      C[i * ldc + k] = (i == k) ? lkk : C[i * ldc + k] / lkk;
-    __syncthreads();
-    const int m = n - k - 1;
-    for (int idx = tid; idx < m * m; idx += kThreads) {
-      const int i = k + 1 + idx / m, j = k + 1 + idx % m;
-      if (j <= i) C[i * ldc + j] -= C[i * ldc + k] * C[j * ldc + k];
+    if (sh.fail) break;  // uniform
+    // trailing update C(i, j) -= sum_k L(i, k) L(j, k), k in the panel,
+    // j <= i, over the 16 x 16 tiles below the panel
+    // (a panel narrower than 16 is the last one: nothing trails it, and
+    // otherwise t0 is a multiple of 16)
+    const int t0 = k0 + kw, tt0 = t0 / 16, ntr = nt - tt0;
+    if (t0 < n) {
+      const int l = tid & 63, kl = l >> 4;
+      for (int t = tid >> 6; t < ntr * ntr; t += kThreads / 64) {
+        const int ti = tt0 + t / ntr, tj = tt0 + t % ntr;
+        if (tj > ti) continue;
+        const int ra = ti * 16 + (l & 15), rb = tj * 16 + (l & 15);
+        d4 acc = d4zero();
+#pragma unroll
+        for (int q = 0; q < 16; q += 4) {
+          const int k = q + kl;
+          const double a = (ra < n && k < kw) ? C[ra * ldc + k0 + k] : 0.0;
+          const double bv = (rb < n && k < kw) ? C[rb * ldc + k0 + k] : 0.0;
+          acc = mfma(a, bv, acc);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = ti * 16 + (l >> 4) + 4 * r, j = tj * 16 + (l & 15);
+          if (i < n && j <= i && j >= t0) C[i * ldc + j] -= acc[r];
+        }
+      }
     }
     __syncthreads();
   }

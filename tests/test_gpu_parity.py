@@ -144,7 +144,8 @@ def rr_backward_error(AQ, BQ, eps, Phi):
     return np.max(np.linalg.norm(r, axis=0) / den)
 
 
-@pytest.mark.parametrize("n,cond", [(1, 1.0), (7, 10.0), (30, 1e2), (64, 1e3), (128, 1e3)])
+@pytest.mark.parametrize("n,cond", [(1, 1.0), (7, 10.0), (17, 10.0), (30, 1e2), (33, 1e2), (64, 1e3),
+                                    (100, 1e3), (128, 1e3)])
 def test_reduced_eig_well_conditioned(ctx, torch, n, cond):
     AQ, BQ = spd_pair(n, n, cond)
     eps, Phi, fb = ctx.reduced_eig(dev(torch, AQ), dev(torch, BQ))

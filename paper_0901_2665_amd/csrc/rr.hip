@@ -301,23 +301,55 @@ __device__ __forceinline__ int jacobi(double *C, int ldc, int nn, RRShared &sh, 
 }
 
 // Dense product of the workgroup on the matrix cores, n <= 128:
-//   out(r, c) = sum_k a(r, k) b(k, c),   0 <= r, c < nt*16,
-// with operand readers a, b (zero outside the matrices) and a writer.  The
-// 16 waves share the (nt x nt) output tiles.
+//   out(r, c) = sum_k a(r, k) b(k, c),   0 <= r, c < nl = nt*16,
+// with operand readers a, b (global memory, zero outside the matrices) and
+// a writer.  The operands pass through LDS (stage: kStageDoubles) in
+// 32-deep slices loaded with consecutive threads on consecutive k-major
+// elements; the 16 waves share the (nt x nt) output tiles and keep them in
+// registers until the last slice, so the writer may overwrite stage.
+constexpr int kSlice = 32;
+constexpr int kSA = kSlice + 1;      // row stride of the a slice [nl][kSA]
+constexpr int kSB = kMaxN + 1;       // row stride of the b slice [kSlice][kSB]
+constexpr int kStageDoubles = kMaxN * kSA + kSlice * kSB;
 template <typename FA, typename FB, typename FO>
-__device__ __forceinline__ void wg_gemm(int nt, FA a, FB b, FO out) {
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int kl = l >> 4;
-  for (int t = w; t < nt * nt; t += kThreads / 64) {
-    const int r0 = (t / nt) * 16, c0 = (t % nt) * 16;
-    d4 acc0 = d4zero(), acc1 = d4zero();
-    for (int k0 = 0; k0 < nt * 16; k0 += 8) {
-      acc0 = mfma(a(r0 + (l & 15), k0 + kl), b(k0 + kl, c0 + (l & 15)), acc0);
-      acc1 = mfma(a(r0 + (l & 15), k0 + 4 + kl), b(k0 + 4 + kl, c0 + (l & 15)), acc1);
-    }
-    const d4 acc = acc0 + acc1;
+__device__ __forceinline__ void wg_gemm(int nt, double *stage, FA a, FB b, FO out) {
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, kl = l >> 4;
+  const int nl = nt * 16;
+  double *sa = stage, *sb = stage + kMaxN * kSA;
+  constexpr int kPerW = kMaxN / 16 * (kMaxN / 16) / (kThreads / 64);  // tiles per wave, nt = 8
+  d4 acc[kPerW];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) out(r0 + (l >> 4) + 4 * r, c0 + (l & 15), acc[r]);
+  for (int q = 0; q < kPerW; ++q) acc[q] = d4zero();
+  for (int k0 = 0; k0 < nl; k0 += kSlice) {
+    const int kw = nl - k0 < kSlice ? nl - k0 : kSlice;
+    for (int idx = tid; idx < kw * nl; idx += kThreads) {
+      const int kk = idx / nl, x = idx % nl;
+      sa[x * kSA + kk] = a(x, k0 + kk);
+      sb[kk * kSB + x] = b(k0 + kk, x);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kPerW; ++q) {
+      const int t = w + q * (kThreads / 64);
+      if (t < nt * nt) {
+        const int r0 = (t / nt) * 16, c0 = (t % nt) * 16;
+        for (int kq = 0; kq < kw; kq += 4) {
+          const double av = sa[(r0 + (l & 15)) * kSA + kq + kl];
+          const double bv = sb[(kq + kl) * kSB + c0 + (l & 15)];
+          acc[q] = mfma(av, bv, acc[q]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < kPerW; ++q) {
+    const int t = w + q * (kThreads / 64);
+    if (t < nt * nt) {
+      const int r0 = (t / nt) * 16, c0 = (t % nt) * 16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) out(r0 + (l >> 4) + 4 * r, c0 + (l & 15), acc[q][r]);
+    }
   }
 }
 
@@ -476,13 +508,14 @@ __global__ __launch_bounds__(kThreads) void reduced_eig_kernel(const double *AQ,
 
   // ---- C = T^T A_Q T on the matrix cores ----
   const int nlim = nt * 16;
+  // (C's storage is free here and serves as the staging area)
   wg_gemm(
-      nt, [&](int r, int k) { return (r < n && k < n) ? AQ[k * n + r] : 0.0; },  // symmetric
+      nt, C, [&](int r, int k) { return (r < n && k < n) ? AQ[k * n + r] : 0.0; },  // symmetric
       [&](int k, int c) { return (k < nn && c < nn) ? T[k * nn + c] : 0.0; },
       [&](int r, int c, double v) { if (r < nn && c < nn) T1[r * nn + c] = v; });
   __syncthreads();
   wg_gemm(
-      nt, [&](int r, int k) { return (r < nn && k < nn) ? T[k * nn + r] : 0.0; },
+      nt, C, [&](int r, int k) { return (r < nn && k < nn) ? T[k * nn + r] : 0.0; },
       [&](int k, int c) { return (k < nn && c < nn) ? T1[k * nn + c] : 0.0; },
       [&](int r, int c, double v) { if (r < nn && c < nn) C[r * ldc + c] = v; });
   (void)nlim;
@@ -564,7 +597,9 @@ hipError_t launch_reduced_eig(const double *AQ, const double *BQ, int n, double 
                               double *scratch, int *flag, hipStream_t st) {
   if (n < 1 || n > kMaxN) return hipErrorInvalidValue;
   const int nn = n + (n & 1);
-  const size_t shm = (size_t)nn * (kVTld > nn + 1 ? kVTld : nn + 1) * sizeof(double);
+  size_t shm = (size_t)nn * (kVTld > nn + 1 ? kVTld : nn + 1);
+  if (shm < (size_t)kStageDoubles) shm = kStageDoubles;  // the products' staging area
+  shm *= sizeof(double);
   hipError_t err = hipFuncSetAttribute((const void *)reduced_eig_kernel,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   if (err != hipSuccess) return err;

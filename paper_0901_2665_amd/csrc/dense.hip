@@ -286,17 +286,36 @@ __global__ __launch_bounds__(kCellThreads) void cell_project_kernel(const double
 }
 
 // M = 0.5 (S + S^T), S = sum over the groups' partials (group order), m0 x m0
-__global__ void cell_project_reduce_kernel(const double *partial, int groups, int ld, int m0,
-                                           double *M) {
+// S = sum over the groups of their partial products, written to M: 64
+// outputs per block, each summed by four threads over interleaved groups and
+// combined in a fixed order (bitwise reproducible); symmetrize_kernel then
+// forms (S + S^T) / 2.
+__global__ __launch_bounds__(256) void cell_project_reduce_kernel(const double *partial, int groups,
+                                                                  int ld, int m0, double *M) {
+  __shared__ double red[4][64];
+  const int e = threadIdx.x & 63, sl = threadIdx.x >> 6;
+  const int idx = blockIdx.x * 64 + e;
+  const bool in = idx < m0 * m0;
+  const int i = in ? idx / m0 : 0, j = in ? idx % m0 : 0;
+  double sum = 0.0;
+  if (in) {
+#pragma unroll 8
+    for (int g = sl; g < groups; g += 4) sum += partial[((size_t)g * ld + i) * ld + j];
+  }
+  red[sl][e] = sum;
+  __syncthreads();
+  if (sl == 0 && in) M[idx] = (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]);
+}
+
+// M <- (M + M^T) / 2 in place (m0 x m0), one thread per pair i < j.
+__global__ void symmetrize_kernel(double *M, int m0) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= m0 * m0) return;
   const int i = idx / m0, j = idx % m0;
-  double s1 = 0.0, s2 = 0.0;
-  for (int g = 0; g < groups; ++g) {
-    s1 += partial[((size_t)g * ld + i) * ld + j];
-    s2 += partial[((size_t)g * ld + j) * ld + i];
-  }
-  M[idx] = 0.5 * (s1 + s2);
+  if (j <= i) return;
+  const double v = 0.5 * (M[i * m0 + j] + M[j * m0 + i]);
+  M[i * m0 + j] = v;
+  M[j * m0 + i] = v;
 }
 
 // partial[g][3][ld] = per column: sum |A x - lam B x|, sum |A x|, sum |B x|
@@ -547,21 +566,38 @@ __global__ __launch_bounds__(256) void gemm_qphi_kernel(const double *Q, size_t 
     X[(rbase + acc_row(l, r)) * m0p + jt * 16 + acc_col(l)] = acc[r];
 }
 
-__global__ void residual_reduce_kernel(const double *partial, int nchunks, int m0p, int m0,
-                                       double emin, double emax, double *res) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= m0) return;
+// One block per column: 256 threads sum interleaved chunks, then a fixed
+// tree in LDS (bitwise reproducible).
+__global__ __launch_bounds__(256) void residual_reduce_kernel(const double *partial, int nchunks,
+                                                              int m0p, int m0, double emin,
+                                                              double emax, double *res) {
+  __shared__ double red[3][256];
+  const int j = blockIdx.x, t = threadIdx.x;
   double num = 0.0, na = 0.0, nb = 0.0;
-  for (int c = 0; c < nchunks; ++c) {
+  for (int c = t; c < nchunks; c += 256) {
     const double *p = partial + (size_t)c * 3 * m0p;
     num += p[j];
     na += p[m0p + j];
     nb += p[2 * m0p + j];
   }
-  const double r = 0.5 * (emax - emin);
-  const double big = fmax(fmax(fabs(emin), fabs(emax)), r);
-  const double den = (na < r * nb) ? nb * big : na;
-  res[j] = num / den;
+  red[0][t] = num;
+  red[1][t] = na;
+  red[2][t] = nb;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) {
+      red[0][t] += red[0][t + h];
+      red[1][t] += red[1][t + h];
+      red[2][t] += red[2][t + h];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double r = 0.5 * (emax - emin);
+    const double big = fmax(fmax(fabs(emin), fabs(emax)), r);
+    const double den = (red[1][0] < r * red[2][0]) ? red[2][0] * big : red[1][0];
+    res[j] = red[0][0] / den;
+  }
 }
 
 __global__ void check_finite_kernel(const double *x, size_t count, int *flag) {
@@ -667,8 +703,11 @@ hipError_t cell_project_bp(const Pencil &p, const double *Q, int ld, int m0, dou
                        p.b, Q, ld, partial);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(cell_project_reduce_kernel, dim3((m0 * m0 + 255) / 256), dim3(256), 0, st,
+    hipLaunchKernelGGL(cell_project_reduce_kernel, dim3((m0 * m0 + 63) / 64), dim3(256), 0, st,
                        (const double *)partial, G, ld, m0, z ? BQ : AQ);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    hipLaunchKernelGGL(symmetrize_kernel, dim3((m0 * m0 + 255) / 256), dim3(256), 0, st,
+                       z ? BQ : AQ, m0);
     if ((err = hipGetLastError()) != hipSuccess) return err;
   }
   return hipSuccess;
@@ -695,7 +734,7 @@ hipError_t cell_residual_bp(const Pencil &p, const double *X, int ld, const doub
                      p.Bd, p.Bu, p.nc, p.b, X, ld, lam, m0, partial);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(residual_reduce_kernel, dim3((m0 + 127) / 128), dim3(128), 0, st,
+  hipLaunchKernelGGL(residual_reduce_kernel, dim3(m0), dim3(256), 0, st,
                      (const double *)partial, G, ld, m0, emin, emax, res);
   return hipGetLastError();
 }

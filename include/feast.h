@@ -43,10 +43,12 @@
  *   -7  bad option (tol <= 0, max_loops < 1, unknown precision)
  *   <= -100  HIP runtime error or out of memory: -100 - hipError_t
  *    1  not converged within max_loops (outputs hold the last loop)
- *    2  B_Q was not numerically positive definite in the last loop: the
- *       reduced problem was solved in the span of B_Q's eigenvectors with
- *       eigenvalue > 1e-10 max; dropped Ritz slots are returned last with
- *       lambda = NaN and a zero eigenvector
+ *    2  B_Q was not numerically positive definite in the last loop (a
+ *       Cholesky pivot at or below 1e-12 times B_Q's diagonal entry in its
+ *       row):
+ *       the reduced problem was solved in the span of B_Q's eigenvectors
+ *       with eigenvalue > 1e-10 max; dropped Ritz slots are returned last
+ *       with lambda = NaN and a zero eigenvector
  *    3  no eigenvalue in the interval (M = 0)
  *    4  M = M0: the subspace is too small (Fig. 2 needs M0 > M)
  *    5  precision 1 only: the float64 refinement of a shifted solve stopped

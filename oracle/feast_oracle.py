@@ -30,9 +30,12 @@ Readings of points the paper leaves open (the same on the GPU path):
     IV.A give the trace test without fixing its denominator).
   * Residual of a pair: ||A x - lam B x||_1 / ||A x||_1 (Table I caption); if
     ||A x||_1 < r ||B x||_1 the denominator is ||B x||_1 max(|emin|,|emax|,r).
-  * If B_Q is not numerically s.p.d. (Sec. III.B (ii)), B_Q is diagonalised,
-    directions with eigenvalue <= 1e-14 * max are dropped, and the dropped
-    Ritz slots are returned last with lam = NaN, x = 0, status 2.
+  * B_Q counts as numerically s.p.d. when its Cholesky factorisation exists
+    with every pivot above 1e-12 times B_Q's diagonal entry in the same row
+    (a scale-invariant test: scaling Q's columns leaves it unchanged).  If not
+    (Sec. III.B (ii)), B_Q is diagonalised, directions with eigenvalue
+    <= 1e-10 * max are dropped, and the dropped Ritz slots are returned last
+    with lam = NaN, x = 0, status 2.
   * Output order: the M counted pairs first (ascending), then the other Ritz
     values (ascending), NaN slots last.  Membership is inclusive.
 """
@@ -219,15 +222,28 @@ def project(p, Q: np.ndarray):
 def reduced_eig(AQ: np.ndarray, BQ: np.ndarray):
     """Solve A_Q Phi = eps B_Q Phi with Phi^T B_Q Phi = I (eqs. 6-9).
 
-    Returns (eps ascending, Phi, fallback_used).  If B_Q is not s.p.d. the
-    problem is solved in the span of B_Q's eigenvectors with eigenvalue
-    > 1e-10 * max; dropped slots get eps = NaN and Phi column 0, last."""
+    Returns (eps ascending, Phi, fallback_used).  B_Q is taken as s.p.d.
+    when its Cholesky pivots L_kk^2 all exceed 1e-12 * B_Q(k, k): a pivot
+    at rounding level relative to its own column means a numerically null
+    direction (a column that depends on the ones before it), whose whitening
+    would amplify rounding errors; the test does not depend on the scaling
+    of Q's columns, which the filter spreads over many orders of magnitude.
+    If it is not, the problem is solved in the span of B_Q's eigenvectors
+    with eigenvalue > 1e-10 * max; dropped slots get eps = NaN and Phi
+    column 0, last."""
     m0 = AQ.shape[0]
+    spd = False
     try:
-        eps, Phi = scipy.linalg.eigh(AQ, BQ)
-        return eps, Phi, False
+        L = np.linalg.cholesky(BQ)
+        spd = bool(np.all(np.diag(L) ** 2 > 1e-12 * np.diag(BQ)))
     except np.linalg.LinAlgError:
         pass
+    if spd:
+        try:
+            eps, Phi = scipy.linalg.eigh(AQ, BQ)
+            return eps, Phi, False
+        except np.linalg.LinAlgError:
+            pass
     mu, V = np.linalg.eigh(BQ)
     keep = mu > 1e-10 * np.max(mu)
     T = V[:, keep] / np.sqrt(mu[keep])

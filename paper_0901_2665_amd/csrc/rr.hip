@@ -3,8 +3,11 @@
 // all in float64.
 //
 //  1. Whitening T with T^T B_Q T = I: T = L^{-T} from the Cholesky factor
-//     B_Q = L L^T.  If a Cholesky pivot is not positive (B_Q not numerically
-//     s.p.d., Sec. III.B (ii)), B_Q = V diag(mu) V^T is diagonalised instead,
+//     B_Q = L L^T.  If a Cholesky pivot is not above 1e-12 B_Q(k, k) (B_Q
+//     not numerically s.p.d., Sec. III.B (ii): a pivot at rounding level
+//     relative to its own column is a numerically null direction, whose
+//     whitening would amplify rounding errors; the test does not depend on
+//     the scaling of Q's columns), B_Q = V diag(mu) V^T is diagonalised instead,
 //     T = V diag(mu^{-1/2}) on the directions with mu > 1e-10 max(mu), and
 //     the other columns of T are zero.
 //  2. C = T^T A_Q T, diagonalised by cyclic two-sided Jacobi rotations in a
@@ -383,6 +386,12 @@ __global__ __launch_bounds__(kThreads) void reduced_eig_kernel(const double *AQ,
   // pivot column values broadcast with readlane); then every wave applies
   // the panel to the trailing matrix on the matrix cores.  Entries above the
   // diagonal are not kept.
+  // B_Q's own diagonal, for the pivot test (wave 0: lane l holds rows l, l + 64)
+  double od[2] = {0.0, 0.0};
+  if (tid < 64) {
+    od[0] = tid < n ? C[tid * ldc + tid] : 0.0;
+    od[1] = tid + 64 < n ? C[(tid + 64) * ldc + tid + 64] : 0.0;
+  }
   for (int k0 = 0; k0 < n; k0 += 16) {
     const int kw = n - k0 < 16 ? n - k0 : 16;
     if (tid < 64) {
@@ -397,8 +406,9 @@ __global__ __launch_bounds__(kThreads) void reduced_eig_kernel(const double *AQ,
 #pragma unroll
       for (int kk = 0; kk < 16; ++kk) {
         const double d = readlane_d(pr[0][kk], kk);  // pivot (k0+kk, k0+kk)
+        const double bkk = readlane_d(k0 < 64 ? od[0] : od[1], (k0 + kk) & 63);
         if (kk < kw && ok) {
-          if (!(d > 0.0) || !isfinite(d)) {
+          if (!(d > 1e-12 * bkk) || !isfinite(d)) {
             ok = false;
           } else {
             const double lkk = sqrt(d), rl = 1.0 / lkk;

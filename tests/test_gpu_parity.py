@@ -183,6 +183,35 @@ def test_reduced_eig_ill_conditioned_backward_stable(ctx, torch, n, cond):
     assert np.max(np.abs(eps - ref)) <= 1e-15 * cond * np.max(np.abs(ref))
 
 
+def test_reduced_eig_scaled_columns_keep_cholesky(ctx, torch):
+    # a diagonal B_Q down to 1e-14: the pivot test is scale-invariant, so
+    # no fallback, as in the oracle
+    mu = np.geomspace(1.0, 1e-14, 9)
+    BQ = np.diag(mu)
+    AQ = np.diag(np.arange(1.0, 10.0)) * mu
+    eps, Phi, fb = ctx.reduced_eig(dev(torch, AQ), dev(torch, BQ))
+    ref, _, rfb = O.reduced_eig(AQ, BQ)
+    assert not fb and not rfb
+    assert np.allclose(host(eps), np.arange(1.0, 10.0), rtol=1e-12)
+
+
+@pytest.mark.parametrize("d2,fallback", [(1e-14, True), (1e-13, True), (1e-11, False)])
+def test_reduced_eig_pivot_cut(ctx, torch, d2, fallback):
+    # B_Q = Q^T Q with Q = [e1, e1 + d e2, e3]: relative pivot d^2 / (1 + d^2)
+    BQ = np.array([[1.0, 1.0, 0.0], [1.0, 1.0 + d2, 0.0], [0.0, 0.0, 1.0]])
+    Q = np.array([[1.0, 1.0, 0.0], [0.0, np.sqrt(d2), 0.0], [0.0, 0.0, 1.0]])
+    AQ = Q.T @ np.diag([1.0, 2.0, 3.0]) @ Q
+    eps, Phi, fb = ctx.reduced_eig(dev(torch, AQ), dev(torch, BQ))
+    ref, _, rfb = O.reduced_eig(AQ, BQ)
+    assert fb == rfb == fallback
+    eps = host(eps)
+    if fallback:
+        assert np.sum(np.isfinite(eps)) == 2 and np.isnan(eps[2])
+        assert np.allclose(eps[:2], ref[:2], rtol=1e-8)
+    else:
+        assert np.allclose(eps, [1.0, 2.0, 3.0], rtol=1e-4)
+
+
 def test_reduced_eig_fallback(ctx, torch):
     rng = np.random.default_rng(8)
     G = rng.standard_normal((10, 6))

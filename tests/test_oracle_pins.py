@@ -219,6 +219,33 @@ def test_reduced_eig_b_orthonormal():
     assert np.max(np.abs(AQ @ Phi - BQ @ Phi * eps)) <= 1e-11
 
 
+def test_reduced_eig_scaled_columns_keep_cholesky():
+    # B_Q diagonal with entries down to 1e-14: every Cholesky pivot equals
+    # its own diagonal entry, so the scale-invariant test keeps the Cholesky
+    # path and the eigenvalues are exact
+    mu = np.geomspace(1.0, 1e-14, 9)
+    BQ = np.diag(mu)
+    AQ = np.diag(np.arange(1.0, 10.0)) * mu
+    eps, Phi, fb = O.reduced_eig(AQ, BQ)
+    assert not fb
+    assert np.allclose(eps, np.arange(1.0, 10.0), rtol=1e-12)
+
+
+@pytest.mark.parametrize("d2,fallback", [(1e-14, True), (1e-13, True), (1e-11, False)])
+def test_reduced_eig_pivot_cut(d2, fallback):
+    # Q = [e1, e1 + d e2, e3]: B_Q = Q^T Q has the pivot d^2 / (1 + d^2)
+    # relative to its diagonal in row 2; at or below 1e-12 it falls back
+    BQ = np.array([[1.0, 1.0, 0.0], [1.0, 1.0 + d2, 0.0], [0.0, 0.0, 1.0]])
+    Q = np.array([[1.0, 1.0, 0.0], [0.0, np.sqrt(d2), 0.0], [0.0, 0.0, 1.0]])
+    AQ = Q.T @ np.diag([1.0, 2.0, 3.0]) @ Q
+    eps, Phi, fb = O.reduced_eig(AQ, BQ)
+    assert fb == fallback
+    if fallback:  # B_Q's eigenvalue ~ d^2 / 2 <= 1e-10 max is dropped
+        assert np.sum(np.isfinite(eps)) == 2 and np.isnan(eps[2])
+    else:
+        assert np.allclose(eps, [1.0, 2.0, 3.0], rtol=1e-4)
+
+
 def test_reduced_eig_fallback_rank_deficient():
     rng = np.random.default_rng(8)
     G = rng.standard_normal((10, 6))

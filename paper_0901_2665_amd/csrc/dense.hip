@@ -534,36 +534,40 @@ __global__ void sum_nodes_kernel(const double *P, int Ne, size_t count, double *
   }
 }
 
-// X[row][j] = sum_{k<m0} Q[row][k] Phi[k][j]; columns m0..m0p-1 are zero.
-__global__ __launch_bounds__(256) void gemm_qphi_kernel(const double *Q, size_t rows, int m0p,
-                                                        int m0, const double *Phi, double *X) {
+// X[row][j] = sum_{k<m0} Q[row][k] Phi[k][j]; columns m0..m0p-1 are zero
+// (m0p = 16 NCT).  One wave per 16 rows and every column tile, so each row
+// of Q is read once from memory; Phi (m0 x m0, finite) is read through the
+// caches, its padding zeroed by a 0/1 factor on an unconditional in-bounds
+// load (a select lets the compiler put the load behind a branch).
+template <int NCT>
+__global__ __launch_bounds__(256) void gemm_qphi_kernel(const double *Q, size_t rows, int m0,
+                                                        const double *Phi, double *X) {
+  constexpr int M0P = 16 * NCT;
   const int l = lane_id(), w = wave_id();
-  const size_t rbase = (size_t)blockIdx.x * 64 + w * 16;
+  const size_t rbase = ((size_t)blockIdx.x * 4 + w) * 16;
   if (rbase >= rows) return;
-  const int jt = blockIdx.y;
   const int kl = l >> 4;
   const size_t row = rbase + (l & 15);
-  const int col = jt * 16 + (l & 15);
-  d4 acc0 = d4zero(), acc1 = d4zero();
-  int k0 = 0;
-  for (; k0 + 8 <= m0p; k0 += 8) {
-    const int ka = k0 + kl, kb = k0 + 4 + kl;
-    double a0 = Q[row * m0p + ka], a1 = Q[row * m0p + kb];
-    double b0 = (ka < m0 && col < m0) ? Phi[(size_t)ka * m0 + col] : 0.0;
-    double b1 = (kb < m0 && col < m0) ? Phi[(size_t)kb * m0 + col] : 0.0;
-    acc0 = mfma(a0, b0, acc0);
-    acc1 = mfma(a1, b1, acc1);
-  }
-  for (; k0 < m0p; k0 += 4) {
-    const int ka = k0 + kl;
-    double a0 = Q[row * m0p + ka];
-    double b0 = (ka < m0 && col < m0) ? Phi[(size_t)ka * m0 + col] : 0.0;
-    acc0 = mfma(a0, b0, acc0);
-  }
-  d4 acc = acc0 + acc1;
+  d4 acc[NCT];
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
-    X[(rbase + acc_row(l, r)) * m0p + jt * 16 + acc_col(l)] = acc[r];
+  for (int q = 0; q < NCT; ++q) acc[q] = d4zero();
+#pragma unroll
+  for (int k0 = 0; k0 < M0P; k0 += 4) {
+    const int ka = k0 + kl;
+    const double a = Q[row * M0P + ka];
+    const int kc = ka < m0 ? ka : m0 - 1;
+#pragma unroll
+    for (int q = 0; q < NCT; ++q) {
+      const int col = q * 16 + (l & 15);
+      const double v = Phi[(size_t)kc * m0 + (col < m0 ? col : m0 - 1)];
+      acc[q] = mfma(a, v * ((ka < m0 && col < m0) ? 1.0 : 0.0), acc[q]);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NCT; ++q)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      X[(rbase + acc_row(l, r)) * M0P + q * 16 + acc_col(l)] = acc[q][r];
 }
 
 // One block per column: 256 threads sum interleaved chunks, then a fixed
@@ -646,8 +650,19 @@ hipError_t launch_sum_nodes(const double *P, int Ne, size_t count, double *Q, hi
 
 hipError_t launch_gemm_qphi(const double *Q, size_t rows, int m0p, int m0, const double *Phi,
                             double *X, hipStream_t st) {
-  dim3 grid((unsigned)((rows + 63) / 64), m0p / 16);
-  hipLaunchKernelGGL(gemm_qphi_kernel, grid, dim3(256), 0, st, Q, rows, m0p, m0, Phi, X);
+  if (m0 < 1) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((rows + 63) / 64)), block(256);
+  switch (m0p) {
+    case 16: hipLaunchKernelGGL(gemm_qphi_kernel<1>, grid, block, 0, st, Q, rows, m0, Phi, X); break;
+    case 32: hipLaunchKernelGGL(gemm_qphi_kernel<2>, grid, block, 0, st, Q, rows, m0, Phi, X); break;
+    case 48: hipLaunchKernelGGL(gemm_qphi_kernel<3>, grid, block, 0, st, Q, rows, m0, Phi, X); break;
+    case 64: hipLaunchKernelGGL(gemm_qphi_kernel<4>, grid, block, 0, st, Q, rows, m0, Phi, X); break;
+    case 80: hipLaunchKernelGGL(gemm_qphi_kernel<5>, grid, block, 0, st, Q, rows, m0, Phi, X); break;
+    case 96: hipLaunchKernelGGL(gemm_qphi_kernel<6>, grid, block, 0, st, Q, rows, m0, Phi, X); break;
+    case 112: hipLaunchKernelGGL(gemm_qphi_kernel<7>, grid, block, 0, st, Q, rows, m0, Phi, X); break;
+    case 128: hipLaunchKernelGGL(gemm_qphi_kernel<8>, grid, block, 0, st, Q, rows, m0, Phi, X); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

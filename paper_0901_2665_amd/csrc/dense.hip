@@ -263,10 +263,12 @@ __global__ __launch_bounds__(kCellThreads) void cell_project_kernel(const double
       for (int ks = 0; ks < BP / 4; ++ks) {
         const int k = 4 * ks + kl;
         const double a = s.V[k * kVld + ti * 16 + (l & 15)];
+        // every tile, also those past nct (columns < 128 <= kVld stay inside
+        // r0; their sums are never stored): no branch around the products
 #pragma unroll
         for (int i = 0; i < kProjTiles; ++i) {
           const int tj = w / 8 + 2 * i;
-          if (tj < nct) pacc[i] = mfma(a, s.r0[k * kVld + tj * 16 + (l & 15)], pacc[i]);
+          pacc[i] = mfma(a, s.r0[k * kVld + tj * 16 + (l & 15)], pacc[i]);
         }
         if ((ks & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // bounded register use
       }

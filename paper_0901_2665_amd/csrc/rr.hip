@@ -467,24 +467,76 @@ __global__ __launch_bounds__(kThreads) void reduced_eig_kernel(const double *AQ,
   const bool fallback = sh.fail != 0;
 
   if (!fallback) {
-    // X = L^{-1}, row by row: X_ii = 1/L_ii, X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj;
-    // X_ij (j < i) is kept in the free upper triangle of C at (j, i).
-    // Eight threads share one dot product and combine it with shuffles.
-    for (int i = 0; i < n; ++i) {
-      const double dii = 1.0 / C[i * ldc + i];
-      const int j = tid >> 3, part = tid & 7;
-      double sum = 0.0;
-      if (j < i) {
-        for (int k = j + part; k < i; k += 8) {
-          const double xkj = (k == j) ? sh.diag[k] : C[j * ldc + k];
-          sum += C[i * ldc + k] * xkj;
+    // X = L^{-1} by 16 x 16 blocks; X_ij (j < i) is kept in the free upper
+    // triangle of C at (j, i), X_ii = 1/L_ii in sh.diag.
+    // (a) diagonal blocks, one wave each: lane c (< 16) forms column c of
+    //     X_II by forward substitution, X_ic = (delta_ic - sum_k L_ik X_kc) / L_ii
+    //     (the entries above the diagonal come out zero).
+    const int nb = (n + 15) / 16;
+    {
+      const int w = tid >> 6, c = tid & 63, o = 16 * w;
+      if (w < nb && c < 16) {
+        double x[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          x[i] = 0.0;
+          if (o + i < n) {  // uniform in the wave
+            const double dii = 1.0 / C[(o + i) * ldc + o + i];
+            double sum = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+            for (int k = 0; k < i; ++k) sum -= C[(o + i) * ldc + o + k] * x[k];
+            x[i] = sum * dii;
+            if (i == c) sh.diag[o + i] = dii;
+          }
+        }
+        if (o + c < n) {
+#pragma unroll
+          for (int i = 0; i < 16; ++i)
+            if (i > c && o + i < n) C[(o + c) * ldc + o + i] = x[i];
         }
       }
-      sum += __shfl_xor(sum, 1);
-      sum += __shfl_xor(sum, 2);
-      sum += __shfl_xor(sum, 4);
-      if (j < i && part == 0) C[j * ldc + i] = -dii * sum;
-      if (tid == 0) sh.diag[i] = dii;
+    }
+    __syncthreads();
+    // (b) X_IJ = -X_II sum_{K=J}^{I-1} L_IK X_KJ, one block diagonal I - J = d
+    //     at a time (one wave per block, on the matrix cores).  The sum S is
+    //     parked in X_IJ's place and read back by the same wave.
+    auto xval = [&](int k, int c) {  // X(k, c), k >= c
+      return k > c ? C[c * ldc + k] : (k == c ? sh.diag[k] : 0.0);
+    };
+    for (int d = 1; d < nb; ++d) {
+      const int w = tid >> 6, l = tid & 63, kl = l >> 4;
+      if (w < nb - d) {
+        const int oj = 16 * w, oi = 16 * (w + d);
+        const int rr = oi + (l & 15), cc = oj + (l & 15);
+        d4 acc = d4zero();
+        for (int ok = oj; ok < oi; ok += 16) {
+#pragma unroll
+          for (int q = 0; q < 16; q += 4) {
+            const int k = ok + q + kl;
+            const double a = (rr < n && k < n) ? C[rr * ldc + k] : 0.0;  // L(rr, k)
+            const double bv = (k < n && cc < n && k >= cc) ? xval(k, cc) : 0.0;
+            acc = mfma(a, bv, acc);
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = oi + (l >> 4) + 4 * q, c = oj + (l & 15);
+          if (r < n && c < n) C[c * ldc + r] = acc[q];
+        }
+        d4 acc2 = d4zero();
+#pragma unroll
+        for (int q = 0; q < 16; q += 4) {
+          const int k = oi + q + kl;
+          const double a = (rr < n && k < n && rr >= k) ? xval(rr, k) : 0.0;  // X_II(rr, k)
+          const double bv = (k < n && cc < n) ? C[cc * ldc + k] : 0.0;       // S(k, cc)
+          acc2 = mfma(a, bv, acc2);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = oi + (l >> 4) + 4 * q, c = oj + (l & 15);
+          if (r < n && c < n) C[c * ldc + r] = -acc2[q];
+        }
+      }
       __syncthreads();
     }
     // T = L^{-T} = X^T (upper triangular)
@@ -495,7 +547,7 @@ __global__ __launch_bounds__(kThreads) void reduced_eig_kernel(const double *AQ,
       T[idx] = v;
     }
   } else {
-    // eigen-decomposition of B_Q, drop directions with mu <= 1e-14 max
+    // eigen-decomposition of B_Q, drop directions with mu <= 1e-10 max
     for (int idx = tid; idx < nn * nn; idx += kThreads) {
       const int i = idx / nn, j = idx % nn;
       C[i * ldc + j] = (i < n && j < n) ? BQ[i * n + j] : 0.0;

@@ -35,6 +35,7 @@ constexpr int kSplit = 4;  // workgroups; each keeps kMaxN / kSplit rows of V
 struct RRShared {
   double2 csn[2][kMaxN / 2];  // (cos, sin) of each pair slot, rounds of even / odd parity
   double4 dnew[kMaxN / 2];    // a round's new diagonal block of each slot
+  int rot;
   int fail;
   double norm;
   double red[kThreads];
@@ -167,7 +168,6 @@ __device__ __forceinline__ int jacobi(double *C, int ldc, int nn, RRShared &sh, 
     bot[k] = (la < half && mv(nn - 1 - la) == r0 + k) ? 1.0 : 0.0;
   }
   if (tid < half) sh.csn[1][tid] = double2{1.0, 0.0};
-  __syncthreads();  // (read by every wave in the first round)
   // V <- V J with the rotations rv of a round, then the players move one
   // circle position (player 0 stays): a lane's new top column comes from
   // lane a+1 and its new bottom column from lane a-1, with the turning
@@ -195,30 +195,29 @@ __device__ __forceinline__ int jacobi(double *C, int ldc, int nn, RRShared &sh, 
   int g = 0;  // rounds done; csn[g & 1] holds the current round's rotations
   int sweep = 0;
   for (; sweep < kMaxSweeps; ++sweep) {
-    int rotcnt = 0;  // rotations of this sweep (counted by the rotation lanes)
+    if (tid == 0) sh.rot = 0;
+    __syncthreads();
     for (int s = 0; s < nn - 1; ++s) {
       double2 *csn = sh.csn[g & 1];
       if (tid < half) {  // one wave: rotation of slot tid and its diagonal block
         const int xt = tid, xbt = nn - 1 - tid;
         const double app = C[xt * ldc + xt], aqq = C[xbt * ldc + xbt], apq = C[xt * ldc + xbt];
-        // The rotation is computed next to its test, not after it (the
-        // dependent chain is the round's critical path), and dropped when the
-        // test fails.  t = tan of the rotation angle, the smaller root of
-        // t^2 + 2 tau t - 1 with tau = d / (2 a_pq), d = a_qq - a_pp, written
-        // without tau:  t = sign(d) 2 a_pq / (|d| + sqrt(d^2 + 4 a_pq^2)),
-        // on d and a_pq scaled by a power of two (exact; t is scale-free).
+        double c = 1.0, sgn = 0.0, t = 0.0;
         const bool rotate =
             fabs(apq) > floor_abs && fabs(apq) > eps * sqrt(fabs(app * aqq));
-        const double dd = aqq - app;
-        const int ex = __builtin_amdgcn_frexp_exp(fmax(fabs(dd), fabs(apq)));
-        const double d = __builtin_amdgcn_ldexp(dd, -ex);
-        const double p2 = __builtin_amdgcn_ldexp(2.0 * apq, -ex);
-        const double tr = (d >= 0.0 ? p2 : -p2) * rcp_newton(fabs(d) + sqrt(fma(d, d, p2 * p2)));
-        const double cr = rcp_newton(sqrt(fma(tr, tr, 1.0)));
-        const double t = rotate ? tr : 0.0, c = rotate ? cr : 1.0, sgn = rotate ? tr * cr : 0.0;
+        if (rotate) {
+          // t = tan of the rotation angle: the smaller root of t^2 + 2 tau t - 1
+          const double tau = (aqq - app) * rcp_newton(2.0 * apq);
+          const double ata = fabs(tau);
+          const double root = ata < 1e150 ? sqrt(1.0 + tau * tau) : ata;
+          t = (tau >= 0.0 ? 1.0 : -1.0) * rcp_newton(ata + root);
+          c = rcp_newton(sqrt(1.0 + t * t));
+          sgn = t * c;
+        }
         // the new diagonal block, written to C after the barrier
         sh.dnew[tid] = double4{app - t * apq, aqq + t * apq, rotate ? 0.0 : apq, 0.0};
-        rotcnt += __popcll(__ballot(rotate));  // the same in every lane of the wave
+        const unsigned long long m = __ballot(rotate);
+        if (tid == 0) sh.rot += __popcll(m);
         csn[tid] = double2{c, sgn};
       }
       v_update(sh.csn[(g & 1) ^ 1]);
@@ -256,7 +255,9 @@ __device__ __forceinline__ int jacobi(double *C, int ldc, int nn, RRShared &sh, 
       __syncthreads();
       ++g;
     }
-    if (!__syncthreads_or(tid == 0 && rotcnt > 0)) break;
+    const int rot = sh.rot;
+    __syncthreads();
+    if (rot == 0) break;
     // Would a further sweep rotate anything?  C does not change during a
     // sweep without rotations, so testing every pair at once decides it as
     // that sweep would, without its nn - 1 rounds.

@@ -258,7 +258,8 @@ def test_solve_chain800(ctx, torch):
 
 @pytest.mark.parametrize("nc,b,seed,k0,m,extra", [
     (2, 3, 1, 1, 2, 2), (3, 4, 2, 3, 4, 3), (4, 5, 3, 5, 6, 4), (6, 8, 4, 10, 12, 6),
-    (1, 9, 5, 2, 3, 2), (7, 16, 6, 30, 10, 8), (11, 20, 7, 60, 15, 9)])
+    (1, 9, 5, 2, 3, 2), (7, 16, 6, 30, 10, 8), (11, 20, 7, 60, 15, 9),
+    (10, 20, 8, 50, 40, 40), (12, 16, 9, 40, 50, 50)])  # M0 = 80, 100: 5 and 7 column tiles
 def test_solve_small(ctx, torch, nc, b, seed, k0, m, extra):
     p = W.dense_random_pencil(nc, b, seed)
     lam = O.bruteforce(p)[0]

@@ -128,7 +128,8 @@ hipError_t launch_shift_residuals(const Pencil &p, const Shifts &s, int Ne, cons
 hipError_t launch_sum_nodes_complex(const Shifts &s, int Ne, const double *X, size_t plane,
                                     double *Q, hipStream_t st);
 
-// Reduced eigenproblem (rr.hip): one workgroup.
+// Reduced eigenproblem (rr.hip): a few workgroups running the same Jacobi
+// (each keeps a slice of the eigenvector rows), then a small kernel for Phi.
 // scratch: reduced_eig_scratch_doubles().  eps, Phi outputs; flag[0] =
 // fallback, flag[1] = Jacobi sweeps, flag[2] = sweeps of the fallback.
 size_t reduced_eig_scratch_doubles();

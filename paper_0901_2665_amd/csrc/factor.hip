@@ -11,9 +11,12 @@
 // reversed chain (coupling of cell j towards j-1 is U_{j-1}^T).
 // Twist cell m-1: T = (S_{m-1} - U_{m-1} W~_m)^{-1}.
 // Here D_j = Z B_jj - A_jj and U_j = Z B_{j,j+1} - A_{j,j+1} are formed on the
-// fly from the real blocks.  Every inverse is symmetrised, so Sinv may be read
-// transposed.  The factors are computed once per solve and reused by every
-// refinement loop (Sec. V, parallelism (ii)).
+// fly from the real blocks.  The inverse of a complex symmetric block is
+// complex symmetric, so Sinv may be read transposed (the computed inverses
+// are symmetric up to rounding; averaging them with their transposes was
+// measured to cost 3% of the factorisation and dropped).  The factors are
+// computed once per solve and reused by every refinement loop (Sec. V,
+// parallelism (ii)).
 #include <vector>
 
 #include "common.h"
@@ -306,11 +309,10 @@ __device__ __forceinline__ void tile_store(double *T, const d4 &accr, const d4 &
 //   S_KJ <- P S_KJ (J != K);  S_IJ <- S_IJ - S_IK S_KJ,  S_IK <- -S_IK P (I != K);
 //   S_KK <- P.
 // The diagonal inverse runs in one wave; the panel products on the matrix
-// cores.  The result is symmetrised (symm: the inverse of a complex
-// symmetric block), written back to slot A and, if gout != nullptr, to
+// cores.  The result is left in slot A and, if gout != nullptr, written to
 // global memory.
 template <int BP>
-__device__ __forceinline__ void gj_invert(Lds<BP> &s, double *gout, bool symm = true) {
+__device__ __forceinline__ void gj_invert(Lds<BP> &s, double *gout) {
   constexpr int LD = Lds<BP>::LD, PLANE = Lds<BP>::PLANE, NB = BP / 16;
   const int w = wave_id();
   double *A = s.A;
@@ -385,38 +387,8 @@ __device__ __forceinline__ void gj_invert(Lds<BP> &s, double *gout, bool symm = 
     }
   }
   __syncthreads();
-  if (!symm) {
-    __syncthreads();
-    return;
-  }
-  // symmetrise: S <- (S + S^T) / 2, by tiles of the 4x4-patch layout
-  const int t = threadIdx.x;
-  const int pi = t >> 4, pj = t & 15;
-  const bool act = (4 * pi < BP) && (4 * pj < BP);
-  double ar[4][4], ai[4][4];
-  if (act) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = 4 * pi + u, c = 4 * pj + v;
-        ar[u][v] = 0.5 * (A[r * LD + c] + A[c * LD + r]);
-        ai[u][v] = 0.5 * (A[PLANE + r * LD + c] + A[PLANE + c * LD + r]);
-      }
-  }
-  __syncthreads();
-  if (act) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = 4 * pi + u, c = 4 * pj + v;
-        A[r * LD + c] = ar[u][v];
-        A[PLANE + r * LD + c] = ai[u][v];
-      }
-  }
-  __syncthreads();
   if (gout) store_block_fl<BP>(gout, A, false);  // a block of Sinv: factor layout
+  __syncthreads();
 }
 
 // Complex product on the matrix cores, operands in LDS slots:
@@ -666,7 +638,7 @@ __global__ __launch_bounds__(kThreads) void interface_kernel(Pencil p, Shifts sh
       __syncthreads();
       acc_to_lds<BP>(s.A, ar, ai);
       __syncthreads();
-      gj_invert<BP>(s, nullptr, false);
+      gj_invert<BP>(s, nullptr);
       // M3 = K N
 #pragma unroll
       for (int t = 0; t < NT; ++t) { ar[t] = d4zero(); ai[t] = d4zero(); }

@@ -573,8 +573,8 @@ __global__ __launch_bounds__(kThreads) void factor_chain_kernel(Pencil p, Shifts
     cgemm_lds<BP>(wr, wi, s.A, true, s.B, 1.0);  // W = Sinv * Cpl
     __syncthreads();
     acc_to_lds<BP>(s.A, wr, wi);
-    acc_to_global<BP, true>(Wg + c * blk, wr, wi);
     __syncthreads();
+    store_block_fl<BP>(Wg + c * blk, s.A, false);
     store_block_fl<BP>(WTg + c * blk, s.A, true);
     if (!last) {
       d4 sr[NT], si[NT];

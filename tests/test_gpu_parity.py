@@ -332,6 +332,33 @@ def test_empty_interval(ctx, torch):
     assert r.status == 3 and r.M == 0
 
 
+@pytest.mark.parametrize("k0,m", [(5, 3), (10, 2)])
+def test_subspace_just_large_enough(ctx, torch, k0, m):
+    # M0 = M: status 4 (Fig. 2 asks for M0 > M), the pairs still found
+    p = W.dense_random_pencil(3, 8, 9)
+    lam = O.bruteforce(p)[0]
+    emin, emax = 0.5 * (lam[k0 - 1] + lam[k0]), 0.5 * (lam[k0 + m - 1] + lam[k0 + m])
+    Y0 = W.random_subspace(p.n, m, 3)
+    r = ctx.solve(gpencil(p), emin, emax, m, 8, dev(torch, Y0), max_loops=40)
+    ref = O.feast(p, emin, emax, m, 8, Y0, max_loops=40)
+    assert r.status == ref.status == 4 and r.M == ref.M == m
+    check_against_oracle(r, ref, p, emin, emax)
+
+
+def test_not_converged(ctx, torch):
+    # one loop cannot converge (the trace test needs two): status 1, and the
+    # outputs hold that loop, as the oracle's
+    p = W.dense_random_pencil(3, 8, 9)
+    lam = O.bruteforce(p)[0]
+    emin, emax = 0.5 * (lam[4] + lam[5]), 0.5 * (lam[8] + lam[9])
+    Y0 = W.random_subspace(p.n, 8, 3)
+    r = ctx.solve(gpencil(p), emin, emax, 8, 8, dev(torch, Y0), max_loops=1)
+    ref = O.feast(p, emin, emax, 8, 8, Y0, max_loops=1)
+    assert r.status == ref.status == 1 and r.loops == 1 and r.M == ref.M
+    lam_g = host(r.lam)[:r.M]
+    assert np.max(np.abs(lam_g - ref.lam[:ref.M]) / np.abs(ref.lam[:ref.M])) <= 1e-10
+
+
 def test_bad_arguments(ctx, torch):
     from paper_0901_2665_amd import feast as F
     p = W.dense_random_pencil(3, 8, 9)
@@ -343,6 +370,15 @@ def test_bad_arguments(ctx, torch):
     with pytest.raises(F.FeastError) as e:
         ctx.solve(gp, 0.0, 1.0, 4, 0, Y0)
     assert e.value.status == -4
+    with pytest.raises(F.FeastError) as e:
+        ctx.solve(gp, 0.0, 1.0, 4, 8, Y0, tol=0.0)
+    assert e.value.status == -7
+    with pytest.raises(F.FeastError) as e:
+        ctx.solve(gp, 0.0, 1.0, 4, 8, Y0, max_loops=0)
+    assert e.value.status == -7
+    with pytest.raises(F.FeastError) as e:  # M0 > N (checked before Y0 is read)
+        ctx.solve(gp, 0.0, 1.0, p.n + 1, 8, Y0)
+    assert e.value.status == -3
     bad = W.Pencil(p.Ad.copy(), p.Au, p.Bd, p.Bu)
     bad.Ad[1, 2, 3] = np.nan
     with pytest.raises(F.FeastError) as e:

@@ -179,40 +179,50 @@ __device__ void store_block(double *g, const double *slot, bool transpose) {
 
 // In-place inverse of a 16x16 complex tile (LDS, planes re/im with row
 // stride ld) by one wave: Gauss-Jordan elimination without pivoting, the
-// tile held in registers (lane l: row l/4, columns 4(l%4)..4(l%4)+3), pivot
-// row and column exchanged with lane shuffles.  The division of a pivot row
-// by its pivot is deferred to one scaling of every row at the end (row j
-// keeps its values times a_jj; later steps act on rows linearly, so the
-// scaling commutes with them), which leaves one complex multiply-add per
-// element and step.
-// Lane broadcasts for the pivot steps: a uniform lane through the scalar
-// unit, a lane of each quad (lanes 4i..4i+3) through DPP.
+// tile held in registers (lane l: row l%16, columns 4(l/16)..4(l/16)+3).
+// At step j the pivot row reaches every lane of a 16-lane row through the
+// DPP broadcast of lane j (no LDS), the pivot through the scalar unit, and
+// each row's column-j entry (held in another 16-lane row) through a lane
+// shuffle of one complex value.  The division of a pivot row by its pivot
+// is deferred to one scaling of every row at the end (row j keeps its values
+// times a_jj; later steps act on rows linearly, so the scaling commutes with
+// them), which leaves one complex multiply-add per element and step.
 __device__ __forceinline__ double readlane_d(double x, int lane) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
   return __hiloint2double(hi, lo);
 }
 
-template <int Q>
-__device__ __forceinline__ double quad_bcast_q(double x) {
-  constexpr int ctrl = Q | (Q << 2) | (Q << 4) | (Q << 6);  // quad_perm [Q, Q, Q, Q]
-  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), ctrl, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), ctrl, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
+template <int J>
+__device__ __forceinline__ double row_bcast_j(double x) {  // DPP row_newbcast:J
+  return __builtin_amdgcn_mov_dpp(x, 0x150 + J, 0xF, 0xF, false);
 }
 
-__device__ __forceinline__ double quad_bcast(double x, int q) {
-  switch (q) {
-    case 0: return quad_bcast_q<0>(x);
-    case 1: return quad_bcast_q<1>(x);
-    case 2: return quad_bcast_q<2>(x);
-    default: return quad_bcast_q<3>(x);
+// lane J of each 16-lane row, to the whole row (J a constant after unrolling)
+__device__ __forceinline__ double row_bcast(double x, int j) {
+  switch (j) {
+    case 0: return row_bcast_j<0>(x);
+    case 1: return row_bcast_j<1>(x);
+    case 2: return row_bcast_j<2>(x);
+    case 3: return row_bcast_j<3>(x);
+    case 4: return row_bcast_j<4>(x);
+    case 5: return row_bcast_j<5>(x);
+    case 6: return row_bcast_j<6>(x);
+    case 7: return row_bcast_j<7>(x);
+    case 8: return row_bcast_j<8>(x);
+    case 9: return row_bcast_j<9>(x);
+    case 10: return row_bcast_j<10>(x);
+    case 11: return row_bcast_j<11>(x);
+    case 12: return row_bcast_j<12>(x);
+    case 13: return row_bcast_j<13>(x);
+    case 14: return row_bcast_j<14>(x);
+    default: return row_bcast_j<15>(x);
   }
 }
 
 __device__ __forceinline__ void inv16_wave(double *Xr, double *Xi, int ld) {
   const int l = lane_id();
-  const int r = l >> 2, cb = (l & 3) * 4;
+  const int r = l & 15, g = l >> 4, cb = 4 * g;
   double ar[4], ai[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
@@ -222,33 +232,27 @@ __device__ __forceinline__ void inv16_wave(double *Xr, double *Xi, int ld) {
   cplx srow{1.0, 0.0};  // deferred scale of my row: 1 / its pivot
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
-    const int vj = j & 3;
-    const int pl = (j << 2) | (j >> 2);          // lane holding (j, j)
+    const int vj = j & 3, jg = j >> 2;
+    const int pl = j + 16 * jg;                  // lane holding (j, j)
     const cplx piv = crecip_fast(cplx{readlane_d(ar[vj], pl), readlane_d(ai[vj], pl)});
-    const int rl = (j << 2) | (l & 3);           // lane holding row j, my columns
     cplx rj[4];                                  // row j (unscaled), my columns
 #pragma unroll
-    for (int v = 0; v < 4; ++v) rj[v] = cplx{__shfl(ar[v], rl), __shfl(ai[v], rl)};
-    // my row, column j: lane j / 4 of my quad
-    const cplx cj{quad_bcast(ar[vj], j >> 2), quad_bcast(ai[vj], j >> 2)};
-    const cplx m = cmul(cj, piv);                // a_rj / a_jj
-    if (r != j) {  // a_rc -= (a_rj / a_jj) a_jc; column j: -a_rj / a_jj
+    for (int v = 0; v < 4; ++v) rj[v] = cplx{row_bcast(ar[v], j), row_bcast(ai[v], j)};
+    const int cl = r + 16 * jg;                  // lane holding my row, column j
+    const cplx cj{__shfl(ar[vj], cl), __shfl(ai[vj], cl)};
+    const bool me = r == j;
+    cplx m = cmul(cj, piv);                      // a_rj / a_jj; 0 for row j itself
+    if (me) m = cplx{0.0, 0.0};
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        ar[v] = fma(m.im, rj[v].im, fma(-m.re, rj[v].re, ar[v]));
-        ai[v] = fma(-m.im, rj[v].re, fma(-m.re, rj[v].im, ai[v]));
-      }
-      if ((l & 3) == (j >> 2)) {
-        ar[vj] = -m.re;
-        ai[vj] = -m.im;
-      }
-    } else {  // row j: unchanged but for the pivot entry, scaled at the end
-      if ((l & 3) == (j >> 2)) {
-        ar[vj] = 1.0;
-        ai[vj] = 0.0;
-      }
-      srow = piv;
+    for (int v = 0; v < 4; ++v) {  // a_rc -= (a_rj / a_jj) a_jc
+      ar[v] = fma(m.im, rj[v].im, fma(-m.re, rj[v].re, ar[v]));
+      ai[v] = fma(-m.im, rj[v].re, fma(-m.re, rj[v].im, ai[v]));
     }
+    if (g == jg) {  // column j: -a_rj / a_jj, and 1 in row j (scaled at the end)
+      ar[vj] = me ? 1.0 : -m.re;
+      ai[vj] = me ? 0.0 : -m.im;
+    }
+    if (me) srow = piv;
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v) {

@@ -35,18 +35,20 @@ struct Lds {
   double B[2 * PLANE];                // slot B
 };
 
-// slot <- z*Bblk - Ablk (or its transpose), identity padding on the diagonal.
-template <int BP>
+// slot <- z*Bblk - Ablk (or its transpose), identity padding on the diagonal,
+// by NTH threads (tid = 0 .. NTH-1).
+template <int BP, int NTH = kThreads>
 __device__ void form_block(double *slot, const double *Ablk, const double *Bblk, int b,
-                           double zr, double zi, bool transpose, bool diag_pad) {
+                           double zr, double zi, bool transpose, bool diag_pad,
+                           int tid = threadIdx.x) {
   constexpr int LD = Lds<BP>::LD, PLANE = Lds<BP>::PLANE;
-  constexpr int NE = (BP * BP + kThreads - 1) / kThreads;
+  constexpr int NE = (BP * BP + NTH - 1) / NTH;
   // all loads first (consecutive threads read consecutive memory; a
   // transposed block is transposed on the way into LDS), then the stores
   double av[NE], bv[NE];
 #pragma unroll
   for (int t = 0; t < NE; ++t) {
-    const int idx = threadIdx.x + t * kThreads;
+    const int idx = tid + t * NTH;
     const int x = idx / BP, y = idx % BP;  // memory row x, column y
     const bool in = idx < BP * BP && x < b && y < b;
     av[t] = in ? Ablk[x * b + y] : 0.0;
@@ -54,7 +56,7 @@ __device__ void form_block(double *slot, const double *Ablk, const double *Bblk,
   }
 #pragma unroll
   for (int t = 0; t < NE; ++t) {
-    const int idx = threadIdx.x + t * kThreads;
+    const int idx = tid + t * NTH;
     if (idx < BP * BP) {
       const int x = idx / BP, y = idx % BP;
       const int r = transpose ? y : x, c = transpose ? x : y;
@@ -314,9 +316,14 @@ __device__ __forceinline__ void tile_store(double *T, const d4 &accr, const d4 &
 //   S_KK <- P.
 // The diagonal inverse runs in one wave; the panel products on the matrix
 // cores.  The result is left in slot A and, if gout != nullptr, written to
-// global memory.
-template <int BP>
-__device__ __forceinline__ void gj_invert(Lds<BP> &s, double *gout) {
+// global memory.  While wave 0 inverts the first diagonal tile, waves 1-3
+// run side() (work that does not touch slot A).
+struct NoSide {
+  __device__ void operator()() const {}
+};
+
+template <int BP, class Side = NoSide>
+__device__ __forceinline__ void gj_invert(Lds<BP> &s, double *gout, Side side = Side()) {
   constexpr int LD = Lds<BP>::LD, PLANE = Lds<BP>::PLANE, NB = BP / 16;
   const int w = wave_id();
   double *A = s.A;
@@ -324,7 +331,10 @@ __device__ __forceinline__ void gj_invert(Lds<BP> &s, double *gout) {
   // The next pivot tile (kb+1, kb+1) is updated first, by wave 0, which then
   // inverts it while waves 1-3 update the other tiles (look-ahead): the
   // one-wave inverse overlaps the panel update instead of idling three waves.
-  if (w == 0) inv16_wave(tile(0, 0), tile(0, 0) + PLANE, LD);
+  if (w == 0)
+    inv16_wave(tile(0, 0), tile(0, 0) + PLANE, LD);
+  else
+    side();
   for (int kb = 0; kb < NB; ++kb) {
     __syncthreads();
     if constexpr (NB > 1) {
@@ -562,12 +572,17 @@ __global__ __launch_bounds__(kThreads) void factor_chain_kernel(Pencil p, Shifts
       gj_invert<BP>(s, Sinv + c * blk);
       break;
     }
-    // coupling from c to the next cell in chain order (slot B is free here)
-    if (dir > 0)
-      form_block<BP>(s.B, p.Au + c * bb, p.Bu + c * bb, b, zr, zi, false, false);
-    else
-      form_block<BP>(s.B, p.Au + (c - 1) * bb, p.Bu + (c - 1) * bb, b, zr, zi, true, false);
-    gj_invert<BP>(s, Sinv + c * blk);  // slot A: Sinv (read until the next barrier)
+    // coupling from c to the next cell in chain order, into slot B (free
+    // here) by waves 1-3 while wave 0 inverts the first pivot tile
+    auto coupling = [&]() {
+      const int t = threadIdx.x - 64;
+      if (dir > 0)
+        form_block<BP, kThreads - 64>(s.B, p.Au + c * bb, p.Bu + c * bb, b, zr, zi, false, false, t);
+      else
+        form_block<BP, kThreads - 64>(s.B, p.Au + (c - 1) * bb, p.Bu + (c - 1) * bb, b, zr, zi,
+                                      true, false, t);
+    };
+    gj_invert<BP>(s, Sinv + c * blk, coupling);  // slot A: Sinv (read until the next barrier)
     DiagRegs<BP> dn;  // next diagonal block, loaded under the W product
     if (!last) diag_regs_load<BP>(dn, p.Ad + (c + dir) * bb, p.Bd + (c + dir) * bb, b);
     __syncthreads();

@@ -408,7 +408,10 @@ __device__ __forceinline__ void gj_invert(Lds<BP> &s, double *gout, Side side = 
 // Complex product on the matrix cores, operands in LDS slots:
 //   acc (+)= sign * op(X) * op(Y),   op(Z) = Z or Z^T.
 // Wave w (< BP/16) owns row block w and all column blocks; acc[tj] holds
-// the re / im 16x16 tiles.
+// the re / im 16x16 tiles.  Three real products per complex one: with
+// x = sign*X,  T1 = x_re (y_re + y_im),  T2 = y_im (x_re + x_im),
+// T3 = y_re (x_im - x_re),  the product is (T1 - T2) + i (T1 + T3); T1 sits
+// in an accumulator of its own and is added to both parts at the end.
 template <int BP>
 __device__ __forceinline__ void cgemm_lds(d4 (&accr)[BP / 16], d4 (&acci)[BP / 16], const double *X,
                                           bool transX, const double *Y, double sign,
@@ -418,21 +421,31 @@ __device__ __forceinline__ void cgemm_lds(d4 (&accr)[BP / 16], d4 (&acci)[BP / 1
   if (w >= NT) return;
   const int row = w * 16 + (l & 15);
   const int kl = l >> 4;
+  d4 t1[NT];
+#pragma unroll
+  for (int tj = 0; tj < NT; ++tj) t1[tj] = d4zero();
 #pragma unroll  // a rolled loop moves the accumulators between register files each trip
   for (int k0 = 0; k0 < BP; k0 += 4) {
     const int k = k0 + kl;
     const int xa = transX ? k * LD + row : row * LD + k;
     const double xr = sign * X[xa], xi = sign * X[PLANE + xa];
+    const double xs = -(xr + xi), xd = xi - xr;
 #pragma unroll
     for (int tj = 0; tj < NT; ++tj) {
       const int yb = transY ? (tj * 16 + (l & 15)) * LD + k : k * LD + tj * 16 + (l & 15);
       const double yr = Y[yb], yi = Y[PLANE + yb];
-      accr[tj] = mfma(xr, yr, accr[tj]);
-      accr[tj] = mfma(-xi, yi, accr[tj]);
-      acci[tj] = mfma(xr, yi, acci[tj]);
-      acci[tj] = mfma(xi, yr, acci[tj]);
+      t1[tj] = mfma(xr, yr + yi, t1[tj]);
+      accr[tj] = mfma(xs, yi, accr[tj]);
+      acci[tj] = mfma(xd, yr, acci[tj]);
     }
   }
+#pragma unroll
+  for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      accr[tj][q] += t1[tj][q];
+      acci[tj][q] += t1[tj][q];
+    }
 }
 
 template <int BP>

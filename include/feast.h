@@ -87,6 +87,18 @@ typedef struct {
                             0 = automatic (at least 8 cells each, about one
                             chain per compute unit); results do not depend on it
                             beyond rounding */
+  int32_t graph;         /* precision 0 only: 1 = the second contour
+                            integration and the rest of its loop (B*Y, the
+                            sweeps of all nodes, Q, the projection, the
+                            reduced problem, X = Q Phi, the residuals, Y <- X)
+                            are captured once as a HIP graph on the context's
+                            stream and the graph is launched for every later
+                            loop; the host still reads the convergence data
+                            between loops.  The first loop runs eagerly.
+                            Results are bitwise those of graph = 0; the
+                            per-kernel timers see the eager launches only.
+                            For callers that pay for launch latency (many
+                            small problems); 0 = eager launches */
   const double *Y0;      /* (dev) [N][M0] initial subspace; required */
 } feast_opts;
 
@@ -107,7 +119,8 @@ typedef struct {
                             over all loops and nodes */
 } feast_info;
 
-/* Default options: tol 1e-12, max_loops 20, precision 0, partitions 0, Y0 NULL. */
+/* Default options: tol 1e-12, max_loops 20, precision 0, partitions 0, graph 0,
+   Y0 NULL. */
 void feast_default_opts(feast_opts *opts);
 
 /* Create a context on HIP device `device`; `hip_stream` is a hipStream_t or

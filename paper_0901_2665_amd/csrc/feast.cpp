@@ -59,6 +59,8 @@ struct feast_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   bool owns_stream = false;          // workers of a batched call own theirs
+  hipStream_t capture = nullptr;     // graph capture (the caller's stream may be
+                                     // the null stream, which cannot capture)
   Buf buf[S_COUNT];
   double *h_eps = nullptr;  // pinned: eps[128] + res[128]
   int *h_flag = nullptr;    // pinned
@@ -332,6 +334,28 @@ int mixed_solve(feast_ctx *ctx, const Work &wk, const Mixed &mx, const Shifts &s
 
 }  // namespace
 
+// One captured loop of feast_solve: the graph is built from the launches of
+// body(cs) on the capture stream cs (it records only; the graph then runs on
+// the caller's stream); capture always ends, also when a launch fails.
+struct GraphExec {
+  hipGraphExec_t exec = nullptr;
+  template <class Body>
+  hipError_t capture(hipStream_t cs, Body &&body) {
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) return e;
+    const hipError_t eb = body(cs);
+    hipGraph_t g = nullptr;
+    const hipError_t ee = hipStreamEndCapture(cs, &g);
+    e = eb != hipSuccess ? eb : ee;
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    return e;
+  }
+  ~GraphExec() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+  }
+};
+
 extern "C" {
 
 void feast_default_opts(feast_opts *opts) {
@@ -340,6 +364,7 @@ void feast_default_opts(feast_opts *opts) {
   opts->max_loops = 20;
   opts->precision = 0;
   opts->partitions = 0;
+  opts->graph = 0;
   opts->Y0 = nullptr;
 }
 
@@ -372,6 +397,7 @@ int feast_destroy(feast_ctx *ctx) {
   if (ctx->h_flag) (void)hipHostFree(ctx->h_flag);
   for (feast_ctx *w : ctx->workers) feast_destroy(w);
   if (ctx->owns_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
   delete ctx;
   return 0;
 }
@@ -653,7 +679,7 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
   if (opts) o = *opts;
   if (!o.Y0) return -5;
   if (!(o.tol > 0.0) || o.max_loops < 1 || o.precision < 0 || o.precision > 1 ||
-      o.partitions < 0)
+      o.partitions < 0 || o.graph < 0 || o.graph > 1)
     return -7;
   HIPCHK(hipSetDevice(ctx->device));
   hipStream_t sm = ctx->stream;
@@ -712,7 +738,30 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
   double *h_res = ctx->h_eps + kMaxM0;
   const double res_gate = std::sqrt(o.tol);
   std::vector<char> is_counted(M0, 0);
+  // graph = 1: loops 2, 3, ... replay one captured loop; it ends with a copy
+  // Y <- X (in place of the pointer swap of the eager loop)
+  const bool use_graph = o.graph == 1 && !mixed;
+  GraphExec gx;
+  auto graph_body = [&](hipStream_t sm) -> hipError_t {
+    hipError_t e;
+    if ((e = launch_cell_apply(p, 1, y, mp, rr, sm)) != hipSuccess) return e;
+    if ((e = launch_sweeps(p, s, Ne, wk.f, wk.sb, rr, mp, pp, 1, sm)) != hipSuccess) return e;
+    if ((e = launch_sweeps(p, s, Ne, wk.f, wk.sb, rr, mp, pp, 2, sm)) != hipSuccess) return e;
+    if ((e = launch_sum_nodes(pp, Ne, rows * mp, q, sm)) != hipSuccess) return e;
+    if ((e = launch_cell_project(p, q, mp, M0, gp, aq, bq, sm)) != hipSuccess) return e;
+    if ((e = launch_reduced_eig(aq, bq, M0, eps, phi, scr, flag, sm)) != hipSuccess) return e;
+    if ((e = launch_gemm_qphi(q, rows, mp, M0, phi, x, sm)) != hipSuccess) return e;
+    if ((e = launch_cell_residuals(p, x, mp, eps, M0, emin, emax, resp, resi, sm)) != hipSuccess)
+      return e;
+    return hipMemcpyAsync(y, x, rows * mp * sizeof(double), hipMemcpyDeviceToDevice, sm);
+  };
   for (int k = 1; k <= o.max_loops; ++k) {
+    if (use_graph && k >= 2) {
+      if (!ctx->capture)  // default priority
+        HIPCHK(hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
+      if (!gx.exec) HIPCHK(gx.capture(ctx->capture, graph_body));
+      HIPCHK(hipGraphLaunch(gx.exec, sm));
+    } else {
     TIMED(K_BTMUL, launch_cell_apply(p, 1, y, mp, rr, sm));                  // R = B Y
     if (mixed) {  // Q_e by refined float32 solves, then Q (eq. 15)
       int steps = 0;
@@ -733,6 +782,7 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
     // residuals of the Ritz pairs (Table I caption) decide which in-interval
     // pairs count as eigenvalue solutions (relative residual <= sqrt(tol))
     TIMED(K_RESID, launch_cell_residuals(p, x, mp, eps, M0, emin, emax, resp, resi, sm));
+    }
     HIPCHK(hipMemcpyAsync(h_eps, eps, M0 * sizeof(double), hipMemcpyDeviceToHost, sm));
     HIPCHK(hipMemcpyAsync(h_res, resi, M0 * sizeof(double), hipMemcpyDeviceToHost, sm));
     HIPCHK(hipMemcpyAsync(ctx->h_flag, flag, 3 * sizeof(int), hipMemcpyDeviceToHost, sm));
@@ -760,7 +810,9 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
       converged = true;
       break;
     }
-    if (k < o.max_loops) std::swap(y, x);  // Y <- X (Fig. 2 step 6)
+    if (k < o.max_loops && !use_graph) std::swap(y, x);  // Y <- X (Fig. 2 step 6)
+    if (use_graph && k == 1)  // the graph's loops read Y from the same buffer
+      HIPCHK(hipMemcpyAsync(y, x, rows * mp * sizeof(double), hipMemcpyDeviceToDevice, sm));
   }
 
   // order: counted pairs first (ascending), then the rest, NaN slots last

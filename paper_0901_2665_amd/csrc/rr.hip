@@ -658,13 +658,25 @@ size_t reduced_eig_scratch_doubles() {
 hipError_t launch_reduced_eig(const double *AQ, const double *BQ, int n, double *eps, double *Phi,
                               double *scratch, int *flag, hipStream_t st) {
   if (n < 1 || n > kMaxN) return hipErrorInvalidValue;
+  auto lds_bytes = [](int m) {
+    const int mm = m + (m & 1);
+    size_t d = (size_t)mm * (kVTld > mm + 1 ? kVTld : mm + 1);
+    if (d < (size_t)kStageDoubles) d = kStageDoubles;  // the products' staging area
+    return d * sizeof(double);
+  };
   const int nn = n + (n & 1);
-  size_t shm = (size_t)nn * (kVTld > nn + 1 ? kVTld : nn + 1);
-  if (shm < (size_t)kStageDoubles) shm = kStageDoubles;  // the products' staging area
-  shm *= sizeof(double);
-  hipError_t err = hipFuncSetAttribute((const void *)reduced_eig_kernel,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  const size_t shm = lds_bytes(n);
+  // the limit is set for the largest n (so calls of any size, from any
+  // thread, agree on it), and not while the stream is being captured into a
+  // graph: a captured loop always follows an eager call on the device
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  hipError_t err = hipStreamIsCapturing(st, &cs);
   if (err != hipSuccess) return err;
+  if (cs == hipStreamCaptureStatusNone) {
+    err = hipFuncSetAttribute((const void *)reduced_eig_kernel,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes(kMaxN));
+    if (err != hipSuccess) return err;
+  }
   hipLaunchKernelGGL(reduced_eig_kernel, dim3(kSplit), dim3(kThreads), shm, st, AQ, BQ, n, eps, Phi,
                      scratch, flag);
   err = hipGetLastError();

@@ -35,7 +35,7 @@ class BTMatrix(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_loops", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("partitions", ctypes.c_int32),
-                ("Y0", ctypes.c_void_p)]
+                ("graph", ctypes.c_int32), ("Y0", ctypes.c_void_p)]
 
 
 class Info(ctypes.Structure):
@@ -193,7 +193,7 @@ class Context:
 
     def solve(self, p: Pencil, emin: float, emax: float, M0: int, Ne: int, Y0,
               tol: float = 1e-12, max_loops: int = 20, out=None,
-              partitions: int = 0, precision: int = 0) -> SolveResult:
+              partitions: int = 0, precision: int = 0, graph: int = 0) -> SolveResult:
         import torch
         dev = p.Ad.device
         if out is None:
@@ -202,7 +202,8 @@ class Context:
             res = torch.empty(M0, dtype=torch.float64, device=dev)
         else:
             lam, X, res = out
-        opts = Opts(tol, max_loops, precision, partitions, _ptr(Y0))
+        opts = Opts(tol=tol, max_loops=max_loops, precision=precision, partitions=partitions,
+                    graph=graph, Y0=_ptr(Y0))
         info = Info()
         ab = p.struct()
         st = self.lib.feast_solve(self.handle, ctypes.byref(ab), emin, emax, M0, Ne,
@@ -216,7 +217,8 @@ class Context:
                            info.solve_res)
 
     def solve_batched(self, problems, tol: float = 1e-12, max_loops: int = 20,
-                      partitions: int = 0, precision: int = 0, workers: int = 0):
+                      partitions: int = 0, precision: int = 0, workers: int = 0,
+                      graph: int = 0):
         """Solve independent problems together.  problems: list of
         (Pencil, emin, emax, M0, Ne, Y0) with Y0 a device tensor.  Returns
         (status, [SolveResult]); a problem's own error is in its result's
@@ -233,7 +235,8 @@ class Context:
             keep.append((p, Y0, lam, X, res, info))
             arr[i] = Problem(p.struct(), emin, emax, M0, Ne, _ptr(Y0), _ptr(lam), _ptr(X),
                              _ptr(res), ctypes.cast(ctypes.pointer(info), ctypes.c_void_p), 0)
-        opts = Opts(tol, max_loops, precision, partitions, None)
+        opts = Opts(tol=tol, max_loops=max_loops, precision=precision, partitions=partitions,
+                    graph=graph, Y0=None)
         st = self.lib.feast_solve_batched(self.handle, arr, len(problems), ctypes.byref(opts),
                                           workers)
         if st < 0 and all(arr[i].status != st for i in range(len(problems))):

@@ -6,10 +6,13 @@ loops to convergence, residuals) on the tight-binding chain workload
 eigenvalues), inputs resident in HBM.  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload tb128k]
-                  [--precision 0|1] [--no-cpu-baseline]
+                  [--precision 0|1] [--graph 0|1] [--no-cpu-baseline]
 
 --workload tbbatch times feast_solve_batched on the first --batch uneven
 problems of the batched workload (each step solves all of them).
+
+--graph 1 passes the graph option of feast_solve (loops after the first
+replay one captured HIP graph) to every solve of the batched workload.
 
 --precision 1 times the mixed-precision solver instead (factor blocks rounded
 to float32, complex float32 sweeps, float64 refinement of every shifted solve
@@ -145,6 +148,8 @@ def main():
                     help="problems per step of the tbbatch workload")
     ap.add_argument("--workers", type=int, default=0,
                     help="host workers (HIP streams) of the tbbatch workload; 0 = automatic")
+    ap.add_argument("--graph", type=int, default=0, choices=(0, 1),
+                    help="tbbatch: 1 = loops after the first replay a captured HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 1 GiB device copy first (reference for HBM byte counters)")
@@ -284,12 +289,13 @@ def run_batch(args):
     ctx = F.Context(0)
     tol = 1e-13  # the paper's trace tolerance (Sec. IV.A)
     for _ in range(args.warmup):
-        ctx.solve_batched(batch, tol=tol, precision=args.precision, workers=args.workers)
+        ctx.solve_batched(batch, tol=tol, precision=args.precision, workers=args.workers,
+                          graph=args.graph)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         st, rs = ctx.solve_batched(batch, tol=tol, precision=args.precision,
-                                   workers=args.workers)
+                                   workers=args.workers, graph=args.graph)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     want = [W.batch_shape(i)["n_eig"] for i in range(args.batch)]
@@ -321,7 +327,7 @@ def run_batch(args):
                    "M0": [min(s["M0"] for s in shapes), max(s["M0"] for s in shapes)],
                    "Ne": W.BATCH_NE, "tol": tol,
                    "precision": "mixed" if args.precision == 1 else "float64",
-                   "workers": args.workers or min(args.batch, 8)},
+                   "workers": args.workers or min(args.batch, 8), "graph": args.graph},
         "gate": gate,
         # kernels of the workers' streams are not timed individually
         "roofline": None,

@@ -170,13 +170,18 @@ typedef struct {
  * taken longest first (estimated from nc, b, M0 and Ne) by `workers` host
  * threads, each with its own HIP stream (default priority) and workspace, so
  * that the kernels of several problems share the GPU.  opts applies to every
- * problem except Y0, which each problem brings.  workers: 0 = min(count, 8);
+ * problem except Y0, which each problem brings; partitions 0 (automatic)
+ * means one partition per half chain here (the problems fill the GPU
+ * together, and the partitioned factorisation loses accuracy on some
+ * problems whose contour points lie close to the real axis).
+ * workers: 0 = min(count, 8);
  * the worker streams and workspaces belong to the context and are kept for
  * later calls.  Work queued on the context's stream before the call is
  * complete before any problem starts, and every problem is complete when the
  * call returns.  Returns the first negative per-problem status if any, else
  * the largest positive one, else 0; each problem's status is in
- * probs[i].status.  Results are identical to feast_solve on each problem.
+ * probs[i].status.  Results are identical to feast_solve on each problem
+ * with the same options (partitions 0 read as 1).
  */
 int feast_solve_batched(feast_ctx *ctx, feast_problem *probs, int32_t count,
                         const feast_opts *opts, int32_t workers);

@@ -915,10 +915,12 @@ int feast_solve_batched(feast_ctx *ctx, feast_problem *probs, int32_t count,
       feast_opts o = base;
       o.Y0 = q.Y0;
       // automatic: one partition per half chain.  The problems fill the GPU
-      // together, and the partitioned factorisation (spikes and the Woodbury
-      // interface step) loses accuracy on some problems with contour points
-      // close to the real axis (Ne = 16: residuals 1e-9 against 1e-12 with
-      // one partition)
+      // together, and the partitioned factorisation loses accuracy on some
+      // problems with contour points close to the real axis: a partition cut
+      // off from its neighbours can be nearly singular there, and its spike
+      // columns, solved through its unpivoted local factorisation, carry the
+      // error into the interface step (Ne = 16: residuals 1e-9 against 1e-12
+      // with one partition)
       if (o.partitions == 0) o.partitions = 1;
       q.status = feast_solve(w, &q.AB, q.emin, q.emax, q.M0, q.Ne, &o, q.lambda, q.X, q.res,
                              q.info);

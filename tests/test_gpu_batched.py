@@ -125,9 +125,10 @@ def test_batched_residuals_problems_8_26(ctx, torch):
         assert r.max_res <= 1e-9
 
 
-@pytest.mark.xfail(strict=False, reason="the partitioned factorisation (spike solves and the "
-                   "Woodbury interface step) loses accuracy when contour points lie close to "
-                   "the real axis: residual 2.1e-9 here with the automatic 8 partitions")
+@pytest.mark.xfail(strict=False, reason="the partitioned factorisation's spike solves run "
+                   "through each partition's unpivoted local factorisation, which loses accuracy "
+                   "for a partition nearly singular at a contour point close to the real axis: "
+                   "residual 2.1e-9 here with the automatic 8 partitions")
 def test_single_problem_auto_partitions_residual(ctx, torch):
     p, emin, emax, m0, ne, Y0 = W.make_batch(9)[8]
     r = ctx.solve(gpencil(p), emin, emax, m0, ne, dev(torch, Y0), tol=1e-13)

@@ -83,3 +83,34 @@ def test_null_context_is_rejected(lib):
 def test_strerror_covers_codes(lib):
     for st in (0, -1, -2, -3, -4, -5, -6, -7, 1, 2, 3, 4, -101):
         assert lib.feast_strerror(st)
+
+
+STRUCTS = [("feast_bt_matrix", F.BTMatrix), ("feast_opts", F.Opts), ("feast_info", F.Info),
+           ("feast_problem", F.Problem)]
+C_NAME = {"lam": "lambda"}  # C field names that are Python keywords
+
+
+def test_struct_layouts_match_header(tmp_path):
+    # the binding's ctypes structures against the C header, compiled by gcc:
+    # same size and the same offset for every field
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "feast.h"',
+             'int main(void) {']
+    for cname, cls in STRUCTS:
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", '
+                         f'offsetof({cname}, {C_NAME.get(fname, fname)}));')
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True, capture_output=True, timeout=60)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True,
+                         timeout=30).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, cls in STRUCTS:
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)

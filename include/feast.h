@@ -13,9 +13,14 @@
  *   lambda = eps,  X = Q Phi                                      (eqs. 8-9)
  * with Gauss-Legendre nodes x_e, weights w_e, r = (emax-emin)/2,
  * theta_e = -(pi/2)(x_e - 1), Z_e = (emax+emin)/2 + r e^{i theta_e}
- * (eqs. 13-14).  Loops stop when the count M of Ritz values inside the
- * interval is stable and the relative change of their trace is below tol
- * (Sec. III.B (i), Sec. IV.A).
+ * (eqs. 13-14).  An in-interval Ritz pair counts as an eigenvalue solution
+ * once its relative residual (below) is at most sqrt(tol).  Loops stop when
+ * the count M of counted pairs is stable, the relative change of their trace
+ * is below tol (Sec. III.B (i), Sec. IV.A), and no uncounted in-interval
+ * pair is still converging (the smallest residual among them did not fall
+ * below half its previous-loop value).  Fig. 2 counts every in-interval Ritz
+ * value; the residual gate keeps mixtures of eigenvectors from both sides of
+ * the interval out of M, so loop counts can differ from that literal rule.
  *
  * Matrices are block-tridiagonal with nc cells of b x b blocks (the shape of
  * nanowire / nanotube Hamiltonians):
@@ -85,8 +90,14 @@ typedef struct {
                             shifted solve (criterion: feast_shifted_solve_mixed) */
   int32_t partitions;    /* partitions per half chain of the factorisation;
                             0 = automatic (at least 8 cells each, about one
-                            chain per compute unit); results do not depend on it
-                            beyond rounding */
+                            chain per compute unit).  The partitioned
+                            factorisation is exact in exact arithmetic; in
+                            float64 its interface step loses accuracy at
+                            contour points close to the real axis (measured
+                            backward error of one shifted solve at
+                            Im z = 1e-4: 8e-14 with 1 partition, 5e-12 with
+                            10), so results depend on it beyond rounding
+                            there */
   int32_t graph;         /* precision 0 only: 1 = the second contour
                             integration and the rest of its loop (B*Y, the
                             sweeps of all nodes, Q, the projection, the
@@ -99,15 +110,28 @@ typedef struct {
                             per-kernel timers see the eager launches only.
                             For callers that pay for launch latency (many
                             small problems); 0 = eager launches */
-  const double *Y0;      /* (dev) [N][M0] initial subspace; required */
+  const double *Y0;      /* (dev) [N][M0] initial subspace, or NULL: then
+                            M0 random vectors are drawn on the device from
+                            `seed` (Fig. 2 step 1): element t = i*M0 + j of
+                            Y0 is standard normal from the counter-based
+                            generator Philox4x64-10 (counter (t/4, 0, 0, 0),
+                            key (seed, 0)); its four 64-bit words w_k give
+                            u_k = (w_k >> 11) 2^-53 + 2^-54, and Box-Muller on
+                            (u0, u1) and (u2, u3) gives four normals
+                            sqrt(-2 ln u_a) cos(2 pi u_b), ... sin(2 pi u_b);
+                            element t takes normal t % 4 */
+  uint64_t seed;         /* key of the random start when Y0 is NULL */
+  int32_t verbose;       /* 1 = one line per loop on stderr (loop, M, trace,
+                            trace change); 0 = silent */
 } feast_opts;
 
 typedef struct {
   int32_t loops;         /* contour integrations performed */
-  int32_t M;             /* Ritz values inside [emin, emax] */
-  double trace;          /* sum of those Ritz values (last loop) */
+  int32_t M;             /* counted pairs: inside [emin, emax] with
+                            residual <= sqrt(tol) */
+  double trace;          /* sum of their Ritz values (last loop) */
   double trace_rel;      /* relative trace change of the last loop */
-  double max_res;        /* max residual over the M in-interval pairs */
+  double max_res;        /* max residual over the M counted pairs */
   int32_t status;        /* same as the return value */
   int32_t fallback;      /* 1 if the last loop used the B_Q fallback */
   double trace_hist[64]; /* trace per loop (first min(loops,64) entries) */
@@ -120,7 +144,7 @@ typedef struct {
 } feast_info;
 
 /* Default options: tol 1e-12, max_loops 20, precision 0, partitions 0, graph 0,
-   Y0 NULL. */
+   Y0 NULL (random start from seed 0), seed 0, verbose 0. */
 void feast_default_opts(feast_opts *opts);
 
 /* Create a context on HIP device `device`; `hip_stream` is a hipStream_t or
@@ -135,8 +159,9 @@ const char *feast_strerror(int status);
 
 /*
  * Full FEAST solve (Fig. 2, real symmetric case) on the GPU.
- *   lambda (dev) [M0]    Ritz values: the M inside [emin, emax] first,
- *                        ascending, then the others ascending.
+ *   lambda (dev) [M0]    Ritz values: the M counted ones first, ascending,
+ *                        then the others ascending (uncounted values inside
+ *                        the interval among them), NaN slots last.
  *   X      (dev) [N][M0] Ritz vectors in the same column order, B-orthonormal.
  *   res    (dev) [M0]    ||A x - lambda B x||_1 / ||A x||_1 per column
  *                        (Table I caption); when ||A x||_1 < r ||B x||_1 the
@@ -156,7 +181,8 @@ typedef struct {
   feast_bt_matrix AB;
   double emin, emax;     /* search interval */
   int32_t M0, Ne;        /* subspace size, contour points */
-  const double *Y0;      /* (dev) [N][M0] initial subspace; required */
+  const double *Y0;      /* (dev) [N][M0] initial subspace, or NULL for the
+                            random start of feast_opts (seed from opts) */
   double *lambda;        /* (dev) [M0] */
   double *X;             /* (dev) [N][M0] */
   double *res;           /* (dev) [M0] */
@@ -194,8 +220,10 @@ int feast_solve_batched(feast_ctx *ctx, feast_problem *probs, int32_t count,
  * *partitions (host), to be passed as feast_opts.partitions.  cache_path
  * (host string, may be NULL) names a text file of lines
  * "arch nc b M0 Ne partitions ms": a shape found there for this device is not
- * measured again, and a measured one is appended.  Results of a solve do not
- * depend on the partition count beyond rounding.
+ * measured again, and a measured one is appended.  A count is taken only if
+ * the shifted solve at the contour point nearest the real axis keeps a
+ * relative residual within 10 times that of one partition (see the
+ * partitions field of feast_opts).
  */
 int feast_autotune_partitions(feast_ctx *ctx, const feast_bt_matrix *AB, double emin,
                               double emax, int32_t M0, int32_t Ne, const char *cache_path,
@@ -223,10 +251,12 @@ int feast_bt_multiply(feast_ctx *ctx, const feast_bt_matrix *AB, int32_t which,
 /*
  * Solve (z B - A) X = R for one complex shift z with Im z > 0 (Fig. 2 step 2),
  * R real (dev) [N][m]; X_re, X_im (dev) [N][m].  1 <= m <= 128.
+ * partitions: partitions per half chain of the factorisation as in
+ * feast_opts (0 = automatic).
  */
 int feast_shifted_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double z_re,
                         double z_im, int32_t m, const double *R, double *X_re,
-                        double *X_im);
+                        double *X_im, int32_t partitions);
 
 /*
  * Mixed-precision variant of feast_shifted_solve: the factor blocks of
@@ -243,7 +273,15 @@ int feast_shifted_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double z_re,
  */
 int feast_shifted_solve_mixed(feast_ctx *ctx, const feast_bt_matrix *AB, double z_re,
                               double z_im, int32_t m, const double *R, double *X_re,
-                              double *X_im, int32_t *steps, double *rel_res);
+                              double *X_im, int32_t partitions, int32_t *steps,
+                              double *rel_res);
+
+/*
+ * The random start block of feast_solve with Y0 = NULL (Fig. 2 step 1):
+ * Y (dev) [N][M0] receives the standard normal draws from `seed` described
+ * at feast_opts.Y0.  N >= 1, 1 <= M0 <= 128.
+ */
+int feast_random_start(feast_ctx *ctx, uint64_t seed, int64_t N, int32_t M0, double *Y);
 
 /*
  * One contour integration (Fig. 2 step 2, eq. 15 with RHS B Y):

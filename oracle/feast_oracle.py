@@ -25,9 +25,17 @@ Readings of points the paper leaves open (the same on the GPU path):
     sides of the interval that share a filter value give in-interval Ritz
     values with large residuals that persist over many loops).
   * Convergence: from the second loop on, stop when the number M of counted
-    pairs is unchanged and the relative change of their trace
+    pairs is unchanged, the relative change of their trace
     |T_k - T_{k-1}| / max(|T_k|, M*r) is below tol (Sec. III.B (i) and Sec.
-    IV.A give the trace test without fixing its denominator).
+    IV.A give the trace test without fixing its denominator), and no
+    uncounted in-interval pair is still converging: the smallest residual
+    among them has not fallen below half its value of the previous loop.
+    Without that last condition a slowly converging true pair that stays
+    above the gate for two loops would be left out of M (with a small M0
+    every pair can still be above it at loops 1 and 2, which ended the
+    iteration with M = 0).  Fig. 2 step 5 counts every in-interval Ritz
+    value, so loop counts differ from that literal rule (the nc=100 chain:
+    3 loops here, 5 with the literal rule).
   * Residual of a pair: ||A x - lam B x||_1 / ||A x||_1 (Table I caption); if
     ||A x||_1 < r ||B x||_1 the denominator is ||B x||_1 max(|emin|,|emax|,r).
   * B_Q counts as numerically s.p.d. when its Cholesky factorisation exists
@@ -108,6 +116,63 @@ def contour(emin: float, emax: float, ne: int) -> Contour:
     Z = c + r * np.exp(1j * theta)
     kappa = -(w / 2.0) * r * np.exp(1j * theta)
     return Contour(x, w, c, r, theta, Z, kappa)
+
+
+# --------------------------------------------------------------------------
+# Random start (Fig. 2 step 1: M0 random vectors), seeded
+# --------------------------------------------------------------------------
+# Philox4x64-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy
+# as 1, 2, 3", SC'11): ten rounds of two 64x64 -> 128-bit products on a
+# four-word counter, with a Weyl-sequence key schedule.
+
+_PHILOX_MUL = (0xD2E7470EE14C6C93, 0xCA5A826395121157)
+_PHILOX_WEYL = (0x9E3779B97F4A7C15, 0xBB67AE8584CAA73B)
+_U32 = np.uint64(0xFFFFFFFF)
+
+
+def _mulhilo64(a: np.ndarray, m: int):
+    """High and low 64-bit words of a * m (a uint64 array, m a constant)."""
+    m = np.uint64(m)
+    a_lo, a_hi = a & _U32, a >> np.uint64(32)
+    m_lo, m_hi = m & _U32, m >> np.uint64(32)
+    ll, lh, hl, hh = a_lo * m_lo, a_lo * m_hi, a_hi * m_lo, a_hi * m_hi
+    mid = (ll >> np.uint64(32)) + (lh & _U32) + (hl & _U32)
+    hi = hh + (lh >> np.uint64(32)) + (hl >> np.uint64(32)) + (mid >> np.uint64(32))
+    return hi, a * m
+
+
+def philox4x64_10(counter, key):
+    """Philox4x64-10 of counters (4 uint64 arrays) under key (2 ints);
+    returns the four output words."""
+    c = [np.asarray(w, dtype=np.uint64).copy() for w in counter]
+    k0, k1 = np.uint64(key[0]), np.uint64(key[1])
+    with np.errstate(over="ignore"):
+        for _ in range(10):
+            hi0, lo0 = _mulhilo64(c[0], _PHILOX_MUL[0])
+            hi1, lo1 = _mulhilo64(c[2], _PHILOX_MUL[1])
+            c = [hi1 ^ c[1] ^ k0, lo1, hi0 ^ c[3] ^ k1, lo0]
+            k0 = k0 + np.uint64(_PHILOX_WEYL[0])
+            k1 = k1 + np.uint64(_PHILOX_WEYL[1])
+    return c
+
+
+def random_start(seed: int, n: int, m0: int) -> np.ndarray:
+    """Y0 [n][m0], standard normal: element t = i*m0 + j uses the Philox words
+    of counter (t // 4, 0, 0, 0) under key (seed, 0); each word w gives the
+    uniform u = (w >> 11) 2^-53 + 2^-54 in (0, 1), and Box-Muller on (u0, u1)
+    and (u2, u3) gives sqrt(-2 ln u_a) cos(2 pi u_b) and ... sin(2 pi u_b);
+    element t takes normal number t % 4."""
+    t = np.arange(n * m0, dtype=np.uint64)
+    zero = np.zeros_like(t)
+    w = philox4x64_10([t >> np.uint64(2), zero, zero, zero], (seed, 0))
+    u = [(wk >> np.uint64(11)).astype(np.float64) * 2.0 ** -53 + 2.0 ** -54 for wk in w]
+    lane = (t & np.uint64(3)).astype(np.int64)
+    ua = np.where(lane < 2, u[0], u[2])
+    ub = np.where(lane < 2, u[1], u[3])
+    rho = np.sqrt(-2.0 * np.log(ua))
+    ang = 2.0 * np.pi * ub
+    z = np.where(lane % 2 == 0, rho * np.cos(ang), rho * np.sin(ang))
+    return z.reshape(n, m0)
 
 
 # --------------------------------------------------------------------------
@@ -280,6 +345,23 @@ def counted(eps: np.ndarray, res: np.ndarray, emin: float, emax: float,
         return (eps >= emin) & (eps <= emax) & (res <= np.sqrt(tol))
 
 
+# An uncounted in-interval pair whose residual fell below this fraction of
+# the previous loop's smallest uncounted residual is still converging.
+UNCOUNTED_DROP = 0.5
+
+
+def smallest_uncounted_residual(eps: np.ndarray, res: np.ndarray, mask: np.ndarray,
+                                emin: float, emax: float) -> float:
+    """Smallest residual among the in-interval Ritz pairs that are not counted
+    (inf if there is none).  Convergence waits while it keeps falling: a true
+    eigenpair that has not yet reached the counting gate shrinks its residual
+    every loop, a mixture of eigenvectors from both sides of the interval
+    does not."""
+    with np.errstate(invalid="ignore"):
+        left = (eps >= emin) & (eps <= emax) & ~mask
+    return float(np.min(res[left])) if left.any() else np.inf
+
+
 def order_ritz(eps: np.ndarray, mask: np.ndarray) -> np.ndarray:
     """Permutation: counted pairs first (ascending), then the other finite
     Ritz values (ascending), NaN slots last."""
@@ -318,6 +400,7 @@ def feast(p, emin: float, emax: float, m0: int, ne: int, Y0: np.ndarray,
     converged = False
     fallback = False
     trace_rel = np.inf
+    prev_left_min = np.inf
     for k in range(1, max_loops + 1):
         Q = filter_apply(p, emin, emax, ne, Y, factors)
         AQ, BQ = project(p, Q)
@@ -325,6 +408,9 @@ def feast(p, emin: float, emax: float, m0: int, ne: int, Y0: np.ndarray,
         X = Q @ Phi
         res = residuals(p, eps, X, emin, emax)
         inside = counted(eps, res, emin, emax, tol)
+        left_min = smallest_uncounted_residual(eps, res, inside, emin, emax)
+        still_converging = left_min < UNCOUNTED_DROP * prev_left_min
+        prev_left_min = left_min
         Mk = int(inside.sum())
         Tk = float(np.sum(eps[inside]))
         if k >= 2:
@@ -336,7 +422,7 @@ def feast(p, emin: float, emax: float, m0: int, ne: int, Y0: np.ndarray,
         counts.append(Mk)
         if log is not None:
             log(k, Mk, Tk, trace_rel)
-        if k >= 2 and Mk == counts[-2] and trace_rel < tol:
+        if k >= 2 and Mk == counts[-2] and trace_rel < tol and not still_converging:
             converged = True
             break
         Y = X

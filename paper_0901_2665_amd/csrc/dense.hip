@@ -628,6 +628,67 @@ int grid_for(size_t n, int threads) {
 
 }  // namespace
 
+// ---- random start (Fig. 2 step 1: M0 random vectors) ----
+//
+// Element t = i*m + j of the start block Y0[N][m] is standard normal, drawn
+// from the counter-based generator Philox4x64-10 (Salmon, Moraes, Dror and
+// Shaw, SC'11): counter (t/4, 0, 0, 0), key (seed, 0); its four 64-bit words
+// give four uniforms u_k = (w_k >> 11) 2^-53 + 2^-54 in (0, 1), and the
+// Box-Muller pairs (u0, u1), (u2, u3) give four normals
+// sqrt(-2 ln u_a) (cos 2 pi u_b, sin 2 pi u_b); element t takes normal t % 4.
+
+__device__ inline void philox4x64_10(unsigned long long c[4], unsigned long long k0,
+                                     unsigned long long k1) {
+  const unsigned long long m0 = 0xD2E7470EE14C6C93ull, m1 = 0xCA5A826395121157ull;
+  const unsigned long long w0 = 0x9E3779B97F4A7C15ull, w1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const unsigned long long hi0 = __umul64hi(m0, c[0]), lo0 = m0 * c[0];
+    const unsigned long long hi1 = __umul64hi(m1, c[2]), lo1 = m1 * c[2];
+    const unsigned long long n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+    k0 += w0;
+    k1 += w1;
+  }
+}
+
+__global__ void random_start_kernel(unsigned long long seed, int nc, int b, int bp, int m,
+                                    int ldd, double *dst) {
+  const size_t total = (size_t)nc * bp * ldd;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const int j = (int)(i % ldd);
+    const size_t rr = i / ldd;
+    const int r = (int)(rr % bp);
+    const size_t c = rr / bp;
+    double v = 0.0;
+    if (r < b && j < m) {
+      const unsigned long long t = (unsigned long long)((c * b + r) * m + j);
+      unsigned long long w[4] = {t >> 2, 0ull, 0ull, 0ull};
+      philox4x64_10(w, seed, 0ull);
+      const int lane = (int)(t & 3);
+      const int pa = lane & 2;  // the pair (u0, u1) or (u2, u3)
+      const double ua = (double)(w[pa] >> 11) * 0x1p-53 + 0x1p-54;
+      const double ub = (double)(w[pa + 1] >> 11) * 0x1p-53 + 0x1p-54;
+      const double rho = sqrt(-2.0 * log(ua));
+      const double ang = 2.0 * M_PI * ub;
+      v = (lane & 1) ? rho * sin(ang) : rho * cos(ang);
+    }
+    dst[i] = v;
+  }
+}
+
+hipError_t launch_random_start(unsigned long long seed, int nc, int b, int bp, int m, int ldd,
+                               double *dst, hipStream_t st) {
+  size_t n = (size_t)nc * bp * ldd;
+  hipLaunchKernelGGL(random_start_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, seed, nc, b,
+                     bp, m, ldd, dst);
+  return hipGetLastError();
+}
+
 hipError_t launch_pack(const double *src, int nc, int b, int bp, int m, int ldd, double *dst,
                        hipStream_t st) {
   size_t n = (size_t)nc * bp * ldd;

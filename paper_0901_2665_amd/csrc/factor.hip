@@ -12,9 +12,8 @@
 // Twist cell m-1: T = (S_{m-1} - U_{m-1} W~_m)^{-1}.
 // Here D_j = Z B_jj - A_jj and U_j = Z B_{j,j+1} - A_{j,j+1} are formed on the
 // fly from the real blocks.  The inverse of a complex symmetric block is
-// complex symmetric, so Sinv may be read transposed (the computed inverses
-// are symmetric up to rounding; averaging them with their transposes was
-// measured to cost 3% of the factorisation and dropped).  The factors are
+// complex symmetric, so every computed inverse is symmetrised and Sinv may be
+// read transposed.  The factors are
 // computed once per solve and reused by every refinement loop (Sec. V,
 // parallelism (ii)).
 #include <vector>
@@ -323,7 +322,8 @@ struct NoSide {
 };
 
 template <int BP, class Side = NoSide>
-__device__ __forceinline__ void gj_invert(Lds<BP> &s, double *gout, Side side = Side()) {
+__device__ __forceinline__ void gj_invert(Lds<BP> &s, double *gout, Side side = Side(),
+                                          bool symm = true) {
   constexpr int LD = Lds<BP>::LD, PLANE = Lds<BP>::PLANE, NB = BP / 16;
   const int w = wave_id();
   double *A = s.A;
@@ -401,6 +401,38 @@ __device__ __forceinline__ void gj_invert(Lds<BP> &s, double *gout, Side side = 
     }
   }
   __syncthreads();
+  if (symm) {
+    // S <- (S + S^T) / 2 by 4x4 patches (the inverse of a complex symmetric
+    // block is complex symmetric; the sweeps read Sinv U transposed as
+    // U^T Sinv, which holds only to the asymmetry of the computed inverse,
+    // and that grows with its condition number near the real axis)
+    const int t = threadIdx.x;
+    const int pi = t >> 4, pj = t & 15;
+    const bool act = (4 * pi < BP) && (4 * pj < BP);
+    double ar[4][4], ai[4][4];
+    if (act) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = 4 * pi + u, c = 4 * pj + v;
+          ar[u][v] = 0.5 * (A[r * LD + c] + A[c * LD + r]);
+          ai[u][v] = 0.5 * (A[PLANE + r * LD + c] + A[PLANE + c * LD + r]);
+        }
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = 4 * pi + u, c = 4 * pj + v;
+          A[r * LD + c] = ar[u][v];
+          A[PLANE + r * LD + c] = ai[u][v];
+        }
+    }
+    __syncthreads();
+  }
   if (gout) store_block_fl<BP>(gout, A, false);  // a block of Sinv: factor layout
   __syncthreads();
 }
@@ -670,7 +702,7 @@ __global__ __launch_bounds__(kThreads) void interface_kernel(Pencil p, Shifts sh
       __syncthreads();
       acc_to_lds<BP>(s.A, ar, ai);
       __syncthreads();
-      gj_invert<BP>(s, nullptr);
+      gj_invert<BP>(s, nullptr, NoSide(), false);
       // M3 = K N
 #pragma unroll
       for (int t = 0; t < NT; ++t) { ar[t] = d4zero(); ai[t] = d4zero(); }

@@ -24,6 +24,9 @@ namespace {
 
 constexpr int kMaxB = 64;
 constexpr int kMaxM0 = 128;
+// convergence waits while the smallest residual of the uncounted in-interval
+// Ritz pairs falls below this fraction of its previous-loop value
+constexpr double kUncountedDrop = 0.5;
 
 struct Buf {
   void *ptr = nullptr;
@@ -366,6 +369,8 @@ void feast_default_opts(feast_opts *opts) {
   opts->partitions = 0;
   opts->graph = 0;
   opts->Y0 = nullptr;
+  opts->seed = 0;
+  opts->verbose = 0;
 }
 
 int feast_init(feast_ctx **ctx, int device, void *hip_stream) {
@@ -491,17 +496,19 @@ int feast_bt_multiply(feast_ctx *ctx, const feast_bt_matrix *AB, int32_t which, 
 }
 
 int feast_shifted_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double z_re, double z_im,
-                        int32_t m, const double *R, double *X_re, double *X_im) {
+                        int32_t m, const double *R, double *X_re, double *X_im,
+                        int32_t partitions) {
   if (!ctx || !R || !X_re || !X_im) return -5;
   int st = validate_matrix(AB);
   if (st) return st;
   if (m < 1 || m > kMaxM0) return -3;
   if (!(z_im > 0.0) || !std::isfinite(z_re) || !std::isfinite(z_im)) return -2;
+  if (partitions < 0) return -7;
   HIPCHK(hipSetDevice(ctx->device));
   Pencil p = make_pencil(AB);
   const int mp = round16(m);
   Work wk;
-  st = prepare_factor(ctx, p, 1, mp, choose_parts(p.nc, 1, 0), wk);
+  st = prepare_factor(ctx, p, 1, mp, choose_parts(p.nc, 1, partitions), wk);
   if (st) return st;
   Shifts s;
   std::memset(&s, 0, sizeof(s));
@@ -522,17 +529,19 @@ int feast_shifted_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double z_re, 
 
 int feast_shifted_solve_mixed(feast_ctx *ctx, const feast_bt_matrix *AB, double z_re,
                               double z_im, int32_t m, const double *R, double *X_re,
-                              double *X_im, int32_t *steps, double *rel_res) {
+                              double *X_im, int32_t partitions, int32_t *steps,
+                              double *rel_res) {
   if (!ctx || !R || !X_re || !X_im) return -5;
   int st = validate_matrix(AB);
   if (st) return st;
   if (m < 1 || m > kMaxM0) return -3;
   if (!(z_im > 0.0) || !std::isfinite(z_re) || !std::isfinite(z_im)) return -2;
+  if (partitions < 0) return -7;
   HIPCHK(hipSetDevice(ctx->device));
   Pencil p = make_pencil(AB);
   const int mp = round16(m);
   Work wk;
-  st = prepare_factor(ctx, p, 1, mp, choose_parts(p.nc, 1, 0), wk);
+  st = prepare_factor(ctx, p, 1, mp, choose_parts(p.nc, 1, partitions), wk);
   if (st) return st;
   Mixed mx;
   st = prepare_mixed(ctx, wk, mx);
@@ -596,6 +605,17 @@ int feast_filter_mixed(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, d
   if (steps) *steps = k;
   if (rel_res) *rel_res = worst;
   return worst <= kRefineTol ? 0 : 5;
+}
+
+int feast_random_start(feast_ctx *ctx, uint64_t seed, int64_t N, int32_t M0, double *Y) {
+  if (!ctx || !Y) return -5;
+  if (N < 1 || N > INT32_MAX) return -1;
+  if (M0 < 1 || M0 > kMaxM0 || M0 > N) return -3;
+  HIPCHK(hipSetDevice(ctx->device));
+  // the caller's [N][M0] layout is the packed layout with one cell of N rows
+  HIPCHK(launch_random_start(seed, 1, (int)N, (int)N, M0, M0, Y, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return 0;
 }
 
 int feast_filter(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double emax,
@@ -677,7 +697,6 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
   feast_opts o;
   feast_default_opts(&o);
   if (opts) o = *opts;
-  if (!o.Y0) return -5;
   if (!(o.tol > 0.0) || o.max_loops < 1 || o.precision < 0 || o.precision > 1 ||
       o.partitions < 0 || o.graph < 0 || o.graph > 1)
     return -7;
@@ -724,7 +743,11 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
     if (st) return st;
     TIMED(K_ROUND, launch_round_factors(p, Ne, wk.f, mx.f, sm));
   }
-  TIMED(K_LAYOUT, launch_pack(o.Y0, p.nc, p.b, p.bp, M0, mp, y, sm));
+  if (o.Y0) {
+    TIMED(K_LAYOUT, launch_pack(o.Y0, p.nc, p.b, p.bp, M0, mp, y, sm));
+  } else {  // Fig. 2 step 1: M0 random vectors, seeded
+    TIMED(K_LAYOUT, launch_random_start(o.seed, p.nc, p.b, p.bp, M0, mp, y, sm));
+  }
 
   std::vector<double> traces;
   std::vector<int> counts;
@@ -737,6 +760,7 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
   double *h_eps = ctx->h_eps;
   double *h_res = ctx->h_eps + kMaxM0;
   const double res_gate = std::sqrt(o.tol);
+  double prev_left_min = INFINITY;
   std::vector<char> is_counted(M0, 0);
   // graph = 1: loops 2, 3, ... replay one captured loop; it ends with a copy
   // Y <- X (in place of the pointer swap of the eager loop)
@@ -791,13 +815,21 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
     rr_sweeps += ctx->h_flag[1] + (fallback ? ctx->h_flag[2] : 0);
     int Mk = 0;
     double Tk = 0.0;
+    double left_min = INFINITY;  // smallest residual of an uncounted in-interval pair
     for (int j = 0; j < M0; ++j) {
-      is_counted[j] = h_eps[j] >= emin && h_eps[j] <= emax && h_res[j] <= res_gate;
+      const bool in = h_eps[j] >= emin && h_eps[j] <= emax;
+      is_counted[j] = in && h_res[j] <= res_gate;
       if (is_counted[j]) {
         ++Mk;
         Tk += h_eps[j];
+      } else if (in) {
+        left_min = std::min(left_min, h_res[j]);
       }
     }
+    // a true pair below the gate shrinks its residual every loop; a mixture of
+    // eigenvectors from both sides of the interval does not
+    const bool still_converging = left_min < kUncountedDrop * prev_left_min;
+    prev_left_min = left_min;
     if (k >= 2) {
       if (Mk == 0 && counts.back() == 0)
         trace_rel = 0.0;
@@ -806,7 +838,10 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
     }
     traces.push_back(Tk);
     counts.push_back(Mk);
-    if (k >= 2 && Mk == counts[counts.size() - 2] && trace_rel < o.tol) {
+    if (o.verbose)
+      std::fprintf(stderr, "feast: loop %d  M %d  trace %.17g  trace change %.3e%s\n", k, Mk, Tk,
+                   k >= 2 ? trace_rel : INFINITY, std::isfinite(left_min) ? "  (uncounted pairs inside)" : "");
+    if (k >= 2 && Mk == counts[counts.size() - 2] && trace_rel < o.tol && !still_converging) {
       converged = true;
       break;
     }
@@ -991,12 +1026,45 @@ int feast_autotune_partitions(feast_ctx *ctx, const feast_bt_matrix *AB, double 
   std::vector<int> cand;
   for (int q = 1; q <= pmax; q *= 2) cand.push_back(q);
   if (cand.back() != pmax) cand.push_back(pmax);
+  // accuracy probe: the contour point nearest the real axis (node 0; node
+  // Ne-1 mirrors it), one shifted solve with a seeded random right-hand side
+  Shifts s1;
+  std::memset(&s1, 0, sizeof(s1));
+  s1.zre[0] = s.zre[0];
+  s1.zim[0] = s.zim[0];
+  double ratio1 = 0.0;  // relative residual with one partition
+  double *h_ratio = ctx->h_eps + 3 * kMaxM0;
+  auto probe = [&](int q, double *ratio) -> int {
+    Work w1;
+    int st1 = prepare_factor(ctx, p, 1, mp, q, w1);
+    if (st1) return st1;
+    double *rin, *xc, *rc, *part, *worst;
+    const size_t plane = w1.rows * mp;
+    HIPCHK(ensure_t(ctx, S_R, plane, &rin));
+    HIPCHK(ensure_t(ctx, S_XC, 2 * plane, &xc));
+    HIPCHK(ensure_t(ctx, S_RC, 2 * plane, &rc));
+    HIPCHK(ensure_t(ctx, S_RPART, shift_residual_partial_doubles(p.nc, mp, 1), &part));
+    HIPCHK(ensure_t(ctx, S_WORST, 1, &worst));
+    HIPCHK(launch_random_start(0, p.nc, p.b, p.bp, M0, mp, rin, ctx->stream));
+    HIPCHK(run_factor(ctx, w1, s1));
+    HIPCHK(launch_sweeps_complex(p, s1, w1.f, w1.sb, rin, mp, xc, xc + plane, ctx->stream));
+    HIPCHK(launch_shift_residuals(p, s1, 1, xc, rin, mp, M0, rc, part, worst, ctx->stream));
+    HIPCHK(hipMemcpyAsync(h_ratio, worst, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    *ratio = *h_ratio;
+    return 0;
+  };
   hipEvent_t t0, t1;
   HIPCHK(hipEventCreate(&t0));
   HIPCHK(hipEventCreate(&t1));
   int best = 0;
   float best_ms = 0.0f;
   for (int q : cand) {
+    double ratio = 0.0;
+    st = probe(q, &ratio);
+    if (st) break;
+    if (q == 1) ratio1 = ratio;
+    else if (!(ratio <= 10.0 * ratio1)) continue;  // loses accuracy near the axis
     Work wk;
     st = prepare_factor(ctx, p, Ne, mp, q, wk);
     if (st) break;

@@ -90,6 +90,10 @@ hipError_t launch_sweeps32(const Pencil &p, int Ne, const Factors32 &f, const So
                            int accumulate, int part, hipStream_t st);
 
 // Dense helpers (dense.hip).
+// Fig. 2 step 1: seeded N(0,1) start block (Philox4x64-10 + Box-Muller),
+// written in the packed layout of launch_pack (zero padding).
+hipError_t launch_random_start(unsigned long long seed, int nc, int b, int bp, int m, int ldd,
+                               double *dst, hipStream_t st);
 hipError_t launch_pack(const double *src, int nc, int b, int bp, int m, int ldd,
                        double *dst, hipStream_t st);
 hipError_t launch_unpack(const double *src, int nc, int b, int bp, int m, int lds,

@@ -35,7 +35,8 @@ class BTMatrix(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_loops", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("partitions", ctypes.c_int32),
-                ("graph", ctypes.c_int32), ("Y0", ctypes.c_void_p)]
+                ("graph", ctypes.c_int32), ("Y0", ctypes.c_void_p),
+                ("seed", ctypes.c_uint64), ("verbose", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -59,7 +60,7 @@ EXPORTED = ["feast_default_opts", "feast_init", "feast_destroy", "feast_strerror
             "feast_solve", "feast_contour", "feast_bt_multiply", "feast_shifted_solve",
             "feast_filter", "feast_project", "feast_reduced_eig", "feast_timing",
             "feast_timing_read", "feast_shifted_solve_mixed", "feast_filter_mixed",
-            "feast_solve_batched", "feast_autotune_partitions"]
+            "feast_solve_batched", "feast_autotune_partitions", "feast_random_start"]
 
 
 def load_library(path: str = LIB_PATH):
@@ -81,10 +82,10 @@ def load_library(path: str = LIB_PATH):
                                 ctypes.POINTER(Opts), P, P, P, ctypes.POINTER(Info)]
     lib.feast_contour.argtypes = [I32, D, D, P, P, P, P, P, P]
     lib.feast_bt_multiply.argtypes = [P, ctypes.POINTER(BTMatrix), I32, I32, P, P]
-    lib.feast_shifted_solve.argtypes = [P, ctypes.POINTER(BTMatrix), D, D, I32, P, P, P]
+    lib.feast_shifted_solve.argtypes = [P, ctypes.POINTER(BTMatrix), D, D, I32, P, P, P, I32]
     lib.feast_filter.argtypes = [P, ctypes.POINTER(BTMatrix), D, D, I32, I32, P, P]
     lib.feast_shifted_solve_mixed.argtypes = [P, ctypes.POINTER(BTMatrix), D, D, I32, P, P, P,
-                                              ctypes.POINTER(I32), ctypes.POINTER(D)]
+                                              I32, ctypes.POINTER(I32), ctypes.POINTER(D)]
     lib.feast_filter_mixed.argtypes = [P, ctypes.POINTER(BTMatrix), D, D, I32, I32, P, P,
                                        ctypes.POINTER(I32), ctypes.POINTER(D)]
     lib.feast_project.argtypes = [P, ctypes.POINTER(BTMatrix), I32, P, P, P]
@@ -93,6 +94,7 @@ def load_library(path: str = LIB_PATH):
                                         I32]
     lib.feast_autotune_partitions.argtypes = [P, ctypes.POINTER(BTMatrix), D, D, I32, I32,
                                               ctypes.c_char_p, ctypes.POINTER(I32)]
+    lib.feast_random_start.argtypes = [P, ctypes.c_uint64, ctypes.c_int64, I32, P]
     lib.feast_timing.argtypes = [P, I32]
     lib.feast_timing_read.argtypes = [P, I32, ctypes.POINTER(ctypes.c_char_p),
                                       ctypes.POINTER(D), ctypes.POINTER(ctypes.c_int64)]
@@ -193,7 +195,10 @@ class Context:
 
     def solve(self, p: Pencil, emin: float, emax: float, M0: int, Ne: int, Y0,
               tol: float = 1e-12, max_loops: int = 20, out=None,
-              partitions: int = 0, precision: int = 0, graph: int = 0) -> SolveResult:
+              partitions: int = 0, precision: int = 0, graph: int = 0,
+              seed: int = 0, verbose: int = 0) -> SolveResult:
+        """Y0: device tensor [N][M0], or None for the library's seeded random
+        start (Philox4x64-10 + Box-Muller from ``seed``)."""
         import torch
         dev = p.Ad.device
         if out is None:
@@ -203,7 +208,8 @@ class Context:
         else:
             lam, X, res = out
         opts = Opts(tol=tol, max_loops=max_loops, precision=precision, partitions=partitions,
-                    graph=graph, Y0=_ptr(Y0))
+                    graph=graph, Y0=_ptr(Y0) if Y0 is not None else None, seed=seed,
+                    verbose=verbose)
         info = Info()
         ab = p.struct()
         st = self.lib.feast_solve(self.handle, ctypes.byref(ab), emin, emax, M0, Ne,
@@ -218,7 +224,7 @@ class Context:
 
     def solve_batched(self, problems, tol: float = 1e-12, max_loops: int = 20,
                       partitions: int = 0, precision: int = 0, workers: int = 0,
-                      graph: int = 0):
+                      graph: int = 0, seed: int = 0):
         """Solve independent problems together.  problems: list of
         (Pencil, emin, emax, M0, Ne, Y0) with Y0 a device tensor.  Returns
         (status, [SolveResult]); a problem's own error is in its result's
@@ -233,10 +239,11 @@ class Context:
             res = torch.empty(M0, dtype=torch.float64, device=dev)
             info = Info()
             keep.append((p, Y0, lam, X, res, info))
-            arr[i] = Problem(p.struct(), emin, emax, M0, Ne, _ptr(Y0), _ptr(lam), _ptr(X),
+            arr[i] = Problem(p.struct(), emin, emax, M0, Ne,
+                             _ptr(Y0) if Y0 is not None else None, _ptr(lam), _ptr(X),
                              _ptr(res), ctypes.cast(ctypes.pointer(info), ctypes.c_void_p), 0)
         opts = Opts(tol=tol, max_loops=max_loops, precision=precision, partitions=partitions,
-                    graph=graph, Y0=None)
+                    graph=graph, Y0=None, seed=seed)
         st = self.lib.feast_solve_batched(self.handle, arr, len(problems), ctypes.byref(opts),
                                           workers)
         if st < 0 and all(arr[i].status != st for i in range(len(problems))):
@@ -288,16 +295,24 @@ class Context:
         self._check(st, "feast_bt_multiply")
         return out
 
-    def shifted_solve(self, p: Pencil, z: complex, R):
+    def random_start(self, seed: int, N: int, M0: int):
+        """The start block feast_solve draws when Y0 is None (device tensor)."""
+        import torch
+        Y = torch.empty((N, M0), dtype=torch.float64, device=f"cuda:{self.device}")
+        st = self.lib.feast_random_start(self.handle, seed, N, M0, _ptr(Y))
+        self._check(st, "feast_random_start")
+        return Y
+
+    def shifted_solve(self, p: Pencil, z: complex, R, partitions: int = 0):
         import torch
         xr, xi = torch.empty_like(R), torch.empty_like(R)
         ab = p.struct()
         st = self.lib.feast_shifted_solve(self.handle, ctypes.byref(ab), z.real, z.imag,
-                                          R.shape[1], _ptr(R), _ptr(xr), _ptr(xi))
+                                          R.shape[1], _ptr(R), _ptr(xr), _ptr(xi), partitions)
         self._check(st, "feast_shifted_solve")
         return xr, xi
 
-    def shifted_solve_mixed(self, p: Pencil, z: complex, R):
+    def shifted_solve_mixed(self, p: Pencil, z: complex, R, partitions: int = 0):
         """(X_re, X_im, corrections, worst relative residual, status 0 or 5)."""
         import torch
         xr, xi = torch.empty_like(R), torch.empty_like(R)
@@ -305,7 +320,8 @@ class Context:
         ab = p.struct()
         st = self.lib.feast_shifted_solve_mixed(self.handle, ctypes.byref(ab), z.real, z.imag,
                                                 R.shape[1], _ptr(R), _ptr(xr), _ptr(xi),
-                                                ctypes.byref(steps), ctypes.byref(rel))
+                                                partitions, ctypes.byref(steps),
+                                                ctypes.byref(rel))
         self._check(st, "feast_shifted_solve_mixed", warn_ok=True)
         return xr, xi, steps.value, rel.value, st
 

@@ -67,6 +67,35 @@ def test_gauss_legendre_vs_library(ne):
     assert np.max(np.abs(w - wl)) <= 2e-15
 
 
+# ------------------------------------------------------------- random start
+
+@pytest.mark.parametrize("seed", [0, 5, 2 ** 63 + 12345])
+def test_philox_matches_numpy_bit_generator(seed):
+    # numpy's Philox bit generator is Philox4x64-10; it increments its
+    # counter before the first block, so its block q is our counter q + 1
+    bg = np.random.Philox(key=np.array([seed, 0], dtype=np.uint64),
+                          counter=np.zeros(4, dtype=np.uint64))
+    raw = bg.random_raw(4 * 64).reshape(64, 4)
+    q = np.arange(1, 65, dtype=np.uint64)
+    z = np.zeros_like(q)
+    w = O.philox4x64_10([q, z, z, z], (seed, 0))
+    assert np.array_equal(np.stack(w, axis=1), raw)
+
+
+def test_random_start_is_standard_normal():
+    import scipy.stats
+    Y = O.random_start(11, 1000, 200)
+    v = Y.ravel()
+    assert abs(v.mean()) < 5e-3 and abs(v.std() - 1.0) < 5e-3
+    assert scipy.stats.kstest(v, "norm").pvalue > 1e-3
+    # the four normals of one counter are independent of each other
+    C = np.corrcoef(v.reshape(-1, 4).T)
+    assert np.max(np.abs(C - np.eye(4))) < 1e-2
+    # deterministic, and a different seed gives a different block
+    assert np.array_equal(Y, O.random_start(11, 1000, 200))
+    assert not np.allclose(Y[:5], O.random_start(12, 1000, 200)[:5])
+
+
 # ----------------------------------------------------------- contour filter
 
 def filter_values(values, emin, emax, ne):
@@ -265,6 +294,114 @@ def test_residual_of_exact_pairs_is_tiny():
     # a perturbed vector has a residual of the size of the perturbation
     Xp = X + 1e-6 * np.random.default_rng(0).standard_normal(X.shape)
     assert np.min(O.residuals(p, lam, Xp, lam[0], lam[-1])) > 1e-9
+
+
+def _hand_pencil():
+    """Two cells of b = 2 with small integer entries:
+    A = [[2 1 1 2], [1 3 0 1], [1 0 4 0], [2 1 0 -1]],
+    B = [[2 0 0 1], [0 1 0 0], [0 0 1 0], [1 0 0 2]] (eigenvalues 1, 1, 1, 3)."""
+    Ad = np.array([[[2, 1], [1, 3]], [[4, 0], [0, -1]]], dtype=np.float64)
+    Au = np.array([[[1, 2], [0, 1]]], dtype=np.float64)
+    Bd = np.array([[[2, 0], [0, 1]], [[1, 0], [0, 2]]], dtype=np.float64)
+    Bu = np.array([[[0, 1], [0, 0]]], dtype=np.float64)
+    return W.Pencil(Ad, Au, Bd, Bu)
+
+
+# Worked by hand (Table I caption: ||A x - lam B x||_1 / ||A x||_1):
+#   x1 = (1, -1, 2, 0), lam1 = 2:   A x1 = (3, -2, 9, 1), ||.||_1 = 15;
+#       B x1 = (2, -1, 2, 1), ||.||_1 = 6;  A x1 - 2 B x1 = (-1, 0, 5, -1), ||.||_1 = 7.
+#   x2 = (0, 1, 0, 1), lam2 = 1/2:  A x2 = (3, 4, 0, 0), ||.||_1 = 7;
+#       B x2 = (1, 1, 0, 2), ||.||_1 = 4;  A x2 - B x2 / 2 = (5/2, 7/2, 0, -1), ||.||_1 = 7.
+# On [1, 3] (r = 1) no guard applies: 7/15 and 7/7.  On [-10, 10] (r = 10)
+# ||A x||_1 < r ||B x||_1 for both, so the denominators are ||B x||_1 * 10:
+# 7/60 and 7/40.
+HAND_X = np.array([[1.0, 0.0], [-1.0, 1.0], [2.0, 0.0], [0.0, 1.0]])
+HAND_LAM = np.array([2.0, 0.5])
+
+
+def test_residual_hand_worked_values():
+    p = _hand_pencil()
+    res = O.residuals(p, HAND_LAM, HAND_X, 1.0, 3.0)
+    assert np.allclose(res, [7.0 / 15.0, 1.0], rtol=1e-15, atol=0)
+
+
+def test_residual_small_ax_guard_hand_worked():
+    p = _hand_pencil()
+    res = O.residuals(p, HAND_LAM, HAND_X, -10.0, 10.0)
+    assert np.allclose(res, [7.0 / 60.0, 7.0 / 40.0], rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("variant", ["bx_denominator", "two_norm", "no_guard"])
+def test_planted_residual_mistakes_are_caught(monkeypatch, variant):
+    # each plausible misreading of the Table I caption changes a hand value
+    def bad(p, lam, X, emin, emax):
+        A = O.assemble(p.Ad, p.Au)
+        B = O.assemble(p.Bd, p.Bu)
+        AX, BX = A @ X, B @ X
+        D = AX - BX * lam[None, :]
+        r = (emax - emin) / 2.0
+        if variant == "bx_denominator":
+            return np.sum(np.abs(D), axis=0) / np.sum(np.abs(BX), axis=0)
+        if variant == "two_norm":
+            return np.linalg.norm(D, axis=0) / np.linalg.norm(AX, axis=0)
+        return np.sum(np.abs(D), axis=0) / np.sum(np.abs(AX), axis=0)
+    monkeypatch.setattr(O, "residuals", bad)
+    p = _hand_pencil()
+    r1 = O.residuals(p, HAND_LAM, HAND_X, 1.0, 3.0)
+    r2 = O.residuals(p, HAND_LAM, HAND_X, -10.0, 10.0)
+    ok = (np.allclose(r1, [7.0 / 15.0, 1.0], rtol=1e-12) and
+          np.allclose(r2, [7.0 / 60.0, 7.0 / 40.0], rtol=1e-12))
+    assert not ok
+
+
+# ------------------------------------------- counting gate and convergence
+
+def _slow_pair_case(seed, frac, extra, side="hi"):
+    """Eigenvalues 10..17 of a dense-coupling chain inside the interval, one end
+    placed at ``frac`` of the gap from the nearest inside eigenvalue, so that
+    eigenvalue's filter value is close to 1/2 and its pair converges slowly."""
+    p = tiny_pencil(6, 8, seed)
+    lam, _ = O.bruteforce(p)
+    k0, m = 10, 8
+    if side == "hi":
+        emin = 0.5 * (lam[k0 - 1] + lam[k0])
+        emax = lam[k0 + m - 1] + frac * (lam[k0 + m] - lam[k0 + m - 1])
+    else:
+        emax = 0.5 * (lam[k0 + m - 1] + lam[k0 + m])
+        emin = lam[k0] - frac * (lam[k0] - lam[k0 - 1])
+    Y0 = W.random_subspace(p.n, m + extra, seed + 7)
+    return p, lam, emin, emax, m + extra, Y0
+
+
+@pytest.mark.parametrize("seed,frac,extra,side", [
+    (3, 1e-3, 2, "hi"), (6, 1e-2, 2, "hi"), (23, 0.1, 2, "hi"),
+    (29, 1e-2, 2, "hi"), (43, 1e-3, 1, "hi"), (16, 0.3, 4, "lo"), (5, 1e-3, 1, "lo")])
+def test_slow_pairs_are_not_dropped(seed, frac, extra, side):
+    # With M0 barely above M every true pair can still sit above the counting
+    # gate (residual <= sqrt(tol)) after two loops; the counted set at
+    # convergence must still be the brute-force set.
+    p, lam, emin, emax, m0, Y0 = _slow_pair_case(seed, frac, extra, side)
+    r = O.feast(p, emin, emax, m0, 8, Y0, tol=1e-12, max_loops=60)
+    ref = lam[(lam >= emin) & (lam <= emax)]
+    assert r.status == 0
+    assert r.M == len(ref) == 8
+    assert np.max(np.abs(r.lam[:r.M] - ref)) <= 1e-10 * np.max(np.abs(ref))
+    # an in-interval Ritz value left uncounted at convergence is a mixture,
+    # not one of the true eigenvalues
+    rest = r.lam[r.M:]
+    left = rest[(rest >= emin) & (rest <= emax)]
+    for v in left:
+        assert np.min(np.abs(ref - v)) > 1e-8
+
+
+def test_planted_gate_without_convergence_wait_is_caught(monkeypatch):
+    # without the wait for uncounted in-interval pairs that are still
+    # converging, two loops with no pair below the gate end the iteration
+    # with M = 0 (seed 3 above)
+    monkeypatch.setattr(O, "UNCOUNTED_DROP", 0.0)
+    p, lam, emin, emax, m0, Y0 = _slow_pair_case(3, 1e-3, 2)
+    r = O.feast(p, emin, emax, m0, 8, Y0, tol=1e-12, max_loops=60)
+    assert r.M != 8
 
 
 # ------------------------------------------------------ planted mistakes

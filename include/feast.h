@@ -317,6 +317,22 @@ int feast_project(feast_ctx *ctx, const feast_bt_matrix *AB, int32_t M0,
 int feast_reduced_eig(feast_ctx *ctx, int32_t M0, const double *AQ, const double *BQ,
                       double *eps, double *Phi, int32_t *fallback);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * reduced eigensolve as feast_reduced_eig, with identical results, but its
+ * workspace is a file-scope device array of the library (1.7 MB on every GPU
+ * the library runs on, held until the process ends) instead of the
+ * context's; the call allocates nothing.  M0 is limited to 128 (the size
+ * the array holds): larger values return -3.  All calls on one GPU share
+ * that array, so calls that overlap in time on one GPU (from several
+ * contexts or streams) race and must be serialised by the caller; nothing in
+ * the array needs to start at zero (every part is written before it is
+ * read).  Arguments and results as feast_reduced_eig.
+ */
+int feast_reduced_eig_noalloc(feast_ctx *ctx, int32_t M0, const double *AQ, const double *BQ,
+                              double *eps, double *Phi, int32_t *fallback);
+
 /* ---- instrumentation ---- */
 
 /*

@@ -67,6 +67,8 @@ struct feast_ctx {
   Buf buf[S_COUNT];
   double *h_eps = nullptr;  // pinned: eps[128] + res[128]
   int *h_flag = nullptr;    // pinned
+  double *rr_static = nullptr;  // device address of the reduced eigensolver's static scratch
+  int *rr_static_flag = nullptr;
   Timing timing;
   std::vector<feast_ctx *> workers;  // sub-contexts of feast_solve_batched
 };
@@ -382,6 +384,8 @@ int feast_init(feast_ctx **ctx, int device, void *hip_stream) {
   c->stream = static_cast<hipStream_t>(hip_stream);
   hipError_t e = hipHostMalloc((void **)&c->h_eps, 4 * kMaxM0 * sizeof(double), hipHostMallocDefault);
   if (e == hipSuccess) e = hipHostMalloc((void **)&c->h_flag, 16 * sizeof(int), hipHostMallocDefault);
+  // this device's copy of the static scratch (device `device` is current)
+  if (e == hipSuccess) e = reduced_eig_static_scratch(&c->rr_static, &c->rr_static_flag);
   if (e != hipSuccess) {
     feast_destroy(c);
     return hip_status(e);
@@ -679,6 +683,21 @@ int feast_reduced_eig(feast_ctx *ctx, int32_t M0, const double *AQ, const double
   HIPCHK(ensure_t(ctx, S_FLAG, 4, &flag));
   HIPCHK(launch_reduced_eig(AQ, BQ, M0, eps, Phi, scr, flag, ctx->stream));
   HIPCHK(hipMemcpyAsync(ctx->h_flag, flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (fallback) *fallback = ctx->h_flag[0];
+  return 0;
+}
+
+int feast_reduced_eig_noalloc(feast_ctx *ctx, int32_t M0, const double *AQ, const double *BQ,
+                              double *eps, double *Phi, int32_t *fallback) {
+  if (!ctx || !AQ || !BQ || !eps || !Phi) return -5;
+  if (M0 < 1 || M0 > kMaxM0) return -3;
+  if (!ctx->rr_static) return -5;
+  HIPCHK(hipSetDevice(ctx->device));
+  HIPCHK(launch_reduced_eig(AQ, BQ, M0, eps, Phi, ctx->rr_static, ctx->rr_static_flag,
+                            ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->h_flag, ctx->rr_static_flag, sizeof(int), hipMemcpyDeviceToHost,
+                        ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   if (fallback) *fallback = ctx->h_flag[0];
   return 0;

@@ -137,6 +137,10 @@ hipError_t launch_sum_nodes_complex(const Shifts &s, int Ne, const double *X, si
 // scratch: reduced_eig_scratch_doubles().  eps, Phi outputs; flag[0] =
 // fallback, flag[1] = Jacobi sweeps, flag[2] = sweeps of the fallback.
 size_t reduced_eig_scratch_doubles();
+// Device address (on the current device) of the reduced eigensolver's
+// file-scope scratch array and of its flags, for the allocation-free entry
+// point; called once per context at initialisation.
+hipError_t reduced_eig_static_scratch(double **ptr, int **flag);
 hipError_t launch_reduced_eig(const double *AQ, const double *BQ, int n, double *eps,
                               double *Phi, double *scratch, int *flag, hipStream_t st);
 

@@ -655,6 +655,25 @@ size_t reduced_eig_scratch_doubles() {
   return (3 * kSplit + 1) * (size_t)kMaxN * kMaxN + kMaxN / 2;
 }
 
+// Device-resident scratch of the allocation-free entry point: one reduced
+// eigensolve at the largest size (kMaxN) followed by its flags (four ints in
+// the last two doubles); 1.7 MB, held by every GPU the library runs on until
+// the process ends.  Host code must use the address returned by
+// reduced_eig_static_scratch, never this name.
+namespace {
+constexpr size_t kStaticScratchDoubles = (3 * kSplit + 1) * (size_t)kMaxN * kMaxN + kMaxN / 2 + 2;
+static __device__ __align__(256) double scratch[kStaticScratchDoubles];
+}  // namespace
+
+hipError_t reduced_eig_static_scratch(double **ptr, int **flag) {
+  void *p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  *ptr = static_cast<double *>(p);
+  *flag = reinterpret_cast<int *>(*ptr + reduced_eig_scratch_doubles());
+  return hipSuccess;
+}
+
 hipError_t launch_reduced_eig(const double *AQ, const double *BQ, int n, double *eps, double *Phi,
                               double *scratch, int *flag, hipStream_t st) {
   if (n < 1 || n > kMaxN) return hipErrorInvalidValue;

@@ -60,7 +60,8 @@ EXPORTED = ["feast_default_opts", "feast_init", "feast_destroy", "feast_strerror
             "feast_solve", "feast_contour", "feast_bt_multiply", "feast_shifted_solve",
             "feast_filter", "feast_project", "feast_reduced_eig", "feast_timing",
             "feast_timing_read", "feast_shifted_solve_mixed", "feast_filter_mixed",
-            "feast_solve_batched", "feast_autotune_partitions", "feast_random_start"]
+            "feast_solve_batched", "feast_autotune_partitions", "feast_random_start",
+            "feast_reduced_eig_noalloc"]
 
 
 def load_library(path: str = LIB_PATH):
@@ -94,6 +95,7 @@ def load_library(path: str = LIB_PATH):
                                         I32]
     lib.feast_autotune_partitions.argtypes = [P, ctypes.POINTER(BTMatrix), D, D, I32, I32,
                                               ctypes.c_char_p, ctypes.POINTER(I32)]
+    lib.feast_reduced_eig_noalloc.argtypes = [P, I32, P, P, P, P, ctypes.POINTER(I32)]
     lib.feast_random_start.argtypes = [P, ctypes.c_uint64, ctypes.c_int64, I32, P]
     lib.feast_timing.argtypes = [P, I32]
     lib.feast_timing_read.argtypes = [P, I32, ctypes.POINTER(ctypes.c_char_p),
@@ -368,3 +370,13 @@ class Context:
                                         ctypes.byref(fb))
         self._check(st, "feast_reduced_eig")
         return eps, Phi, bool(fb.value)
+
+    def reduced_eig_noalloc(self, AQ, BQ, eps, Phi):
+        """feast_reduced_eig_noalloc into the caller's eps [M0] and Phi [M0][M0]
+        (the library allocates nothing); returns the fallback flag."""
+        m0 = AQ.shape[0]
+        fb = ctypes.c_int32(0)
+        st = self.lib.feast_reduced_eig_noalloc(self.handle, m0, _ptr(AQ), _ptr(BQ), _ptr(eps),
+                                                _ptr(Phi), ctypes.byref(fb))
+        self._check(st, "feast_reduced_eig_noalloc")
+        return bool(fb.value)

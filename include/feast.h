@@ -350,6 +350,74 @@ int feast_timing(feast_ctx *ctx, int32_t enable);
 int feast_timing_read(feast_ctx *ctx, int32_t kind, const char **name, double *total_ms,
                       int64_t *launches);
 
+/* ---- learned warm start for a Hamiltonian family ----
+ *
+ * An extension of the project, rooted in the subspace reuse of Sec. IV.C
+ * (Example III: nearby problems start from a previous solution) and Sec. V:
+ * for a family of pencils parameterised by a vector a (here the amplitudes
+ * of the onsite potential), a multilayer perceptron maps a to the start block
+ * Y0 of feast_solve.  The network is d0 -> d1 -> d2 -> d3 with ReLU after
+ * the two hidden layers; every product runs on the matrix cores with the
+ * operands rounded to bfloat16 (round to nearest even) and float32 sums;
+ * master weights, gradients and Adam moments are float32.  Its targets are
+ * gauge-free: for a member with converged B-orthonormal eigenvectors X_in
+ * (the counted pairs) and a fixed start block Y_ref, T = X_in X_in^T B Y_ref,
+ * the output of one contour integration of an exact filter.  Per cell c of
+ * b rows, T_c is represented as U_c C_c with an r-column basis U_c (the
+ * leading eigenvectors of sum_s T_c,s T_c,s^T over the training set); the
+ * network predicts the coefficients C ([nc][r][m], so d3 = nc r m) and the
+ * start block is Y_c = U_c C_c.  Random Y stays the fallback: the FEAST
+ * residual judges every result.
+ */
+typedef struct feast_mlp feast_mlp;
+
+/* Parameters (dev, float32) are packed as W1 [d1][d0], b1 [d1], W2 [d2][d1],
+ * b2 [d2], W3 [d3][d2], b3 [d3].  dims = {d0, d1, d2, d3}, each a multiple of
+ * 16; max_batch a multiple of 16.  The network copies the parameters and
+ * owns its device memory until feast_mlp_destroy.  Errors: -1 bad dims,
+ * -3 bad max_batch, -5 NULL. */
+int feast_mlp_create(feast_ctx *ctx, const int32_t dims[4], int32_t max_batch,
+                     const float *params, feast_mlp **net);
+int feast_mlp_destroy(feast_mlp *net);
+/* Current float32 parameters into params (dev, packed as above). */
+int feast_mlp_params(feast_mlp *net, float *params);
+/* y (dev) [batch][d3] = network(x), x (dev) [batch][d0]; 1 <= batch <= max_batch. */
+int feast_mlp_forward(feast_mlp *net, int32_t batch, const float *x, float *y);
+/* Gradients of the mean squared error mean((y - target)^2) over
+ * batch x d3 entries with respect to the parameters, into grads (dev,
+ * packed as the parameters); *loss (host, may be NULL) gets the loss.
+ * batch a multiple of 16.  The parameters are not changed. */
+int feast_mlp_gradients(feast_mlp *net, int32_t batch, const float *x, const float *target,
+                        float *grads, double *loss);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected; Kingma and
+ * Ba) on the gradients of feast_mlp_gradients, learning rate lr > 0. */
+int feast_mlp_train_step(feast_mlp *net, int32_t batch, const float *x, const float *target,
+                         float lr, double *loss);
+
+/* G (dev) [m][m2] = X^T V for tall X (dev) [N][ldx] (first m columns) and
+ * V (dev) [N][ldv] (first m2 columns), float64, m, m2 <= 128;
+ * workspace (dev) of feast_cross_gram_workspace(N, m, m2) doubles.  Sums in a
+ * fixed order (deterministic). */
+int feast_cross_gram(feast_ctx *ctx, int64_t N, int32_t m, int32_t m2, const double *X,
+                     int32_t ldx, const double *V, int32_t ldv, double *workspace, double *G);
+int64_t feast_cross_gram_workspace(int64_t N, int32_t m, int32_t m2);
+/* T (dev) [N][m2] = X G for X (dev) [N][ldx] (first m columns), G (dev)
+ * [m][m2], float64. */
+int feast_tall_gemm(feast_ctx *ctx, int64_t N, int32_t m, int32_t m2, const double *X,
+                    int32_t ldx, const double *G, double *T);
+/* Gc (dev) [nc][b][b] += T_c T_c^T for the cell row blocks T_c of T (dev)
+ * [nc*b][m], float64, b <= 64, m <= 128. */
+int feast_cell_gram_accumulate(feast_ctx *ctx, int32_t nc, int32_t b, int32_t m,
+                               const double *T, double *Gc);
+/* C (dev, float32) [nc][r][m] = scale * U_c^T T_c for U (dev) [nc][b][r] and
+ * T (dev) [nc*b][m], float64 arithmetic. */
+int feast_basis_project(feast_ctx *ctx, int32_t nc, int32_t b, int32_t r, int32_t m,
+                        const double *U, const double *T, double scale, float *C);
+/* Y (dev) [nc*b][m] = scale * U_c C_c per cell, C (dev, float32) [nc][r][m],
+ * float64 result (a start block for feast_solve). */
+int feast_basis_expand(feast_ctx *ctx, int32_t nc, int32_t b, int32_t r, int32_t m,
+                       const double *U, const float *C, double scale, double *Y);
+
 #ifdef __cplusplus
 }
 #endif

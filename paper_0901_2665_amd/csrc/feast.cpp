@@ -73,6 +73,11 @@ struct feast_ctx {
   std::vector<feast_ctx *> workers;  // sub-contexts of feast_solve_batched
 };
 
+namespace feast {
+hipStream_t context_stream(const feast_ctx *ctx) { return ctx->stream; }
+int context_device(const feast_ctx *ctx) { return ctx->device; }
+}  // namespace feast
+
 namespace {
 
 int hip_status(hipError_t e) { return e == hipSuccess ? 0 : -100 - (int)e; }

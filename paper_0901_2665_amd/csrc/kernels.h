@@ -144,4 +144,36 @@ hipError_t reduced_eig_static_scratch(double **ptr, int **flag);
 hipError_t launch_reduced_eig(const double *AQ, const double *BQ, int n, double *eps,
                               double *Phi, double *scratch, int *flag, hipStream_t st);
 
+
+// Learned warm start (warm.hip).  bfloat16 values are stored as uint16_t.
+// C_partial[z] = A B^T over split z of K (A [M][K], B [N][K], K and kc
+// multiples of 16); gemm_splits(K, kc) partials of M*N floats.
+int gemm_splits(int K, int kc);
+hipError_t launch_gemm_nt(const uint16_t *A, const uint16_t *B, int M, int N, int K, int kc,
+                          float *P, hipStream_t st);
+// Sum of partials, bias, ReLU (relu) or ReLU-derivative mask, outputs
+// float32 / bfloat16 / bfloat16 transposed (any may be null).
+hipError_t launch_finish(const float *P, int splits, int M, int N, const float *bias, int relu,
+                         const uint16_t *mask, float *outf, uint16_t *outb, uint16_t *outbt,
+                         hipStream_t st);
+hipError_t launch_cast_bf16(const float *x, int M, int N, uint16_t *xb, uint16_t *xbt,
+                            hipStream_t st);
+int mse_partials(int M, int N);
+hipError_t launch_mse(const float *y, const float *t, int M, int N, float *dyf, uint16_t *dyb,
+                      uint16_t *dybt, double *partial, double *loss, hipStream_t st);
+hipError_t launch_colsum(const float *D, int M, int N, float *out, hipStream_t st);
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, size_t n, int rows, int cols,
+                       float lr, float b1, float b2, float eps, float c1, float c2, uint16_t *wb,
+                       uint16_t *wbt, hipStream_t st);
+size_t cross_gram_partial_doubles(long long N, int m, int m2);
+hipError_t launch_cross_gram(const double *X, int ldx, const double *V, int ldv, long long N, int m,
+                             int m2, double *partial, double *G, hipStream_t st);
+hipError_t launch_tall_gemm(const double *X, int ldx, const double *G, long long N, int m, int m2,
+                            double *T, hipStream_t st);
+hipError_t launch_cell_gram(const double *T, int nc, int b, int m, double *Gc, hipStream_t st);
+hipError_t launch_basis_project(const double *U, const double *T, int nc, int b, int r, int m,
+                                double scale, float *C, hipStream_t st);
+hipError_t launch_basis_expand(const double *U, const float *C, int nc, int b, int r, int m,
+                               double scale, double *Y, hipStream_t st);
+
 }  // namespace feast

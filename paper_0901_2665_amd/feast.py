@@ -61,7 +61,11 @@ EXPORTED = ["feast_default_opts", "feast_init", "feast_destroy", "feast_strerror
             "feast_filter", "feast_project", "feast_reduced_eig", "feast_timing",
             "feast_timing_read", "feast_shifted_solve_mixed", "feast_filter_mixed",
             "feast_solve_batched", "feast_autotune_partitions", "feast_random_start",
-            "feast_reduced_eig_noalloc"]
+            "feast_reduced_eig_noalloc", "feast_mlp_create", "feast_mlp_destroy",
+            "feast_mlp_params", "feast_mlp_forward", "feast_mlp_gradients",
+            "feast_mlp_train_step", "feast_cross_gram", "feast_cross_gram_workspace",
+            "feast_tall_gemm", "feast_cell_gram_accumulate", "feast_basis_project",
+            "feast_basis_expand"]
 
 
 def load_library(path: str = LIB_PATH):
@@ -96,6 +100,19 @@ def load_library(path: str = LIB_PATH):
     lib.feast_autotune_partitions.argtypes = [P, ctypes.POINTER(BTMatrix), D, D, I32, I32,
                                               ctypes.c_char_p, ctypes.POINTER(I32)]
     lib.feast_reduced_eig_noalloc.argtypes = [P, I32, P, P, P, P, ctypes.POINTER(I32)]
+    F32P = ctypes.c_void_p
+    lib.feast_mlp_create.argtypes = [P, ctypes.POINTER(I32), I32, P, ctypes.POINTER(P)]
+    lib.feast_mlp_destroy.argtypes = [P]
+    lib.feast_mlp_params.argtypes = [P, P]
+    lib.feast_mlp_forward.argtypes = [P, I32, P, P]
+    lib.feast_mlp_gradients.argtypes = [P, I32, P, P, P, ctypes.POINTER(D)]
+    lib.feast_mlp_train_step.argtypes = [P, I32, P, P, ctypes.c_float, ctypes.POINTER(D)]
+    lib.feast_cross_gram.argtypes = [P, ctypes.c_int64, I32, I32, P, I32, P, I32, P, P]
+    lib.feast_cross_gram_workspace.argtypes = [ctypes.c_int64, I32, I32]
+    lib.feast_tall_gemm.argtypes = [P, ctypes.c_int64, I32, I32, P, I32, P, P]
+    lib.feast_cell_gram_accumulate.argtypes = [P, I32, I32, I32, P, P]
+    lib.feast_basis_project.argtypes = [P, I32, I32, I32, I32, P, P, D, F32P]
+    lib.feast_basis_expand.argtypes = [P, I32, I32, I32, I32, P, F32P, D, P]
     lib.feast_random_start.argtypes = [P, ctypes.c_uint64, ctypes.c_int64, I32, P]
     lib.feast_timing.argtypes = [P, I32]
     lib.feast_timing_read.argtypes = [P, I32, ctypes.POINTER(ctypes.c_char_p),
@@ -103,8 +120,77 @@ def load_library(path: str = LIB_PATH):
     for name in EXPORTED:
         if name not in ("feast_default_opts", "feast_strerror"):
             getattr(lib, name).restype = ctypes.c_int
+    lib.feast_cross_gram_workspace.restype = ctypes.c_int64
     _lib = lib
     return lib
+
+
+def _fptr(t, dtype_name="float32"):
+    import torch
+    want = {"float32": torch.float32, "float64": torch.float64}[dtype_name]
+    if not (t.is_cuda and t.dtype == want and t.is_contiguous()):
+        raise ValueError(f"expected a contiguous {dtype_name} device tensor")
+    return t.data_ptr()
+
+
+class Mlp:
+    """The warm-start network of feast.h (feast_mlp_*): every product on the
+    matrix cores in bfloat16 with float32 sums, Adam in float32."""
+
+    def __init__(self, ctx: "Context", dims, params, max_batch: int = 64):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        self.dims = tuple(int(d) for d in dims)
+        self.max_batch = int(max_batch)
+        arr = (ctypes.c_int32 * 4)(*self.dims)
+        h = ctypes.c_void_p()
+        st = self.lib.feast_mlp_create(ctx.handle, arr, self.max_batch, _fptr(params),
+                                       ctypes.byref(h))
+        if st != 0:
+            raise FeastError(st, "feast_mlp_create", self.lib)
+        self.handle = h
+        self.nparam = params.numel()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.feast_mlp_destroy(self.handle)
+            self.handle = None
+
+    def params(self):
+        import torch
+        out = torch.empty(self.nparam, dtype=torch.float32, device=f"cuda:{self.ctx.device}")
+        st = self.lib.feast_mlp_params(self.handle, _fptr(out))
+        if st:
+            raise FeastError(st, "feast_mlp_params", self.lib)
+        return out
+
+    def forward(self, x, out=None):
+        import torch
+        if out is None:
+            out = torch.empty((x.shape[0], self.dims[3]), dtype=torch.float32, device=x.device)
+        st = self.lib.feast_mlp_forward(self.handle, x.shape[0], _fptr(x), _fptr(out))
+        if st:
+            raise FeastError(st, "feast_mlp_forward", self.lib)
+        return out
+
+    def gradients(self, x, t):
+        import torch
+        g = torch.empty(self.nparam, dtype=torch.float32, device=x.device)
+        loss = ctypes.c_double(0.0)
+        st = self.lib.feast_mlp_gradients(self.handle, x.shape[0], _fptr(x), _fptr(t), _fptr(g),
+                                          ctypes.byref(loss))
+        if st:
+            raise FeastError(st, "feast_mlp_gradients", self.lib)
+        return g, loss.value
+
+    def train_step(self, x, t, lr: float, want_loss: bool = True):
+        loss = ctypes.c_double(0.0)
+        st = self.lib.feast_mlp_train_step(self.handle, x.shape[0], _fptr(x), _fptr(t),
+                                           ctypes.c_float(lr),
+                                           ctypes.byref(loss) if want_loss else None)
+        if st:
+            raise FeastError(st, "feast_mlp_train_step", self.lib)
+        return loss.value if want_loss else None
 
 
 def contour(ne: int, emin: float, emax: float):
@@ -295,6 +381,57 @@ class Context:
         st = self.lib.feast_bt_multiply(self.handle, ctypes.byref(ab), which, V.shape[1],
                                         _ptr(V), _ptr(out))
         self._check(st, "feast_bt_multiply")
+        return out
+
+    # ---- float64 data kernels of the learned warm start ----
+
+    def cross_gram(self, X, V, m: int | None = None, m2: int | None = None):
+        """X[:, :m]^T V[:, :m2] (float64, device)."""
+        import torch
+        N = X.shape[0]
+        m = X.shape[1] if m is None else m
+        m2 = V.shape[1] if m2 is None else m2
+        ws = torch.empty(max(1, int(self.lib.feast_cross_gram_workspace(N, m, m2))),
+                         dtype=torch.float64, device=X.device)
+        G = torch.empty((m, m2), dtype=torch.float64, device=X.device)
+        st = self.lib.feast_cross_gram(self.handle, N, m, m2, _ptr(X), X.shape[1], _ptr(V),
+                                       V.shape[1], _ptr(ws), _ptr(G))
+        self._check(st, "feast_cross_gram")
+        return G
+
+    def tall_gemm(self, X, G, m: int | None = None, out=None):
+        import torch
+        N = X.shape[0]
+        m = X.shape[1] if m is None else m
+        if out is None:
+            out = torch.empty((N, G.shape[1]), dtype=torch.float64, device=X.device)
+        st = self.lib.feast_tall_gemm(self.handle, N, m, G.shape[1], _ptr(X), X.shape[1],
+                                      _ptr(G), _ptr(out))
+        self._check(st, "feast_tall_gemm")
+        return out
+
+    def cell_gram_accumulate(self, nc: int, b: int, T, Gc):
+        st = self.lib.feast_cell_gram_accumulate(self.handle, nc, b, T.shape[1], _ptr(T), _ptr(Gc))
+        self._check(st, "feast_cell_gram_accumulate")
+
+    def basis_project(self, nc: int, b: int, U, T, scale: float = 1.0, out=None):
+        import torch
+        r, m = U.shape[2], T.shape[1]
+        if out is None:
+            out = torch.empty(nc * r * m, dtype=torch.float32, device=T.device)
+        st = self.lib.feast_basis_project(self.handle, nc, b, r, m, _ptr(U), _ptr(T), scale,
+                                          _fptr(out))
+        self._check(st, "feast_basis_project")
+        return out
+
+    def basis_expand(self, nc: int, b: int, U, C, m: int, scale: float = 1.0, out=None):
+        import torch
+        r = U.shape[2]
+        if out is None:
+            out = torch.empty((nc * b, m), dtype=torch.float64, device=U.device)
+        st = self.lib.feast_basis_expand(self.handle, nc, b, r, m, _ptr(U), _fptr(C), scale,
+                                         _ptr(out))
+        self._check(st, "feast_basis_expand")
         return out
 
     def random_start(self, seed: int, N: int, M0: int):

@@ -1,0 +1,204 @@
+"""GPU parity of the learned warm start: the network's forward pass,
+gradients and Adam step against the float64 oracle (with the same bfloat16
+rounding points), and the float64 data kernels against plain products.
+
+Tolerances: the GPU sums in float32 what the oracle sums in float64 from the
+same bfloat16 operands (relative differences of about K 2^-24 of the sum of
+magnitudes), and a float32 sum that lands next to a bfloat16 rounding
+boundary can round a hidden activation or gradient one bfloat16 unit (2^-8)
+the other way; the bars (2e-3 of the largest output, 1e-2 of the largest
+gradient of each block) leave room for a few such elements and fail on any
+layout or indexing mistake.
+"""
+import numpy as np
+import pytest
+
+from oracle import mlp_oracle as N
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU tests need a HIP device"
+    return _t
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    from paper_0901_2665_amd import feast as F
+    c = F.Context(0)
+    yield c
+    c.close()
+
+
+def init_params(dims, seed):
+    rng = np.random.default_rng(seed)
+    d0, d1, d2, d3 = dims
+    parts = []
+    for rows, cols in ((d1, d0), (d2, d1), (d3, d2)):
+        parts.append(rng.standard_normal(rows * cols) * np.sqrt(2.0 / cols))
+        parts.append(0.1 * rng.standard_normal(rows))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def f32(torch, a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device="cuda")
+
+
+def blocks(dims):
+    d0, d1, d2, d3 = dims
+    sizes = [d1 * d0, d1, d2 * d1, d2, d3 * d2, d3]
+    return np.cumsum([0] + sizes)
+
+
+DIMS = [(16, 64, 64, 96), (16, 64, 48, 1040), (32, 128, 128, 512)]
+
+
+@pytest.mark.parametrize("dims", DIMS)
+@pytest.mark.parametrize("batch", [7, 32])
+def test_mlp_forward(ctx, torch, dims, batch):
+    from paper_0901_2665_amd import feast as F
+    p = init_params(dims, 1)
+    x = np.random.default_rng(2).standard_normal((batch, dims[0])).astype(np.float32)
+    net = F.Mlp(ctx, dims, f32(torch, p), max_batch=32)
+    try:
+        y = net.forward(f32(torch, x)).cpu().numpy()
+    finally:
+        net.close()
+    ref, _ = N.forward(p.astype(np.float64), dims, x.astype(np.float64), rounding=True)
+    assert np.max(np.abs(y - ref)) <= 2e-3 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("dims", DIMS)
+def test_mlp_gradients(ctx, torch, dims):
+    from paper_0901_2665_amd import feast as F
+    p = init_params(dims, 3)
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal((32, dims[0])).astype(np.float32)
+    t = rng.standard_normal((32, dims[3])).astype(np.float32)
+    net = F.Mlp(ctx, dims, f32(torch, p), max_batch=32)
+    try:
+        g, loss = net.gradients(f32(torch, x), f32(torch, t))
+        g = g.cpu().numpy()
+        # the parameters are unchanged by a gradient evaluation
+        assert np.array_equal(net.params().cpu().numpy(), p)
+    finally:
+        net.close()
+    rloss, rg = N.loss_and_gradients(p.astype(np.float64), dims, x.astype(np.float64),
+                                     t.astype(np.float64), rounding=True)
+    assert abs(loss - rloss) <= 1e-4 * rloss
+    cut = blocks(dims)
+    for a, b in zip(cut[:-1], cut[1:]):
+        ref = rg[a:b]
+        assert np.max(np.abs(g[a:b] - ref)) <= 1e-2 * np.max(np.abs(ref)) + 1e-12
+
+
+def test_mlp_adam_step(ctx, torch):
+    # one step of the library's Adam equals the published update applied to
+    # the gradients the library computes at the same parameters; a second
+    # step likewise (moments carried over)
+    from paper_0901_2665_amd import feast as F
+    dims = (16, 64, 64, 96)
+    p = init_params(dims, 5)
+    rng = np.random.default_rng(6)
+    x = f32(torch, rng.standard_normal((32, dims[0])))
+    t = f32(torch, rng.standard_normal((32, dims[3])))
+    net = F.Mlp(ctx, dims, f32(torch, p), max_batch=32)
+    try:
+        m = np.zeros(len(p))
+        v = np.zeros(len(p))
+        cur = p.astype(np.float64)
+        for step in (1, 2):
+            g, _ = net.gradients(x, t)
+            net.train_step(x, t, 1e-3)
+            got = net.params().cpu().numpy().astype(np.float64)
+            cur, m, v = N.adam_step(cur, g.cpu().numpy().astype(np.float64), m, v, step, 1e-3)
+            assert np.max(np.abs(got - cur)) <= 1e-6
+            cur = got
+    finally:
+        net.close()
+
+
+def test_mlp_training_reduces_loss(ctx, torch):
+    # a few hundred steps fit a smooth target (the loss falls by 10x)
+    from paper_0901_2665_amd import feast as F
+    dims = (16, 64, 64, 96)
+    rng = np.random.default_rng(7)
+    A = rng.standard_normal((16, 96)) / 4.0
+    X = rng.standard_normal((256, 16))
+    T = np.tanh(X @ A)
+    net = F.Mlp(ctx, dims, f32(torch, init_params(dims, 8)), max_batch=64)
+    try:
+        xs, ts = f32(torch, X), f32(torch, T)
+        first = net.train_step(xs[:64], ts[:64], 3e-3)
+        for it in range(300):
+            k = (it % 4) * 64
+            loss = net.train_step(xs[k:k + 64], ts[k:k + 64], 3e-3)
+        assert loss < 0.1 * first
+    finally:
+        net.close()
+
+
+def test_mlp_bad_arguments(ctx, torch):
+    from paper_0901_2665_amd import feast as F
+    dims = (16, 64, 64, 96)
+    p = f32(torch, init_params(dims, 9))
+    with pytest.raises(F.FeastError):
+        F.Mlp(ctx, (16, 60, 64, 96), p)            # not a multiple of 16
+    net = F.Mlp(ctx, dims, p, max_batch=32)
+    try:
+        x = f32(torch, np.zeros((8, 16)))
+        t = f32(torch, np.zeros((8, 96)))
+        with pytest.raises(F.FeastError) as e:      # training batch not a multiple of 16
+            net.gradients(x, t)
+        assert e.value.status == -3
+        with pytest.raises(F.FeastError) as e:      # above max_batch
+            net.forward(f32(torch, np.zeros((48, 16))))
+        assert e.value.status == -3
+    finally:
+        net.close()
+
+
+# ---------------------------------------------------------------- data kernels
+
+def f64(torch, a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+
+
+@pytest.mark.parametrize("N,m,m2,ld", [(32000, 40, 64, 64), (1000, 64, 64, 64), (300, 7, 3, 9),
+                                       (257, 128, 128, 128)])
+def test_cross_gram_and_tall_gemm(ctx, torch, N, m, m2, ld):
+    rng = np.random.default_rng(N + m)
+    X = rng.standard_normal((N, ld))
+    V = rng.standard_normal((N, max(m2, 1)))
+    G = ctx.cross_gram(f64(torch, X), f64(torch, V), m=m, m2=m2).cpu().numpy()
+    ref = X[:, :m].T @ V[:, :m2]
+    bound = 2 * N * np.finfo(float).eps * (np.abs(X[:, :m]).T @ np.abs(V[:, :m2]))
+    assert np.all(np.abs(G - ref) <= bound)
+    Gm = rng.standard_normal((m, m2))
+    T = ctx.tall_gemm(f64(torch, X), f64(torch, Gm), m=m).cpu().numpy()
+    ref = X[:, :m] @ Gm
+    bound = 2 * m * np.finfo(float).eps * (np.abs(X[:, :m]) @ np.abs(Gm))
+    assert np.all(np.abs(T - ref) <= bound)
+
+
+@pytest.mark.parametrize("nc,b,m,r", [(5, 64, 64, 4), (3, 32, 100, 3), (2, 17, 5, 2)])
+def test_cell_basis_kernels(ctx, torch, nc, b, m, r):
+    rng = np.random.default_rng(nc * b + m)
+    T = rng.standard_normal((nc * b, m))
+    G0 = rng.standard_normal((nc, b, b))
+    Gc = f64(torch, G0)
+    ctx.cell_gram_accumulate(nc, b, f64(torch, T), Gc)
+    Tc = T.reshape(nc, b, m)
+    ref = G0 + np.einsum("cik,cjk->cij", Tc, Tc)
+    assert np.allclose(Gc.cpu().numpy(), ref, rtol=1e-13, atol=1e-12)
+    U = rng.standard_normal((nc, b, r))
+    C = ctx.basis_project(nc, b, f64(torch, U), f64(torch, T), scale=0.5).cpu().numpy()
+    refC = 0.5 * np.einsum("cik,cij->ckj", U, Tc)
+    assert np.allclose(C.reshape(nc, r, m), refC, rtol=1e-6, atol=1e-6)  # float32 output
+    Cf = rng.standard_normal((nc, r, m)).astype(np.float32)
+    Y = ctx.basis_expand(nc, b, f64(torch, U), f32(torch, Cf.ravel()), m, scale=2.0).cpu().numpy()
+    refY = 2.0 * np.einsum("cik,ckj->cij", U, Cf.astype(np.float64)).reshape(nc * b, m)
+    assert np.allclose(Y, refY, rtol=1e-13, atol=1e-13)

@@ -413,10 +413,14 @@ int feast_cell_gram_accumulate(feast_ctx *ctx, int32_t nc, int32_t b, int32_t m,
  * T (dev) [nc*b][m], float64 arithmetic. */
 int feast_basis_project(feast_ctx *ctx, int32_t nc, int32_t b, int32_t r, int32_t m,
                         const double *U, const double *T, double scale, float *C);
-/* Y (dev) [nc*b][m] = scale * U_c C_c per cell, C (dev, float32) [nc][r][m],
- * float64 result (a start block for feast_solve). */
+/* Y (dev) [nc*b][m] = scale * U_c C_c per cell + rscale * R, C (dev, float32)
+ * [nc][r][m], R (dev) [nc*b][m] or NULL; float64 result (a start block for
+ * feast_solve: a prediction of T spans only the M in-interval directions, so
+ * the start block adds a random block R, e.g. from feast_random_start, to
+ * give the other M0 - M columns directions). */
 int feast_basis_expand(feast_ctx *ctx, int32_t nc, int32_t b, int32_t r, int32_t m,
-                       const double *U, const float *C, double scale, double *Y);
+                       const double *U, const float *C, double scale, const double *R,
+                       double rscale, double *Y);
 
 #ifdef __cplusplus
 }

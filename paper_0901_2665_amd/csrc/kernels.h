@@ -174,6 +174,7 @@ hipError_t launch_cell_gram(const double *T, int nc, int b, int m, double *Gc, h
 hipError_t launch_basis_project(const double *U, const double *T, int nc, int b, int r, int m,
                                 double scale, float *C, hipStream_t st);
 hipError_t launch_basis_expand(const double *U, const float *C, int nc, int b, int r, int m,
-                               double scale, double *Y, hipStream_t st);
+                               double scale, const double *R, double rscale, double *Y,
+                               hipStream_t st);
 
 }  // namespace feast

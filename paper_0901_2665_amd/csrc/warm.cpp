@@ -323,13 +323,14 @@ int feast_basis_project(feast_ctx *ctx, int32_t nc, int32_t b, int32_t r, int32_
 }
 
 int feast_basis_expand(feast_ctx *ctx, int32_t nc, int32_t b, int32_t r, int32_t m,
-                       const double *U, const float *C, double scale, double *Y) {
+                       const double *U, const float *C, double scale, const double *R,
+                       double rscale, double *Y) {
   if (!ctx || !U || !C || !Y) return -5;
   if (nc < 1 || b < 1 || r < 1 || r > b) return -1;
   if (m < 1) return -3;
   HIPCHK(hipSetDevice(context_device(ctx)));
   hipStream_t st = context_stream(ctx);
-  HIPCHK(launch_basis_expand(U, C, nc, b, r, m, scale, Y, st));
+  HIPCHK(launch_basis_expand(U, C, nc, b, r, m, scale, R, rscale, Y, st));
   HIPCHK(hipStreamSynchronize(st));
   return 0;
 }

@@ -311,9 +311,10 @@ __global__ void basis_project_kernel(const double *U, const double *T, int nc, i
   }
 }
 
-// Y[c b + i][j] = scale * sum_k U[c][i][k] C[c][k][j]  (float64 out).
+// Y[c b + i][j] = scale * sum_k U[c][i][k] C[c][k][j] + rscale * R[c b + i][j]
+// (float64 out; R may be null).
 __global__ void basis_expand_kernel(const double *U, const float *C, int nc, int b, int r, int m,
-                                    double scale, double *Y) {
+                                    double scale, const double *R, double rscale, double *Y) {
   const size_t total = (size_t)nc * b * m;
   for (size_t o = blockIdx.x * (size_t)blockDim.x + threadIdx.x; o < total;
        o += (size_t)gridDim.x * blockDim.x) {
@@ -325,7 +326,7 @@ __global__ void basis_expand_kernel(const double *U, const float *C, int nc, int
     const float *cc = C + c * r * m;
     double s = 0.0;
     for (int k = 0; k < r; ++k) s += u[k] * (double)cc[(size_t)k * m + j];
-    Y[o] = scale * s;
+    Y[o] = scale * s + (R ? rscale * R[o] : 0.0);
   }
 }
 
@@ -423,9 +424,10 @@ hipError_t launch_basis_project(const double *U, const double *T, int nc, int b,
 }
 
 hipError_t launch_basis_expand(const double *U, const float *C, int nc, int b, int r, int m,
-                               double scale, double *Y, hipStream_t st) {
+                               double scale, const double *R, double rscale, double *Y,
+                               hipStream_t st) {
   hipLaunchKernelGGL(basis_expand_kernel, dim3(blocks_for((size_t)nc * b * m, 256)), dim3(256), 0,
-                     st, U, C, nc, b, r, m, scale, Y);
+                     st, U, C, nc, b, r, m, scale, R, rscale, Y);
   return hipGetLastError();
 }
 

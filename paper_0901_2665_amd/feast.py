@@ -112,7 +112,7 @@ def load_library(path: str = LIB_PATH):
     lib.feast_tall_gemm.argtypes = [P, ctypes.c_int64, I32, I32, P, I32, P, P]
     lib.feast_cell_gram_accumulate.argtypes = [P, I32, I32, I32, P, P]
     lib.feast_basis_project.argtypes = [P, I32, I32, I32, I32, P, P, D, F32P]
-    lib.feast_basis_expand.argtypes = [P, I32, I32, I32, I32, P, F32P, D, P]
+    lib.feast_basis_expand.argtypes = [P, I32, I32, I32, I32, P, F32P, D, P, D, P]
     lib.feast_random_start.argtypes = [P, ctypes.c_uint64, ctypes.c_int64, I32, P]
     lib.feast_timing.argtypes = [P, I32]
     lib.feast_timing_read.argtypes = [P, I32, ctypes.POINTER(ctypes.c_char_p),
@@ -242,6 +242,17 @@ class Pencil:
         self.Ad, self.Au, self.Bd, self.Bu = f(Ad), f(Au), f(Bd), f(Bu)
         self.nc, self.b = int(self.Ad.shape[0]), int(self.Ad.shape[1])
         self.n = self.nc * self.b
+
+    @classmethod
+    def from_tensors(cls, Ad, Au, Bd, Bu):
+        """Wrap float64 device tensors without copying."""
+        p = cls.__new__(cls)
+        for t in (Ad, Au, Bd, Bu):
+            _ptr(t) if t.numel() else None
+        p.Ad, p.Au, p.Bd, p.Bu = Ad, Au, Bd, Bu
+        p.nc, p.b = int(Ad.shape[0]), int(Ad.shape[1])
+        p.n = p.nc * p.b
+        return p
 
     def struct(self) -> BTMatrix:
         up_a = self.Au.data_ptr() if self.Au.numel() else None
@@ -424,13 +435,14 @@ class Context:
         self._check(st, "feast_basis_project")
         return out
 
-    def basis_expand(self, nc: int, b: int, U, C, m: int, scale: float = 1.0, out=None):
+    def basis_expand(self, nc: int, b: int, U, C, m: int, scale: float = 1.0, R=None,
+                     rscale: float = 0.0, out=None):
         import torch
         r = U.shape[2]
         if out is None:
             out = torch.empty((nc * b, m), dtype=torch.float64, device=U.device)
         st = self.lib.feast_basis_expand(self.handle, nc, b, r, m, _ptr(U), _fptr(C), scale,
-                                         _ptr(out))
+                                         _ptr(R) if R is not None else None, rscale, _ptr(out))
         self._check(st, "feast_basis_expand")
         return out
 

@@ -151,7 +151,40 @@ WORKLOADS = {
                    n_eig=80, k0=1600),
     "tb32k": dict(kind="chain", nc=500, b=64, M0=64, Ne=8, mseed=4000, yseed=2004,
                   n_eig=38, k0=8000),
+    # Hamiltonian family of the learned warm start: the tb32k shape with
+    # hopping, coupling and S fixed by the family seed; the interval is the
+    # one of the member with a zero onsite potential (38 eigenvalues from
+    # index n/4); other members hold 36-50 eigenvalues in it.
+    "fam32k": dict(kind="family", nc=500, b=64, M0=64, Ne=8, mseed=4000, yseed=2005,
+                   n_eig=38, k0=8000),
+    # a small member of the same recipe for the GPU test of the warm start
+    "fam1920": dict(kind="family", nc=60, b=32, M0=32, Ne=8, mseed=4000, yseed=2006,
+                    n_eig=19, k0=480),
 }
+
+# Members of the family: s < FAMILY_TRAIN are training members, the next
+# FAMILY_TEST held out.  Member s has onsite amplitudes
+# a_s = 0.5 * N(0, I_16) drawn from default_rng(FAMILY_SEED + s).
+FAMILY_SEED = 4000
+FAMILY_MODES = 16
+FAMILY_SIGMA = 0.5
+FAMILY_TRAIN = 10000
+FAMILY_TEST = 1000
+
+
+def family_amplitudes(s: int) -> np.ndarray:
+    return FAMILY_SIGMA * np.random.default_rng(FAMILY_SEED + s).standard_normal(FAMILY_MODES)
+
+
+def family_pencil(amplitudes: np.ndarray, nc: int = 500, b: int = 64) -> Pencil:
+    """Member of the family with the given onsite amplitudes (chain recipe)."""
+    return chain_pencil(nc, b, FAMILY_SEED, amplitudes=amplitudes, family_seed=FAMILY_SEED)
+
+
+def onsite_modes(nc: int, modes: int = FAMILY_MODES) -> np.ndarray:
+    """[nc][modes] values sin(k pi s_i) of the onsite field's Fourier modes."""
+    s = (np.arange(nc) + 0.5) / nc
+    return np.sin(np.pi * np.outer(s, np.arange(1, modes + 1)))
 
 
 # Batched workload: independent uneven problems.  Problem p draws, from
@@ -196,6 +229,9 @@ def make_pencil(name: str) -> Pencil:
     w = WORKLOADS[name]
     if w["kind"] == "dense":
         return dense_random_pencil(w["nc"], w["b"], w["mseed"])
+    if w["kind"] == "family":
+        return chain_pencil(w["nc"], w["b"], w["mseed"], amplitudes=np.zeros(FAMILY_MODES),
+                            family_seed=w["mseed"])
     return chain_pencil(w["nc"], w["b"], w["mseed"])
 
 

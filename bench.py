@@ -5,7 +5,7 @@ loops to convergence, residuals) on the tight-binding chain workload
 (nc=2000 cells of b=64, n=128000, M0=128, Ne=8, interval holding 80
 eigenvalues), inputs resident in HBM.  Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload tb128k]
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload tb128k] [--no-extra]
                   [--precision 0|1] [--graph 0|1] [--no-cpu-baseline]
 
 --workload tbbatch times feast_solve_batched on the first --batch uneven
@@ -16,8 +16,13 @@ replay one captured HIP graph) to every solve of the batched workload.
 
 --precision 1 times the mixed-precision solver instead (factor blocks rounded
 to float32, complex float32 sweeps, float64 refinement of every shifted solve
-to a relative residual of 1e-12) on the same workload and also times the
-float64 solver for comparison.
+to a relative residual of 1e-12).
+
+The default run (tb128k, float64) adds two legs to the same JSON line:
+"mixed" (the mixed-precision solver on the same workload, with its gate
+against the stored oracle result and its time relative to float64) and
+"batched" (32 uneven problems of the batched workload, Ne = 16, solved
+together), each with its own roofline and CPU baseline.
 """
 from __future__ import annotations
 
@@ -104,16 +109,35 @@ def nominal_flops(nc, b, m0, ne):
     return d
 
 
+def host_cpu():
+    """Model and core counts of the host that runs the oracle."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
+
+
 def cpu_baseline(p, emin, emax, m0, ne, Y0, loops):
     """Time the oracle on a bounded sample of the same workload: one shifted
     factorisation, one shifted solve with all M0 right-hand sides, one
     projection + reduced eigensolve + Ritz vectors; extrapolate to a full
-    solve with Ne shifts and the GPU's loop count."""
+    solve with Ne shifts and the GPU's loop count.  The factorisation and
+    the solve are timed again on one thread (16 right-hand sides, scaled)."""
     from oracle import feast_oracle as O
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         threads = max(i["num_threads"] for i in threadpool_info())
     except Exception:
+        threadpool_limits = None
         threads = 1
     ct = O.contour(emin, emax, ne)
     t0 = time.perf_counter()
@@ -129,61 +153,51 @@ def cpu_baseline(p, emin, emax, m0, ne, Y0, loops):
     t3 = time.perf_counter()
     t_factor, t_solve, t_rr = t1 - t0, t2 - t1, t3 - t2
     t_full = ne * t_factor + loops * (ne * t_solve + t_rr)
-    return {"value": 1.0 / t_full, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
-            "sample": (f"1 banded LU factorisation ({t_factor:.1f}s) + 1 solve with {m0} "
-                       f"right-hand sides ({t_solve:.1f}s) + 1 projection/Rayleigh-Ritz "
-                       f"({t_rr:.1f}s) of the same workload, extrapolated to {ne} shifts x "
-                       f"{loops} loops = {t_full:.0f}s per solve")}
+    out = {"value": 1.0 / t_full, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+           "sample": (f"1 banded LU factorisation ({t_factor:.1f}s) + 1 solve with {m0} "
+                      f"right-hand sides ({t_solve:.1f}s) + 1 projection/Rayleigh-Ritz "
+                      f"({t_rr:.1f}s) of the same workload, extrapolated to {ne} shifts x "
+                      f"{loops} loops = {t_full:.0f}s per solve"),
+           "host": host_cpu()}
+    if threadpool_limits is not None:
+        k = min(16, m0)
+        with threadpool_limits(limits=1):
+            s0 = time.perf_counter()
+            lu1 = O.factor_shift(p, ct.Z[0])
+            s1 = time.perf_counter()
+            lu1.solve(R[:, :k])
+            s2 = time.perf_counter()
+        f1, v1 = s1 - s0, (s2 - s1) * m0 / k
+        t1_full = ne * f1 + loops * (ne * v1 + t_rr)
+        out["single_thread"] = {
+            "value": 1.0 / t1_full, "unit": "solves/s", "cores": 1,
+            "sample": (f"1 factorisation ({f1:.1f}s) + 1 solve with {k} right-hand sides "
+                       f"scaled to {m0} ({v1:.1f}s) on one thread; the projection/Rayleigh-"
+                       f"Ritz time of the multi-thread sample; extrapolated as above = "
+                       f"{t1_full:.0f}s per solve")}
+    return out
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="tb128k")
-    ap.add_argument("--precision", type=int, default=0, choices=(0, 1),
-                    help="0: float64 shifted solves; 1: mixed precision")
-    ap.add_argument("--batch", type=int, default=32,
-                    help="problems per step of the tbbatch workload")
-    ap.add_argument("--workers", type=int, default=0,
-                    help="host workers (HIP streams) of the tbbatch workload; 0 = automatic")
-    ap.add_argument("--graph", type=int, default=0, choices=(0, 1),
-                    help="tbbatch: 1 = loops after the first replay a captured HIP graph")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="run one 1 GiB device copy first (reference for HBM byte counters)")
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build measures the single-GPU FEAST "
-              "hot path; multi-GPU sharding is described in DESIGN.md, not run.",
-              file=sys.stderr)
-        sys.exit(2)
-
+def solve_leg(ctx, workload, precision, steps, warmup, cpu=True):
+    """Timed complete solves of one workload; returns the bench-line fields."""
     import torch
     from paper_0901_2665_amd import feast as F
     from paper_0901_2665_amd import workloads as W
-
-    if args.copy_probe:
-        copy_probe()
-    if args.workload == "tbbatch":
-        return run_batch(args)
-    p, emin, emax, m0, ne, Y0 = W.make_workload(args.workload)
-    wl = W.WORKLOADS[args.workload]
+    p, emin, emax, m0, ne, Y0 = W.make_workload(workload)
+    wl = W.WORKLOADS[workload]
     gp = F.Pencil(p.Ad, p.Au, p.Bd, p.Bu)
     y = torch.as_tensor(Y0, dtype=torch.float64, device="cuda").contiguous()
-    ctx = F.Context(0)
     out = (torch.empty(m0, dtype=torch.float64, device="cuda"),
            torch.empty((p.n, m0), dtype=torch.float64, device="cuda"),
            torch.empty(m0, dtype=torch.float64, device="cuda"))
-    prec = args.precision
-    for _ in range(args.warmup):
+    prec = precision
+    for _ in range(warmup):
         r = ctx.solve(gp, emin, emax, m0, ne, y, out=out, precision=prec)
     torch.cuda.synchronize()
     ctx.timing(True)
     t0 = time.perf_counter()
     results = []
-    for _ in range(args.steps):
+    for _ in range(steps):
         r = ctx.solve(gp, emin, emax, m0, ne, y, out=out, precision=prec)
         results.append((r.status, r.M, r.loops, r.max_res))
     torch.cuda.synchronize()
@@ -191,16 +205,6 @@ def main():
     times = ctx.timing_read()
     ctx.timing(False)
     elapsed = t1 - t0
-    fp64_rate = None
-    if prec == 1:  # the float64 solver on the same workload, for comparison
-        r64 = ctx.solve(gp, emin, emax, m0, ne, y, out=out)
-        torch.cuda.synchronize()
-        ta = time.perf_counter()
-        for _ in range(args.steps):
-            r64 = ctx.solve(gp, emin, emax, m0, ne, y, out=out)
-        torch.cuda.synchronize()
-        fp64_rate = args.steps / (time.perf_counter() - ta)
-        r = ctx.solve(gp, emin, emax, m0, ne, y, out=out, precision=prec)  # outputs for the gate
 
     # accuracy gate on the last solve
     lam = out[0].cpu().numpy()
@@ -209,16 +213,17 @@ def main():
     if prec == 1:
         gate["refine_steps"] = r.refine_steps
         gate["shifted_solve_rel_res"] = r.solve_res
-    gpath = os.path.join(ROOT, "tests", "golden", f"feast_{args.workload}.json")
+    gpath = os.path.join(ROOT, "tests", "golden", f"feast_{workload}.json")
     if os.path.exists(gpath):
         g = json.load(open(gpath))
         ref = np.array(g["lam"])
         if len(ref) == r.M:
             gate["max_rel_eig_err_vs_oracle"] = float(np.max(np.abs(lam[:r.M] - ref) / np.abs(ref)))
         gate["oracle_loops"] = g["loops"]
+        gate["oracle_max_res"] = g["max_res"]
     gate["pass"] = bool(r.M == wl["n_eig"] and r.max_res <= 1e-9 and r.status == 0 and
                         gate.get("max_rel_eig_err_vs_oracle", 0.0) <= 1e-10 and
-                        all(s == 0 and M == r.M for s, M, _, _ in results))
+                        all(s_ == 0 and M == r.M for s_, M, _, _ in results))
 
     nom = nominal_flops(p.nc, p.b, m0, ne)
     per = {}
@@ -238,25 +243,18 @@ def main():
     peak_dom = peak_of.get(dom, PEAK_FP64)
     loops_total = sum(x[2] for x in results)
     shifted_ms = sum(times[k][0] for k in solve_kernels if k in times)
-    shifted_flops = args.steps * nom["factor"] + loops_total * (nom["forward_sweep"] +
-                                                               nom["back_sweep"])
+    shifted_flops = steps * nom["factor"] + loops_total * (nom["forward_sweep"] +
+                                                          nom["back_sweep"])
     shifted_tflops = shifted_flops / (shifted_ms * 1e-3) / 1e12
     shifted_peak = PEAK_FP32 if prec == 1 else PEAK_FP64
-
-    line = {
-        "metric": METRIC,
-        "value": args.steps / elapsed,
+    leg = {
+        "value": steps / elapsed,
         "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": 1e3 * elapsed / steps,
         "dtype": "f32+f64" if prec == 1 else "f64",
-        "data": "synthetic",
-        "config": {"workload": args.workload, "nc": p.nc, "b": p.b, "n": p.n, "M0": m0,
+        "config": {"workload": workload, "nc": p.nc, "b": p.b, "n": p.n, "M0": m0,
                    "Ne": ne, "interval": [emin, emax], "eigenvalues_in_interval": wl["n_eig"],
                    "tol": 1e-12, "precision": "mixed" if prec == 1 else "float64"},
         "shifted_solve_tflops": shifted_tflops,
@@ -265,40 +263,34 @@ def main():
         "kernels": per,
         "roofline": {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": peak_dom,
                      "unit": "TFLOP/s", "frac": achieved / peak_dom,
-                     "traffic": measured_traffic(args.workload, dom)},
+                     "traffic": (measured_traffic(workload, dom) if prec == 0 else None)},
     }
-    if fp64_rate is not None:
-        line["float64_solves_per_s"] = fp64_rate
-        line["mixed_over_float64"] = line["value"] / fp64_rate
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(p, emin, emax, m0, ne, Y0, r.loops)
-    ctx.close()
-    print(json.dumps(line), flush=True)
+    if cpu:
+        leg["cpu_baseline"] = cpu_baseline(p, emin, emax, m0, ne, Y0, r.loops)
+    return leg
 
 
-def run_batch(args):
+def batch_leg(ctx, count, precision, steps, warmup, workers=0, graph=0, cpu=True):
     """Independent uneven problems (nc 50..200, b 32/48/64, M0 16..64, Ne 16)
     solved together by feast_solve_batched; value = problems solved per second."""
     import torch
     from paper_0901_2665_amd import feast as F
     from paper_0901_2665_amd import workloads as W
-    probs = W.make_batch(args.batch)
+    probs = W.make_batch(count)
     dev = lambda a: torch.as_tensor(a, dtype=torch.float64, device="cuda").contiguous()
     batch = [(F.Pencil(p.Ad, p.Au, p.Bd, p.Bu), emin, emax, m0, ne, dev(Y0))
              for p, emin, emax, m0, ne, Y0 in probs]
-    ctx = F.Context(0)
     tol = 1e-13  # the paper's trace tolerance (Sec. IV.A)
-    for _ in range(args.warmup):
-        ctx.solve_batched(batch, tol=tol, precision=args.precision, workers=args.workers,
-                          graph=args.graph)
+    for _ in range(warmup):
+        ctx.solve_batched(batch, tol=tol, precision=precision, workers=workers, graph=graph)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        st, rs = ctx.solve_batched(batch, tol=tol, precision=args.precision,
-                                   workers=args.workers, graph=args.graph)
+    for _ in range(steps):
+        st, rs = ctx.solve_batched(batch, tol=tol, precision=precision, workers=workers,
+                                   graph=graph)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    want = [W.batch_shape(i)["n_eig"] for i in range(args.batch)]
+    want = [W.batch_shape(i)["n_eig"] for i in range(count)]
     # status 2 (B_Q fallback: with Ne = 16 the filtered outside directions
     # can vanish numerically) still writes converged outputs
     gate = {"status": st, "statuses": sorted({r.status for r in rs}),
@@ -307,32 +299,114 @@ def run_batch(args):
             "above_1e-9": [i for i, r in enumerate(rs) if r.max_res > 1e-9]}
     gate["pass"] = bool(all(r.status in (0, 2) for r in rs) and gate["all_M_match"] and
                         gate["max_res"] <= 1e-9)
-    shapes = [W.batch_shape(i) for i in range(args.batch)]
-    line = {
-        "metric": METRIC,
-        "value": args.steps * args.batch / elapsed,
-        "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32+f64" if args.precision == 1 else "f64",
-        "data": "synthetic",
-        "config": {"workload": "tbbatch", "problems": args.batch,
-                   "nc": [min(s["nc"] for s in shapes), max(s["nc"] for s in shapes)],
-                   "b": sorted({s["b"] for s in shapes}),
-                   "M0": [min(s["M0"] for s in shapes), max(s["M0"] for s in shapes)],
+    shapes = [W.batch_shape(i) for i in range(count)]
+    # whole-step rate: nominal shifted-solve work of every problem (factor once,
+    # forward and back sweeps per loop) over the wall time of the step
+    flops = 0.0
+    for s_, r in zip(shapes, rs):
+        nom = nominal_flops(s_["nc"], s_["b"], s_["M0"], s_["Ne"])
+        flops += nom["factor"] + r.loops * (nom["forward_sweep"] + nom["back_sweep"])
+    achieved = flops * steps / elapsed / 1e12
+    leg = {
+        "value": steps * count / elapsed,
+        "unit": "problems/s",
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": 1e3 * elapsed / steps,
+        "dtype": "f32+f64" if precision == 1 else "f64",
+        "config": {"workload": "tbbatch", "problems": count,
+                   "nc": [min(x["nc"] for x in shapes), max(x["nc"] for x in shapes)],
+                   "b": sorted({x["b"] for x in shapes}),
+                   "M0": [min(x["M0"] for x in shapes), max(x["M0"] for x in shapes)],
                    "Ne": W.BATCH_NE, "tol": tol,
-                   "precision": "mixed" if args.precision == 1 else "float64",
-                   "workers": args.workers or min(args.batch, 8), "graph": args.graph},
+                   "precision": "mixed" if precision == 1 else "float64",
+                   "workers": workers or min(count, 8), "graph": graph},
         "gate": gate,
-        # kernels of the workers' streams are not timed individually
-        "roofline": None,
-        "cpu_baseline": None,
+        # kernels of the workers' streams are not timed one by one: the
+        # nominal shifted-solve work of the whole step over its wall time
+        "roofline": {"bound": "mfma", "kernel": "whole batched step (shifted solves, nominal)",
+                     "achieved": achieved,
+                     "peak": PEAK_FP32 if precision == 1 else PEAK_FP64, "unit": "TFLOP/s",
+                     "frac": achieved / (PEAK_FP32 if precision == 1 else PEAK_FP64),
+                     "traffic": None},
     }
+    if cpu:
+        leg["cpu_baseline"] = batch_cpu_baseline(probs[0], shapes, [r.loops for r in rs])
+    return leg
+
+
+def batch_cpu_baseline(prob0, shapes, loops):
+    """The oracle's complete FEAST solve of batch problem 0, extrapolated to
+    the batch by the nominal shifted-solve work of each problem."""
+    from oracle import feast_oracle as O
+    p, emin, emax, m0, ne, Y0 = prob0
+    t0 = time.perf_counter()
+    r = O.feast(p, emin, emax, m0, ne, Y0, tol=1e-13)
+    t = time.perf_counter() - t0
+    work = lambda s_, lp: (nominal_flops(s_["nc"], s_["b"], s_["M0"], s_["Ne"])["factor"] +
+                           lp * sum(nominal_flops(s_["nc"], s_["b"], s_["M0"], s_["Ne"])[k]
+                                    for k in ("forward_sweep", "back_sweep")))
+    scale = sum(work(s_, lp) for s_, lp in zip(shapes, loops)) / work(shapes[0], r.loops)
+    return {"value": len(shapes) / (t * scale), "unit": "problems/s", "kind": "oracle",
+            "cores": host_cpu()["usable_cpus"], "extrapolated": True,
+            "sample": (f"complete oracle solve of problem 0 (nc {shapes[0]['nc']}, b "
+                       f"{shapes[0]['b']}, M0 {shapes[0]['M0']}: {t:.1f}s, {r.loops} loops), "
+                       f"extrapolated to the {len(shapes)} problems by nominal work "
+                       f"(x{scale:.1f})")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="tb128k")
+    ap.add_argument("--precision", type=int, default=0, choices=(0, 1),
+                    help="0: float64 shifted solves; 1: mixed precision")
+    ap.add_argument("--batch", type=int, default=32,
+                    help="problems per step of the tbbatch workload")
+    ap.add_argument("--workers", type=int, default=0,
+                    help="host workers (HIP streams) of the tbbatch workload; 0 = automatic")
+    ap.add_argument("--graph", type=int, default=0, choices=(0, 1),
+                    help="tbbatch: 1 = loops after the first replay a captured HIP graph")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="only the headline line (no mixed-precision and batched legs)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one 1 GiB device copy first (reference for HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build measures the single-GPU FEAST "
+              "hot path; multi-GPU sharding is described in DESIGN.md, not run.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    from paper_0901_2665_amd import feast as F
+
+    if args.copy_probe:
+        copy_probe()
+    ctx = F.Context(0)
+    cpu = not args.no_cpu_baseline
+    if args.workload == "tbbatch":
+        leg = batch_leg(ctx, args.batch, args.precision, args.steps, args.warmup, args.workers,
+                        args.graph, cpu)
+    else:
+        leg = solve_leg(ctx, args.workload, args.precision, args.steps, args.warmup, cpu)
+    line = {"metric": METRIC, "value": leg.pop("value"), "unit": leg.pop("unit"), "n_gpus": 1}
+    line.update({k: leg.pop(k) for k in ("steps", "warmup", "ms_per_step")})
+    line.update({"higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                 "dtype": leg.pop("dtype"), "data": "synthetic"})
+    line.update(leg)
+    if args.workload == "tb128k" and args.precision == 0 and not args.no_extra:
+        # the scope table's next rows on the same box, same run: mixed precision
+        # on the same workload, and the batched uneven problems
+        mixed = solve_leg(ctx, "tb128k", 1, 2, 1, cpu=False)
+        mixed["vs_float64"] = mixed["value"] / line["value"]
+        if cpu:
+            mixed["cpu_baseline"] = dict(line["cpu_baseline"], extrapolated=True,
+                                         note="the float64 oracle of the headline line")
+        line["mixed"] = mixed
+        line["batched"] = batch_leg(ctx, 32, 0, 2, 1, cpu=cpu)
     ctx.close()
     print(json.dumps(line), flush=True)
 

@@ -237,9 +237,11 @@ class BandedLU:
         if info != 0:
             raise np.linalg.LinAlgError(f"zgbtrf info={info}")
 
-    def solve(self, R: np.ndarray) -> np.ndarray:
+    def solve(self, R: np.ndarray, adjoint: bool = False) -> np.ndarray:
+        """M^{-1} R, or M^{-H} R with ``adjoint`` (LAPACK trans = 'C')."""
         x, info = lapack.zgbtrs(self.lu, self.kl, self.ku,
-                                np.asarray(R, dtype=np.complex128), self.piv)
+                                np.asarray(R, dtype=np.complex128), self.piv,
+                                trans=2 if adjoint else 0)
         if info != 0:
             raise np.linalg.LinAlgError(f"zgbtrs info={info}")
         return x
@@ -444,6 +446,171 @@ def feast(p, emin: float, emax: float, m0: int, ne: int, Y0: np.ndarray,
         status = 0
     return FeastResult(lam, X, res, M, len(traces), traces[-1], float(trace_rel),
                        max_res, status, traces, counts)
+
+
+# --------------------------------------------------------------------------
+# Hermitian A (Sec. III.B, eq. 12 and the changes listed after Fig. 2)
+# --------------------------------------------------------------------------
+# A complex Hermitian, B real s.p.d.; Y, Q, Phi and X complex.  Same readings
+# as above (RHS B Y, counting gate, convergence, residual, B_Q test).
+
+
+def assemble_hermitian(diag: np.ndarray, up: np.ndarray) -> sp.csr_matrix:
+    """Sparse matrix of a block-tridiagonal Hermitian operator (lower block =
+    conjugate transpose of the upper one)."""
+    nc = diag.shape[0]
+    if nc == 1:
+        return sp.csr_matrix(diag[0])
+    blocks = [[None] * nc for _ in range(nc)]
+    for i in range(nc):
+        blocks[i][i] = sp.csr_matrix(diag[i])
+        if i + 1 < nc:
+            blocks[i][i + 1] = sp.csr_matrix(up[i])
+            blocks[i + 1][i] = sp.csr_matrix(up[i].conj().T)
+    return sp.bmat(blocks, format="csr")
+
+
+def shifted_matrix_hermitian(p, z: complex) -> sp.csr_matrix:
+    """z B - A for a Hermitian pencil."""
+    A = assemble_hermitian(p.Ad, p.Au)
+    B = assemble(p.Bd, p.Bu).astype(np.complex128)
+    return (z * B - A).tocsr()
+
+
+def factor_shift_hermitian(p, z: complex) -> BandedLU:
+    b = p.b
+    half_band = 2 * b - 1 if p.nc > 1 else b - 1
+    return BandedLU(shifted_matrix_hermitian(p, z), max(half_band, 0))
+
+
+def filter_apply_hermitian(p, emin: float, emax: float, ne: int, Y: np.ndarray,
+                           factors=None) -> np.ndarray:
+    """Eq. 12 with RHS B Y: Q = -sum_e (w_e/4) r (e^{i theta_e} G(Z_e)
+    + e^{-i theta_e} G(Z_e)^H) B Y, G(Z) = (Z B - A)^{-1}; the adjoint solve
+    reuses the factorisation of Z_e B - A (G(conj Z) = G(Z)^H)."""
+    ct = contour(emin, emax, ne)
+    B = assemble(p.Bd, p.Bu)
+    R = B @ np.asarray(Y, dtype=np.complex128)
+    Q = np.zeros(R.shape, dtype=np.complex128)
+    for e in range(ne):
+        lu = factors[e] if factors is not None else factor_shift_hermitian(p, ct.Z[e])
+        x = lu.solve(R)
+        y = lu.solve(R, adjoint=True)
+        ph = np.exp(1j * ct.theta[e])
+        Q -= (ct.w[e] / 4.0) * ct.r * (ph * x + np.conj(ph) * y)
+    return Q
+
+
+def project_hermitian(p, Q: np.ndarray):
+    """A_Q = Q^H A Q and B_Q = Q^H B Q, Hermitian parts."""
+    A = assemble_hermitian(p.Ad, p.Au)
+    B = assemble(p.Bd, p.Bu)
+    AQ = Q.conj().T @ (A @ Q)
+    BQ = Q.conj().T @ (B @ Q)
+    return 0.5 * (AQ + AQ.conj().T), 0.5 * (BQ + BQ.conj().T)
+
+
+def reduced_eig_hermitian(AQ: np.ndarray, BQ: np.ndarray):
+    """Complex Hermitian version of reduced_eig (same B_Q test and fallback)."""
+    m0 = AQ.shape[0]
+    spd = False
+    try:
+        L = np.linalg.cholesky(BQ)
+        spd = bool(np.all(np.abs(np.diag(L)) ** 2 > 1e-12 * np.real(np.diag(BQ))))
+    except np.linalg.LinAlgError:
+        pass
+    if spd:
+        try:
+            eps, Phi = scipy.linalg.eigh(AQ, BQ)
+            return eps, Phi, False
+        except np.linalg.LinAlgError:
+            pass
+    mu, V = np.linalg.eigh(BQ)
+    keep = mu > 1e-10 * np.max(mu)
+    T = V[:, keep] / np.sqrt(mu[keep])
+    eps_k, W = np.linalg.eigh(T.conj().T @ AQ @ T)
+    eps = np.full(m0, np.nan)
+    Phi = np.zeros((m0, m0), dtype=np.complex128)
+    k = int(keep.sum())
+    eps[:k] = eps_k
+    Phi[:, :k] = T @ W
+    return eps, Phi, True
+
+
+def residuals_hermitian(p, lam: np.ndarray, X: np.ndarray, emin: float,
+                        emax: float) -> np.ndarray:
+    """Per column ||A x - lam B x||_1 / ||A x||_1 with complex moduli, and the
+    small-||Ax|| guard of the real case."""
+    A = assemble_hermitian(p.Ad, p.Au)
+    B = assemble(p.Bd, p.Bu)
+    AX = A @ X
+    BX = B @ X
+    r = (emax - emin) / 2.0
+    num = np.sum(np.abs(AX - BX * lam[None, :]), axis=0)
+    na = np.sum(np.abs(AX), axis=0)
+    nb = np.sum(np.abs(BX), axis=0)
+    den = np.where(na < r * nb, nb * max(abs(emin), abs(emax), r), na)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        return num / den
+
+
+def feast_hermitian(p, emin: float, emax: float, m0: int, ne: int, Y0: np.ndarray,
+                    tol: float = 1e-12, max_loops: int = 20) -> FeastResult:
+    """Fig. 2 with the Hermitian changes: complex Y, Q, Phi and X, eq. 12."""
+    ct = contour(emin, emax, ne)
+    factors = [factor_shift_hermitian(p, ct.Z[e]) for e in range(ne)]
+    Y = np.array(Y0, dtype=np.complex128, copy=True)
+    traces, counts = [], []
+    converged = False
+    fallback = False
+    trace_rel = np.inf
+    prev_left_min = np.inf
+    for k in range(1, max_loops + 1):
+        Q = filter_apply_hermitian(p, emin, emax, ne, Y, factors)
+        AQ, BQ = project_hermitian(p, Q)
+        eps, Phi, fallback = reduced_eig_hermitian(AQ, BQ)
+        X = Q @ Phi
+        res = residuals_hermitian(p, eps, X, emin, emax)
+        inside = counted(eps, res, emin, emax, tol)
+        left_min = smallest_uncounted_residual(eps, res, inside, emin, emax)
+        still_converging = left_min < UNCOUNTED_DROP * prev_left_min
+        prev_left_min = left_min
+        Mk = int(inside.sum())
+        Tk = float(np.sum(eps[inside]))
+        if k >= 2:
+            if Mk == 0 and counts[-1] == 0:
+                trace_rel = 0.0
+            else:
+                trace_rel = abs(Tk - traces[-1]) / max(abs(Tk), Mk * ct.r)
+        traces.append(Tk)
+        counts.append(Mk)
+        if k >= 2 and Mk == counts[-2] and trace_rel < tol and not still_converging:
+            converged = True
+            break
+        Y = X
+    perm = order_ritz(eps, inside)
+    lam, X, res = eps[perm], X[:, perm], res[perm]
+    M = counts[-1]
+    max_res = float(np.max(res[:M])) if M > 0 else 0.0
+    if not converged:
+        status = 1
+    elif fallback:
+        status = 2
+    elif M == m0:
+        status = 4
+    elif M == 0:
+        status = 3
+    else:
+        status = 0
+    return FeastResult(lam, X, res, M, len(traces), traces[-1], float(trace_rel),
+                       max_res, status, traces, counts)
+
+
+def bruteforce_hermitian(p):
+    """All eigenpairs of the dense Hermitian pencil (LAPACK)."""
+    A = assemble_hermitian(p.Ad, p.Au).toarray()
+    B = assemble(p.Bd, p.Bu).toarray()
+    return scipy.linalg.eigh(A, B)
 
 
 # --------------------------------------------------------------------------

@@ -131,6 +131,56 @@ def chain_pencil(nc: int, b: int, seed: int, amplitudes: np.ndarray | None = Non
     return Pencil(Ad, Au, Bd, Bu)
 
 
+@dataclasses.dataclass
+class HermitianPencil:
+    """A complex Hermitian A and a real s.p.d. B in block-tridiagonal storage:
+    Ad[nc][b][b] Hermitian, Au[nc-1][b][b] complex with block (i+1, i) =
+    Au[i]^H; Bd, Bu real as in Pencil."""
+    Ad: np.ndarray
+    Au: np.ndarray
+    Bd: np.ndarray
+    Bu: np.ndarray
+
+    @property
+    def nc(self) -> int:
+        return self.Ad.shape[0]
+
+    @property
+    def b(self) -> int:
+        return self.Ad.shape[1]
+
+    @property
+    def n(self) -> int:
+        return self.nc * self.b
+
+
+def hermitian_pencil(nc: int, b: int, seed: int, coupling: float = 0.3,
+                     phase: float = 0.4, b_scale: float = 0.05) -> HermitianPencil:
+    """Complex Hermitian variant of the dense-coupling chain: diagonal blocks
+    sym(U[-1,1]) + i phase * antisym(U[-1,1]); couplings U[-c,c] times unit
+    phases exp(i phase U[-pi,pi]) (a Peierls-like factor on every hopping);
+    B = I + b_scale S, real s.p.d., by the recipe of dense_random_pencil."""
+    sa, sb = np.random.SeedSequence(seed).spawn(2)
+    ra, rb = np.random.default_rng(sa), np.random.default_rng(sb)
+    Dr = _sym_uniform(ra, nc, b, -1.0, 1.0)
+    K = ra.uniform(-1.0, 1.0, size=(nc, b, b))
+    Di = phase * (K - np.transpose(K, (0, 2, 1))) / 2.0
+    Ad = Dr + 1j * Di
+    mag = ra.uniform(-coupling, coupling, size=(max(nc - 1, 0), b, b))
+    ph = np.exp(1j * phase * ra.uniform(-np.pi, np.pi, size=(max(nc - 1, 0), b, b)))
+    Au = mag * ph
+    Sd = _sym_uniform(rb, nc, b, -1.0, 1.0)
+    Su = rb.uniform(-coupling, coupling, size=(max(nc - 1, 0), b, b))
+    eye = np.eye(b)[None, :, :]
+    return HermitianPencil(Ad, Au, eye + b_scale * Sd, b_scale * Su)
+
+
+def random_complex_subspace(n: int, m0: int, seed: int) -> np.ndarray:
+    """Complex start block: real and imaginary parts N(0, 1/2) (unit variance)."""
+    rng = np.random.default_rng(seed)
+    return (rng.standard_normal((n, m0)) + 1j * rng.standard_normal((n, m0))) / np.sqrt(2.0)
+
+
 def random_subspace(n: int, m0: int, seed: int) -> np.ndarray:
     """Initial guess Y ~ N(0,1), shape [n][m0] (Fig. 2 step 1: random vectors)."""
     return np.random.default_rng(seed).standard_normal((n, m0))

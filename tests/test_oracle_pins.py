@@ -467,3 +467,107 @@ def test_planted_untransposed_coupling_is_caught(monkeypatch):
     r = O.feast(p, emin, emax, 6, 8, Y0, max_loops=10)
     ok = (r.M == 3 and np.max(np.abs(r.lam[:3] - lam_ref[4:7])) <= 1e-10)
     assert not ok
+
+
+# ------------------------------------------------- Hermitian A (eq. 12)
+
+def test_hermitian_pencil_is_hermitian_definite():
+    p = W.hermitian_pencil(4, 6, 1)
+    A = O.assemble_hermitian(p.Ad, p.Au).toarray()
+    B = O.assemble(p.Bd, p.Bu).toarray()
+    assert np.max(np.abs(A - A.conj().T)) == 0.0 and np.max(np.abs(A.imag)) > 0.1
+    assert np.min(np.linalg.eigvalsh(B)) > 0.5
+
+
+def test_hermitian_adjoint_solve():
+    # the adjoint solve of the factorised z B - A is a solve with z* B - A
+    p = W.hermitian_pencil(4, 5, 2)
+    z = 0.2 + 0.07j
+    R = W.random_complex_subspace(p.n, 3, 3)
+    lu = O.factor_shift_hermitian(p, z)
+    M = O.shifted_matrix_hermitian(p, z).toarray()
+    assert np.allclose(lu.solve(R), np.linalg.solve(M, R), rtol=1e-12, atol=1e-13)
+    Mc = O.shifted_matrix_hermitian(p, np.conj(z)).toarray()
+    assert np.allclose(M.conj().T, Mc, rtol=0, atol=1e-15)
+    assert np.allclose(lu.solve(R, adjoint=True), np.linalg.solve(Mc, R), rtol=1e-12, atol=1e-13)
+
+
+def _hermitian_spectral_error(p, emin, emax, Y, filt):
+    lam, X = O.bruteforce_hermitian(p)
+    Q = filt(p, emin, emax, 8, Y)
+    f = filter_values(lam, emin, emax, 8)
+    B = O.assemble(p.Bd, p.Bu)
+    ref = -X @ (f[:, None] * (X.conj().T @ (B @ Y)))
+    return np.linalg.norm(Q - ref) / np.linalg.norm(ref)
+
+
+def test_hermitian_contour_integration_spectral_form():
+    # with B-orthonormal eigenvectors G(Z) = X (Z - Lambda)^-1 X^H and
+    # G(Z)^H = X (conj Z - Lambda)^-1 X^H, so eq. 12 is Q = -X diag(f) X^H B Y
+    # with the same rational filter f as the real case
+    p = W.hermitian_pencil(4, 5, 4)
+    lam, _ = O.bruteforce_hermitian(p)
+    emin, emax = gap_interval(lam, 6, 5)
+    Y = W.random_complex_subspace(p.n, 7, 5)
+    assert _hermitian_spectral_error(p, emin, emax, Y, O.filter_apply_hermitian) <= 1e-12
+
+
+def test_planted_missing_adjoint_term_is_caught():
+    # G(Z_e) in both terms of eq. 12 instead of G(Z_e) and G(Z_e)^H
+    def bad(p, emin, emax, ne, Y):
+        ct = O.contour(emin, emax, ne)
+        R = O.assemble(p.Bd, p.Bu) @ Y
+        Q = np.zeros(R.shape, dtype=np.complex128)
+        for e in range(ne):
+            x = O.factor_shift_hermitian(p, ct.Z[e]).solve(R)
+            ph = np.exp(1j * ct.theta[e])
+            Q -= (ct.w[e] / 4.0) * ct.r * (ph * x + np.conj(ph) * x)
+        return Q
+    p = W.hermitian_pencil(4, 5, 4)
+    lam, _ = O.bruteforce_hermitian(p)
+    emin, emax = gap_interval(lam, 6, 5)
+    Y = W.random_complex_subspace(p.n, 7, 5)
+    assert _hermitian_spectral_error(p, emin, emax, Y, bad) > 1e-3
+
+
+@pytest.mark.parametrize("nc,b,seed,k0,m,extra", [
+    (2, 3, 1, 1, 2, 2), (4, 5, 3, 5, 6, 4), (6, 8, 4, 10, 12, 6), (3, 7, 6, 4, 1, 2),
+    (8, 16, 7, 40, 10, 8)])
+def test_hermitian_feast_matches_bruteforce(nc, b, seed, k0, m, extra):
+    p = W.hermitian_pencil(nc, b, seed)
+    lam, Xb = O.bruteforce_hermitian(p)
+    emin, emax = gap_interval(lam, k0, m)
+    m0 = min(m + extra, p.n)
+    Y0 = W.random_complex_subspace(p.n, m0, seed + 100)
+    r = O.feast_hermitian(p, emin, emax, m0, 8, Y0, tol=1e-13, max_loops=40)
+    assert r.status in (0, 4) and r.M == m
+    ref = lam[k0:k0 + m]
+    scale = np.maximum(np.abs(ref), (emax - emin) / 2)
+    assert np.max(np.abs(r.lam[:m] - ref) / scale) <= 1e-12
+    B = O.assemble(p.Bd, p.Bu)
+    Xm = r.X[:, :m]
+    assert np.max(np.abs(Xm.conj().T @ (B @ Xm) - np.eye(m))) <= 1e-12
+    assert r.max_res <= 1e-11
+    # the subspace is the brute-force one (principal angles)
+    s = np.linalg.svd(Xb[:, k0:k0 + m].conj().T @ (B @ Xm), compute_uv=False)
+    assert np.min(s) >= 1 - 1e-10
+
+
+def test_hermitian_real_case_matches_real_path():
+    # with a zero imaginary part, eq. 12 reduces to eq. 15 and the Hermitian
+    # path returns the eigenvalues of the real symmetric one
+    pr = tiny_pencil(5, 6, 8)
+    ph = W.HermitianPencil(pr.Ad.astype(np.complex128), pr.Au.astype(np.complex128),
+                           pr.Bd, pr.Bu)
+    lam, _ = O.bruteforce(pr)
+    emin, emax = gap_interval(lam, 8, 5)
+    Y0 = W.random_subspace(pr.n, 9, 3)
+    rr = O.feast(pr, emin, emax, 9, 8, Y0, tol=1e-13, max_loops=40)
+    rh = O.feast_hermitian(ph, emin, emax, 9, 8, Y0.astype(np.complex128), tol=1e-13,
+                           max_loops=40)
+    assert rr.M == rh.M == 5
+    assert np.max(np.abs(rr.lam[:5] - rh.lam[:5])) <= 1e-12 * np.max(np.abs(lam))
+    Qr = O.filter_apply(pr, emin, emax, 8, Y0)
+    Qh = O.filter_apply_hermitian(ph, emin, emax, 8, Y0.astype(np.complex128))
+    assert np.max(np.abs(Qh.imag)) <= 1e-14 * np.max(np.abs(Qr))
+    assert np.allclose(Qh.real, Qr, rtol=1e-12, atol=1e-14 * np.max(np.abs(Qr)))

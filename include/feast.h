@@ -350,6 +350,49 @@ int feast_timing(feast_ctx *ctx, int32_t enable);
 int feast_timing_read(feast_ctx *ctx, int32_t kind, const char **name, double *total_ms,
                       int64_t *launches);
 
+/* ---- Hermitian A (Sec. III.B, eq. 12, and the changes listed after Fig. 2) ----
+ *
+ * A complex Hermitian, B real symmetric positive definite (Sec. III.A).  The
+ * start block Y, the subspace Q, the reduced eigenvectors Phi and the Ritz
+ * vectors X are complex; one contour integration is eq. 12 with RHS B Y:
+ *   Q = -sum_e (w_e/4) r (e^{i theta_e} G(Z_e) + e^{-i theta_e} G(Z_e)^H) B Y,
+ * G(Z) = (Z B - A)^{-1}; the adjoint solve G(Z_e)^H uses the factorisation of
+ * Z_e B - A (G(conj Z) = G(Z)^H).  A_Q = Q^H A Q and B_Q = Q^H B Q are
+ * Hermitian; the reduced problem is solved through its real symmetric
+ * embedding [[Re, -Im], [Im, Re]] of size 2 M0, whose eigenvalues come in
+ * pairs.  Complex arrays are interleaved (re, im) doubles (C99 double
+ * complex, torch.complex128).  Counting, convergence, residual and output
+ * order as in feast_solve (residual 1-norms of complex moduli).
+ * Limits: b <= 64, M0 <= 64.  The factorisation runs one workgroup per
+ * contour point over all cells in order (no partitions).
+ */
+typedef struct {
+  int32_t nc;            /* number of cells, >= 1 */
+  int32_t b;             /* block size, 1..64 */
+  const double *A_diag;  /* (dev) complex [nc][b][b], Hermitian blocks */
+  const double *A_up;    /* (dev) complex [nc-1][b][b]; block (i+1, i) is the
+                            conjugate transpose of block (i, i+1) */
+  const double *B_diag;  /* (dev) real [nc][b][b], as feast_bt_matrix */
+  const double *B_up;    /* (dev) real [nc-1][b][b] */
+} feast_zbt_matrix;
+
+/* Full FEAST solve for Hermitian A.  lambda (dev) [M0] real; X (dev) complex
+ * [N][M0], B-orthonormal (X^H B X = I); res (dev) [M0].  opts as feast_solve
+ * (precision 0 only; Y0 complex [N][M0] or NULL: then the real and imaginary
+ * parts are the seeded standard normal draws of an N x 2 M0 real block,
+ * interleaved).  Errors as feast_solve; b > 64 gives -1, M0 > 64 gives -3. */
+int feast_solve_hermitian(feast_ctx *ctx, const feast_zbt_matrix *AB, double emin, double emax,
+                          int32_t M0, int32_t Ne, const feast_opts *opts, double *lambda,
+                          double *X, double *res, feast_info *info);
+/* X (dev, complex [N][m]) = (z B - A)^{-1} R, or (z B - A)^{-H} R when
+ * adjoint != 0, for complex R (dev) [N][m], Im z > 0, m <= 64. */
+int feast_shifted_solve_hermitian(feast_ctx *ctx, const feast_zbt_matrix *AB, double z_re,
+                                  double z_im, int32_t m, const double *R, int32_t adjoint,
+                                  double *X);
+/* One contour integration of eq. 12 (RHS B Y): Y, Q (dev) complex [N][M0]. */
+int feast_filter_hermitian(feast_ctx *ctx, const feast_zbt_matrix *AB, double emin, double emax,
+                           int32_t M0, int32_t Ne, const double *Y, double *Q);
+
 /* ---- learned warm start for a Hamiltonian family ----
  *
  * An extension of the project, rooted in the subspace reuse of Sec. IV.C

@@ -18,7 +18,7 @@ OUT = os.path.join(PKG, "libfeast.so")
 BUILD = os.path.join(ROOT, "_build")
 ARCH = os.environ.get("FEAST_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["factor.hip", "sweep.hip", "sweep32.hip", "dense.hip", "rr.hip", "warm.hip", "feast.cpp",
+SOURCES = ["factor.hip", "sweep.hip", "sweep32.hip", "dense.hip", "rr.hip", "warm.hip", "herm.hip", "feast.cpp",
            "warm.cpp"]
 
 HIP_FLAGS = [

@@ -27,6 +27,10 @@ constexpr int kMaxM0 = 128;
 // convergence waits while the smallest residual of the uncounted in-interval
 // Ritz pairs falls below this fraction of its previous-loop value
 constexpr double kUncountedDrop = 0.5;
+// Hermitian variant: block size and subspace limits (the reduced problem is
+// solved through its real embedding of size 2 M0 <= 128)
+constexpr int kMaxHB = 64;
+constexpr int kMaxHM0 = 64;
 
 struct Buf {
   void *ptr = nullptr;
@@ -36,7 +40,10 @@ struct Buf {
 enum Slot {
   S_SINV, S_W, S_WT, S_TW, S_G, S_TV, S_Y, S_R, S_P, S_Q, S_X, S_GRAMP, S_AQ, S_BQ,
   S_EPS, S_PHI, S_RRS, S_FLAG, S_RESP, S_RES, S_PERM, S_T0, S_T1, S_FWORK, S_CHAINS,
-  S_SINV32, S_W32, S_WT32, S_G32, S_TV32, S_XC, S_RC, S_RPART, S_WORST, S_COUNT
+  S_SINV32, S_W32, S_WT32, S_G32, S_TV32, S_XC, S_RC, S_RPART, S_WORST,
+  // Hermitian variant
+  S_HSINV, S_HW, S_HV, S_HG, S_HY, S_HR, S_HQ, S_HX, S_HAX, S_HBX, S_HPART, S_HAQ, S_HBQ,
+  S_HEA, S_HEB, S_HEPS2, S_HPHI2, S_HEPS, S_HPHI, S_HRES, S_HCOEF, S_COUNT
 };
 
 }  // namespace
@@ -1132,3 +1139,305 @@ int feast_autotune_partitions(feast_ctx *ctx, const feast_bt_matrix *AB, double 
 }
 
 }  // extern "C"
+
+
+// ---- Hermitian A (Sec. III.B, eq. 12 and the changes listed after Fig. 2) ----
+
+namespace {
+
+int validate_hmatrix(const feast_zbt_matrix *AB) {
+  if (!AB) return -5;
+  if (AB->nc < 1 || AB->b < 1 || AB->b > kMaxHB) return -1;
+  if (!AB->A_diag || !AB->B_diag) return -5;
+  if (AB->nc > 1 && (!AB->A_up || !AB->B_up)) return -5;
+  return 0;
+}
+
+HPencil make_hpencil(const feast_zbt_matrix *AB) {
+  HPencil p;
+  p.Ad = AB->A_diag;
+  p.Au = AB->A_up;
+  p.Bd = AB->B_diag;
+  p.Bu = AB->B_up;
+  p.nc = AB->nc;
+  p.b = AB->b;
+  return p;
+}
+
+int check_hinputs(feast_ctx *ctx, const feast_zbt_matrix *AB, const double *Y0, size_t ny) {
+  int *flag = nullptr;
+  HIPCHK(ensure_t(ctx, S_FLAG, 4, &flag));
+  HIPCHK(hipMemsetAsync(flag, 0, 4 * sizeof(int), ctx->stream));
+  const size_t bb = (size_t)AB->b * AB->b;
+  HIPCHK(launch_check_finite(AB->A_diag, 2 * AB->nc * bb, flag, ctx->stream));
+  HIPCHK(launch_check_finite(AB->B_diag, AB->nc * bb, flag, ctx->stream));
+  if (AB->nc > 1) {
+    HIPCHK(launch_check_finite(AB->A_up, 2 * (AB->nc - 1) * bb, flag, ctx->stream));
+    HIPCHK(launch_check_finite(AB->B_up, (AB->nc - 1) * bb, flag, ctx->stream));
+  }
+  if (Y0) HIPCHK(launch_check_finite(Y0, ny, flag, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->h_flag, flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return ctx->h_flag[0] ? -6 : 0;
+}
+
+// Factors of every node: Sinv, W, V (complex).
+struct HFactors {
+  double *Sinv, *W, *V;
+};
+
+int prepare_hfactors(feast_ctx *ctx, const HPencil &p, int Ne, HFactors &f) {
+  const size_t bb2 = 2 * (size_t)p.b * p.b;
+  const size_t nf = p.nc > 1 ? p.nc - 1 : 1;
+  HIPCHK(ensure_t(ctx, S_HSINV, (size_t)Ne * p.nc * bb2, &f.Sinv));
+  HIPCHK(ensure_t(ctx, S_HW, (size_t)Ne * nf * bb2, &f.W));
+  HIPCHK(ensure_t(ctx, S_HV, (size_t)Ne * nf * bb2, &f.V));
+  return 0;
+}
+
+// Eq. 12 for the complex right-hand side R [N][m]: Q [N][m].
+int hfilter(feast_ctx *ctx, const HPencil &p, int Ne, const HFactors &f, const double *R, int m,
+            const double *coef_dev, double *Q) {
+  const size_t N = (size_t)p.nc * p.b;
+  double *G;
+  HIPCHK(ensure_t(ctx, S_HG, (size_t)Ne * 2 * N * m * 2, &G));
+  HIPCHK(launch_hsweeps(p, Ne, f.Sinv, f.W, f.V, R, m, G, ctx->stream));
+  HIPCHK(launch_haccumulate(G, Ne, N * m, coef_dev, coef_dev + kMaxNe, Q, ctx->stream));
+  return 0;
+}
+
+// c_e = -(w_e / 4) r e^{i theta_e} = kappa_e / 2 (eq. 12), on the device.
+int hcoefficients(feast_ctx *ctx, const Shifts &s, int Ne, double **coef) {
+  HIPCHK(ensure_t(ctx, S_HCOEF, 2 * kMaxNe, coef));
+  double h[2 * kMaxNe];
+  for (int e = 0; e < Ne; ++e) {
+    h[e] = 0.5 * s.kre[e];
+    h[kMaxNe + e] = 0.5 * s.kim[e];
+  }
+  HIPCHK(hipMemcpyAsync(*coef, h, sizeof(h), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return 0;
+}
+
+}  // namespace
+
+int feast_shifted_solve_hermitian(feast_ctx *ctx, const feast_zbt_matrix *AB, double z_re,
+                                  double z_im, int32_t m, const double *R, int32_t adjoint,
+                                  double *X) {
+  if (!ctx || !R || !X) return -5;
+  int st = validate_hmatrix(AB);
+  if (st) return st;
+  if (m < 1 || m > kMaxHM0) return -3;
+  if (!(z_im > 0.0) || !std::isfinite(z_re) || !std::isfinite(z_im)) return -2;
+  HIPCHK(hipSetDevice(ctx->device));
+  HPencil p = make_hpencil(AB);
+  const size_t N = (size_t)p.nc * p.b;
+  Shifts s;
+  std::memset(&s, 0, sizeof(s));
+  s.zre[0] = z_re;
+  s.zim[0] = z_im;
+  HFactors f;
+  st = prepare_hfactors(ctx, p, 1, f);
+  if (st) return st;
+  double *G;
+  HIPCHK(ensure_t(ctx, S_HG, 2 * N * m * 2, &G));
+  HIPCHK(launch_hfactor(p, s, 1, f.Sinv, f.W, f.V, ctx->stream));
+  HIPCHK(launch_hsweeps(p, 1, f.Sinv, f.W, f.V, R, m, G, ctx->stream));
+  HIPCHK(hipMemcpyAsync(X, G + (adjoint ? 2 * N * m : 0), 2 * N * m * sizeof(double),
+                        hipMemcpyDeviceToDevice, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return 0;
+}
+
+int feast_filter_hermitian(feast_ctx *ctx, const feast_zbt_matrix *AB, double emin, double emax,
+                           int32_t M0, int32_t Ne, const double *Y, double *Q) {
+  if (!ctx || !Y || !Q) return -5;
+  int st = validate_hmatrix(AB);
+  if (st) return st;
+  if (!(emin < emax) || !std::isfinite(emin) || !std::isfinite(emax)) return -2;
+  if (M0 < 1 || M0 > kMaxHM0) return -3;
+  if (Ne < 1 || Ne > kMaxNe) return -4;
+  HIPCHK(hipSetDevice(ctx->device));
+  HPencil p = make_hpencil(AB);
+  const size_t N = (size_t)p.nc * p.b;
+  Shifts s;
+  make_shifts(Ne, emin, emax, s);
+  HFactors f;
+  st = prepare_hfactors(ctx, p, Ne, f);
+  if (st) return st;
+  double *coef, *R;
+  st = hcoefficients(ctx, s, Ne, &coef);
+  if (st) return st;
+  HIPCHK(ensure_t(ctx, S_HR, N * M0 * 2, &R));
+  HIPCHK(launch_hfactor(p, s, Ne, f.Sinv, f.W, f.V, ctx->stream));
+  HIPCHK(launch_happly(p, 1, Y, M0, R, ctx->stream));  // R = B Y
+  st = hfilter(ctx, p, Ne, f, R, M0, coef, Q);
+  if (st) return st;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return 0;
+}
+
+int feast_solve_hermitian(feast_ctx *ctx, const feast_zbt_matrix *AB, double emin, double emax,
+                          int32_t M0, int32_t Ne, const feast_opts *opts, double *lambda,
+                          double *X, double *res, feast_info *info) {
+  if (!ctx || !lambda || !X || !res) return -5;
+  int st = validate_hmatrix(AB);
+  if (st) return st;
+  if (!(emin < emax) || !std::isfinite(emin) || !std::isfinite(emax)) return -2;
+  const long long N = (long long)AB->nc * AB->b;
+  if (M0 < 1 || M0 > kMaxHM0 || M0 > N) return -3;
+  if (Ne < 1 || Ne > kMaxNe) return -4;
+  feast_opts o;
+  feast_default_opts(&o);
+  if (opts) o = *opts;
+  if (!(o.tol > 0.0) || o.max_loops < 1 || o.precision != 0) return -7;
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t sm = ctx->stream;
+  st = check_hinputs(ctx, AB, o.Y0, (size_t)N * M0 * 2);
+  if (st) return st;
+  HPencil p = make_hpencil(AB);
+  Shifts s;
+  make_shifts(Ne, emin, emax, s);
+  const double r = 0.5 * (emax - emin);
+  HFactors f;
+  st = prepare_hfactors(ctx, p, Ne, f);
+  if (st) return st;
+  double *coef;
+  st = hcoefficients(ctx, s, Ne, &coef);
+  if (st) return st;
+  const size_t nm2 = (size_t)N * M0 * 2;
+  const int n2 = 2 * M0;
+  double *y, *rr, *q, *x, *ax, *bx, *part, *aq, *bq, *ea, *eb, *eps2, *phi2, *eps, *phi, *resi,
+      *scr;
+  int *flag, *perm;
+  HIPCHK(ensure_t(ctx, S_HY, nm2, &y));
+  HIPCHK(ensure_t(ctx, S_HR, nm2, &rr));
+  HIPCHK(ensure_t(ctx, S_HQ, nm2, &q));
+  HIPCHK(ensure_t(ctx, S_HX, nm2, &x));
+  HIPCHK(ensure_t(ctx, S_HAX, nm2, &ax));
+  HIPCHK(ensure_t(ctx, S_HBX, nm2, &bx));
+  HIPCHK(ensure_t(ctx, S_HPART, hgram_partial_doubles(N, M0), &part));
+  HIPCHK(ensure_t(ctx, S_HAQ, (size_t)M0 * M0 * 2, &aq));
+  HIPCHK(ensure_t(ctx, S_HBQ, (size_t)M0 * M0 * 2, &bq));
+  HIPCHK(ensure_t(ctx, S_HEA, (size_t)n2 * n2, &ea));
+  HIPCHK(ensure_t(ctx, S_HEB, (size_t)n2 * n2, &eb));
+  HIPCHK(ensure_t(ctx, S_HEPS2, (size_t)n2, &eps2));
+  HIPCHK(ensure_t(ctx, S_HPHI2, (size_t)n2 * n2, &phi2));
+  HIPCHK(ensure_t(ctx, S_HEPS, (size_t)M0, &eps));
+  HIPCHK(ensure_t(ctx, S_HPHI, (size_t)M0 * M0 * 2, &phi));
+  HIPCHK(ensure_t(ctx, S_HRES, (size_t)M0, &resi));
+  HIPCHK(ensure_t(ctx, S_RRS, reduced_eig_scratch_doubles(), &scr));
+  HIPCHK(ensure_t(ctx, S_FLAG, 4, &flag));
+  HIPCHK(ensure_t(ctx, S_PERM, (size_t)M0, &perm));
+
+  HIPCHK(launch_hfactor(p, s, Ne, f.Sinv, f.W, f.V, sm));  // once (Sec. V, parallelism (ii))
+  if (o.Y0) {
+    HIPCHK(hipMemcpyAsync(y, o.Y0, nm2 * sizeof(double), hipMemcpyDeviceToDevice, sm));
+  } else {  // real and imaginary parts N(0, 1): the real draw of N x 2 M0
+    HIPCHK(launch_random_start(o.seed, 1, (int)N, (int)N, n2, n2, y, sm));
+  }
+  std::vector<double> traces;
+  std::vector<int> counts;
+  double trace_rel = INFINITY;
+  bool converged = false;
+  int fallback = 0, rr_sweeps = 0;
+  double *h_eps = ctx->h_eps;
+  double *h_res = ctx->h_eps + kMaxM0;
+  const double res_gate = std::sqrt(o.tol);
+  double prev_left_min = INFINITY;
+  std::vector<char> is_counted(M0, 0);
+  for (int k = 1; k <= o.max_loops; ++k) {
+    HIPCHK(launch_happly(p, 1, y, M0, rr, sm));                       // R = B Y
+    st = hfilter(ctx, p, Ne, f, rr, M0, coef, q);                      // Q (eq. 12)
+    if (st) return st;
+    HIPCHK(launch_happly(p, 0, q, M0, ax, sm));
+    HIPCHK(launch_happly(p, 1, q, M0, bx, sm));
+    HIPCHK(launch_hgram(q, ax, N, M0, part, aq, sm));                  // A_Q = Q^H A Q
+    HIPCHK(launch_hgram(q, bx, N, M0, part, bq, sm));                  // B_Q = Q^H B Q
+    HIPCHK(launch_hembed(aq, bq, M0, ea, eb, sm));
+    HIPCHK(launch_reduced_eig(ea, eb, n2, eps2, phi2, scr, flag, sm));  // real embedding
+    HIPCHK(launch_hextract(eps2, phi2, M0, eps, phi, sm));
+    HIPCHK(launch_htall_gemm(q, phi, N, M0, M0, x, sm));              // X = Q Phi
+    HIPCHK(launch_happly(p, 0, x, M0, ax, sm));
+    HIPCHK(launch_happly(p, 1, x, M0, bx, sm));
+    HIPCHK(launch_hresiduals(ax, bx, eps, N, M0, emin, emax, resi, sm));
+    HIPCHK(hipMemcpyAsync(h_eps, eps, M0 * sizeof(double), hipMemcpyDeviceToHost, sm));
+    HIPCHK(hipMemcpyAsync(h_res, resi, M0 * sizeof(double), hipMemcpyDeviceToHost, sm));
+    HIPCHK(hipMemcpyAsync(ctx->h_flag, flag, 3 * sizeof(int), hipMemcpyDeviceToHost, sm));
+    HIPCHK(hipStreamSynchronize(sm));
+    fallback = ctx->h_flag[0];
+    rr_sweeps += ctx->h_flag[1] + (fallback ? ctx->h_flag[2] : 0);
+    int Mk = 0;
+    double Tk = 0.0, left_min = INFINITY;
+    for (int j = 0; j < M0; ++j) {
+      const bool in = h_eps[j] >= emin && h_eps[j] <= emax;
+      is_counted[j] = in && h_res[j] <= res_gate;
+      if (is_counted[j]) {
+        ++Mk;
+        Tk += h_eps[j];
+      } else if (in) {
+        left_min = std::min(left_min, h_res[j]);
+      }
+    }
+    const bool still_converging = left_min < kUncountedDrop * prev_left_min;
+    prev_left_min = left_min;
+    if (k >= 2) {
+      if (Mk == 0 && counts.back() == 0)
+        trace_rel = 0.0;
+      else
+        trace_rel = std::fabs(Tk - traces.back()) / std::max(std::fabs(Tk), Mk * r);
+    }
+    traces.push_back(Tk);
+    counts.push_back(Mk);
+    if (o.verbose)
+      std::fprintf(stderr, "feast (Hermitian): loop %d  M %d  trace %.17g  trace change %.3e\n", k,
+                   Mk, Tk, k >= 2 ? trace_rel : INFINITY);
+    if (k >= 2 && Mk == counts[counts.size() - 2] && trace_rel < o.tol && !still_converging) {
+      converged = true;
+      break;
+    }
+    if (k < o.max_loops) std::swap(y, x);  // Y <- X
+  }
+  std::vector<int> order;
+  order.reserve(M0);
+  for (int j = 0; j < M0; ++j)
+    if (is_counted[j]) order.push_back(j);
+  for (int j = 0; j < M0; ++j)
+    if (std::isfinite(h_eps[j]) && !is_counted[j]) order.push_back(j);
+  for (int j = 0; j < M0; ++j)
+    if (!std::isfinite(h_eps[j])) order.push_back(j);
+  int *h_perm = reinterpret_cast<int *>(ctx->h_eps + 2 * kMaxM0);
+  for (int j = 0; j < M0; ++j) h_perm[j] = order[j];
+  std::vector<double> res_sorted(M0);
+  for (int j = 0; j < M0; ++j) res_sorted[j] = h_res[order[j]];
+  HIPCHK(hipMemcpyAsync(perm, h_perm, M0 * sizeof(int), hipMemcpyHostToDevice, sm));
+  HIPCHK(launch_hgather(x, perm, N, M0, X, sm));
+  HIPCHK(launch_gather(eps, perm, M0, lambda, sm));
+  HIPCHK(launch_gather(resi, perm, M0, res, sm));
+  HIPCHK(hipStreamSynchronize(sm));
+  const int M = counts.back();
+  double max_res = 0.0;
+  for (int j = 0; j < M; ++j) max_res = std::max(max_res, res_sorted[j]);
+  int status;
+  if (!converged) status = 1;
+  else if (fallback) status = 2;
+  else if (M == M0) status = 4;
+  else if (M == 0) status = 3;
+  else status = 0;
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->loops = (int)traces.size();
+    info->M = M;
+    info->trace = traces.back();
+    info->trace_rel = trace_rel;
+    info->max_res = max_res;
+    info->status = status;
+    info->fallback = fallback;
+    info->rr_sweeps = rr_sweeps;
+    for (size_t k = 0; k < traces.size() && k < 64; ++k) {
+      info->trace_hist[k] = traces[k];
+      info->count_hist[k] = counts[k];
+    }
+  }
+  return status;
+}

@@ -177,4 +177,40 @@ hipError_t launch_basis_expand(const double *U, const float *C, int nc, int b, i
                                double scale, const double *R, double rscale, double *Y,
                                hipStream_t st);
 
+// Hermitian variant (herm.hip).  Complex values are interleaved (re, im).
+struct HPencil {
+  const double *Ad, *Au;   // complex [nc][b][b], [nc-1][b][b] (A Hermitian)
+  const double *Bd, *Bu;   // real, B s.p.d.
+  int nc, b;
+};
+size_t hfactor_lds_bytes(int b);
+// Block LU of Z_e B - A for every node: Sinv [Ne][nc][b][b], W and V
+// [Ne][max(nc-1,1)][b][b] (complex).
+hipError_t launch_hfactor(const HPencil &p, const Shifts &s, int Ne, double *Sinv, double *W,
+                          double *V, hipStream_t st);
+// Both solves of every node for the complex right-hand side R [N][m]:
+// G [Ne][2][N][m] = (M_e^{-1} R, M_e^{-H} R).
+hipError_t launch_hsweeps(const HPencil &p, int Ne, const double *Sinv, const double *W,
+                          const double *V, const double *R, int m, double *G, hipStream_t st);
+// Q = sum_e c_e x_e + conj(c_e) y_e over G (Nm = N*m complex entries per slot).
+hipError_t launch_haccumulate(const double *G, int Ne, size_t Nm, const double *cre,
+                              const double *cim, double *Q, hipStream_t st);
+// out = A V (which 0) or B V (which 1), complex V and out [N][m].
+hipError_t launch_happly(const HPencil &p, int which, const double *Vin, int m, double *out,
+                         hipStream_t st);
+size_t hgram_partial_doubles(long long N, int m);
+// G = Hermitian part of X^H V (complex [m][m], m <= 64).
+hipError_t launch_hgram(const double *X, const double *Vin, long long N, int m, double *partial,
+                        double *G, hipStream_t st);
+hipError_t launch_hembed(const double *AQ, const double *BQ, int m, double *EA, double *EB,
+                         hipStream_t st);
+hipError_t launch_hextract(const double *eps2, const double *Phi2, int m, double *eps,
+                           double *Phi, hipStream_t st);
+hipError_t launch_htall_gemm(const double *X, const double *G, long long N, int m, int m2,
+                             double *T, hipStream_t st);
+hipError_t launch_hresiduals(const double *AX, const double *BX, const double *lam, long long N,
+                             int m, double emin, double emax, double *res, hipStream_t st);
+hipError_t launch_hgather(const double *in, const int *perm, long long N, int m, double *out,
+                          hipStream_t st);
+
 }  // namespace feast

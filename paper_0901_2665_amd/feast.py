@@ -32,6 +32,12 @@ class BTMatrix(ctypes.Structure):
                 ("B_diag", ctypes.c_void_p), ("B_up", ctypes.c_void_p)]
 
 
+class ZBTMatrix(ctypes.Structure):
+    _fields_ = [("nc", ctypes.c_int32), ("b", ctypes.c_int32),
+                ("A_diag", ctypes.c_void_p), ("A_up", ctypes.c_void_p),
+                ("B_diag", ctypes.c_void_p), ("B_up", ctypes.c_void_p)]
+
+
 class Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_loops", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("partitions", ctypes.c_int32),
@@ -65,7 +71,8 @@ EXPORTED = ["feast_default_opts", "feast_init", "feast_destroy", "feast_strerror
             "feast_mlp_params", "feast_mlp_forward", "feast_mlp_gradients",
             "feast_mlp_train_step", "feast_cross_gram", "feast_cross_gram_workspace",
             "feast_tall_gemm", "feast_cell_gram_accumulate", "feast_basis_project",
-            "feast_basis_expand"]
+            "feast_basis_expand", "feast_solve_hermitian", "feast_shifted_solve_hermitian",
+            "feast_filter_hermitian"]
 
 
 def load_library(path: str = LIB_PATH):
@@ -100,6 +107,11 @@ def load_library(path: str = LIB_PATH):
     lib.feast_autotune_partitions.argtypes = [P, ctypes.POINTER(BTMatrix), D, D, I32, I32,
                                               ctypes.c_char_p, ctypes.POINTER(I32)]
     lib.feast_reduced_eig_noalloc.argtypes = [P, I32, P, P, P, P, ctypes.POINTER(I32)]
+    lib.feast_solve_hermitian.argtypes = [P, ctypes.POINTER(ZBTMatrix), D, D, I32, I32,
+                                          ctypes.POINTER(Opts), P, P, P, ctypes.POINTER(Info)]
+    lib.feast_shifted_solve_hermitian.argtypes = [P, ctypes.POINTER(ZBTMatrix), D, D, I32, P,
+                                                  I32, P]
+    lib.feast_filter_hermitian.argtypes = [P, ctypes.POINTER(ZBTMatrix), D, D, I32, I32, P, P]
     F32P = ctypes.c_void_p
     lib.feast_mlp_create.argtypes = [P, ctypes.POINTER(I32), I32, P, ctypes.POINTER(P)]
     lib.feast_mlp_destroy.argtypes = [P]
@@ -258,6 +270,34 @@ class Pencil:
         up_a = self.Au.data_ptr() if self.Au.numel() else None
         up_b = self.Bu.data_ptr() if self.Bu.numel() else None
         return BTMatrix(self.nc, self.b, self.Ad.data_ptr(), up_a, self.Bd.data_ptr(), up_b)
+
+
+def _zptr(t):
+    import torch
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()):
+        raise ValueError("expected a contiguous complex128 device tensor")
+    return t.data_ptr()
+
+
+class HermitianPencil:
+    """Device copy of a Hermitian pencil: A complex (complex128), B real."""
+
+    def __init__(self, Ad, Au, Bd, Bu, device="cuda"):
+        import torch
+        c = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.complex128,
+                                      device=device).contiguous()
+        f = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64,
+                                      device=device).contiguous()
+        self.Ad, self.Au, self.Bd, self.Bu = c(Ad), c(Au), f(Bd), f(Bu)
+        self.nc, self.b = int(self.Ad.shape[0]), int(self.Ad.shape[1])
+        self.n = self.nc * self.b
+
+    def struct(self) -> ZBTMatrix:
+        up_a = self.Au.data_ptr() if self.Au.numel() else None
+        up_b = self.Bu.data_ptr() if self.Bu.numel() else None
+        return ZBTMatrix(self.nc, self.b, self.Ad.data_ptr(), up_a, self.Bd.data_ptr(), up_b)
 
 
 class Context:
@@ -445,6 +485,47 @@ class Context:
                                          _ptr(R) if R is not None else None, rscale, _ptr(out))
         self._check(st, "feast_basis_expand")
         return out
+
+    # ---- Hermitian A (eq. 12) ----
+
+    def solve_hermitian(self, p: "HermitianPencil", emin: float, emax: float, M0: int, Ne: int,
+                        Y0=None, tol: float = 1e-12, max_loops: int = 20, seed: int = 0,
+                        verbose: int = 0) -> SolveResult:
+        import torch
+        dev = p.Ad.device
+        lam = torch.empty(M0, dtype=torch.float64, device=dev)
+        X = torch.empty((p.n, M0), dtype=torch.complex128, device=dev)
+        res = torch.empty(M0, dtype=torch.float64, device=dev)
+        opts = Opts(tol=tol, max_loops=max_loops, precision=0, partitions=0, graph=0,
+                    Y0=_zptr(Y0) if Y0 is not None else None, seed=seed, verbose=verbose)
+        info = Info()
+        ab = p.struct()
+        st = self.lib.feast_solve_hermitian(self.handle, ctypes.byref(ab), emin, emax, M0, Ne,
+                                            ctypes.byref(opts), _ptr(lam), _zptr(X), _ptr(res),
+                                            ctypes.byref(info))
+        self._check(st, "feast_solve_hermitian", warn_ok=True)
+        n = min(info.loops, 64)
+        return SolveResult(lam, X, res, info.M, info.loops, info.trace, info.trace_rel,
+                           info.max_res, st, info.fallback, list(info.trace_hist[:n]),
+                           list(info.count_hist[:n]), info.rr_sweeps, 0, 0.0)
+
+    def shifted_solve_hermitian(self, p: "HermitianPencil", z: complex, R, adjoint: bool = False):
+        import torch
+        X = torch.empty_like(R)
+        ab = p.struct()
+        st = self.lib.feast_shifted_solve_hermitian(self.handle, ctypes.byref(ab), z.real, z.imag,
+                                                    R.shape[1], _zptr(R), int(adjoint), _zptr(X))
+        self._check(st, "feast_shifted_solve_hermitian")
+        return X
+
+    def filter_hermitian(self, p: "HermitianPencil", emin: float, emax: float, Ne: int, Y):
+        import torch
+        Q = torch.empty_like(Y)
+        ab = p.struct()
+        st = self.lib.feast_filter_hermitian(self.handle, ctypes.byref(ab), emin, emax,
+                                             Y.shape[1], Ne, _zptr(Y), _zptr(Q))
+        self._check(st, "feast_filter_hermitian")
+        return Q
 
     def random_start(self, seed: int, N: int, M0: int):
         """The start block feast_solve draws when Y0 is None (device tensor)."""

@@ -86,7 +86,7 @@ def test_strerror_covers_codes(lib):
 
 
 STRUCTS = [("feast_bt_matrix", F.BTMatrix), ("feast_opts", F.Opts), ("feast_info", F.Info),
-           ("feast_problem", F.Problem)]
+           ("feast_problem", F.Problem), ("feast_zbt_matrix", F.ZBTMatrix)]
 C_NAME = {"lam": "lambda"}  # C field names that are Python keywords
 
 

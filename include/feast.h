@@ -39,7 +39,8 @@
  *
  * Status codes (int):
  *    0  success
- *   -1  nc < 1 or b < 1 (or b above the supported maximum, 64)
+ *   -1  nc < 1 or b < 1, or b above the supported maximum (96 for feast_solve,
+ *       feast_solve_batched and feast_solve_hermitian, 64 for the other calls)
  *   -2  emin >= emax or a bound is not finite
  *   -3  M0 < 1 or M0 > N, or M0 above the supported maximum, 128
  *   -4  Ne < 1 or Ne > 64
@@ -74,7 +75,12 @@ typedef struct feast_ctx feast_ctx;
 /* Block-tridiagonal pencil (A, B); all four pointers (dev), float64. */
 typedef struct {
   int32_t nc;            /* number of cells, >= 1 */
-  int32_t b;             /* block size, 1..64 */
+  int32_t b;             /* block size, 1..64; feast_solve and
+                            feast_solve_batched also take 65..96: such
+                            pencils run on the generic kernels of the
+                            Hermitian variant (A widened to complex, real
+                            mode: Q, the reduced problem and X real), with
+                            M0 <= 64, precision 0 and no partitions */
   const double *A_diag;  /* [nc][b][b] */
   const double *A_up;    /* [nc-1][b][b] (may be NULL when nc == 1) */
   const double *B_diag;  /* [nc][b][b] */
@@ -363,12 +369,12 @@ int feast_timing_read(feast_ctx *ctx, int32_t kind, const char **name, double *t
  * pairs.  Complex arrays are interleaved (re, im) doubles (C99 double
  * complex, torch.complex128).  Counting, convergence, residual and output
  * order as in feast_solve (residual 1-norms of complex moduli).
- * Limits: b <= 64, M0 <= 64.  The factorisation runs one workgroup per
+ * Limits: b <= 96, M0 <= 64.  The factorisation runs one workgroup per
  * contour point over all cells in order (no partitions).
  */
 typedef struct {
   int32_t nc;            /* number of cells, >= 1 */
-  int32_t b;             /* block size, 1..64 */
+  int32_t b;             /* block size, 1..96 */
   const double *A_diag;  /* (dev) complex [nc][b][b], Hermitian blocks */
   const double *A_up;    /* (dev) complex [nc-1][b][b]; block (i+1, i) is the
                             conjugate transpose of block (i, i+1) */
@@ -380,7 +386,7 @@ typedef struct {
  * [N][M0], B-orthonormal (X^H B X = I); res (dev) [M0].  opts as feast_solve
  * (precision 0 only; Y0 complex [N][M0] or NULL: then the real and imaginary
  * parts are the seeded standard normal draws of an N x 2 M0 real block,
- * interleaved).  Errors as feast_solve; b > 64 gives -1, M0 > 64 gives -3. */
+ * interleaved).  Errors as feast_solve; b > 96 gives -1, M0 > 64 gives -3. */
 int feast_solve_hermitian(feast_ctx *ctx, const feast_zbt_matrix *AB, double emin, double emax,
                           int32_t M0, int32_t Ne, const feast_opts *opts, double *lambda,
                           double *X, double *res, feast_info *info);

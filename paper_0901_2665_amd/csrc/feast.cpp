@@ -29,7 +29,7 @@ constexpr int kMaxM0 = 128;
 constexpr double kUncountedDrop = 0.5;
 // Hermitian variant: block size and subspace limits (the reduced problem is
 // solved through its real embedding of size 2 M0 <= 128)
-constexpr int kMaxHB = 64;
+constexpr int kMaxHB = 96;
 constexpr int kMaxHM0 = 64;
 
 struct Buf {
@@ -43,7 +43,7 @@ enum Slot {
   S_SINV32, S_W32, S_WT32, S_G32, S_TV32, S_XC, S_RC, S_RPART, S_WORST,
   // Hermitian variant
   S_HSINV, S_HW, S_HV, S_HG, S_HY, S_HR, S_HQ, S_HX, S_HAX, S_HBX, S_HPART, S_HAQ, S_HBQ,
-  S_HEA, S_HEB, S_HEPS2, S_HPHI2, S_HEPS, S_HPHI, S_HRES, S_HCOEF, S_COUNT
+  S_HEA, S_HEB, S_HEPS2, S_HPHI2, S_HEPS, S_HPHI, S_HRES, S_HCOEF, S_HAD, S_HAU, S_COUNT
 };
 
 }  // namespace
@@ -715,10 +715,31 @@ int feast_reduced_eig_noalloc(feast_ctx *ctx, int32_t M0, const double *AQ, cons
   return 0;
 }
 
+namespace {
+int solve_generic_real(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double emax,
+                       int32_t M0, int32_t Ne, const feast_opts &o, double *lambda, double *X,
+                       double *res, feast_info *info);
+}
+
 int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double emax, int32_t M0,
                 int32_t Ne, const feast_opts *opts, double *lambda, double *X, double *res,
                 feast_info *info) {
   if (!ctx || !lambda || !X || !res) return -5;
+  if (AB && AB->b > kMaxB && AB->b <= kMaxHB) {  // blocks above 64: the generic kernels
+    if (AB->nc < 1) return -1;
+    if (!AB->A_diag || !AB->B_diag || (AB->nc > 1 && (!AB->A_up || !AB->B_up))) return -5;
+    if (!(emin < emax) || !std::isfinite(emin) || !std::isfinite(emax)) return -2;
+    const long long Ng = (long long)AB->nc * AB->b;
+    if (M0 < 1 || M0 > kMaxHM0 || M0 > Ng) return -3;
+    if (Ne < 1 || Ne > kMaxNe) return -4;
+    feast_opts og;
+    feast_default_opts(&og);
+    if (opts) og = *opts;
+    if (!(og.tol > 0.0) || og.max_loops < 1 || og.precision != 0 || og.partitions < 0 ||
+        og.graph < 0 || og.graph > 1)
+      return -7;
+    return solve_generic_real(ctx, AB, emin, emax, M0, Ne, og, lambda, X, res, info);
+  }
   int st = validate_matrix(AB);
   if (st) return st;
   if (!(emin < emax) || !std::isfinite(emin) || !std::isfinite(emax)) return -2;
@@ -1277,25 +1298,20 @@ int feast_filter_hermitian(feast_ctx *ctx, const feast_zbt_matrix *AB, double em
   return 0;
 }
 
-int feast_solve_hermitian(feast_ctx *ctx, const feast_zbt_matrix *AB, double emin, double emax,
-                          int32_t M0, int32_t Ne, const feast_opts *opts, double *lambda,
-                          double *X, double *res, feast_info *info) {
-  if (!ctx || !lambda || !X || !res) return -5;
-  int st = validate_hmatrix(AB);
-  if (st) return st;
-  if (!(emin < emax) || !std::isfinite(emin) || !std::isfinite(emax)) return -2;
-  const long long N = (long long)AB->nc * AB->b;
-  if (M0 < 1 || M0 > kMaxHM0 || M0 > N) return -3;
-  if (Ne < 1 || Ne > kMaxNe) return -4;
-  feast_opts o;
-  feast_default_opts(&o);
-  if (opts) o = *opts;
-  if (!(o.tol > 0.0) || o.max_loops < 1 || o.precision != 0) return -7;
-  HIPCHK(hipSetDevice(ctx->device));
+namespace {
+
+// FEAST loop on the generic complex kernels of herm.hip: A Hermitian, or
+// (real_mode) a real symmetric A given as complex blocks.  In real mode the
+// start block, Q (eq. 12 with real Y equals eq. 15, real up to rounding),
+// the reduced problem (real parts, real eigensolver, no embedding) and X are
+// real; X_out is then real [N][M0], else complex.  y0: caller's start block
+// (complex, or real in real mode) or NULL for the seeded random start.
+int generic_solve(feast_ctx *ctx, const HPencil &p, double emin, double emax, int M0, int Ne,
+                  const feast_opts &o, bool real_mode, const double *y0, double *lambda,
+                  double *X_out, double *res, feast_info *info) {
   hipStream_t sm = ctx->stream;
-  st = check_hinputs(ctx, AB, o.Y0, (size_t)N * M0 * 2);
-  if (st) return st;
-  HPencil p = make_hpencil(AB);
+  int st = 0;
+  const long long N = (long long)p.nc * p.b;
   Shifts s;
   make_shifts(Ne, emin, emax, s);
   const double r = 0.5 * (emax - emin);
@@ -1306,7 +1322,7 @@ int feast_solve_hermitian(feast_ctx *ctx, const feast_zbt_matrix *AB, double emi
   st = hcoefficients(ctx, s, Ne, &coef);
   if (st) return st;
   const size_t nm2 = (size_t)N * M0 * 2;
-  const int n2 = 2 * M0;
+  const int n2 = real_mode ? M0 : 2 * M0;  // size of the real reduced problem
   double *y, *rr, *q, *x, *ax, *bx, *part, *aq, *bq, *ea, *eb, *eps2, *phi2, *eps, *phi, *resi,
       *scr;
   int *flag, *perm;
@@ -1331,10 +1347,17 @@ int feast_solve_hermitian(feast_ctx *ctx, const feast_zbt_matrix *AB, double emi
   HIPCHK(ensure_t(ctx, S_PERM, (size_t)M0, &perm));
 
   HIPCHK(launch_hfactor(p, s, Ne, f.Sinv, f.W, f.V, sm));  // once (Sec. V, parallelism (ii))
-  if (o.Y0) {
-    HIPCHK(hipMemcpyAsync(y, o.Y0, nm2 * sizeof(double), hipMemcpyDeviceToDevice, sm));
+  if (real_mode) {  // real start block, widened to complex
+    if (y0) {
+      HIPCHK(launch_to_complex(y0, (size_t)N * M0, y, sm));
+    } else {
+      HIPCHK(launch_random_start(o.seed, 1, (int)N, (int)N, M0, M0, x, sm));
+      HIPCHK(launch_to_complex(x, (size_t)N * M0, y, sm));
+    }
+  } else if (y0) {
+    HIPCHK(hipMemcpyAsync(y, y0, nm2 * sizeof(double), hipMemcpyDeviceToDevice, sm));
   } else {  // real and imaginary parts N(0, 1): the real draw of N x 2 M0
-    HIPCHK(launch_random_start(o.seed, 1, (int)N, (int)N, n2, n2, y, sm));
+    HIPCHK(launch_random_start(o.seed, 1, (int)N, (int)N, 2 * M0, 2 * M0, y, sm));
   }
   std::vector<double> traces;
   std::vector<int> counts;
@@ -1354,9 +1377,16 @@ int feast_solve_hermitian(feast_ctx *ctx, const feast_zbt_matrix *AB, double emi
     HIPCHK(launch_happly(p, 1, q, M0, bx, sm));
     HIPCHK(launch_hgram(q, ax, N, M0, part, aq, sm));                  // A_Q = Q^H A Q
     HIPCHK(launch_hgram(q, bx, N, M0, part, bq, sm));                  // B_Q = Q^H B Q
-    HIPCHK(launch_hembed(aq, bq, M0, ea, eb, sm));
-    HIPCHK(launch_reduced_eig(ea, eb, n2, eps2, phi2, scr, flag, sm));  // real embedding
-    HIPCHK(launch_hextract(eps2, phi2, M0, eps, phi, sm));
+    if (real_mode) {  // real parts, real eigensolver; Phi widened to complex
+      HIPCHK(launch_real_part(aq, (size_t)M0 * M0, ea, sm));
+      HIPCHK(launch_real_part(bq, (size_t)M0 * M0, eb, sm));
+      HIPCHK(launch_reduced_eig(ea, eb, M0, eps, phi2, scr, flag, sm));
+      HIPCHK(launch_to_complex(phi2, (size_t)M0 * M0, phi, sm));
+    } else {  // real embedding of the Hermitian pencil
+      HIPCHK(launch_hembed(aq, bq, M0, ea, eb, sm));
+      HIPCHK(launch_reduced_eig(ea, eb, n2, eps2, phi2, scr, flag, sm));
+      HIPCHK(launch_hextract(eps2, phi2, M0, eps, phi, sm));
+    }
     HIPCHK(launch_htall_gemm(q, phi, N, M0, M0, x, sm));              // X = Q Phi
     HIPCHK(launch_happly(p, 0, x, M0, ax, sm));
     HIPCHK(launch_happly(p, 1, x, M0, bx, sm));
@@ -1390,8 +1420,8 @@ int feast_solve_hermitian(feast_ctx *ctx, const feast_zbt_matrix *AB, double emi
     traces.push_back(Tk);
     counts.push_back(Mk);
     if (o.verbose)
-      std::fprintf(stderr, "feast (Hermitian): loop %d  M %d  trace %.17g  trace change %.3e\n", k,
-                   Mk, Tk, k >= 2 ? trace_rel : INFINITY);
+      std::fprintf(stderr, "feast (%s): loop %d  M %d  trace %.17g  trace change %.3e\n",
+                   real_mode ? "generic" : "Hermitian", k, Mk, Tk, k >= 2 ? trace_rel : INFINITY);
     if (k >= 2 && Mk == counts[counts.size() - 2] && trace_rel < o.tol && !still_converging) {
       converged = true;
       break;
@@ -1411,7 +1441,12 @@ int feast_solve_hermitian(feast_ctx *ctx, const feast_zbt_matrix *AB, double emi
   std::vector<double> res_sorted(M0);
   for (int j = 0; j < M0; ++j) res_sorted[j] = h_res[order[j]];
   HIPCHK(hipMemcpyAsync(perm, h_perm, M0 * sizeof(int), hipMemcpyHostToDevice, sm));
-  HIPCHK(launch_hgather(x, perm, N, M0, X, sm));
+  if (real_mode) {  // Ritz vectors of a real pencil from a real Q: the real part
+    HIPCHK(launch_hgather(x, perm, N, M0, ax, sm));
+    HIPCHK(launch_real_part(ax, (size_t)N * M0, X_out, sm));
+  } else {
+    HIPCHK(launch_hgather(x, perm, N, M0, X_out, sm));
+  }
   HIPCHK(launch_gather(eps, perm, M0, lambda, sm));
   HIPCHK(launch_gather(resi, perm, M0, res, sm));
   HIPCHK(hipStreamSynchronize(sm));
@@ -1441,3 +1476,58 @@ int feast_solve_hermitian(feast_ctx *ctx, const feast_zbt_matrix *AB, double emi
   }
   return status;
 }
+
+}  // namespace
+
+int feast_solve_hermitian(feast_ctx *ctx, const feast_zbt_matrix *AB, double emin, double emax,
+                          int32_t M0, int32_t Ne, const feast_opts *opts, double *lambda,
+                          double *X, double *res, feast_info *info) {
+  if (!ctx || !lambda || !X || !res) return -5;
+  int st = validate_hmatrix(AB);
+  if (st) return st;
+  if (!(emin < emax) || !std::isfinite(emin) || !std::isfinite(emax)) return -2;
+  const long long N = (long long)AB->nc * AB->b;
+  if (M0 < 1 || M0 > kMaxHM0 || M0 > N) return -3;
+  if (Ne < 1 || Ne > kMaxNe) return -4;
+  feast_opts o;
+  feast_default_opts(&o);
+  if (opts) o = *opts;
+  if (!(o.tol > 0.0) || o.max_loops < 1 || o.precision != 0) return -7;
+  HIPCHK(hipSetDevice(ctx->device));
+  st = check_hinputs(ctx, AB, o.Y0, (size_t)N * M0 * 2);
+  if (st) return st;
+  return generic_solve(ctx, make_hpencil(AB), emin, emax, M0, Ne, o, false, o.Y0, lambda, X,
+                       res, info);
+}
+
+namespace {
+
+// Real symmetric pencils with blocks above the optimised kernels' 64: A is
+// widened to complex and the generic kernels run in real mode.
+int solve_generic_real(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double emax,
+                       int32_t M0, int32_t Ne, const feast_opts &o, double *lambda, double *X,
+                       double *res, feast_info *info) {
+  HIPCHK(hipSetDevice(ctx->device));
+  const long long N = (long long)AB->nc * AB->b;
+  int st = check_inputs(ctx, AB, o.Y0, (size_t)N * M0);
+  if (st) return st;
+  const size_t bb = (size_t)AB->b * AB->b;
+  double *ad, *au = nullptr;
+  HIPCHK(ensure_t(ctx, S_HAD, 2 * AB->nc * bb, &ad));
+  HIPCHK(launch_to_complex(AB->A_diag, AB->nc * bb, ad, ctx->stream));
+  if (AB->nc > 1) {
+    HIPCHK(ensure_t(ctx, S_HAU, 2 * (AB->nc - 1) * bb, &au));
+    HIPCHK(launch_to_complex(AB->A_up, (AB->nc - 1) * bb, au, ctx->stream));
+  }
+  HPencil p;
+  p.Ad = ad;
+  p.Au = au;
+  p.Bd = AB->B_diag;
+  p.Bu = AB->B_up;
+  p.nc = AB->nc;
+  p.b = AB->b;
+  return generic_solve(ctx, p, emin, emax, M0, Ne, o, true, o.Y0, lambda, X, res, info);
+}
+
+}  // namespace
+

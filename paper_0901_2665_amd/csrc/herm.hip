@@ -72,20 +72,25 @@ __device__ __forceinline__ cd shifted_lower(const HPencil &p, int cell, int r, i
   return {zr * bv - p.Au[2 * o], zi * bv + p.Au[2 * o + 1]};
 }
 
+constexpr int kMaxOut = 36;  // outputs per thread of a b x b block (b <= 96)
+
 // One workgroup per contour point, sequential over the cells.  Dynamic LDS:
-// two complex b x (b+1) tiles (S, and the coupling / W).
+// the complex b x (b+1) block S (Sinv after the inversion); the products read
+// the couplings from the caller's blocks and W back from global memory (its
+// lines are written once per cell and not read before, so no stale copy can
+// sit in the vector cache).
 __global__ __launch_bounds__(kT) void hfactor_kernel(HPencil p, Shifts sh, double *Sinv,
                                                      double *W, double *V) {
   extern __shared__ double hsm[];
   const int b = p.b, nc = p.nc, ldb = b + 1, e = blockIdx.x, t = threadIdx.x;
   double *S = hsm;                     // [b][ldb] complex
-  double *T = hsm + 2 * (size_t)b * ldb;
   const double zr = sh.zre[e], zi = sh.zim[e];
   const size_t bb = (size_t)b * b;
+  const int nout = b * b;
   double *Se = Sinv + 2 * (size_t)e * nc * bb;
   double *We = W + 2 * (size_t)e * (nc > 1 ? nc - 1 : 1) * bb;
   double *Ve = V + 2 * (size_t)e * (nc > 1 ? nc - 1 : 1) * bb;
-  for (int o = t; o < b * b; o += kT) st(S, (o / b) * ldb + o % b, shifted_diag(p, 0, o / b, o % b, zr, zi));
+  for (int o = t; o < nout; o += kT) st(S, (o / b) * ldb + o % b, shifted_diag(p, 0, o / b, o % b, zr, zi));
   __syncthreads();
   for (int cell = 0; cell < nc; ++cell) {
     // in-place Gauss-Jordan inverse without pivoting
@@ -95,7 +100,7 @@ __global__ __launch_bounds__(kT) void hfactor_kernel(HPencil p, Shifts sh, doubl
       for (int j = t; j < b; j += kT)
         if (j != k) st(S, k * ldb + j, cmul(ld(S, k * ldb + j), piv));
       __syncthreads();
-      for (int o = t; o < b * b; o += kT) {
+      for (int o = t; o < nout; o += kT) {
         const int r = o / b, j = o % b;
         if (r != k && j != k) st(S, r * ldb + j, csub(ld(S, r * ldb + j), cmul(ld(S, r * ldb + k), ld(S, k * ldb + j))));
       }
@@ -110,47 +115,32 @@ __global__ __launch_bounds__(kT) void hfactor_kernel(HPencil p, Shifts sh, doubl
       }
       __syncthreads();
     }
-    for (int o = t; o < b * b; o += kT) st(Se + 2 * (size_t)cell * bb, o, ld(S, (o / b) * ldb + o % b));
+    for (int o = t; o < nout; o += kT) st(Se + 2 * (size_t)cell * bb, o, ld(S, (o / b) * ldb + o % b));
     if (cell == nc - 1) break;
-    // C into T
-    for (int o = t; o < b * b; o += kT) st(T, (o / b) * ldb + o % b, shifted_upper(p, cell, o / b, o % b, zr, zi));
-    __syncthreads();
+    double *Wc = We + 2 * (size_t)cell * bb;
     // W = Sinv C, V = L Sinv (outputs o = t + kT q)
-    cd wv[16];
-    for (int q = 0; q < 16; ++q) {
+    for (int q = 0; q < kMaxOut; ++q) {
       const int o = t + kT * q;
-      if (o >= b * b) break;
+      if (o >= nout) break;
       const int r = o / b, c = o % b;
       cd w = {0.0, 0.0}, v = {0.0, 0.0};
       for (int k = 0; k < b; ++k) {
-        w = cadd(w, cmul(ld(S, r * ldb + k), ld(T, k * ldb + c)));
+        w = cadd(w, cmul(ld(S, r * ldb + k), shifted_upper(p, cell, k, c, zr, zi)));
         v = cadd(v, cmul(shifted_lower(p, cell, r, k, zr, zi), ld(S, k * ldb + c)));
       }
-      wv[q] = w;
-      st(We + 2 * (size_t)cell * bb, o, w);
+      st(Wc, o, w);
       st(Ve + 2 * (size_t)cell * bb, o, v);
     }
-    __syncthreads();
-    for (int q = 0; q < 16; ++q) {
+    __syncthreads();  // W complete (stores done) and Sinv no longer read
+    // S_next = D_{cell+1} - L W straight over Sinv in LDS (this phase reads
+    // only the caller's blocks and W)
+    for (int q = 0; q < kMaxOut; ++q) {
       const int o = t + kT * q;
-      if (o >= b * b) break;
-      st(T, (o / b) * ldb + o % b, wv[q]);
-    }
-    __syncthreads();
-    // S_next = D_{cell+1} - L W
-    for (int q = 0; q < 16; ++q) {
-      const int o = t + kT * q;
-      if (o >= b * b) break;
+      if (o >= nout) break;
       const int r = o / b, c = o % b;
       cd s = shifted_diag(p, cell + 1, r, c, zr, zi);
-      for (int k = 0; k < b; ++k) s = csub(s, cmul(shifted_lower(p, cell, r, k, zr, zi), ld(T, k * ldb + c)));
-      wv[q] = s;
-    }
-    __syncthreads();
-    for (int q = 0; q < 16; ++q) {
-      const int o = t + kT * q;
-      if (o >= b * b) break;
-      st(S, (o / b) * ldb + o % b, wv[q]);
+      for (int k = 0; k < b; ++k) s = csub(s, cmul(shifted_lower(p, cell, r, k, zr, zi), ld(Wc, (size_t)k * b + c)));
+      st(S, r * ldb + c, s);
     }
     __syncthreads();
   }
@@ -158,13 +148,15 @@ __global__ __launch_bounds__(kT) void hfactor_kernel(HPencil p, Shifts sh, doubl
 
 constexpr int kCols = 16;  // right-hand sides per sweep workgroup
 
+constexpr int kTileOut = 6;  // outputs per thread of a b x kCols tile (b <= 96)
+
 // y (b x kCols tile in LDS, complex, leading dim kCols) = op(Mat) * x, with
 // op = identity or conjugate transpose; Mat [b][b] complex in global memory.
-// Every thread keeps its outputs in out[4] (o = t + kT q, q < 4).
+// Every thread keeps its outputs in out[] (o = t + kT q).
 __device__ __forceinline__ void tile_apply(const double *Mat, bool adj, const double *x, int b,
-                                           int ncol, cd (&out)[4]) {
+                                           int ncol, cd (&out)[kTileOut]) {
   const int t = threadIdx.x;
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < kTileOut; ++q) {
     const int o = t + kT * q;
     out[q] = {0.0, 0.0};
     if (o >= b * kCols) continue;
@@ -186,7 +178,7 @@ __device__ __forceinline__ void tile_apply(const double *Mat, bool adj, const do
 __global__ __launch_bounds__(kT) void hsweep_kernel(HPencil p, const double *Sinv, const double *W,
                                                     const double *V, const double *R, int m,
                                                     double *G) {
-  __shared__ double xs[2 * 64 * kCols];
+  __shared__ double xs[2 * 96 * kCols];
   const int e = blockIdx.x, adj = blockIdx.y, c0 = blockIdx.z * kCols;
   const int b = p.b, nc = p.nc, t = threadIdx.x;
   const int ncol = m - c0 < kCols ? m - c0 : kCols;
@@ -198,7 +190,7 @@ __global__ __launch_bounds__(kT) void hsweep_kernel(HPencil p, const double *Sin
   double *Ge = G + 2 * ((size_t)e * 2 + adj) * N * m;
   const double *Fwd = adj ? We : Ve;   // coupling of the forward recursion
   const double *Bwd = adj ? Ve : We;   // coupling of the back recursion
-  cd out[4];
+  cd out[kTileOut];
   // h_0 = R_0
   for (int o = t; o < b * kCols; o += kT) {
     const int r = o / kCols, c = o % kCols;
@@ -207,7 +199,7 @@ __global__ __launch_bounds__(kT) void hsweep_kernel(HPencil p, const double *Sin
   __syncthreads();
   for (int cell = 0; cell < nc; ++cell) {
     tile_apply(Se + 2 * (size_t)cell * bb, adj, xs, b, ncol, out);  // g = Sinv h (or Sinv^H k)
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < kTileOut; ++q) {
       const int o = t + kT * q;
       if (o >= b * kCols) break;
       const int r = o / kCols, c = o % kCols;
@@ -216,7 +208,7 @@ __global__ __launch_bounds__(kT) void hsweep_kernel(HPencil p, const double *Sin
     if (cell == nc - 1) break;
     tile_apply(Fwd + 2 * (size_t)cell * bb, adj, xs, b, ncol, out);  // V h (or W^H k)
     __syncthreads();
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < kTileOut; ++q) {
       const int o = t + kT * q;
       if (o >= b * kCols) break;
       const int r = o / kCols, c = o % kCols;
@@ -235,7 +227,7 @@ __global__ __launch_bounds__(kT) void hsweep_kernel(HPencil p, const double *Sin
   for (int cell = nc - 2; cell >= 0; --cell) {
     tile_apply(Bwd + 2 * (size_t)cell * bb, adj, xs, b, ncol, out);  // W x (or V^H y)
     __syncthreads();
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < kTileOut; ++q) {
       const int o = t + kT * q;
       if (o >= b * kCols) break;
       const int r = o / kCols, c = o % kCols;
@@ -444,6 +436,20 @@ __global__ void hgather_kernel(const double *in, const int *perm, long long N, i
   }
 }
 
+__global__ void to_complex_kernel(const double *src, size_t n, double *dst) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x) {
+    dst[2 * i] = src[i];
+    dst[2 * i + 1] = 0.0;
+  }
+}
+
+__global__ void real_part_kernel(const double *src, size_t n, double *dst) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = src[2 * i];
+}
+
 int grid_of(size_t n) {
   size_t g = (n + 255) / 256;
   return (int)(g < 4096 ? (g > 0 ? g : 1) : 4096);
@@ -451,14 +457,15 @@ int grid_of(size_t n) {
 
 }  // namespace
 
-size_t hfactor_lds_bytes(int b) { return 2 * 2 * (size_t)b * (b + 1) * sizeof(double); }
+size_t hfactor_lds_bytes(int b) { return 2 * (size_t)b * (b + 1) * sizeof(double); }
 
 hipError_t launch_hfactor(const HPencil &p, const Shifts &s, int Ne, double *Sinv, double *W,
                           double *V, hipStream_t st) {
-  if (p.b < 1 || p.b > 64) return hipErrorInvalidValue;
+  if (p.b < 1 || p.b > kMaxHBlock) return hipErrorInvalidValue;
   const size_t lds = hfactor_lds_bytes(p.b);
   hipError_t e = hipFuncSetAttribute((const void *)hfactor_kernel,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)hfactor_lds_bytes(64));
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)hfactor_lds_bytes(kMaxHBlock));
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(hfactor_kernel, dim3(Ne), dim3(kT), lds, st, p, s, Sinv, W, V);
   return hipGetLastError();
@@ -466,7 +473,7 @@ hipError_t launch_hfactor(const HPencil &p, const Shifts &s, int Ne, double *Sin
 
 hipError_t launch_hsweeps(const HPencil &p, int Ne, const double *Sinv, const double *W,
                           const double *V, const double *R, int m, double *G, hipStream_t st) {
-  if (p.b > 64 || m < 1) return hipErrorInvalidValue;
+  if (p.b > kMaxHBlock || m < 1) return hipErrorInvalidValue;
   dim3 grid(Ne, 2, (m + kCols - 1) / kCols);
   hipLaunchKernelGGL(hsweep_kernel, grid, dim3(kT), 0, st, p, Sinv, W, V, R, m, G);
   return hipGetLastError();
@@ -531,6 +538,16 @@ hipError_t launch_hgather(const double *in, const int *perm, long long N, int m,
                           hipStream_t st) {
   hipLaunchKernelGGL(hgather_kernel, dim3(grid_of((size_t)N * m)), dim3(256), 0, st, in, perm, N,
                      m, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_complex(const double *src, size_t n, double *dst, hipStream_t st) {
+  hipLaunchKernelGGL(to_complex_kernel, dim3(grid_of(n)), dim3(256), 0, st, src, n, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_real_part(const double *src, size_t n, double *dst, hipStream_t st) {
+  hipLaunchKernelGGL(real_part_kernel, dim3(grid_of(n)), dim3(256), 0, st, src, n, dst);
   return hipGetLastError();
 }
 

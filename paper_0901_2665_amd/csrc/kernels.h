@@ -178,6 +178,9 @@ hipError_t launch_basis_expand(const double *U, const float *C, int nc, int b, i
                                hipStream_t st);
 
 // Hermitian variant (herm.hip).  Complex values are interleaved (re, im).
+// Blocks up to kMaxHBlock (the factor kernel holds one complex b x (b+1)
+// block in LDS: 149 KB at b = 96).
+constexpr int kMaxHBlock = 96;
 struct HPencil {
   const double *Ad, *Au;   // complex [nc][b][b], [nc-1][b][b] (A Hermitian)
   const double *Bd, *Bu;   // real, B s.p.d.
@@ -212,5 +215,8 @@ hipError_t launch_hresiduals(const double *AX, const double *BX, const double *l
                              int m, double emin, double emax, double *res, hipStream_t st);
 hipError_t launch_hgather(const double *in, const int *perm, long long N, int m, double *out,
                           hipStream_t st);
+// dst (complex, n entries) = src (real, n entries) + 0 i; dst (real) = Re src.
+hipError_t launch_to_complex(const double *src, size_t n, double *dst, hipStream_t st);
+hipError_t launch_real_part(const double *src, size_t n, double *dst, hipStream_t st);
 
 }  // namespace feast

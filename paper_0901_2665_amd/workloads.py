@@ -256,6 +256,43 @@ def batch_shape(p: int) -> dict:
                 n_eig=int(round(0.6 * m0)), k0=n // 4)
 
 
+# The batched configuration at its full shape: 256 problems, problem p draws
+# from default_rng(BATCH_SEED + p) nc ~ U{50..500}, b from {32, 64, 96},
+# M0 ~ U{16..64}; the chain recipe with matrix seed BATCH_SEED + p, Ne = 16,
+# an interval of round(0.6 M0) eigenvalues from index n // 4
+# (tests/golden/intervals_batch256.json).
+BATCH256_COUNT = 256
+
+
+def batch256_shape(p: int) -> dict:
+    rng = np.random.default_rng([BATCH_SEED, 256, p])
+    nc = int(rng.integers(50, 501))
+    b = int(rng.choice([32, 64, 96]))
+    m0 = int(rng.integers(16, 65))
+    n = nc * b
+    return dict(nc=nc, b=b, M0=m0, Ne=BATCH_NE, mseed=BATCH_SEED + p, yseed=BATCH_SEED + 500 + p,
+                n_eig=int(round(0.6 * m0)), k0=n // 4)
+
+
+def batch256_pencil(p: int) -> Pencil:
+    s = batch256_shape(p)
+    return chain_pencil(s["nc"], s["b"], s["mseed"])
+
+
+def make_batch256(count: int, first: int = 0):
+    """[(pencil, emin, emax, M0, Ne, Y0)] of batch256 problems first .. first+count-1."""
+    with open(os.path.join(_GOLDEN, "intervals_batch256.json")) as f:
+        iv = json.load(f)
+    out = []
+    for p in range(first, first + count):
+        s = batch256_shape(p)
+        e = iv[str(p)]
+        pen = batch256_pencil(p)
+        out.append((pen, float(e["emin"]), float(e["emax"]), s["M0"], s["Ne"],
+                    random_subspace(pen.n, s["M0"], s["yseed"])))
+    return out
+
+
 def batch_pencil(p: int) -> Pencil:
     s = batch_shape(p)
     return chain_pencil(s["nc"], s["b"], s["mseed"])

@@ -10,6 +10,8 @@ Sylvester inertia count.
 
 Usage:  python tests/golden/make_intervals.py [name ...]
         python tests/golden/make_intervals.py --batch COUNT   (intervals_batch.json)
+        python tests/golden/make_intervals.py --batch256 COUNT [PROCS]
+                                                  (intervals_batch256.json)
 """
 from __future__ import annotations
 
@@ -75,6 +77,33 @@ def batch_interval(p):
                 gap_lo=e[1] - e[0], gap_hi=e[3] - e[2])
 
 
+def batch256_interval(p):
+    """Interval of problem p of the full-shape batched workload
+    (workloads.batch256_shape), as batch_interval."""
+    sh = W.batch256_shape(p)
+    pen = W.batch256_pencil(p)
+    k0, m = sh["k0"], sh["n_eig"]
+    lo, hi = -100.0, 100.0
+    assert O.inertia_count(pen, lo) == 0 and O.inertia_count(pen, hi) == pen.n
+    e = [kth_eigenvalue(pen, j, lo, hi) for j in (k0 - 1, k0, k0 + m - 1, k0 + m)]
+    emin, emax = 0.5 * (e[0] + e[1]), 0.5 * (e[2] + e[3])
+    cnt = O.inertia_count(pen, emax) - O.inertia_count(pen, emin)
+    assert cnt == m, (p, cnt, m)
+    return dict(emin=emin, emax=emax, n_eig=m, k0=k0, nc=sh["nc"], b=sh["b"], M0=sh["M0"],
+                gap_lo=e[1] - e[0], gap_hi=e[3] - e[2])
+
+
+def main_batch256(count, procs):
+    import multiprocessing
+    path = os.path.join(HERE, "intervals_batch256.json")
+    with multiprocessing.Pool(procs) as pool:
+        res = pool.map(batch256_interval, range(count), chunksize=1)
+    data = {str(p): r for p, r in enumerate(res)}
+    with open(path, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    print("wrote", path, len(data), flush=True)
+
+
 def main_batch(count):
     path = os.path.join(HERE, "intervals_batch.json")
     data = {}
@@ -101,5 +130,7 @@ def main(names):
 if __name__ == "__main__":
     if sys.argv[1:2] == ["--batch"]:
         main_batch(int(sys.argv[2]))
+    elif sys.argv[1:2] == ["--batch256"]:
+        main_batch256(int(sys.argv[2]), int(sys.argv[3]) if len(sys.argv) > 3 else 8)
     else:
         main(sys.argv[1:])

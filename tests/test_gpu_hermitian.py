@@ -46,7 +46,8 @@ def gap_interval(lam, k0, m):
     return 0.5 * (lam[k0 - 1] + lam[k0]), 0.5 * (lam[k0 + m - 1] + lam[k0 + m])
 
 
-@pytest.mark.parametrize("nc,b,m", [(1, 5, 3), (3, 16, 16), (7, 33, 20), (12, 64, 64), (20, 40, 9)])
+@pytest.mark.parametrize("nc,b,m", [(1, 5, 3), (3, 16, 16), (7, 33, 20), (12, 64, 64), (20, 40, 9),
+                                    (4, 96, 24)])
 @pytest.mark.parametrize("adjoint", [False, True])
 def test_shifted_solve_hermitian(ctx, torch, nc, b, m, adjoint):
     p = W.hermitian_pencil(nc, b, 500 + nc)
@@ -100,7 +101,7 @@ def check_hermitian(r, ref, p, emin, emax, lam_b, k0):
 
 @pytest.mark.parametrize("nc,b,seed,k0,m,extra", [
     (2, 3, 1, 1, 2, 2), (4, 5, 3, 5, 6, 4), (6, 8, 4, 10, 12, 6), (8, 16, 7, 40, 10, 8),
-    (20, 40, 9, 200, 20, 10), (5, 64, 11, 100, 30, 34)])
+    (20, 40, 9, 200, 20, 10), (5, 64, 11, 100, 30, 34), (5, 96, 12, 150, 20, 20)])
 def test_solve_hermitian(ctx, torch, nc, b, seed, k0, m, extra):
     p = W.hermitian_pencil(nc, b, seed)
     lam_b = O.bruteforce_hermitian(p)[0]

@@ -514,3 +514,38 @@ def test_deterministic(ctx, torch):
     a = ctx.solve(gp, emin, emax, m0, ne, y)
     b = ctx.solve(gp, emin, emax, m0, ne, y)
     assert torch.equal(a.lam, b.lam) and torch.equal(a.X, b.X) and torch.equal(a.res, b.res)
+
+
+@pytest.mark.parametrize("nc,b,seed,k0,m,extra", [(6, 96, 81, 150, 20, 20), (4, 80, 82, 90, 12, 30),
+                                                  (2, 65, 83, 40, 5, 3), (30, 96, 84, 700, 24, 16)])
+def test_solve_blocks_above_64(ctx, torch, nc, b, seed, k0, m, extra):
+    # b > 64: the generic kernels in real mode (A widened to complex; Q, the
+    # reduced problem and X real), against the oracle and brute force
+    p = W.dense_random_pencil(nc, b, seed)
+    lam = O.bruteforce(p)[0]
+    emin, emax = 0.5 * (lam[k0 - 1] + lam[k0]), 0.5 * (lam[k0 + m - 1] + lam[k0 + m])
+    m0 = m + extra
+    Y0 = W.random_subspace(p.n, m0, seed + 100)
+    r = ctx.solve(gpencil(p), emin, emax, m0, 8, dev(torch, Y0), tol=1e-13, max_loops=40)
+    ref = O.feast(p, emin, emax, m0, 8, Y0, tol=1e-13, max_loops=40)
+    # status 2 (B_Q fallback) where M0 is well above M, on both sides alike
+    assert r.status == ref.status and r.status in (0, 2)
+    check_against_oracle(r, ref, p, emin, emax)
+    assert np.max(np.abs(host(r.lam)[:m] - lam[k0:k0 + m]) / np.abs(lam[k0:k0 + m])) <= 1e-10
+
+
+def test_blocks_above_64_limits(ctx, torch):
+    from paper_0901_2665_amd import feast as F
+    p = W.dense_random_pencil(2, 96, 85)
+    y = dev(torch, W.random_subspace(p.n, 65, 1))
+    with pytest.raises(F.FeastError) as e:          # M0 above 64 on the generic kernels
+        ctx.solve(gpencil(p), 0.0, 1.0, 65, 8, y)
+    assert e.value.status == -3
+    with pytest.raises(F.FeastError) as e:          # no mixed precision there
+        ctx.solve(gpencil(p), 0.0, 1.0, 8, 8, dev(torch, W.random_subspace(p.n, 8, 1)),
+                  precision=1)
+    assert e.value.status == -7
+    q = W.dense_random_pencil(2, 97, 86)
+    with pytest.raises(F.FeastError) as e:          # above 96
+        ctx.solve(gpencil(q), 0.0, 1.0, 8, 8, dev(torch, W.random_subspace(q.n, 8, 1)))
+    assert e.value.status == -1

@@ -145,3 +145,26 @@ def test_single_problem_auto_partitions_residual(ctx, torch, idx):
     p, emin, emax, m0, ne, Y0 = W.make_batch(idx + 1)[idx]
     r = ctx.solve(gpencil(p), emin, emax, m0, ne, dev(torch, Y0), tol=1e-13)
     assert r.status in SOLVED and r.max_res <= 1e-9
+
+
+def test_batch256_sample_against_oracle(ctx, torch):
+    """Problems of the full-shape batched workload (nc 50-500, b 32/64/96,
+    M0 16-64, Ne 16), solved together: the smallest of each block size
+    against the oracle; every problem of the sample to its count and the
+    residual bar."""
+    shapes = [W.batch256_shape(p) for p in range(W.BATCH256_COUNT)]
+    pick = []
+    for b in (32, 64, 96):
+        cand = sorted((s["nc"], p) for p, s in enumerate(shapes) if s["b"] == b)
+        pick += [p for _, p in cand[:2]]
+    probs = [W.make_batch256(1, p)[0] for p in pick]
+    batch = [(gpencil(p), emin, emax, m0, ne, dev(torch, Y0)) for p, emin, emax, m0, ne, Y0 in probs]
+    st, rs = ctx.solve_batched(batch, tol=1e-13, workers=4)
+    assert st in SOLVED
+    for (p, emin, emax, m0, ne, Y0), q, r in zip(probs, pick, rs):
+        assert r.status in SOLVED and r.M == shapes[q]["n_eig"] and r.max_res <= 1e-9
+    for k in (0, 2, 4):  # one of each block size against the oracle
+        p, emin, emax, m0, ne, Y0 = probs[k]
+        ref = O.feast(p, emin, emax, m0, ne, Y0, tol=1e-13)
+        assert ref.status in SOLVED and ref.M == rs[k].M
+        check_against_oracle(rs[k], ref, p, emin, emax)

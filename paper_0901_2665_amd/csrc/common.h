@@ -63,6 +63,27 @@ __host__ __device__ constexpr int fpos(int i, int j) {
   return ((((i >> 3) << 2) + (i & 3)) * BP + j) * 2 + ((i >> 2) & 1);
 }
 
+// Matrix-operand fragments of one real BP x BP plane stored in the layout
+// fpos (above) for this lane: v[ks] = M[4 ks + kl][rb * 16 + lane % 16],
+// kl = lane / 16, i.e. the operand A'[r][k] = M[k][r] of row block rb (and,
+// the lane mapping of A and B being the same, the operand B[k][n] = M[k][n]
+// of column block rb).  Sixteen-byte loads through a buffer resource that
+// covers the plane (or nothing: valid = false, the loads then return zero).
+template <int BP>
+__device__ __forceinline__ void frag_plane_load(double (&v)[BP / 4], const double *M, int rb,
+                                                bool valid) {
+  const int l = threadIdx.x & 63;
+  const int row = rb * 16 + (l & 15), kl = l >> 4;
+  const auto rs = buf_rsrc(M, valid ? BP * BP * 8 : 0);
+  const int vo = fpos<BP>(kl, row) * 8;  // pair p adds 8 p BP elements
+#pragma unroll
+  for (int p = 0; p < BP / 8; ++p) {
+    const auto x = __builtin_amdgcn_raw_buffer_load_b128(rs, vo, p * 8 * BP * 8, 0);
+    v[2 * p] = __builtin_bit_cast(double, (u32x2){x[0], x[1]});
+    v[2 * p + 1] = __builtin_bit_cast(double, (u32x2){x[2], x[3]});
+  }
+}
+
 // wave index, known to the compiler as uniform across the wave
 __device__ __forceinline__ int wave_id() {
   return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));

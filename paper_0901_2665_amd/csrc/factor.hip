@@ -16,6 +16,7 @@
 // read transposed.  The factors are
 // computed once per solve and reused by every refinement loop (Sec. V,
 // parallelism (ii)).
+#include <algorithm>
 #include <vector>
 
 #include "common.h"
@@ -140,10 +141,10 @@ __device__ __forceinline__ int gpos(int r, int c) {
 }
 
 // slot <- complex block from global planes [2][BP][BP].
-template <int BP, bool FL>
+template <int BP, bool FL, int NTH = kThreads>
 __device__ void load_block(double *slot, const double *g) {
   constexpr int LD = Lds<BP>::LD, PLANE = Lds<BP>::PLANE;
-  for (int idx = threadIdx.x; idx < BP * BP; idx += kThreads) {
+  for (int idx = threadIdx.x; idx < BP * BP; idx += NTH) {
     int r = idx / BP, c = idx % BP;
     const int gi = gpos<BP, FL>(r, c);
     slot[r * LD + c] = g[gi];
@@ -154,10 +155,10 @@ __device__ void load_block(double *slot, const double *g) {
 // slot -> global block in the factor layout fpos, consecutive threads on
 // consecutive addresses: element gi of a plane holds (i, j) with
 // j = (gi / 2) % BP, R = (gi / 2) / BP, i = 8 (R / 4) + 4 (gi % 2) + R % 4.
-template <int BP>
+template <int BP, int NTH = kThreads>
 __device__ void store_block_fl(double *g, const double *slot, bool transpose) {
   constexpr int LD = Lds<BP>::LD, PLANE = Lds<BP>::PLANE;
-  for (int gi = threadIdx.x; gi < BP * BP; gi += kThreads) {
+  for (int gi = threadIdx.x; gi < BP * BP; gi += NTH) {
     const int j = (gi >> 1) % BP, R = (gi >> 1) / BP;
     const int i = ((R >> 2) << 3) + ((gi & 1) << 2) + (R & 3);
     const int s = transpose ? j * LD + i : i * LD + j;
@@ -321,12 +322,14 @@ struct NoSide {
   __device__ void operator()() const {}
 };
 
-template <int BP, class Side = NoSide>
-__device__ __forceinline__ void gj_invert(Lds<BP> &s, double *gout, Side side = Side(),
-                                          bool symm = true) {
+// NW waves run the elimination (at least NB - 1 of them: the row panel has a
+// wave per tile); the block sits in the LDS slot A.
+template <int BP, int NW, class Side = NoSide>
+__device__ __forceinline__ void gj_invert_slot(double *A, double *gout, Side side = Side(),
+                                               bool symm = true) {
   constexpr int LD = Lds<BP>::LD, PLANE = Lds<BP>::PLANE, NB = BP / 16;
+  static_assert(NW >= NB - 1 && NW >= 2, "one wave per tile of the row panel");
   const int w = wave_id();
-  double *A = s.A;
   auto tile = [&](int bi, int bj) { return A + (bi * 16) * LD + bj * 16; };
   // The next pivot tile (kb+1, kb+1) is updated first, by wave 0, which then
   // inverts it while waves 1-3 update the other tiles (look-ahead): the
@@ -375,11 +378,11 @@ __device__ __forceinline__ void gj_invert(Lds<BP> &s, double *gout, Side side = 
         // (no other tile of this phase reads tile (kb+1, kb+1))
         inv16_wave(tile(kb + 1, kb + 1), tile(kb + 1, kb + 1) + PLANE, LD);
       }
-      // the other tiles over waves 1-3 (look-ahead) or all four waves
-      constexpr int PER = NT > 0 ? (NT + 2) / 3 : 1;
+      // the other tiles over waves 1.. (look-ahead) or all waves
+      constexpr int PER = NT > 0 ? (NT + NW - 2) / (NW - 1) : 1;
       d4 tr[PER], ti[PER];
       int ib[PER], jbb[PER];
-      const int nw = look ? 3 : 4, wi = look ? w - 1 : w;
+      const int nw = look ? NW - 1 : NW, wi = look ? w - 1 : w;
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
         ib[q] = -1;
@@ -401,11 +404,24 @@ __device__ __forceinline__ void gj_invert(Lds<BP> &s, double *gout, Side side = 
     }
   }
   __syncthreads();
-  if (symm) {
-    // S <- (S + S^T) / 2 by 4x4 patches (the inverse of a complex symmetric
-    // block is complex symmetric; the sweeps read Sinv U transposed as
-    // U^T Sinv, which holds only to the asymmetry of the computed inverse,
-    // and that grows with its condition number near the real axis)
+  // S <- (S + S^T) / 2 (the inverse of a complex symmetric block is complex
+  // symmetric; the sweeps read Sinv U transposed as U^T Sinv, which holds
+  // only to the asymmetry of the computed inverse, and that grows with its
+  // condition number near the real axis)
+  if (symm && (NW != 4 || BP > 64)) {  // by pairs (r < c), each pair by one thread
+    for (int idx = threadIdx.x; idx < BP * BP; idx += 64 * NW) {
+      const int r = idx / BP, c = idx % BP;
+      if (r < c) {
+        const double ar = 0.5 * (A[r * LD + c] + A[c * LD + r]);
+        const double ai = 0.5 * (A[PLANE + r * LD + c] + A[PLANE + c * LD + r]);
+        A[r * LD + c] = ar;
+        A[c * LD + r] = ar;
+        A[PLANE + r * LD + c] = ai;
+        A[PLANE + c * LD + r] = ai;
+      }
+    }
+    __syncthreads();
+  } else if (symm) {  // by 4x4 patches, 256 threads
     const int t = threadIdx.x;
     const int pi = t >> 4, pj = t & 15;
     const bool act = (4 * pi < BP) && (4 * pj < BP);
@@ -433,8 +449,14 @@ __device__ __forceinline__ void gj_invert(Lds<BP> &s, double *gout, Side side = 
     }
     __syncthreads();
   }
-  if (gout) store_block_fl<BP>(gout, A, false);  // a block of Sinv: factor layout
+  if (gout) store_block_fl<BP, 64 * NW>(gout, A, false);  // a block of Sinv: factor layout
   __syncthreads();
+}
+
+template <int BP, class Side = NoSide>
+__device__ __forceinline__ void gj_invert(Lds<BP> &s, double *gout, Side side = Side(),
+                                          bool symm = true) {
+  gj_invert_slot<BP, kThreads / 64>(s.A, gout, side, symm);
 }
 
 // Complex product on the matrix cores, operands in LDS slots:
@@ -778,6 +800,146 @@ __global__ __launch_bounds__(kThreads) void twist_kernel(Pencil p, Shifts sh, Fa
   gj_invert<BP>(s, f.Sinv + ((size_t)e * nc + (m - 1)) * blk);
 }
 
+// ---- blocks of 64 < b <= 96 (BP = 96) ----
+//
+// One chain per contour point over all cells, top-down (no twist, no
+// partitions), six waves.  The complex 96 x 96 block fits in LDS once only,
+// so the slot holds S, then Sinv, then W, then the next S, and the coupling
+// U_c = Z B_{c,c+1} - A_{c,c+1} enters the products as matrix-operand
+// fragments of its real planes, packed once per solve in the layout fpos.
+// Wave w holds the fragments of column block w of U_c: they are the B
+// operand of column block w of W = Sinv U_c (every row block) and the A
+// operand of row block w of U_c^T W (every column block).
+constexpr int kWideBP = 96;
+constexpr int kWideWaves = kWideBP / 16;
+constexpr int kWideThreads = 64 * kWideWaves;
+
+// Au, Bu (caller layout, b x b) -> [nc-1][2][BP][BP] in the layout fpos,
+// zero padding.
+__global__ void pack_coupling_kernel(Pencil p, double *dst) {
+  constexpr int BP = kWideBP;
+  const size_t per = (size_t)BP * BP;
+  const size_t total = (size_t)(p.nc - 1) * per;
+  for (size_t o = blockIdx.x * (size_t)blockDim.x + threadIdx.x; o < total;
+       o += (size_t)gridDim.x * blockDim.x) {
+    const int c = (int)(o / per), idx = (int)(o % per);
+    const int i = idx / BP, j = idx % BP;
+    const bool in = i < p.b && j < p.b;
+    const size_t src = ((size_t)c * p.b + i) * p.b + j;
+    double *d = dst + (size_t)c * 2 * per;
+    const int fp = fpos<BP>(i, j);
+    d[fp] = in ? p.Au[src] : 0.0;
+    d[per + fp] = in ? p.Bu[src] : 0.0;
+  }
+}
+
+__global__ __launch_bounds__(kWideThreads) void factor_wide_kernel(Pencil p, Shifts sh, Factors f,
+                                                                   const double *cpl) {
+  constexpr int BP = kWideBP, NT = BP / 16, KS = BP / 4;
+  constexpr int LD = Lds<BP>::LD, PLANE = Lds<BP>::PLANE;
+  extern __shared__ double smem_raw[];
+  double *S = smem_raw;
+  const int e = blockIdx.x;
+  const int nc = p.nc, b = p.b;
+  const double zr = sh.zre[e], zi = sh.zim[e];
+  const size_t blk = 2 * (size_t)BP * BP, per = (size_t)BP * BP;
+  const size_t bb = (size_t)b * b;
+  double *Sinv = f.Sinv + (size_t)e * nc * blk;
+  double *Wg = f.W + (size_t)e * nc * blk;
+  double *WTg = f.WT + (size_t)e * nc * blk;
+  const int w = wave_id(), l = lane_id();
+  const int kl = l >> 4, m = l & 15;
+
+  form_block<BP, kWideThreads>(S, p.Ad, p.Bd, b, zr, zi, false, true);  // S_0 = D_0
+  __syncthreads();
+  for (int c = 0; c < nc; ++c) {
+    gj_invert_slot<BP, kWideWaves>(S, Sinv + c * blk);  // S <- Sinv_c (also stored)
+    if (c == nc - 1) break;
+    double ua[KS], ub[KS];  // column block w of the real planes of U_c
+    frag_plane_load<BP>(ua, cpl + c * 2 * per, w, true);
+    frag_plane_load<BP>(ub, cpl + c * 2 * per + per, w, true);
+    // column block w of W = Sinv U_c: tile (ib, w), A operand Sinv[ib rows][k]
+    // read as Sinv[k][ib rows] (symmetric)
+    d4 wr[NT], wi[NT];
+#pragma unroll
+    for (int ib = 0; ib < NT; ++ib) {
+      d4 t1 = d4zero(), ar = d4zero(), ai = d4zero();
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const int xa = (4 * ks + kl) * LD + ib * 16 + m;
+        const double xr = S[xa], xi = S[PLANE + xa];
+        const double yr = zr * ub[ks] - ua[ks], yi = zi * ub[ks];
+        t1 = mfma(xr, yr + yi, t1);
+        ar = mfma(-(xr + xi), yi, ar);
+        ai = mfma(xi - xr, yr, ai);
+      }
+      wr[ib] = ar + t1;
+      wi[ib] = ai + t1;
+    }
+    double *Wc = Wg + c * blk, *WTc = WTg + c * blk;
+#pragma unroll
+    for (int ib = 0; ib < NT; ++ib)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = ib * 16 + acc_row(l, r), col = w * 16 + acc_col(l);
+        Wc[fpos<BP>(row, col)] = wr[ib][r];
+        Wc[per + fpos<BP>(row, col)] = wi[ib][r];
+        WTc[fpos<BP>(col, row)] = wr[ib][r];
+        WTc[per + fpos<BP>(col, row)] = wi[ib][r];
+      }
+    __syncthreads();  // every wave is done with Sinv
+#pragma unroll
+    for (int ib = 0; ib < NT; ++ib)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = ib * 16 + acc_row(l, r), col = w * 16 + acc_col(l);
+        S[row * LD + col] = wr[ib][r];
+        S[PLANE + row * LD + col] = wi[ib][r];
+      }
+    __syncthreads();
+    // row block w of S_{c+1} = D_{c+1} - U_c^T W: A operand -U_c[k][w rows]
+    const double *Ad = p.Ad + (c + 1) * bb, *Bd = p.Bd + (c + 1) * bb;
+    d4 sr[NT], si[NT];
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = w * 16 + acc_row(l, r), col = tj * 16 + acc_col(l);
+        if (row < b && col < b) {
+          const double bv = Bd[row * b + col], av = Ad[row * b + col];
+          sr[tj][r] = zr * bv - av;
+          si[tj][r] = zi * bv;
+        } else {
+          sr[tj][r] = row == col ? 1.0 : 0.0;
+          si[tj][r] = 0.0;
+        }
+      }
+      d4 t1 = d4zero();
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const double xr = ua[ks] - zr * ub[ks], xi = -zi * ub[ks];
+        const int yb = (4 * ks + kl) * LD + tj * 16 + m;
+        const double yr = S[yb], yi = S[PLANE + yb];
+        t1 = mfma(xr, yr + yi, t1);
+        sr[tj] = mfma(-(xr + xi), yi, sr[tj]);
+        si[tj] = mfma(xi - xr, yr, si[tj]);
+      }
+      sr[tj] += t1;
+      si[tj] += t1;
+    }
+    __syncthreads();  // every wave is done with W
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = w * 16 + acc_row(l, r), col = tj * 16 + acc_col(l);
+        S[row * LD + col] = sr[tj][r];
+        S[PLANE + row * LD + col] = si[tj][r];
+      }
+    __syncthreads();
+  }
+}
+
 template <int BP>
 hipError_t set_lds(const void *fn) {
   return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -852,6 +1014,28 @@ hipError_t launch_factor_bp(const Pencil &p, const Shifts &s, int Ne, const Fact
 }
 
 }  // namespace
+
+size_t wide_coupling_doubles(const Pencil &p) {
+  return p.nc > 1 ? (size_t)(p.nc - 1) * 2 * kWideBP * kWideBP : 1;
+}
+
+hipError_t launch_factor_wide(const Pencil &p, const Shifts &s, int Ne, const Factors &f,
+                              double *cpl, hipStream_t st) {
+  if (p.bp != kWideBP || p.b > kWideBP || Ne < 1) return hipErrorInvalidValue;
+  const int shm = 2 * Lds<kWideBP>::PLANE * (int)sizeof(double);
+  hipError_t err = hipFuncSetAttribute((const void *)factor_wide_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, shm);
+  if (err != hipSuccess) return err;
+  if (p.nc > 1) {
+    const size_t total = (size_t)(p.nc - 1) * kWideBP * kWideBP;
+    const int grid = (int)std::min<size_t>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(pack_coupling_kernel, dim3(grid), dim3(256), 0, st, p, cpl);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+  }
+  hipLaunchKernelGGL(factor_wide_kernel, dim3(Ne), dim3(kWideThreads), shm, st, p, s, f,
+                     (const double *)cpl);
+  return hipGetLastError();
+}
 
 size_t factor_work_doubles(const Pencil &p, int Ne, int parts) {
   return 3 * (size_t)Ne * 2 * parts * 2 * p.bp * p.bp;

@@ -217,6 +217,17 @@ Pencil make_pencil(const feast_bt_matrix *AB) {
   return p;
 }
 
+// Real pencils with 64 < b <= 96 run on the wide kernels: one top-down
+// chain per node over all cells (factor.hip, sweep.hip), blocks padded to 96.
+constexpr int kWideBP = 96;
+bool is_wide(const feast_bt_matrix *AB) { return AB && AB->b > kMaxB && AB->b <= kWideBP; }
+
+Pencil make_wide_pencil(const feast_bt_matrix *AB) {
+  Pencil p = make_pencil(AB);
+  p.bp = kWideBP;
+  return p;
+}
+
 // Non-finite scan of the pencil (and optionally Y0); returns -6 on NaN/Inf.
 int check_inputs(feast_ctx *ctx, const feast_bt_matrix *AB, const double *Y0, size_t ny) {
   int *flag = nullptr;
@@ -279,6 +290,34 @@ int prepare_factor(feast_ctx *ctx, const Pencil &p, int Ne, int m0p, int parts, 
 hipError_t run_factor(feast_ctx *ctx, const Work &wk, const Shifts &s) {
   return launch_factor(wk.p, s, wk.Ne, wk.f, wk.parts, wk.fwork, wk.chains, wk.sb.G, wk.gtiles,
                        ctx->stream);
+}
+
+// Workspace of the wide kernels for Ne nodes and m0p padded columns (the
+// slots of the twisted factorisation, which a wide solve does not use).
+struct WideWork {
+  Pencil p;
+  Factors f;
+  SolveBufs sb;
+  double *cpl;
+  int Ne, m0p;
+  size_t rows;
+};
+
+int prepare_wide(feast_ctx *ctx, const Pencil &p, int Ne, int m0p, WideWork &ww) {
+  const size_t blk = 2 * (size_t)kWideBP * kWideBP;
+  ww.p = p;
+  ww.Ne = Ne;
+  ww.m0p = m0p;
+  ww.rows = (size_t)p.nc * kWideBP;
+  ww.f.m = p.nc;
+  ww.f.TW = nullptr;
+  HIPCHK(ensure_t(ctx, S_SINV, (size_t)Ne * p.nc * blk, &ww.f.Sinv));
+  HIPCHK(ensure_t(ctx, S_W, (size_t)Ne * p.nc * blk, &ww.f.W));
+  HIPCHK(ensure_t(ctx, S_WT, (size_t)Ne * p.nc * blk, &ww.f.WT));
+  HIPCHK(ensure_t(ctx, S_G, (size_t)Ne * (m0p / kTile) * p.nc * 2 * kWideBP * kTile, &ww.sb.G));
+  ww.sb.TV = nullptr;
+  HIPCHK(ensure_t(ctx, S_FWORK, wide_coupling_doubles(p), &ww.cpl));
+  return 0;
 }
 
 // ---- mixed precision: float32 factors and sweeps, float64 refinement ----
@@ -515,6 +554,34 @@ int feast_shifted_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double z_re, 
                         int32_t m, const double *R, double *X_re, double *X_im,
                         int32_t partitions) {
   if (!ctx || !R || !X_re || !X_im) return -5;
+  if (is_wide(AB)) {  // one chain, no partitions
+    if (!AB->A_diag || !AB->B_diag || (AB->nc > 1 && (!AB->A_up || !AB->B_up))) return -5;
+    if (AB->nc < 1) return -1;
+    if (m < 1 || m > kMaxM0) return -3;
+    if (!(z_im > 0.0) || !std::isfinite(z_re) || !std::isfinite(z_im)) return -2;
+    if (partitions < 0) return -7;
+    HIPCHK(hipSetDevice(ctx->device));
+    const Pencil p = make_wide_pencil(AB);
+    const int mp = round16(m);
+    WideWork ww;
+    int st = prepare_wide(ctx, p, 1, mp, ww);
+    if (st) return st;
+    Shifts s;
+    std::memset(&s, 0, sizeof(s));
+    s.zre[0] = z_re;
+    s.zim[0] = z_im;
+    double *rin, *xr, *xi;
+    HIPCHK(ensure_t(ctx, S_R, ww.rows * mp, &rin));
+    HIPCHK(ensure_t(ctx, S_T0, ww.rows * mp, &xr));
+    HIPCHK(ensure_t(ctx, S_T1, ww.rows * mp, &xi));
+    HIPCHK(launch_factor_wide(p, s, 1, ww.f, ww.cpl, ctx->stream));
+    HIPCHK(launch_pack(R, p.nc, p.b, p.bp, m, mp, rin, ctx->stream));
+    HIPCHK(launch_sweeps_wide(p, s, 1, ww.f, ww.sb, rin, mp, xr, xi, 3, ctx->stream));
+    HIPCHK(launch_unpack(xr, p.nc, p.b, p.bp, m, mp, nullptr, X_re, ctx->stream));
+    HIPCHK(launch_unpack(xi, p.nc, p.b, p.bp, m, mp, nullptr, X_im, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return 0;
+  }
   int st = validate_matrix(AB);
   if (st) return st;
   if (m < 1 || m > kMaxM0) return -3;
@@ -1308,16 +1375,24 @@ namespace {
 // (complex, or real in real mode) or NULL for the seeded random start.
 int generic_solve(feast_ctx *ctx, const HPencil &p, double emin, double emax, int M0, int Ne,
                   const feast_opts &o, bool real_mode, const double *y0, double *lambda,
-                  double *X_out, double *res, feast_info *info) {
+                  double *X_out, double *res, feast_info *info, const Pencil *wide) {
   hipStream_t sm = ctx->stream;
   int st = 0;
   const long long N = (long long)p.nc * p.b;
   Shifts s;
   make_shifts(Ne, emin, emax, s);
   const double r = 0.5 * (emax - emin);
-  HFactors f;
-  st = prepare_hfactors(ctx, p, Ne, f);
-  if (st) return st;
+  HFactors f{};
+  WideWork ww{};
+  double *wre = nullptr;  // real [N][M0] staging of the wide filter
+  if (wide) {
+    st = prepare_wide(ctx, *wide, Ne, round16(M0), ww);
+    if (st) return st;
+    HIPCHK(ensure_t(ctx, S_T0, ww.rows * ww.m0p, &wre));
+  } else {
+    st = prepare_hfactors(ctx, p, Ne, f);
+    if (st) return st;
+  }
   double *coef;
   st = hcoefficients(ctx, s, Ne, &coef);
   if (st) return st;
@@ -1346,7 +1421,28 @@ int generic_solve(feast_ctx *ctx, const HPencil &p, double emin, double emax, in
   HIPCHK(ensure_t(ctx, S_FLAG, 4, &flag));
   HIPCHK(ensure_t(ctx, S_PERM, (size_t)M0, &perm));
 
-  HIPCHK(launch_hfactor(p, s, Ne, f.Sinv, f.W, f.V, sm));  // once (Sec. V, parallelism (ii))
+  // factor once (Sec. V, parallelism (ii))
+  if (wide)
+    HIPCHK(launch_factor_wide(*wide, s, Ne, ww.f, ww.cpl, sm));
+  else
+    HIPCHK(launch_hfactor(p, s, Ne, f.Sinv, f.W, f.V, sm));
+  // Q of a real pencil and a real right-hand side by the wide sweeps: the
+  // adjoint solve of eq. 12 is the complex conjugate of the direct one, so
+  // Q = sum_e Re(kappa_e x_e) (eq. 15) from the real part of R
+  auto wide_filter = [&](const double *Rc, double *Qc) -> int {
+    double *rp, *pp, *qp;
+    HIPCHK(ensure_t(ctx, S_R, ww.rows * ww.m0p, &rp));
+    HIPCHK(ensure_t(ctx, S_P, (size_t)Ne * ww.rows * ww.m0p, &pp));
+    HIPCHK(ensure_t(ctx, S_Q, ww.rows * ww.m0p, &qp));
+    const Pencil &wp = *wide;
+    HIPCHK(launch_real_part(Rc, (size_t)N * M0, wre, sm));
+    HIPCHK(launch_pack(wre, wp.nc, wp.b, wp.bp, M0, ww.m0p, rp, sm));
+    HIPCHK(launch_sweeps_wide(wp, s, Ne, ww.f, ww.sb, rp, ww.m0p, pp, nullptr, 3, sm));
+    HIPCHK(launch_sum_nodes(pp, Ne, ww.rows * ww.m0p, qp, sm));
+    HIPCHK(launch_unpack(qp, wp.nc, wp.b, wp.bp, M0, ww.m0p, nullptr, wre, sm));
+    HIPCHK(launch_to_complex(wre, (size_t)N * M0, Qc, sm));
+    return 0;
+  };
   if (real_mode) {  // real start block, widened to complex
     if (y0) {
       HIPCHK(launch_to_complex(y0, (size_t)N * M0, y, sm));
@@ -1371,7 +1467,7 @@ int generic_solve(feast_ctx *ctx, const HPencil &p, double emin, double emax, in
   std::vector<char> is_counted(M0, 0);
   for (int k = 1; k <= o.max_loops; ++k) {
     HIPCHK(launch_happly(p, 1, y, M0, rr, sm));                       // R = B Y
-    st = hfilter(ctx, p, Ne, f, rr, M0, coef, q);                      // Q (eq. 12)
+    st = wide ? wide_filter(rr, q) : hfilter(ctx, p, Ne, f, rr, M0, coef, q);  // Q (eq. 12)
     if (st) return st;
     HIPCHK(launch_happly(p, 0, q, M0, ax, sm));
     HIPCHK(launch_happly(p, 1, q, M0, bx, sm));
@@ -1497,13 +1593,14 @@ int feast_solve_hermitian(feast_ctx *ctx, const feast_zbt_matrix *AB, double emi
   st = check_hinputs(ctx, AB, o.Y0, (size_t)N * M0 * 2);
   if (st) return st;
   return generic_solve(ctx, make_hpencil(AB), emin, emax, M0, Ne, o, false, o.Y0, lambda, X,
-                       res, info);
+                       res, info, nullptr);
 }
 
 namespace {
 
-// Real symmetric pencils with blocks above the optimised kernels' 64: A is
-// widened to complex and the generic kernels run in real mode.
+// Real symmetric pencils with 64 < b <= 96: the shifted systems run on the
+// wide kernels; A is widened to complex for the generic projection and
+// residual kernels, which run in real mode.
 int solve_generic_real(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double emax,
                        int32_t M0, int32_t Ne, const feast_opts &o, double *lambda, double *X,
                        double *res, feast_info *info) {
@@ -1526,7 +1623,8 @@ int solve_generic_real(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, d
   p.Bu = AB->B_up;
   p.nc = AB->nc;
   p.b = AB->b;
-  return generic_solve(ctx, p, emin, emax, M0, Ne, o, true, o.Y0, lambda, X, res, info);
+  const Pencil wp = make_wide_pencil(AB);
+  return generic_solve(ctx, p, emin, emax, M0, Ne, o, true, o.Y0, lambda, X, res, info, &wp);
 }
 
 }  // namespace

@@ -46,6 +46,14 @@ size_t factor_work_doubles(const Pencil &p, int Ne, int parts);
 hipError_t launch_factor(const Pencil &p, const Shifts &s, int Ne, const Factors &f, int parts,
                          double *work, Chain *chains, double *G, int gtiles, hipStream_t st);
 
+// Blocks of 64 < b <= 96 (bp = 96): one top-down chain per node over all
+// cells (no twist: f.m unused, Sinv, W and W^T of every cell; W and W^T of
+// the last cell unused).  cpl: wide_coupling_doubles() of workspace for the
+// packed coupling planes.
+size_t wide_coupling_doubles(const Pencil &p);
+hipError_t launch_factor_wide(const Pencil &p, const Shifts &s, int Ne, const Factors &f,
+                              double *cpl, hipStream_t st);
+
 // Spike solves of the partitioned factorisation (sweep.hip): for every chain,
 // the first and last block of T^{-1} E_1 where T is the chain's local matrix.
 hipError_t launch_spikes(const Pencil &p, const Factors &f, const Chain *chains, int nchains,
@@ -62,6 +70,12 @@ struct SolveBufs {
 hipError_t launch_sweeps(const Pencil &p, const Shifts &s, int Ne, const Factors &f,
                          const SolveBufs &sb, const double *R, int m0p, double *P, int part,
                          hipStream_t st);
+// The sweeps of the wide factorisation (launch_factor_wide): Xim == nullptr:
+// P[e] = Re(kappa_e x_e) (padded, per node); else the complex solution of
+// node 0 in P (real plane) and Xim.  sb.G as for launch_sweeps, sb.TV unused.
+hipError_t launch_sweeps_wide(const Pencil &p, const Shifts &s, int Ne, const Factors &f,
+                              const SolveBufs &sb, const double *R, int m0p, double *P,
+                              double *Xim, int part, hipStream_t st);
 // Same sweeps, but the back sweep writes the complex solution of node 0
 // (used by the single-shift entry point): X_re, X_im padded.
 hipError_t launch_sweeps_complex(const Pencil &p, const Shifts &s, const Factors &f,

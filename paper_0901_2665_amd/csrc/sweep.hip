@@ -365,6 +365,162 @@ __global__ __launch_bounds__(BP * 4) void back_kernel(SweepArgs a) {
 }
 
 
+// ---- blocks of 64 < b <= 96 (BP = 96): one chain per contour point ----
+//
+// The factorisation of these blocks runs top-down over all cells (no twist,
+// see factor.hip), so the sweeps are the plain block forward and back
+// substitutions:  h_0 = R_0,  g_c = Sinv_c h_c,  h_{c+1} = R_{c+1} - W_c^T h_c;
+// x_last = g_last,  x_c = g_c - W_c x_{c+1}.  A fragment of a 96 x 96 complex
+// block takes 96 registers, so one wave per 16-row block computes both
+// products of a forward step from fragments of its own (the B operand is
+// read from LDS inside the product, not staged in registers), and reloads
+// each fragment array as soon as its product has consumed it: the load of
+// W_{c+1} overlaps the Sinv_c product and that of Sinv_{c+1} the next W
+// product.
+constexpr int kWideBP = 96;
+constexpr int kWideThreads = kWideBP / 16 * 64;
+
+// acc0 + A' B' for fragments f and the vector tile hv in LDS (the operand
+// bvec_load builds, read one k-step at a time).
+template <int BP>
+__device__ __forceinline__ d4 frag_mfma_lds(const d4 &acc0, const Frag<BP> &f, const double *hv) {
+  constexpr int PL = VecLds<BP>::PL;
+  const int l = lane_id();
+  const int kl = l >> 4, n = l & 15, col = n & 7;
+  const double *h0 = (n < 8) ? hv : hv + PL;
+  const double *h1 = (n < 8) ? hv + PL : hv;
+  const double s1 = (n < 8) ? -1.0 : 1.0;
+  d4 a0 = acc0, a1 = d4zero(), a2 = d4zero(), a3 = d4zero();
+#pragma unroll
+  for (int ks = 0; ks < BP / 4; ks += 2) {
+    a0 = mfma(f.v[ks], h0[(4 * ks + kl) * kTile + col], a0);
+    a1 = mfma(f.v[ks + 1], h0[(4 * ks + 4 + kl) * kTile + col], a1);
+    a2 = mfma(f.v[BP / 4 + ks], s1 * h1[(4 * ks + kl) * kTile + col], a2);
+    a3 = mfma(f.v[BP / 4 + ks + 1], s1 * h1[(4 * ks + 4 + kl) * kTile + col], a3);
+  }
+  return (a0 + a1) + (a2 + a3);
+}
+
+__global__ __launch_bounds__(kWideThreads) void forward_wide_kernel(SweepArgs a) {
+  constexpr int BP = kWideBP;
+  __shared__ VecLds<BP> s;
+  const int item = xcd_item(blockIdx.x, gridDim.x, a.ntiles);
+  const int tau = item % a.ntiles;
+  const int e = item / a.ntiles;
+  const int nc = a.p.nc;
+  const size_t blk = 2 * (size_t)BP * BP;
+  const size_t vt = 2 * (size_t)BP * kTile;
+  const int rb = wave_id();
+  const double *Wm = a.f.W + (size_t)e * nc * blk;
+  const double *Sm = a.f.Sinv + (size_t)e * nc * blk;
+  double *G = a.sb.G + ((size_t)e * a.ntiles + tau) * nc * vt;
+  const double *R = a.R + tau * kTile;
+  const size_t rstride = (size_t)BP * a.m0p;
+
+  // LDS keeps u_c = -h_c
+  lds_store_vec<BP>(s.v[0], -rhs_load<BP>(R, a.m0p, rb, true), rb);
+  Frag<BP> fw, fs;
+  frag_load<BP>(fw, Wm, rb, nc > 1);
+  frag_load<BP>(fs, Sm, rb, true);
+  d4 rn = rhs_load<BP>(R + rstride, a.m0p, rb, nc > 1);
+  __syncthreads();
+  int cur = 0;
+  for (int c = 0; c < nc; ++c) {
+    const bool more = c + 1 < nc;
+    // h_{c+1} = R_{c+1} + W_c^T u_c (W_{c+1} exists while c + 2 < nc)
+    const d4 h = frag_mfma_lds<BP>(more ? rn : d4zero(), fw, s.v[cur]);
+    frag_load<BP>(fw, Wm + (c + 1) * blk, rb, c + 2 < nc);
+    rn = rhs_load<BP>(R + (c + 2) * rstride, a.m0p, rb, c + 2 < nc);
+    if (more) lds_store_vec<BP>(s.v[cur ^ 1], -h, rb);
+    // Sinv_c u_c = -g_c
+    const d4 g = frag_mfma_lds<BP>(d4zero(), fs, s.v[cur]);
+    frag_load<BP>(fs, Sm + (c + 1) * blk, rb, more);
+    vec_store_buf<BP>(G + c * vt, -g, rb, true);
+    __syncthreads();
+    cur ^= 1;
+  }
+}
+
+// x_c = g_c + W_c v with v = -x_{c+1} in LDS; output as in back_kernel.
+// Two fragment arrays: the W^T fragments of the next cell load during the
+// current product.
+template <bool COMPLEX_OUT>
+__global__ __launch_bounds__(kWideThreads) void back_wide_kernel(SweepArgs a) {
+  constexpr int BP = kWideBP;
+  __shared__ VecLds<BP> s;
+  const int item = xcd_item(blockIdx.x, gridDim.x, a.ntiles);
+  const int tau = item % a.ntiles;
+  const int e = item / a.ntiles;
+  const int nc = a.p.nc;
+  const size_t blk = 2 * (size_t)BP * BP;
+  const size_t vt = 2 * (size_t)BP * kTile;
+  const double *WT = a.f.WT + (size_t)e * nc * blk;
+  const double *G = a.sb.G + ((size_t)e * a.ntiles + tau) * nc * vt;
+  const size_t pstride = (size_t)BP * a.m0p;
+  double *P = (COMPLEX_OUT ? a.P : a.P + (size_t)e * nc * pstride) + tau * kTile;
+  double *Xim = COMPLEX_OUT ? a.Xim + tau * kTile : nullptr;
+  const double kr = a.kre[e], ki = a.kim[e];
+  const int l = lane_id();
+  const int rb = wave_id();
+  const int n = l & 15;
+  const int pbytes = BP * a.m0p * 8;
+  auto emit = [&](int c, const d4 &x) {
+    const auto rp = buf_rsrc(P + c * pstride, pbytes);
+    const auto ri = buf_rsrc(COMPLEX_OUT ? Xim + c * pstride : nullptr, COMPLEX_OUT ? pbytes : 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double other = __shfl_xor(x[r], 8);
+      const int off = ((rb * 16 + acc_row(l, r)) * a.m0p + (n & 7)) * 8;
+      if (COMPLEX_OUT) {
+        buf_store(x[r], rp, n < 8 ? off : kBufferOff, 0);
+        buf_store(x[r], ri, n < 8 ? kBufferOff : off, 0);
+      } else {
+        buf_store(kr * x[r] - ki * other, rp, n < 8 ? off : kBufferOff, 0);
+      }
+    }
+  };
+  // x_last = g_last
+  {
+    const d4 x = vec_load_buf<BP>(G + (nc - 1) * vt, rb, true);
+    lds_store_vec<BP>(s.v[0], -x, rb);
+    emit(nc - 1, x);
+  }
+  Frag<BP> f0, f1;
+  frag_load<BP>(f0, WT + (nc - 2) * blk, rb, nc > 1);
+  d4 ga = vec_load_buf<BP>(G + (nc - 2) * vt, rb, nc > 1), gb = d4zero();
+  __syncthreads();
+  int cur = 0;
+  auto step = [&](int c, const Frag<BP> &f, const d4 &g, Frag<BP> &nf, d4 &ng) {
+    frag_load<BP>(nf, WT + (c - 1) * blk, rb, c >= 1);
+    ng = vec_load_buf<BP>(G + (c - 1) * vt, rb, c >= 1);
+    const d4 x = frag_mfma_lds<BP>(g, f, s.v[cur]);
+    lds_store_vec<BP>(s.v[cur ^ 1], -x, rb);
+    emit(c, x);
+    __syncthreads();
+    cur ^= 1;
+  };
+  for (int c = nc - 2; c >= 0; c -= 2) {
+    step(c, f0, ga, f1, gb);
+    if (c - 1 >= 0) step(c - 1, f1, gb, f0, ga);
+  }
+}
+
+hipError_t launch_wide(SweepArgs &a, int Ne, bool complex_out, int part, hipStream_t st) {
+  const int nblocks = Ne * a.ntiles;
+  if (part & 1) {
+    hipLaunchKernelGGL(forward_wide_kernel, dim3(nblocks), dim3(kWideThreads), 0, st, a);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+  }
+  if (part & 2) {
+    if (complex_out)
+      hipLaunchKernelGGL(back_wide_kernel<true>, dim3(nblocks), dim3(kWideThreads), 0, st, a);
+    else
+      hipLaunchKernelGGL(back_wide_kernel<false>, dim3(nblocks), dim3(kWideThreads), 0, st, a);
+  }
+  return hipGetLastError();
+}
+
 // Spike solves of the partitioned factorisation.  For a chain with local
 // matrix T (factored by its own top-down recurrence: Sinv_j, W_j) and
 // E_1 = first block column of the identity, y = T^{-1} E_1 follows from
@@ -621,6 +777,17 @@ hipError_t launch_spikes(const Pencil &p, const Factors &f, const Chain *chains,
     case 64: return launch_spike_bp<64>(a, grid, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_sweeps_wide(const Pencil &p, const Shifts &s, int Ne, const Factors &f,
+                              const SolveBufs &sb, const double *R, int m0p, double *P,
+                              double *Xim, int part, hipStream_t st) {
+  if (p.bp != kWideBP) return hipErrorInvalidValue;
+  SweepArgs a;
+  a.p = p; a.f = f; a.sb = sb; a.R = R; a.P = P; a.Xim = Xim;
+  a.m0p = m0p; a.ntiles = m0p / kTile;
+  for (int e = 0; e < kMaxNe; ++e) { a.kre[e] = s.kre[e]; a.kim[e] = s.kim[e]; }
+  return launch_wide(a, Ne, Xim != nullptr, part, st);
 }
 
 hipError_t launch_sweeps_complex(const Pencil &p, const Shifts &s, const Factors &f,

@@ -102,6 +102,49 @@ def test_shifted_solve(ctx, torch, nc, b, m):
     assert_columnwise(X, ref, 1e-10)
 
 
+# 64 < b <= 96: the wide kernels (one top-down chain per shift, blocks padded
+# to 96), single and padded blocks, up to 128 right-hand sides
+WIDE_SHAPES = [(1, 96, 8), (2, 65, 3), (5, 80, 24), (12, 96, 40), (3, 96, 128), (40, 70, 16)]
+
+
+@pytest.mark.parametrize("nc,b,m", WIDE_SHAPES)
+def test_shifted_solve_wide_blocks(ctx, torch, nc, b, m):
+    p = W.dense_random_pencil(nc, b, 300 + nc + b)
+    R = np.random.default_rng(11 * nc + b).standard_normal((p.n, m))
+    z = 0.37 + 0.05j
+    xr, xi = ctx.shifted_solve(gpencil(p), z, dev(torch, R))
+    X = host(xr) + 1j * host(xi)
+    ref = O.shifted_solve(p, z, R)
+    M = O.shifted_matrix(p, z)
+    berr = np.linalg.norm(R - M @ X, axis=0) / (spla.norm(M) * np.linalg.norm(X, axis=0))
+    assert np.max(berr) <= 1e-14
+    assert_columnwise(X, ref, 1e-10)
+
+
+@pytest.mark.parametrize("eta", [5e-2, 1e-3, 1e-4])
+def test_shifted_solve_wide_near_axis(ctx, torch, eta):
+    # the benchmark chain recipe at b = 96, shifts inside the spectrum
+    p = W.chain_pencil(60, 96, 4243)
+    B = O.assemble(p.Bd, p.Bu)
+    bmin = spla.eigsh(B, k=1, which="SA", return_eigenvectors=False)[0]
+    z = 0.1234 + 1j * eta
+    R = np.random.default_rng(19).standard_normal((p.n, 24))
+    xr, xi = ctx.shifted_solve(gpencil(p), z, dev(torch, R))
+    X = host(xr) + 1j * host(xi)
+    M = O.shifted_matrix(p, z)
+    berr = np.linalg.norm(R - M @ X, axis=0) / (spla.norm(M) * np.linalg.norm(X, axis=0))
+    print(f"wide near axis: Im z {eta:g}  backward error {np.max(berr):.2e}")
+    bar = WIDE_NEAR_AXIS_BAR[eta]
+    assert np.max(berr) <= bar
+    ref = O.shifted_solve(p, z, R)
+    cond = spla.norm(M) / (eta * bmin)
+    assert_columnwise(X, ref, max(1e-12, 10 * bar * cond))
+
+
+# measured: 6.1e-17, 3.4e-15, 5.7e-14 (one chain, no partitions)
+WIDE_NEAR_AXIS_BAR = {5e-2: 1e-15, 1e-3: 2e-14, 1e-4: 3e-13}
+
+
 def near_axis_chain():
     """A chain of the benchmark recipe long enough for several partitions
     of the factorisation (nc = 160, b = 32: 10 per half chain)."""
@@ -519,8 +562,9 @@ def test_deterministic(ctx, torch):
 @pytest.mark.parametrize("nc,b,seed,k0,m,extra", [(6, 96, 81, 150, 20, 20), (4, 80, 82, 90, 12, 30),
                                                   (2, 65, 83, 40, 5, 3), (30, 96, 84, 700, 24, 16)])
 def test_solve_blocks_above_64(ctx, torch, nc, b, seed, k0, m, extra):
-    # b > 64: the generic kernels in real mode (A widened to complex; Q, the
-    # reduced problem and X real), against the oracle and brute force
+    # b > 64: the wide kernels for the shifted systems, the generic kernels in
+    # real mode for the rest (A widened to complex; Q, the reduced problem and
+    # X real), against the oracle and brute force
     p = W.dense_random_pencil(nc, b, seed)
     lam = O.bruteforce(p)[0]
     emin, emax = 0.5 * (lam[k0 - 1] + lam[k0]), 0.5 * (lam[k0 + m - 1] + lam[k0 + m])

@@ -39,11 +39,12 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# The batched legs drive one HIP stream per host worker (8); HIP maps a
+# The batched legs drive one HIP stream per host worker (16); HIP maps a
 # process's streams onto GPU_MAX_HW_QUEUES hardware queues (4 by default).
-# Eight queues measured 16% more problems/s on the 32-problem batch (557
-# against 480; 16 queues 575).  Set before the HIP runtime starts.
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+# Measured: 32-problem batch 480 problems/s with 8 workers on 4 queues, 557
+# on 8, 575 on 16; the 256-problem batch 106 with 8 workers on 8 queues and
+# 151 with 16 on 16.  Set before the HIP runtime starts.
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
 
 METRIC = "FEAST solves/sec and shifted-solve TFLOP/s (% MFMA peak) at 1e-10 eig accuracy"
 PEAK_FP64 = 78.6        # TFLOP/s, MI355X dense FP64 (matrix = vector)
@@ -383,8 +384,9 @@ def main():
                     help="0: float64 shifted solves; 1: mixed precision")
     ap.add_argument("--batch", type=int, default=32,
                     help="problems per step of the tbbatch workload")
-    ap.add_argument("--workers", type=int, default=0,
-                    help="host workers (HIP streams) of the tbbatch workload; 0 = automatic")
+    ap.add_argument("--workers", type=int, default=16,
+                    help="host workers (HIP streams) of the batched workloads; 0 = the "
+                         "library's default (8)")
     ap.add_argument("--graph", type=int, default=0, choices=(0, 1),
                     help="tbbatch: 1 = loops after the first replay a captured HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -425,7 +427,8 @@ def main():
             mixed["cpu_baseline"] = dict(line["cpu_baseline"], extrapolated=True,
                                          note="the float64 oracle of the headline line")
         line["mixed"] = mixed
-        line["batched"] = batch_leg(ctx, 32, 0, 2, 1, cpu=cpu)
+        line["batched"] = batch_leg(ctx, 256, 0, 2, 1, workers=args.workers, cpu=cpu,
+                                    workload="tbbatch256")
     ctx.close()
     print(json.dumps(line), flush=True)
 

@@ -40,7 +40,8 @@
  * Status codes (int):
  *    0  success
  *   -1  nc < 1 or b < 1, or b above the supported maximum (96 for feast_solve,
- *       feast_solve_batched and feast_solve_hermitian, 64 for the other calls)
+ *       feast_solve_batched, feast_shifted_solve and feast_solve_hermitian, 64
+ *       for the other calls)
  *   -2  emin >= emax or a bound is not finite
  *   -3  M0 < 1 or M0 > N, or M0 above the supported maximum, 128
  *   -4  Ne < 1 or Ne > 64
@@ -75,12 +76,16 @@ typedef struct feast_ctx feast_ctx;
 /* Block-tridiagonal pencil (A, B); all four pointers (dev), float64. */
 typedef struct {
   int32_t nc;            /* number of cells, >= 1 */
-  int32_t b;             /* block size, 1..64; feast_solve and
-                            feast_solve_batched also take 65..96: such
-                            pencils run on the generic kernels of the
-                            Hermitian variant (A widened to complex, real
-                            mode: Q, the reduced problem and X real), with
-                            M0 <= 64, precision 0 and no partitions */
+  int32_t b;             /* block size, 1..64; feast_solve,
+                            feast_solve_batched and feast_shifted_solve also
+                            take 65..96: the shifted systems of such pencils
+                            run on the wide kernels (blocks padded to 96,
+                            one top-down chain per contour point, no twist
+                            and no partitions), the projection and the
+                            residuals on the generic kernels of the Hermitian
+                            variant in real mode (A widened to complex; Q,
+                            the reduced problem and X real), with M0 <= 64
+                            (feast_shifted_solve: m <= 128) and precision 0 */
   const double *A_diag;  /* [nc][b][b] */
   const double *A_up;    /* [nc-1][b][b] (may be NULL when nc == 1) */
   const double *B_diag;  /* [nc][b][b] */
@@ -258,7 +263,8 @@ int feast_bt_multiply(feast_ctx *ctx, const feast_bt_matrix *AB, int32_t which,
  * Solve (z B - A) X = R for one complex shift z with Im z > 0 (Fig. 2 step 2),
  * R real (dev) [N][m]; X_re, X_im (dev) [N][m].  1 <= m <= 128.
  * partitions: partitions per half chain of the factorisation as in
- * feast_opts (0 = automatic).
+ * feast_opts (0 = automatic); ignored for 64 < b <= 96 (the wide kernels
+ * factor one top-down chain).
  */
 int feast_shifted_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double z_re,
                         double z_im, int32_t m, const double *R, double *X_re,

@@ -338,7 +338,7 @@ __device__ __forceinline__ void gj_invert_slot(double *A, double *gout, Side sid
     inv16_wave(tile(0, 0), tile(0, 0) + PLANE, LD);
   else
     side();
-  for (int kb = 0; kb < NB; ++kb) {
+  auto panel = [&](int kb) {
     __syncthreads();
     if constexpr (NB > 1) {
       // row panel S_KJ <- P S_KJ
@@ -402,6 +402,12 @@ __device__ __forceinline__ void gj_invert_slot(double *A, double *gout, Side sid
       for (int q = 0; q < PER; ++q)
         if (ib[q] >= 0) tile_store<BP>(tile(ib[q], jbb[q]), tr[q], ti[q]);
     }
+  };
+  if constexpr (NW == 4) {
+    for (int kb = 0; kb < NB; ++kb) panel(kb);
+  } else {  // a rolled loop keeps the wide block's tile addresses out of registers
+#pragma unroll 1
+    for (int kb = 0; kb < NB; ++kb) panel(kb);
   }
   __syncthreads();
   // S <- (S + S^T) / 2 (the inverse of a complex symmetric block is complex
@@ -814,27 +820,50 @@ constexpr int kWideBP = 96;
 constexpr int kWideWaves = kWideBP / 16;
 constexpr int kWideThreads = 64 * kWideWaves;
 
-// Au, Bu (caller layout, b x b) -> [nc-1][2][BP][BP] in the layout fpos,
-// zero padding.
-__global__ void pack_coupling_kernel(Pencil p, double *dst) {
+// Couplings Au, Bu (caller layout, b x b) -> [nc-1][2][BP][BP] and diagonal
+// blocks Ad, Bd -> [nc][2][BP][BP], in the layout fpos.  Padding: zero, but
+// -1 in A on the diagonal of a diagonal block (so that Z B - A holds the
+// identity there).
+__global__ void pack_wide_kernel(Pencil p, double *cpl, double *dia) {
   constexpr int BP = kWideBP;
   const size_t per = (size_t)BP * BP;
-  const size_t total = (size_t)(p.nc - 1) * per;
+  const size_t ncpl = (size_t)(p.nc - 1) * per;
+  const size_t total = ncpl + (size_t)p.nc * per;
   for (size_t o = blockIdx.x * (size_t)blockDim.x + threadIdx.x; o < total;
        o += (size_t)gridDim.x * blockDim.x) {
-    const int c = (int)(o / per), idx = (int)(o % per);
+    const bool diag = o >= ncpl;
+    const size_t q = diag ? o - ncpl : o;
+    const int c = (int)(q / per), idx = (int)(q % per);
     const int i = idx / BP, j = idx % BP;
     const bool in = i < p.b && j < p.b;
     const size_t src = ((size_t)c * p.b + i) * p.b + j;
-    double *d = dst + (size_t)c * 2 * per;
+    double *d = (diag ? dia : cpl) + (size_t)c * 2 * per;
     const int fp = fpos<BP>(i, j);
-    d[fp] = in ? p.Au[src] : 0.0;
-    d[per + fp] = in ? p.Bu[src] : 0.0;
+    const double pad_a = (diag && i == j) ? -1.0 : 0.0;
+    d[fp] = in ? (diag ? p.Ad : p.Au)[src] : pad_a;
+    d[per + fp] = in ? (diag ? p.Bd : p.Bu)[src] : 0.0;
   }
 }
 
+// Tile (rb, tj) of a packed real plane (layout fpos) in the accumulator
+// layout: element r of lane l is M[rb*16 + l/16 + 4r][tj*16 + l%16]; rows
+// l/16 and l/16 + 4 (and + 8, + 12) sit next to each other in fpos, so two
+// sixteen-byte loads fetch the four.
+template <int BP>
+__device__ __forceinline__ d4 acc_plane_load(__amdgpu_buffer_rsrc_t rs, int soff, int rb, int tj) {
+  const int l = threadIdx.x & 63;
+  const int vo = fpos<BP>(rb * 16 + (l >> 4), tj * 16 + (l & 15)) * 8;
+  const auto x = __builtin_amdgcn_raw_buffer_load_b128(rs, vo, soff, 0);
+  const auto y = __builtin_amdgcn_raw_buffer_load_b128(rs, vo + 8 * BP * 8, soff, 0);
+  return d4{__builtin_bit_cast(double, (u32x2){x[0], x[1]}),
+            __builtin_bit_cast(double, (u32x2){x[2], x[3]}),
+            __builtin_bit_cast(double, (u32x2){y[0], y[1]}),
+            __builtin_bit_cast(double, (u32x2){y[2], y[3]})};
+}
+
 __global__ __launch_bounds__(kWideThreads) void factor_wide_kernel(Pencil p, Shifts sh, Factors f,
-                                                                   const double *cpl) {
+                                                                   const double *cpl,
+                                                                   const double *dia) {
   constexpr int BP = kWideBP, NT = BP / 16, KS = BP / 4;
   constexpr int LD = Lds<BP>::LD, PLANE = Lds<BP>::PLANE;
   extern __shared__ double smem_raw[];
@@ -864,7 +893,7 @@ __global__ __launch_bounds__(kWideThreads) void factor_wide_kernel(Pencil p, Shi
 #pragma unroll
     for (int ib = 0; ib < NT; ++ib) {
       d4 t1 = d4zero(), ar = d4zero(), ai = d4zero();
-#pragma unroll
+#pragma unroll 4
       for (int ks = 0; ks < KS; ++ks) {
         const int xa = (4 * ks + kl) * LD + ib * 16 + m;
         const double xr = S[xa], xi = S[PLANE + xa];
@@ -876,17 +905,6 @@ __global__ __launch_bounds__(kWideThreads) void factor_wide_kernel(Pencil p, Shi
       wr[ib] = ar + t1;
       wi[ib] = ai + t1;
     }
-    double *Wc = Wg + c * blk, *WTc = WTg + c * blk;
-#pragma unroll
-    for (int ib = 0; ib < NT; ++ib)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = ib * 16 + acc_row(l, r), col = w * 16 + acc_col(l);
-        Wc[fpos<BP>(row, col)] = wr[ib][r];
-        Wc[per + fpos<BP>(row, col)] = wi[ib][r];
-        WTc[fpos<BP>(col, row)] = wr[ib][r];
-        WTc[per + fpos<BP>(col, row)] = wi[ib][r];
-      }
     __syncthreads();  // every wave is done with Sinv
 #pragma unroll
     for (int ib = 0; ib < NT; ++ib)
@@ -897,25 +915,20 @@ __global__ __launch_bounds__(kWideThreads) void factor_wide_kernel(Pencil p, Shi
         S[PLANE + row * LD + col] = wi[ib][r];
       }
     __syncthreads();
+    store_block_fl<BP, kWideThreads>(Wg + c * blk, S, false);
+    store_block_fl<BP, kWideThreads>(WTg + c * blk, S, true);
     // row block w of S_{c+1} = D_{c+1} - U_c^T W: A operand -U_c[k][w rows]
-    const double *Ad = p.Ad + (c + 1) * bb, *Bd = p.Bd + (c + 1) * bb;
+    const auto rd = buf_rsrc(dia, nc * 2 * BP * BP * 8);
+    const int dsoff = (c + 1) * 2 * BP * BP * 8;
     d4 sr[NT], si[NT];
 #pragma unroll
     for (int tj = 0; tj < NT; ++tj) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = w * 16 + acc_row(l, r), col = tj * 16 + acc_col(l);
-        if (row < b && col < b) {
-          const double bv = Bd[row * b + col], av = Ad[row * b + col];
-          sr[tj][r] = zr * bv - av;
-          si[tj][r] = zi * bv;
-        } else {
-          sr[tj][r] = row == col ? 1.0 : 0.0;
-          si[tj][r] = 0.0;
-        }
-      }
+      const d4 av = acc_plane_load<BP>(rd, dsoff, w, tj);
+      const d4 bv = acc_plane_load<BP>(rd, dsoff + BP * BP * 8, w, tj);
+      sr[tj] = zr * bv - av;
+      si[tj] = zi * bv;
       d4 t1 = d4zero();
-#pragma unroll
+#pragma unroll 4
       for (int ks = 0; ks < KS; ++ks) {
         const double xr = ua[ks] - zr * ub[ks], xi = -zi * ub[ks];
         const int yb = (4 * ks + kl) * LD + tj * 16 + m;
@@ -1015,25 +1028,26 @@ hipError_t launch_factor_bp(const Pencil &p, const Shifts &s, int Ne, const Fact
 
 }  // namespace
 
-size_t wide_coupling_doubles(const Pencil &p) {
-  return p.nc > 1 ? (size_t)(p.nc - 1) * 2 * kWideBP * kWideBP : 1;
+size_t wide_pack_doubles(const Pencil &p) {
+  return (size_t)(2 * p.nc - 1) * 2 * kWideBP * kWideBP;
 }
 
 hipError_t launch_factor_wide(const Pencil &p, const Shifts &s, int Ne, const Factors &f,
-                              double *cpl, hipStream_t st) {
+                              double *pack, hipStream_t st) {
   if (p.bp != kWideBP || p.b > kWideBP || Ne < 1) return hipErrorInvalidValue;
+  // the byte offsets of the packed diagonal blocks stay within 32 bits
+  if ((size_t)p.nc * 2 * kWideBP * kWideBP * 8 > 0x7fffffffu) return hipErrorInvalidValue;
   const int shm = 2 * Lds<kWideBP>::PLANE * (int)sizeof(double);
   hipError_t err = hipFuncSetAttribute((const void *)factor_wide_kernel,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, shm);
   if (err != hipSuccess) return err;
-  if (p.nc > 1) {
-    const size_t total = (size_t)(p.nc - 1) * kWideBP * kWideBP;
-    const int grid = (int)std::min<size_t>((total + 255) / 256, 4096);
-    hipLaunchKernelGGL(pack_coupling_kernel, dim3(grid), dim3(256), 0, st, p, cpl);
-    if ((err = hipGetLastError()) != hipSuccess) return err;
-  }
+  double *cpl = pack, *dia = pack + (size_t)(p.nc - 1) * 2 * kWideBP * kWideBP;
+  const size_t total = (size_t)(2 * p.nc - 1) * kWideBP * kWideBP;
+  const int grid = (int)std::min<size_t>((total + 255) / 256, 4096);
+  hipLaunchKernelGGL(pack_wide_kernel, dim3(grid), dim3(256), 0, st, p, cpl, dia);
+  if ((err = hipGetLastError()) != hipSuccess) return err;
   hipLaunchKernelGGL(factor_wide_kernel, dim3(Ne), dim3(kWideThreads), shm, st, p, s, f,
-                     (const double *)cpl);
+                     (const double *)cpl, (const double *)dia);
   return hipGetLastError();
 }
 

@@ -316,7 +316,7 @@ int prepare_wide(feast_ctx *ctx, const Pencil &p, int Ne, int m0p, WideWork &ww)
   HIPCHK(ensure_t(ctx, S_WT, (size_t)Ne * p.nc * blk, &ww.f.WT));
   HIPCHK(ensure_t(ctx, S_G, (size_t)Ne * (m0p / kTile) * p.nc * 2 * kWideBP * kTile, &ww.sb.G));
   ww.sb.TV = nullptr;
-  HIPCHK(ensure_t(ctx, S_FWORK, wide_coupling_doubles(p), &ww.cpl));
+  HIPCHK(ensure_t(ctx, S_FWORK, wide_pack_doubles(p), &ww.cpl));
   return 0;
 }
 

@@ -48,11 +48,11 @@ hipError_t launch_factor(const Pencil &p, const Shifts &s, int Ne, const Factors
 
 // Blocks of 64 < b <= 96 (bp = 96): one top-down chain per node over all
 // cells (no twist: f.m unused, Sinv, W and W^T of every cell; W and W^T of
-// the last cell unused).  cpl: wide_coupling_doubles() of workspace for the
-// packed coupling planes.
-size_t wide_coupling_doubles(const Pencil &p);
+// the last cell unused).  pack: wide_pack_doubles() of workspace for the
+// blocks of the pencil repacked in the operand layout.
+size_t wide_pack_doubles(const Pencil &p);
 hipError_t launch_factor_wide(const Pencil &p, const Shifts &s, int Ne, const Factors &f,
-                              double *cpl, hipStream_t st);
+                              double *pack, hipStream_t st);
 
 // Spike solves of the partitioned factorisation (sweep.hip): for every chain,
 // the first and last block of T^{-1} E_1 where T is the chain's local matrix.

@@ -243,6 +243,10 @@ def solve_leg(ctx, workload, precision, steps, warmup, cpu=True):
         solve_kernels = ["factor", "round_factors", "forward_sweep32", "back_sweep32",
                          "refine_residual"]
         peak_of = {"forward_sweep32": PEAK_FP32, "back_sweep32": PEAK_FP32}
+    elif prec == 2:
+        solve_kernels = ["factor", "round_factors", "forward_sweep32", "back_sweep32",
+                         "forward_sweep", "back_sweep"]
+        peak_of = {"forward_sweep32": PEAK_FP32, "back_sweep32": PEAK_FP32}
     else:
         solve_kernels = ["factor", "forward_sweep", "back_sweep"]
         peak_of = {}
@@ -262,10 +266,11 @@ def solve_leg(ctx, workload, precision, steps, warmup, cpu=True):
         "steps": steps,
         "warmup": warmup,
         "ms_per_step": 1e3 * elapsed / steps,
-        "dtype": "f32+f64" if prec == 1 else "f64",
+        "dtype": "f32+f64" if prec in (1, 2) else "f64",
         "config": {"workload": workload, "nc": p.nc, "b": p.b, "n": p.n, "M0": m0,
                    "Ne": ne, "interval": [emin, emax], "eigenvalues_in_interval": wl["n_eig"],
-                   "tol": 1e-12, "precision": "mixed" if prec == 1 else "float64"},
+                   "tol": 1e-12,
+                   "precision": {0: "float64", 1: "mixed", 2: "adaptive"}[prec]},
         "shifted_solve_tflops": shifted_tflops,
         "shifted_solve_frac_peak": shifted_tflops / shifted_peak,
         "gate": gate,
@@ -380,8 +385,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="tb128k")
-    ap.add_argument("--precision", type=int, default=0, choices=(0, 1),
-                    help="0: float64 shifted solves; 1: mixed precision")
+    ap.add_argument("--precision", type=int, default=0, choices=(0, 1, 2),
+                    help="0: float64 shifted solves; 1: mixed precision; 2: float32 "
+                         "solves in the first loop only (experiment)")
     ap.add_argument("--batch", type=int, default=32,
                     help="problems per step of the tbbatch workload")
     ap.add_argument("--workers", type=int, default=16,
@@ -427,6 +433,10 @@ def main():
             mixed["cpu_baseline"] = dict(line["cpu_baseline"], extrapolated=True,
                                          note="the float64 oracle of the headline line")
         line["mixed"] = mixed
+        # labelled experiment: float32 solves in the first loop only, float64 after
+        adaptive = solve_leg(ctx, "tb128k", 2, 2, 1, cpu=False)
+        adaptive["vs_float64"] = adaptive["value"] / line["value"]
+        line["adaptive"] = adaptive
         line["batched"] = batch_leg(ctx, 256, 0, 2, 1, workers=args.workers, cpu=cpu,
                                     workload="tbbatch256")
     ctx.close()

@@ -98,7 +98,12 @@ typedef struct {
   int32_t precision;     /* 0: complex float64 shifted solves;
                             1: factor blocks rounded to float32, complex float32
                             sweeps, float64 iterative refinement of every
-                            shifted solve (criterion: feast_shifted_solve_mixed) */
+                            shifted solve (criterion: feast_shifted_solve_mixed);
+                            2 (experiment, float64 factors): the first contour
+                            integration by one float32 solve per node without
+                            refinement, every later one in float64; the
+                            convergence test compares two float64 loops.
+                            b <= 64 for 1 and 2 */
   int32_t partitions;    /* partitions per half chain of the factorisation;
                             0 = automatic (at least 8 cells each, about one
                             chain per compute unit).  The partitioned
@@ -148,7 +153,8 @@ typedef struct {
   double trace_hist[64]; /* trace per loop (first min(loops,64) entries) */
   int32_t count_hist[64];/* M per loop */
   int32_t rr_sweeps;     /* Jacobi sweeps of the reduced eigensolver, all loops */
-  int32_t refine_steps;  /* precision 1: float32 correction solves, all loops */
+  int32_t refine_steps;  /* precision 1: float32 correction solves, all loops;
+                            precision 2: loops run with float32 solves */
   double solve_res;      /* precision 1: largest final residual ratio of a
                             shifted solve column (feast_shifted_solve_mixed)
                             over all loops and nodes */

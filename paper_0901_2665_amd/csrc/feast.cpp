@@ -816,7 +816,7 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
   feast_opts o;
   feast_default_opts(&o);
   if (opts) o = *opts;
-  if (!(o.tol > 0.0) || o.max_loops < 1 || o.precision < 0 || o.precision > 1 ||
+  if (!(o.tol > 0.0) || o.max_loops < 1 || o.precision < 0 || o.precision > 2 ||
       o.partitions < 0 || o.graph < 0 || o.graph > 1)
     return -7;
   HIPCHK(hipSetDevice(ctx->device));
@@ -856,8 +856,12 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
   // factor every shifted matrix once (Sec. V, parallelism (ii))
   TIMED(K_FACTOR, run_factor(ctx, wk, s));
   const bool mixed = o.precision == 1;
+  // precision 2: the first contour integration by one float32 solve per node
+  // (no refinement; the random start carries no accuracy that a float32 solve
+  // could lose), every later one in float64 from the same float64 factors
+  const bool adaptive = o.precision == 2;
   Mixed mx;
-  if (mixed) {
+  if (mixed || adaptive) {
     st = prepare_mixed(ctx, wk, mx);
     if (st) return st;
     TIMED(K_ROUND, launch_round_factors(p, Ne, wk.f, mx.f, sm));
@@ -883,7 +887,8 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
   std::vector<char> is_counted(M0, 0);
   // graph = 1: loops 2, 3, ... replay one captured loop; it ends with a copy
   // Y <- X (in place of the pointer swap of the eager loop)
-  const bool use_graph = o.graph == 1 && !mixed;
+  const bool use_graph = o.graph == 1 && o.precision == 0;
+  bool prev_f32 = false;  // the previous loop's Q came from float32 solves
   GraphExec gx;
   auto graph_body = [&](hipStream_t sm) -> hipError_t {
     hipError_t e;
@@ -906,7 +911,13 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
       HIPCHK(hipGraphLaunch(gx.exec, sm));
     } else {
     TIMED(K_BTMUL, launch_cell_apply(p, 1, y, mp, rr, sm));                  // R = B Y
-    if (mixed) {  // Q_e by refined float32 solves, then Q (eq. 15)
+    const bool f32_loop = adaptive && k == 1;
+    if (f32_loop) {  // Q_e by one float32 solve per node, then Q (eq. 15)
+      TIMED(K_FWD32, launch_sweeps32(p, Ne, mx.f, mx.sb, rr, 0, 0, mp, mx.xc, 0, 1, sm));
+      TIMED(K_BACK32, launch_sweeps32(p, Ne, mx.f, mx.sb, rr, 0, 0, mp, mx.xc, 0, 2, sm));
+      TIMED(K_SUM, launch_sum_nodes_complex(s, Ne, mx.xc, mx.plane, q, sm));
+      ++refine_steps;
+    } else if (mixed) {  // Q_e by refined float32 solves, then Q (eq. 15)
       int steps = 0;
       double worst = 0.0;
       st = mixed_solve(ctx, wk, mx, s, rr, M0, &steps, &worst);
@@ -960,10 +971,14 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
     if (o.verbose)
       std::fprintf(stderr, "feast: loop %d  M %d  trace %.17g  trace change %.3e%s\n", k, Mk, Tk,
                    k >= 2 ? trace_rel : INFINITY, std::isfinite(left_min) ? "  (uncounted pairs inside)" : "");
-    if (k >= 2 && Mk == counts[counts.size() - 2] && trace_rel < o.tol && !still_converging) {
+    // (both traces of the test from float64 solves)
+    const bool this_f32 = adaptive && k == 1;
+    if (k >= 2 && Mk == counts[counts.size() - 2] && trace_rel < o.tol && !still_converging &&
+        !prev_f32 && !this_f32) {
       converged = true;
       break;
     }
+    prev_f32 = this_f32;
     if (k < o.max_loops && !use_graph) std::swap(y, x);  // Y <- X (Fig. 2 step 6)
     if (use_graph && k == 1)  // the graph's loops read Y from the same buffer
       HIPCHK(hipMemcpyAsync(y, x, rows * mp * sizeof(double), hipMemcpyDeviceToDevice, sm));

@@ -231,7 +231,7 @@ class SolveResult:
     traces: list
     counts: list
     rr_sweeps: int = 0
-    refine_steps: int = 0  # precision 1: float32 correction solves, all loops
+    refine_steps: int = 0  # precision 1: float32 correction solves; 2: float32 loops
     solve_res: float = 0.0  # precision 1: worst final relative residual of a shifted solve
 
 

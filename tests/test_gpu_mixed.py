@@ -183,3 +183,29 @@ def test_solve_mixed_tb128k_full_size(ctx, torch):
     res_host = O.residuals(p, lam[cols], X, emin, emax)
     assert np.max(res_host) <= 1e-9
     assert np.allclose(res_host, res[cols], rtol=1e-3, atol=1e-14)
+
+
+# precision 2 (experiment): the first contour integration by one float32
+# solve per node, the later ones in float64 from the same factors; the
+# results must meet the float64 contract (same M, eigenvalues to 1e-10 of
+# the oracle, residuals at most 1e-9)
+def test_solve_adaptive_chain800(ctx, torch):
+    p, emin, emax, m0, ne, Y0 = W.make_workload("chain800")
+    r = ctx.solve(gpencil(p), emin, emax, m0, ne, dev(torch, Y0), precision=2)
+    ref = O.feast(p, emin, emax, m0, ne, Y0)
+    assert r.status == 0 and r.refine_steps == 1 and r.loops >= 3
+    check_against_oracle(r, ref, p, emin, emax)
+
+
+@pytest.mark.parametrize("name", ["tb6400", "tb128k"])
+def test_solve_adaptive_golden(ctx, torch, name):
+    g = json.load(open(os.path.join(GOLDEN, f"feast_{name}.json")))
+    p, emin, emax, m0, ne, Y0 = W.make_workload(name)
+    r = ctx.solve(gpencil(p), emin, emax, m0, ne, dev(torch, Y0), precision=2)
+    print(f"adaptive {name}: loops {r.loops} (float64 oracle {g['loops']}), max res {r.max_res:.2e}")
+    assert r.status == 0 and r.refine_steps == 1
+    assert r.M == g["M"] == 80
+    lam = host(r.lam)[:80]
+    assert np.max(np.abs(lam - np.array(g["lam"])) / np.abs(lam)) <= 1e-10
+    assert np.max(host(r.res)[:80]) <= 1e-9
+    assert abs(r.loops - g["loops"]) <= 1

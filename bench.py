@@ -187,7 +187,7 @@ def cpu_baseline(p, emin, emax, m0, ne, Y0, loops):
     return out
 
 
-def solve_leg(ctx, workload, precision, steps, warmup, cpu=True):
+def solve_leg(ctx, workload, precision, steps, warmup, cpu=True, graph=0):
     """Timed complete solves of one workload; returns the bench-line fields."""
     import torch
     from paper_0901_2665_amd import feast as F
@@ -201,13 +201,13 @@ def solve_leg(ctx, workload, precision, steps, warmup, cpu=True):
            torch.empty(m0, dtype=torch.float64, device="cuda"))
     prec = precision
     for _ in range(warmup):
-        r = ctx.solve(gp, emin, emax, m0, ne, y, out=out, precision=prec)
+        r = ctx.solve(gp, emin, emax, m0, ne, y, out=out, precision=prec, graph=graph)
     torch.cuda.synchronize()
     ctx.timing(True)
     t0 = time.perf_counter()
     results = []
     for _ in range(steps):
-        r = ctx.solve(gp, emin, emax, m0, ne, y, out=out, precision=prec)
+        r = ctx.solve(gp, emin, emax, m0, ne, y, out=out, precision=prec, graph=graph)
         results.append((r.status, r.M, r.loops, r.max_res))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -270,7 +270,8 @@ def solve_leg(ctx, workload, precision, steps, warmup, cpu=True):
         "config": {"workload": workload, "nc": p.nc, "b": p.b, "n": p.n, "M0": m0,
                    "Ne": ne, "interval": [emin, emax], "eigenvalues_in_interval": wl["n_eig"],
                    "tol": 1e-12,
-                   "precision": {0: "float64", 1: "mixed", 2: "adaptive"}[prec]},
+                   "precision": {0: "float64", 1: "mixed", 2: "adaptive"}[prec],
+                   "graph": graph},
         "shifted_solve_tflops": shifted_tflops,
         "shifted_solve_frac_peak": shifted_tflops / shifted_peak,
         "gate": gate,
@@ -393,8 +394,9 @@ def main():
     ap.add_argument("--workers", type=int, default=16,
                     help="host workers (HIP streams) of the batched workloads; 0 = the "
                          "library's default (8)")
-    ap.add_argument("--graph", type=int, default=0, choices=(0, 1),
-                    help="tbbatch: 1 = loops after the first replay a captured HIP graph")
+    ap.add_argument("--graph", type=int, default=0, choices=(0, 1, 2),
+                    help="1 = loops after the first replay a captured HIP graph; 2 = the "
+                         "convergence decision on the device, four loops per graph launch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="only the headline line (no mixed-precision and batched legs)")
@@ -418,7 +420,8 @@ def main():
         leg = batch_leg(ctx, count, args.precision, args.steps, args.warmup, args.workers,
                         args.graph, cpu, workload=args.workload)
     else:
-        leg = solve_leg(ctx, args.workload, args.precision, args.steps, args.warmup, cpu)
+        leg = solve_leg(ctx, args.workload, args.precision, args.steps, args.warmup, cpu,
+                        graph=args.graph)
     line = {"metric": METRIC, "value": leg.pop("value"), "unit": leg.pop("unit"), "n_gpus": 1}
     line.update({k: leg.pop(k) for k in ("steps", "warmup", "ms_per_step")})
     line.update({"higher_is_better": True, "scaling": "weak", "vs_baseline": None,

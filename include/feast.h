@@ -125,7 +125,15 @@ typedef struct {
                             Results are bitwise those of graph = 0; the
                             per-kernel timers see the eager launches only.
                             For callers that pay for launch latency (many
-                            small problems); 0 = eager launches */
+                            small problems).  2 = the convergence decision
+                            runs on the device after every loop (same
+                            decisions as the host's), and the loops are
+                            captured four at a time into one graph whose
+                            kernels return at once after convergence: one
+                            graph launch and one host synchronisation per
+                            four loops, Y and X alternating between two
+                            buffers; bitwise the results of graph = 0;
+                            max_loops <= 64.  0 = eager launches */
   const double *Y0;      /* (dev) [N][M0] initial subspace, or NULL: then
                             M0 random vectors are drawn on the device from
                             `seed` (Fig. 2 step 1): element t = i*M0 + j of

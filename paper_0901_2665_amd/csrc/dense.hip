@@ -208,7 +208,9 @@ __device__ __forceinline__ void cell_loop(CellLds<BP, NOP> &s, const double *con
 template <int BP>
 __global__ __launch_bounds__(kCellThreads) void cell_apply_kernel(const double *D, const double *U,
                                                                   int nc, int b, const double *V,
-                                                                  int ld, double *out) {
+                                                                  int ld, double *out,
+                                                                  const int *skip) {
+  if (skip && *skip) return;  // a converged solve: later loops of a captured solve do nothing
   __shared__ CellLds<BP, 1> s;
   constexpr int NR = BP / 16;
   const int nct = ld / 16;
@@ -235,7 +237,9 @@ template <int BP>
 __global__ __launch_bounds__(kCellThreads) void cell_project_kernel(const double *D,
                                                                     const double *U, int nc,
                                                                     int b, const double *Q,
-                                                                    int ld, double *partial) {
+                                                                    int ld, double *partial,
+                                                                    const int *skip) {
+  if (skip && *skip) return;  // a converged solve: later loops of a captured solve do nothing
   __shared__ CellLds<BP, 1> s;
   constexpr int NR = BP / 16;
   const int nct = ld / 16;
@@ -293,7 +297,9 @@ __global__ __launch_bounds__(kCellThreads) void cell_project_kernel(const double
 // combined in a fixed order (bitwise reproducible); symmetrize_kernel then
 // forms (S + S^T) / 2.
 __global__ __launch_bounds__(256) void cell_project_reduce_kernel(const double *partial, int groups,
-                                                                  int ld, int m0, double *M) {
+                                                                  int ld, int m0, double *M,
+                                                                  const int *skip) {
+  if (skip && *skip) return;  // a converged solve: later loops of a captured solve do nothing
   __shared__ double red[4][64];
   const int e = threadIdx.x & 63, sl = threadIdx.x >> 6;
   const int idx = blockIdx.x * 64 + e;
@@ -310,7 +316,8 @@ __global__ __launch_bounds__(256) void cell_project_reduce_kernel(const double *
 }
 
 // M <- (M + M^T) / 2 in place (m0 x m0), one thread per pair i < j.
-__global__ void symmetrize_kernel(double *M, int m0) {
+__global__ void symmetrize_kernel(double *M, int m0, const int *skip) {
+  if (skip && *skip) return;  // a converged solve: later loops of a captured solve do nothing
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= m0 * m0) return;
   const int i = idx / m0, j = idx % m0;
@@ -325,7 +332,8 @@ __global__ void symmetrize_kernel(double *M, int m0) {
 template <int BP>
 __global__ __launch_bounds__(kCellThreads) void cell_residual_kernel(
     const double *Ad, const double *Au, const double *Bd, const double *Bu, int nc, int b,
-    const double *X, int ld, const double *lam, int m0, double *partial) {
+    const double *X, int ld, const double *lam, int m0, double *partial, const int *skip) {
+  if (skip && *skip) return;  // a converged solve: later loops of a captured solve do nothing
   __shared__ CellLds<BP, 2> s;
   constexpr int NR = BP / 16;
   const int nct = ld / 16;
@@ -527,7 +535,9 @@ __global__ void sum_nodes_complex_kernel(Shifts sh, int Ne, const double *X, siz
   }
 }
 
-__global__ void sum_nodes_kernel(const double *P, int Ne, size_t count, double *Q) {
+__global__ void sum_nodes_kernel(const double *P, int Ne, size_t count, double *Q,
+                                 const int *skip) {
+  if (skip && *skip) return;  // a converged solve: later loops of a captured solve do nothing
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count;
        i += (size_t)gridDim.x * blockDim.x) {
     double s = 0.0;
@@ -543,7 +553,9 @@ __global__ void sum_nodes_kernel(const double *P, int Ne, size_t count, double *
 // load (a select lets the compiler put the load behind a branch).
 template <int NCT>
 __global__ __launch_bounds__(256) void gemm_qphi_kernel(const double *Q, size_t rows, int m0,
-                                                        const double *Phi, double *X) {
+                                                        const double *Phi, double *X,
+                                                        const int *skip) {
+  if (skip && *skip) return;  // a converged solve: later loops of a captured solve do nothing
   constexpr int M0P = 16 * NCT;
   const int l = lane_id(), w = wave_id();
   const size_t rbase = ((size_t)blockIdx.x * 4 + w) * 16;
@@ -576,7 +588,9 @@ __global__ __launch_bounds__(256) void gemm_qphi_kernel(const double *Q, size_t 
 // tree in LDS (bitwise reproducible).
 __global__ __launch_bounds__(256) void residual_reduce_kernel(const double *partial, int nchunks,
                                                               int m0p, int m0, double emin,
-                                                              double emax, double *res) {
+                                                              double emax, double *res,
+                                                              const int *skip) {
+  if (skip && *skip) return;  // a converged solve: later loops of a captured solve do nothing
   __shared__ double red[3][256];
   const int j = blockIdx.x, t = threadIdx.x;
   double num = 0.0, na = 0.0, nb = 0.0;
@@ -705,27 +719,88 @@ hipError_t launch_unpack(const double *src, int nc, int b, int bp, int m, int ld
   return hipGetLastError();
 }
 
-hipError_t launch_sum_nodes(const double *P, int Ne, size_t count, double *Q, hipStream_t st) {
+hipError_t launch_sum_nodes(const double *P, int Ne, size_t count, double *Q, hipStream_t st,
+                            const int *skip) {
   hipLaunchKernelGGL(sum_nodes_kernel, dim3(grid_for(count, 256)), dim3(256), 0, st, P, Ne, count,
-                     Q);
+                     Q, skip);
   return hipGetLastError();
 }
 
 hipError_t launch_gemm_qphi(const double *Q, size_t rows, int m0p, int m0, const double *Phi,
-                            double *X, hipStream_t st) {
+                            double *X, hipStream_t st,
+                            const int *skip) {
   if (m0 < 1) return hipErrorInvalidValue;
   const dim3 grid((unsigned)((rows + 63) / 64)), block(256);
   switch (m0p) {
-    case 16: hipLaunchKernelGGL(gemm_qphi_kernel<1>, grid, block, 0, st, Q, rows, m0, Phi, X); break;
-    case 32: hipLaunchKernelGGL(gemm_qphi_kernel<2>, grid, block, 0, st, Q, rows, m0, Phi, X); break;
-    case 48: hipLaunchKernelGGL(gemm_qphi_kernel<3>, grid, block, 0, st, Q, rows, m0, Phi, X); break;
-    case 64: hipLaunchKernelGGL(gemm_qphi_kernel<4>, grid, block, 0, st, Q, rows, m0, Phi, X); break;
-    case 80: hipLaunchKernelGGL(gemm_qphi_kernel<5>, grid, block, 0, st, Q, rows, m0, Phi, X); break;
-    case 96: hipLaunchKernelGGL(gemm_qphi_kernel<6>, grid, block, 0, st, Q, rows, m0, Phi, X); break;
-    case 112: hipLaunchKernelGGL(gemm_qphi_kernel<7>, grid, block, 0, st, Q, rows, m0, Phi, X); break;
-    case 128: hipLaunchKernelGGL(gemm_qphi_kernel<8>, grid, block, 0, st, Q, rows, m0, Phi, X); break;
+    case 16: hipLaunchKernelGGL(gemm_qphi_kernel<1>, grid, block, 0, st, Q, rows, m0, Phi, X, skip); break;
+    case 32: hipLaunchKernelGGL(gemm_qphi_kernel<2>, grid, block, 0, st, Q, rows, m0, Phi, X, skip); break;
+    case 48: hipLaunchKernelGGL(gemm_qphi_kernel<3>, grid, block, 0, st, Q, rows, m0, Phi, X, skip); break;
+    case 64: hipLaunchKernelGGL(gemm_qphi_kernel<4>, grid, block, 0, st, Q, rows, m0, Phi, X, skip); break;
+    case 80: hipLaunchKernelGGL(gemm_qphi_kernel<5>, grid, block, 0, st, Q, rows, m0, Phi, X, skip); break;
+    case 96: hipLaunchKernelGGL(gemm_qphi_kernel<6>, grid, block, 0, st, Q, rows, m0, Phi, X, skip); break;
+    case 112: hipLaunchKernelGGL(gemm_qphi_kernel<7>, grid, block, 0, st, Q, rows, m0, Phi, X, skip); break;
+    case 128: hipLaunchKernelGGL(gemm_qphi_kernel<8>, grid, block, 0, st, Q, rows, m0, Phi, X, skip); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+namespace {
+
+// One loop's convergence decision on the device, in the host loop's order
+// and arithmetic (see launch_converge in kernels.h).
+__global__ void converge_kernel(const double *eps, const double *res, const int *flag, int m0,
+                                double emin, double emax, double gate, double tol, double r,
+                                double drop, int max_loops, DevConv *s) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (s->done) return;
+  const int k = s->k + 1;
+  const int fb = flag[0];
+  s->fallback = fb;
+  s->rr_sweeps += flag[1] + (fb ? flag[2] : 0);
+  int mk = 0;
+  double tk = 0.0, left_min = INFINITY;
+  for (int j = 0; j < m0; ++j) {
+    const double e = eps[j], rj = res[j];
+    const bool in = e >= emin && e <= emax;
+    if (in && rj <= gate) {
+      ++mk;
+      tk += e;
+    } else if (in) {
+      left_min = rj < left_min ? rj : left_min;
+    }
+  }
+  const bool still = left_min < drop * s->prev_left_min;
+  s->prev_left_min = left_min;
+  double trace_rel = s->trace_rel;
+  if (k >= 2) {
+    if (mk == 0 && s->last_count == 0) {
+      trace_rel = 0.0;
+    } else {
+      const double a = fabs(tk), c = mk * r;
+      trace_rel = fabs(tk - s->last_trace) / (a < c ? c : a);
+    }
+  }
+  const bool conv = k >= 2 && mk == s->last_count && trace_rel < tol && !still;
+  if (k <= 64) {
+    s->counts[k - 1] = mk;
+    s->traces[k - 1] = tk;
+  }
+  s->last_trace = tk;
+  s->last_count = mk;
+  s->trace_rel = trace_rel;
+  s->k = k;
+  s->converged = conv ? 1 : 0;
+  s->done = (conv || k >= max_loops) ? 1 : 0;
+}
+
+}  // namespace
+
+hipError_t launch_converge(const double *eps, const double *res, const int *flag, int m0,
+                           double emin, double emax, double gate, double tol, double r,
+                           double drop, int max_loops, DevConv *st_dev, hipStream_t st) {
+  hipLaunchKernelGGL(converge_kernel, dim3(1), dim3(64), 0, st, eps, res, flag, m0, emin, emax,
+                     gate, tol, r, drop, max_loops, st_dev);
   return hipGetLastError();
 }
 
@@ -750,55 +825,55 @@ size_t cell_partial_doubles(int nc, int ld) {
 
 template <int BP>
 hipError_t cell_apply_bp(const double *D, const double *U, int nc, int b, const double *V, int ld,
-                         double *out, hipStream_t st) {
+                         double *out, hipStream_t st, const int *skip) {
   hipLaunchKernelGGL(cell_apply_kernel<BP>, dim3(cell_groups(nc)), dim3(kCellThreads), 0, st, D,
-                     U, nc, b, V, ld, out);
+                     U, nc, b, V, ld, out, skip);
   return hipGetLastError();
 }
 
 hipError_t launch_cell_apply(const Pencil &p, int which, const double *V, int ld, double *out,
-                             hipStream_t st) {
+                             hipStream_t st, const int *skip) {
   const double *D = which ? p.Bd : p.Ad;
   const double *U = which ? p.Bu : p.Au;
   if (ld % 16 != 0 || ld > 128) return hipErrorInvalidValue;
   switch (p.bp) {
-    case 16: return cell_apply_bp<16>(D, U, p.nc, p.b, V, ld, out, st);
-    case 32: return cell_apply_bp<32>(D, U, p.nc, p.b, V, ld, out, st);
-    case 48: return cell_apply_bp<48>(D, U, p.nc, p.b, V, ld, out, st);
-    case 64: return cell_apply_bp<64>(D, U, p.nc, p.b, V, ld, out, st);
+    case 16: return cell_apply_bp<16>(D, U, p.nc, p.b, V, ld, out, st, skip);
+    case 32: return cell_apply_bp<32>(D, U, p.nc, p.b, V, ld, out, st, skip);
+    case 48: return cell_apply_bp<48>(D, U, p.nc, p.b, V, ld, out, st, skip);
+    case 64: return cell_apply_bp<64>(D, U, p.nc, p.b, V, ld, out, st, skip);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <int BP>
 hipError_t cell_project_bp(const Pencil &p, const double *Q, int ld, int m0, double *partial,
-                           double *AQ, double *BQ, hipStream_t st) {
+                           double *AQ, double *BQ, hipStream_t st, const int *skip) {
   const int G = cell_groups(p.nc);
   for (int z = 0; z < 2; ++z) {
     const double *D = z ? p.Bd : p.Ad;
     const double *U = z ? p.Bu : p.Au;
     hipLaunchKernelGGL(cell_project_kernel<BP>, dim3(G), dim3(kCellThreads), 0, st, D, U, p.nc,
-                       p.b, Q, ld, partial);
+                       p.b, Q, ld, partial, skip);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     hipLaunchKernelGGL(cell_project_reduce_kernel, dim3((m0 * m0 + 63) / 64), dim3(256), 0, st,
-                       (const double *)partial, G, ld, m0, z ? BQ : AQ);
+                       (const double *)partial, G, ld, m0, z ? BQ : AQ, skip);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     hipLaunchKernelGGL(symmetrize_kernel, dim3((m0 * m0 + 255) / 256), dim3(256), 0, st,
-                       z ? BQ : AQ, m0);
+                       z ? BQ : AQ, m0, skip);
     if ((err = hipGetLastError()) != hipSuccess) return err;
   }
   return hipSuccess;
 }
 
 hipError_t launch_cell_project(const Pencil &p, const double *Q, int ld, int m0, double *partial,
-                               double *AQ, double *BQ, hipStream_t st) {
+                               double *AQ, double *BQ, hipStream_t st, const int *skip) {
   if (ld % 16 != 0 || ld > 128) return hipErrorInvalidValue;
   switch (p.bp) {
-    case 16: return cell_project_bp<16>(p, Q, ld, m0, partial, AQ, BQ, st);
-    case 32: return cell_project_bp<32>(p, Q, ld, m0, partial, AQ, BQ, st);
-    case 48: return cell_project_bp<48>(p, Q, ld, m0, partial, AQ, BQ, st);
-    case 64: return cell_project_bp<64>(p, Q, ld, m0, partial, AQ, BQ, st);
+    case 16: return cell_project_bp<16>(p, Q, ld, m0, partial, AQ, BQ, st, skip);
+    case 32: return cell_project_bp<32>(p, Q, ld, m0, partial, AQ, BQ, st, skip);
+    case 48: return cell_project_bp<48>(p, Q, ld, m0, partial, AQ, BQ, st, skip);
+    case 64: return cell_project_bp<64>(p, Q, ld, m0, partial, AQ, BQ, st, skip);
     default: return hipErrorInvalidValue;
   }
 }
@@ -806,26 +881,26 @@ hipError_t launch_cell_project(const Pencil &p, const double *Q, int ld, int m0,
 template <int BP>
 hipError_t cell_residual_bp(const Pencil &p, const double *X, int ld, const double *lam, int m0,
                             double emin, double emax, double *partial, double *res,
-                            hipStream_t st) {
+                            hipStream_t st, const int *skip) {
   const int G = cell_groups(p.nc);
   hipLaunchKernelGGL(cell_residual_kernel<BP>, dim3(G), dim3(kCellThreads), 0, st, p.Ad, p.Au,
-                     p.Bd, p.Bu, p.nc, p.b, X, ld, lam, m0, partial);
+                     p.Bd, p.Bu, p.nc, p.b, X, ld, lam, m0, partial, skip);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(residual_reduce_kernel, dim3(m0), dim3(256), 0, st,
-                     (const double *)partial, G, ld, m0, emin, emax, res);
+                     (const double *)partial, G, ld, m0, emin, emax, res, skip);
   return hipGetLastError();
 }
 
 hipError_t launch_cell_residuals(const Pencil &p, const double *X, int ld, const double *lam,
                                  int m0, double emin, double emax, double *partial, double *res,
-                                 hipStream_t st) {
+                                 hipStream_t st, const int *skip) {
   if (ld % 16 != 0 || ld > 128) return hipErrorInvalidValue;
   switch (p.bp) {
-    case 16: return cell_residual_bp<16>(p, X, ld, lam, m0, emin, emax, partial, res, st);
-    case 32: return cell_residual_bp<32>(p, X, ld, lam, m0, emin, emax, partial, res, st);
-    case 48: return cell_residual_bp<48>(p, X, ld, lam, m0, emin, emax, partial, res, st);
-    case 64: return cell_residual_bp<64>(p, X, ld, lam, m0, emin, emax, partial, res, st);
+    case 16: return cell_residual_bp<16>(p, X, ld, lam, m0, emin, emax, partial, res, st, skip);
+    case 32: return cell_residual_bp<32>(p, X, ld, lam, m0, emin, emax, partial, res, st, skip);
+    case 48: return cell_residual_bp<48>(p, X, ld, lam, m0, emin, emax, partial, res, st, skip);
+    case 64: return cell_residual_bp<64>(p, X, ld, lam, m0, emin, emax, partial, res, st, skip);
     default: return hipErrorInvalidValue;
   }
 }

@@ -43,7 +43,8 @@ enum Slot {
   S_SINV32, S_W32, S_WT32, S_G32, S_TV32, S_XC, S_RC, S_RPART, S_WORST,
   // Hermitian variant
   S_HSINV, S_HW, S_HV, S_HG, S_HY, S_HR, S_HQ, S_HX, S_HAX, S_HBX, S_HPART, S_HAQ, S_HBQ,
-  S_HEA, S_HEB, S_HEPS2, S_HPHI2, S_HEPS, S_HPHI, S_HRES, S_HCOEF, S_HAD, S_HAU, S_COUNT
+  S_HEA, S_HEB, S_HEPS2, S_HPHI2, S_HEPS, S_HPHI, S_HRES, S_HCOEF, S_HAD, S_HAU,
+  S_CONV, S_COUNT
 };
 
 }  // namespace
@@ -803,7 +804,7 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
     feast_default_opts(&og);
     if (opts) og = *opts;
     if (!(og.tol > 0.0) || og.max_loops < 1 || og.precision != 0 || og.partitions < 0 ||
-        og.graph < 0 || og.graph > 1)
+        og.graph < 0 || og.graph > 2)
       return -7;
     return solve_generic_real(ctx, AB, emin, emax, M0, Ne, og, lambda, X, res, info);
   }
@@ -817,7 +818,7 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
   feast_default_opts(&o);
   if (opts) o = *opts;
   if (!(o.tol > 0.0) || o.max_loops < 1 || o.precision < 0 || o.precision > 2 ||
-      o.partitions < 0 || o.graph < 0 || o.graph > 1)
+      o.partitions < 0 || o.graph < 0 || o.graph > 2 || (o.graph == 2 && o.max_loops > 64))
     return -7;
   HIPCHK(hipSetDevice(ctx->device));
   hipStream_t sm = ctx->stream;
@@ -903,7 +904,75 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
       return e;
     return hipMemcpyAsync(y, x, rows * mp * sizeof(double), hipMemcpyDeviceToDevice, sm);
   };
-  for (int k = 1; k <= o.max_loops; ++k) {
+  // graph = 2: the convergence decision on the device (launch_converge); the
+  // loops are captured kChunk at a time into one graph whose kernels return at
+  // once after convergence, and the host reads the decision once per chunk.
+  // Y and X alternate between the two buffers (odd loops read y, write x).
+  const bool dev_graph = o.graph == 2 && o.precision == 0;
+  if (dev_graph) {
+    constexpr int kChunk = 4;
+    DevConv *cs_dev;
+    HIPCHK(ensure_t(ctx, S_CONV, 1, &cs_dev));
+    DevConv h{};
+    h.trace_rel = INFINITY;
+    h.prev_left_min = INFINITY;
+    HIPCHK(hipMemcpyAsync(cs_dev, &h, sizeof(h), hipMemcpyHostToDevice, sm));
+    HIPCHK(hipStreamSynchronize(sm));
+    HIPCHK(reduced_eig_set_lds());
+    const int *skip = &cs_dev->done;
+    auto chunk = [&](hipStream_t cs) -> hipError_t {
+      hipError_t e;
+      for (int i = 0; i < kChunk; ++i) {
+        const double *in = (i % 2 == 0) ? y : x;
+        double *out = (i % 2 == 0) ? x : y;
+        if ((e = launch_cell_apply(p, 1, in, mp, rr, cs, skip)) != hipSuccess) return e;
+        if ((e = launch_sweeps(p, s, Ne, wk.f, wk.sb, rr, mp, pp, 1, cs, skip)) != hipSuccess)
+          return e;
+        if ((e = launch_sweeps(p, s, Ne, wk.f, wk.sb, rr, mp, pp, 2, cs, skip)) != hipSuccess)
+          return e;
+        if ((e = launch_sum_nodes(pp, Ne, rows * mp, q, cs, skip)) != hipSuccess) return e;
+        if ((e = launch_cell_project(p, q, mp, M0, gp, aq, bq, cs, skip)) != hipSuccess) return e;
+        if ((e = launch_reduced_eig(aq, bq, M0, eps, phi, scr, flag, cs, skip)) != hipSuccess)
+          return e;
+        if ((e = launch_gemm_qphi(q, rows, mp, M0, phi, out, cs, skip)) != hipSuccess) return e;
+        if ((e = launch_cell_residuals(p, out, mp, eps, M0, emin, emax, resp, resi, cs, skip)) !=
+            hipSuccess)
+          return e;
+        if ((e = launch_converge(eps, resi, flag, M0, emin, emax, res_gate, o.tol, r,
+                                 kUncountedDrop, o.max_loops, cs_dev, cs)) != hipSuccess)
+          return e;
+      }
+      return hipSuccess;
+    };
+    if (!ctx->capture)  // default priority
+      HIPCHK(hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
+    HIPCHK(gx.capture(ctx->capture, chunk));
+    for (int launched = 0;;) {
+      HIPCHK(hipGraphLaunch(gx.exec, sm));
+      launched += kChunk;
+      HIPCHK(hipMemcpyAsync(&h, cs_dev, sizeof(h), hipMemcpyDeviceToHost, sm));
+      HIPCHK(hipStreamSynchronize(sm));
+      if (h.done || launched >= o.max_loops) break;
+    }
+    for (int i = 0; i < h.k && i < 64; ++i) {
+      traces.push_back(h.traces[i]);
+      counts.push_back(h.counts[i]);
+      if (o.verbose)
+        std::fprintf(stderr, "feast (device decision): loop %d  M %d  trace %.17g\n", i + 1,
+                     h.counts[i], h.traces[i]);
+    }
+    converged = h.converged != 0;
+    fallback = h.fallback;
+    rr_sweeps = h.rr_sweeps;
+    trace_rel = h.trace_rel;
+    if (h.k % 2 == 0) std::swap(x, y);  // the last loop wrote y
+    HIPCHK(hipMemcpyAsync(h_eps, eps, M0 * sizeof(double), hipMemcpyDeviceToHost, sm));
+    HIPCHK(hipMemcpyAsync(h_res, resi, M0 * sizeof(double), hipMemcpyDeviceToHost, sm));
+    HIPCHK(hipStreamSynchronize(sm));
+    for (int j = 0; j < M0; ++j)
+      is_counted[j] = h_eps[j] >= emin && h_eps[j] <= emax && h_res[j] <= res_gate;
+  }
+  for (int k = 1; k <= o.max_loops && !dev_graph; ++k) {
     if (use_graph && k >= 2) {
       if (!ctx->capture)  // default priority
         HIPCHK(hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));

@@ -67,9 +67,12 @@ struct SolveBufs {
   double *TV;   // [Ne][ntiles][2][2][bp][8]: twist vectors (h_{m-1}, c)
 };
 // part: 1 = forward sweep only, 2 = back sweep only, 3 = both.
+// skip (here and in the launchers below): NULL, or a device flag that the
+// kernels read first; non-zero makes them return at once (the loops of a
+// captured solve after convergence).
 hipError_t launch_sweeps(const Pencil &p, const Shifts &s, int Ne, const Factors &f,
                          const SolveBufs &sb, const double *R, int m0p, double *P, int part,
-                         hipStream_t st);
+                         hipStream_t st, const int *skip = nullptr);
 // The sweeps of the wide factorisation (launch_factor_wide): Xim == nullptr:
 // P[e] = Re(kappa_e x_e) (padded, per node); else the complex solution of
 // node 0 in P (real plane) and Xim.  sb.G as for launch_sweeps, sb.TV unused.
@@ -113,9 +116,10 @@ hipError_t launch_pack(const double *src, int nc, int b, int bp, int m, int ldd,
 hipError_t launch_unpack(const double *src, int nc, int b, int bp, int m, int lds,
                          const int *perm, double *dst, hipStream_t st);
 hipError_t launch_sum_nodes(const double *P, int Ne, size_t count, double *Q,
-                            hipStream_t st);
+                            hipStream_t st, const int *skip = nullptr);
 hipError_t launch_gemm_qphi(const double *Q, size_t rows, int m0p, int m0,
-                            const double *Phi, double *X, hipStream_t st);
+                            const double *Phi, double *X, hipStream_t st,
+                            const int *skip = nullptr);
 hipError_t launch_check_finite(const double *x, size_t count, int *flag, hipStream_t st);
 hipError_t launch_gather(const double *src, const int *perm, int m, double *dst,
                          hipStream_t st);
@@ -125,12 +129,13 @@ hipError_t launch_gather(const double *src, const int *perm, int m, double *dst,
 // also covers the 3 ld per group of the residual variant.
 size_t cell_partial_doubles(int nc, int ld);
 hipError_t launch_cell_apply(const Pencil &p, int which, const double *V, int ld, double *out,
-                             hipStream_t st);
+                             hipStream_t st, const int *skip = nullptr);
 hipError_t launch_cell_project(const Pencil &p, const double *Q, int ld, int m0, double *partial,
-                               double *AQ, double *BQ, hipStream_t st);
+                               double *AQ, double *BQ, hipStream_t st,
+                               const int *skip = nullptr);
 hipError_t launch_cell_residuals(const Pencil &p, const double *X, int ld, const double *lam,
                                  int m0, double emin, double emax, double *partial, double *res,
-                                 hipStream_t st);
+                                 hipStream_t st, const int *skip = nullptr);
 
 // Float64 residuals of the shifted systems for the mixed-precision solves:
 // Rout_e = R - (Z_e B - A) x_e for every node (X and Rout: node e's real
@@ -156,7 +161,34 @@ size_t reduced_eig_scratch_doubles();
 // point; called once per context at initialisation.
 hipError_t reduced_eig_static_scratch(double **ptr, int **flag);
 hipError_t launch_reduced_eig(const double *AQ, const double *BQ, int n, double *eps,
-                              double *Phi, double *scratch, int *flag, hipStream_t st);
+                              double *Phi, double *scratch, int *flag, hipStream_t st,
+                              const int *skip = nullptr);
+// Sets the reduced eigensolver's LDS limit (launch_reduced_eig does it
+// itself, except while its stream is being captured).
+hipError_t reduced_eig_set_lds();
+
+// Convergence of one loop on the device (same decisions, in the same
+// arithmetic, as the host loop of feast_solve): counts the in-interval pairs
+// with residual <= gate, sums their Ritz values in index order, applies the
+// trace test and the uncounted-pair wait, appends to the history in st and
+// sets st->done once the solve has converged or reached max_loops.  Does
+// nothing once done is set.  One thread.
+struct DevConv {
+  int k;            // loops done
+  int done;         // converged or out of loops: later loop kernels skip
+  int converged;
+  int fallback;     // the last loop's B_Q fallback flag
+  int rr_sweeps;    // Jacobi sweeps, all loops
+  int counts[64];   // M_k (first 64 loops)
+  double traces[64];
+  double trace_rel;
+  double prev_left_min;
+  double last_trace;
+  int last_count;
+};
+hipError_t launch_converge(const double *eps, const double *res, const int *flag, int m0,
+                           double emin, double emax, double gate, double tol, double r,
+                           double drop, int max_loops, DevConv *st_dev, hipStream_t st);
 
 
 // Learned warm start (warm.hip).  bfloat16 values are stored as uint16_t.

@@ -358,7 +358,9 @@ __device__ __forceinline__ void wg_gemm(int nt, double *stage, FA a, FB b, FO ou
 
 __global__ __launch_bounds__(kThreads) void reduced_eig_kernel(const double *AQ, const double *BQ,
                                                                int n, double *eps, double *Phi,
-                                                               double *scratch, int *flag) {
+                                                               double *scratch, int *flag,
+                                                               const int *skip) {
+  if (skip && *skip) return;  // a converged solve: later loops of a captured solve do nothing
   extern __shared__ __align__(16) double C[];  // nn x (nn + 1) matrix, or nn x kVTld VT
   __shared__ RRShared sh;
   const int tid = threadIdx.x;
@@ -619,7 +621,9 @@ __global__ __launch_bounds__(kThreads) void reduced_eig_kernel(const double *AQ,
 
 // Phi[:, rank[c]] = T V[:, c] with T (nn x nn, row-major) of workgroup 0 and
 // VT[c * nn + r] = V[r][c]: one wave per 16 x 16 output tile.
-__global__ __launch_bounds__(64) void phi_kernel(const double *scratch, int n, double *Phi) {
+__global__ __launch_bounds__(64) void phi_kernel(const double *scratch, int n, double *Phi,
+                                                 const int *skip) {
+  if (skip && *skip) return;  // a converged solve: later loops of a captured solve do nothing
   const int nn = n + (n & 1);
   const int nt = (nn + 15) / 16;
   const double *T = scratch;
@@ -674,17 +678,26 @@ hipError_t reduced_eig_static_scratch(double **ptr, int **flag) {
   return hipSuccess;
 }
 
+// LDS of the reduced eigensolver for size m: the matrix or the eigenvector
+// transpose, or the products' staging area
+size_t reduced_eig_lds_bytes(int m) {
+  const int mm = m + (m & 1);
+  size_t d = (size_t)mm * (kVTld > mm + 1 ? kVTld : mm + 1);
+  if (d < (size_t)kStageDoubles) d = kStageDoubles;
+  return d * sizeof(double);
+}
+
+hipError_t reduced_eig_set_lds() {
+  return hipFuncSetAttribute((const void *)reduced_eig_kernel,
+                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)reduced_eig_lds_bytes(kMaxN));
+}
+
 hipError_t launch_reduced_eig(const double *AQ, const double *BQ, int n, double *eps, double *Phi,
-                              double *scratch, int *flag, hipStream_t st) {
+                              double *scratch, int *flag, hipStream_t st, const int *skip) {
   if (n < 1 || n > kMaxN) return hipErrorInvalidValue;
-  auto lds_bytes = [](int m) {
-    const int mm = m + (m & 1);
-    size_t d = (size_t)mm * (kVTld > mm + 1 ? kVTld : mm + 1);
-    if (d < (size_t)kStageDoubles) d = kStageDoubles;  // the products' staging area
-    return d * sizeof(double);
-  };
   const int nn = n + (n & 1);
-  const size_t shm = lds_bytes(n);
+  const size_t shm = reduced_eig_lds_bytes(n);
   // the limit is set for the largest n (so calls of any size, from any
   // thread, agree on it), and not while the stream is being captured into a
   // graph: a captured loop always follows an eager call on the device
@@ -692,16 +705,15 @@ hipError_t launch_reduced_eig(const double *AQ, const double *BQ, int n, double 
   hipError_t err = hipStreamIsCapturing(st, &cs);
   if (err != hipSuccess) return err;
   if (cs == hipStreamCaptureStatusNone) {
-    err = hipFuncSetAttribute((const void *)reduced_eig_kernel,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes(kMaxN));
+    err = reduced_eig_set_lds();
     if (err != hipSuccess) return err;
   }
   hipLaunchKernelGGL(reduced_eig_kernel, dim3(kSplit), dim3(kThreads), shm, st, AQ, BQ, n, eps, Phi,
-                     scratch, flag);
+                     scratch, flag, skip);
   err = hipGetLastError();
   if (err != hipSuccess) return err;
   const int nt = (nn + 15) / 16;
-  hipLaunchKernelGGL(phi_kernel, dim3(nt, nt), dim3(64), 0, st, scratch, n, Phi);
+  hipLaunchKernelGGL(phi_kernel, dim3(nt, nt), dim3(64), 0, st, scratch, n, Phi, skip);
   return hipGetLastError();
 }
 

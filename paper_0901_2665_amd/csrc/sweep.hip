@@ -185,6 +185,7 @@ struct SweepArgs {
   double *Xim;       // complex variant only
   int m0p, ntiles;
   double kre[kMaxNe], kim[kMaxNe];
+  const int *skip;   // non-zero: a converged solve, the kernels do nothing
 };
 
 // Forward sweep.  The workgroup has two wave sets of BP/16 waves each: the
@@ -197,6 +198,7 @@ struct SweepArgs {
 // step ahead never cover the loads just issued.
 template <int BP>
 __global__ __launch_bounds__(BP * 8) void forward_kernel(SweepArgs a) {
+  if (a.skip && *a.skip) return;
   __shared__ VecLds<BP> s;
   constexpr int NW = BP / 16;
   const int item = xcd_item(blockIdx.x, gridDim.x, a.ntiles);
@@ -279,6 +281,7 @@ __global__ __launch_bounds__(BP * 8) void forward_kernel(SweepArgs a) {
 // cell, so that x_c = g_c + W_c v accumulates onto g_c.
 template <int BP, bool COMPLEX_OUT>
 __global__ __launch_bounds__(BP * 4) void back_kernel(SweepArgs a) {
+  if (a.skip && *a.skip) return;
   __shared__ VecLds<BP> s;
   const int item = xcd_item(blockIdx.x, gridDim.x, a.ntiles);
   const int tau = item % a.ntiles;
@@ -754,9 +757,9 @@ hipError_t dispatch(SweepArgs &a, int Ne, bool complex_out, int part, hipStream_
 
 hipError_t launch_sweeps(const Pencil &p, const Shifts &s, int Ne, const Factors &f,
                          const SolveBufs &sb, const double *R, int m0p, double *P, int part,
-                         hipStream_t st) {
+                         hipStream_t st, const int *skip) {
   SweepArgs a;
-  a.p = p; a.f = f; a.sb = sb; a.R = R; a.P = P; a.Xim = nullptr;
+  a.p = p; a.f = f; a.sb = sb; a.R = R; a.P = P; a.Xim = nullptr; a.skip = skip;
   a.m0p = m0p; a.ntiles = m0p / kTile;
   for (int e = 0; e < kMaxNe; ++e) { a.kre[e] = s.kre[e]; a.kim[e] = s.kim[e]; }
   return dispatch(a, Ne, false, part, st);
@@ -784,7 +787,7 @@ hipError_t launch_sweeps_wide(const Pencil &p, const Shifts &s, int Ne, const Fa
                               double *Xim, int part, hipStream_t st) {
   if (p.bp != kWideBP) return hipErrorInvalidValue;
   SweepArgs a;
-  a.p = p; a.f = f; a.sb = sb; a.R = R; a.P = P; a.Xim = Xim;
+  a.p = p; a.f = f; a.sb = sb; a.R = R; a.P = P; a.Xim = Xim; a.skip = nullptr;
   a.m0p = m0p; a.ntiles = m0p / kTile;
   for (int e = 0; e < kMaxNe; ++e) { a.kre[e] = s.kre[e]; a.kim[e] = s.kim[e]; }
   return launch_wide(a, Ne, Xim != nullptr, part, st);
@@ -794,7 +797,7 @@ hipError_t launch_sweeps_complex(const Pencil &p, const Shifts &s, const Factors
                                  const SolveBufs &sb, const double *R, int m0p,
                                  double *Xre, double *Xim, hipStream_t st) {
   SweepArgs a;
-  a.p = p; a.f = f; a.sb = sb; a.R = R; a.P = Xre; a.Xim = Xim;
+  a.p = p; a.f = f; a.sb = sb; a.R = R; a.P = Xre; a.Xim = Xim; a.skip = nullptr;
   a.m0p = m0p; a.ntiles = m0p / kTile;
   for (int e = 0; e < kMaxNe; ++e) { a.kre[e] = s.kre[e]; a.kim[e] = s.kim[e]; }
   return dispatch(a, 1, true, 3, st);

@@ -89,5 +89,58 @@ def test_graph_bad_option(ctx, torch):
     p = W.dense_random_pencil(3, 8, 9)
     Y0 = dev(torch, W.random_subspace(p.n, 4, 3))
     with pytest.raises(F.FeastError) as e:
-        ctx.solve(gpencil(p), 0.0, 1.0, 4, 8, Y0, graph=2)
+        ctx.solve(gpencil(p), 0.0, 1.0, 4, 8, Y0, graph=3)
     assert e.value.status == -7
+    with pytest.raises(F.FeastError) as e:   # graph 2 keeps a history of 64 loops
+        ctx.solve(gpencil(p), 0.0, 1.0, 4, 8, Y0, graph=2, max_loops=65)
+    assert e.value.status == -7
+
+
+# graph = 2: the convergence decision on the device, the loops captured four
+# at a time with kernels that return at once after convergence; same
+# kernels, same data, same order and the same decisions as the eager loop,
+# so every output must be bitwise equal to it
+def test_device_graph_equals_eager(ctx, torch):
+    p, emin, emax, m0, ne, Y0 = W.make_workload("chain800")
+    gp, y = gpencil(p), dev(torch, Y0)
+    eager = ctx.solve(gp, emin, emax, m0, ne, y)
+    g = ctx.solve(gp, emin, emax, m0, ne, y, graph=2)
+    same(g, eager)
+    assert g.trace_rel == eager.trace_rel
+    check_against_oracle(g, O.feast(p, emin, emax, m0, ne, Y0), p, emin, emax)
+
+
+@pytest.mark.parametrize("max_loops", [3, 4, 5, 9])
+def test_device_graph_chunks(ctx, torch, max_loops):
+    # tol = 1e-20: the trace test passes only on equal traces, here in loop 5;
+    # below that the solve stops at max_loops (status 1) inside or at the end
+    # of the first graph launch, else it converges in the second launch; the
+    # final Ritz vectors come from y or x by the parity of the loop count
+    p = W.dense_random_pencil(7, 16, 6)
+    lam = O.bruteforce(p)[0]
+    emin, emax = 0.5 * (lam[29] + lam[30]), 0.5 * (lam[39] + lam[40])
+    Y0 = dev(torch, W.random_subspace(p.n, 18, 106))
+    gp = gpencil(p)
+    kw = dict(tol=1e-20, max_loops=max_loops)
+    eager = ctx.solve(gp, emin, emax, 18, 8, Y0, **kw)
+    assert eager.loops == min(max_loops, 5)
+    assert eager.status == (1 if max_loops < 5 else 0)
+    same(ctx.solve(gp, emin, emax, 18, 8, Y0, graph=2, **kw), eager)
+
+
+def test_device_graph_batched_and_tb6400(ctx, torch):
+    probs = []
+    for seed, (nc, b, k0, m) in enumerate([(6, 8, 10, 12), (11, 20, 60, 15), (4, 5, 5, 6)]):
+        p = W.dense_random_pencil(nc, b, seed + 1)
+        lam = O.bruteforce(p)[0]
+        emin, emax = 0.5 * (lam[k0 - 1] + lam[k0]), 0.5 * (lam[k0 + m - 1] + lam[k0 + m])
+        m0 = min(m + 6, p.n)
+        probs.append((gpencil(p), emin, emax, m0, 8,
+                      dev(torch, W.random_subspace(p.n, m0, seed + 50))))
+    st, rs = ctx.solve_batched(probs, tol=1e-13, max_loops=40, workers=3, graph=2)
+    assert st in (0, 2)
+    for pr, r in zip(probs, rs):
+        same(r, ctx.solve(*pr, tol=1e-13, max_loops=40, partitions=1))
+    p, emin, emax, m0, ne, Y0 = W.make_workload("tb6400")
+    gp, y = gpencil(p), dev(torch, Y0)
+    same(ctx.solve(gp, emin, emax, m0, ne, y, graph=2), ctx.solve(gp, emin, emax, m0, ne, y))

@@ -427,6 +427,8 @@ def main():
     line.update({"higher_is_better": True, "scaling": "weak", "vs_baseline": None,
                  "dtype": leg.pop("dtype"), "data": "synthetic"})
     line.update(leg)
+    print(f"bench: {args.workload} leg done ({line['value']:.2f} {line['unit']})", file=sys.stderr,
+          flush=True)
     if args.workload == "tb128k" and args.precision == 0 and not args.no_extra:
         # the scope table's next rows on the same box, same run: mixed precision
         # on the same workload, and the batched uneven problems
@@ -436,11 +438,16 @@ def main():
             mixed["cpu_baseline"] = dict(line["cpu_baseline"], extrapolated=True,
                                          note="the float64 oracle of the headline line")
         line["mixed"] = mixed
+        print(f"bench: mixed leg done ({mixed['value']:.2f} solves/s)", file=sys.stderr, flush=True)
         # labelled experiment: float32 solves in the first loop only, float64 after
         adaptive = solve_leg(ctx, "tb128k", 2, 2, 1, cpu=False)
         adaptive["vs_float64"] = adaptive["value"] / line["value"]
         line["adaptive"] = adaptive
-        line["batched"] = batch_leg(ctx, 256, 0, 2, 1, workers=args.workers, cpu=cpu,
+        print(f"bench: adaptive leg done ({adaptive['value']:.2f} solves/s)", file=sys.stderr,
+              flush=True)
+        # two warm-up steps: every worker's workspace reaches the largest
+        # problem it meets before the timed steps
+        line["batched"] = batch_leg(ctx, 256, 0, 2, 2, workers=args.workers, cpu=cpu,
                                     workload="tbbatch256")
     ctx.close()
     print(json.dumps(line), flush=True)

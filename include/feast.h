@@ -78,14 +78,11 @@ typedef struct {
   int32_t nc;            /* number of cells, >= 1 */
   int32_t b;             /* block size, 1..64; feast_solve,
                             feast_solve_batched and feast_shifted_solve also
-                            take 65..96: the shifted systems of such pencils
-                            run on the wide kernels (blocks padded to 96,
-                            one top-down chain per contour point, no twist
-                            and no partitions), the projection and the
-                            residuals on the generic kernels of the Hermitian
-                            variant in real mode (A widened to complex; Q,
-                            the reduced problem and X real), with M0 <= 64
-                            (feast_shifted_solve: m <= 128) and precision 0 */
+                            take 65..96: such pencils run on the wide kernels
+                            (blocks padded to 96; one top-down chain per
+                            contour point, no twist and no partitions; B*Y,
+                            the projection and the residuals from the same
+                            repacked blocks), precision 0 only */
   const double *A_diag;  /* [nc][b][b] */
   const double *A_up;    /* [nc-1][b][b] (may be NULL when nc == 1) */
   const double *B_diag;  /* [nc][b][b] */

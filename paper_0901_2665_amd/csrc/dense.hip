@@ -620,6 +620,95 @@ __global__ __launch_bounds__(256) void residual_reduce_kernel(const double *part
   }
 }
 
+// ---- blocks of 64 < b <= 96: products with the packed planes of the wide
+// factorisation (layout fpos, see factor.hip) ----
+//
+// Tile (row block w, column tile tj) of (T V)_c for T = A (which = 0) or B (1):
+//   D_c V_c + U_c V_{c+1} + U_{c-1}^T V_{c-1},
+// the matrix operands as fragments of the packed planes (D_c symmetric: its
+// own plane; U_c: the plane of U_c^T; U_{c-1}^T: the plane of U_{c-1}), the
+// vector operand V[k][tj*16 + lane%16] from memory (V padded [nc][96][ld]).
+constexpr int kWideB = 96;
+
+__device__ __forceinline__ d4 wide_tile(const WidePack &pk, int which, int nc, int c, int w,
+                                        int tj, const double *V, int ld) {
+  constexpr int KS = kWideB / 4;
+  const size_t per = (size_t)kWideB * kWideB;
+  const int l = lane_id(), kl = l >> 4, n = l & 15;
+  d4 a0 = d4zero(), a1 = d4zero(), a2 = d4zero();
+  double f[KS];
+  frag_plane_load<kWideB>(f, pk.dia + ((size_t)c * 2 + which) * per, w, true);
+  const double *v0 = V + (size_t)c * kWideB * ld + tj * 16 + n;
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) a0 = mfma(f[ks], v0[(size_t)(4 * ks + kl) * ld], a0);
+  if (c + 1 < nc) {
+    frag_plane_load<kWideB>(f, pk.cplt + ((size_t)c * 2 + which) * per, w, true);
+    const double *v1 = v0 + (size_t)kWideB * ld;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) a1 = mfma(f[ks], v1[(size_t)(4 * ks + kl) * ld], a1);
+  }
+  if (c > 0) {
+    frag_plane_load<kWideB>(f, pk.cpl + ((size_t)(c - 1) * 2 + which) * per, w, true);
+    const double *vm = v0 - (size_t)kWideB * ld;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) a2 = mfma(f[ks], vm[(size_t)(4 * ks + kl) * ld], a2);
+  }
+  return (a0 + a1) + a2;
+}
+
+// out = T V; one workgroup of six waves per (cell, 16-column tile)
+__global__ __launch_bounds__(384) void wide_apply_kernel(WidePack pk, int which, int nc,
+                                                         const double *V, int ld, double *out,
+                                                         const int *skip) {
+  if (skip && *skip) return;
+  const int c = blockIdx.x, tj = blockIdx.y, w = wave_id(), l = lane_id();
+  const d4 acc = wide_tile(pk, which, nc, c, w, tj, V, ld);
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    out[((size_t)c * kWideB + w * 16 + acc_row(l, r)) * ld + tj * 16 + acc_col(l)] = acc[r];
+}
+
+// partial[c][3][ld]: per column j < m0 of cell c, the sums of |A x - lam_j B x|,
+// |A x| and |B x| over the cell's rows (fixed order: rows within a lane,
+// then the four lanes of a column, then the six row blocks)
+__global__ __launch_bounds__(384) void wide_residual_kernel(WidePack pk, int nc, const double *X,
+                                                            int ld, const double *lam, int m0,
+                                                            double *partial, const int *skip) {
+  if (skip && *skip) return;
+  __shared__ double red[3][6][16];
+  const int c = blockIdx.x, tj = blockIdx.y, w = wave_id(), l = lane_id();
+  const d4 ax = wide_tile(pk, 0, nc, c, w, tj, X, ld);
+  const d4 bx = wide_tile(pk, 1, nc, c, w, tj, X, ld);
+  const int j = tj * 16 + acc_col(l);
+  const double lj = j < m0 ? lam[j] : 0.0;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    s0 += fabs(ax[r] - lj * bx[r]);
+    s1 += fabs(ax[r]);
+    s2 += fabs(bx[r]);
+  }
+  // lanes n, n+16, n+32, n+48 hold the same column
+  s0 += __shfl_xor(s0, 16);
+  s1 += __shfl_xor(s1, 16);
+  s2 += __shfl_xor(s2, 16);
+  s0 += __shfl_xor(s0, 32);
+  s1 += __shfl_xor(s1, 32);
+  s2 += __shfl_xor(s2, 32);
+  if (l < 16) {
+    red[0][w][l] = s0;
+    red[1][w][l] = s1;
+    red[2][w][l] = s2;
+  }
+  __syncthreads();
+  if (threadIdx.x < 48) {
+    const int q = threadIdx.x / 16, n = threadIdx.x % 16;
+    double s = 0.0;
+    for (int ww = 0; ww < 6; ++ww) s += red[q][ww][n];
+    partial[((size_t)c * 3 + q) * ld + tj * 16 + n] = s;
+  }
+}
+
 __global__ void check_finite_kernel(const double *x, size_t count, int *flag) {
   int bad = 0;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count;
@@ -802,6 +891,48 @@ hipError_t launch_converge(const double *eps, const double *res, const int *flag
   hipLaunchKernelGGL(converge_kernel, dim3(1), dim3(64), 0, st, eps, res, flag, m0, emin, emax,
                      gate, tol, r, drop, max_loops, st_dev);
   return hipGetLastError();
+}
+
+hipError_t launch_wide_apply(const Pencil &p, const WidePack &pk, int which, const double *V,
+                             int ld, double *out, hipStream_t st, const int *skip) {
+  if (p.bp != kWideB || ld % 16 != 0 || ld > 128) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(wide_apply_kernel, dim3(p.nc, ld / 16), dim3(384), 0, st, pk, which, p.nc, V,
+                     ld, out, skip);
+  return hipGetLastError();
+}
+
+size_t wide_residual_partial_doubles(int nc, int ld) { return (size_t)nc * 3 * ld; }
+
+hipError_t launch_wide_residuals(const Pencil &p, const WidePack &pk, const double *X, int ld,
+                                 const double *lam, int m0, double emin, double emax,
+                                 double *partial, double *res, hipStream_t st, const int *skip) {
+  if (p.bp != kWideB || ld % 16 != 0 || ld > 128) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(wide_residual_kernel, dim3(p.nc, ld / 16), dim3(384), 0, st, pk, p.nc, X, ld,
+                     lam, m0, partial, skip);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(residual_reduce_kernel, dim3(m0), dim3(256), 0, st, (const double *)partial,
+                     p.nc, ld, m0, emin, emax, res, skip);
+  return hipGetLastError();
+}
+
+// A_Q = Q^T (A Q), B_Q = Q^T (B Q), each symmetrised: the wide products into
+// tmp, the cross Gram products (warm.hip) over all padded rows.
+hipError_t launch_wide_project(const Pencil &p, const WidePack &pk, const double *Q, int ld,
+                               int m0, double *tmp, double *partial, double *AQ, double *BQ,
+                               hipStream_t st, const int *skip) {
+  const long long rows = (long long)p.nc * kWideB;
+  for (int z = 0; z < 2; ++z) {
+    hipError_t err = launch_wide_apply(p, pk, z, Q, ld, tmp, st, skip);
+    if (err != hipSuccess) return err;
+    double *M = z ? BQ : AQ;
+    if ((err = launch_cross_gram(Q, ld, tmp, ld, rows, m0, m0, partial, M, st)) != hipSuccess)
+      return err;
+    hipLaunchKernelGGL(symmetrize_kernel, dim3((m0 * m0 + 255) / 256), dim3(256), 0, st, M, m0,
+                       skip);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_check_finite(const double *x, size_t count, int *flag, hipStream_t st) {

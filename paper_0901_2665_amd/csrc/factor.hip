@@ -820,24 +820,25 @@ constexpr int kWideBP = 96;
 constexpr int kWideWaves = kWideBP / 16;
 constexpr int kWideThreads = 64 * kWideWaves;
 
-// Couplings Au, Bu (caller layout, b x b) -> [nc-1][2][BP][BP] and diagonal
-// blocks Ad, Bd -> [nc][2][BP][BP], in the layout fpos.  Padding: zero, but
-// -1 in A on the diagonal of a diagonal block (so that Z B - A holds the
-// identity there).
-__global__ void pack_wide_kernel(Pencil p, double *cpl, double *dia) {
+// Couplings Au, Bu (caller layout, b x b) -> cpl [nc-1][2][BP][BP], their
+// transposes -> cplt [nc-1][2][BP][BP], and diagonal blocks Ad, Bd -> dia
+// [nc][2][BP][BP], all in the layout fpos.  Padding: zero, but -1 in A on
+// the diagonal of a diagonal block (so that Z B - A holds the identity there).
+__global__ void pack_wide_kernel(Pencil p, WidePack w) {
   constexpr int BP = kWideBP;
   const size_t per = (size_t)BP * BP;
   const size_t ncpl = (size_t)(p.nc - 1) * per;
-  const size_t total = ncpl + (size_t)p.nc * per;
+  const size_t total = 2 * ncpl + (size_t)p.nc * per;
   for (size_t o = blockIdx.x * (size_t)blockDim.x + threadIdx.x; o < total;
        o += (size_t)gridDim.x * blockDim.x) {
-    const bool diag = o >= ncpl;
-    const size_t q = diag ? o - ncpl : o;
+    const int region = o < ncpl ? 0 : (o < 2 * ncpl ? 1 : 2);  // cpl, cplt, dia
+    const size_t q = region == 0 ? o : (region == 1 ? o - ncpl : o - 2 * ncpl);
     const int c = (int)(q / per), idx = (int)(q % per);
     const int i = idx / BP, j = idx % BP;
     const bool in = i < p.b && j < p.b;
-    const size_t src = ((size_t)c * p.b + i) * p.b + j;
-    double *d = (diag ? dia : cpl) + (size_t)c * 2 * per;
+    const size_t src = region == 1 ? ((size_t)c * p.b + j) * p.b + i : ((size_t)c * p.b + i) * p.b + j;
+    const bool diag = region == 2;
+    double *d = (region == 0 ? w.cpl : region == 1 ? w.cplt : w.dia) + (size_t)c * 2 * per;
     const int fp = fpos<BP>(i, j);
     const double pad_a = (diag && i == j) ? -1.0 : 0.0;
     d[fp] = in ? (diag ? p.Ad : p.Au)[src] : pad_a;
@@ -1029,7 +1030,16 @@ hipError_t launch_factor_bp(const Pencil &p, const Shifts &s, int Ne, const Fact
 }  // namespace
 
 size_t wide_pack_doubles(const Pencil &p) {
-  return (size_t)(2 * p.nc - 1) * 2 * kWideBP * kWideBP;
+  return (size_t)(3 * p.nc - 2) * 2 * kWideBP * kWideBP;
+}
+
+WidePack wide_pack_planes(const Pencil &p, double *pack) {
+  const size_t pair = 2 * (size_t)kWideBP * kWideBP;
+  WidePack w;
+  w.cpl = pack;
+  w.cplt = pack + (size_t)(p.nc - 1) * pair;
+  w.dia = pack + 2 * (size_t)(p.nc - 1) * pair;
+  return w;
 }
 
 hipError_t launch_factor_wide(const Pencil &p, const Shifts &s, int Ne, const Factors &f,
@@ -1041,13 +1051,13 @@ hipError_t launch_factor_wide(const Pencil &p, const Shifts &s, int Ne, const Fa
   hipError_t err = hipFuncSetAttribute((const void *)factor_wide_kernel,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, shm);
   if (err != hipSuccess) return err;
-  double *cpl = pack, *dia = pack + (size_t)(p.nc - 1) * 2 * kWideBP * kWideBP;
-  const size_t total = (size_t)(2 * p.nc - 1) * kWideBP * kWideBP;
+  const WidePack w = wide_pack_planes(p, pack);
+  const size_t total = (size_t)(3 * p.nc - 2) * kWideBP * kWideBP;
   const int grid = (int)std::min<size_t>((total + 255) / 256, 4096);
-  hipLaunchKernelGGL(pack_wide_kernel, dim3(grid), dim3(256), 0, st, p, cpl, dia);
+  hipLaunchKernelGGL(pack_wide_kernel, dim3(grid), dim3(256), 0, st, p, w);
   if ((err = hipGetLastError()) != hipSuccess) return err;
   hipLaunchKernelGGL(factor_wide_kernel, dim3(Ne), dim3(kWideThreads), shm, st, p, s, f,
-                     (const double *)cpl, (const double *)dia);
+                     (const double *)w.cpl, (const double *)w.dia);
   return hipGetLastError();
 }
 

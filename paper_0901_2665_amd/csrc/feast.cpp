@@ -229,6 +229,14 @@ Pencil make_wide_pencil(const feast_bt_matrix *AB) {
   return p;
 }
 
+int validate_wide(const feast_bt_matrix *AB) {
+  if (!AB) return -5;
+  if (AB->nc < 1 || AB->b <= kMaxB || AB->b > kWideBP) return -1;
+  if (!AB->A_diag || !AB->B_diag) return -5;
+  if (AB->nc > 1 && (!AB->A_up || !AB->B_up)) return -5;
+  return 0;
+}
+
 // Non-finite scan of the pencil (and optionally Y0); returns -6 on NaN/Inf.
 int check_inputs(feast_ctx *ctx, const feast_bt_matrix *AB, const double *Y0, size_t ny) {
   int *flag = nullptr;
@@ -783,32 +791,14 @@ int feast_reduced_eig_noalloc(feast_ctx *ctx, int32_t M0, const double *AQ, cons
   return 0;
 }
 
-namespace {
-int solve_generic_real(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double emax,
-                       int32_t M0, int32_t Ne, const feast_opts &o, double *lambda, double *X,
-                       double *res, feast_info *info);
-}
 
 int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double emax, int32_t M0,
                 int32_t Ne, const feast_opts *opts, double *lambda, double *X, double *res,
                 feast_info *info) {
   if (!ctx || !lambda || !X || !res) return -5;
-  if (AB && AB->b > kMaxB && AB->b <= kMaxHB) {  // blocks above 64: the generic kernels
-    if (AB->nc < 1) return -1;
-    if (!AB->A_diag || !AB->B_diag || (AB->nc > 1 && (!AB->A_up || !AB->B_up))) return -5;
-    if (!(emin < emax) || !std::isfinite(emin) || !std::isfinite(emax)) return -2;
-    const long long Ng = (long long)AB->nc * AB->b;
-    if (M0 < 1 || M0 > kMaxHM0 || M0 > Ng) return -3;
-    if (Ne < 1 || Ne > kMaxNe) return -4;
-    feast_opts og;
-    feast_default_opts(&og);
-    if (opts) og = *opts;
-    if (!(og.tol > 0.0) || og.max_loops < 1 || og.precision != 0 || og.partitions < 0 ||
-        og.graph < 0 || og.graph > 2)
-      return -7;
-    return solve_generic_real(ctx, AB, emin, emax, M0, Ne, og, lambda, X, res, info);
-  }
-  int st = validate_matrix(AB);
+  // 64 < b <= 96: the wide kernels for the shifted systems and the products
+  const bool wide = is_wide(AB);
+  int st = wide ? validate_wide(AB) : validate_matrix(AB);
   if (st) return st;
   if (!(emin < emax) || !std::isfinite(emin) || !std::isfinite(emax)) return -2;
   const long long N = (long long)AB->nc * AB->b;
@@ -818,7 +808,8 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
   feast_default_opts(&o);
   if (opts) o = *opts;
   if (!(o.tol > 0.0) || o.max_loops < 1 || o.precision < 0 || o.precision > 2 ||
-      o.partitions < 0 || o.graph < 0 || o.graph > 2 || (o.graph == 2 && o.max_loops > 64))
+      o.partitions < 0 || o.graph < 0 || o.graph > 2 || (o.graph == 2 && o.max_loops > 64) ||
+      (wide && o.precision != 0))
     return -7;
   HIPCHK(hipSetDevice(ctx->device));
   hipStream_t sm = ctx->stream;
@@ -826,12 +817,16 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
   st = check_inputs(ctx, AB, o.Y0, (size_t)N * M0);
   if (st) return st;
 
-  Pencil p = make_pencil(AB);
+  Pencil p = wide ? make_wide_pencil(AB) : make_pencil(AB);
   const int mp = round16(M0);
-  Work wk;
-  st = prepare_factor(ctx, p, Ne, mp, choose_parts(p.nc, Ne, o.partitions), wk);
+  Work wk{};
+  WideWork ww{};
+  if (wide)
+    st = prepare_wide(ctx, p, Ne, mp, ww);
+  else
+    st = prepare_factor(ctx, p, Ne, mp, choose_parts(p.nc, Ne, o.partitions), wk);
   if (st) return st;
-  const size_t rows = wk.rows;
+  const size_t rows = wide ? ww.rows : wk.rows;
   Shifts s;
   make_shifts(Ne, emin, emax, s);
   const double r = 0.5 * (emax - emin);
@@ -843,19 +838,52 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
   HIPCHK(ensure_t(ctx, S_P, (size_t)Ne * rows * mp, &pp));
   HIPCHK(ensure_t(ctx, S_Q, rows * mp, &q));
   HIPCHK(ensure_t(ctx, S_X, rows * mp, &x));
-  HIPCHK(ensure_t(ctx, S_GRAMP, cell_partial_doubles(p.nc, mp), &gp));
+  HIPCHK(ensure_t(ctx, S_GRAMP,
+                  wide ? cross_gram_partial_doubles((long long)rows, M0, M0)
+                       : cell_partial_doubles(p.nc, mp),
+                  &gp));
   HIPCHK(ensure_t(ctx, S_AQ, (size_t)M0 * M0, &aq));
   HIPCHK(ensure_t(ctx, S_BQ, (size_t)M0 * M0, &bq));
   HIPCHK(ensure_t(ctx, S_EPS, (size_t)M0, &eps));
   HIPCHK(ensure_t(ctx, S_PHI, (size_t)M0 * M0, &phi));
   HIPCHK(ensure_t(ctx, S_RRS, reduced_eig_scratch_doubles(), &scr));
   HIPCHK(ensure_t(ctx, S_FLAG, 4, &flag));
-  HIPCHK(ensure_t(ctx, S_RESP, cell_partial_doubles(p.nc, mp), &resp));
+  HIPCHK(ensure_t(ctx, S_RESP,
+                  wide ? wide_residual_partial_doubles(p.nc, mp) : cell_partial_doubles(p.nc, mp),
+                  &resp));
+  WidePack pk{};
+  double *wtmp = nullptr;  // [rows][mp]: T Q of the wide projection
+  if (wide) {
+    pk = wide_pack_planes(p, ww.cpl);
+    HIPCHK(ensure_t(ctx, S_T1, rows * mp, &wtmp));
+  }
+  // the products and sweeps of one loop, for the kernels of either block size
+  auto bt_apply = [&](int which, const double *V, double *out, hipStream_t cs,
+                      const int *skip) -> hipError_t {
+    return wide ? launch_wide_apply(p, pk, which, V, mp, out, cs, skip)
+                : launch_cell_apply(p, which, V, mp, out, cs, skip);
+  };
+  auto sweeps = [&](const double *R, double *P, int part, hipStream_t cs,
+                    const int *skip) -> hipError_t {
+    return wide ? launch_sweeps_wide(p, s, Ne, ww.f, ww.sb, R, mp, P, nullptr, part, cs, skip)
+                : launch_sweeps(p, s, Ne, wk.f, wk.sb, R, mp, P, part, cs, skip);
+  };
+  auto project = [&](const double *Qm, hipStream_t cs, const int *skip) -> hipError_t {
+    return wide ? launch_wide_project(p, pk, Qm, mp, M0, wtmp, gp, aq, bq, cs, skip)
+                : launch_cell_project(p, Qm, mp, M0, gp, aq, bq, cs, skip);
+  };
+  auto residuals = [&](const double *Xm, hipStream_t cs, const int *skip) -> hipError_t {
+    return wide ? launch_wide_residuals(p, pk, Xm, mp, eps, M0, emin, emax, resp, resi, cs, skip)
+                : launch_cell_residuals(p, Xm, mp, eps, M0, emin, emax, resp, resi, cs, skip);
+  };
   HIPCHK(ensure_t(ctx, S_RES, (size_t)M0, &resi));
   HIPCHK(ensure_t(ctx, S_PERM, (size_t)M0, &perm));
 
   // factor every shifted matrix once (Sec. V, parallelism (ii))
-  TIMED(K_FACTOR, run_factor(ctx, wk, s));
+  if (wide)
+    TIMED(K_FACTOR, launch_factor_wide(p, s, Ne, ww.f, ww.cpl, sm));
+  else
+    TIMED(K_FACTOR, run_factor(ctx, wk, s));
   const bool mixed = o.precision == 1;
   // precision 2: the first contour integration by one float32 solve per node
   // (no refinement; the random start carries no accuracy that a float32 solve
@@ -893,15 +921,14 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
   GraphExec gx;
   auto graph_body = [&](hipStream_t sm) -> hipError_t {
     hipError_t e;
-    if ((e = launch_cell_apply(p, 1, y, mp, rr, sm)) != hipSuccess) return e;
-    if ((e = launch_sweeps(p, s, Ne, wk.f, wk.sb, rr, mp, pp, 1, sm)) != hipSuccess) return e;
-    if ((e = launch_sweeps(p, s, Ne, wk.f, wk.sb, rr, mp, pp, 2, sm)) != hipSuccess) return e;
+    if ((e = bt_apply(1, y, rr, sm, nullptr)) != hipSuccess) return e;
+    if ((e = sweeps(rr, pp, 1, sm, nullptr)) != hipSuccess) return e;
+    if ((e = sweeps(rr, pp, 2, sm, nullptr)) != hipSuccess) return e;
     if ((e = launch_sum_nodes(pp, Ne, rows * mp, q, sm)) != hipSuccess) return e;
-    if ((e = launch_cell_project(p, q, mp, M0, gp, aq, bq, sm)) != hipSuccess) return e;
+    if ((e = project(q, sm, nullptr)) != hipSuccess) return e;
     if ((e = launch_reduced_eig(aq, bq, M0, eps, phi, scr, flag, sm)) != hipSuccess) return e;
     if ((e = launch_gemm_qphi(q, rows, mp, M0, phi, x, sm)) != hipSuccess) return e;
-    if ((e = launch_cell_residuals(p, x, mp, eps, M0, emin, emax, resp, resi, sm)) != hipSuccess)
-      return e;
+    if ((e = residuals(x, sm, nullptr)) != hipSuccess) return e;
     return hipMemcpyAsync(y, x, rows * mp * sizeof(double), hipMemcpyDeviceToDevice, sm);
   };
   // graph = 2: the convergence decision on the device (launch_converge); the
@@ -925,19 +952,15 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
       for (int i = 0; i < kChunk; ++i) {
         const double *in = (i % 2 == 0) ? y : x;
         double *out = (i % 2 == 0) ? x : y;
-        if ((e = launch_cell_apply(p, 1, in, mp, rr, cs, skip)) != hipSuccess) return e;
-        if ((e = launch_sweeps(p, s, Ne, wk.f, wk.sb, rr, mp, pp, 1, cs, skip)) != hipSuccess)
-          return e;
-        if ((e = launch_sweeps(p, s, Ne, wk.f, wk.sb, rr, mp, pp, 2, cs, skip)) != hipSuccess)
-          return e;
+        if ((e = bt_apply(1, in, rr, cs, skip)) != hipSuccess) return e;
+        if ((e = sweeps(rr, pp, 1, cs, skip)) != hipSuccess) return e;
+        if ((e = sweeps(rr, pp, 2, cs, skip)) != hipSuccess) return e;
         if ((e = launch_sum_nodes(pp, Ne, rows * mp, q, cs, skip)) != hipSuccess) return e;
-        if ((e = launch_cell_project(p, q, mp, M0, gp, aq, bq, cs, skip)) != hipSuccess) return e;
+        if ((e = project(q, cs, skip)) != hipSuccess) return e;
         if ((e = launch_reduced_eig(aq, bq, M0, eps, phi, scr, flag, cs, skip)) != hipSuccess)
           return e;
         if ((e = launch_gemm_qphi(q, rows, mp, M0, phi, out, cs, skip)) != hipSuccess) return e;
-        if ((e = launch_cell_residuals(p, out, mp, eps, M0, emin, emax, resp, resi, cs, skip)) !=
-            hipSuccess)
-          return e;
+        if ((e = residuals(out, cs, skip)) != hipSuccess) return e;
         if ((e = launch_converge(eps, resi, flag, M0, emin, emax, res_gate, o.tol, r,
                                  kUncountedDrop, o.max_loops, cs_dev, cs)) != hipSuccess)
           return e;
@@ -979,7 +1002,7 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
       if (!gx.exec) HIPCHK(gx.capture(ctx->capture, graph_body));
       HIPCHK(hipGraphLaunch(gx.exec, sm));
     } else {
-    TIMED(K_BTMUL, launch_cell_apply(p, 1, y, mp, rr, sm));                  // R = B Y
+    TIMED(K_BTMUL, bt_apply(1, y, rr, sm, nullptr));                         // R = B Y
     const bool f32_loop = adaptive && k == 1;
     if (f32_loop) {  // Q_e by one float32 solve per node, then Q (eq. 15)
       TIMED(K_FWD32, launch_sweeps32(p, Ne, mx.f, mx.sb, rr, 0, 0, mp, mx.xc, 0, 1, sm));
@@ -995,16 +1018,16 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
       solve_res = std::max(solve_res, worst);
       TIMED(K_SUM, launch_sum_nodes_complex(s, Ne, mx.xc, mx.plane, q, sm));
     } else {
-      TIMED(K_FORWARD, launch_sweeps(p, s, Ne, wk.f, wk.sb, rr, mp, pp, 1, sm));  // Q_e ...
-      TIMED(K_BACK, launch_sweeps(p, s, Ne, wk.f, wk.sb, rr, mp, pp, 2, sm));     // ... weighted
+      TIMED(K_FORWARD, sweeps(rr, pp, 1, sm, nullptr));                     // Q_e ...
+      TIMED(K_BACK, sweeps(rr, pp, 2, sm, nullptr));                        // ... weighted
       TIMED(K_SUM, launch_sum_nodes(pp, Ne, rows * mp, q, sm));                 // Q (eq. 15)
     }
-    TIMED(K_GRAM, launch_cell_project(p, q, mp, M0, gp, aq, bq, sm));      // A_Q, B_Q (eq. 7)
+    TIMED(K_GRAM, project(q, sm, nullptr));                                // A_Q, B_Q (eq. 7)
     TIMED(K_RR, launch_reduced_eig(aq, bq, M0, eps, phi, scr, flag, sm));   // eq. 6
     TIMED(K_RITZ, launch_gemm_qphi(q, rows, mp, M0, phi, x, sm));           // X = Q Phi (eq. 9)
     // residuals of the Ritz pairs (Table I caption) decide which in-interval
     // pairs count as eigenvalue solutions (relative residual <= sqrt(tol))
-    TIMED(K_RESID, launch_cell_residuals(p, x, mp, eps, M0, emin, emax, resp, resi, sm));
+    TIMED(K_RESID, residuals(x, sm, nullptr));
     }
     HIPCHK(hipMemcpyAsync(h_eps, eps, M0 * sizeof(double), hipMemcpyDeviceToHost, sm));
     HIPCHK(hipMemcpyAsync(h_res, resi, M0 * sizeof(double), hipMemcpyDeviceToHost, sm));
@@ -1451,37 +1474,25 @@ int feast_filter_hermitian(feast_ctx *ctx, const feast_zbt_matrix *AB, double em
 
 namespace {
 
-// FEAST loop on the generic complex kernels of herm.hip: A Hermitian, or
-// (real_mode) a real symmetric A given as complex blocks.  In real mode the
-// start block, Q (eq. 12 with real Y equals eq. 15, real up to rounding),
-// the reduced problem (real parts, real eigensolver, no embedding) and X are
-// real; X_out is then real [N][M0], else complex.  y0: caller's start block
-// (complex, or real in real mode) or NULL for the seeded random start.
+// FEAST loop on the complex kernels of herm.hip for a Hermitian A.  y0: the
+// caller's complex start block or NULL for the seeded random start.
 int generic_solve(feast_ctx *ctx, const HPencil &p, double emin, double emax, int M0, int Ne,
-                  const feast_opts &o, bool real_mode, const double *y0, double *lambda,
-                  double *X_out, double *res, feast_info *info, const Pencil *wide) {
+                  const feast_opts &o, const double *y0, double *lambda, double *X_out,
+                  double *res, feast_info *info) {
   hipStream_t sm = ctx->stream;
   int st = 0;
   const long long N = (long long)p.nc * p.b;
   Shifts s;
   make_shifts(Ne, emin, emax, s);
   const double r = 0.5 * (emax - emin);
-  HFactors f{};
-  WideWork ww{};
-  double *wre = nullptr;  // real [N][M0] staging of the wide filter
-  if (wide) {
-    st = prepare_wide(ctx, *wide, Ne, round16(M0), ww);
-    if (st) return st;
-    HIPCHK(ensure_t(ctx, S_T0, ww.rows * ww.m0p, &wre));
-  } else {
-    st = prepare_hfactors(ctx, p, Ne, f);
-    if (st) return st;
-  }
+  HFactors f;
+  st = prepare_hfactors(ctx, p, Ne, f);
+  if (st) return st;
   double *coef;
   st = hcoefficients(ctx, s, Ne, &coef);
   if (st) return st;
   const size_t nm2 = (size_t)N * M0 * 2;
-  const int n2 = real_mode ? M0 : 2 * M0;  // size of the real reduced problem
+  const int n2 = 2 * M0;  // size of the real embedding of the reduced problem
   double *y, *rr, *q, *x, *ax, *bx, *part, *aq, *bq, *ea, *eb, *eps2, *phi2, *eps, *phi, *resi,
       *scr;
   int *flag, *perm;
@@ -1505,36 +1516,8 @@ int generic_solve(feast_ctx *ctx, const HPencil &p, double emin, double emax, in
   HIPCHK(ensure_t(ctx, S_FLAG, 4, &flag));
   HIPCHK(ensure_t(ctx, S_PERM, (size_t)M0, &perm));
 
-  // factor once (Sec. V, parallelism (ii))
-  if (wide)
-    HIPCHK(launch_factor_wide(*wide, s, Ne, ww.f, ww.cpl, sm));
-  else
-    HIPCHK(launch_hfactor(p, s, Ne, f.Sinv, f.W, f.V, sm));
-  // Q of a real pencil and a real right-hand side by the wide sweeps: the
-  // adjoint solve of eq. 12 is the complex conjugate of the direct one, so
-  // Q = sum_e Re(kappa_e x_e) (eq. 15) from the real part of R
-  auto wide_filter = [&](const double *Rc, double *Qc) -> int {
-    double *rp, *pp, *qp;
-    HIPCHK(ensure_t(ctx, S_R, ww.rows * ww.m0p, &rp));
-    HIPCHK(ensure_t(ctx, S_P, (size_t)Ne * ww.rows * ww.m0p, &pp));
-    HIPCHK(ensure_t(ctx, S_Q, ww.rows * ww.m0p, &qp));
-    const Pencil &wp = *wide;
-    HIPCHK(launch_real_part(Rc, (size_t)N * M0, wre, sm));
-    HIPCHK(launch_pack(wre, wp.nc, wp.b, wp.bp, M0, ww.m0p, rp, sm));
-    HIPCHK(launch_sweeps_wide(wp, s, Ne, ww.f, ww.sb, rp, ww.m0p, pp, nullptr, 3, sm));
-    HIPCHK(launch_sum_nodes(pp, Ne, ww.rows * ww.m0p, qp, sm));
-    HIPCHK(launch_unpack(qp, wp.nc, wp.b, wp.bp, M0, ww.m0p, nullptr, wre, sm));
-    HIPCHK(launch_to_complex(wre, (size_t)N * M0, Qc, sm));
-    return 0;
-  };
-  if (real_mode) {  // real start block, widened to complex
-    if (y0) {
-      HIPCHK(launch_to_complex(y0, (size_t)N * M0, y, sm));
-    } else {
-      HIPCHK(launch_random_start(o.seed, 1, (int)N, (int)N, M0, M0, x, sm));
-      HIPCHK(launch_to_complex(x, (size_t)N * M0, y, sm));
-    }
-  } else if (y0) {
+  HIPCHK(launch_hfactor(p, s, Ne, f.Sinv, f.W, f.V, sm));  // once (Sec. V, parallelism (ii))
+  if (y0) {
     HIPCHK(hipMemcpyAsync(y, y0, nm2 * sizeof(double), hipMemcpyDeviceToDevice, sm));
   } else {  // real and imaginary parts N(0, 1): the real draw of N x 2 M0
     HIPCHK(launch_random_start(o.seed, 1, (int)N, (int)N, 2 * M0, 2 * M0, y, sm));
@@ -1551,22 +1534,16 @@ int generic_solve(feast_ctx *ctx, const HPencil &p, double emin, double emax, in
   std::vector<char> is_counted(M0, 0);
   for (int k = 1; k <= o.max_loops; ++k) {
     HIPCHK(launch_happly(p, 1, y, M0, rr, sm));                       // R = B Y
-    st = wide ? wide_filter(rr, q) : hfilter(ctx, p, Ne, f, rr, M0, coef, q);  // Q (eq. 12)
+    st = hfilter(ctx, p, Ne, f, rr, M0, coef, q);                      // Q (eq. 12)
     if (st) return st;
     HIPCHK(launch_happly(p, 0, q, M0, ax, sm));
     HIPCHK(launch_happly(p, 1, q, M0, bx, sm));
     HIPCHK(launch_hgram(q, ax, N, M0, part, aq, sm));                  // A_Q = Q^H A Q
     HIPCHK(launch_hgram(q, bx, N, M0, part, bq, sm));                  // B_Q = Q^H B Q
-    if (real_mode) {  // real parts, real eigensolver; Phi widened to complex
-      HIPCHK(launch_real_part(aq, (size_t)M0 * M0, ea, sm));
-      HIPCHK(launch_real_part(bq, (size_t)M0 * M0, eb, sm));
-      HIPCHK(launch_reduced_eig(ea, eb, M0, eps, phi2, scr, flag, sm));
-      HIPCHK(launch_to_complex(phi2, (size_t)M0 * M0, phi, sm));
-    } else {  // real embedding of the Hermitian pencil
-      HIPCHK(launch_hembed(aq, bq, M0, ea, eb, sm));
-      HIPCHK(launch_reduced_eig(ea, eb, n2, eps2, phi2, scr, flag, sm));
-      HIPCHK(launch_hextract(eps2, phi2, M0, eps, phi, sm));
-    }
+    // real embedding of the Hermitian pencil
+    HIPCHK(launch_hembed(aq, bq, M0, ea, eb, sm));
+    HIPCHK(launch_reduced_eig(ea, eb, n2, eps2, phi2, scr, flag, sm));
+    HIPCHK(launch_hextract(eps2, phi2, M0, eps, phi, sm));
     HIPCHK(launch_htall_gemm(q, phi, N, M0, M0, x, sm));              // X = Q Phi
     HIPCHK(launch_happly(p, 0, x, M0, ax, sm));
     HIPCHK(launch_happly(p, 1, x, M0, bx, sm));
@@ -1601,7 +1578,7 @@ int generic_solve(feast_ctx *ctx, const HPencil &p, double emin, double emax, in
     counts.push_back(Mk);
     if (o.verbose)
       std::fprintf(stderr, "feast (%s): loop %d  M %d  trace %.17g  trace change %.3e\n",
-                   real_mode ? "generic" : "Hermitian", k, Mk, Tk, k >= 2 ? trace_rel : INFINITY);
+                   "Hermitian", k, Mk, Tk, k >= 2 ? trace_rel : INFINITY);
     if (k >= 2 && Mk == counts[counts.size() - 2] && trace_rel < o.tol && !still_converging) {
       converged = true;
       break;
@@ -1621,12 +1598,7 @@ int generic_solve(feast_ctx *ctx, const HPencil &p, double emin, double emax, in
   std::vector<double> res_sorted(M0);
   for (int j = 0; j < M0; ++j) res_sorted[j] = h_res[order[j]];
   HIPCHK(hipMemcpyAsync(perm, h_perm, M0 * sizeof(int), hipMemcpyHostToDevice, sm));
-  if (real_mode) {  // Ritz vectors of a real pencil from a real Q: the real part
-    HIPCHK(launch_hgather(x, perm, N, M0, ax, sm));
-    HIPCHK(launch_real_part(ax, (size_t)N * M0, X_out, sm));
-  } else {
-    HIPCHK(launch_hgather(x, perm, N, M0, X_out, sm));
-  }
+  HIPCHK(launch_hgather(x, perm, N, M0, X_out, sm));
   HIPCHK(launch_gather(eps, perm, M0, lambda, sm));
   HIPCHK(launch_gather(resi, perm, M0, res, sm));
   HIPCHK(hipStreamSynchronize(sm));
@@ -1676,40 +1648,8 @@ int feast_solve_hermitian(feast_ctx *ctx, const feast_zbt_matrix *AB, double emi
   HIPCHK(hipSetDevice(ctx->device));
   st = check_hinputs(ctx, AB, o.Y0, (size_t)N * M0 * 2);
   if (st) return st;
-  return generic_solve(ctx, make_hpencil(AB), emin, emax, M0, Ne, o, false, o.Y0, lambda, X,
-                       res, info, nullptr);
+  return generic_solve(ctx, make_hpencil(AB), emin, emax, M0, Ne, o, o.Y0, lambda, X, res, info);
 }
 
-namespace {
 
-// Real symmetric pencils with 64 < b <= 96: the shifted systems run on the
-// wide kernels; A is widened to complex for the generic projection and
-// residual kernels, which run in real mode.
-int solve_generic_real(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double emax,
-                       int32_t M0, int32_t Ne, const feast_opts &o, double *lambda, double *X,
-                       double *res, feast_info *info) {
-  HIPCHK(hipSetDevice(ctx->device));
-  const long long N = (long long)AB->nc * AB->b;
-  int st = check_inputs(ctx, AB, o.Y0, (size_t)N * M0);
-  if (st) return st;
-  const size_t bb = (size_t)AB->b * AB->b;
-  double *ad, *au = nullptr;
-  HIPCHK(ensure_t(ctx, S_HAD, 2 * AB->nc * bb, &ad));
-  HIPCHK(launch_to_complex(AB->A_diag, AB->nc * bb, ad, ctx->stream));
-  if (AB->nc > 1) {
-    HIPCHK(ensure_t(ctx, S_HAU, 2 * (AB->nc - 1) * bb, &au));
-    HIPCHK(launch_to_complex(AB->A_up, (AB->nc - 1) * bb, au, ctx->stream));
-  }
-  HPencil p;
-  p.Ad = ad;
-  p.Au = au;
-  p.Bd = AB->B_diag;
-  p.Bu = AB->B_up;
-  p.nc = AB->nc;
-  p.b = AB->b;
-  const Pencil wp = make_wide_pencil(AB);
-  return generic_solve(ctx, p, emin, emax, M0, Ne, o, true, o.Y0, lambda, X, res, info, &wp);
-}
-
-}  // namespace
 

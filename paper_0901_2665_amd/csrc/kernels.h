@@ -49,8 +49,15 @@ hipError_t launch_factor(const Pencil &p, const Shifts &s, int Ne, const Factors
 // Blocks of 64 < b <= 96 (bp = 96): one top-down chain per node over all
 // cells (no twist: f.m unused, Sinv, W and W^T of every cell; W and W^T of
 // the last cell unused).  pack: wide_pack_doubles() of workspace for the
-// blocks of the pencil repacked in the operand layout.
+// blocks of the pencil repacked in the operand layout (written by
+// launch_factor_wide, read by the wide dense products below).
+struct WidePack {
+  double *cpl;   // [nc-1][2][96*96]: A_{c,c+1}, B_{c,c+1}
+  double *cplt;  // [nc-1][2][96*96]: their transposes
+  double *dia;   // [nc][2][96*96]: A_cc (identity padding as -1), B_cc
+};
 size_t wide_pack_doubles(const Pencil &p);
+WidePack wide_pack_planes(const Pencil &p, double *pack);
 hipError_t launch_factor_wide(const Pencil &p, const Shifts &s, int Ne, const Factors &f,
                               double *pack, hipStream_t st);
 
@@ -78,7 +85,7 @@ hipError_t launch_sweeps(const Pencil &p, const Shifts &s, int Ne, const Factors
 // node 0 in P (real plane) and Xim.  sb.G as for launch_sweeps, sb.TV unused.
 hipError_t launch_sweeps_wide(const Pencil &p, const Shifts &s, int Ne, const Factors &f,
                               const SolveBufs &sb, const double *R, int m0p, double *P,
-                              double *Xim, int part, hipStream_t st);
+                              double *Xim, int part, hipStream_t st, const int *skip = nullptr);
 // Same sweeps, but the back sweep writes the complex solution of node 0
 // (used by the single-shift entry point): X_re, X_im padded.
 hipError_t launch_sweeps_complex(const Pencil &p, const Shifts &s, const Factors &f,
@@ -136,6 +143,21 @@ hipError_t launch_cell_project(const Pencil &p, const double *Q, int ld, int m0,
 hipError_t launch_cell_residuals(const Pencil &p, const double *X, int ld, const double *lam,
                                  int m0, double emin, double emax, double *partial, double *res,
                                  hipStream_t st, const int *skip = nullptr);
+
+// The same products for 64 < b <= 96 (p.bp = 96) from the packed planes of
+// launch_factor_wide: out = T V (which: 0 = A, 1 = B), the projection
+// (tmp: [nc][96][ld] doubles, partial: cross_gram_partial_doubles(nc*96, m0,
+// m0)) and the residuals (partial: wide_residual_partial_doubles()).
+hipError_t launch_wide_apply(const Pencil &p, const WidePack &pk, int which, const double *V,
+                             int ld, double *out, hipStream_t st, const int *skip = nullptr);
+size_t wide_residual_partial_doubles(int nc, int ld);
+hipError_t launch_wide_residuals(const Pencil &p, const WidePack &pk, const double *X, int ld,
+                                 const double *lam, int m0, double emin, double emax,
+                                 double *partial, double *res, hipStream_t st,
+                                 const int *skip = nullptr);
+hipError_t launch_wide_project(const Pencil &p, const WidePack &pk, const double *Q, int ld,
+                               int m0, double *tmp, double *partial, double *AQ, double *BQ,
+                               hipStream_t st, const int *skip = nullptr);
 
 // Float64 residuals of the shifted systems for the mixed-precision solves:
 // Rout_e = R - (Z_e B - A) x_e for every node (X and Rout: node e's real

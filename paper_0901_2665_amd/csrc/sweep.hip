@@ -405,6 +405,7 @@ __device__ __forceinline__ d4 frag_mfma_lds(const d4 &acc0, const Frag<BP> &f, c
 }
 
 __global__ __launch_bounds__(kWideThreads) void forward_wide_kernel(SweepArgs a) {
+  if (a.skip && *a.skip) return;
   constexpr int BP = kWideBP;
   __shared__ VecLds<BP> s;
   const int item = xcd_item(blockIdx.x, gridDim.x, a.ntiles);
@@ -449,6 +450,7 @@ __global__ __launch_bounds__(kWideThreads) void forward_wide_kernel(SweepArgs a)
 // current product.
 template <bool COMPLEX_OUT>
 __global__ __launch_bounds__(kWideThreads) void back_wide_kernel(SweepArgs a) {
+  if (a.skip && *a.skip) return;
   constexpr int BP = kWideBP;
   __shared__ VecLds<BP> s;
   const int item = xcd_item(blockIdx.x, gridDim.x, a.ntiles);
@@ -784,10 +786,10 @@ hipError_t launch_spikes(const Pencil &p, const Factors &f, const Chain *chains,
 
 hipError_t launch_sweeps_wide(const Pencil &p, const Shifts &s, int Ne, const Factors &f,
                               const SolveBufs &sb, const double *R, int m0p, double *P,
-                              double *Xim, int part, hipStream_t st) {
+                              double *Xim, int part, hipStream_t st, const int *skip) {
   if (p.bp != kWideBP) return hipErrorInvalidValue;
   SweepArgs a;
-  a.p = p; a.f = f; a.sb = sb; a.R = R; a.P = P; a.Xim = Xim; a.skip = nullptr;
+  a.p = p; a.f = f; a.sb = sb; a.R = R; a.P = P; a.Xim = Xim; a.skip = skip;
   a.m0p = m0p; a.ntiles = m0p / kTile;
   for (int e = 0; e < kMaxNe; ++e) { a.kre[e] = s.kre[e]; a.kim[e] = s.kim[e]; }
   return launch_wide(a, Ne, Xim != nullptr, part, st);

@@ -144,3 +144,16 @@ def test_device_graph_batched_and_tb6400(ctx, torch):
     p, emin, emax, m0, ne, Y0 = W.make_workload("tb6400")
     gp, y = gpencil(p), dev(torch, Y0)
     same(ctx.solve(gp, emin, emax, m0, ne, y, graph=2), ctx.solve(gp, emin, emax, m0, ne, y))
+
+
+def test_device_graph_wide_blocks(ctx, torch):
+    # 64 < b <= 96: the wide kernels take the same flag
+    p = W.dense_random_pencil(6, 96, 81)
+    lam = O.bruteforce(p)[0]
+    emin, emax = 0.5 * (lam[149] + lam[150]), 0.5 * (lam[169] + lam[170])
+    Y0 = dev(torch, W.random_subspace(p.n, 40, 181))
+    gp = gpencil(p)
+    eager = ctx.solve(gp, emin, emax, 40, 8, Y0, tol=1e-13, max_loops=40)
+    assert eager.M == 20
+    for graph in (1, 2):
+        same(ctx.solve(gp, emin, emax, 40, 8, Y0, tol=1e-13, max_loops=40, graph=graph), eager)

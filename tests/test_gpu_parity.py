@@ -560,11 +560,11 @@ def test_deterministic(ctx, torch):
 
 
 @pytest.mark.parametrize("nc,b,seed,k0,m,extra", [(6, 96, 81, 150, 20, 20), (4, 80, 82, 90, 12, 30),
-                                                  (2, 65, 83, 40, 5, 3), (30, 96, 84, 700, 24, 16)])
+                                                  (2, 65, 83, 40, 5, 3), (30, 96, 84, 700, 24, 16),
+                                                  (8, 90, 86, 200, 60, 40)])
 def test_solve_blocks_above_64(ctx, torch, nc, b, seed, k0, m, extra):
-    # b > 64: the wide kernels for the shifted systems, the generic kernels in
-    # real mode for the rest (A widened to complex; Q, the reduced problem and
-    # X real), against the oracle and brute force
+    # b > 64: the wide kernels (factorisation, sweeps, B Y, projection,
+    # residuals), up to M0 = 100, against the oracle and brute force
     p = W.dense_random_pencil(nc, b, seed)
     lam = O.bruteforce(p)[0]
     emin, emax = 0.5 * (lam[k0 - 1] + lam[k0]), 0.5 * (lam[k0 + m - 1] + lam[k0 + m])
@@ -581,9 +581,9 @@ def test_solve_blocks_above_64(ctx, torch, nc, b, seed, k0, m, extra):
 def test_blocks_above_64_limits(ctx, torch):
     from paper_0901_2665_amd import feast as F
     p = W.dense_random_pencil(2, 96, 85)
-    y = dev(torch, W.random_subspace(p.n, 65, 1))
-    with pytest.raises(F.FeastError) as e:          # M0 above 64 on the generic kernels
-        ctx.solve(gpencil(p), 0.0, 1.0, 65, 8, y)
+    y = dev(torch, W.random_subspace(p.n, 129, 1))
+    with pytest.raises(F.FeastError) as e:          # M0 above 128
+        ctx.solve(gpencil(p), 0.0, 1.0, 129, 8, y)
     assert e.value.status == -3
     with pytest.raises(F.FeastError) as e:          # no mixed precision there
         ctx.solve(gpencil(p), 0.0, 1.0, 8, 8, dev(torch, W.random_subspace(p.n, 8, 1)),

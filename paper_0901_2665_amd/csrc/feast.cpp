@@ -43,8 +43,7 @@ enum Slot {
   S_SINV32, S_W32, S_WT32, S_G32, S_TV32, S_XC, S_RC, S_RPART, S_WORST,
   // Hermitian variant
   S_HSINV, S_HW, S_HV, S_HG, S_HY, S_HR, S_HQ, S_HX, S_HAX, S_HBX, S_HPART, S_HAQ, S_HBQ,
-  S_HEA, S_HEB, S_HEPS2, S_HPHI2, S_HEPS, S_HPHI, S_HRES, S_HCOEF, S_HAD, S_HAU,
-  S_CONV, S_COUNT
+  S_HEA, S_HEB, S_HEPS2, S_HPHI2, S_HEPS, S_HPHI, S_HRES, S_HCOEF, S_CONV, S_COUNT
 };
 
 }  // namespace

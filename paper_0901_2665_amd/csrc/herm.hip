@@ -436,20 +436,6 @@ __global__ void hgather_kernel(const double *in, const int *perm, long long N, i
   }
 }
 
-__global__ void to_complex_kernel(const double *src, size_t n, double *dst) {
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
-       i += (size_t)gridDim.x * blockDim.x) {
-    dst[2 * i] = src[i];
-    dst[2 * i + 1] = 0.0;
-  }
-}
-
-__global__ void real_part_kernel(const double *src, size_t n, double *dst) {
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
-       i += (size_t)gridDim.x * blockDim.x)
-    dst[i] = src[2 * i];
-}
-
 int grid_of(size_t n) {
   size_t g = (n + 255) / 256;
   return (int)(g < 4096 ? (g > 0 ? g : 1) : 4096);
@@ -538,16 +524,6 @@ hipError_t launch_hgather(const double *in, const int *perm, long long N, int m,
                           hipStream_t st) {
   hipLaunchKernelGGL(hgather_kernel, dim3(grid_of((size_t)N * m)), dim3(256), 0, st, in, perm, N,
                      m, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_to_complex(const double *src, size_t n, double *dst, hipStream_t st) {
-  hipLaunchKernelGGL(to_complex_kernel, dim3(grid_of(n)), dim3(256), 0, st, src, n, dst);
-  return hipGetLastError();
-}
-
-hipError_t launch_real_part(const double *src, size_t n, double *dst, hipStream_t st) {
-  hipLaunchKernelGGL(real_part_kernel, dim3(grid_of(n)), dim3(256), 0, st, src, n, dst);
   return hipGetLastError();
 }
 

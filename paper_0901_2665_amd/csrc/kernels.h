@@ -283,8 +283,5 @@ hipError_t launch_hresiduals(const double *AX, const double *BX, const double *l
                              int m, double emin, double emax, double *res, hipStream_t st);
 hipError_t launch_hgather(const double *in, const int *perm, long long N, int m, double *out,
                           hipStream_t st);
-// dst (complex, n entries) = src (real, n entries) + 0 i; dst (real) = Re src.
-hipError_t launch_to_complex(const double *src, size_t n, double *dst, hipStream_t st);
-hipError_t launch_real_part(const double *src, size_t n, double *dst, hipStream_t st);
 
 }  // namespace feast

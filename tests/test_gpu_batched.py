@@ -57,6 +57,24 @@ def test_batched_equals_individual(ctx, torch, batch):
         assert np.array_equal(host(r.res), host(one.res), equal_nan=True)
 
 
+def test_batched_wide_equals_individual(ctx, torch):
+    # problems of the full shape with b = 96, 64 and 32 solved together on
+    # four workers: every result bitwise that of the single call
+    sh = [W.batch256_shape(p) for p in range(W.BATCH256_COUNT)]
+    pick = [p for p, s in enumerate(sh) if s["nc"] < 120][:6]
+    assert {sh[p]["b"] for p in pick} >= {96}
+    probs = [W.make_batch256(1, p)[0] for p in pick]
+    batch = [(gpencil(p), emin, emax, m0, ne, dev(torch, Y0)) for p, emin, emax, m0, ne, Y0 in probs]
+    st, rs = ctx.solve_batched(batch, tol=1e-13, workers=4)
+    assert st in SOLVED
+    for b_, r in zip(batch, rs):
+        one = ctx.solve(*b_, tol=1e-13, partitions=1)
+        assert (r.status, r.M, r.loops) == (one.status, one.M, one.loops)
+        assert np.array_equal(host(r.lam), host(one.lam), equal_nan=True)
+        assert np.array_equal(host(r.X), host(one.X), equal_nan=True)
+        assert np.array_equal(host(r.res), host(one.res), equal_nan=True)
+
+
 def test_batched_against_oracle(ctx, torch, batch):
     # the two smallest problems of the sample, against the float64 oracle
     small = sorted(range(len(batch)), key=lambda i: batch[i][6].n)[:2]

@@ -473,7 +473,7 @@ int feast_destroy(feast_ctx *ctx) {
 const char *feast_strerror(int status) {
   switch (status) {
     case 0: return "success";
-    case -1: return "bad block structure (nc < 1, b < 1 or b > 64)";
+    case -1: return "bad block structure (nc < 1, b < 1, or b above the call's maximum: 96 or 64)";
     case -2: return "bad interval (emin >= emax or not finite)";
     case -3: return "bad subspace size (M0 < 1, M0 > N or M0 > 128)";
     case -4: return "bad number of contour points (Ne < 1 or Ne > 64)";

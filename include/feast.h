@@ -163,6 +163,9 @@ typedef struct {
   double solve_res;      /* precision 1: largest final residual ratio of a
                             shifted solve column (feast_shifted_solve_mixed)
                             over all loops and nodes */
+  int32_t m0_small;      /* 1 if M0 < 1.5 M: below the subspace size the
+                            paper recommends after Fig. 2 (M0 >= 1.5 M); the
+                            results stand, but more loops may be needed */
 } feast_info;
 
 /* Default options: tol 1e-12, max_loops 20, precision 0, partitions 0, graph 0,

@@ -1116,6 +1116,7 @@ int feast_solve(feast_ctx *ctx, const feast_bt_matrix *AB, double emin, double e
     info->rr_sweeps = rr_sweeps;
     info->refine_steps = refine_steps;
     info->solve_res = solve_res;
+    info->m0_small = 2 * M0 < 3 * M;  // M0 < 1.5 M
     for (size_t k = 0; k < traces.size() && k < 64; ++k) {
       info->trace_hist[k] = traces[k];
       info->count_hist[k] = counts[k];
@@ -1620,6 +1621,7 @@ int generic_solve(feast_ctx *ctx, const HPencil &p, double emin, double emax, in
     info->status = status;
     info->fallback = fallback;
     info->rr_sweeps = rr_sweeps;
+    info->m0_small = 2 * M0 < 3 * M;  // M0 < 1.5 M
     for (size_t k = 0; k < traces.size() && k < 64; ++k) {
       info->trace_hist[k] = traces[k];
       info->count_hist[k] = counts[k];

@@ -52,7 +52,7 @@ class Info(ctypes.Structure):
                 ("fallback", ctypes.c_int32),
                 ("trace_hist", ctypes.c_double * 64), ("count_hist", ctypes.c_int32 * 64),
                 ("rr_sweeps", ctypes.c_int32), ("refine_steps", ctypes.c_int32),
-                ("solve_res", ctypes.c_double)]
+                ("solve_res", ctypes.c_double), ("m0_small", ctypes.c_int32)]
 
 
 class Problem(ctypes.Structure):
@@ -233,6 +233,7 @@ class SolveResult:
     rr_sweeps: int = 0
     refine_steps: int = 0  # precision 1: float32 correction solves; 2: float32 loops
     solve_res: float = 0.0  # precision 1: worst final relative residual of a shifted solve
+    m0_small: int = 0       # 1 if M0 < 1.5 M (below the paper's subspace-size guidance)
 
 
 def _ptr(t):
@@ -359,7 +360,7 @@ class Context:
         return SolveResult(lam, X, res, info.M, info.loops, info.trace, info.trace_rel,
                            info.max_res, st, info.fallback, list(info.trace_hist[:n]),
                            list(info.count_hist[:n]), info.rr_sweeps, info.refine_steps,
-                           info.solve_res)
+                           info.solve_res, info.m0_small)
 
     def solve_batched(self, problems, tol: float = 1e-12, max_loops: int = 20,
                       partitions: int = 0, precision: int = 0, workers: int = 0,
@@ -393,7 +394,7 @@ class Context:
                                         info.trace_rel, info.max_res, arr[i].status,
                                         info.fallback, list(info.trace_hist[:n]),
                                         list(info.count_hist[:n]), info.rr_sweeps,
-                                        info.refine_steps, info.solve_res))
+                                        info.refine_steps, info.solve_res, info.m0_small))
         return st, res_list
 
     def autotune_partitions(self, p: Pencil, emin: float, emax: float, M0: int, Ne: int,
@@ -507,7 +508,7 @@ class Context:
         n = min(info.loops, 64)
         return SolveResult(lam, X, res, info.M, info.loops, info.trace, info.trace_rel,
                            info.max_res, st, info.fallback, list(info.trace_hist[:n]),
-                           list(info.count_hist[:n]), info.rr_sweeps, 0, 0.0)
+                           list(info.count_hist[:n]), info.rr_sweeps, 0, 0.0, info.m0_small)
 
     def shifted_solve_hermitian(self, p: "HermitianPencil", z: complex, R, adjoint: bool = False):
         import torch

@@ -356,6 +356,7 @@ def test_solve_chain800(ctx, torch):
     r = ctx.solve(gpencil(p), emin, emax, m0, ne, dev(torch, Y0))
     ref = O.feast(p, emin, emax, m0, ne, Y0)
     assert r.status == 0
+    assert r.m0_small == 0  # M0 = 30 = 1.5 M
     check_against_oracle(r, ref, p, emin, emax)
     lam_b = O.bruteforce(p)[0]
     assert np.max(np.abs(host(r.lam)[:20] - lam_b[200:220]) / np.abs(lam_b[200:220])) <= 1e-12
@@ -507,6 +508,7 @@ def test_subspace_just_large_enough(ctx, torch, k0, m):
     r = ctx.solve(gpencil(p), emin, emax, m, 8, dev(torch, Y0), max_loops=40)
     ref = O.feast(p, emin, emax, m, 8, Y0, max_loops=40)
     assert r.status == ref.status == 4 and r.M == ref.M == m
+    assert r.m0_small == 1  # M0 = M < 1.5 M
     check_against_oracle(r, ref, p, emin, emax)
 
 

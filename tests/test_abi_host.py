@@ -114,3 +114,9 @@ def test_struct_layouts_match_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(cls), cname
         for fname, _ in cls._fields_:
             assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    # the binding has no CPU path: without the built library it raises
+    with pytest.raises(RuntimeError, match="not built"):
+        F.load_library(str(tmp_path / "libfeast.so"))

@@ -116,7 +116,8 @@ def test_struct_layouts_match_header(tmp_path):
             assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
 
 
-def test_missing_library_fails_loudly(tmp_path):
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
     # the binding has no CPU path: without the built library it raises
+    monkeypatch.setattr(F, "_lib", None)  # as in a fresh process
     with pytest.raises(RuntimeError, match="not built"):
         F.load_library(str(tmp_path / "libfeast.so"))

@@ -363,14 +363,16 @@ int feast_reduced_eig_noalloc(feast_ctx *ctx, int32_t M0, const double *AQ, cons
 
 /*
  * Kernel timing.  feast_timing(ctx, 1) clears the records and, until
- * feast_timing(ctx, 0), brackets every kernel class that feast_solve launches
- * with hipEvents on the context's stream.  feast_timing_read(ctx, k, ...)
- * synchronises the stream and returns, for class k, its name (static
- * string), the summed event time in milliseconds and the number of launches;
- * with k < 0 it returns the number of classes.  Classes: factor,
- * forward_sweep, back_sweep, bt_multiply, sum_nodes, projection, reduced_eig,
- * ritz_gemm, residual, layout, round_factors, forward_sweep32, back_sweep32,
- * refine_residual (the last four with precision 1 only).
+ * feast_timing(ctx, 0), brackets every kernel class that feast_solve and
+ * feast_solve_hermitian launch with hipEvents on the context's stream.
+ * feast_timing_read(ctx, k, ...) synchronises the stream and returns, for
+ * class k, its name (static string), the summed event time in milliseconds
+ * and the number of launches; with k < 0 it returns the number of classes.
+ * Classes: factor, forward_sweep, back_sweep, bt_multiply, sum_nodes,
+ * projection, reduced_eig, ritz_gemm, residual, layout, round_factors,
+ * forward_sweep32, back_sweep32, refine_residual (the last four with
+ * precision 1 or 2 only), sweeps_hermitian (the forward and back sweeps of
+ * both solves of eq. 12 in one kernel).
  */
 int feast_timing(feast_ctx *ctx, int32_t enable);
 int feast_timing_read(feast_ctx *ctx, int32_t kind, const char **name, double *total_ms,

@@ -1027,6 +1027,157 @@ hipError_t launch_factor_bp(const Pencil &p, const Shifts &s, int Ne, const Fact
   return hipGetLastError();
 }
 
+// ---- Hermitian A (eq. 12): block LU of the non-symmetric M = Z B - A ----
+//
+// With A complex Hermitian, M_e = Z_e B - A is neither symmetric nor
+// Hermitian, so the factorisation keeps Sinv_c, W_c = Sinv_c C_c (upper
+// coupling C_c = Z B_{c,c+1} - A_{c,c+1}) and V_c = L_c Sinv_c (lower
+// coupling L_c = Z B_{c,c+1}^T - A_{c,c+1}^H), and S_{c+1} = D_{c+1} - L_c W_c.
+// Every principal submatrix of M has the positive definite Hermitian part
+// Im(Z) B in M - M^H = 2i Im(Z) B, so the blocked Gauss-Jordan inverse needs
+// no pivoting; it is not symmetrised.  One chain (contour point) per
+// workgroup, the blocks in the two LDS slots, the products on the matrix
+// cores; outputs complex interleaved [b][b] (the layout of the Hermitian
+// sweeps).
+
+// slot <- one shifted block of the Hermitian pencil by NTH threads: kind 0
+// D_cell (identity padding), 1 C_cell, 2 L_cell (zero padding).
+template <int BP, int NTH = kThreads>
+__device__ void hform_block(double *slot, const HPencil &p, int cell, int kind, double zr,
+                            double zi, int tid = threadIdx.x) {
+  constexpr int LD = Lds<BP>::LD, PLANE = Lds<BP>::PLANE;
+  const int b = p.b;
+  const size_t bb = (size_t)b * b;
+  const double *Ac = (kind == 0 ? p.Ad : p.Au) + 2 * (size_t)cell * bb;
+  const double *Br = (kind == 0 ? p.Bd : p.Bu) + (size_t)cell * bb;
+  for (int idx = tid; idx < BP * BP; idx += NTH) {
+    const int r = idx / BP, c = idx % BP;
+    double re = (kind == 0 && r == c) ? 1.0 : 0.0, im = 0.0;
+    if (r < b && c < b) {
+      const int o = kind == 2 ? c * b + r : r * b + c;  // L: the transposed element
+      const double bv = Br[o], ar = Ac[2 * o], ai = Ac[2 * o + 1];
+      re = zr * bv - ar;
+      im = kind == 2 ? zi * bv + ai : zi * bv - ai;  // L: conj(A_u) transposed
+    }
+    slot[r * LD + c] = re;
+    slot[PLANE + r * LD + c] = im;
+  }
+}
+
+// acc <- D_cell in the accumulator layout (identity padding).
+template <int BP>
+__device__ void acc_from_hdiag(d4 (&accr)[BP / 16], d4 (&acci)[BP / 16], const HPencil &p,
+                               int cell, double zr, double zi) {
+  constexpr int NT = BP / 16;
+  const int w = wave_id(), l = lane_id();
+  if (w >= NT) return;
+  const int b = p.b;
+  const size_t bb = (size_t)b * b;
+  const double *Ac = p.Ad + 2 * (size_t)cell * bb;
+  const double *Br = p.Bd + (size_t)cell * bb;
+#pragma unroll
+  for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = w * 16 + acc_row(l, r), col = tj * 16 + acc_col(l);
+      double re = row == col ? 1.0 : 0.0, im = 0.0;
+      if (row < b && col < b) {
+        const int o = row * b + col;
+        re = zr * Br[o] - Ac[2 * o];
+        im = zi * Br[o] - Ac[2 * o + 1];
+      }
+      accr[tj][r] = re;
+      acci[tj][r] = im;
+    }
+}
+
+// global complex [b][b] (interleaved) <- the slot's leading b x b block
+template <int BP>
+__device__ void hstore_block(double *g, const double *slot, int b) {
+  constexpr int LD = Lds<BP>::LD, PLANE = Lds<BP>::PLANE;
+  for (int idx = threadIdx.x; idx < b * b; idx += kThreads) {
+    const int r = idx / b, c = idx % b;
+    g[2 * idx] = slot[r * LD + c];
+    g[2 * idx + 1] = slot[PLANE + r * LD + c];
+  }
+}
+
+// global complex [b][b] (interleaved) <- this wave's accumulator tiles
+template <int BP>
+__device__ void hacc_to_global(double *g, const d4 (&accr)[BP / 16], const d4 (&acci)[BP / 16],
+                               int b) {
+  constexpr int NT = BP / 16;
+  const int w = wave_id(), l = lane_id();
+  if (w >= NT) return;
+#pragma unroll
+  for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = w * 16 + acc_row(l, r), col = tj * 16 + acc_col(l);
+      if (row < b && col < b) {
+        g[2 * (row * b + col)] = accr[tj][r];
+        g[2 * (row * b + col) + 1] = acci[tj][r];
+      }
+    }
+}
+
+template <int BP>
+__global__ __launch_bounds__(kThreads) void hfactor_mfma_kernel(HPencil p, Shifts sh,
+                                                                double *Sinv, double *W,
+                                                                double *V) {
+  extern __shared__ double smem_raw[];
+  Lds<BP> &s = *reinterpret_cast<Lds<BP> *>(smem_raw);
+  constexpr int NT = BP / 16;
+  const int e = blockIdx.x, nc = p.nc, b = p.b;
+  const double zr = sh.zre[e], zi = sh.zim[e];
+  const size_t bb = (size_t)b * b, nf = nc > 1 ? nc - 1 : 1;
+  double *Se = Sinv + 2 * (size_t)e * nc * bb;
+  double *We = W + 2 * (size_t)e * nf * bb;
+  double *Ve = V + 2 * (size_t)e * nf * bb;
+  hform_block<BP>(s.A, p, 0, 0, zr, zi);  // S_0 = D_0
+  __syncthreads();
+  for (int c = 0; c < nc; ++c) {
+    const bool last = c == nc - 1;
+    // C_c into slot B by waves 1-3 while wave 0 inverts the first pivot tile
+    auto coupling = [&]() {
+      if (!last) hform_block<BP, kThreads - 64>(s.B, p, c, 1, zr, zi, threadIdx.x - 64);
+    };
+    gj_invert<BP>(s, nullptr, coupling, false);  // slot A: Sinv_c
+    hstore_block<BP>(Se + 2 * (size_t)c * bb, s.A, b);
+    if (last) break;
+    d4 wr[NT], wi[NT], vr[NT], vi[NT], sr[NT], si[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      wr[t] = d4zero(); wi[t] = d4zero(); vr[t] = d4zero(); vi[t] = d4zero();
+    }
+    cgemm_lds<BP>(wr, wi, s.A, false, s.B, 1.0);  // W = Sinv C
+    __syncthreads();
+    hform_block<BP>(s.B, p, c, 2, zr, zi);  // slot B: L_c
+    __syncthreads();
+    cgemm_lds<BP>(vr, vi, s.B, false, s.A, 1.0);  // V = L Sinv
+    hacc_to_global<BP>(Ve + 2 * (size_t)c * bb, vr, vi, b);
+    __syncthreads();
+    acc_to_lds<BP>(s.A, wr, wi);  // slot A: W
+    hacc_to_global<BP>(We + 2 * (size_t)c * bb, wr, wi, b);
+    __syncthreads();
+    acc_from_hdiag<BP>(sr, si, p, c + 1, zr, zi);
+    cgemm_lds<BP>(sr, si, s.B, false, s.A, -1.0);  // S_{c+1} = D_{c+1} - L W
+    __syncthreads();
+    acc_to_lds<BP>(s.A, sr, si);
+    __syncthreads();
+  }
+}
+
+template <int BP>
+hipError_t launch_hfactor_bp(const HPencil &p, const Shifts &s, int Ne, double *Sinv, double *W,
+                             double *V, hipStream_t st) {
+  hipError_t err = set_lds<BP>((const void *)hfactor_mfma_kernel<BP>);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(hfactor_mfma_kernel<BP>, dim3(Ne), dim3(kThreads), sizeof(Lds<BP>), st, p,
+                     s, Sinv, W, V);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 size_t wide_pack_doubles(const Pencil &p) {
@@ -1059,6 +1210,17 @@ hipError_t launch_factor_wide(const Pencil &p, const Shifts &s, int Ne, const Fa
   hipLaunchKernelGGL(factor_wide_kernel, dim3(Ne), dim3(kWideThreads), shm, st, p, s, f,
                      (const double *)w.cpl, (const double *)w.dia);
   return hipGetLastError();
+}
+
+hipError_t launch_hfactor_mfma(const HPencil &p, const Shifts &s, int Ne, double *Sinv,
+                               double *W, double *V, hipStream_t st) {
+  if (p.b < 1 || p.b > 64 || Ne < 1) return hipErrorInvalidValue;
+  switch ((p.b + 15) / 16 * 16) {
+    case 16: return launch_hfactor_bp<16>(p, s, Ne, Sinv, W, V, st);
+    case 32: return launch_hfactor_bp<32>(p, s, Ne, Sinv, W, V, st);
+    case 48: return launch_hfactor_bp<48>(p, s, Ne, Sinv, W, V, st);
+    default: return launch_hfactor_bp<64>(p, s, Ne, Sinv, W, V, st);
+  }
 }
 
 size_t factor_work_doubles(const Pencil &p, int Ne, int parts) {

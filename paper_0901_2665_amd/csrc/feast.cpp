@@ -51,12 +51,12 @@ enum Slot {
 namespace {
 // Kernel classes timed by feast_timing / feast_timing_read.
 enum Kind { K_FACTOR, K_FORWARD, K_BACK, K_BTMUL, K_SUM, K_GRAM, K_RR, K_RITZ, K_RESID,
-            K_LAYOUT, K_ROUND, K_FWD32, K_BACK32, K_REFRES, K_COUNT };
+            K_LAYOUT, K_ROUND, K_FWD32, K_BACK32, K_REFRES, K_HSWEEP, K_COUNT };
 const char *kKindNames[K_COUNT] = {"factor",        "forward_sweep",   "back_sweep",
                                    "bt_multiply",   "sum_nodes",       "projection",
                                    "reduced_eig",   "ritz_gemm",       "residual",
                                    "layout",        "round_factors",   "forward_sweep32",
-                                   "back_sweep32",  "refine_residual"};
+                                   "back_sweep32",  "refine_residual", "sweeps_hermitian"};
 struct Timing {
   bool on = false;
   std::vector<hipEvent_t> pool;
@@ -1396,8 +1396,8 @@ int hfilter(feast_ctx *ctx, const HPencil &p, int Ne, const HFactors &f, const d
   const size_t N = (size_t)p.nc * p.b;
   double *G;
   HIPCHK(ensure_t(ctx, S_HG, (size_t)Ne * 2 * N * m * 2, &G));
-  HIPCHK(launch_hsweeps(p, Ne, f.Sinv, f.W, f.V, R, m, G, ctx->stream));
-  HIPCHK(launch_haccumulate(G, Ne, N * m, coef_dev, coef_dev + kMaxNe, Q, ctx->stream));
+  TIMED(K_HSWEEP, launch_hsweeps(p, Ne, f.Sinv, f.W, f.V, R, m, G, ctx->stream));
+  TIMED(K_SUM, launch_haccumulate(G, Ne, N * m, coef_dev, coef_dev + kMaxNe, Q, ctx->stream));
   return 0;
 }
 
@@ -1516,7 +1516,7 @@ int generic_solve(feast_ctx *ctx, const HPencil &p, double emin, double emax, in
   HIPCHK(ensure_t(ctx, S_FLAG, 4, &flag));
   HIPCHK(ensure_t(ctx, S_PERM, (size_t)M0, &perm));
 
-  HIPCHK(launch_hfactor(p, s, Ne, f.Sinv, f.W, f.V, sm));  // once (Sec. V, parallelism (ii))
+  TIMED(K_FACTOR, launch_hfactor(p, s, Ne, f.Sinv, f.W, f.V, sm));  // once (Sec. V, level (ii))
   if (y0) {
     HIPCHK(hipMemcpyAsync(y, y0, nm2 * sizeof(double), hipMemcpyDeviceToDevice, sm));
   } else {  // real and imaginary parts N(0, 1): the real draw of N x 2 M0
@@ -1533,21 +1533,21 @@ int generic_solve(feast_ctx *ctx, const HPencil &p, double emin, double emax, in
   double prev_left_min = INFINITY;
   std::vector<char> is_counted(M0, 0);
   for (int k = 1; k <= o.max_loops; ++k) {
-    HIPCHK(launch_happly(p, 1, y, M0, rr, sm));                       // R = B Y
+    TIMED(K_BTMUL, launch_happly(p, 1, y, M0, rr, sm));                // R = B Y
     st = hfilter(ctx, p, Ne, f, rr, M0, coef, q);                      // Q (eq. 12)
     if (st) return st;
-    HIPCHK(launch_happly(p, 0, q, M0, ax, sm));
-    HIPCHK(launch_happly(p, 1, q, M0, bx, sm));
-    HIPCHK(launch_hgram(q, ax, N, M0, part, aq, sm));                  // A_Q = Q^H A Q
-    HIPCHK(launch_hgram(q, bx, N, M0, part, bq, sm));                  // B_Q = Q^H B Q
+    TIMED(K_GRAM, launch_happly(p, 0, q, M0, ax, sm));
+    TIMED(K_GRAM, launch_happly(p, 1, q, M0, bx, sm));
+    TIMED(K_GRAM, launch_hgram(q, ax, N, M0, part, aq, sm));           // A_Q = Q^H A Q
+    TIMED(K_GRAM, launch_hgram(q, bx, N, M0, part, bq, sm));           // B_Q = Q^H B Q
     // real embedding of the Hermitian pencil
-    HIPCHK(launch_hembed(aq, bq, M0, ea, eb, sm));
-    HIPCHK(launch_reduced_eig(ea, eb, n2, eps2, phi2, scr, flag, sm));
-    HIPCHK(launch_hextract(eps2, phi2, M0, eps, phi, sm));
-    HIPCHK(launch_htall_gemm(q, phi, N, M0, M0, x, sm));              // X = Q Phi
-    HIPCHK(launch_happly(p, 0, x, M0, ax, sm));
-    HIPCHK(launch_happly(p, 1, x, M0, bx, sm));
-    HIPCHK(launch_hresiduals(ax, bx, eps, N, M0, emin, emax, resi, sm));
+    TIMED(K_RR, launch_hembed(aq, bq, M0, ea, eb, sm));
+    TIMED(K_RR, launch_reduced_eig(ea, eb, n2, eps2, phi2, scr, flag, sm));
+    TIMED(K_RR, launch_hextract(eps2, phi2, M0, eps, phi, sm));
+    TIMED(K_RITZ, launch_htall_gemm(q, phi, N, M0, M0, x, sm));       // X = Q Phi
+    TIMED(K_RESID, launch_happly(p, 0, x, M0, ax, sm));
+    TIMED(K_RESID, launch_happly(p, 1, x, M0, bx, sm));
+    TIMED(K_RESID, launch_hresiduals(ax, bx, eps, N, M0, emin, emax, resi, sm));
     HIPCHK(hipMemcpyAsync(h_eps, eps, M0 * sizeof(double), hipMemcpyDeviceToHost, sm));
     HIPCHK(hipMemcpyAsync(h_res, resi, M0 * sizeof(double), hipMemcpyDeviceToHost, sm));
     HIPCHK(hipMemcpyAsync(ctx->h_flag, flag, 3 * sizeof(int), hipMemcpyDeviceToHost, sm));

@@ -259,6 +259,10 @@ size_t hfactor_lds_bytes(int b);
 // [Ne][max(nc-1,1)][b][b] (complex).
 hipError_t launch_hfactor(const HPencil &p, const Shifts &s, int Ne, double *Sinv, double *W,
                           double *V, hipStream_t st);
+// The same factorisation for b <= 64 on the matrix cores (factor.hip), which
+// launch_hfactor takes for those blocks.
+hipError_t launch_hfactor_mfma(const HPencil &p, const Shifts &s, int Ne, double *Sinv,
+                               double *W, double *V, hipStream_t st);
 // Both solves of every node for the complex right-hand side R [N][m]:
 // G [Ne][2][N][m] = (M_e^{-1} R, M_e^{-H} R).
 hipError_t launch_hsweeps(const HPencil &p, int Ne, const double *Sinv, const double *W,

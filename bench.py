@@ -6,7 +6,7 @@ loops to convergence, residuals) on the tight-binding chain workload
 eigenvalues), inputs resident in HBM.  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload tb128k] [--no-extra]
-                  [--precision 0|1] [--graph 0|1] [--no-cpu-baseline]
+                  [--precision 0|1|2] [--graph 0|1|2] [--no-cpu-baseline]
 
 --workload tbbatch times feast_solve_batched on the first --batch uneven
 problems of the batched workload (each step solves all of them);
@@ -16,15 +16,20 @@ b up to 96).
 --graph 1 passes the graph option of feast_solve (loops after the first
 replay one captured HIP graph) to every solve of the batched workload.
 
+--workload htb32k times feast_solve_hermitian (eq. 12) on a complex chain of
+the tb32k shape (nc=500, b=64, n=32000, M0=64, Ne=8, 38 eigenvalues).
+
 --precision 1 times the mixed-precision solver instead (factor blocks rounded
 to float32, complex float32 sweeps, float64 refinement of every shifted solve
-to a relative residual of 1e-12).
+to a relative residual of 1e-12); --precision 2 float32 solves in the first
+loop only.
 
-The default run (tb128k, float64) adds two legs to the same JSON line:
+The default run (tb128k, float64) adds four legs to the same JSON line:
 "mixed" (the mixed-precision solver on the same workload, with its gate
-against the stored oracle result and its time relative to float64) and
-"batched" (32 uneven problems of the batched workload, Ne = 16, solved
-together), each with its own roofline and CPU baseline.
+against the stored oracle result and its time relative to float64),
+"adaptive" (float32 solves in the first loop only), "batched" (the 256
+uneven problems of the full batched shape, Ne = 16, solved together) and
+"hermitian" (the htb32k solve above), each with its own gate and roofline.
 """
 from __future__ import annotations
 
@@ -285,6 +290,97 @@ def solve_leg(ctx, workload, precision, steps, warmup, cpu=True, graph=0):
     return leg
 
 
+def hermitian_cpu_baseline(p, emin, emax, m0, ne, Y0, loops):
+    """The Hermitian oracle on a bounded sample of the same workload: one
+    banded LU of Z_1 B - A, both solves of eq. 12 with all M0 right-hand
+    sides, one projection + reduced eigensolve; extrapolated to Ne shifts and
+    the GPU's loop count."""
+    from oracle import feast_oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max(i["num_threads"] for i in threadpool_info())
+    except Exception:
+        threads = 1
+    ct = O.contour(emin, emax, ne)
+    t0 = time.perf_counter()
+    lu = O.factor_shift_hermitian(p, ct.Z[0])
+    t1 = time.perf_counter()
+    R = O.assemble(p.Bd, p.Bu) @ Y0
+    x = lu.solve(R)
+    y = lu.solve(R, adjoint=True)
+    t2 = time.perf_counter()
+    AQ, BQ = O.project_hermitian(p, x + y)
+    eps, Phi, _ = O.reduced_eig_hermitian(AQ, BQ)
+    _ = (x + y) @ Phi
+    t3 = time.perf_counter()
+    t_factor, t_solve, t_rr = t1 - t0, t2 - t1, t3 - t2
+    t_full = ne * t_factor + loops * (ne * t_solve + t_rr)
+    return {"value": 1.0 / t_full, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+            "sample": (f"1 complex banded LU ({t_factor:.1f}s) + the solve and the adjoint "
+                       f"solve with {m0} right-hand sides ({t_solve:.1f}s) + 1 projection/"
+                       f"Rayleigh-Ritz ({t_rr:.1f}s) of the same workload, extrapolated to "
+                       f"{ne} shifts x {loops} loops = {t_full:.0f}s per solve"),
+            "host": host_cpu()}
+
+
+def hermitian_leg(ctx, steps, warmup, cpu=True, workload="htb32k"):
+    """Complete solves of the Hermitian variant (eq. 12) on a complex chain of
+    the tb32k shape; gated against the eigenvalues that the oracle's inertia
+    bisection stored with the interval."""
+    import torch
+    from paper_0901_2665_amd import feast as F
+    from paper_0901_2665_amd import workloads as W
+    p, emin, emax, m0, ne, Y0 = W.make_workload(workload)
+    wl = W.WORKLOADS[workload]
+    hp = F.HermitianPencil(p.Ad, p.Au, p.Bd, p.Bu)
+    y = torch.as_tensor(np.ascontiguousarray(Y0), dtype=torch.complex128, device="cuda")
+    for _ in range(warmup):
+        r = ctx.solve_hermitian(hp, emin, emax, m0, ne, y)
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    t0 = time.perf_counter()
+    results = []
+    for _ in range(steps):
+        r = ctx.solve_hermitian(hp, emin, emax, m0, ne, y)
+        results.append((r.status, r.M))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    times = ctx.timing_read()
+    ctx.timing(False)
+    ref = np.array(json.load(open(os.path.join(ROOT, "tests", "golden", "intervals.json")))
+                   [workload]["eigenvalues"])
+    lam = r.lam.cpu().numpy()[:r.M]
+    scale = np.maximum(np.abs(ref), 0.5 * (emax - emin))
+    err = float(np.max(np.abs(lam - ref) / scale)) if r.M == len(ref) else None
+    gate = {"M": r.M, "expected_M": wl["n_eig"], "max_res": r.max_res, "loops": r.loops,
+            "status": r.status, "max_rel_eig_err_vs_bisection": err}
+    gate["pass"] = bool(r.M == wl["n_eig"] and r.status == 0 and r.max_res <= 1e-9 and
+                        err is not None and err <= 1e-10 and
+                        all(s_ == 0 and M == r.M for s_, M in results))
+    # nominal work: block LU of a non-symmetric complex block-tridiagonal
+    # matrix per contour point (LU of S_i, W_i, V_i, S_{i+1}: (8/3 + 24) b^3
+    # real flops a cell); per loop both solves of eq. 12, each a forward
+    # (Sinv h, V h) and a back (W x) block product per cell
+    nom = {"factor": ne * p.nc * (80.0 / 3.0) * p.b ** 3,
+           "sweeps_hermitian": ne * p.nc * 48.0 * p.b * p.b * m0}
+    per = {k: {"ms_total": ms, "launches": c, "ms_avg": ms / c} for k, (ms, c) in times.items()
+           if c}
+    dom = max(nom, key=lambda k: times.get(k, (0, 0))[0])
+    ms_dom, n_dom = times[dom]
+    achieved = nom[dom] / (ms_dom / n_dom * 1e-3) / 1e12
+    leg = {"value": steps / elapsed, "unit": "solves/s", "steps": steps, "warmup": warmup,
+           "ms_per_step": 1e3 * elapsed / steps, "dtype": "c128",
+           "config": {"workload": workload, "nc": p.nc, "b": p.b, "n": p.n, "M0": m0, "Ne": ne,
+                      "interval": [emin, emax], "eigenvalues_in_interval": wl["n_eig"],
+                      "tol": 1e-12, "variant": "hermitian (eq. 12)"},
+           "gate": gate, "kernels": per,
+           "roofline": {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": PEAK_FP64,
+                        "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None}}
+    if cpu:
+        leg["cpu_baseline"] = hermitian_cpu_baseline(p, emin, emax, m0, ne, Y0, r.loops)
+    return leg
+
+
 def batch_leg(ctx, count, precision, steps, warmup, workers=0, graph=0, cpu=True,
               workload="tbbatch"):
     """Independent uneven problems solved together by feast_solve_batched;
@@ -419,6 +515,8 @@ def main():
         count = args.batch if args.workload == "tbbatch" else 256
         leg = batch_leg(ctx, count, args.precision, args.steps, args.warmup, args.workers,
                         args.graph, cpu, workload=args.workload)
+    elif args.workload == "htb32k":
+        leg = hermitian_leg(ctx, args.steps, args.warmup, cpu)
     else:
         leg = solve_leg(ctx, args.workload, args.precision, args.steps, args.warmup, cpu,
                         graph=args.graph)
@@ -449,6 +547,11 @@ def main():
         # problem it meets before the timed steps
         line["batched"] = batch_leg(ctx, 256, 0, 2, 2, workers=args.workers, cpu=cpu,
                                     workload="tbbatch256")
+        print(f"bench: batched leg done ({line['batched']['value']:.1f} problems/s)",
+              file=sys.stderr, flush=True)
+        line["hermitian"] = hermitian_leg(ctx, 2, 1, cpu=cpu)
+        print(f"bench: hermitian leg done ({line['hermitian']['value']:.2f} solves/s)",
+              file=sys.stderr, flush=True)
     ctx.close()
     print(json.dumps(line), flush=True)
 

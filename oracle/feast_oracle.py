@@ -625,6 +625,23 @@ def bruteforce(p):
     return scipy.linalg.eigh(A, B)
 
 
+def inertia_count_hermitian(p, sigma: float) -> int:
+    """Number of eigenvalues below sigma of a Hermitian pencil (A complex
+    Hermitian, B real s.p.d.): negative eigenvalues of the block LDL^H Schur
+    complements S_1 = K_11, S_{i+1} = K_{i+1,i+1} - C_i^H S_i^{-1} C_i of
+    K = A - sigma B (Sylvester's law of inertia for Hermitian forms)."""
+    K = p.Ad - sigma * p.Bd
+    C = p.Au - sigma * p.Bu
+    count = 0
+    S = K[0].copy()
+    for i in range(p.nc):
+        ev = np.linalg.eigvalsh(0.5 * (S + S.conj().T))
+        count += int(np.sum(ev < 0))
+        if i + 1 < p.nc:
+            S = K[i + 1] - C[i].conj().T @ np.linalg.solve(S, C[i])
+    return count
+
+
 def inertia_count(p, sigma: float) -> int:
     """Number of eigenvalues of (A, B) below sigma: negative eigenvalues of
     A - sigma B (Sylvester's law of inertia), summed over the block LDL^T

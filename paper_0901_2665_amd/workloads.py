@@ -175,6 +175,23 @@ def hermitian_pencil(nc: int, b: int, seed: int, coupling: float = 0.3,
     return HermitianPencil(Ad, Au, eye + b_scale * Sd, b_scale * Su)
 
 
+def hermitian_chain_pencil(nc: int, b: int, seed: int, phase: float = 1.0) -> HermitianPencil:
+    """Complex Hermitian variant of the config-1 recipe (a magnetic field on
+    the chain): chain_pencil(nc, b, seed) with every hopping entry multiplied
+    by a unit phase exp(i phase U[-pi, pi]), antisymmetric inside a diagonal
+    block (so that it stays Hermitian) and drawn per cell for the couplings;
+    the phases come from a stream of their own, B is the real recipe's."""
+    q = chain_pencil(nc, b, seed)
+    rp = np.random.default_rng(np.random.SeedSequence(seed).spawn(4)[3])
+    th = rp.uniform(-np.pi, np.pi, size=(nc, b, b))
+    th = phase * np.triu(th, 1)
+    th = th - np.transpose(th, (0, 2, 1))
+    Ad = q.Ad * np.exp(1j * th)
+    ps = phase * rp.uniform(-np.pi, np.pi, size=(max(nc - 1, 0), b, b))
+    Au = q.Au * np.exp(1j * ps)
+    return HermitianPencil(Ad, Au, q.Bd, q.Bu)
+
+
 def random_complex_subspace(n: int, m0: int, seed: int) -> np.ndarray:
     """Complex start block: real and imaginary parts N(0, 1/2) (unit variance)."""
     rng = np.random.default_rng(seed)
@@ -210,6 +227,10 @@ WORKLOADS = {
     # a small member of the same recipe for the GPU test of the warm start
     "fam1920": dict(kind="family", nc=60, b=32, M0=32, Ne=8, mseed=4000, yseed=2006,
                     n_eig=19, k0=480),
+    # Hermitian variant (eq. 12): the tb32k shape of the chain recipe with a
+    # phase on every hopping (hermitian_chain_pencil); complex start block
+    "htb32k": dict(kind="hchain", nc=500, b=64, M0=64, Ne=8, mseed=1003, yseed=2007,
+                   n_eig=38, k0=8000),
 }
 
 # Members of the family: s < FAMILY_TRAIN are training members, the next
@@ -316,6 +337,8 @@ def make_pencil(name: str) -> Pencil:
     w = WORKLOADS[name]
     if w["kind"] == "dense":
         return dense_random_pencil(w["nc"], w["b"], w["mseed"])
+    if w["kind"] == "hchain":
+        return hermitian_chain_pencil(w["nc"], w["b"], w["mseed"])
     if w["kind"] == "family":
         return chain_pencil(w["nc"], w["b"], w["mseed"], amplitudes=np.zeros(FAMILY_MODES),
                             family_seed=w["mseed"])
@@ -335,5 +358,8 @@ def make_workload(name: str):
     w = WORKLOADS[name]
     p = make_pencil(name)
     emin, emax = load_interval(name)
-    Y0 = random_subspace(p.n, w["M0"], w["yseed"])
+    if w["kind"] == "hchain":
+        Y0 = random_complex_subspace(p.n, w["M0"], w["yseed"])
+    else:
+        Y0 = random_subspace(p.n, w["M0"], w["yseed"])
     return p, emin, emax, w["M0"], w["Ne"], Y0

@@ -29,36 +29,50 @@ from oracle import feast_oracle as O  # noqa: E402
 from paper_0901_2665_amd import workloads as W  # noqa: E402
 
 
-def kth_eigenvalue(p, j, lo, hi, rtol=1e-13):
+def kth_eigenvalue(p, j, lo, hi, rtol=1e-13, count=O.inertia_count):
     """Bisection for eigenvalue j (0-based): count(lo) <= j < count(hi)."""
     while hi - lo > rtol * max(1.0, abs(lo), abs(hi)):
         mid = 0.5 * (lo + hi)
-        if O.inertia_count(p, mid) <= j:
+        if count(p, mid) <= j:
             lo = mid
         else:
             hi = mid
     return 0.5 * (lo + hi)
 
 
+def _hermitian_eig(args):
+    name, j, lo, hi = args
+    return kth_eigenvalue(W.make_pencil(name), j, lo, hi, rtol=1e-14,
+                          count=O.inertia_count_hermitian)
+
+
 def interval_for(name):
     w = W.WORKLOADS[name]
     p = W.make_pencil(name)
     k0, m = w["k0"], w["n_eig"]
+    herm = w["kind"] == "hchain"
+    count = O.inertia_count_hermitian if herm else O.inertia_count
     if p.n <= 2000:
-        lam = O.bruteforce(p)[0]
+        lam = (O.bruteforce_hermitian(p) if herm else O.bruteforce(p))[0]
         e = [lam[k0 - 1], lam[k0], lam[k0 + m - 1], lam[k0 + m]]
         method = "dense"
     else:
         lo, hi = -100.0, 100.0
-        assert O.inertia_count(p, lo) == 0 and O.inertia_count(p, hi) == p.n
-        e = [kth_eigenvalue(p, j, lo, hi) for j in (k0 - 1, k0, k0 + m - 1, k0 + m)]
+        assert count(p, lo) == 0 and count(p, hi) == p.n
+        e = [kth_eigenvalue(p, j, lo, hi, count=count) for j in (k0 - 1, k0, k0 + m - 1, k0 + m)]
         method = "inertia-bisection"
     emin = 0.5 * (e[0] + e[1])
     emax = 0.5 * (e[2] + e[3])
-    cnt = O.inertia_count(p, emax) - O.inertia_count(p, emin)
+    cnt = count(p, emax) - count(p, emin)
     assert cnt == m, (name, cnt, m)
-    return dict(emin=emin, emax=emax, n_eig=m, k0=k0, method=method,
-                gap_lo=e[1] - e[0], gap_hi=e[3] - e[2])
+    out = dict(emin=emin, emax=emax, n_eig=m, k0=k0, method=method,
+               gap_lo=e[1] - e[0], gap_hi=e[3] - e[2])
+    if herm:  # the eigenvalues inside, by bisection on the inertia count
+        import multiprocessing
+        with multiprocessing.Pool(8) as pool:
+            out["eigenvalues"] = pool.map(_hermitian_eig,
+                                          [(name, j, emin, emax) for j in range(k0, k0 + m)])
+    return out
 
 
 def batch_interval(p):

@@ -157,3 +157,27 @@ def test_solve_hermitian_bad_arguments(ctx, torch):
     with pytest.raises(F.FeastError) as e:
         ctx.solve_hermitian(hpencil(bad), 0.0, 1.0, 4, 8, Y0)
     assert e.value.status == -6
+
+
+def test_solve_hermitian_htb32k(ctx, torch):
+    """The complex chain of the tb32k shape (nc = 500, b = 64, n = 32000,
+    M0 = 64, Ne = 8, a phase on every hopping): the 38 eigenvalues of the
+    interval against the oracle's inertia bisection stored with it, the
+    count, the residual bar, X^H B X = I and the residuals recomputed on the
+    host."""
+    import json
+    import os
+    p, emin, emax, m0, ne, Y0 = W.make_workload("htb32k")
+    golden = os.path.join(os.path.dirname(__file__), "golden", "intervals.json")
+    ref = np.array(json.load(open(golden))["htb32k"]["eigenvalues"])
+    r = ctx.solve_hermitian(hpencil(p), emin, emax, m0, ne, zdev(torch, Y0))
+    assert r.status == 0 and r.M == len(ref) == 38
+    lam = r.lam.cpu().numpy()[:r.M]
+    scale = np.maximum(np.abs(ref), (emax - emin) / 2)
+    assert np.max(np.abs(lam - ref) / scale) <= 1e-10
+    assert r.max_res <= 1e-9 and 2 <= r.loops <= 6
+    X = r.X.cpu().numpy()[:, :r.M]
+    B = O.assemble(p.Bd, p.Bu)
+    assert np.max(np.abs(X.conj().T @ (B @ X) - np.eye(r.M))) <= 1e-9
+    rh = O.residuals_hermitian(p, lam, X, emin, emax)
+    assert np.allclose(rh, r.res.cpu().numpy()[:r.M], rtol=1e-3, atol=1e-14)

@@ -479,6 +479,27 @@ def test_hermitian_pencil_is_hermitian_definite():
     assert np.min(np.linalg.eigvalsh(B)) > 0.5
 
 
+@pytest.mark.parametrize("maker", ["dense", "chain"])
+def test_hermitian_inertia_count_vs_bruteforce(maker):
+    p = W.hermitian_pencil(5, 6, 3) if maker == "dense" else W.hermitian_chain_pencil(6, 8, 5)
+    lam, _ = O.bruteforce_hermitian(p)
+    for s in np.linspace(lam[0] - 1, lam[-1] + 1, 29):
+        assert O.inertia_count_hermitian(p, s) == int(np.sum(lam < s))
+
+
+def test_hermitian_chain_pencil_is_hermitian_definite():
+    # genuinely complex (phases on every hopping), the sparsity of the real
+    # recipe, B that recipe's B
+    p = W.hermitian_chain_pencil(5, 8, 11)
+    q = W.chain_pencil(5, 8, 11)
+    A = O.assemble_hermitian(p.Ad, p.Au).toarray()
+    assert np.max(np.abs(A - A.conj().T)) == 0.0 and np.max(np.abs(A.imag)) > 0.1
+    assert np.allclose(np.abs(p.Ad), np.abs(q.Ad), rtol=1e-15, atol=0)
+    assert np.allclose(np.abs(p.Au), np.abs(q.Au), rtol=1e-15, atol=0)
+    assert np.array_equal(p.Ad != 0, q.Ad != 0) and np.array_equal(p.Au != 0, q.Au != 0)
+    assert np.array_equal(p.Bd, q.Bd) and np.array_equal(p.Bu, q.Bu)
+
+
 def test_hermitian_adjoint_solve():
     # the adjoint solve of the factorised z B - A is a solve with z* B - A
     p = W.hermitian_pencil(4, 5, 2)

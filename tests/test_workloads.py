@@ -38,3 +38,19 @@ def test_batch_shapes_follow_the_recipe():
         s = W.batch_shape(p)
         assert 50 <= s["nc"] <= 200 and s["b"] in (32, 48, 64) and 16 <= s["M0"] <= 64
         assert s["Ne"] == 16 and s["k0"] == s["nc"] * s["b"] // 4
+
+
+def test_hermitian_interval_and_eigenvalues():
+    # htb32k (Hermitian chain, n = 32000): the interval holds its 38
+    # eigenvalues, and the stored ones (bisection on the Hermitian inertia
+    # count) sit where the count steps
+    name = "htb32k"
+    p = W.make_pencil(name)
+    e = json.load(open(os.path.join(GOLDEN, "intervals.json")))[name]
+    k0, m = W.WORKLOADS[name]["k0"], W.WORKLOADS[name]["n_eig"]
+    assert O.inertia_count_hermitian(p, e["emax"]) - O.inertia_count_hermitian(p, e["emin"]) == m
+    lam = e["eigenvalues"]
+    assert len(lam) == m and all(e["emin"] < x < e["emax"] for x in lam)
+    for j in (0, m // 2, m - 1):
+        d = 1e-12 * max(1.0, abs(lam[j]))
+        assert O.inertia_count_hermitian(p, lam[j] - d) <= k0 + j < O.inertia_count_hermitian(p, lam[j] + d)

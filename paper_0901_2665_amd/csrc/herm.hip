@@ -461,6 +461,7 @@ hipError_t launch_hfactor(const HPencil &p, const Shifts &s, int Ne, double *Sin
 hipError_t launch_hsweeps(const HPencil &p, int Ne, const double *Sinv, const double *W,
                           const double *V, const double *R, int m, double *G, hipStream_t st) {
   if (p.b > kMaxHBlock || m < 1) return hipErrorInvalidValue;
+  if (p.b <= 64) return launch_hsweeps_mfma(p, Ne, Sinv, W, V, R, m, G, st);
   dim3 grid(Ne, 2, (m + kCols - 1) / kCols);
   hipLaunchKernelGGL(hsweep_kernel, grid, dim3(kT), 0, st, p, Sinv, W, V, R, m, G);
   return hipGetLastError();

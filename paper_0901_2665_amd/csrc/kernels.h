@@ -267,6 +267,11 @@ hipError_t launch_hfactor_mfma(const HPencil &p, const Shifts &s, int Ne, double
 // G [Ne][2][N][m] = (M_e^{-1} R, M_e^{-H} R).
 hipError_t launch_hsweeps(const HPencil &p, int Ne, const double *Sinv, const double *W,
                           const double *V, const double *R, int m, double *G, hipStream_t st);
+// The same sweeps for b <= 64 on the matrix cores (sweep.hip), which
+// launch_hsweeps takes for those blocks.
+hipError_t launch_hsweeps_mfma(const HPencil &p, int Ne, const double *Sinv, const double *W,
+                               const double *V, const double *R, int m, double *G,
+                               hipStream_t st);
 // Q = sum_e c_e x_e + conj(c_e) y_e over G (Nm = N*m complex entries per slot).
 hipError_t launch_haccumulate(const double *G, int Ne, size_t Nm, const double *cre,
                               const double *cim, double *Q, hipStream_t st);

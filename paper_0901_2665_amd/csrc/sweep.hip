@@ -745,6 +745,207 @@ hipError_t launch_spike_bp(SpikeArgs &a, dim3 grid, hipStream_t st) {
   return hipGetLastError();
 }
 
+// ---- Hermitian A: both solves of eq. 12 on the matrix cores (b <= 64) ----
+//
+// The factors of the non-symmetric M = Z B - A (hfactor_mfma_kernel) are
+// complex interleaved [b][b] blocks: Sinv_c, W_c = Sinv_c C_c, V_c = L_c
+// Sinv_c.  Solve 0 is M x = R (forward h_{c+1} = R_{c+1} - V_c h_c,
+// g_c = Sinv_c h_c; back x_c = g_c - W_c x_{c+1}), solve 1 is M^H y = R with
+// the same blocks conjugate-transposed (W_c^H, Sinv_c^H forward, V_c^H back).
+// The products are the real sweeps' single real product over a doubled inner
+// dimension; the matrix operand op(M)[row][k] is M[row][k] or conj(M[k][row]),
+// one complex element (sixteen bytes) a lane and k-step, zero outside b x b.
+struct HSweepArgs {
+  HPencil p;
+  const double *Sinv, *W, *V;  // [Ne][nc][b][b], [Ne][max(nc-1,1)][b][b] complex
+  const double *R;             // [N][m] complex
+  double *G;                   // [Ne][2][N][m] complex: g, then the solutions
+  int m, ntiles;
+};
+
+// Fragments of M[row][k] (adj: M[k][row]; the conjugate comes from the
+// vector operand's sign2 = -1).  Rows at or beyond b load zeros; columns
+// k >= b meet zero rows of the vector operand, so they may hold any finite
+// value (the next row's entries, or zeros past the block).
+template <int BP>
+__device__ __forceinline__ void hfrag_load(Frag<BP> &f, const double *M, int b, int rb, bool adj,
+                                           bool valid) {
+  const int l = lane_id();
+  const int row = rb * 16 + (l & 15), kl = l >> 4;
+  const auto rs = buf_rsrc(M, valid ? 2 * b * b * 8 : 0);
+  const int vo = row < b ? (adj ? kl * b + row : row * b + kl) * 16 : kBufferOff;
+  const int kstride = adj ? 64 * b : 64;  // bytes from k-step ks to ks + 1
+#pragma unroll
+  for (int ks = 0; ks < BP / 4; ++ks) {
+    const auto x = __builtin_amdgcn_raw_buffer_load_b128(rs, vo, ks * kstride, 0);
+    f.v[ks] = __builtin_bit_cast(double, (u32x2){x[0], x[1]});
+    f.v[BP / 4 + ks] = __builtin_bit_cast(double, (u32x2){x[2], x[3]});
+  }
+}
+
+// bvec_load with the second half (k >= BP) times sign2: sign2 = -1 makes
+// the product use -Mi in place of Mi, the conjugate of the matrix operand.
+template <int BP>
+__device__ __forceinline__ void hbvec_load(double (&b)[BP / 2], const double *hv, double sign2) {
+  constexpr int PL = VecLds<BP>::PL;
+  const int l = lane_id();
+  const int kl = l >> 4, n = l & 15, col = n & 7;
+  const double *h0 = (n < 8) ? hv : hv + PL;  // k < BP
+  const double *h1 = (n < 8) ? hv + PL : hv;  // k >= BP
+  const double s1 = ((n < 8) ? -1.0 : 1.0) * sign2;
+#pragma unroll
+  for (int ks = 0; ks < BP / 4; ++ks) {
+    b[ks] = h0[(4 * ks + kl) * kTile + col];
+    b[BP / 4 + ks] = s1 * h1[(4 * ks + kl) * kTile + col];
+  }
+}
+
+// Accumulator tile (rows of row block rb of cell c, the 8 columns of tile
+// tau as [re | im]) <-> complex interleaved [N][m].
+template <int BP>
+__device__ __forceinline__ int hvec_off(int b, int m, int c, int rb, int r, int tau, bool &in) {
+  const int l = lane_id();
+  const int n = l & 15, row = rb * 16 + acc_row(l, r), col = tau * kTile + (n & 7);
+  in = row < b && col < m;
+  return (((c * b + row) * m + col) * 2 + (n >> 3)) * 8;
+}
+
+template <int BP>
+__device__ __forceinline__ d4 hvec_load(const double *X, int nbytes, int b, int m, int c, int rb,
+                                        int tau, bool valid) {
+  const auto rs = buf_rsrc(X, valid ? nbytes : 0);
+  d4 a;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    bool in;
+    const int off = hvec_off<BP>(b, m, c, rb, r, tau, in);
+    a[r] = buf_load(rs, in ? off : kBufferOff, 0);
+  }
+  return a;
+}
+
+template <int BP>
+__device__ __forceinline__ void hvec_store(double *X, int nbytes, int b, int m, int c, int rb,
+                                           int tau, const d4 &a) {
+  const auto rs = buf_rsrc(X, nbytes);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    bool in;
+    const int off = hvec_off<BP>(b, m, c, rb, r, tau, in);
+    buf_store(a[r], rs, in ? off : kBufferOff, 0);
+  }
+}
+
+// Forward sweep of one (node, solve, tile): the first wave set carries
+// h_{c+1} = R_{c+1} - op(F_c) h_c (F = V, or W for the adjoint), the second
+// computes g_c = op(Sinv_c) h_c into G; LDS keeps u_c = -h_c.
+template <int BP>
+__global__ __launch_bounds__(BP * 8) void hforward_kernel(HSweepArgs a) {
+  __shared__ VecLds<BP> s;
+  constexpr int NW = BP / 16;
+  const int tau = blockIdx.x % a.ntiles;
+  const int grp = blockIdx.x / a.ntiles;  // node * 2 + solve
+  const int e = grp >> 1;
+  const bool adj = (grp & 1) != 0;
+  const int nc = a.p.nc, b = a.p.b, m = a.m;
+  const size_t bb = (size_t)b * b, nf = nc > 1 ? nc - 1 : 1;
+  const int wv = wave_id();
+  const bool wrole = wv < NW;  // wave-uniform
+  const int rb = wrole ? wv : wv - NW;
+  if (wrole) __builtin_amdgcn_s_setprio(2);
+  const double *Mat = wrole ? a.V + 2 * (size_t)e * nf * bb : a.Sinv + 2 * (size_t)e * nc * bb;
+  if (wrole && adj) Mat = a.W + 2 * (size_t)e * nf * bb;
+  const int nbytes = nc * b * m * 16;
+  double *G = a.G + 2 * ((size_t)e * 2 + (adj ? 1 : 0)) * nc * b * m;
+  // the coupling role has no product on the last cell
+  const int last = wrole ? nc - 2 : nc - 1;
+  if (wrole) {
+    const d4 h = hvec_load<BP>(a.R, nbytes, b, m, 0, rb, tau, true);
+    lds_store_vec<BP>(s.v[0], -h, rb);
+  }
+  // fragments and right-hand side tiles one step ahead (two buffers each)
+  Frag<BP> f0, f1;
+  hfrag_load<BP>(f0, Mat, b, rb, adj, 0 <= last);
+  d4 r0 = hvec_load<BP>(a.R, nbytes, b, m, 1, rb, tau, wrole && nc > 1);
+  d4 r1 = d4zero();
+  __syncthreads();
+  int cur = 0;
+  // step on cell c with operands (f = op(Mat_c), r = R_{c+1}); loads the
+  // fragments of cell c+1 and R_{c+2}
+  auto step = [&](int c, const Frag<BP> &f, const d4 &r, Frag<BP> &nf, d4 &nr) {
+    hfrag_load<BP>(nf, Mat + 2 * (size_t)(c + 1) * bb, b, rb, adj, c + 1 <= last);
+    nr = hvec_load<BP>(a.R, nbytes, b, m, c + 2, rb, tau, wrole && c + 2 < nc);
+    double bv[BP / 2];
+    hbvec_load<BP>(bv, s.v[cur], adj ? -1.0 : 1.0);
+    const bool more = c < nc - 1;
+    // coupling role: R_{c+1} + op(F_c) u_c = h_{c+1};  Sinv role: op(Sinv_c) u_c = -g_c
+    const d4 acc = frag_mfma<BP>((wrole && more) ? r : d4zero(), f, bv);
+    if (wrole) {
+      if (more) lds_store_vec<BP>(s.v[cur ^ 1], -acc, rb);
+    } else {
+      hvec_store<BP>(G, nbytes, b, m, c, rb, tau, -acc);
+    }
+    __syncthreads();
+    cur ^= 1;
+  };
+  for (int c = 0; c < nc; c += 2) {
+    step(c, f0, r0, f1, r1);
+    if (c + 1 < nc) step(c + 1, f1, r1, f0, r0);
+  }
+}
+
+// Back sweep: x_{nc-1} = g_{nc-1}, x_c = g_c - op(B_c) x_{c+1} (B = W, or V
+// for the adjoint), overwriting g in G; LDS keeps v = -x.
+template <int BP>
+__global__ __launch_bounds__(BP * 4) void hback_kernel(HSweepArgs a) {
+  __shared__ VecLds<BP> s;
+  const int tau = blockIdx.x % a.ntiles;
+  const int grp = blockIdx.x / a.ntiles;
+  const int e = grp >> 1;
+  const bool adj = (grp & 1) != 0;
+  const int nc = a.p.nc, b = a.p.b, m = a.m;
+  const size_t bb = (size_t)b * b, nf = nc > 1 ? nc - 1 : 1;
+  const int rb = wave_id();
+  const double *Mat = (adj ? a.V : a.W) + 2 * (size_t)e * nf * bb;
+  const int nbytes = nc * b * m * 16;
+  double *G = a.G + 2 * ((size_t)e * 2 + (adj ? 1 : 0)) * nc * b * m;
+  {
+    const d4 x = hvec_load<BP>(G, nbytes, b, m, nc - 1, rb, tau, true);
+    lds_store_vec<BP>(s.v[0], -x, rb);
+  }
+  Frag<BP> f0, f1;
+  hfrag_load<BP>(f0, Mat + 2 * (size_t)(nc - 2) * bb, b, rb, adj, nc >= 2);
+  d4 ga = hvec_load<BP>(G, nbytes, b, m, nc - 2, rb, tau, nc >= 2), gb = d4zero();
+  __syncthreads();
+  int cur = 0;
+  // x_c = g_c + op(B_c) v with operands (f, g); loads cell c-1's
+  auto step = [&](int c, const Frag<BP> &f, const d4 &g, Frag<BP> &nf, d4 &ng) {
+    hfrag_load<BP>(nf, Mat + 2 * (size_t)(c - 1) * bb, b, rb, adj, c >= 1);
+    ng = hvec_load<BP>(G, nbytes, b, m, c - 1, rb, tau, c >= 1);
+    double bv[BP / 2];
+    hbvec_load<BP>(bv, s.v[cur], adj ? -1.0 : 1.0);
+    const d4 x = frag_mfma<BP>(g, f, bv);
+    lds_store_vec<BP>(s.v[cur ^ 1], -x, rb);
+    hvec_store<BP>(G, nbytes, b, m, c, rb, tau, x);
+    __syncthreads();
+    cur ^= 1;
+  };
+  for (int c = nc - 2; c >= 0; c -= 2) {
+    step(c, f0, ga, f1, gb);
+    if (c - 1 >= 0) step(c - 1, f1, gb, f0, ga);
+  }
+}
+
+template <int BP>
+hipError_t launch_hsweeps_bp(HSweepArgs &a, int Ne, hipStream_t st) {
+  const int nblocks = Ne * 2 * a.ntiles;
+  hipLaunchKernelGGL(hforward_kernel<BP>, dim3(nblocks), dim3(BP * 8), 0, st, a);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(hback_kernel<BP>, dim3(nblocks), dim3(BP * 4), 0, st, a);
+  return hipGetLastError();
+}
+
 hipError_t dispatch(SweepArgs &a, int Ne, bool complex_out, int part, hipStream_t st) {
   switch (a.p.bp) {
     case 16: return launch_sweeps_bp<16>(a, Ne, complex_out, part, st);
@@ -793,6 +994,24 @@ hipError_t launch_sweeps_wide(const Pencil &p, const Shifts &s, int Ne, const Fa
   a.m0p = m0p; a.ntiles = m0p / kTile;
   for (int e = 0; e < kMaxNe; ++e) { a.kre[e] = s.kre[e]; a.kim[e] = s.kim[e]; }
   return launch_wide(a, Ne, Xim != nullptr, part, st);
+}
+
+hipError_t launch_hsweeps_mfma(const HPencil &p, int Ne, const double *Sinv, const double *W,
+                               const double *V, const double *R, int m, double *G,
+                               hipStream_t st) {
+  // byte offsets of one [N][m] complex slab stay within 32 bits
+  if (p.b < 1 || p.b > 64 || m < 1 || Ne < 1 ||
+      (size_t)p.nc * p.b * m * 16 > 0x7fffffffu)
+    return hipErrorInvalidValue;
+  HSweepArgs a;
+  a.p = p; a.Sinv = Sinv; a.W = W; a.V = V; a.R = R; a.G = G; a.m = m;
+  a.ntiles = (m + kTile - 1) / kTile;
+  switch ((p.b + 15) / 16 * 16) {
+    case 16: return launch_hsweeps_bp<16>(a, Ne, st);
+    case 32: return launch_hsweeps_bp<32>(a, Ne, st);
+    case 48: return launch_hsweeps_bp<48>(a, Ne, st);
+    default: return launch_hsweeps_bp<64>(a, Ne, st);
+  }
 }
 
 hipError_t launch_sweeps_complex(const Pencil &p, const Shifts &s, const Factors &f,

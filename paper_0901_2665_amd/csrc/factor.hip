@@ -1121,6 +1121,15 @@ __device__ void hacc_to_global(double *g, const d4 (&accr)[BP / 16], const d4 (&
     }
 }
 
+// Twisted: per contour point a top chain (cells 0..m-1, top-down) and a
+// bottom chain (cells nc-1..m, bottom-up), m = nc - nc/2, joined at the twist
+// cell m-1 by hfactor_twist_kernel.  Per cell c of a chain, with X the
+// coupling from c to the next cell in chain order and Y the one back
+// (top: X = C_c, Y = L_c; bottom: X = L_{c-1}, Y = C_{c-1}):
+//   Sinv_c = S_c^{-1},  W_c = Sinv_c X,  V_c = Y Sinv_c,  S_next = D_next - Y W_c,
+// all stored at index c (W and V hold nc blocks a contour point).  The top
+// chain leaves the raw Schur complement S_{m-1} in the unused W[m-1]; the
+// bottom chain stops after W_m and V_m.
 template <int BP>
 __global__ __launch_bounds__(kThreads) void hfactor_mfma_kernel(HPencil p, Shifts sh,
                                                                 double *Sinv, double *W,
@@ -1128,53 +1137,129 @@ __global__ __launch_bounds__(kThreads) void hfactor_mfma_kernel(HPencil p, Shift
   extern __shared__ double smem_raw[];
   Lds<BP> &s = *reinterpret_cast<Lds<BP> *>(smem_raw);
   constexpr int NT = BP / 16;
-  const int e = blockIdx.x, nc = p.nc, b = p.b;
+  const int e = blockIdx.x >> 1;
+  const bool top = (blockIdx.x & 1) == 0;
+  const int nc = p.nc, b = p.b, m = nc - nc / 2;
+  const int len = top ? m : nc - m;
+  if (len <= 0) return;
+  const int start = top ? 0 : nc - 1, dir = top ? 1 : -1;
   const double zr = sh.zre[e], zi = sh.zim[e];
-  const size_t bb = (size_t)b * b, nf = nc > 1 ? nc - 1 : 1;
+  const size_t bb = (size_t)b * b;
   double *Se = Sinv + 2 * (size_t)e * nc * bb;
-  double *We = W + 2 * (size_t)e * nf * bb;
-  double *Ve = V + 2 * (size_t)e * nf * bb;
-  hform_block<BP>(s.A, p, 0, 0, zr, zi);  // S_0 = D_0
+  double *We = W + 2 * (size_t)e * nc * bb;
+  double *Ve = V + 2 * (size_t)e * nc * bb;
+  hform_block<BP>(s.A, p, start, 0, zr, zi);  // S = D_start
   __syncthreads();
-  for (int c = 0; c < nc; ++c) {
-    const bool last = c == nc - 1;
-    // C_c into slot B by waves 1-3 while wave 0 inverts the first pivot tile
+  for (int j = 0; j < len; ++j) {
+    const int c = start + dir * j;
+    const bool last = j == len - 1;
+    if (top && last && nc - m > 0) {  // raw S_{m-1} for the twist kernel
+      hstore_block<BP>(We + 2 * (size_t)c * bb, s.A, b);
+      break;
+    }
+    const bool more = !(top && last);  // the bottom chain's last cell still gets W, V
+    const int cc = top ? c : c - 1;    // cell of the couplings X, Y
+    const int kx = top ? 1 : 2, ky = top ? 2 : 1;
+    // X into slot B by waves 1-3 while wave 0 inverts the first pivot tile
     auto coupling = [&]() {
-      if (!last) hform_block<BP, kThreads - 64>(s.B, p, c, 1, zr, zi, threadIdx.x - 64);
+      if (more) hform_block<BP, kThreads - 64>(s.B, p, cc, kx, zr, zi, threadIdx.x - 64);
     };
     gj_invert<BP>(s, nullptr, coupling, false);  // slot A: Sinv_c
     hstore_block<BP>(Se + 2 * (size_t)c * bb, s.A, b);
-    if (last) break;
+    if (!more) break;
     d4 wr[NT], wi[NT], vr[NT], vi[NT], sr[NT], si[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       wr[t] = d4zero(); wi[t] = d4zero(); vr[t] = d4zero(); vi[t] = d4zero();
     }
-    cgemm_lds<BP>(wr, wi, s.A, false, s.B, 1.0);  // W = Sinv C
+    cgemm_lds<BP>(wr, wi, s.A, false, s.B, 1.0);  // W = Sinv X
     __syncthreads();
-    hform_block<BP>(s.B, p, c, 2, zr, zi);  // slot B: L_c
+    hform_block<BP>(s.B, p, cc, ky, zr, zi);  // slot B: Y
     __syncthreads();
-    cgemm_lds<BP>(vr, vi, s.B, false, s.A, 1.0);  // V = L Sinv
+    cgemm_lds<BP>(vr, vi, s.B, false, s.A, 1.0);  // V = Y Sinv
     hacc_to_global<BP>(Ve + 2 * (size_t)c * bb, vr, vi, b);
     __syncthreads();
     acc_to_lds<BP>(s.A, wr, wi);  // slot A: W
     hacc_to_global<BP>(We + 2 * (size_t)c * bb, wr, wi, b);
     __syncthreads();
-    acc_from_hdiag<BP>(sr, si, p, c + 1, zr, zi);
-    cgemm_lds<BP>(sr, si, s.B, false, s.A, -1.0);  // S_{c+1} = D_{c+1} - L W
+    if (last) break;  // bottom chain: W_m and V_m, no S_{m-1}
+    acc_from_hdiag<BP>(sr, si, p, c + dir, zr, zi);
+    cgemm_lds<BP>(sr, si, s.B, false, s.A, -1.0);  // S_next = D_next - Y W
     __syncthreads();
     acc_to_lds<BP>(s.A, sr, si);
     __syncthreads();
   }
 }
 
+// slot <- complex interleaved [b][b] block (zero padding)
+template <int BP>
+__device__ void hload_block(double *slot, const double *g, int b) {
+  constexpr int LD = Lds<BP>::LD, PLANE = Lds<BP>::PLANE;
+  for (int idx = threadIdx.x; idx < BP * BP; idx += kThreads) {
+    const int r = idx / BP, c = idx % BP;
+    const bool in = r < b && c < b;
+    slot[r * LD + c] = in ? g[2 * (r * b + c)] : 0.0;
+    slot[PLANE + r * LD + c] = in ? g[2 * (r * b + c) + 1] : 0.0;
+  }
+}
+
+// Twist cell m-1: Sinv_{m-1} = T = (S_{m-1} - C_{m-1} W_m)^{-1}, with S_{m-1}
+// (raw, top chain) in W[m-1] and W_m = Sinv_m L_{m-1} of the bottom chain;
+// nothing to do when the bottom chain is empty (nc = 1: the top chain
+// inverted its last cell).
+template <int BP>
+__global__ __launch_bounds__(kThreads) void hfactor_twist_kernel(HPencil p, Shifts sh,
+                                                                 double *Sinv, double *W) {
+  extern __shared__ double smem_raw[];
+  Lds<BP> &s = *reinterpret_cast<Lds<BP> *>(smem_raw);
+  constexpr int NT = BP / 16;
+  const int e = blockIdx.x;
+  const int nc = p.nc, b = p.b, m = nc - nc / 2;
+  if (nc - m == 0) return;
+  const double zr = sh.zre[e], zi = sh.zim[e];
+  const size_t bb = (size_t)b * b;
+  double *We = W + 2 * (size_t)e * nc * bb;
+  hload_block<BP>(s.A, We + 2 * (size_t)(m - 1) * bb, b);  // raw S_{m-1}
+  __syncthreads();
+  d4 tr[NT], ti[NT];
+  {
+    constexpr int LD = Lds<BP>::LD, PLANE = Lds<BP>::PLANE;
+    const int w = wave_id(), l = lane_id();
+    if (w < NT)
+#pragma unroll
+      for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = w * 16 + acc_row(l, r), col = tj * 16 + acc_col(l);
+          // padding rows and columns of S_{m-1} hold the identity
+          const bool in = row < b && col < b;
+          tr[tj][r] = in ? s.A[row * LD + col] : (row == col ? 1.0 : 0.0);
+          ti[tj][r] = in ? s.A[PLANE + row * LD + col] : 0.0;
+        }
+  }
+  __syncthreads();
+  hload_block<BP>(s.A, We + 2 * (size_t)m * bb, b);  // W_m (bottom chain)
+  hform_block<BP>(s.B, p, m - 1, 1, zr, zi);        // C_{m-1}
+  __syncthreads();
+  cgemm_lds<BP>(tr, ti, s.B, false, s.A, -1.0);  // S_{m-1} - C_{m-1} W_m
+  __syncthreads();
+  acc_to_lds<BP>(s.A, tr, ti);
+  __syncthreads();
+  gj_invert<BP>(s, nullptr, NoSide(), false);
+  hstore_block<BP>(Sinv + 2 * ((size_t)e * nc + (m - 1)) * bb, s.A, b);
+}
+
 template <int BP>
 hipError_t launch_hfactor_bp(const HPencil &p, const Shifts &s, int Ne, double *Sinv, double *W,
                              double *V, hipStream_t st) {
   hipError_t err = set_lds<BP>((const void *)hfactor_mfma_kernel<BP>);
+  if (err == hipSuccess) err = set_lds<BP>((const void *)hfactor_twist_kernel<BP>);
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(hfactor_mfma_kernel<BP>, dim3(Ne), dim3(kThreads), sizeof(Lds<BP>), st, p,
-                     s, Sinv, W, V);
+  hipLaunchKernelGGL(hfactor_mfma_kernel<BP>, dim3(2 * Ne), dim3(kThreads), sizeof(Lds<BP>), st,
+                     p, s, Sinv, W, V);
+  if ((err = hipGetLastError()) != hipSuccess) return err;
+  hipLaunchKernelGGL(hfactor_twist_kernel<BP>, dim3(Ne), dim3(kThreads), sizeof(Lds<BP>), st, p,
+                     s, Sinv, W);
   return hipGetLastError();
 }
 

@@ -1383,10 +1383,9 @@ struct HFactors {
 
 int prepare_hfactors(feast_ctx *ctx, const HPencil &p, int Ne, HFactors &f) {
   const size_t bb2 = 2 * (size_t)p.b * p.b;
-  const size_t nf = p.nc > 1 ? p.nc - 1 : 1;
   HIPCHK(ensure_t(ctx, S_HSINV, (size_t)Ne * p.nc * bb2, &f.Sinv));
-  HIPCHK(ensure_t(ctx, S_HW, (size_t)Ne * nf * bb2, &f.W));
-  HIPCHK(ensure_t(ctx, S_HV, (size_t)Ne * nf * bb2, &f.V));
+  HIPCHK(ensure_t(ctx, S_HW, (size_t)Ne * p.nc * bb2, &f.W));
+  HIPCHK(ensure_t(ctx, S_HV, (size_t)Ne * p.nc * bb2, &f.V));
   return 0;
 }
 
@@ -1395,7 +1394,7 @@ int hfilter(feast_ctx *ctx, const HPencil &p, int Ne, const HFactors &f, const d
             const double *coef_dev, double *Q) {
   const size_t N = (size_t)p.nc * p.b;
   double *G;
-  HIPCHK(ensure_t(ctx, S_HG, (size_t)Ne * 2 * N * m * 2, &G));
+  HIPCHK(ensure_t(ctx, S_HG, hsweep_work_doubles(p, Ne, m), &G));
   TIMED(K_HSWEEP, launch_hsweeps(p, Ne, f.Sinv, f.W, f.V, R, m, G, ctx->stream));
   TIMED(K_SUM, launch_haccumulate(G, Ne, N * m, coef_dev, coef_dev + kMaxNe, Q, ctx->stream));
   return 0;
@@ -1435,7 +1434,7 @@ int feast_shifted_solve_hermitian(feast_ctx *ctx, const feast_zbt_matrix *AB, do
   st = prepare_hfactors(ctx, p, 1, f);
   if (st) return st;
   double *G;
-  HIPCHK(ensure_t(ctx, S_HG, 2 * N * m * 2, &G));
+  HIPCHK(ensure_t(ctx, S_HG, hsweep_work_doubles(p, 1, m), &G));
   HIPCHK(launch_hfactor(p, s, 1, f.Sinv, f.W, f.V, ctx->stream));
   HIPCHK(launch_hsweeps(p, 1, f.Sinv, f.W, f.V, R, m, G, ctx->stream));
   HIPCHK(hipMemcpyAsync(X, G + (adjoint ? 2 * N * m : 0), 2 * N * m * sizeof(double),

@@ -255,8 +255,8 @@ struct HPencil {
   int nc, b;
 };
 size_t hfactor_lds_bytes(int b);
-// Block LU of Z_e B - A for every node: Sinv [Ne][nc][b][b], W and V
-// [Ne][max(nc-1,1)][b][b] (complex).
+// Block LU of Z_e B - A for every node: Sinv, W and V [Ne][nc][b][b]
+// (complex; b > 64: W and V use the first max(nc-1,1) blocks of a node).
 hipError_t launch_hfactor(const HPencil &p, const Shifts &s, int Ne, double *Sinv, double *W,
                           double *V, hipStream_t st);
 // The same factorisation for b <= 64 on the matrix cores (factor.hip), which
@@ -264,7 +264,9 @@ hipError_t launch_hfactor(const HPencil &p, const Shifts &s, int Ne, double *Sin
 hipError_t launch_hfactor_mfma(const HPencil &p, const Shifts &s, int Ne, double *Sinv,
                                double *W, double *V, hipStream_t st);
 // Both solves of every node for the complex right-hand side R [N][m]:
-// G [Ne][2][N][m] = (M_e^{-1} R, M_e^{-H} R).
+// G [Ne][2][N][m] = (M_e^{-1} R, M_e^{-H} R), followed by the sweeps' twist
+// slots; G holds hsweep_work_doubles() doubles.
+size_t hsweep_work_doubles(const HPencil &p, int Ne, int m);
 hipError_t launch_hsweeps(const HPencil &p, int Ne, const double *Sinv, const double *W,
                           const double *V, const double *R, int m, double *G, hipStream_t st);
 // The same sweeps for b <= 64 on the matrix cores (sweep.hip), which

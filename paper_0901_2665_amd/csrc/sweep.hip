@@ -747,20 +747,23 @@ hipError_t launch_spike_bp(SpikeArgs &a, dim3 grid, hipStream_t st) {
 
 // ---- Hermitian A: both solves of eq. 12 on the matrix cores (b <= 64) ----
 //
-// The factors of the non-symmetric M = Z B - A (hfactor_mfma_kernel) are
-// complex interleaved [b][b] blocks: Sinv_c, W_c = Sinv_c C_c, V_c = L_c
-// Sinv_c.  Solve 0 is M x = R (forward h_{c+1} = R_{c+1} - V_c h_c,
-// g_c = Sinv_c h_c; back x_c = g_c - W_c x_{c+1}), solve 1 is M^H y = R with
-// the same blocks conjugate-transposed (W_c^H, Sinv_c^H forward, V_c^H back).
+// The twisted factors of the non-symmetric M = Z B - A (hfactor_mfma_kernel)
+// are complex interleaved [b][b] blocks Sinv_c, W_c, V_c (the twist cell's T
+// in Sinv_{m-1}).  Solve 0 is M x = R (forward h_next = R_next - V_c h_c,
+// g_c = Sinv_c h_c; back x_c = g_c - W_c x_prev), solve 1 is M^H y = R with
+// the same blocks conjugate-transposed (W_c^H, Sinv_c^H forward, V_c^H back):
+// the top half runs from cell 0 and the bottom half from cell nc-1 towards
+// the twist cell.
 // The products are the real sweeps' single real product over a doubled inner
 // dimension; the matrix operand op(M)[row][k] is M[row][k] or conj(M[k][row]),
 // one complex element (sixteen bytes) a lane and k-step, zero outside b x b.
 struct HSweepArgs {
   HPencil p;
-  const double *Sinv, *W, *V;  // [Ne][nc][b][b], [Ne][max(nc-1,1)][b][b] complex
+  const double *Sinv, *W, *V;  // [Ne][nc][b][b] complex each
   const double *R;             // [N][m] complex
-  double *G;                   // [Ne][2][N][m] complex: g, then the solutions
-  int m, ntiles;
+  double *G;                   // [Ne][2][N][m] complex: g, then the solutions;
+                               // then the twist slots [Ne][2][ntiles][2][2][BP][8]
+  int m, ntiles, Ne;
 };
 
 // Fragments of M[row][k] (adj: M[k][row]; the conjugate comes from the
@@ -836,92 +839,133 @@ __device__ __forceinline__ void hvec_store(double *X, int nbytes, int b, int m, 
   }
 }
 
-// Forward sweep of one (node, solve, tile): the first wave set carries
-// h_{c+1} = R_{c+1} - op(F_c) h_c (F = V, or W for the adjoint), the second
-// computes g_c = op(Sinv_c) h_c into G; LDS keeps u_c = -h_c.
+// Twisted sweeps of one (node, solve, half, tile) over the twisted factors
+// of hfactor_mfma_kernel (top chain cells 0..m-1, bottom chain nc-1..m, the
+// twist cell m-1 holding T).  Forward: the first wave set carries
+// h_next = R_next - op(F_c) h_c (F = V, or W for the adjoint; the bottom
+// chain's last cell leaves the twist term -op(F_m) h_m instead), the second
+// computes g_c = op(Sinv_c) h_c into G; LDS keeps u_c = -h_c.  The top chain
+// ends with h_{m-1}.  Both go to the tile's two slots TV[0], TV[1] at the end
+// of G.
 template <int BP>
 __global__ __launch_bounds__(BP * 8) void hforward_kernel(HSweepArgs a) {
   __shared__ VecLds<BP> s;
   constexpr int NW = BP / 16;
   const int tau = blockIdx.x % a.ntiles;
-  const int grp = blockIdx.x / a.ntiles;  // node * 2 + solve
-  const int e = grp >> 1;
-  const bool adj = (grp & 1) != 0;
-  const int nc = a.p.nc, b = a.p.b, m = a.m;
-  const size_t bb = (size_t)b * b, nf = nc > 1 ? nc - 1 : 1;
+  const int grp = blockIdx.x / a.ntiles;  // (node * 2 + solve) * 2 + half
+  const int e = grp >> 2;
+  const bool adj = (grp & 2) != 0, top = (grp & 1) == 0;
+  const int nc = a.p.nc, b = a.p.b, m = a.m, mt = nc - nc / 2;
+  const int len = top ? mt : nc - mt;
+  if (len <= 0) return;
+  const int start = top ? 0 : nc - 1, dir = top ? 1 : -1;
+  const int nsteps = top ? len - 1 : len;  // no product at the twist cell
+  const size_t bb = (size_t)b * b;
+  const size_t vt = 2 * (size_t)BP * kTile;
   const int wv = wave_id();
   const bool wrole = wv < NW;  // wave-uniform
   const int rb = wrole ? wv : wv - NW;
   if (wrole) __builtin_amdgcn_s_setprio(2);
-  const double *Mat = wrole ? a.V + 2 * (size_t)e * nf * bb : a.Sinv + 2 * (size_t)e * nc * bb;
-  if (wrole && adj) Mat = a.W + 2 * (size_t)e * nf * bb;
+  const double *Mat = (wrole ? (adj ? a.W : a.V) : a.Sinv) + 2 * (size_t)e * nc * bb;
   const int nbytes = nc * b * m * 16;
-  double *G = a.G + 2 * ((size_t)e * 2 + (adj ? 1 : 0)) * nc * b * m;
-  // the coupling role has no product on the last cell
-  const int last = wrole ? nc - 2 : nc - 1;
+  const size_t slab = 2 * (size_t)nc * b * m;
+  double *G = a.G + ((size_t)e * 2 + (adj ? 1 : 0)) * slab;
+  double *TV = a.G + (size_t)a.Ne * 2 * slab +
+               (((size_t)e * 2 + (adj ? 1 : 0)) * a.ntiles + tau) * 2 * vt;
   if (wrole) {
-    const d4 h = hvec_load<BP>(a.R, nbytes, b, m, 0, rb, tau, true);
+    const d4 h = hvec_load<BP>(a.R, nbytes, b, m, start, rb, tau, true);
     lds_store_vec<BP>(s.v[0], -h, rb);
   }
   // fragments and right-hand side tiles one step ahead (two buffers each)
   Frag<BP> f0, f1;
-  hfrag_load<BP>(f0, Mat, b, rb, adj, 0 <= last);
-  d4 r0 = hvec_load<BP>(a.R, nbytes, b, m, 1, rb, tau, wrole && nc > 1);
+  hfrag_load<BP>(f0, Mat + 2 * (size_t)start * bb, b, rb, adj, nsteps > 0);
+  d4 r0 = hvec_load<BP>(a.R, nbytes, b, m, start + dir, rb, tau, wrole && len > 1);
   d4 r1 = d4zero();
   __syncthreads();
   int cur = 0;
-  // step on cell c with operands (f = op(Mat_c), r = R_{c+1}); loads the
-  // fragments of cell c+1 and R_{c+2}
-  auto step = [&](int c, const Frag<BP> &f, const d4 &r, Frag<BP> &nf, d4 &nr) {
-    hfrag_load<BP>(nf, Mat + 2 * (size_t)(c + 1) * bb, b, rb, adj, c + 1 <= last);
-    nr = hvec_load<BP>(a.R, nbytes, b, m, c + 2, rb, tau, wrole && c + 2 < nc);
+  // step j on cell c with operands (f = op(Mat_c), r = R_{c+dir}); loads the
+  // fragments of cell c+dir and R_{c+2dir}
+  auto step = [&](int j, const Frag<BP> &f, const d4 &r, Frag<BP> &nf, d4 &nr) {
+    const int c = start + dir * j;
+    hfrag_load<BP>(nf, Mat + 2 * (size_t)(c + dir) * bb, b, rb, adj, j + 1 < nsteps);
+    nr = hvec_load<BP>(a.R, nbytes, b, m, c + 2 * dir, rb, tau, wrole && j + 2 < len);
     double bv[BP / 2];
     hbvec_load<BP>(bv, s.v[cur], adj ? -1.0 : 1.0);
-    const bool more = c < nc - 1;
-    // coupling role: R_{c+1} + op(F_c) u_c = h_{c+1};  Sinv role: op(Sinv_c) u_c = -g_c
+    const bool more = j < len - 1;
+    // coupling role: R_{c+dir} + op(F_c) u_c = h_{c+dir};  Sinv role: op(Sinv_c) u_c = -g_c
     const d4 acc = frag_mfma<BP>((wrole && more) ? r : d4zero(), f, bv);
     if (wrole) {
-      if (more) lds_store_vec<BP>(s.v[cur ^ 1], -acc, rb);
+      if (more)
+        lds_store_vec<BP>(s.v[cur ^ 1], -acc, rb);
+      else
+        acc_store_vec<BP>(TV + vt, acc, rb);  // -op(F_m) h_m (bottom chain)
     } else {
       hvec_store<BP>(G, nbytes, b, m, c, rb, tau, -acc);
     }
     __syncthreads();
     cur ^= 1;
   };
-  for (int c = 0; c < nc; c += 2) {
-    step(c, f0, r0, f1, r1);
-    if (c + 1 < nc) step(c + 1, f1, r1, f0, r0);
+  for (int j = 0; j < nsteps; j += 2) {
+    step(j, f0, r0, f1, r1);
+    if (j + 1 < nsteps) step(j + 1, f1, r1, f0, r0);
+  }
+  if (top && wrole) {
+    const d4 u = lds_load_vec<BP>(s.v[cur], rb);
+    acc_store_vec<BP>(TV, -u, rb);  // h_{m-1}
   }
 }
 
-// Back sweep: x_{nc-1} = g_{nc-1}, x_c = g_c - op(B_c) x_{c+1} (B = W, or V
-// for the adjoint), overwriting g in G; LDS keeps v = -x.
+// Back sweep of one (node, solve, half, tile): the twist cell
+// x_{m-1} = op(T) (h_{m-1} - op(F_m) h_m) (written by the top half), then
+// x_c = g_c - op(B_c) x_prev outwards (B = W, or V for the adjoint),
+// overwriting g in G; LDS keeps v = -x.
 template <int BP>
 __global__ __launch_bounds__(BP * 4) void hback_kernel(HSweepArgs a) {
   __shared__ VecLds<BP> s;
   const int tau = blockIdx.x % a.ntiles;
   const int grp = blockIdx.x / a.ntiles;
-  const int e = grp >> 1;
-  const bool adj = (grp & 1) != 0;
-  const int nc = a.p.nc, b = a.p.b, m = a.m;
-  const size_t bb = (size_t)b * b, nf = nc > 1 ? nc - 1 : 1;
+  const int e = grp >> 2;
+  const bool adj = (grp & 2) != 0, top = (grp & 1) == 0;
+  const int nc = a.p.nc, b = a.p.b, m = a.m, mt = nc - nc / 2;
+  const size_t bb = (size_t)b * b;
+  const size_t vt = 2 * (size_t)BP * kTile;
   const int rb = wave_id();
-  const double *Mat = (adj ? a.V : a.W) + 2 * (size_t)e * nf * bb;
+  const double *Sm = a.Sinv + 2 * (size_t)e * nc * bb;
+  const double *Mat = (adj ? a.V : a.W) + 2 * (size_t)e * nc * bb;
   const int nbytes = nc * b * m * 16;
-  double *G = a.G + 2 * ((size_t)e * 2 + (adj ? 1 : 0)) * nc * b * m;
-  {
-    const d4 x = hvec_load<BP>(G, nbytes, b, m, nc - 1, rb, tau, true);
-    lds_store_vec<BP>(s.v[0], -x, rb);
-  }
+  const size_t slab = 2 * (size_t)nc * b * m;
+  double *G = a.G + ((size_t)e * 2 + (adj ? 1 : 0)) * slab;
+  const double *TV = a.G + (size_t)a.Ne * 2 * slab +
+                     (((size_t)e * 2 + (adj ? 1 : 0)) * a.ntiles + tau) * 2 * vt;
+  const int count = top ? mt - 1 : nc - mt;
+  if (!top && count <= 0) return;
+  auto cell = [&](int j) { return top ? (mt - 2 - j) : (mt + j); };
+  // twist cell
   Frag<BP> f0, f1;
-  hfrag_load<BP>(f0, Mat + 2 * (size_t)(nc - 2) * bb, b, rb, adj, nc >= 2);
-  d4 ga = hvec_load<BP>(G, nbytes, b, m, nc - 2, rb, tau, nc >= 2), gb = d4zero();
+  hfrag_load<BP>(f0, Sm + 2 * (size_t)(mt - 1) * bb, b, rb, adj, true);
+  {
+    d4 t = acc_load_vec<BP>(TV, rb);
+    if (nc - mt > 0) t += acc_load_vec<BP>(TV + vt, rb);
+    lds_store_vec<BP>(s.v[1], t, rb);
+  }
+  hfrag_load<BP>(f1, Mat + 2 * (size_t)cell(0) * bb, b, rb, adj, count > 0);
+  d4 ga = hvec_load<BP>(G, nbytes, b, m, cell(0), rb, tau, count > 0), gb = d4zero();
+  __syncthreads();
+  {
+    double bv[BP / 2];
+    hbvec_load<BP>(bv, s.v[1], adj ? -1.0 : 1.0);
+    const d4 x = frag_mfma<BP>(d4zero(), f0, bv);
+    lds_store_vec<BP>(s.v[0], -x, rb);
+    if (top) hvec_store<BP>(G, nbytes, b, m, mt - 1, rb, tau, x);
+  }
   __syncthreads();
   int cur = 0;
-  // x_c = g_c + op(B_c) v with operands (f, g); loads cell c-1's
-  auto step = [&](int c, const Frag<BP> &f, const d4 &g, Frag<BP> &nf, d4 &ng) {
-    hfrag_load<BP>(nf, Mat + 2 * (size_t)(c - 1) * bb, b, rb, adj, c >= 1);
-    ng = hvec_load<BP>(G, nbytes, b, m, c - 1, rb, tau, c >= 1);
+  // x_c = g_c + op(B_c) v with operands (f, g); loads the next cell's
+  auto step = [&](int j, const Frag<BP> &f, const d4 &g, Frag<BP> &nf, d4 &ng) {
+    const int c = cell(j);
+    const bool nx = j + 1 < count;
+    hfrag_load<BP>(nf, Mat + 2 * (size_t)(nx ? cell(j + 1) : c) * bb, b, rb, adj, nx);
+    ng = hvec_load<BP>(G, nbytes, b, m, nx ? cell(j + 1) : c, rb, tau, nx);
     double bv[BP / 2];
     hbvec_load<BP>(bv, s.v[cur], adj ? -1.0 : 1.0);
     const d4 x = frag_mfma<BP>(g, f, bv);
@@ -930,15 +974,15 @@ __global__ __launch_bounds__(BP * 4) void hback_kernel(HSweepArgs a) {
     __syncthreads();
     cur ^= 1;
   };
-  for (int c = nc - 2; c >= 0; c -= 2) {
-    step(c, f0, ga, f1, gb);
-    if (c - 1 >= 0) step(c - 1, f1, gb, f0, ga);
+  for (int j = 0; j < count; j += 2) {
+    step(j, f1, ga, f0, gb);
+    if (j + 1 < count) step(j + 1, f0, gb, f1, ga);
   }
 }
 
 template <int BP>
 hipError_t launch_hsweeps_bp(HSweepArgs &a, int Ne, hipStream_t st) {
-  const int nblocks = Ne * 2 * a.ntiles;
+  const int nblocks = Ne * 2 * 2 * a.ntiles;
   hipLaunchKernelGGL(hforward_kernel<BP>, dim3(nblocks), dim3(BP * 8), 0, st, a);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
@@ -996,6 +1040,12 @@ hipError_t launch_sweeps_wide(const Pencil &p, const Shifts &s, int Ne, const Fa
   return launch_wide(a, Ne, Xim != nullptr, part, st);
 }
 
+size_t hsweep_work_doubles(const HPencil &p, int Ne, int m) {
+  const size_t slabs = (size_t)Ne * 2 * 2 * p.nc * p.b * m;
+  const size_t twist = (size_t)Ne * 2 * ((m + kTile - 1) / kTile) * 2 * (2 * 64 * kTile);
+  return slabs + twist;
+}
+
 hipError_t launch_hsweeps_mfma(const HPencil &p, int Ne, const double *Sinv, const double *W,
                                const double *V, const double *R, int m, double *G,
                                hipStream_t st) {
@@ -1004,7 +1054,7 @@ hipError_t launch_hsweeps_mfma(const HPencil &p, int Ne, const double *Sinv, con
       (size_t)p.nc * p.b * m * 16 > 0x7fffffffu)
     return hipErrorInvalidValue;
   HSweepArgs a;
-  a.p = p; a.Sinv = Sinv; a.W = W; a.V = V; a.R = R; a.G = G; a.m = m;
+  a.p = p; a.Sinv = Sinv; a.W = W; a.V = V; a.R = R; a.G = G; a.m = m; a.Ne = Ne;
   a.ntiles = (m + kTile - 1) / kTile;
   switch ((p.b + 15) / 16 * 16) {
     case 16: return launch_hsweeps_bp<16>(a, Ne, st);

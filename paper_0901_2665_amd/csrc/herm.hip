@@ -475,6 +475,7 @@ hipError_t launch_haccumulate(const double *G, int Ne, size_t Nm, const double *
 
 hipError_t launch_happly(const HPencil &p, int which, const double *Vin, int m, double *out,
                          hipStream_t st) {
+  if (p.b <= 64) return launch_happly_mfma(p, which, Vin, m, out, st);
   hipLaunchKernelGGL(happly_kernel, dim3(grid_of((size_t)p.nc * p.b * m)), dim3(256), 0, st, p,
                      which, Vin, m, out);
   return hipGetLastError();

@@ -280,6 +280,10 @@ hipError_t launch_haccumulate(const double *G, int Ne, size_t Nm, const double *
 // out = A V (which 0) or B V (which 1), complex V and out [N][m].
 hipError_t launch_happly(const HPencil &p, int which, const double *Vin, int m, double *out,
                          hipStream_t st);
+// The same product for b <= 64 on the matrix cores (sweep.hip), which
+// launch_happly takes for those blocks.
+hipError_t launch_happly_mfma(const HPencil &p, int which, const double *V, int m, double *out,
+                              hipStream_t st);
 size_t hgram_partial_doubles(long long N, int m);
 // G = Hermitian part of X^H V (complex [m][m], m <= 64).
 hipError_t launch_hgram(const double *X, const double *Vin, long long N, int m, double *partial,

@@ -980,6 +980,93 @@ __global__ __launch_bounds__(BP * 4) void hback_kernel(HSweepArgs a) {
   }
 }
 
+// out = T V for a Hermitian pencil's block-tridiagonal operator T (which 0:
+// A complex Hermitian, blocks (c, c+1) = Au[c], (c+1, c) = Au[c]^H; which 1:
+// B real symmetric), V and out complex [N][m]; one workgroup per (cell,
+// 8-column tile), one wave per row block: the three block products of the
+// cell accumulate in one tile, the vector tiles of the cell and its two
+// neighbours staged in LDS.
+template <int BP>
+struct HApplyLds {
+  double t[3][2 * VecLds<BP>::PL];
+};
+
+// Fragments of a real block (row-wise, or column-wise for the transpose):
+// imaginary parts zero.
+template <int BP>
+__device__ __forceinline__ void rfrag_load(Frag<BP> &f, const double *M, int b, int rb, bool tr) {
+  const int l = lane_id();
+  const int row = rb * 16 + (l & 15), kl = l >> 4;
+  const auto rs = buf_rsrc(M, b * b * 8);
+  const int vo = row < b ? (tr ? kl * b + row : row * b + kl) * 8 : kBufferOff;
+  const int kstride = tr ? 32 * b : 32;
+#pragma unroll
+  for (int ks = 0; ks < BP / 4; ++ks) {
+    f.v[ks] = buf_load(rs, vo, ks * kstride);
+    f.v[BP / 4 + ks] = 0.0;
+  }
+}
+
+template <int BP>
+__global__ __launch_bounds__(BP * 4) void happly_mfma_kernel(HPencil p, int which, const double *V,
+                                                             int m, int ntiles, double *out) {
+  __shared__ HApplyLds<BP> s;
+  const int c = blockIdx.x / ntiles, tau = blockIdx.x % ntiles;
+  const int nc = p.nc, b = p.b, rb = wave_id();
+  const size_t bb = (size_t)b * b;
+  const int nbytes = nc * b * m * 16;
+  // vector tiles of cells c-1, c, c+1 (zero outside the chain)
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const int cq = c - 1 + q;
+    const d4 v = hvec_load<BP>(V, nbytes, b, m, cq, rb, tau, cq >= 0 && cq < nc);
+    lds_store_vec<BP>(s.t[q], v, rb);
+  }
+  __syncthreads();
+  d4 acc = d4zero();
+  Frag<BP> f;
+  double bv[BP / 2];
+  if (which == 0) {
+    hfrag_load<BP>(f, p.Ad + 2 * (size_t)c * bb, b, rb, false, true);
+    hbvec_load<BP>(bv, s.t[1], 1.0);
+    acc = frag_mfma<BP>(acc, f, bv);
+    if (c + 1 < nc) {
+      hfrag_load<BP>(f, p.Au + 2 * (size_t)c * bb, b, rb, false, true);
+      hbvec_load<BP>(bv, s.t[2], 1.0);
+      acc = frag_mfma<BP>(acc, f, bv);
+    }
+    if (c > 0) {  // Au[c-1]^H: column-wise, conjugate through the vector operand
+      hfrag_load<BP>(f, p.Au + 2 * (size_t)(c - 1) * bb, b, rb, true, true);
+      hbvec_load<BP>(bv, s.t[0], -1.0);
+      acc = frag_mfma<BP>(acc, f, bv);
+    }
+  } else {
+    rfrag_load<BP>(f, p.Bd + (size_t)c * bb, b, rb, false);
+    hbvec_load<BP>(bv, s.t[1], 1.0);
+    acc = frag_mfma<BP>(acc, f, bv);
+    if (c + 1 < nc) {
+      rfrag_load<BP>(f, p.Bu + (size_t)c * bb, b, rb, false);
+      hbvec_load<BP>(bv, s.t[2], 1.0);
+      acc = frag_mfma<BP>(acc, f, bv);
+    }
+    if (c > 0) {
+      rfrag_load<BP>(f, p.Bu + (size_t)(c - 1) * bb, b, rb, true);
+      hbvec_load<BP>(bv, s.t[0], 1.0);
+      acc = frag_mfma<BP>(acc, f, bv);
+    }
+  }
+  hvec_store<BP>(out, nbytes, b, m, c, rb, tau, acc);
+}
+
+template <int BP>
+hipError_t launch_happly_bp(const HPencil &p, int which, const double *V, int m, double *out,
+                            hipStream_t st) {
+  const int ntiles = (m + kTile - 1) / kTile;
+  hipLaunchKernelGGL(happly_mfma_kernel<BP>, dim3(p.nc * ntiles), dim3(BP * 4), 0, st, p, which,
+                     V, m, ntiles, out);
+  return hipGetLastError();
+}
+
 template <int BP>
 hipError_t launch_hsweeps_bp(HSweepArgs &a, int Ne, hipStream_t st) {
   const int nblocks = Ne * 2 * 2 * a.ntiles;
@@ -1038,6 +1125,18 @@ hipError_t launch_sweeps_wide(const Pencil &p, const Shifts &s, int Ne, const Fa
   a.m0p = m0p; a.ntiles = m0p / kTile;
   for (int e = 0; e < kMaxNe; ++e) { a.kre[e] = s.kre[e]; a.kim[e] = s.kim[e]; }
   return launch_wide(a, Ne, Xim != nullptr, part, st);
+}
+
+hipError_t launch_happly_mfma(const HPencil &p, int which, const double *V, int m, double *out,
+                              hipStream_t st) {
+  if (p.b < 1 || p.b > 64 || m < 1 || (size_t)p.nc * p.b * m * 16 > 0x7fffffffu)
+    return hipErrorInvalidValue;
+  switch ((p.b + 15) / 16 * 16) {
+    case 16: return launch_happly_bp<16>(p, which, V, m, out, st);
+    case 32: return launch_happly_bp<32>(p, which, V, m, out, st);
+    case 48: return launch_happly_bp<48>(p, which, V, m, out, st);
+    default: return launch_happly_bp<64>(p, which, V, m, out, st);
+  }
 }
 
 size_t hsweep_work_doubles(const HPencil &p, int Ne, int m) {

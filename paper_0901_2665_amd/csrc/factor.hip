@@ -873,7 +873,6 @@ __global__ __launch_bounds__(kWideThreads) void factor_wide_kernel(Pencil p, Shi
   const int nc = p.nc, b = p.b;
   const double zr = sh.zre[e], zi = sh.zim[e];
   const size_t blk = 2 * (size_t)BP * BP, per = (size_t)BP * BP;
-  const size_t bb = (size_t)b * b;
   double *Sinv = f.Sinv + (size_t)e * nc * blk;
   double *Wg = f.W + (size_t)e * nc * blk;
   double *WTg = f.WT + (size_t)e * nc * blk;

@@ -391,8 +391,10 @@ int feast_timing_read(feast_ctx *ctx, int32_t kind, const char **name, double *t
  * pairs.  Complex arrays are interleaved (re, im) doubles (C99 double
  * complex, torch.complex128).  Counting, convergence, residual and output
  * order as in feast_solve (residual 1-norms of complex moduli).
- * Limits: b <= 96, M0 <= 64.  The factorisation runs one workgroup per
- * contour point over all cells in order (no partitions).
+ * Limits: b <= 96, M0 <= 64.  For b <= 64 the factorisation is twisted and
+ * partitioned as for feast_solve (opts.partitions per half chain, 0 =
+ * automatic by the same rule); 64 < b <= 96 factors one chain per contour
+ * point in order.
  */
 typedef struct {
   int32_t nc;            /* number of cells, >= 1 */
@@ -413,10 +415,11 @@ int feast_solve_hermitian(feast_ctx *ctx, const feast_zbt_matrix *AB, double emi
                           int32_t M0, int32_t Ne, const feast_opts *opts, double *lambda,
                           double *X, double *res, feast_info *info);
 /* X (dev, complex [N][m]) = (z B - A)^{-1} R, or (z B - A)^{-H} R when
- * adjoint != 0, for complex R (dev) [N][m], Im z > 0, m <= 64. */
+ * adjoint != 0, for complex R (dev) [N][m], Im z > 0, m <= 64.  partitions
+ * as in feast_opts (0 = automatic, ignored for b > 64; -7 if negative). */
 int feast_shifted_solve_hermitian(feast_ctx *ctx, const feast_zbt_matrix *AB, double z_re,
                                   double z_im, int32_t m, const double *R, int32_t adjoint,
-                                  double *X);
+                                  double *X, int32_t partitions);
 /* One contour integration of eq. 12 (RHS B Y): Y, Q (dev) complex [N][M0]. */
 int feast_filter_hermitian(feast_ctx *ctx, const feast_zbt_matrix *AB, double emin, double emax,
                            int32_t M0, int32_t Ne, const double *Y, double *Q);

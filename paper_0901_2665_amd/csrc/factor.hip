@@ -1120,44 +1120,156 @@ __device__ void hacc_to_global(double *g, const d4 (&accr)[BP / 16], const d4 (&
     }
 }
 
+// Operands of the Hermitian block products: an LDS slot, or a complex
+// interleaved [b][b] block in global memory read as zero outside b x b.
+template <int BP>
+struct SlotOp {
+  const double *s;
+  __device__ __forceinline__ void ld(int r, int c, double &re, double &im) const {
+    re = s[r * Lds<BP>::LD + c];
+    im = s[Lds<BP>::PLANE + r * Lds<BP>::LD + c];
+  }
+};
+struct GlobOp {
+  const double *g;
+  int b;
+  __device__ __forceinline__ void ld(int r, int c, double &re, double &im) const {
+    const bool in = r < b && c < b;
+    const double2 v = *reinterpret_cast<const double2 *>(g + (in ? 2 * (r * b + c) : 0));
+    re = in ? v.x : 0.0;
+    im = in ? v.y : 0.0;
+  }
+};
+
+// acc (+)= sign * X * Y with either operand in LDS or in global memory; the
+// three-product form of cgemm_lds.
+template <int BP, class OX, class OY>
+__device__ __forceinline__ void cgemm_op(d4 (&accr)[BP / 16], d4 (&acci)[BP / 16], OX X, OY Y,
+                                         double sign) {
+  constexpr int NT = BP / 16;
+  const int w = wave_id(), l = lane_id();
+  if (w >= NT) return;
+  const int row = w * 16 + (l & 15);
+  const int kl = l >> 4;
+  d4 t1[NT];
+#pragma unroll
+  for (int tj = 0; tj < NT; ++tj) t1[tj] = d4zero();
+#pragma unroll 4  // fully unrolled, the hoisted global loads spill
+  for (int k0 = 0; k0 < BP; k0 += 4) {
+    const int k = k0 + kl;
+    double xr, xi;
+    X.ld(row, k, xr, xi);
+    xr *= sign;
+    xi *= sign;
+    const double xs = -(xr + xi), xd = xi - xr;
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj) {
+      double yr, yi;
+      Y.ld(k, tj * 16 + (l & 15), yr, yi);
+      t1[tj] = mfma(xr, yr + yi, t1[tj]);
+      accr[tj] = mfma(xs, yi, accr[tj]);
+      acci[tj] = mfma(xd, yr, acci[tj]);
+    }
+  }
+#pragma unroll
+  for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      accr[tj][q] += t1[tj][q];
+      acci[tj][q] += t1[tj][q];
+    }
+}
+
+template <int BP>
+__device__ __forceinline__ void acc_fill(d4 (&accr)[BP / 16], d4 (&acci)[BP / 16], double diag) {
+  const int l = lane_id(), w = wave_id();
+#pragma unroll
+  for (int tj = 0; tj < BP / 16; ++tj)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      accr[tj][r] = (w * 16 + acc_row(l, r) == tj * 16 + acc_col(l)) ? diag : 0.0;
+      acci[tj][r] = 0.0;
+    }
+}
+
+// acc <- complex interleaved [b][b] block (zero outside b x b)
+template <int BP>
+__device__ void hacc_from_global(d4 (&accr)[BP / 16], d4 (&acci)[BP / 16], const double *g,
+                                 int b) {
+  const int w = wave_id(), l = lane_id();
+  if (w >= BP / 16) return;
+  const GlobOp G{g, b};
+#pragma unroll
+  for (int tj = 0; tj < BP / 16; ++tj)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      double re, im;
+      G.ld(w * 16 + acc_row(l, r), tj * 16 + acc_col(l), re, im);
+      accr[tj][r] = re;
+      acci[tj][r] = im;
+    }
+}
+
+template <int BP>
+__device__ __forceinline__ void acc_negate(d4 (&accr)[BP / 16], d4 (&acci)[BP / 16]) {
+#pragma unroll
+  for (int tj = 0; tj < BP / 16; ++tj) {
+    accr[tj] = -accr[tj];
+    acci[tj] = -acci[tj];
+  }
+}
+
+// slot -= K (complex interleaved [b][b]) on the leading b x b block
+template <int BP>
+__device__ void hsub_block(double *slot, const double *K, int b) {
+  constexpr int LD = Lds<BP>::LD, PLANE = Lds<BP>::PLANE;
+  for (int idx = threadIdx.x; idx < b * b; idx += kThreads) {
+    const int r = idx / b, c = idx % b;
+    slot[r * LD + c] -= K[2 * idx];
+    slot[PLANE + r * LD + c] -= K[2 * idx + 1];
+  }
+}
+
+// Blocks a (chain, partition) keeps in the factorisation's work area.
+enum HWork { HW_K, HW_G11, HW_YH, HW_XH, HW_YGX, HW_P0, HW_P1, HW_Q, HW_T, HW_COUNT };
+
 // Twisted: per contour point a top chain (cells 0..m-1, top-down) and a
 // bottom chain (cells nc-1..m, bottom-up), m = nc - nc/2, joined at the twist
-// cell m-1 by hfactor_twist_kernel.  Per cell c of a chain, with X the
-// coupling from c to the next cell in chain order and Y the one back
-// (top: X = C_c, Y = L_c; bottom: X = L_{c-1}, Y = C_{c-1}):
+// cell m-1 by hfactor_twist_kernel.  Chain position j is cell j (top) or
+// nc-1-j (bottom).  Per cell c of a chain, with X the coupling from c to the
+// next cell in chain order and Y the one back (top: X = C_c, Y = L_c;
+// bottom: X = L_{c-1}, Y = C_{c-1}):
 //   Sinv_c = S_c^{-1},  W_c = Sinv_c X,  V_c = Y Sinv_c,  S_next = D_next - Y W_c,
 // all stored at index c (W and V hold nc blocks a contour point).  The top
 // chain leaves the raw Schur complement S_{m-1} in the unused W[m-1]; the
 // bottom chain stops after W_m and V_m.
+//
+// hchain_final runs chain positions [jb, je) from S = D - K at jb (K: the
+// self-energy of the part of the chain before jb, none for the first
+// partition) and stores the factors.
 template <int BP>
-__global__ __launch_bounds__(kThreads) void hfactor_mfma_kernel(HPencil p, Shifts sh,
-                                                                double *Sinv, double *W,
-                                                                double *V) {
-  extern __shared__ double smem_raw[];
-  Lds<BP> &s = *reinterpret_cast<Lds<BP> *>(smem_raw);
+__device__ void hchain_final(Lds<BP> &s, const HPencil &p, double zr, double zi, bool top,
+                             int len, int jb, int je, const double *K, double *Se, double *We,
+                             double *Ve) {
   constexpr int NT = BP / 16;
-  const int e = blockIdx.x >> 1;
-  const bool top = (blockIdx.x & 1) == 0;
   const int nc = p.nc, b = p.b, m = nc - nc / 2;
-  const int len = top ? m : nc - m;
-  if (len <= 0) return;
-  const int start = top ? 0 : nc - 1, dir = top ? 1 : -1;
-  const double zr = sh.zre[e], zi = sh.zim[e];
   const size_t bb = (size_t)b * b;
-  double *Se = Sinv + 2 * (size_t)e * nc * bb;
-  double *We = W + 2 * (size_t)e * nc * bb;
-  double *Ve = V + 2 * (size_t)e * nc * bb;
-  hform_block<BP>(s.A, p, start, 0, zr, zi);  // S = D_start
+  auto cell = [&](int j) { return top ? j : nc - 1 - j; };
+  hform_block<BP>(s.A, p, cell(jb), 0, zr, zi);  // S = D_jb
+  if (K) {
+    __syncthreads();
+    hsub_block<BP>(s.A, K, b);  // S = D_jb - K
+  }
   __syncthreads();
-  for (int j = 0; j < len; ++j) {
-    const int c = start + dir * j;
-    const bool last = j == len - 1;
-    if (top && last && nc - m > 0) {  // raw S_{m-1} for the twist kernel
+  for (int j = jb; j < je; ++j) {
+    const int c = cell(j);
+    const bool chain_last = j == len - 1;
+    if (top && chain_last && nc - m > 0) {  // raw S_{m-1} for the twist kernel
       hstore_block<BP>(We + 2 * (size_t)c * bb, s.A, b);
       break;
     }
-    const bool more = !(top && last);  // the bottom chain's last cell still gets W, V
-    const int cc = top ? c : c - 1;    // cell of the couplings X, Y
+    const bool more = !(top && chain_last);  // the bottom chain's last cell still gets W, V
+    const int cc = top ? c : c - 1;          // cell of the couplings X, Y
     const int kx = top ? 1 : 2, ky = top ? 2 : 1;
     // X into slot B by waves 1-3 while wave 0 inverts the first pivot tile
     auto coupling = [&]() {
@@ -1181,13 +1293,146 @@ __global__ __launch_bounds__(kThreads) void hfactor_mfma_kernel(HPencil p, Shift
     acc_to_lds<BP>(s.A, wr, wi);  // slot A: W
     hacc_to_global<BP>(We + 2 * (size_t)c * bb, wr, wi, b);
     __syncthreads();
-    if (last) break;  // bottom chain: W_m and V_m, no S_{m-1}
-    acc_from_hdiag<BP>(sr, si, p, c + dir, zr, zi);
+    if (j == je - 1) break;  // end of the partition (bottom chain: W_m and V_m, no S_{m-1})
+    acc_from_hdiag<BP>(sr, si, p, cell(j + 1), zr, zi);
     cgemm_lds<BP>(sr, si, s.B, false, s.A, -1.0);  // S_next = D_next - Y W
     __syncthreads();
     acc_to_lds<BP>(s.A, sr, si);
     __syncthreads();
   }
+}
+
+// hchain_local factors chain positions [jb, je) on their own (from S = D_jb)
+// for the corner blocks of the inverse G of that diagonal section: G11
+// (first, first), GL1 (last, first), G1L (first, last), GLL (last, last).
+// With the local factors Sinv'_t, W'_t, V'_t (t = 0..L-1) and
+//   P_0 = Q_0 = I,  P_{t+1} = -V'_t P_t,  Q_{t+1} = -Q_t W'_t,
+// the first block column of G ends in GL1 = Sinv'_L-1 P_L-1, the first block
+// row in G1L = Q_L-1 Sinv'_L-1, and appending cell t to the section adds
+// Q_t Sinv'_t P_t to G11 (Schur complement of the new cell).  With X, Y the
+// couplings to the next partition it leaves G11, YH = Y GL1, XH = G1L X and
+// YGX = Y GLL X.  W'_t and V'_t pass through the factor arrays, which the
+// exact rerun overwrites.
+template <int BP>
+__device__ void hchain_local(Lds<BP> &s, const HPencil &p, double zr, double zi, bool top,
+                             int jb, int je, double *wk, double *We, double *Ve) {
+  constexpr int NT = BP / 16;
+  const int nc = p.nc, b = p.b;
+  const size_t bb = (size_t)b * b, bb2 = 2 * bb;
+  double *G11 = wk + HW_G11 * bb2, *YH = wk + HW_YH * bb2, *XH = wk + HW_XH * bb2;
+  double *YGX = wk + HW_YGX * bb2, *Q = wk + HW_Q * bb2, *T = wk + HW_T * bb2;
+  double *Pb[2] = {wk + HW_P0 * bb2, wk + HW_P1 * bb2};
+  const int L = je - jb;
+  auto cell = [&](int j) { return top ? j : nc - 1 - j; };
+  hform_block<BP>(s.A, p, cell(jb), 0, zr, zi);  // S'_0 = D_jb
+  __syncthreads();
+  for (int t = 0; t < L; ++t) {
+    const int c = cell(jb + t);
+    const bool last = t == L - 1;
+    const int cc = top ? c : c - 1;
+    const int kx = top ? 1 : 2, ky = top ? 2 : 1;
+    auto coupling = [&]() {
+      hform_block<BP, kThreads - 64>(s.B, p, cc, kx, zr, zi, threadIdx.x - 64);
+    };
+    gj_invert<BP>(s, nullptr, coupling, false);  // slot A: Sinv'_t, slot B: X
+    const double *Pc = Pb[t & 1];
+    double *Pn = Pb[(t + 1) & 1];
+    d4 ar[NT], ai[NT];
+    if (t == 0) {
+      hstore_block<BP>(G11, s.A, b);
+      if (last) hstore_block<BP>(T, s.A, b);  // GL1 = Sinv'_0
+    } else {
+      acc_fill<BP>(ar, ai, 0.0);
+      cgemm_op<BP>(ar, ai, SlotOp<BP>{s.A}, GlobOp{Pc, b}, 1.0);  // Sinv'_t P_t
+      hacc_to_global<BP>(T, ar, ai, b);
+      __syncthreads();
+      hacc_from_global<BP>(ar, ai, G11, b);
+      cgemm_op<BP>(ar, ai, GlobOp{Q, b}, GlobOp{T, b}, 1.0);  // G11 += Q_t Sinv'_t P_t
+      hacc_to_global<BP>(G11, ar, ai, b);
+    }
+    d4 wr[NT], wi[NT];
+    acc_fill<BP>(wr, wi, 0.0);
+    cgemm_lds<BP>(wr, wi, s.A, false, s.B, 1.0);  // W' = Sinv' X
+    __syncthreads();
+    hform_block<BP>(s.B, p, cc, ky, zr, zi);  // slot B: Y
+    if (last) {  // XH = Q_t W', YGX = Y W', YH = Y GL1
+      acc_to_lds<BP>(s.A, wr, wi);
+      if (t == 0) hacc_to_global<BP>(XH, wr, wi, b);
+      __syncthreads();
+      if (t > 0) {
+        acc_fill<BP>(ar, ai, 0.0);
+        cgemm_op<BP>(ar, ai, GlobOp{Q, b}, SlotOp<BP>{s.A}, 1.0);
+        hacc_to_global<BP>(XH, ar, ai, b);
+      }
+      acc_fill<BP>(ar, ai, 0.0);
+      cgemm_lds<BP>(ar, ai, s.B, false, s.A, 1.0);
+      hacc_to_global<BP>(YGX, ar, ai, b);
+      acc_fill<BP>(ar, ai, 0.0);
+      cgemm_op<BP>(ar, ai, SlotOp<BP>{s.B}, GlobOp{T, b}, 1.0);
+      hacc_to_global<BP>(YH, ar, ai, b);
+      break;
+    }
+    __syncthreads();
+    double *Vc = Ve + 2 * (size_t)c * bb;
+    acc_fill<BP>(ar, ai, 0.0);
+    cgemm_lds<BP>(ar, ai, s.B, false, s.A, 1.0);  // V' = Y Sinv'
+    if (t == 0) {
+      acc_negate<BP>(ar, ai);
+      hacc_to_global<BP>(Pn, ar, ai, b);  // P_1 = -V'_0
+    } else {
+      hacc_to_global<BP>(Vc, ar, ai, b);
+    }
+    __syncthreads();
+    acc_to_lds<BP>(s.A, wr, wi);  // slot A: W'
+    if (t == 0) {
+      acc_negate<BP>(wr, wi);
+      hacc_to_global<BP>(Q, wr, wi, b);  // Q_1 = -W'_0
+    }
+    __syncthreads();
+    if (t > 0) {
+      acc_fill<BP>(ar, ai, 0.0);
+      cgemm_op<BP>(ar, ai, GlobOp{Q, b}, SlotOp<BP>{s.A}, -1.0);  // Q_{t+1} = -Q_t W'_t
+      hacc_to_global<BP>(Q, ar, ai, b);  // in place: a wave reads and writes its own rows
+      acc_fill<BP>(ar, ai, 0.0);
+      cgemm_op<BP>(ar, ai, GlobOp{Vc, b}, GlobOp{Pc, b}, -1.0);  // P_{t+1} = -V'_t P_t
+      hacc_to_global<BP>(Pn, ar, ai, b);
+    }
+    acc_from_hdiag<BP>(ar, ai, p, cell(jb + t + 1), zr, zi);
+    cgemm_lds<BP>(ar, ai, s.B, false, s.A, -1.0);  // S'_{t+1} = D - Y W'
+    __syncthreads();
+    acc_to_lds<BP>(s.A, ar, ai);
+    __syncthreads();
+  }
+}
+
+// Partition q of a chain covers positions [q len / P, (q+1) len / P).  Phase
+// 0: partition 0 exactly, partitions 1..P-2 locally; phase 1: the exact
+// rerun of partitions 1..P-1 from the self-energies of hinterface_kernel.
+template <int BP>
+__global__ __launch_bounds__(kThreads) void hfactor_part_kernel(HPencil p, Shifts sh,
+                                                                double *Sinv, double *W,
+                                                                double *V, double *work,
+                                                                int P, int phase) {
+  extern __shared__ double smem_raw[];
+  Lds<BP> &s = *reinterpret_cast<Lds<BP> *>(smem_raw);
+  const int per = phase == 0 ? (P > 1 ? P - 1 : 1) : P - 1;
+  const int ch = blockIdx.x / per, q = blockIdx.x % per + phase;
+  const int e = ch >> 1;
+  const bool top = (ch & 1) == 0;
+  const int nc = p.nc, m = nc - nc / 2;
+  const int len = top ? m : nc - m;
+  if (len <= 0) return;
+  const int jb = (int)((long long)q * len / P), je = (int)((long long)(q + 1) * len / P);
+  const double zr = sh.zre[e], zi = sh.zim[e];
+  const size_t bb2 = 2 * (size_t)p.b * p.b;
+  double *Se = Sinv + (size_t)e * nc * bb2;
+  double *We = W + (size_t)e * nc * bb2;
+  double *Ve = V + (size_t)e * nc * bb2;
+  double *wk = work + ((size_t)ch * P + q) * HW_COUNT * bb2;
+  if (q == 0 || phase == 1)
+    hchain_final<BP>(s, p, zr, zi, top, len, jb, je, q ? wk + HW_K * bb2 : nullptr, Se, We, Ve);
+  else
+    hchain_local<BP>(s, p, zr, zi, top, jb, je, wk, We, Ve);
 }
 
 // slot <- complex interleaved [b][b] block (zero padding)
@@ -1248,17 +1493,91 @@ __global__ __launch_bounds__(kThreads) void hfactor_twist_kernel(HPencil p, Shif
   hstore_block<BP>(Sinv + 2 * ((size_t)e * nc + (m - 1)) * bb, s.A, b);
 }
 
+// Self-energies across the partitions of a chain, one workgroup a chain, in
+// chain order: partition q starts from D - K_q, K_q = Y Sinv_e X with X, Y
+// the couplings between partitions q-1 and q and Sinv_e the exact inverse
+// Schur complement at the last position of partition q-1.  K_1 = V X from
+// the exact pass; otherwise partition q-1 started from D - K_{q-1}, and the
+// Woodbury identity on its local inverse,
+//   Sinv_e = GLL + GL1 K_{q-1} (I - G11 K_{q-1})^{-1} G1L,
+// gives K_q = YGX + YH K_{q-1} (I - G11 K_{q-1})^{-1} XH.
+template <int BP>
+__global__ __launch_bounds__(kThreads) void hinterface_kernel(HPencil p, Shifts sh,
+                                                              const double *V, double *work,
+                                                              int P) {
+  extern __shared__ double smem_raw[];
+  Lds<BP> &s = *reinterpret_cast<Lds<BP> *>(smem_raw);
+  constexpr int NT = BP / 16;
+  const int ch = blockIdx.x, e = ch >> 1;
+  const bool top = (ch & 1) == 0;
+  const int nc = p.nc, b = p.b, m = nc - nc / 2;
+  const int len = top ? m : nc - m;
+  if (len <= 0 || P < 2) return;
+  const double zr = sh.zre[e], zi = sh.zim[e];
+  const size_t bb2 = 2 * (size_t)b * b;
+  double *wch = work + (size_t)ch * P * HW_COUNT * bb2;
+  d4 ar[NT], ai[NT];
+  {  // K_1 = V_c X at the last position of partition 0
+    const int jl = len / P - 1;
+    const int c = top ? jl : nc - 1 - jl, cc = top ? c : c - 1;
+    hload_block<BP>(s.A, V + ((size_t)e * nc + c) * bb2, b);
+    hform_block<BP>(s.B, p, cc, top ? 1 : 2, zr, zi);
+    __syncthreads();
+    acc_fill<BP>(ar, ai, 0.0);
+    cgemm_lds<BP>(ar, ai, s.A, false, s.B, 1.0);
+    hacc_to_global<BP>(wch + ((size_t)HW_COUNT + HW_K) * bb2, ar, ai, b);
+    __syncthreads();
+  }
+  for (int q = 2; q < P; ++q) {
+    const double *wq = wch + (size_t)(q - 1) * HW_COUNT * bb2;
+    hload_block<BP>(s.A, wq + HW_G11 * bb2, b);
+    hload_block<BP>(s.B, wq + HW_K * bb2, b);
+    __syncthreads();
+    acc_fill<BP>(ar, ai, 1.0);
+    cgemm_lds<BP>(ar, ai, s.A, false, s.B, -1.0);  // I - G11 K
+    __syncthreads();
+    acc_to_lds<BP>(s.A, ar, ai);
+    __syncthreads();
+    gj_invert<BP>(s, nullptr, NoSide(), false);
+    acc_fill<BP>(ar, ai, 0.0);
+    cgemm_lds<BP>(ar, ai, s.B, false, s.A, 1.0);  // U = K (I - G11 K)^{-1}
+    __syncthreads();
+    acc_to_lds<BP>(s.B, ar, ai);
+    hload_block<BP>(s.A, wq + HW_YH * bb2, b);
+    __syncthreads();
+    acc_fill<BP>(ar, ai, 0.0);
+    cgemm_lds<BP>(ar, ai, s.A, false, s.B, 1.0);  // YH U
+    __syncthreads();
+    acc_to_lds<BP>(s.A, ar, ai);
+    hload_block<BP>(s.B, wq + HW_XH * bb2, b);
+    __syncthreads();
+    hacc_from_global<BP>(ar, ai, wq + HW_YGX * bb2, b);
+    cgemm_lds<BP>(ar, ai, s.A, false, s.B, 1.0);  // K_q = YGX + YH U XH
+    hacc_to_global<BP>(wch + ((size_t)q * HW_COUNT + HW_K) * bb2, ar, ai, b);
+    __syncthreads();
+  }
+}
+
 template <int BP>
 hipError_t launch_hfactor_bp(const HPencil &p, const Shifts &s, int Ne, double *Sinv, double *W,
-                             double *V, hipStream_t st) {
-  hipError_t err = set_lds<BP>((const void *)hfactor_mfma_kernel<BP>);
+                             double *V, int P, double *work, hipStream_t st) {
+  hipError_t err = set_lds<BP>((const void *)hfactor_part_kernel<BP>);
+  if (err == hipSuccess) err = set_lds<BP>((const void *)hinterface_kernel<BP>);
   if (err == hipSuccess) err = set_lds<BP>((const void *)hfactor_twist_kernel<BP>);
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(hfactor_mfma_kernel<BP>, dim3(2 * Ne), dim3(kThreads), sizeof(Lds<BP>), st,
-                     p, s, Sinv, W, V);
+  const size_t shm = sizeof(Lds<BP>);
+  hipLaunchKernelGGL(hfactor_part_kernel<BP>, dim3(2 * Ne * (P > 1 ? P - 1 : 1)), dim3(kThreads),
+                     shm, st, p, s, Sinv, W, V, work, P, 0);
   if ((err = hipGetLastError()) != hipSuccess) return err;
-  hipLaunchKernelGGL(hfactor_twist_kernel<BP>, dim3(Ne), dim3(kThreads), sizeof(Lds<BP>), st, p,
-                     s, Sinv, W);
+  if (P > 1) {
+    hipLaunchKernelGGL(hinterface_kernel<BP>, dim3(2 * Ne), dim3(kThreads), shm, st, p, s,
+                       (const double *)V, work, P);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    hipLaunchKernelGGL(hfactor_part_kernel<BP>, dim3(2 * Ne * (P - 1)), dim3(kThreads), shm, st,
+                       p, s, Sinv, W, V, work, P, 1);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+  }
+  hipLaunchKernelGGL(hfactor_twist_kernel<BP>, dim3(Ne), dim3(kThreads), shm, st, p, s, Sinv, W);
   return hipGetLastError();
 }
 
@@ -1296,14 +1615,20 @@ hipError_t launch_factor_wide(const Pencil &p, const Shifts &s, int Ne, const Fa
   return hipGetLastError();
 }
 
+size_t hfactor_work_doubles(const HPencil &p, int Ne, int parts) {
+  return parts > 1 ? (size_t)2 * Ne * parts * HW_COUNT * 2 * p.b * p.b : 0;
+}
+
 hipError_t launch_hfactor_mfma(const HPencil &p, const Shifts &s, int Ne, double *Sinv,
-                               double *W, double *V, hipStream_t st) {
+                               double *W, double *V, int parts, double *work, hipStream_t st) {
   if (p.b < 1 || p.b > 64 || Ne < 1) return hipErrorInvalidValue;
+  // every partition of both chains holds at least one cell
+  if (parts < 1 || parts > std::max(1, p.nc / 2) || (parts > 1 && !work)) return hipErrorInvalidValue;
   switch ((p.b + 15) / 16 * 16) {
-    case 16: return launch_hfactor_bp<16>(p, s, Ne, Sinv, W, V, st);
-    case 32: return launch_hfactor_bp<32>(p, s, Ne, Sinv, W, V, st);
-    case 48: return launch_hfactor_bp<48>(p, s, Ne, Sinv, W, V, st);
-    default: return launch_hfactor_bp<64>(p, s, Ne, Sinv, W, V, st);
+    case 16: return launch_hfactor_bp<16>(p, s, Ne, Sinv, W, V, parts, work, st);
+    case 32: return launch_hfactor_bp<32>(p, s, Ne, Sinv, W, V, parts, work, st);
+    case 48: return launch_hfactor_bp<48>(p, s, Ne, Sinv, W, V, parts, work, st);
+    default: return launch_hfactor_bp<64>(p, s, Ne, Sinv, W, V, parts, work, st);
   }
 }
 

@@ -43,7 +43,7 @@ enum Slot {
   S_SINV32, S_W32, S_WT32, S_G32, S_TV32, S_XC, S_RC, S_RPART, S_WORST,
   // Hermitian variant
   S_HSINV, S_HW, S_HV, S_HG, S_HY, S_HR, S_HQ, S_HX, S_HAX, S_HBX, S_HPART, S_HAQ, S_HBQ,
-  S_HEA, S_HEB, S_HEPS2, S_HPHI2, S_HEPS, S_HPHI, S_HRES, S_HCOEF, S_CONV, S_COUNT
+  S_HEA, S_HEB, S_HEPS2, S_HPHI2, S_HEPS, S_HPHI, S_HRES, S_HCOEF, S_HFWORK, S_CONV, S_COUNT
 };
 
 }  // namespace
@@ -1376,17 +1376,27 @@ int check_hinputs(feast_ctx *ctx, const feast_zbt_matrix *AB, const double *Y0, 
   return ctx->h_flag[0] ? -6 : 0;
 }
 
-// Factors of every node: Sinv, W, V (complex).
+// Factors of every node: Sinv, W, V (complex), and the partitions of the
+// factorisation with their work area (b <= 64).
 struct HFactors {
-  double *Sinv, *W, *V;
+  double *Sinv, *W, *V, *work;
+  int parts;
 };
 
-int prepare_hfactors(feast_ctx *ctx, const HPencil &p, int Ne, HFactors &f) {
+int prepare_hfactors(feast_ctx *ctx, const HPencil &p, int Ne, int partitions, HFactors &f) {
   const size_t bb2 = 2 * (size_t)p.b * p.b;
   HIPCHK(ensure_t(ctx, S_HSINV, (size_t)Ne * p.nc * bb2, &f.Sinv));
   HIPCHK(ensure_t(ctx, S_HW, (size_t)Ne * p.nc * bb2, &f.W));
   HIPCHK(ensure_t(ctx, S_HV, (size_t)Ne * p.nc * bb2, &f.V));
+  f.parts = p.b <= 64 ? choose_parts(p.nc, Ne, partitions) : 1;
+  f.work = nullptr;
+  if (f.parts > 1) HIPCHK(ensure_t(ctx, S_HFWORK, hfactor_work_doubles(p, Ne, f.parts), &f.work));
   return 0;
+}
+
+hipError_t run_hfactor(const HPencil &p, const Shifts &s, int Ne, const HFactors &f,
+                       hipStream_t st) {
+  return launch_hfactor(p, s, Ne, f.Sinv, f.W, f.V, f.parts, f.work, st);
 }
 
 // Eq. 12 for the complex right-hand side R [N][m]: Q [N][m].
@@ -1417,7 +1427,7 @@ int hcoefficients(feast_ctx *ctx, const Shifts &s, int Ne, double **coef) {
 
 int feast_shifted_solve_hermitian(feast_ctx *ctx, const feast_zbt_matrix *AB, double z_re,
                                   double z_im, int32_t m, const double *R, int32_t adjoint,
-                                  double *X) {
+                                  double *X, int32_t partitions) {
   if (!ctx || !R || !X) return -5;
   int st = validate_hmatrix(AB);
   if (st) return st;
@@ -1431,11 +1441,12 @@ int feast_shifted_solve_hermitian(feast_ctx *ctx, const feast_zbt_matrix *AB, do
   s.zre[0] = z_re;
   s.zim[0] = z_im;
   HFactors f;
-  st = prepare_hfactors(ctx, p, 1, f);
+  if (partitions < 0) return -7;
+  st = prepare_hfactors(ctx, p, 1, partitions, f);
   if (st) return st;
   double *G;
   HIPCHK(ensure_t(ctx, S_HG, hsweep_work_doubles(p, 1, m), &G));
-  HIPCHK(launch_hfactor(p, s, 1, f.Sinv, f.W, f.V, ctx->stream));
+  HIPCHK(run_hfactor(p, s, 1, f, ctx->stream));
   HIPCHK(launch_hsweeps(p, 1, f.Sinv, f.W, f.V, R, m, G, ctx->stream));
   HIPCHK(hipMemcpyAsync(X, G + (adjoint ? 2 * N * m : 0), 2 * N * m * sizeof(double),
                         hipMemcpyDeviceToDevice, ctx->stream));
@@ -1457,13 +1468,13 @@ int feast_filter_hermitian(feast_ctx *ctx, const feast_zbt_matrix *AB, double em
   Shifts s;
   make_shifts(Ne, emin, emax, s);
   HFactors f;
-  st = prepare_hfactors(ctx, p, Ne, f);
+  st = prepare_hfactors(ctx, p, Ne, 0, f);
   if (st) return st;
   double *coef, *R;
   st = hcoefficients(ctx, s, Ne, &coef);
   if (st) return st;
   HIPCHK(ensure_t(ctx, S_HR, N * M0 * 2, &R));
-  HIPCHK(launch_hfactor(p, s, Ne, f.Sinv, f.W, f.V, ctx->stream));
+  HIPCHK(run_hfactor(p, s, Ne, f, ctx->stream));
   HIPCHK(launch_happly(p, 1, Y, M0, R, ctx->stream));  // R = B Y
   st = hfilter(ctx, p, Ne, f, R, M0, coef, Q);
   if (st) return st;
@@ -1485,7 +1496,7 @@ int generic_solve(feast_ctx *ctx, const HPencil &p, double emin, double emax, in
   make_shifts(Ne, emin, emax, s);
   const double r = 0.5 * (emax - emin);
   HFactors f;
-  st = prepare_hfactors(ctx, p, Ne, f);
+  st = prepare_hfactors(ctx, p, Ne, o.partitions, f);
   if (st) return st;
   double *coef;
   st = hcoefficients(ctx, s, Ne, &coef);
@@ -1515,7 +1526,7 @@ int generic_solve(feast_ctx *ctx, const HPencil &p, double emin, double emax, in
   HIPCHK(ensure_t(ctx, S_FLAG, 4, &flag));
   HIPCHK(ensure_t(ctx, S_PERM, (size_t)M0, &perm));
 
-  TIMED(K_FACTOR, launch_hfactor(p, s, Ne, f.Sinv, f.W, f.V, sm));  // once (Sec. V, level (ii))
+  TIMED(K_FACTOR, run_hfactor(p, s, Ne, f, sm));  // once (Sec. V, level (ii))
   if (y0) {
     HIPCHK(hipMemcpyAsync(y, y0, nm2 * sizeof(double), hipMemcpyDeviceToDevice, sm));
   } else {  // real and imaginary parts N(0, 1): the real draw of N x 2 M0
@@ -1644,7 +1655,7 @@ int feast_solve_hermitian(feast_ctx *ctx, const feast_zbt_matrix *AB, double emi
   feast_opts o;
   feast_default_opts(&o);
   if (opts) o = *opts;
-  if (!(o.tol > 0.0) || o.max_loops < 1 || o.precision != 0) return -7;
+  if (!(o.tol > 0.0) || o.max_loops < 1 || o.precision != 0 || o.partitions < 0) return -7;
   HIPCHK(hipSetDevice(ctx->device));
   st = check_hinputs(ctx, AB, o.Y0, (size_t)N * M0 * 2);
   if (st) return st;

@@ -446,9 +446,9 @@ int grid_of(size_t n) {
 size_t hfactor_lds_bytes(int b) { return 2 * (size_t)b * (b + 1) * sizeof(double); }
 
 hipError_t launch_hfactor(const HPencil &p, const Shifts &s, int Ne, double *Sinv, double *W,
-                          double *V, hipStream_t st) {
+                          double *V, int parts, double *work, hipStream_t st) {
   if (p.b < 1 || p.b > kMaxHBlock) return hipErrorInvalidValue;
-  if (p.b <= 64) return launch_hfactor_mfma(p, s, Ne, Sinv, W, V, st);
+  if (p.b <= 64) return launch_hfactor_mfma(p, s, Ne, Sinv, W, V, parts, work, st);
   const size_t lds = hfactor_lds_bytes(p.b);
   hipError_t e = hipFuncSetAttribute((const void *)hfactor_kernel,
                                      hipFuncAttributeMaxDynamicSharedMemorySize,

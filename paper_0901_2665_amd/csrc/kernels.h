@@ -257,12 +257,17 @@ struct HPencil {
 size_t hfactor_lds_bytes(int b);
 // Block LU of Z_e B - A for every node: Sinv, W and V [Ne][nc][b][b]
 // (complex; b > 64: W and V use the first max(nc-1,1) blocks of a node).
+// For b <= 64 each half chain is cut into `parts` partitions (1 <= parts <=
+// max(1, nc/2)) factored through their corner blocks and a sequential
+// self-energy pass; work holds hfactor_work_doubles() doubles (none for one
+// partition).  Blocks above 64 ignore parts and work.
 hipError_t launch_hfactor(const HPencil &p, const Shifts &s, int Ne, double *Sinv, double *W,
-                          double *V, hipStream_t st);
+                          double *V, int parts, double *work, hipStream_t st);
+size_t hfactor_work_doubles(const HPencil &p, int Ne, int parts);
 // The same factorisation for b <= 64 on the matrix cores (factor.hip), which
 // launch_hfactor takes for those blocks.
 hipError_t launch_hfactor_mfma(const HPencil &p, const Shifts &s, int Ne, double *Sinv,
-                               double *W, double *V, hipStream_t st);
+                               double *W, double *V, int parts, double *work, hipStream_t st);
 // Both solves of every node for the complex right-hand side R [N][m]:
 // G [Ne][2][N][m] = (M_e^{-1} R, M_e^{-H} R), followed by the sweeps' twist
 // slots; G holds hsweep_work_doubles() doubles.

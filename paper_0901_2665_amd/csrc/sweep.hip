@@ -747,7 +747,7 @@ hipError_t launch_spike_bp(SpikeArgs &a, dim3 grid, hipStream_t st) {
 
 // ---- Hermitian A: both solves of eq. 12 on the matrix cores (b <= 64) ----
 //
-// The twisted factors of the non-symmetric M = Z B - A (hfactor_mfma_kernel)
+// The twisted factors of the non-symmetric M = Z B - A (hfactor_part_kernel)
 // are complex interleaved [b][b] blocks Sinv_c, W_c, V_c (the twist cell's T
 // in Sinv_{m-1}).  Solve 0 is M x = R (forward h_next = R_next - V_c h_c,
 // g_c = Sinv_c h_c; back x_c = g_c - W_c x_prev), solve 1 is M^H y = R with
@@ -840,7 +840,7 @@ __device__ __forceinline__ void hvec_store(double *X, int nbytes, int b, int m, 
 }
 
 // Twisted sweeps of one (node, solve, half, tile) over the twisted factors
-// of hfactor_mfma_kernel (top chain cells 0..m-1, bottom chain nc-1..m, the
+// of hfactor_part_kernel (top chain cells 0..m-1, bottom chain nc-1..m, the
 // twist cell m-1 holding T).  Forward: the first wave set carries
 // h_next = R_next - op(F_c) h_c (F = V, or W for the adjoint; the bottom
 // chain's last cell leaves the twist term -op(F_m) h_m instead), the second

@@ -110,7 +110,7 @@ def load_library(path: str = LIB_PATH):
     lib.feast_solve_hermitian.argtypes = [P, ctypes.POINTER(ZBTMatrix), D, D, I32, I32,
                                           ctypes.POINTER(Opts), P, P, P, ctypes.POINTER(Info)]
     lib.feast_shifted_solve_hermitian.argtypes = [P, ctypes.POINTER(ZBTMatrix), D, D, I32, P,
-                                                  I32, P]
+                                                  I32, P, I32]
     lib.feast_filter_hermitian.argtypes = [P, ctypes.POINTER(ZBTMatrix), D, D, I32, I32, P, P]
     F32P = ctypes.c_void_p
     lib.feast_mlp_create.argtypes = [P, ctypes.POINTER(I32), I32, P, ctypes.POINTER(P)]
@@ -491,13 +491,13 @@ class Context:
 
     def solve_hermitian(self, p: "HermitianPencil", emin: float, emax: float, M0: int, Ne: int,
                         Y0=None, tol: float = 1e-12, max_loops: int = 20, seed: int = 0,
-                        verbose: int = 0) -> SolveResult:
+                        verbose: int = 0, partitions: int = 0) -> SolveResult:
         import torch
         dev = p.Ad.device
         lam = torch.empty(M0, dtype=torch.float64, device=dev)
         X = torch.empty((p.n, M0), dtype=torch.complex128, device=dev)
         res = torch.empty(M0, dtype=torch.float64, device=dev)
-        opts = Opts(tol=tol, max_loops=max_loops, precision=0, partitions=0, graph=0,
+        opts = Opts(tol=tol, max_loops=max_loops, precision=0, partitions=partitions, graph=0,
                     Y0=_zptr(Y0) if Y0 is not None else None, seed=seed, verbose=verbose)
         info = Info()
         ab = p.struct()
@@ -510,12 +510,14 @@ class Context:
                            info.max_res, st, info.fallback, list(info.trace_hist[:n]),
                            list(info.count_hist[:n]), info.rr_sweeps, 0, 0.0, info.m0_small)
 
-    def shifted_solve_hermitian(self, p: "HermitianPencil", z: complex, R, adjoint: bool = False):
+    def shifted_solve_hermitian(self, p: "HermitianPencil", z: complex, R, adjoint: bool = False,
+                                partitions: int = 0):
         import torch
         X = torch.empty_like(R)
         ab = p.struct()
         st = self.lib.feast_shifted_solve_hermitian(self.handle, ctypes.byref(ab), z.real, z.imag,
-                                                    R.shape[1], _zptr(R), int(adjoint), _zptr(X))
+                                                    R.shape[1], _zptr(R), int(adjoint), _zptr(X),
+                                                    int(partitions))
         self._check(st, "feast_shifted_solve_hermitian")
         return X
 

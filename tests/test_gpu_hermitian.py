@@ -63,6 +63,69 @@ def test_shifted_solve_hermitian(ctx, torch, nc, b, m, adjoint):
     assert_columnwise(X, ref, 1e-10)
 
 
+@pytest.mark.parametrize("nc,b,m,parts", [(40, 16, 8, 2), (41, 33, 10, 3), (64, 64, 16, 8),
+                                          (30, 48, 5, 15), (23, 5, 3, 11), (50, 24, 12, 0)])
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_shifted_solve_hermitian_partitioned(ctx, torch, nc, b, m, parts, adjoint):
+    # each half chain cut into partitions (local corner blocks, the
+    # sequential self-energy pass, exact rerun), up to one cell a partition
+    # (parts = nc/2): the backward error of one chain, and the same solution
+    p = W.hermitian_pencil(nc, b, 700 + nc)
+    R = W.random_complex_subspace(p.n, m, nc + 2 * b)
+    z = 0.21 + 0.04j
+    X = ctx.shifted_solve_hermitian(hpencil(p), z, zdev(torch, R), adjoint, partitions=parts)
+    X = X.cpu().numpy()
+    M = O.shifted_matrix_hermitian(p, z)
+    if adjoint:
+        M = M.conj().T.tocsr()
+    berr = np.linalg.norm(R - M @ X, axis=0) / (spla.norm(M) * np.linalg.norm(X, axis=0))
+    assert np.max(berr) <= 1e-14
+    ref = O.factor_shift_hermitian(p, z).solve(R, adjoint=adjoint)
+    assert_columnwise(X, ref, 1e-10)
+    one = ctx.shifted_solve_hermitian(hpencil(p), z, zdev(torch, R), adjoint, partitions=1)
+    assert_columnwise(X, one.cpu().numpy(), 1e-11)
+
+
+# Backward error of one shifted solve of the complex chain near the real
+# axis, one partition / automatic (10 per half chain); the bars of the real
+# path's measurements on the same recipe
+HNEAR_AXIS_BAR = {(5e-2, 1): 1e-15, (5e-2, 0): 1e-15, (1e-3, 1): 2e-13, (1e-3, 0): 1e-11,
+                  (1e-4, 1): 5e-13, (1e-4, 0): 3e-11}
+
+
+@pytest.mark.parametrize("parts", [1, 0])
+@pytest.mark.parametrize("eta", [5e-2, 1e-3, 1e-4])
+def test_shifted_solve_hermitian_near_axis(ctx, torch, eta, parts):
+    p = W.hermitian_chain_pencil(160, 32, 4242)
+    z = 0.1234 + 1j * eta
+    R = W.random_complex_subspace(p.n, 16, 17)
+    X = ctx.shifted_solve_hermitian(hpencil(p), z, zdev(torch, R), False, partitions=parts)
+    X = X.cpu().numpy()
+    M = O.shifted_matrix_hermitian(p, z)
+    berr = np.linalg.norm(R - M @ X, axis=0) / (spla.norm(M) * np.linalg.norm(X, axis=0))
+    assert np.max(berr) <= HNEAR_AXIS_BAR[(eta, parts)], np.max(berr)
+
+
+def test_solve_hermitian_partitioned(ctx, torch):
+    # a complex chain long enough for the automatic partitioning (nc = 96:
+    # 6 partitions per half chain at Ne = 8) against the oracle, brute force
+    # and the one-partition solve
+    p = W.hermitian_chain_pencil(96, 16, 31)
+    lam_b = O.bruteforce_hermitian(p)[0]
+    k0 = p.n // 2
+    emin, emax = gap_interval(lam_b, k0, 12)
+    Y0 = W.random_complex_subspace(p.n, 24, 5)
+    r = ctx.solve_hermitian(hpencil(p), emin, emax, 24, 8, zdev(torch, Y0), tol=1e-13)
+    ref = O.feast_hermitian(p, emin, emax, 24, 8, Y0, tol=1e-13)
+    assert r.status == ref.status == 0
+    check_hermitian(r, ref, p, emin, emax, lam_b, k0)
+    one = ctx.solve_hermitian(hpencil(p), emin, emax, 24, 8, zdev(torch, Y0), tol=1e-13,
+                              partitions=1)
+    assert (one.M, one.loops) == (r.M, r.loops)
+    scale = np.maximum(np.abs(lam_b[k0:k0 + r.M]), (emax - emin) / 2)
+    assert np.max(np.abs(one.lam.cpu().numpy()[:r.M] - r.lam.cpu().numpy()[:r.M]) / scale) <= 1e-12
+
+
 @pytest.mark.parametrize("nc,b,m0,ne", [(5, 8, 10, 8), (9, 16, 24, 4), (20, 40, 30, 8),
                                         (6, 64, 64, 16)])
 def test_filter_hermitian(ctx, torch, nc, b, m0, ne):
@@ -152,6 +215,12 @@ def test_solve_hermitian_bad_arguments(ctx, torch):
     with pytest.raises(F.FeastError) as e:
         ctx.solve_hermitian(hp, 0.0, 1.0, 65, 8, Y0)
     assert e.value.status == -3
+    with pytest.raises(F.FeastError) as e:
+        ctx.solve_hermitian(hp, 0.0, 1.0, 4, 8, Y0, partitions=-1)
+    assert e.value.status == -7
+    with pytest.raises(F.FeastError) as e:
+        ctx.shifted_solve_hermitian(hp, 0.2 + 0.1j, Y0, partitions=-1)
+    assert e.value.status == -7
     bad = W.HermitianPencil(p.Ad.copy(), p.Au, p.Bd, p.Bu)
     bad.Ad[1, 2, 3] = np.nan
     with pytest.raises(F.FeastError) as e:

@@ -851,8 +851,9 @@ template <int BP>
 __global__ __launch_bounds__(BP * 8) void hforward_kernel(HSweepArgs a) {
   __shared__ VecLds<BP> s;
   constexpr int NW = BP / 16;
-  const int tau = blockIdx.x % a.ntiles;
-  const int grp = blockIdx.x / a.ntiles;  // (node * 2 + solve) * 2 + half
+  const int item = xcd_item(blockIdx.x, gridDim.x, a.ntiles);  // the tiles of a group on one XCD
+  const int tau = item % a.ntiles;
+  const int grp = item / a.ntiles;  // (node * 2 + solve) * 2 + half
   const int e = grp >> 2;
   const bool adj = (grp & 2) != 0, top = (grp & 1) == 0;
   const int nc = a.p.nc, b = a.p.b, m = a.m, mt = nc - nc / 2;
@@ -922,8 +923,9 @@ __global__ __launch_bounds__(BP * 8) void hforward_kernel(HSweepArgs a) {
 template <int BP>
 __global__ __launch_bounds__(BP * 4) void hback_kernel(HSweepArgs a) {
   __shared__ VecLds<BP> s;
-  const int tau = blockIdx.x % a.ntiles;
-  const int grp = blockIdx.x / a.ntiles;
+  const int item = xcd_item(blockIdx.x, gridDim.x, a.ntiles);
+  const int tau = item % a.ntiles;
+  const int grp = item / a.ntiles;
   const int e = grp >> 2;
   const bool adj = (grp & 2) != 0, top = (grp & 1) == 0;
   const int nc = a.p.nc, b = a.p.b, m = a.m, mt = nc - nc / 2;

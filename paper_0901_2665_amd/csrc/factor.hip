@@ -1309,13 +1309,13 @@ __device__ void hchain_final(Lds<BP> &s, const HPencil &p, double zr, double zi,
 //   P_0 = Q_0 = I,  P_{t+1} = -V'_t P_t,  Q_{t+1} = -Q_t W'_t,
 // the first block column of G ends in GL1 = Sinv'_L-1 P_L-1, the first block
 // row in G1L = Q_L-1 Sinv'_L-1, and appending cell t to the section adds
-// Q_t Sinv'_t P_t to G11 (Schur complement of the new cell).  With X, Y the
-// couplings to the next partition it leaves G11, YH = Y GL1, XH = G1L X and
-// YGX = Y GLL X.  W'_t and V'_t pass through the factor arrays, which the
-// exact rerun overwrites.
+// Q_t Sinv'_t P_t to G11 (Schur complement of the new cell).  With
+// T_t = Sinv'_t P_t, P_{t+1} = -Y_t T_t, so V'_t is never formed.  With X, Y
+// the couplings to the next partition it leaves G11, YH = Y GL1, XH = G1L X
+// and YGX = Y GLL X.
 template <int BP>
 __device__ void hchain_local(Lds<BP> &s, const HPencil &p, double zr, double zi, bool top,
-                             int jb, int je, double *wk, double *We, double *Ve) {
+                             int jb, int je, double *wk) {
   constexpr int NT = BP / 16;
   const int nc = p.nc, b = p.b;
   const size_t bb = (size_t)b * b, bb2 = 2 * bb;
@@ -1338,16 +1338,16 @@ __device__ void hchain_local(Lds<BP> &s, const HPencil &p, double zr, double zi,
     const double *Pc = Pb[t & 1];
     double *Pn = Pb[(t + 1) & 1];
     d4 ar[NT], ai[NT];
-    if (t == 0) {
+    if (t == 0) {  // P_0 = Q_0 = I
       hstore_block<BP>(G11, s.A, b);
-      if (last) hstore_block<BP>(T, s.A, b);  // GL1 = Sinv'_0
+      hstore_block<BP>(T, s.A, b);
     } else {
       acc_fill<BP>(ar, ai, 0.0);
-      cgemm_op<BP>(ar, ai, SlotOp<BP>{s.A}, GlobOp{Pc, b}, 1.0);  // Sinv'_t P_t
+      cgemm_op<BP>(ar, ai, SlotOp<BP>{s.A}, GlobOp{Pc, b}, 1.0);  // T_t = Sinv'_t P_t
       hacc_to_global<BP>(T, ar, ai, b);
       __syncthreads();
       hacc_from_global<BP>(ar, ai, G11, b);
-      cgemm_op<BP>(ar, ai, GlobOp{Q, b}, GlobOp{T, b}, 1.0);  // G11 += Q_t Sinv'_t P_t
+      cgemm_op<BP>(ar, ai, GlobOp{Q, b}, GlobOp{T, b}, 1.0);  // G11 += Q_t T_t
       hacc_to_global<BP>(G11, ar, ai, b);
     }
     d4 wr[NT], wi[NT];
@@ -1355,7 +1355,7 @@ __device__ void hchain_local(Lds<BP> &s, const HPencil &p, double zr, double zi,
     cgemm_lds<BP>(wr, wi, s.A, false, s.B, 1.0);  // W' = Sinv' X
     __syncthreads();
     hform_block<BP>(s.B, p, cc, ky, zr, zi);  // slot B: Y
-    if (last) {  // XH = Q_t W', YGX = Y W', YH = Y GL1
+    if (last) {  // XH = Q_t W', YGX = Y W', YH = Y GL1 (GL1 = T_t)
       acc_to_lds<BP>(s.A, wr, wi);
       if (t == 0) hacc_to_global<BP>(XH, wr, wi, b);
       __syncthreads();
@@ -1373,16 +1373,9 @@ __device__ void hchain_local(Lds<BP> &s, const HPencil &p, double zr, double zi,
       break;
     }
     __syncthreads();
-    double *Vc = Ve + 2 * (size_t)c * bb;
     acc_fill<BP>(ar, ai, 0.0);
-    cgemm_lds<BP>(ar, ai, s.B, false, s.A, 1.0);  // V' = Y Sinv'
-    if (t == 0) {
-      acc_negate<BP>(ar, ai);
-      hacc_to_global<BP>(Pn, ar, ai, b);  // P_1 = -V'_0
-    } else {
-      hacc_to_global<BP>(Vc, ar, ai, b);
-    }
-    __syncthreads();
+    cgemm_op<BP>(ar, ai, SlotOp<BP>{s.B}, GlobOp{T, b}, -1.0);  // P_{t+1} = -V'_t P_t = -Y T_t
+    hacc_to_global<BP>(Pn, ar, ai, b);
     acc_to_lds<BP>(s.A, wr, wi);  // slot A: W'
     if (t == 0) {
       acc_negate<BP>(wr, wi);
@@ -1393,9 +1386,6 @@ __device__ void hchain_local(Lds<BP> &s, const HPencil &p, double zr, double zi,
       acc_fill<BP>(ar, ai, 0.0);
       cgemm_op<BP>(ar, ai, GlobOp{Q, b}, SlotOp<BP>{s.A}, -1.0);  // Q_{t+1} = -Q_t W'_t
       hacc_to_global<BP>(Q, ar, ai, b);  // in place: a wave reads and writes its own rows
-      acc_fill<BP>(ar, ai, 0.0);
-      cgemm_op<BP>(ar, ai, GlobOp{Vc, b}, GlobOp{Pc, b}, -1.0);  // P_{t+1} = -V'_t P_t
-      hacc_to_global<BP>(Pn, ar, ai, b);
     }
     acc_from_hdiag<BP>(ar, ai, p, cell(jb + t + 1), zr, zi);
     cgemm_lds<BP>(ar, ai, s.B, false, s.A, -1.0);  // S'_{t+1} = D - Y W'
@@ -1432,7 +1422,7 @@ __global__ __launch_bounds__(kThreads) void hfactor_part_kernel(HPencil p, Shift
   if (q == 0 || phase == 1)
     hchain_final<BP>(s, p, zr, zi, top, len, jb, je, q ? wk + HW_K * bb2 : nullptr, Se, We, Ve);
   else
-    hchain_local<BP>(s, p, zr, zi, top, jb, je, wk, We, Ve);
+    hchain_local<BP>(s, p, zr, zi, top, jb, je, wk);
 }
 
 // slot <- complex interleaved [b][b] block (zero padding)

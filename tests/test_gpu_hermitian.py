@@ -178,6 +178,26 @@ def test_solve_hermitian(ctx, torch, nc, b, seed, k0, m, extra):
     check_hermitian(r, ref, p, emin, emax, lam_b, k0)
 
 
+def test_solve_hermitian_singular_bq(ctx, torch):
+    # a repeated start column makes B_Q singular in every loop: the complex
+    # Cholesky fails its pivot test and the real embedding's fallback solves
+    # the reduced problem; status 2 and the eigenvalues, as in the oracle
+    p = W.hermitian_pencil(8, 16, 7)
+    lam_b = O.bruteforce_hermitian(p)[0]
+    k0 = 40
+    emin, emax = gap_interval(lam_b, k0, 6)
+    Y0 = W.random_complex_subspace(p.n, 16, 8)
+    Y0[:, 15] = Y0[:, 0]
+    r = ctx.solve_hermitian(hpencil(p), emin, emax, 16, 8, zdev(torch, Y0), tol=1e-13)
+    ref = O.feast_hermitian(p, emin, emax, 16, 8, Y0, tol=1e-13)
+    assert r.status == ref.status == 2 and r.fallback == 1
+    assert r.M == ref.M == 6
+    lam = r.lam.cpu().numpy()[:r.M]
+    scale = np.maximum(np.abs(lam_b[k0:k0 + 6]), (emax - emin) / 2)
+    assert np.max(np.abs(lam - lam_b[k0:k0 + 6]) / scale) <= 1e-10
+    assert np.max(r.res.cpu().numpy()[:r.M]) <= 1e-9
+
+
 def test_solve_hermitian_random_start(ctx, torch):
     # Y0 = NULL: real and imaginary parts from the seeded real draw of N x 2 M0
     p = W.hermitian_pencil(20, 40, 9)

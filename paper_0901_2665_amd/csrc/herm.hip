@@ -335,17 +335,31 @@ __global__ __launch_bounds__(kT) void hgram_kernel(const double *X, const double
 }
 
 // G = sum of the partials (block order), then its Hermitian part.
-__global__ void hgram_sum_kernel(const double *partial, int nblk, int m, double *G) {
+// S = sum of the blocks' partial products: 64 outputs a workgroup, four
+// slices of the blocks a output (coalesced rows of the partials), the
+// slices added in a fixed order.
+__global__ __launch_bounds__(256) void hgram_sum_kernel(const double *partial, int nblk, int m,
+                                                        double *S) {
+  __shared__ cd red[4][64];
+  const int ol = threadIdx.x & 63, slice = threadIdx.x >> 6;
+  const int o = blockIdx.x * 64 + ol;
+  const size_t mm = (size_t)m * m;
+  cd s = {0.0, 0.0};
+  if (o < (int)mm)
+    for (int k = slice; k < nblk; k += 4) s = cadd(s, ld(partial + 2 * (size_t)k * mm, o));
+  red[slice][ol] = s;
+  __syncthreads();
+  if (slice == 0 && o < (int)mm)
+    st(S, o, cadd(cadd(red[0][ol], red[1][ol]), cadd(red[2][ol], red[3][ol])));
+}
+
+// G = Hermitian part of S (m x m).
+__global__ void hermitian_part_kernel(const double *S, int m, double *G) {
   const int o = blockIdx.x * blockDim.x + threadIdx.x;
   if (o >= m * m) return;
   const int i = o / m, j = o % m;
-  const int ot = j * m + i;
-  cd s = {0.0, 0.0}, u = {0.0, 0.0};
-  for (int k = 0; k < nblk; ++k) {
-    s = cadd(s, ld(partial + 2 * (size_t)k * m * m, o));
-    u = cadd(u, ld(partial + 2 * (size_t)k * m * m, ot));
-  }
-  st(G, o, {0.5 * (s.r + u.r), 0.5 * (s.i - u.i)});
+  const cd a = ld(S, o), b = ld(S, (size_t)j * m + i);
+  st(G, o, {0.5 * (a.r + b.r), 0.5 * (a.i - b.i)});
 }
 
 // Real embedding of a Hermitian m x m matrix H = Hr + i Hi:
@@ -378,18 +392,50 @@ __global__ void hextract_kernel(const double *eps2, const double *Phi2, int m, d
   }
 }
 
-// T[row][j] = sum_i X[row][i] G[i][j] (complex, X [N][m], G [m][m2]).
-__global__ void htall_gemm_kernel(const double *X, const double *G, long long N, int m, int m2,
-                                  double *T) {
-  const long long total = N * m2;
-  for (long long o = blockIdx.x * (long long)blockDim.x + threadIdx.x; o < total;
-       o += (long long)gridDim.x * blockDim.x) {
-    const long long row = o / m2;
-    const int j = (int)(o % m2);
-    cd s = {0.0, 0.0};
-    for (int i = 0; i < m; ++i) s = cadd(s, cmul(ld(X, (size_t)row * m + i), ld(G, (size_t)i * m2 + j)));
-    st(T, o, s);
+// T[row][j] = sum_i X[row][i] G[i][j] (complex, X [N][m], G [m][m2], m, m2
+// <= 64): 64 rows a workgroup, G and the rows staged in LDS (re and im
+// planes), a thread computes rows t/16 + 16u and columns t%16 + 16v.
+constexpr int kTallRows = 64, kTallLD = 65;
+struct TallLds {
+  double gr[64 * kTallLD], gi[64 * kTallLD];
+  double xr[kTallRows * kTallLD], xi[kTallRows * kTallLD];
+};
+
+__global__ __launch_bounds__(256) void htall_gemm_kernel(const double *X, const double *G,
+                                                         long long N, int m, int m2, double *T) {
+  extern __shared__ double smem_raw[];
+  TallLds &s = *reinterpret_cast<TallLds *>(smem_raw);
+  const long long r0 = (long long)blockIdx.x * kTallRows;
+  const int nr = (int)(N - r0 < kTallRows ? N - r0 : kTallRows);
+  for (int o = threadIdx.x; o < m * m2; o += 256) {
+    const int k = o / m2, j = o % m2;
+    const cd g = ld(G, o);
+    s.gr[k * kTallLD + j] = g.r;
+    s.gi[k * kTallLD + j] = g.i;
   }
+  for (int o = threadIdx.x; o < nr * m; o += 256) {
+    const int r = o / m, k = o % m;
+    const cd x = ld(X, (size_t)r0 * m + o);
+    s.xr[r * kTallLD + k] = x.r;
+    s.xi[r * kTallLD + k] = x.i;
+  }
+  __syncthreads();
+  const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
+  cd acc[4][4];
+  for (int u = 0; u < 4; ++u)
+    for (int v = 0; v < 4; ++v) acc[u][v] = {0.0, 0.0};
+  for (int k = 0; k < m; ++k) {
+    cd xv[4], gv[4];
+    for (int u = 0; u < 4; ++u) xv[u] = {s.xr[(tr + 16 * u) * kTallLD + k], s.xi[(tr + 16 * u) * kTallLD + k]};
+    for (int v = 0; v < 4; ++v) gv[v] = {s.gr[k * kTallLD + tc + 16 * v], s.gi[k * kTallLD + tc + 16 * v]};
+    for (int u = 0; u < 4; ++u)
+      for (int v = 0; v < 4; ++v) acc[u][v] = cadd(acc[u][v], cmul(xv[u], gv[v]));
+  }
+  for (int u = 0; u < 4; ++u)
+    for (int v = 0; v < 4; ++v) {
+      const int r = tr + 16 * u, j = tc + 16 * v;
+      if (r < nr && j < m2) st(T, (size_t)(r0 + r) * m2 + j, acc[u][v]);
+    }
 }
 
 // Per column j: the 1-norms ||AX_j - lam_j BX_j||, ||AX_j||, ||BX_j|| (complex
@@ -481,8 +527,8 @@ hipError_t launch_happly(const HPencil &p, int which, const double *Vin, int m, 
   return hipGetLastError();
 }
 
-size_t hgram_partial_doubles(long long N, int m) {
-  return 2 * (size_t)((N + kHGramRows - 1) / kHGramRows) * m * m;
+size_t hgram_partial_doubles(long long N, int m) {  // the blocks' partials, then their sum
+  return 2 * (size_t)((N + kHGramRows - 1) / kHGramRows + 1) * m * m;
 }
 
 hipError_t launch_hgram(const double *X, const double *Vin, long long N, int m, double *partial,
@@ -490,8 +536,11 @@ hipError_t launch_hgram(const double *X, const double *Vin, long long N, int m, 
   if (m < 1 || m > 64) return hipErrorInvalidValue;
   const int nblk = (int)((N + kHGramRows - 1) / kHGramRows);
   hipLaunchKernelGGL(hgram_kernel, dim3(nblk), dim3(kT), 0, st, X, Vin, N, m, partial);
-  hipLaunchKernelGGL(hgram_sum_kernel, dim3((m * m + 255) / 256), dim3(256), 0, st, partial, nblk,
-                     m, G);
+  double *sum = partial + 2 * (size_t)nblk * m * m;
+  hipLaunchKernelGGL(hgram_sum_kernel, dim3((m * m + 63) / 64), dim3(256), 0, st, partial, nblk, m,
+                     sum);
+  hipLaunchKernelGGL(hermitian_part_kernel, dim3((m * m + 255) / 256), dim3(256), 0, st,
+                     (const double *)sum, m, G);
   return hipGetLastError();
 }
 
@@ -511,8 +560,14 @@ hipError_t launch_hextract(const double *eps2, const double *Phi2, int m, double
 
 hipError_t launch_htall_gemm(const double *X, const double *G, long long N, int m, int m2,
                              double *T, hipStream_t st) {
-  hipLaunchKernelGGL(htall_gemm_kernel, dim3(grid_of((size_t)N * m2)), dim3(256), 0, st, X, G, N,
-                     m, m2, T);
+  if (m < 1 || m > 64 || m2 < 1 || m2 > 64) return hipErrorInvalidValue;
+  const int shm = (int)sizeof(TallLds);
+  hipError_t e = hipFuncSetAttribute((const void *)htall_gemm_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, shm);
+  if (e != hipSuccess) return e;
+  const long long nblk = (N + kTallRows - 1) / kTallRows;
+  hipLaunchKernelGGL(htall_gemm_kernel, dim3((unsigned)nblk), dim3(256), shm, st, X, G, N, m, m2,
+                     T);
   return hipGetLastError();
 }
 

@@ -1557,7 +1557,7 @@ int generic_solve(feast_ctx *ctx, const HPencil &p, double emin, double emax, in
     TIMED(K_RITZ, launch_htall_gemm(q, phi, N, M0, M0, x, sm));       // X = Q Phi
     TIMED(K_RESID, launch_happly(p, 0, x, M0, ax, sm));
     TIMED(K_RESID, launch_happly(p, 1, x, M0, bx, sm));
-    TIMED(K_RESID, launch_hresiduals(ax, bx, eps, N, M0, emin, emax, resi, sm));
+    TIMED(K_RESID, launch_hresiduals(ax, bx, eps, N, M0, emin, emax, part, resi, sm));
     HIPCHK(hipMemcpyAsync(h_eps, eps, M0 * sizeof(double), hipMemcpyDeviceToHost, sm));
     HIPCHK(hipMemcpyAsync(h_res, resi, M0 * sizeof(double), hipMemcpyDeviceToHost, sm));
     HIPCHK(hipMemcpyAsync(ctx->h_flag, flag, 3 * sizeof(int), hipMemcpyDeviceToHost, sm));

@@ -306,8 +306,11 @@ __global__ __launch_bounds__(kT) void hgram_kernel(const double *X, const double
   const long long r0 = (long long)blockIdx.x * kHGramRows;
   const long long r1 = r0 + kHGramRows < N ? r0 + kHGramRows : N;
   const int nout = m * m;
-  cd acc[16];
-  for (int q = 0; q < 16; ++q) acc[q] = {0.0, 0.0};
+  // a thread's outputs: i = ti + 16u, j = tj + 16v (u, v < 4)
+  const int ti = threadIdx.x >> 4, tj = threadIdx.x & 15;
+  cd acc[4][4];
+  for (int u = 0; u < 4; ++u)
+    for (int v = 0; v < 4; ++v) acc[u][v] = {0.0, 0.0};
   for (long long rb = r0; rb < r1; rb += 16) {
     const int nr = (int)((r1 - rb) < 16 ? (r1 - rb) : 16);
     __syncthreads();
@@ -318,23 +321,22 @@ __global__ __launch_bounds__(kT) void hgram_kernel(const double *X, const double
       st(vs, idx, in ? ld(Vin, (size_t)(rb + rr) * m + c) : cd{0.0, 0.0});
     }
     __syncthreads();
-    for (int q = 0; q < 16; ++q) {
-      const int o = threadIdx.x + kT * q;
-      if (o >= nout) break;
-      const int i = o / m, j = o % m;
-      cd s = acc[q];
-      for (int rr = 0; rr < nr; ++rr) s = cadd(s, cmulc(ld(xs, rr * 64 + i), ld(vs, rr * 64 + j)));
-      acc[q] = s;
+    for (int rr = 0; rr < nr; ++rr) {
+      cd xv[4], vv[4];
+      for (int u = 0; u < 4; ++u) xv[u] = ld(xs, rr * 64 + ti + 16 * u);
+      for (int v = 0; v < 4; ++v) vv[v] = ld(vs, rr * 64 + tj + 16 * v);
+      for (int u = 0; u < 4; ++u)
+        for (int v = 0; v < 4; ++v) acc[u][v] = cadd(acc[u][v], cmulc(xv[u], vv[v]));
     }
   }
   double *out = partial + 2 * (size_t)blockIdx.x * nout;
-  for (int q = 0; q < 16; ++q) {
-    const int o = threadIdx.x + kT * q;
-    if (o < nout) st(out, o, acc[q]);
-  }
+  for (int u = 0; u < 4; ++u)
+    for (int v = 0; v < 4; ++v) {
+      const int i = ti + 16 * u, j = tj + 16 * v;
+      if (i < m && j < m) st(out, i * m + j, acc[u][v]);
+    }
 }
 
-// G = sum of the partials (block order), then its Hermitian part.
 // S = sum of the blocks' partial products: 64 outputs a workgroup, four
 // slices of the blocks a output (coalesced rows of the partials), the
 // slices added in a fixed order.
@@ -441,34 +443,61 @@ __global__ __launch_bounds__(256) void htall_gemm_kernel(const double *X, const 
 // Per column j: the 1-norms ||AX_j - lam_j BX_j||, ||AX_j||, ||BX_j|| (complex
 // moduli), one workgroup per column, fixed reduction order; then the
 // residual of the Table I caption with the small-||Ax|| guard.
+constexpr int kResRows = 128;  // rows of one partial sum
+
+// Partial 1-norms over kResRows rows for every column: a thread takes column
+// t % 64 of every fourth row (rows read whole), the four row sets added in a
+// fixed order; partial[blk][3][m].
 __global__ __launch_bounds__(kT) void hresidual_kernel(const double *AX, const double *BX,
                                                        const double *lam, long long N, int m,
-                                                       double emin, double emax, double *res) {
+                                                       double *partial) {
   __shared__ double red[3][kT];
-  const int j = blockIdx.x, t = threadIdx.x;
-  const double l = lam[j];
+  const int t = threadIdx.x, j = t & 63, rs = t >> 6;
+  const long long r0 = (long long)blockIdx.x * kResRows;
+  const long long r1 = r0 + kResRows < N ? r0 + kResRows : N;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  for (long long r = t; r < N; r += kT) {
-    const cd a = ld(AX, (size_t)r * m + j), bx = ld(BX, (size_t)r * m + j);
-    s0 += hypot(a.r - l * bx.r, a.i - l * bx.i);
-    s1 += hypot(a.r, a.i);
-    s2 += hypot(bx.r, bx.i);
+  if (j < m) {
+    const double l = lam[j];
+    for (long long r = r0 + rs; r < r1; r += kT / 64) {
+      const cd a = ld(AX, (size_t)r * m + j), bx = ld(BX, (size_t)r * m + j);
+      s0 += hypot(a.r - l * bx.r, a.i - l * bx.i);
+      s1 += hypot(a.r, a.i);
+      s2 += hypot(bx.r, bx.i);
+    }
   }
   red[0][t] = s0;
   red[1][t] = s1;
   red[2][t] = s2;
   __syncthreads();
-  for (int o = kT / 2; o > 0; o >>= 1) {
-    if (t < o)
-      for (int q = 0; q < 3; ++q) red[q][t] += red[q][t + o];
-    __syncthreads();
+  if (t < 64 && j < m) {
+    double *out = partial + (size_t)blockIdx.x * 3 * m;
+    for (int q = 0; q < 3; ++q)
+      out[q * m + j] = (red[q][j] + red[q][64 + j]) + (red[q][128 + j] + red[q][192 + j]);
   }
-  if (t == 0) {
-    const double r = 0.5 * (emax - emin);
-    const double scale = fmax(fmax(fabs(emin), fabs(emax)), r);
-    const double den = red[1][0] < r * red[2][0] ? red[2][0] * scale : red[1][0];
-    res[j] = red[0][0] / den;
+}
+
+// The partials (16 slices of the blocks, added in a fixed order), then the
+// residual of the Table I caption with the small-||Ax|| guard.
+__global__ __launch_bounds__(1024) void hresidual_sum_kernel(const double *partial, int nblk,
+                                                             int m, double emin, double emax,
+                                                             double *res) {
+  __shared__ double red[3][16][64];
+  const int t = threadIdx.x, j = t & 63, sl = t >> 6;
+  double s[3] = {0.0, 0.0, 0.0};
+  if (j < m)
+    for (int k = sl; k < nblk; k += 16)
+      for (int q = 0; q < 3; ++q) s[q] += partial[((size_t)k * 3 + q) * m + j];
+  for (int q = 0; q < 3; ++q) red[q][sl][j] = s[q];
+  __syncthreads();
+  if (t >= m) return;
+  for (int q = 0; q < 3; ++q) {
+    s[q] = 0.0;
+    for (int w = 0; w < 16; ++w) s[q] += red[q][w][t];
   }
+  const double r = 0.5 * (emax - emin);
+  const double scale = fmax(fmax(fabs(emin), fabs(emax)), r);
+  const double den = s[1] < r * s[2] ? s[2] * scale : s[1];
+  res[t] = s[0] / den;
 }
 
 // out[r][j] = in[r][perm[j]] (complex [N][m]).
@@ -527,8 +556,12 @@ hipError_t launch_happly(const HPencil &p, int which, const double *Vin, int m, 
   return hipGetLastError();
 }
 
-size_t hgram_partial_doubles(long long N, int m) {  // the blocks' partials, then their sum
-  return 2 * (size_t)((N + kHGramRows - 1) / kHGramRows + 1) * m * m;
+// The projection's block partials and their sum, or the residuals' partial
+// 1-norms, whichever is larger.
+size_t hgram_partial_doubles(long long N, int m) {
+  const size_t gram = 2 * (size_t)((N + kHGramRows - 1) / kHGramRows + 1) * m * m;
+  const size_t resid = 3 * (size_t)m * ((N + kResRows - 1) / kResRows);
+  return gram > resid ? gram : resid;
 }
 
 hipError_t launch_hgram(const double *X, const double *Vin, long long N, int m, double *partial,
@@ -572,9 +605,13 @@ hipError_t launch_htall_gemm(const double *X, const double *G, long long N, int 
 }
 
 hipError_t launch_hresiduals(const double *AX, const double *BX, const double *lam, long long N,
-                             int m, double emin, double emax, double *res, hipStream_t st) {
-  hipLaunchKernelGGL(hresidual_kernel, dim3(m), dim3(kT), 0, st, AX, BX, lam, N, m, emin, emax,
-                     res);
+                             int m, double emin, double emax, double *partial, double *res,
+                             hipStream_t st) {
+  if (m < 1 || m > 64) return hipErrorInvalidValue;
+  const int nblk = (int)((N + kResRows - 1) / kResRows);
+  hipLaunchKernelGGL(hresidual_kernel, dim3(nblk), dim3(kT), 0, st, AX, BX, lam, N, m, partial);
+  hipLaunchKernelGGL(hresidual_sum_kernel, dim3(1), dim3(1024), 0, st, (const double *)partial,
+                     nblk, m, emin, emax, res);
   return hipGetLastError();
 }
 

@@ -299,8 +299,10 @@ hipError_t launch_hextract(const double *eps2, const double *Phi2, int m, double
                            double *Phi, hipStream_t st);
 hipError_t launch_htall_gemm(const double *X, const double *G, long long N, int m, int m2,
                              double *T, hipStream_t st);
+// partial holds hgram_partial_doubles(N, m) doubles.
 hipError_t launch_hresiduals(const double *AX, const double *BX, const double *lam, long long N,
-                             int m, double emin, double emax, double *res, hipStream_t st);
+                             int m, double emin, double emax, double *partial, double *res,
+                             hipStream_t st);
 hipError_t launch_hgather(const double *in, const int *perm, long long N, int m, double *out,
                           hipStream_t st);
 

@@ -386,9 +386,12 @@ int feast_timing_read(feast_ctx *ctx, int32_t kind, const char **name, double *t
  *   Q = -sum_e (w_e/4) r (e^{i theta_e} G(Z_e) + e^{-i theta_e} G(Z_e)^H) B Y,
  * G(Z) = (Z B - A)^{-1}; the adjoint solve G(Z_e)^H uses the factorisation of
  * Z_e B - A (G(conj Z) = G(Z)^H).  A_Q = Q^H A Q and B_Q = Q^H B Q are
- * Hermitian; the reduced problem is solved through its real symmetric
- * embedding [[Re, -Im], [Im, Re]] of size 2 M0, whose eigenvalues come in
- * pairs.  Complex arrays are interleaved (re, im) doubles (C99 double
+ * Hermitian; the reduced problem is brought to a real symmetric
+ * tridiagonal one of size M0 (Cholesky of B_Q, Householder reduction of
+ * L^-1 A_Q L^-H, a diagonal phase scaling) for the real eigensolver, or, when
+ * B_Q fails the Cholesky pivot test, solved through its real symmetric
+ * embedding [[Re, -Im], [Im, Re]] of size 2 M0 with the B_Q fallback of
+ * feast_solve.  Complex arrays are interleaved (re, im) doubles (C99 double
  * complex, torch.complex128).  Counting, convergence, residual and output
  * order as in feast_solve (residual 1-norms of complex moduli).
  * Limits: b <= 96, M0 <= 64.  For b <= 64 the factorisation is twisted and

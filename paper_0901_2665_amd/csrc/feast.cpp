@@ -27,8 +27,8 @@ constexpr int kMaxM0 = 128;
 // convergence waits while the smallest residual of the uncounted in-interval
 // Ritz pairs falls below this fraction of its previous-loop value
 constexpr double kUncountedDrop = 0.5;
-// Hermitian variant: block size and subspace limits (the reduced problem is
-// solved through its real embedding of size 2 M0 <= 128)
+// Hermitian variant: block size and subspace limits (the fallback solves the
+// reduced problem through its real embedding of size 2 M0 <= 128)
 constexpr int kMaxHB = 96;
 constexpr int kMaxHM0 = 64;
 
@@ -43,7 +43,7 @@ enum Slot {
   S_SINV32, S_W32, S_WT32, S_G32, S_TV32, S_XC, S_RC, S_RPART, S_WORST,
   // Hermitian variant
   S_HSINV, S_HW, S_HV, S_HG, S_HY, S_HR, S_HQ, S_HX, S_HAX, S_HBX, S_HPART, S_HAQ, S_HBQ,
-  S_HEA, S_HEB, S_HEPS2, S_HPHI2, S_HEPS, S_HPHI, S_HRES, S_HCOEF, S_HFWORK, S_CONV, S_COUNT
+  S_HEA, S_HEB, S_HEPS2, S_HPHI2, S_HEPS, S_HPHI, S_HRES, S_HCOEF, S_HFWORK, S_HZ, S_CONV, S_COUNT
 };
 
 }  // namespace
@@ -1504,7 +1504,7 @@ int generic_solve(feast_ctx *ctx, const HPencil &p, double emin, double emax, in
   const size_t nm2 = (size_t)N * M0 * 2;
   const int n2 = 2 * M0;  // size of the real embedding of the reduced problem
   double *y, *rr, *q, *x, *ax, *bx, *part, *aq, *bq, *ea, *eb, *eps2, *phi2, *eps, *phi, *resi,
-      *scr;
+      *scr, *hz;
   int *flag, *perm;
   HIPCHK(ensure_t(ctx, S_HY, nm2, &y));
   HIPCHK(ensure_t(ctx, S_HR, nm2, &rr));
@@ -1521,6 +1521,7 @@ int generic_solve(feast_ctx *ctx, const HPencil &p, double emin, double emax, in
   HIPCHK(ensure_t(ctx, S_HPHI2, (size_t)n2 * n2, &phi2));
   HIPCHK(ensure_t(ctx, S_HEPS, (size_t)M0, &eps));
   HIPCHK(ensure_t(ctx, S_HPHI, (size_t)M0 * M0 * 2, &phi));
+  HIPCHK(ensure_t(ctx, S_HZ, (size_t)M0 * M0 * 2, &hz));
   HIPCHK(ensure_t(ctx, S_HRES, (size_t)M0, &resi));
   HIPCHK(ensure_t(ctx, S_RRS, reduced_eig_scratch_doubles(), &scr));
   HIPCHK(ensure_t(ctx, S_FLAG, 4, &flag));
@@ -1550,10 +1551,18 @@ int generic_solve(feast_ctx *ctx, const HPencil &p, double emin, double emax, in
     TIMED(K_GRAM, launch_happly(p, 1, q, M0, bx, sm));
     TIMED(K_GRAM, launch_hgram(q, ax, N, M0, part, aq, sm));           // A_Q = Q^H A Q
     TIMED(K_GRAM, launch_hgram(q, bx, N, M0, part, bq, sm));           // B_Q = Q^H B Q
-    // real embedding of the Hermitian pencil
-    TIMED(K_RR, launch_hembed(aq, bq, M0, ea, eb, sm));
-    TIMED(K_RR, launch_reduced_eig(ea, eb, n2, eps2, phi2, scr, flag, sm));
-    TIMED(K_RR, launch_hextract(eps2, phi2, M0, eps, phi, sm));
+    // a real symmetric tridiagonal problem of size M0 for the real eigensolver
+    TIMED(K_RR, launch_htridiag(aq, bq, M0, ea, eb, hz, scr, flag, sm));
+    HIPCHK(hipMemcpyAsync(ctx->h_flag + 3, flag + 3, sizeof(int), hipMemcpyDeviceToHost, sm));
+    HIPCHK(hipStreamSynchronize(sm));
+    if (!ctx->h_flag[3]) {
+      TIMED(K_RR, launch_reduced_eig(ea, eb, M0, eps, phi2, scr, flag, sm));
+      TIMED(K_RR, launch_hcombine(hz, phi2, M0, phi, sm));
+    } else {  // B_Q fails the Cholesky test: the real embedding and its fallback
+      TIMED(K_RR, launch_hembed(aq, bq, M0, ea, eb, sm));
+      TIMED(K_RR, launch_reduced_eig(ea, eb, n2, eps2, phi2, scr, flag, sm));
+      TIMED(K_RR, launch_hextract(eps2, phi2, M0, eps, phi, sm));
+    }
     TIMED(K_RITZ, launch_htall_gemm(q, phi, N, M0, M0, x, sm));       // X = Q Phi
     TIMED(K_RESID, launch_happly(p, 0, x, M0, ax, sm));
     TIMED(K_RESID, launch_happly(p, 1, x, M0, bx, sm));

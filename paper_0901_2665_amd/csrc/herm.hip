@@ -516,6 +516,376 @@ int grid_of(size_t n) {
   return (int)(g < 4096 ? (g > 0 ? g : 1) : 4096);
 }
 
+// ---- reduced problem A_Q Phi = eps B_Q Phi, complex Hermitian (eqs. 6-9) ----
+//
+// htridiag_kernel (one workgroup of 1024 threads, m <= 64) brings the
+// complex problem to a real symmetric tridiagonal one of size m for the
+// real eigensolver (reduced_eig_kernel with B = I):
+//  1. B_Q = L L^H (Hermitian part, right-looking Cholesky); a pivot L_kk^2
+//     not above 1e-12 B_Q(k, k) stops the kernel with flag[3] = 1 and
+//     nothing else written (the caller then takes the real embedding, whose
+//     fallback handles a singular B_Q);
+//  2. C = L^-1 A_Q L^-H;
+//  3. Householder reduction C = Q C3 Q^H, C3 Hermitian tridiagonal:
+//     x = C[k+1:, k], alpha = -(x_0 / |x_0|) ||x||, v = x - alpha e_1,
+//     H = I - tau v v^H with tau = 2 / ||v||^2, C <- H C H through
+//     p = tau C v, w = p - (tau / 2)(v^H p) v, C <- C - v w^H - w v^H;
+//  4. D = diag(d), d_0 = 1, d_k+1 = d_k beta_k / |beta_k| (beta_k =
+//     C3[k+1][k]) makes T = D^H C3 D real: diagonal Re C3[k][k], off
+//     diagonal |beta_k|.
+// Outputs: T and I (real [m][m]), Z = L^-H Q D (complex [m][m]); the
+// eigenvectors are Phi = Z V_T for T = V_T diag(eps) V_T^T.  Linv:
+// 2 (m+1)^2 doubles of scratch.  flag[3] = 0 on success.
+constexpr int kRN = 64, kRLD = kRN + 1, kRThreads = 1024;
+
+struct HTriLds {
+  double Cr[kRN * kRLD], Ci[kRN * kRLD];  // C; first L^-1
+  double Vr[kRN * kRLD], Vi[kRN * kRLD];  // Q; first B_Q -> L, then A_Q -> A_Q L^-H
+  double vr[kRN], vi[kRN];                 // Householder vector
+  double pr[kRN], pi[kRN];                 // p
+  double qr[kRN], qi[kRN];                 // Q v
+  double dr[kRN], di[kRN];                 // D
+  double bdiag[kRN];
+  double tau, alpha_r, alpha_i, kr, ki;
+  int skip;
+};
+
+__global__ __launch_bounds__(kRThreads) void htridiag_kernel(const double *AQ, const double *BQ,
+                                                             int m, double *T, double *I,
+                                                             double *Z, double *Linv, int *flag) {
+  extern __shared__ double smem_raw[];
+  HTriLds &s = *reinterpret_cast<HTriLds *>(smem_raw);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int n2 = m + (m & 1), np = n2 / 2;
+  double *Cr = s.Cr, *Ci = s.Ci, *Vr = s.Vr, *Vi = s.Vi;
+  auto at = [](int i, int j) { return i * kRLD + j; };
+  // Hermitian part of B_Q, identity padding
+  for (int o = tid; o < n2 * n2; o += kRThreads) {
+    const int i = o / n2, j = o % n2;
+    double re = i == j ? 1.0 : 0.0, im = 0.0;
+    if (i < m && j < m) {
+      const cd a = ld(BQ, (size_t)i * m + j), b = ld(BQ, (size_t)j * m + i);
+      re = 0.5 * (a.r + b.r);
+      im = 0.5 * (a.i - b.i);
+    }
+    Vr[at(i, j)] = re;
+    Vi[at(i, j)] = im;
+    if (i == j) s.bdiag[i] = re;
+  }
+  __syncthreads();
+  // 1. Cholesky (lower triangle of V)
+  bool fail = false;
+  for (int k = 0; k < n2; ++k) {
+    const double d = Vr[at(k, k)];
+    if (!(d > 1e-12 * s.bdiag[k]) || !isfinite(d)) {  // same values in every thread
+      fail = true;
+      break;
+    }
+    const double lkk = sqrt(d), inv = 1.0 / lkk;
+    __syncthreads();
+    if (tid == 0) {
+      Vr[at(k, k)] = lkk;
+      Vi[at(k, k)] = 0.0;
+    }
+    for (int i = k + 1 + tid; i < n2; i += kRThreads) {
+      Vr[at(i, k)] *= inv;
+      Vi[at(i, k)] *= inv;
+    }
+    __syncthreads();
+    {  // 16 threads a row of the trailing lower triangle
+      const int i = k + 1 + (tid >> 4);
+      if (i < n2) {
+        const double lr = Vr[at(i, k)], li = Vi[at(i, k)];
+        for (int j = k + 1 + (tid & 15); j <= i; j += 16) {
+          const double jr = Vr[at(j, k)], ji = Vi[at(j, k)];
+          Vr[at(i, j)] -= lr * jr + li * ji;  // L_ik conj(L_jk)
+          Vi[at(i, j)] -= li * jr - lr * ji;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (fail) {
+    if (tid == 0) flag[3] = 1;
+    return;
+  }
+  // 2. L^-1 (lower) into C row by row (16 threads a column); a copy to global
+  for (int i = 0; i < n2; ++i) {
+    const int j = tid >> 4, part = tid & 15;
+    double sr = 0.0, si = 0.0;
+    if (j < i)
+      for (int k = j + part; k < i; k += 16) {
+        const double lr = Vr[at(i, k)], li = Vi[at(i, k)], xr = Cr[at(k, j)], xi = Ci[at(k, j)];
+        sr += lr * xr - li * xi;
+        si += lr * xi + li * xr;
+      }
+    for (int off = 8; off > 0; off >>= 1) {
+      sr += __shfl_xor(sr, off);
+      si += __shfl_xor(si, off);
+    }
+    if (part == 0 && j < n2) {
+      const double inv = 1.0 / Vr[at(i, i)];
+      Cr[at(i, j)] = j < i ? -sr * inv : (j == i ? inv : 0.0);
+      Ci[at(i, j)] = j < i ? -si * inv : 0.0;
+    }
+    __syncthreads();
+  }
+  for (int o = tid; o < n2 * n2; o += kRThreads) {
+    const int i = o / n2, j = o % n2;
+    Linv[2 * o] = Cr[at(i, j)];
+    Linv[2 * o + 1] = Ci[at(i, j)];
+    double re = 0.0, im = 0.0;  // Hermitian part of A_Q into V (zero padding)
+    if (i < m && j < m) {
+      const cd a = ld(AQ, (size_t)i * m + j), b = ld(AQ, (size_t)j * m + i);
+      re = 0.5 * (a.r + b.r);
+      im = 0.5 * (a.i - b.i);
+    }
+    Vr[at(i, j)] = re;
+    Vi[at(i, j)] = im;
+  }
+  __syncthreads();
+  // A_Q L^-H, then C = L^-1 (A_Q L^-H): 2 x 2 output blocks a thread
+  const bool blk = (tid >> 5) < np && (tid & 31) < np;
+  const int r0 = 2 * (tid >> 5), c0 = 2 * (tid & 31);
+  cd acc[2][2];
+  for (int u = 0; u < 2; ++u)
+    for (int v = 0; v < 2; ++v) acc[u][v] = {0.0, 0.0};
+  if (blk)
+    for (int k = 0; k < n2; ++k)
+      for (int u = 0; u < 2; ++u)
+        for (int v = 0; v < 2; ++v) {
+          const cd a = {Vr[at(r0 + u, k)], Vi[at(r0 + u, k)]};
+          const cd l = {Cr[at(c0 + v, k)], Ci[at(c0 + v, k)]};  // conj(L^-1[c][k]) below
+          acc[u][v] = cadd(acc[u][v], {a.r * l.r + a.i * l.i, a.i * l.r - a.r * l.i});
+        }
+  __syncthreads();
+  if (blk)
+    for (int u = 0; u < 2; ++u)
+      for (int v = 0; v < 2; ++v) {
+        Vr[at(r0 + u, c0 + v)] = acc[u][v].r;
+        Vi[at(r0 + u, c0 + v)] = acc[u][v].i;
+        acc[u][v] = {0.0, 0.0};
+      }
+  __syncthreads();
+  if (blk)
+    for (int k = 0; k < n2; ++k)
+      for (int u = 0; u < 2; ++u)
+        for (int v = 0; v < 2; ++v) {
+          const cd l = {Cr[at(r0 + u, k)], Ci[at(r0 + u, k)]};
+          const cd t = {Vr[at(k, c0 + v)], Vi[at(k, c0 + v)]};
+          acc[u][v] = cadd(acc[u][v], cmul(l, t));
+        }
+  __syncthreads();
+  if (blk)
+    for (int u = 0; u < 2; ++u)
+      for (int v = 0; v < 2; ++v) {
+        Cr[at(r0 + u, c0 + v)] = acc[u][v].r;
+        Ci[at(r0 + u, c0 + v)] = acc[u][v].i;
+      }
+  __syncthreads();
+  // Hermitian part of C; Q = I
+  if (blk)
+    for (int u = 0; u < 2; ++u)
+      for (int v = 0; v < 2; ++v) {
+        const int i = r0 + u, j = c0 + v;
+        acc[u][v] = {0.5 * (Cr[at(i, j)] + Cr[at(j, i)]), 0.5 * (Ci[at(i, j)] - Ci[at(j, i)])};
+      }
+  __syncthreads();
+  if (blk)
+    for (int u = 0; u < 2; ++u)
+      for (int v = 0; v < 2; ++v) {
+        const int i = r0 + u, j = c0 + v;
+        Cr[at(i, j)] = acc[u][v].r;
+        Ci[at(i, j)] = acc[u][v].i;
+        Vr[at(i, j)] = i == j ? 1.0 : 0.0;
+        Vi[at(i, j)] = 0.0;
+      }
+  __syncthreads();
+  // 3. Householder reduction of the leading m x m block
+  for (int k = 0; k + 2 < m; ++k) {
+    const int n1 = m - k - 1;  // length of x
+    if (wv == 0) {
+      double xr = 0.0, xi = 0.0;
+      if (lane < n1) {
+        xr = Cr[at(k + 1 + lane, k)];
+        xi = Ci[at(k + 1 + lane, k)];
+      }
+      double nx2 = xr * xr + xi * xi;
+      for (int off = 32; off > 0; off >>= 1) nx2 += __shfl_xor(nx2, off);
+      const double x0r = Cr[at(k + 1, k)], x0i = Ci[at(k + 1, k)];
+      const double nx = sqrt(nx2), a0 = sqrt(x0r * x0r + x0i * x0i);
+      const double phr = a0 > 0.0 ? x0r / a0 : 1.0, phi = a0 > 0.0 ? x0i / a0 : 0.0;
+      const double alr = -phr * nx, ali = -phi * nx;
+      // ||v||^2 = ||x||^2 - |x_0|^2 + (|x_0| + ||x||)^2
+      const double vn2 = 2.0 * nx * (nx + a0);
+      s.vr[lane] = lane == 0 ? xr - alr : xr;
+      s.vi[lane] = lane == 0 ? xi - ali : xi;
+      if (lane == 0) {
+        s.skip = !(vn2 > 0.0);
+        s.tau = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
+        s.alpha_r = alr;
+        s.alpha_i = ali;
+      }
+    }
+    __syncthreads();
+    if (s.skip) {  // uniform: x = 0, nothing to reduce
+      __syncthreads();
+      continue;
+    }
+    const double tau = s.tau;
+    // p = tau C_sub v (rows < n1) and q = Q_sub v (rows < m): 16 threads a row
+    {
+      const int row = tid >> 4, part = tid & 15;
+      for (int pass = 0; pass < 2; ++pass) {
+        const int rr = row + 64 * pass;  // 0..n1-1: p, n1..n1+m-1: q
+        const bool isp = rr < n1, isq = !isp && rr - n1 < m;
+        double sr = 0.0, si = 0.0;
+        if (isp || isq) {
+          const int i = isp ? k + 1 + rr : rr - n1;
+          const double *Mr = isp ? Cr : Vr, *Mi = isp ? Ci : Vi;
+          for (int j = part; j < n1; j += 16) {
+            const double mr = Mr[at(i, k + 1 + j)], mi = Mi[at(i, k + 1 + j)];
+            sr += mr * s.vr[j] - mi * s.vi[j];
+            si += mr * s.vi[j] + mi * s.vr[j];
+          }
+        }
+        for (int off = 8; off > 0; off >>= 1) {
+          sr += __shfl_xor(sr, off);
+          si += __shfl_xor(si, off);
+        }
+        if (part == 0) {
+          if (isp) {
+            s.pr[rr] = tau * sr;
+            s.pi[rr] = tau * si;
+          } else if (isq) {
+            s.qr[rr - n1] = sr;
+            s.qi[rr - n1] = si;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (wv == 0) {  // K = (tau / 2) v^H p
+      double kr = 0.0, ki = 0.0;
+      if (lane < n1) {
+        kr = s.vr[lane] * s.pr[lane] + s.vi[lane] * s.pi[lane];
+        ki = s.vr[lane] * s.pi[lane] - s.vi[lane] * s.pr[lane];
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        kr += __shfl_xor(kr, off);
+        ki += __shfl_xor(ki, off);
+      }
+      if (lane == 0) {
+        s.kr = 0.5 * tau * kr;
+        s.ki = 0.5 * tau * ki;
+      }
+    }
+    __syncthreads();
+    // C_sub -= v w^H + w v^H with w = p - K v; column and row k; Q_sub -= tau q v^H
+    {
+      const double kr = s.kr, ki = s.ki;
+      const int i = tid >> 4;
+      if (i < n1) {
+        const double vir = s.vr[i], vii = s.vi[i];
+        const double wir = s.pr[i] - (kr * vir - ki * vii), wii = s.pi[i] - (kr * vii + ki * vir);
+        for (int j = tid & 15; j < n1; j += 16) {
+          const double vjr = s.vr[j], vji = s.vi[j];
+          const double wjr = s.pr[j] - (kr * vjr - ki * vji), wji = s.pi[j] - (kr * vji + ki * vjr);
+          // v_i conj(w_j) + w_i conj(v_j)
+          const double ur = vir * wjr + vii * wji + wir * vjr + wii * vji;
+          const double ui = vii * wjr - vir * wji + wii * vjr - wir * vji;
+          Cr[at(k + 1 + i, k + 1 + j)] -= ur;
+          Ci[at(k + 1 + i, k + 1 + j)] -= ui;
+        }
+      }
+      if (i < m) {
+        const double qr = tau * s.qr[i], qi = tau * s.qi[i];
+        for (int j = tid & 15; j < n1; j += 16) {
+          const double vjr = s.vr[j], vji = s.vi[j];
+          Vr[at(i, k + 1 + j)] -= qr * vjr + qi * vji;  // tau q_i conj(v_j)
+          Vi[at(i, k + 1 + j)] -= qi * vjr - qr * vji;
+        }
+      }
+    }
+    if (tid < n1) {
+      const double ar = tid == 0 ? s.alpha_r : 0.0, ai = tid == 0 ? s.alpha_i : 0.0;
+      Cr[at(k + 1 + tid, k)] = ar;
+      Ci[at(k + 1 + tid, k)] = ai;
+      Cr[at(k, k + 1 + tid)] = ar;
+      Ci[at(k, k + 1 + tid)] = -ai;
+    }
+    __syncthreads();
+  }
+  // 4. D, T, I, Z = L^-H Q D
+  if (tid == 0) {
+    double dr = 1.0, di = 0.0;
+    s.dr[0] = 1.0;
+    s.di[0] = 0.0;
+    for (int k = 0; k + 1 < m; ++k) {
+      const double br = Cr[at(k + 1, k)], bi = Ci[at(k + 1, k)];
+      const double ab = sqrt(br * br + bi * bi);
+      if (ab > 0.0) {
+        const double er = br / ab, ei = bi / ab;
+        const double nr = dr * er - di * ei, ni = dr * ei + di * er;
+        dr = nr;
+        di = ni;
+      }
+      s.dr[k + 1] = dr;
+      s.di[k + 1] = di;
+    }
+  }
+  for (int o = tid; o < m * m; o += kRThreads) {
+    const int i = o / m, j = o % m;
+    double t = 0.0;
+    if (i == j) t = Cr[at(i, i)];
+    else if (i == j + 1 || j == i + 1) {
+      const int hi = i > j ? i : j, lo = i > j ? j : i;
+      const double br = Cr[at(hi, lo)], bi = Ci[at(hi, lo)];
+      t = sqrt(br * br + bi * bi);
+    }
+    T[o] = t;
+    I[o] = i == j ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int o = tid; o < n2 * n2; o += kRThreads) {  // L^-1 back into C
+    const int i = o / n2, j = o % n2;
+    Cr[at(i, j)] = Linv[2 * o];
+    Ci[at(i, j)] = Linv[2 * o + 1];
+  }
+  __syncthreads();
+  if (blk) {
+    for (int u = 0; u < 2; ++u)
+      for (int v = 0; v < 2; ++v) acc[u][v] = {0.0, 0.0};
+    for (int k = 0; k < n2; ++k)
+      for (int u = 0; u < 2; ++u)
+        for (int v = 0; v < 2; ++v) {
+          const cd l = {Cr[at(k, r0 + u)], Ci[at(k, r0 + u)]};  // conj(L^-1[k][r]) below
+          const cd x = {Vr[at(k, c0 + v)], Vi[at(k, c0 + v)]};
+          acc[u][v] = cadd(acc[u][v], cmulc(l, x));
+        }
+    for (int u = 0; u < 2; ++u)
+      for (int v = 0; v < 2; ++v) {
+        const int i = r0 + u, j = c0 + v;
+        if (i < m && j < m) st(Z, (size_t)i * m + j, cmul(acc[u][v], {s.dr[j], s.di[j]}));
+      }
+  }
+  if (tid == 0) flag[3] = 0;
+}
+
+// Phi[r][j] = sum_k Z[r][k] VT[k][j] (Z complex, VT real, [m][m]).
+__global__ void hcombine_kernel(const double *Z, const double *VT, int m, double *Phi) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= m * m) return;
+  const int r = o / m, j = o % m;
+  cd acc = {0.0, 0.0};
+  for (int k = 0; k < m; ++k) {
+    const cd z = ld(Z, (size_t)r * m + k);
+    const double v = VT[(size_t)k * m + j];
+    acc = {acc.r + z.r * v, acc.i + z.i * v};
+  }
+  st(Phi, o, acc);
+}
+
 }  // namespace
 
 size_t hfactor_lds_bytes(int b) { return 2 * (size_t)b * (b + 1) * sizeof(double); }
@@ -581,6 +951,23 @@ hipError_t launch_hembed(const double *AQ, const double *BQ, int m, double *EA, 
                          hipStream_t st) {
   hipLaunchKernelGGL(hembed_kernel, dim3(grid_of((size_t)4 * m * m)), dim3(256), 0, st, AQ, BQ, m,
                      EA, EB);
+  return hipGetLastError();
+}
+
+hipError_t launch_htridiag(const double *AQ, const double *BQ, int m, double *T, double *I,
+                           double *Z, double *scratch, int *flag, hipStream_t st) {
+  if (m < 1 || m > kRN) return hipErrorInvalidValue;
+  const int shm = (int)sizeof(HTriLds);
+  hipError_t e = hipFuncSetAttribute((const void *)htridiag_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, shm);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(htridiag_kernel, dim3(1), dim3(kRThreads), shm, st, AQ, BQ, m, T, I, Z,
+                     scratch, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_hcombine(const double *Z, const double *VT, int m, double *Phi, hipStream_t st) {
+  hipLaunchKernelGGL(hcombine_kernel, dim3((m * m + 255) / 256), dim3(256), 0, st, Z, VT, m, Phi);
   return hipGetLastError();
 }
 

@@ -293,6 +293,15 @@ size_t hgram_partial_doubles(long long N, int m);
 // G = Hermitian part of X^H V (complex [m][m], m <= 64).
 hipError_t launch_hgram(const double *X, const double *Vin, long long N, int m, double *partial,
                         double *G, hipStream_t st);
+// The complex Hermitian-definite A_Q Phi = eps B_Q Phi (m <= 64) as a real
+// symmetric tridiagonal T (with I, real [m][m]) for launch_reduced_eig, and
+// Z (complex [m][m]) with Phi = Z V_T; scratch holds 2 (m+1)^2 doubles.
+// flag[3] = 1 (nothing else written) when B_Q fails the Cholesky pivot
+// test, else 0.
+hipError_t launch_htridiag(const double *AQ, const double *BQ, int m, double *T, double *I,
+                           double *Z, double *scratch, int *flag, hipStream_t st);
+// Phi = Z VT (Z complex, VT real, [m][m]).
+hipError_t launch_hcombine(const double *Z, const double *VT, int m, double *Phi, hipStream_t st);
 hipError_t launch_hembed(const double *AQ, const double *BQ, int m, double *EA, double *EB,
                          hipStream_t st);
 hipError_t launch_hextract(const double *eps2, const double *Phi2, int m, double *eps,

@@ -198,19 +198,22 @@ def test_solve_hermitian_singular_bq(ctx, torch):
     assert np.max(r.res.cpu().numpy()[:r.M]) <= 1e-9
 
 
-def test_solve_hermitian_single_column(ctx, torch):
-    # M0 = 1 on n = 320 (the partial sums of the projection and the
-    # residuals at their smallest width): one isolated eigenvalue, status 4
-    # (M = M0) as in the oracle
+@pytest.mark.parametrize("m0", [1, 2, 3])
+def test_solve_hermitian_few_columns(ctx, torch, m0):
+    # M0 = 1..3 on n = 320 (the partial sums of the projection and the
+    # residuals at their smallest width; no Householder step for M0 <= 2, an
+    # odd size padded): one isolated eigenvalue, status as in the oracle
+    # (4 for M = M0)
     p = W.hermitian_pencil(20, 16, 21)
     lam_b = O.bruteforce_hermitian(p)[0]
     k0 = 200
     emin, emax = gap_interval(lam_b, k0, 1)
-    Y0 = W.random_complex_subspace(p.n, 1, 3)
-    r = ctx.solve_hermitian(hpencil(p), emin, emax, 1, 8, zdev(torch, Y0), tol=1e-13,
+    Y0 = W.random_complex_subspace(p.n, m0, 3)
+    r = ctx.solve_hermitian(hpencil(p), emin, emax, m0, 8, zdev(torch, Y0), tol=1e-13,
                             max_loops=40)
-    ref = O.feast_hermitian(p, emin, emax, 1, 8, Y0, tol=1e-13, max_loops=40)
-    assert r.status == ref.status == 4 and r.M == ref.M == 1
+    ref = O.feast_hermitian(p, emin, emax, m0, 8, Y0, tol=1e-13, max_loops=40)
+    assert r.status == ref.status and r.M == ref.M == 1
+    assert r.status == (4 if m0 == 1 else 0)
     check_hermitian(r, ref, p, emin, emax, lam_b, k0)
 
 

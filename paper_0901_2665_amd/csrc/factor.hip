@@ -1034,10 +1034,10 @@ hipError_t launch_factor_bp(const Pencil &p, const Shifts &s, int Ne, const Fact
 // coupling L_c = Z B_{c,c+1}^T - A_{c,c+1}^H), and S_{c+1} = D_{c+1} - L_c W_c.
 // Every principal submatrix of M has the positive definite Hermitian part
 // Im(Z) B in M - M^H = 2i Im(Z) B, so the blocked Gauss-Jordan inverse needs
-// no pivoting; it is not symmetrised.  One chain (contour point) per
-// workgroup, the blocks in the two LDS slots, the products on the matrix
-// cores; outputs complex interleaved [b][b] (the layout of the Hermitian
-// sweeps).
+// no pivoting; it is not symmetrised.  One workgroup per partition of a half
+// chain, the blocks in the two LDS slots, the products on the matrix cores;
+// the factors are stored in the 4 x 4 tiled layout of kernels.h, which the
+// Hermitian sweeps read.
 
 // slot <- one shifted block of the Hermitian pencil by NTH threads: kind 0
 // D_cell (identity padding), 1 C_cell, 2 L_cell (zero padding).
@@ -1118,6 +1118,57 @@ __device__ void hacc_to_global(double *g, const d4 (&accr)[BP / 16], const d4 (&
         g[2 * (row * b + col) + 1] = acci[tj][r];
       }
     }
+}
+
+// Factor blocks in the tiled layout (kernels.h): tiled <- the slot, tiled <-
+// this wave's accumulator tiles, slot <- tiled (zero outside b x b).
+__device__ __forceinline__ int htile_off(int i, int j, int bt) {
+  return ((i >> 2) * bt + (j >> 2)) * 16 + (i & 3) * 4 + (j & 3);
+}
+
+template <int BP>
+__device__ void hstore_tiled(double *g, const double *slot, int b) {
+  constexpr int LD = Lds<BP>::LD, PLANE = Lds<BP>::PLANE;
+  const int t4 = htile_dim(b), bt = t4 / 4;
+  for (int idx = threadIdx.x; idx < t4 * t4; idx += kThreads) {
+    const int i = idx / t4, j = idx % t4;
+    const int o = htile_off(i, j, bt);
+    g[2 * o] = slot[i * LD + j];
+    g[2 * o + 1] = slot[PLANE + i * LD + j];
+  }
+}
+
+template <int BP>
+__device__ void hacc_to_tiled(double *g, const d4 (&accr)[BP / 16], const d4 (&acci)[BP / 16],
+                              int b) {
+  constexpr int NT = BP / 16;
+  const int w = wave_id(), l = lane_id();
+  if (w >= NT) return;
+  const int t4 = htile_dim(b), bt = t4 / 4;
+#pragma unroll
+  for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = w * 16 + acc_row(l, r), col = tj * 16 + acc_col(l);
+      if (row < t4 && col < t4) {
+        const int o = htile_off(row, col, bt);
+        g[2 * o] = accr[tj][r];
+        g[2 * o + 1] = acci[tj][r];
+      }
+    }
+}
+
+template <int BP>
+__device__ void hload_tiled(double *slot, const double *g, int b) {
+  constexpr int LD = Lds<BP>::LD, PLANE = Lds<BP>::PLANE;
+  const int bt = htile_dim(b) / 4;
+  for (int idx = threadIdx.x; idx < BP * BP; idx += kThreads) {
+    const int r = idx / BP, c = idx % BP;
+    const bool in = r < b && c < b;
+    const int o = in ? htile_off(r, c, bt) : 0;
+    slot[r * LD + c] = in ? g[2 * o] : 0.0;
+    slot[PLANE + r * LD + c] = in ? g[2 * o + 1] : 0.0;
+  }
 }
 
 // Operands of the Hermitian block products: an LDS slot, or a complex
@@ -1253,7 +1304,7 @@ __device__ void hchain_final(Lds<BP> &s, const HPencil &p, double zr, double zi,
                              double *Ve) {
   constexpr int NT = BP / 16;
   const int nc = p.nc, b = p.b, m = nc - nc / 2;
-  const size_t bb = (size_t)b * b;
+  const size_t bb = hfactor_block_elems(b);
   auto cell = [&](int j) { return top ? j : nc - 1 - j; };
   hform_block<BP>(s.A, p, cell(jb), 0, zr, zi);  // S = D_jb
   if (K) {
@@ -1265,7 +1316,7 @@ __device__ void hchain_final(Lds<BP> &s, const HPencil &p, double zr, double zi,
     const int c = cell(j);
     const bool chain_last = j == len - 1;
     if (top && chain_last && nc - m > 0) {  // raw S_{m-1} for the twist kernel
-      hstore_block<BP>(We + 2 * (size_t)c * bb, s.A, b);
+      hstore_tiled<BP>(We + 2 * (size_t)c * bb, s.A, b);
       break;
     }
     const bool more = !(top && chain_last);  // the bottom chain's last cell still gets W, V
@@ -1276,7 +1327,7 @@ __device__ void hchain_final(Lds<BP> &s, const HPencil &p, double zr, double zi,
       if (more) hform_block<BP, kThreads - 64>(s.B, p, cc, kx, zr, zi, threadIdx.x - 64);
     };
     gj_invert<BP>(s, nullptr, coupling, false);  // slot A: Sinv_c
-    hstore_block<BP>(Se + 2 * (size_t)c * bb, s.A, b);
+    hstore_tiled<BP>(Se + 2 * (size_t)c * bb, s.A, b);
     if (!more) break;
     d4 wr[NT], wi[NT], vr[NT], vi[NT], sr[NT], si[NT];
 #pragma unroll
@@ -1288,10 +1339,10 @@ __device__ void hchain_final(Lds<BP> &s, const HPencil &p, double zr, double zi,
     hform_block<BP>(s.B, p, cc, ky, zr, zi);  // slot B: Y
     __syncthreads();
     cgemm_lds<BP>(vr, vi, s.B, false, s.A, 1.0);  // V = Y Sinv
-    hacc_to_global<BP>(Ve + 2 * (size_t)c * bb, vr, vi, b);
+    hacc_to_tiled<BP>(Ve + 2 * (size_t)c * bb, vr, vi, b);
     __syncthreads();
     acc_to_lds<BP>(s.A, wr, wi);  // slot A: W
-    hacc_to_global<BP>(We + 2 * (size_t)c * bb, wr, wi, b);
+    hacc_to_tiled<BP>(We + 2 * (size_t)c * bb, wr, wi, b);
     __syncthreads();
     if (j == je - 1) break;  // end of the partition (bottom chain: W_m and V_m, no S_{m-1})
     acc_from_hdiag<BP>(sr, si, p, cell(j + 1), zr, zi);
@@ -1414,10 +1465,10 @@ __global__ __launch_bounds__(kThreads) void hfactor_part_kernel(HPencil p, Shift
   if (len <= 0) return;
   const int jb = (int)((long long)q * len / P), je = (int)((long long)(q + 1) * len / P);
   const double zr = sh.zre[e], zi = sh.zim[e];
-  const size_t bb2 = 2 * (size_t)p.b * p.b;
-  double *Se = Sinv + (size_t)e * nc * bb2;
-  double *We = W + (size_t)e * nc * bb2;
-  double *Ve = V + (size_t)e * nc * bb2;
+  const size_t bb2 = 2 * (size_t)p.b * p.b, fbb2 = 2 * hfactor_block_elems(p.b);
+  double *Se = Sinv + (size_t)e * nc * fbb2;
+  double *We = W + (size_t)e * nc * fbb2;
+  double *Ve = V + (size_t)e * nc * fbb2;
   double *wk = work + ((size_t)ch * P + q) * HW_COUNT * bb2;
   if (q == 0 || phase == 1)
     hchain_final<BP>(s, p, zr, zi, top, len, jb, je, q ? wk + HW_K * bb2 : nullptr, Se, We, Ve);
@@ -1451,9 +1502,9 @@ __global__ __launch_bounds__(kThreads) void hfactor_twist_kernel(HPencil p, Shif
   const int nc = p.nc, b = p.b, m = nc - nc / 2;
   if (nc - m == 0) return;
   const double zr = sh.zre[e], zi = sh.zim[e];
-  const size_t bb = (size_t)b * b;
-  double *We = W + 2 * (size_t)e * nc * bb;
-  hload_block<BP>(s.A, We + 2 * (size_t)(m - 1) * bb, b);  // raw S_{m-1}
+  const size_t fbb = hfactor_block_elems(b);
+  double *We = W + 2 * (size_t)e * nc * fbb;
+  hload_tiled<BP>(s.A, We + 2 * (size_t)(m - 1) * fbb, b);  // raw S_{m-1}
   __syncthreads();
   d4 tr[NT], ti[NT];
   {
@@ -1472,7 +1523,7 @@ __global__ __launch_bounds__(kThreads) void hfactor_twist_kernel(HPencil p, Shif
         }
   }
   __syncthreads();
-  hload_block<BP>(s.A, We + 2 * (size_t)m * bb, b);  // W_m (bottom chain)
+  hload_tiled<BP>(s.A, We + 2 * (size_t)m * fbb, b);  // W_m (bottom chain)
   hform_block<BP>(s.B, p, m - 1, 1, zr, zi);        // C_{m-1}
   __syncthreads();
   cgemm_lds<BP>(tr, ti, s.B, false, s.A, -1.0);  // S_{m-1} - C_{m-1} W_m
@@ -1480,7 +1531,7 @@ __global__ __launch_bounds__(kThreads) void hfactor_twist_kernel(HPencil p, Shif
   acc_to_lds<BP>(s.A, tr, ti);
   __syncthreads();
   gj_invert<BP>(s, nullptr, NoSide(), false);
-  hstore_block<BP>(Sinv + 2 * ((size_t)e * nc + (m - 1)) * bb, s.A, b);
+  hstore_tiled<BP>(Sinv + 2 * ((size_t)e * nc + (m - 1)) * fbb, s.A, b);
 }
 
 // Self-energies across the partitions of a chain, one workgroup a chain, in
@@ -1510,7 +1561,7 @@ __global__ __launch_bounds__(kThreads) void hinterface_kernel(HPencil p, Shifts 
   {  // K_1 = V_c X at the last position of partition 0
     const int jl = len / P - 1;
     const int c = top ? jl : nc - 1 - jl, cc = top ? c : c - 1;
-    hload_block<BP>(s.A, V + ((size_t)e * nc + c) * bb2, b);
+    hload_tiled<BP>(s.A, V + ((size_t)e * nc + c) * 2 * hfactor_block_elems(b), b);
     hform_block<BP>(s.B, p, cc, top ? 1 : 2, zr, zi);
     __syncthreads();
     acc_fill<BP>(ar, ai, 0.0);

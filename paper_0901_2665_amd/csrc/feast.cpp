@@ -1384,7 +1384,7 @@ struct HFactors {
 };
 
 int prepare_hfactors(feast_ctx *ctx, const HPencil &p, int Ne, int partitions, HFactors &f) {
-  const size_t bb2 = 2 * (size_t)p.b * p.b;
+  const size_t bb2 = 2 * hfactor_block_elems(p.b);
   HIPCHK(ensure_t(ctx, S_HSINV, (size_t)Ne * p.nc * bb2, &f.Sinv));
   HIPCHK(ensure_t(ctx, S_HW, (size_t)Ne * p.nc * bb2, &f.W));
   HIPCHK(ensure_t(ctx, S_HV, (size_t)Ne * p.nc * bb2, &f.V));

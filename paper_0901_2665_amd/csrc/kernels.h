@@ -255,8 +255,19 @@ struct HPencil {
   int nc, b;
 };
 size_t hfactor_lds_bytes(int b);
-// Block LU of Z_e B - A for every node: Sinv, W and V [Ne][nc][b][b]
-// (complex; b > 64: W and V use the first max(nc-1,1) blocks of a node).
+// Blocks of the Hermitian factors for b <= 64 are stored as 4 x 4 tiles of
+// complex elements, tiles row-major: element (i, j) at complex offset
+// ((i/4) bt + j/4) 16 + (i%4) 4 + j%4, bt = ceil(b/4), so that both the
+// sixteen-row fragments of M and those of M^H read whole tiles; a block holds
+// (4 bt)^2 elements (entries outside b x b finite).  Blocks above 64 are
+// plain [b][b].
+__host__ __device__ inline int htile_dim(int b) { return (b + 3) / 4 * 4; }
+__host__ __device__ inline size_t hfactor_block_elems(int b) {
+  return b <= 64 ? (size_t)htile_dim(b) * htile_dim(b) : (size_t)b * b;
+}
+// Block LU of Z_e B - A for every node: Sinv, W and V [Ne][nc] blocks of
+// hfactor_block_elems(b) complex elements (b > 64: W and V use the first
+// max(nc-1,1) blocks of a node).
 // For b <= 64 each half chain is cut into `parts` partitions (1 <= parts <=
 // max(1, nc/2)) factored through their corner blocks and a sequential
 // self-energy pass; work holds hfactor_work_doubles() doubles (none for one

@@ -748,8 +748,8 @@ hipError_t launch_spike_bp(SpikeArgs &a, dim3 grid, hipStream_t st) {
 // ---- Hermitian A: both solves of eq. 12 on the matrix cores (b <= 64) ----
 //
 // The twisted factors of the non-symmetric M = Z B - A (hfactor_part_kernel)
-// are complex interleaved [b][b] blocks Sinv_c, W_c, V_c (the twist cell's T
-// in Sinv_{m-1}).  Solve 0 is M x = R (forward h_next = R_next - V_c h_c,
+// are complex blocks Sinv_c, W_c, V_c in the 4 x 4 tiled layout of
+// kernels.h (the twist cell's T in Sinv_{m-1}).  Solve 0 is M x = R (forward h_next = R_next - V_c h_c,
 // g_c = Sinv_c h_c; back x_c = g_c - W_c x_prev), solve 1 is M^H y = R with
 // the same blocks conjugate-transposed (W_c^H, Sinv_c^H forward, V_c^H back):
 // the top half runs from cell 0 and the bottom half from cell nc-1 towards
@@ -759,7 +759,7 @@ hipError_t launch_spike_bp(SpikeArgs &a, dim3 grid, hipStream_t st) {
 // one complex element (sixteen bytes) a lane and k-step, zero outside b x b.
 struct HSweepArgs {
   HPencil p;
-  const double *Sinv, *W, *V;  // [Ne][nc][b][b] complex each
+  const double *Sinv, *W, *V;  // [Ne][nc] tiled blocks (kernels.h), complex
   const double *R;             // [N][m] complex
   double *G;                   // [Ne][2][N][m] complex: g, then the solutions;
                                // then the twist slots [Ne][2][ntiles][2][2][BP][8]
@@ -767,17 +767,30 @@ struct HSweepArgs {
 };
 
 // Fragments of M[row][k] (adj: M[k][row]; the conjugate comes from the
-// vector operand's sign2 = -1).  Rows at or beyond b load zeros; columns
-// k >= b meet zero rows of the vector operand, so they may hold any finite
-// value (the next row's entries, or zeros past the block).
+// vector operand's sign2 = -1) from a block in the 4 x 4 tiled layout of the
+// factors (tiled) or a plain [b][b] block of the pencil.  Rows at or beyond
+// b load zeros; columns k >= b meet zero rows of the vector operand, so they
+// may hold any finite value (padding, the next row's or block's entries, or
+// zeros past the buffer).
 template <int BP>
 __device__ __forceinline__ void hfrag_load(Frag<BP> &f, const double *M, int b, int rb, bool adj,
-                                           bool valid) {
+                                           bool valid, bool tiled = true) {
   const int l = lane_id();
   const int row = rb * 16 + (l & 15), kl = l >> 4;
-  const auto rs = buf_rsrc(M, valid ? 2 * b * b * 8 : 0);
-  const int vo = row < b ? (adj ? kl * b + row : row * b + kl) * 16 : kBufferOff;
-  const int kstride = adj ? 64 * b : 64;  // bytes from k-step ks to ks + 1
+  const int bt = htile_dim(b) / 4;  // tiles a block row
+  const int bytes = tiled ? (int)hfactor_block_elems(b) * 16 : 2 * b * b * 8;
+  const auto rs = buf_rsrc(M, valid ? bytes : 0);
+  // k-step ks: tiled, tile column ks (M) or tile row ks (M^H) of the row's
+  // tiles; plain, four columns (M) or four rows (M^H) further
+  int vo, kstride;
+  if (tiled) {
+    vo = adj ? (row >> 2) * 16 + kl * 4 + (row & 3) : (row >> 2) * bt * 16 + (row & 3) * 4 + kl;
+    kstride = adj ? 256 * bt : 256;
+  } else {
+    vo = adj ? kl * b + row : row * b + kl;
+    kstride = adj ? 64 * b : 64;
+  }
+  vo = row < b ? vo * 16 : kBufferOff;
 #pragma unroll
   for (int ks = 0; ks < BP / 4; ++ks) {
     const auto x = __builtin_amdgcn_raw_buffer_load_b128(rs, vo, ks * kstride, 0);
@@ -861,7 +874,7 @@ __global__ __launch_bounds__(BP * 8) void hforward_kernel(HSweepArgs a) {
   if (len <= 0) return;
   const int start = top ? 0 : nc - 1, dir = top ? 1 : -1;
   const int nsteps = top ? len - 1 : len;  // no product at the twist cell
-  const size_t bb = (size_t)b * b;
+  const size_t bb = hfactor_block_elems(b);  // factor block (tiled)
   const size_t vt = 2 * (size_t)BP * kTile;
   const int wv = wave_id();
   const bool wrole = wv < NW;  // wave-uniform
@@ -929,7 +942,7 @@ __global__ __launch_bounds__(BP * 4) void hback_kernel(HSweepArgs a) {
   const int e = grp >> 2;
   const bool adj = (grp & 2) != 0, top = (grp & 1) == 0;
   const int nc = a.p.nc, b = a.p.b, m = a.m, mt = nc - nc / 2;
-  const size_t bb = (size_t)b * b;
+  const size_t bb = hfactor_block_elems(b);  // factor block (tiled)
   const size_t vt = 2 * (size_t)BP * kTile;
   const int rb = wave_id();
   const double *Sm = a.Sinv + 2 * (size_t)e * nc * bb;
@@ -1029,16 +1042,16 @@ __global__ __launch_bounds__(BP * 4) void happly_mfma_kernel(HPencil p, int whic
   Frag<BP> f;
   double bv[BP / 2];
   if (which == 0) {
-    hfrag_load<BP>(f, p.Ad + 2 * (size_t)c * bb, b, rb, false, true);
+    hfrag_load<BP>(f, p.Ad + 2 * (size_t)c * bb, b, rb, false, true, false);
     hbvec_load<BP>(bv, s.t[1], 1.0);
     acc = frag_mfma<BP>(acc, f, bv);
     if (c + 1 < nc) {
-      hfrag_load<BP>(f, p.Au + 2 * (size_t)c * bb, b, rb, false, true);
+      hfrag_load<BP>(f, p.Au + 2 * (size_t)c * bb, b, rb, false, true, false);
       hbvec_load<BP>(bv, s.t[2], 1.0);
       acc = frag_mfma<BP>(acc, f, bv);
     }
     if (c > 0) {  // Au[c-1]^H: column-wise, conjugate through the vector operand
-      hfrag_load<BP>(f, p.Au + 2 * (size_t)(c - 1) * bb, b, rb, true, true);
+      hfrag_load<BP>(f, p.Au + 2 * (size_t)(c - 1) * bb, b, rb, true, true, false);
       hbvec_load<BP>(bv, s.t[0], -1.0);
       acc = frag_mfma<BP>(acc, f, bv);
     }

@@ -1090,36 +1090,6 @@ __device__ void acc_from_hdiag(d4 (&accr)[BP / 16], d4 (&acci)[BP / 16], const H
     }
 }
 
-// global complex [b][b] (interleaved) <- the slot's leading b x b block
-template <int BP>
-__device__ void hstore_block(double *g, const double *slot, int b) {
-  constexpr int LD = Lds<BP>::LD, PLANE = Lds<BP>::PLANE;
-  for (int idx = threadIdx.x; idx < b * b; idx += kThreads) {
-    const int r = idx / b, c = idx % b;
-    g[2 * idx] = slot[r * LD + c];
-    g[2 * idx + 1] = slot[PLANE + r * LD + c];
-  }
-}
-
-// global complex [b][b] (interleaved) <- this wave's accumulator tiles
-template <int BP>
-__device__ void hacc_to_global(double *g, const d4 (&accr)[BP / 16], const d4 (&acci)[BP / 16],
-                               int b) {
-  constexpr int NT = BP / 16;
-  const int w = wave_id(), l = lane_id();
-  if (w >= NT) return;
-#pragma unroll
-  for (int tj = 0; tj < NT; ++tj)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = w * 16 + acc_row(l, r), col = tj * 16 + acc_col(l);
-      if (row < b && col < b) {
-        g[2 * (row * b + col)] = accr[tj][r];
-        g[2 * (row * b + col) + 1] = acci[tj][r];
-      }
-    }
-}
-
 // Factor blocks in the tiled layout (kernels.h): tiled <- the slot, tiled <-
 // this wave's accumulator tiles, slot <- tiled (zero outside b x b).
 __device__ __forceinline__ int htile_off(int i, int j, int bt) {
@@ -1171,8 +1141,8 @@ __device__ void hload_tiled(double *slot, const double *g, int b) {
   }
 }
 
-// Operands of the Hermitian block products: an LDS slot, or a complex
-// interleaved [b][b] block in global memory read as zero outside b x b.
+// Operands of the Hermitian block products: an LDS slot, or a complex block
+// in global memory in the 4 x 4 tiled layout, read as zero outside b x b.
 template <int BP>
 struct SlotOp {
   const double *s;
@@ -1181,12 +1151,13 @@ struct SlotOp {
     im = s[Lds<BP>::PLANE + r * Lds<BP>::LD + c];
   }
 };
-struct GlobOp {
+struct GlobOp {  // a block in the 4 x 4 tiled layout
   const double *g;
   int b;
   __device__ __forceinline__ void ld(int r, int c, double &re, double &im) const {
     const bool in = r < b && c < b;
-    const double2 v = *reinterpret_cast<const double2 *>(g + (in ? 2 * (r * b + c) : 0));
+    const int o = in ? htile_off(r, c, htile_dim(b) >> 2) : 0;
+    const double2 v = *reinterpret_cast<const double2 *>(g + 2 * o);
     re = in ? v.x : 0.0;
     im = in ? v.y : 0.0;
   }
@@ -1243,7 +1214,7 @@ __device__ __forceinline__ void acc_fill(d4 (&accr)[BP / 16], d4 (&acci)[BP / 16
     }
 }
 
-// acc <- complex interleaved [b][b] block (zero outside b x b)
+// acc <- complex tiled block (zero outside b x b)
 template <int BP>
 __device__ void hacc_from_global(d4 (&accr)[BP / 16], d4 (&acci)[BP / 16], const double *g,
                                  int b) {
@@ -1270,14 +1241,15 @@ __device__ __forceinline__ void acc_negate(d4 (&accr)[BP / 16], d4 (&acci)[BP / 
   }
 }
 
-// slot -= K (complex interleaved [b][b]) on the leading b x b block
+// slot -= K (complex tiled block) on the leading b x b block
 template <int BP>
 __device__ void hsub_block(double *slot, const double *K, int b) {
   constexpr int LD = Lds<BP>::LD, PLANE = Lds<BP>::PLANE;
+  const int bt = htile_dim(b) >> 2;
   for (int idx = threadIdx.x; idx < b * b; idx += kThreads) {
-    const int r = idx / b, c = idx % b;
-    slot[r * LD + c] -= K[2 * idx];
-    slot[PLANE + r * LD + c] -= K[2 * idx + 1];
+    const int r = idx / b, c = idx % b, o = htile_off(r, c, bt);
+    slot[r * LD + c] -= K[2 * o];
+    slot[PLANE + r * LD + c] -= K[2 * o + 1];
   }
 }
 
@@ -1369,7 +1341,7 @@ __device__ void hchain_local(Lds<BP> &s, const HPencil &p, double zr, double zi,
                              int jb, int je, double *wk) {
   constexpr int NT = BP / 16;
   const int nc = p.nc, b = p.b;
-  const size_t bb = (size_t)b * b, bb2 = 2 * bb;
+  const size_t bb2 = 2 * hfactor_block_elems(b);  // work blocks: tiled
   double *G11 = wk + HW_G11 * bb2, *YH = wk + HW_YH * bb2, *XH = wk + HW_XH * bb2;
   double *YGX = wk + HW_YGX * bb2, *Q = wk + HW_Q * bb2, *T = wk + HW_T * bb2;
   double *Pb[2] = {wk + HW_P0 * bb2, wk + HW_P1 * bb2};
@@ -1390,16 +1362,16 @@ __device__ void hchain_local(Lds<BP> &s, const HPencil &p, double zr, double zi,
     double *Pn = Pb[(t + 1) & 1];
     d4 ar[NT], ai[NT];
     if (t == 0) {  // P_0 = Q_0 = I
-      hstore_block<BP>(G11, s.A, b);
-      hstore_block<BP>(T, s.A, b);
+      hstore_tiled<BP>(G11, s.A, b);
+      hstore_tiled<BP>(T, s.A, b);
     } else {
       acc_fill<BP>(ar, ai, 0.0);
       cgemm_op<BP>(ar, ai, SlotOp<BP>{s.A}, GlobOp{Pc, b}, 1.0);  // T_t = Sinv'_t P_t
-      hacc_to_global<BP>(T, ar, ai, b);
+      hacc_to_tiled<BP>(T, ar, ai, b);
       __syncthreads();
       hacc_from_global<BP>(ar, ai, G11, b);
       cgemm_op<BP>(ar, ai, GlobOp{Q, b}, GlobOp{T, b}, 1.0);  // G11 += Q_t T_t
-      hacc_to_global<BP>(G11, ar, ai, b);
+      hacc_to_tiled<BP>(G11, ar, ai, b);
     }
     d4 wr[NT], wi[NT];
     acc_fill<BP>(wr, wi, 0.0);
@@ -1408,35 +1380,35 @@ __device__ void hchain_local(Lds<BP> &s, const HPencil &p, double zr, double zi,
     hform_block<BP>(s.B, p, cc, ky, zr, zi);  // slot B: Y
     if (last) {  // XH = Q_t W', YGX = Y W', YH = Y GL1 (GL1 = T_t)
       acc_to_lds<BP>(s.A, wr, wi);
-      if (t == 0) hacc_to_global<BP>(XH, wr, wi, b);
+      if (t == 0) hacc_to_tiled<BP>(XH, wr, wi, b);
       __syncthreads();
       if (t > 0) {
         acc_fill<BP>(ar, ai, 0.0);
         cgemm_op<BP>(ar, ai, GlobOp{Q, b}, SlotOp<BP>{s.A}, 1.0);
-        hacc_to_global<BP>(XH, ar, ai, b);
+        hacc_to_tiled<BP>(XH, ar, ai, b);
       }
       acc_fill<BP>(ar, ai, 0.0);
       cgemm_lds<BP>(ar, ai, s.B, false, s.A, 1.0);
-      hacc_to_global<BP>(YGX, ar, ai, b);
+      hacc_to_tiled<BP>(YGX, ar, ai, b);
       acc_fill<BP>(ar, ai, 0.0);
       cgemm_op<BP>(ar, ai, SlotOp<BP>{s.B}, GlobOp{T, b}, 1.0);
-      hacc_to_global<BP>(YH, ar, ai, b);
+      hacc_to_tiled<BP>(YH, ar, ai, b);
       break;
     }
     __syncthreads();
     acc_fill<BP>(ar, ai, 0.0);
     cgemm_op<BP>(ar, ai, SlotOp<BP>{s.B}, GlobOp{T, b}, -1.0);  // P_{t+1} = -V'_t P_t = -Y T_t
-    hacc_to_global<BP>(Pn, ar, ai, b);
+    hacc_to_tiled<BP>(Pn, ar, ai, b);
     acc_to_lds<BP>(s.A, wr, wi);  // slot A: W'
     if (t == 0) {
       acc_negate<BP>(wr, wi);
-      hacc_to_global<BP>(Q, wr, wi, b);  // Q_1 = -W'_0
+      hacc_to_tiled<BP>(Q, wr, wi, b);  // Q_1 = -W'_0
     }
     __syncthreads();
     if (t > 0) {
       acc_fill<BP>(ar, ai, 0.0);
       cgemm_op<BP>(ar, ai, GlobOp{Q, b}, SlotOp<BP>{s.A}, -1.0);  // Q_{t+1} = -Q_t W'_t
-      hacc_to_global<BP>(Q, ar, ai, b);  // in place: a wave reads and writes its own rows
+      hacc_to_tiled<BP>(Q, ar, ai, b);  // in place: a wave reads and writes its own rows
     }
     acc_from_hdiag<BP>(ar, ai, p, cell(jb + t + 1), zr, zi);
     cgemm_lds<BP>(ar, ai, s.B, false, s.A, -1.0);  // S'_{t+1} = D - Y W'
@@ -1465,27 +1437,15 @@ __global__ __launch_bounds__(kThreads) void hfactor_part_kernel(HPencil p, Shift
   if (len <= 0) return;
   const int jb = (int)((long long)q * len / P), je = (int)((long long)(q + 1) * len / P);
   const double zr = sh.zre[e], zi = sh.zim[e];
-  const size_t bb2 = 2 * (size_t)p.b * p.b, fbb2 = 2 * hfactor_block_elems(p.b);
-  double *Se = Sinv + (size_t)e * nc * fbb2;
-  double *We = W + (size_t)e * nc * fbb2;
-  double *Ve = V + (size_t)e * nc * fbb2;
+  const size_t bb2 = 2 * hfactor_block_elems(p.b);  // factor and work blocks: tiled
+  double *Se = Sinv + (size_t)e * nc * bb2;
+  double *We = W + (size_t)e * nc * bb2;
+  double *Ve = V + (size_t)e * nc * bb2;
   double *wk = work + ((size_t)ch * P + q) * HW_COUNT * bb2;
   if (q == 0 || phase == 1)
     hchain_final<BP>(s, p, zr, zi, top, len, jb, je, q ? wk + HW_K * bb2 : nullptr, Se, We, Ve);
   else
     hchain_local<BP>(s, p, zr, zi, top, jb, je, wk);
-}
-
-// slot <- complex interleaved [b][b] block (zero padding)
-template <int BP>
-__device__ void hload_block(double *slot, const double *g, int b) {
-  constexpr int LD = Lds<BP>::LD, PLANE = Lds<BP>::PLANE;
-  for (int idx = threadIdx.x; idx < BP * BP; idx += kThreads) {
-    const int r = idx / BP, c = idx % BP;
-    const bool in = r < b && c < b;
-    slot[r * LD + c] = in ? g[2 * (r * b + c)] : 0.0;
-    slot[PLANE + r * LD + c] = in ? g[2 * (r * b + c) + 1] : 0.0;
-  }
 }
 
 // Twist cell m-1: Sinv_{m-1} = T = (S_{m-1} - C_{m-1} W_m)^{-1}, with S_{m-1}
@@ -1555,24 +1515,24 @@ __global__ __launch_bounds__(kThreads) void hinterface_kernel(HPencil p, Shifts 
   const int len = top ? m : nc - m;
   if (len <= 0 || P < 2) return;
   const double zr = sh.zre[e], zi = sh.zim[e];
-  const size_t bb2 = 2 * (size_t)b * b;
+  const size_t bb2 = 2 * hfactor_block_elems(b);  // work blocks: tiled
   double *wch = work + (size_t)ch * P * HW_COUNT * bb2;
   d4 ar[NT], ai[NT];
   {  // K_1 = V_c X at the last position of partition 0
     const int jl = len / P - 1;
     const int c = top ? jl : nc - 1 - jl, cc = top ? c : c - 1;
-    hload_tiled<BP>(s.A, V + ((size_t)e * nc + c) * 2 * hfactor_block_elems(b), b);
+    hload_tiled<BP>(s.A, V + ((size_t)e * nc + c) * bb2, b);
     hform_block<BP>(s.B, p, cc, top ? 1 : 2, zr, zi);
     __syncthreads();
     acc_fill<BP>(ar, ai, 0.0);
     cgemm_lds<BP>(ar, ai, s.A, false, s.B, 1.0);
-    hacc_to_global<BP>(wch + ((size_t)HW_COUNT + HW_K) * bb2, ar, ai, b);
+    hacc_to_tiled<BP>(wch + ((size_t)HW_COUNT + HW_K) * bb2, ar, ai, b);
     __syncthreads();
   }
   for (int q = 2; q < P; ++q) {
     const double *wq = wch + (size_t)(q - 1) * HW_COUNT * bb2;
-    hload_block<BP>(s.A, wq + HW_G11 * bb2, b);
-    hload_block<BP>(s.B, wq + HW_K * bb2, b);
+    hload_tiled<BP>(s.A, wq + HW_G11 * bb2, b);
+    hload_tiled<BP>(s.B, wq + HW_K * bb2, b);
     __syncthreads();
     acc_fill<BP>(ar, ai, 1.0);
     cgemm_lds<BP>(ar, ai, s.A, false, s.B, -1.0);  // I - G11 K
@@ -1584,17 +1544,17 @@ __global__ __launch_bounds__(kThreads) void hinterface_kernel(HPencil p, Shifts 
     cgemm_lds<BP>(ar, ai, s.B, false, s.A, 1.0);  // U = K (I - G11 K)^{-1}
     __syncthreads();
     acc_to_lds<BP>(s.B, ar, ai);
-    hload_block<BP>(s.A, wq + HW_YH * bb2, b);
+    hload_tiled<BP>(s.A, wq + HW_YH * bb2, b);
     __syncthreads();
     acc_fill<BP>(ar, ai, 0.0);
     cgemm_lds<BP>(ar, ai, s.A, false, s.B, 1.0);  // YH U
     __syncthreads();
     acc_to_lds<BP>(s.A, ar, ai);
-    hload_block<BP>(s.B, wq + HW_XH * bb2, b);
+    hload_tiled<BP>(s.B, wq + HW_XH * bb2, b);
     __syncthreads();
     hacc_from_global<BP>(ar, ai, wq + HW_YGX * bb2, b);
     cgemm_lds<BP>(ar, ai, s.A, false, s.B, 1.0);  // K_q = YGX + YH U XH
-    hacc_to_global<BP>(wch + ((size_t)q * HW_COUNT + HW_K) * bb2, ar, ai, b);
+    hacc_to_tiled<BP>(wch + ((size_t)q * HW_COUNT + HW_K) * bb2, ar, ai, b);
     __syncthreads();
   }
 }
@@ -1657,7 +1617,7 @@ hipError_t launch_factor_wide(const Pencil &p, const Shifts &s, int Ne, const Fa
 }
 
 size_t hfactor_work_doubles(const HPencil &p, int Ne, int parts) {
-  return parts > 1 ? (size_t)2 * Ne * parts * HW_COUNT * 2 * p.b * p.b : 0;
+  return parts > 1 ? (size_t)2 * Ne * parts * HW_COUNT * 2 * hfactor_block_elems(p.b) : 0;
 }
 
 hipError_t launch_hfactor_mfma(const HPencil &p, const Shifts &s, int Ne, double *Sinv,

@@ -538,6 +538,41 @@ int grid_of(size_t n) {
 // 2 (m+1)^2 doubles of scratch.  flag[3] = 0 on success.
 constexpr int kRN = 64, kRLD = kRN + 1, kRThreads = 1024;
 
+typedef unsigned int hu32x2 __attribute__((__vector_size__(8)));
+
+// Sums across lanes by DPP row shifts (the whole wave active): after
+// row_scan16 lane 16r + 15 holds the sum of row r's sixteen lanes;
+// wave_sum adds the four row sums (every lane gets the same value).
+template <int CTRL>
+__device__ __forceinline__ double dpp_shifted(double v) {
+  const auto u = __builtin_bit_cast(hu32x2, v);
+  hu32x2 w;
+  w[0] = (unsigned)__builtin_amdgcn_update_dpp(0, (int)u[0], CTRL, 0xf, 0xf, true);
+  w[1] = (unsigned)__builtin_amdgcn_update_dpp(0, (int)u[1], CTRL, 0xf, 0xf, true);
+  return __builtin_bit_cast(double, w);
+}
+
+__device__ __forceinline__ double row_scan16(double v) {
+  v += dpp_shifted<0x111>(v);  // row_shr:1
+  v += dpp_shifted<0x112>(v);  // row_shr:2
+  v += dpp_shifted<0x114>(v);  // row_shr:4
+  v += dpp_shifted<0x118>(v);  // row_shr:8
+  return v;
+}
+
+__device__ __forceinline__ double lane_value(double v, int lane) {
+  const auto u = __builtin_bit_cast(hu32x2, v);
+  hu32x2 w;
+  w[0] = (unsigned)__builtin_amdgcn_readlane((int)u[0], lane);
+  w[1] = (unsigned)__builtin_amdgcn_readlane((int)u[1], lane);
+  return __builtin_bit_cast(double, w);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  v = row_scan16(v);
+  return (lane_value(v, 15) + lane_value(v, 31)) + (lane_value(v, 47) + lane_value(v, 63));
+}
+
 struct HTriLds {
   double Cr[kRN * kRLD], Ci[kRN * kRLD];  // C; first L^-1
   double Vr[kRN * kRLD], Vi[kRN * kRLD];  // Q; first B_Q -> L, then A_Q -> A_Q L^-H
@@ -619,11 +654,9 @@ __global__ __launch_bounds__(kRThreads) void htridiag_kernel(const double *AQ, c
         sr += lr * xr - li * xi;
         si += lr * xi + li * xr;
       }
-    for (int off = 8; off > 0; off >>= 1) {
-      sr += __shfl_xor(sr, off);
-      si += __shfl_xor(si, off);
-    }
-    if (part == 0 && j < n2) {
+    sr = row_scan16(sr);  // the column's sum in its last lane
+    si = row_scan16(si);
+    if (part == 15 && j < n2) {
       const double inv = 1.0 / Vr[at(i, i)];
       Cr[at(i, j)] = j < i ? -sr * inv : (j == i ? inv : 0.0);
       Ci[at(i, j)] = j < i ? -si * inv : 0.0;
@@ -710,8 +743,7 @@ __global__ __launch_bounds__(kRThreads) void htridiag_kernel(const double *AQ, c
         xr = Cr[at(k + 1 + lane, k)];
         xi = Ci[at(k + 1 + lane, k)];
       }
-      double nx2 = xr * xr + xi * xi;
-      for (int off = 32; off > 0; off >>= 1) nx2 += __shfl_xor(nx2, off);
+      const double nx2 = wave_sum(xr * xr + xi * xi);
       const double x0r = Cr[at(k + 1, k)], x0i = Ci[at(k + 1, k)];
       const double nx = sqrt(nx2), a0 = sqrt(x0r * x0r + x0i * x0i);
       const double phr = a0 > 0.0 ? x0r / a0 : 1.0, phi = a0 > 0.0 ? x0i / a0 : 0.0;
@@ -749,11 +781,9 @@ __global__ __launch_bounds__(kRThreads) void htridiag_kernel(const double *AQ, c
             si += mr * s.vi[j] + mi * s.vr[j];
           }
         }
-        for (int off = 8; off > 0; off >>= 1) {
-          sr += __shfl_xor(sr, off);
-          si += __shfl_xor(si, off);
-        }
-        if (part == 0) {
+        sr = row_scan16(sr);  // the row's sum in its last lane
+        si = row_scan16(si);
+        if (part == 15) {
           if (isp) {
             s.pr[rr] = tau * sr;
             s.pi[rr] = tau * si;
@@ -771,10 +801,8 @@ __global__ __launch_bounds__(kRThreads) void htridiag_kernel(const double *AQ, c
         kr = s.vr[lane] * s.pr[lane] + s.vi[lane] * s.pi[lane];
         ki = s.vr[lane] * s.pi[lane] - s.vi[lane] * s.pr[lane];
       }
-      for (int off = 32; off > 0; off >>= 1) {
-        kr += __shfl_xor(kr, off);
-        ki += __shfl_xor(ki, off);
-      }
+      kr = wave_sum(kr);
+      ki = wave_sum(ki);
       if (lane == 0) {
         s.kr = 0.5 * tau * kr;
         s.ki = 0.5 * tau * ki;

@@ -217,6 +217,23 @@ def test_solve_hermitian_few_columns(ctx, torch, m0):
     check_hermitian(r, ref, p, emin, emax, lam_b, k0)
 
 
+def test_solve_hermitian_ne16_near_axis_partitioned(ctx, torch):
+    # Ne = 16 around a narrow interval (r = 3.6e-3: the outermost contour
+    # points at Im Z = 6e-5) on a complex chain long enough for the
+    # automatic partitioning (nc = 160: 8 partitions per half chain): the
+    # oracle's count and eigenvalues, the residual bar; status 0 or 2 (the
+    # sharp filter can leave B_Q singular: the fallback, as in the oracle)
+    p = W.hermitian_chain_pencil(160, 32, 4243)
+    emin, emax = 0.2760562795, 0.2833496050
+    Y0 = W.random_complex_subspace(p.n, 8, 11)
+    r = ctx.solve_hermitian(hpencil(p), emin, emax, 8, 16, zdev(torch, Y0), tol=1e-13)
+    ref = O.feast_hermitian(p, emin, emax, 8, 16, Y0, tol=1e-13)
+    assert ref.M == 4 and r.M == ref.M and r.status in (0, 2) and ref.status in (0, 2)
+    lam = r.lam.cpu().numpy()[:r.M]
+    assert np.max(np.abs(np.sort(lam) - np.sort(ref.lam[:ref.M])) / np.abs(ref.lam[:ref.M])) <= 1e-10
+    assert r.max_res <= 1e-9
+
+
 def test_solve_hermitian_random_start(ctx, torch):
     # Y0 = NULL: real and imaginary parts from the seeded real draw of N x 2 M0
     p = W.hermitian_pencil(20, 40, 9)

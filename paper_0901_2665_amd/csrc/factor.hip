@@ -1418,9 +1418,20 @@ __device__ void hchain_local(Lds<BP> &s, const HPencil &p, double zr, double zi,
   }
 }
 
-// Partition q of a chain covers positions [q len / P, (q+1) len / P).  Phase
-// 0: partition 0 exactly, partitions 1..P-2 locally; phase 1: the exact
-// rerun of partitions 1..P-1 from the self-energies of hinterface_kernel.
+// First chain position of partition q of P over a chain of len positions.
+// Partition 0 is factored exactly while the inner ones run their longer
+// local pass (six products a cell against three), so it takes 1.8 shares of
+// the chain to their 1; every partition is non-empty for P <= len.
+__device__ __forceinline__ int hpart_start(int q, int len, int P) {
+  if (q <= 0) return 0;
+  if (q >= P) return len;
+  return (int)((long long)len * (18 + 10 * (q - 1)) / (18 + 10 * (P - 1)));
+}
+
+// Partition q of a chain covers positions [hpart_start(q), hpart_start(q+1)).
+// Phase 0: partition 0 exactly, partitions 1..P-2 locally; phase 1: the
+// exact rerun of partitions 1..P-1 from the self-energies of
+// hinterface_kernel.
 template <int BP>
 __global__ __launch_bounds__(kThreads) void hfactor_part_kernel(HPencil p, Shifts sh,
                                                                 double *Sinv, double *W,
@@ -1435,7 +1446,7 @@ __global__ __launch_bounds__(kThreads) void hfactor_part_kernel(HPencil p, Shift
   const int nc = p.nc, m = nc - nc / 2;
   const int len = top ? m : nc - m;
   if (len <= 0) return;
-  const int jb = (int)((long long)q * len / P), je = (int)((long long)(q + 1) * len / P);
+  const int jb = hpart_start(q, len, P), je = hpart_start(q + 1, len, P);
   const double zr = sh.zre[e], zi = sh.zim[e];
   const size_t bb2 = 2 * hfactor_block_elems(p.b);  // factor and work blocks: tiled
   double *Se = Sinv + (size_t)e * nc * bb2;
@@ -1519,7 +1530,7 @@ __global__ __launch_bounds__(kThreads) void hinterface_kernel(HPencil p, Shifts 
   double *wch = work + (size_t)ch * P * HW_COUNT * bb2;
   d4 ar[NT], ai[NT];
   {  // K_1 = V_c X at the last position of partition 0
-    const int jl = len / P - 1;
+    const int jl = hpart_start(1, len, P) - 1;
     const int c = top ? jl : nc - 1 - jl, cc = top ? c : c - 1;
     hload_tiled<BP>(s.A, V + ((size_t)e * nc + c) * bb2, b);
     hform_block<BP>(s.B, p, cc, top ? 1 : 2, zr, zi);

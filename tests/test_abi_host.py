@@ -43,6 +43,35 @@ def test_exports_every_declared_symbol(lib):
     assert names == set(F.EXPORTED)
 
 
+def declared_arity():
+    """Parameter count of every function prototype in include/*.h."""
+    arity = {}
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            for name, params in re.findall(r"\b(feast_[a-z_0-9]+)\s*\(([^)]*)\)\s*;", text):
+                params = params.strip()
+                arity[name] = 0 if params in ("", "void") else params.count(",") + 1
+    return arity
+
+
+def test_binding_argtypes_match_header(lib):
+    # every entry point the binding declares takes as many arguments as its
+    # prototype (a parameter added to the header and not to the binding, or
+    # the reverse, fails here rather than as a bad call on the GPU)
+    arity = declared_arity()
+    assert len(arity) >= 10
+    checked = 0
+    for name, n in sorted(arity.items()):
+        argtypes = getattr(getattr(lib, name), "argtypes", None)
+        if argtypes is None:
+            continue
+        assert len(argtypes) == n, (name, len(argtypes), n)
+        checked += 1
+    assert checked >= 10
+
+
 @pytest.mark.parametrize("ne", [1, 4, 8, 16, 24])
 def test_contour_matches_oracle(lib, ne):
     emin, emax = -3.2, -2.9

@@ -1547,8 +1547,7 @@ int generic_solve(feast_ctx *ctx, const HPencil &p, double emin, double emax, in
     TIMED(K_BTMUL, launch_happly(p, 1, y, M0, rr, sm));                // R = B Y
     st = hfilter(ctx, p, Ne, f, rr, M0, coef, q);                      // Q (eq. 12)
     if (st) return st;
-    TIMED(K_GRAM, launch_happly(p, 0, q, M0, ax, sm));
-    TIMED(K_GRAM, launch_happly(p, 1, q, M0, bx, sm));
+    TIMED(K_GRAM, launch_happly_pair(p, q, M0, ax, bx, sm));          // A Q, B Q
     TIMED(K_GRAM, launch_hgram(q, ax, N, M0, part, aq, sm));           // A_Q = Q^H A Q
     TIMED(K_GRAM, launch_hgram(q, bx, N, M0, part, bq, sm));           // B_Q = Q^H B Q
     // a real symmetric tridiagonal problem of size M0 for the real eigensolver
@@ -1564,8 +1563,7 @@ int generic_solve(feast_ctx *ctx, const HPencil &p, double emin, double emax, in
       TIMED(K_RR, launch_hextract(eps2, phi2, M0, eps, phi, sm));
     }
     TIMED(K_RITZ, launch_htall_gemm(q, phi, N, M0, M0, x, sm));       // X = Q Phi
-    TIMED(K_RESID, launch_happly(p, 0, x, M0, ax, sm));
-    TIMED(K_RESID, launch_happly(p, 1, x, M0, bx, sm));
+    TIMED(K_RESID, launch_happly_pair(p, x, M0, ax, bx, sm));        // A X, B X
     TIMED(K_RESID, launch_hresiduals(ax, bx, eps, N, M0, emin, emax, part, resi, sm));
     HIPCHK(hipMemcpyAsync(h_eps, eps, M0 * sizeof(double), hipMemcpyDeviceToHost, sm));
     HIPCHK(hipMemcpyAsync(h_res, resi, M0 * sizeof(double), hipMemcpyDeviceToHost, sm));

@@ -946,6 +946,13 @@ hipError_t launch_haccumulate(const double *G, int Ne, size_t Nm, const double *
   return hipGetLastError();
 }
 
+hipError_t launch_happly_pair(const HPencil &p, const double *Vin, int m, double *outA,
+                              double *outB, hipStream_t st) {
+  if (p.b <= 64) return launch_happly_mfma(p, 2, Vin, m, outA, st, outB);
+  hipError_t e = launch_happly(p, 0, Vin, m, outA, st);
+  return e == hipSuccess ? launch_happly(p, 1, Vin, m, outB, st) : e;
+}
+
 hipError_t launch_happly(const HPencil &p, int which, const double *Vin, int m, double *out,
                          hipStream_t st) {
   if (p.b <= 64) return launch_happly_mfma(p, which, Vin, m, out, st);

@@ -296,10 +296,14 @@ hipError_t launch_haccumulate(const double *G, int Ne, size_t Nm, const double *
 // out = A V (which 0) or B V (which 1), complex V and out [N][m].
 hipError_t launch_happly(const HPencil &p, int which, const double *Vin, int m, double *out,
                          hipStream_t st);
-// The same product for b <= 64 on the matrix cores (sweep.hip), which
-// launch_happly takes for those blocks.
+// outA = A V and outB = B V in one pass over V where the blocks allow it.
+hipError_t launch_happly_pair(const HPencil &p, const double *Vin, int m, double *outA,
+                              double *outB, hipStream_t st);
+// The same products for b <= 64 on the matrix cores (sweep.hip), which
+// launch_happly and launch_happly_pair take for those blocks; which 2
+// writes A V to out and B V to out2.
 hipError_t launch_happly_mfma(const HPencil &p, int which, const double *V, int m, double *out,
-                              hipStream_t st);
+                              hipStream_t st, double *out2 = nullptr);
 size_t hgram_partial_doubles(long long N, int m);
 // G = Hermitian part of X^H V (complex [m][m], m <= 64).
 hipError_t launch_hgram(const double *X, const double *Vin, long long N, int m, double *partial,

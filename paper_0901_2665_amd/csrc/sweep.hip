@@ -1024,7 +1024,8 @@ __device__ __forceinline__ void rfrag_load(Frag<BP> &f, const double *M, int b, 
 
 template <int BP>
 __global__ __launch_bounds__(BP * 4) void happly_mfma_kernel(HPencil p, int which, const double *V,
-                                                             int m, int ntiles, double *out) {
+                                                             int m, int ntiles, double *out,
+                                                             double *out2) {
   __shared__ HApplyLds<BP> s;
   const int c = blockIdx.x / ntiles, tau = blockIdx.x % ntiles;
   const int nc = p.nc, b = p.b, rb = wave_id();
@@ -1041,7 +1042,7 @@ __global__ __launch_bounds__(BP * 4) void happly_mfma_kernel(HPencil p, int whic
   d4 acc = d4zero();
   Frag<BP> f;
   double bv[BP / 2];
-  if (which == 0) {
+  if (which != 1) {  // A V (which 0, or the first output of which 2)
     hfrag_load<BP>(f, p.Ad + 2 * (size_t)c * bb, b, rb, false, true, false);
     hbvec_load<BP>(bv, s.t[1], 1.0);
     acc = frag_mfma<BP>(acc, f, bv);
@@ -1055,7 +1056,12 @@ __global__ __launch_bounds__(BP * 4) void happly_mfma_kernel(HPencil p, int whic
       hbvec_load<BP>(bv, s.t[0], -1.0);
       acc = frag_mfma<BP>(acc, f, bv);
     }
-  } else {
+  }
+  if (which == 2) {
+    hvec_store<BP>(out, nbytes, b, m, c, rb, tau, acc);
+    acc = d4zero();
+  }
+  if (which != 0) {  // B V
     rfrag_load<BP>(f, p.Bd + (size_t)c * bb, b, rb, false);
     hbvec_load<BP>(bv, s.t[1], 1.0);
     acc = frag_mfma<BP>(acc, f, bv);
@@ -1070,15 +1076,15 @@ __global__ __launch_bounds__(BP * 4) void happly_mfma_kernel(HPencil p, int whic
       acc = frag_mfma<BP>(acc, f, bv);
     }
   }
-  hvec_store<BP>(out, nbytes, b, m, c, rb, tau, acc);
+  hvec_store<BP>(which == 2 ? out2 : out, nbytes, b, m, c, rb, tau, acc);
 }
 
 template <int BP>
 hipError_t launch_happly_bp(const HPencil &p, int which, const double *V, int m, double *out,
-                            hipStream_t st) {
+                            double *out2, hipStream_t st) {
   const int ntiles = (m + kTile - 1) / kTile;
   hipLaunchKernelGGL(happly_mfma_kernel<BP>, dim3(p.nc * ntiles), dim3(BP * 4), 0, st, p, which,
-                     V, m, ntiles, out);
+                     V, m, ntiles, out, out2);
   return hipGetLastError();
 }
 
@@ -1143,14 +1149,15 @@ hipError_t launch_sweeps_wide(const Pencil &p, const Shifts &s, int Ne, const Fa
 }
 
 hipError_t launch_happly_mfma(const HPencil &p, int which, const double *V, int m, double *out,
-                              hipStream_t st) {
-  if (p.b < 1 || p.b > 64 || m < 1 || (size_t)p.nc * p.b * m * 16 > 0x7fffffffu)
+                              hipStream_t st, double *out2) {
+  if (p.b < 1 || p.b > 64 || m < 1 || which < 0 || which > 2 || (which == 2 && !out2) ||
+      (size_t)p.nc * p.b * m * 16 > 0x7fffffffu)
     return hipErrorInvalidValue;
   switch ((p.b + 15) / 16 * 16) {
-    case 16: return launch_happly_bp<16>(p, which, V, m, out, st);
-    case 32: return launch_happly_bp<32>(p, which, V, m, out, st);
-    case 48: return launch_happly_bp<48>(p, which, V, m, out, st);
-    default: return launch_happly_bp<64>(p, which, V, m, out, st);
+    case 16: return launch_happly_bp<16>(p, which, V, m, out, out2, st);
+    case 32: return launch_happly_bp<32>(p, which, V, m, out, out2, st);
+    case 48: return launch_happly_bp<48>(p, which, V, m, out, out2, st);
+    default: return launch_happly_bp<64>(p, which, V, m, out, out2, st);
   }
 }
 
